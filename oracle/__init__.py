@@ -1,0 +1,267 @@
+"""ctypes binding of the FP64 CPU oracle (``libibref.so``, built from ``ibref.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU
+baseline leg of the benchmark.  The product package never imports it.  It
+shares no code with the GPU library; both take their inputs from the seeded
+generators in ``paper_2503_22695_amd.inputs`` (which hold no method arithmetic).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libibref.so")
+
+OK, E_INVAL, E_NOCONV, E_NUMERIC = 0, 1, 4, 5
+
+
+def build(openmp: bool = True, extra: Optional[list] = None) -> str:
+    """Compile ibref.c with gcc (-O2, -ffp-contract=off; OpenMP optional)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter"]
+    if openmp:
+        cmd.append("-fopenmp")
+    cmd += extra or []
+    tmp = LIB_PATH + ".tmp"
+    cmd += [os.path.join(HERE, "ibref.c"), "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class Fluid(C.Structure):
+    _fields_ = [("n", C.c_int32), ("rho", C.c_double), ("mu", C.c_double),
+                ("dt", C.c_double), ("mg_pre", C.c_int32), ("mg_post", C.c_int32),
+                ("mg_max_cycles", C.c_int32), ("mg_fixed_cycles", C.c_int32),
+                ("mg_coarse_sweeps", C.c_int32), ("mg_rtol", C.c_double),
+                ("convection", C.c_int32)]
+
+
+class Mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("X_ref", C.c_void_p), ("n_elems", C.c_int32),
+                ("conn", C.c_void_p), ("fibre", C.c_void_p), ("mat_id", C.c_void_p),
+                ("n_mats", C.c_int32), ("mat_model", C.c_void_p), ("mat_params", C.c_void_p),
+                ("n_faces", C.c_int32), ("faces", C.c_void_p)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("cycles", C.c_int32 * 4), ("relres", C.c_double * 4),
+                ("min_J", C.c_double), ("energy", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        i32, f64 = C.c_int32, C.c_double
+        sig = {
+            "ibref_laplacian": (None, [i32, P, P]),
+            "ibref_divergence": (None, [i32, P, P]),
+            "ibref_gradient": (None, [i32, P, P]),
+            "ibref_convection": (None, [i32, P, P]),
+            "ibref_phi": (f64, [f64]),
+            "ibref_spread": (None, [i32, i32, P, P, P]),
+            "ibref_interpolate": (None, [i32, i32, P, P, P]),
+            "ibref_pk1": (C.c_int, [i32, P, P, P, P, P]),
+            "ibref_fe_force": (C.c_int, [P, P, P, P, P]),
+            "ibref_pressure_load": (None, [i32, P, P, f64, P]),
+            "ibref_mg_solve": (C.c_int, [P, f64, f64, i32, P, P, P, P]),
+            "ibref_ns_step": (C.c_int, [P, P, P, P, P]),
+            "ibref_ib_step": (C.c_int, [P, P, P, P, P, f64, P]),
+            "ibref_advance": (C.c_int, [P, P, P, P, P, f64, i32, f64, f64, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, rc: int, what: str):
+        super().__init__(f"{what}: oracle returned {rc}")
+        self.rc = rc
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise OracleError(rc, what)
+
+
+# --------------------------------------------------------------------------
+# operators
+# --------------------------------------------------------------------------
+
+def laplacian(q: np.ndarray) -> np.ndarray:
+    q = _f64(q)
+    n = q.shape[-1]
+    out = np.empty_like(q)
+    lib().ibref_laplacian(n, _p(q), _p(out))
+    return out
+
+
+def divergence(u: np.ndarray) -> np.ndarray:
+    u = _f64(u)
+    n = u.shape[-1]
+    out = np.empty((n, n, n))
+    lib().ibref_divergence(n, _p(u), _p(out))
+    return out
+
+
+def gradient(p: np.ndarray) -> np.ndarray:
+    p = _f64(p)
+    n = p.shape[-1]
+    out = np.empty((3, n, n, n))
+    lib().ibref_gradient(n, _p(p), _p(out))
+    return out
+
+
+def convection(u: np.ndarray) -> np.ndarray:
+    u = _f64(u)
+    n = u.shape[-1]
+    out = np.empty_like(u)
+    lib().ibref_convection(n, _p(u), _p(out))
+    return out
+
+
+def phi(r: float) -> float:
+    return lib().ibref_phi(float(r))
+
+
+def spread(n: int, X: np.ndarray, F: np.ndarray, f: Optional[np.ndarray] = None) -> np.ndarray:
+    X, F = _f64(X), _f64(F)
+    out = np.zeros((3, n, n, n)) if f is None else _f64(f).copy()
+    lib().ibref_spread(n, X.shape[0], _p(X), _p(F), _p(out))
+    return out
+
+
+def interpolate(X: np.ndarray, u: np.ndarray) -> np.ndarray:
+    X, u = _f64(X), _f64(u)
+    n = u.shape[-1]
+    U = np.empty_like(X)
+    lib().ibref_interpolate(n, X.shape[0], _p(X), _p(u), _p(U))
+    return U
+
+
+def pk1(model: int, params, Fm, ef=(1.0, 0.0, 0.0)):
+    par = _f64(list(params) + [0.0] * (5 - len(params)))
+    Fm = _f64(Fm).reshape(3, 3)
+    ef = _f64(ef)
+    P = np.empty((3, 3))
+    psi = C.c_double(0.0)
+    _check(lib().ibref_pk1(model, _p(par), _p(Fm), _p(ef), _p(P), C.byref(psi)), "pk1")
+    return P, psi.value
+
+
+# --------------------------------------------------------------------------
+# problem wrappers
+# --------------------------------------------------------------------------
+
+class MeshBuffers:
+    """Keeps numpy buffers alive for an ibref_mesh struct."""
+
+    def __init__(self, X_ref, conn, fibre, mat_id, mat_model, mat_params, faces=None):
+        self.X_ref = _f64(X_ref)
+        self.conn = _i32(conn)
+        self.fibre = _f64(fibre)
+        self.mat_id = _i32(mat_id)
+        self.mat_model = _i32(mat_model)
+        self.mat_params = _f64(mat_params).reshape(-1, 5)
+        self.faces = _i32(np.zeros((0, 4)) if faces is None else faces)
+        self.s = Mesh(self.X_ref.shape[0], self.X_ref.ctypes.data, self.conn.shape[0],
+                      self.conn.ctypes.data, self.fibre.ctypes.data, self.mat_id.ctypes.data,
+                      self.mat_model.shape[0], self.mat_model.ctypes.data,
+                      self.mat_params.ctypes.data, self.faces.shape[0], self.faces.ctypes.data)
+
+    @classmethod
+    def from_problem(cls, prob):
+        models, params = prob.material_arrays()
+        return cls(prob.X_ref, prob.conn, prob.fibre, prob.mat_id, models, params, prob.faces)
+
+
+def fluid(n, rho=1.0, mu=0.01, dt=1e-3, rtol=1e-10, pre=2, post=2, max_cycles=50,
+          fixed_cycles=0, coarse_sweeps=64, convection=1) -> Fluid:
+    return Fluid(n, rho, mu, dt, pre, post, max_cycles, fixed_cycles, coarse_sweeps, rtol,
+                 convection)
+
+
+def fluid_from_problem(prob, **over) -> Fluid:
+    kw = dict(rho=prob.rho, mu=prob.mu, dt=prob.dt, rtol=prob.mg_rtol, pre=prob.mg_pre,
+              post=prob.mg_post, max_cycles=prob.mg_max_cycles, convection=prob.convection)
+    kw.update(over)
+    return fluid(prob.n, **kw)
+
+
+def fe_force(mesh: MeshBuffers, x: np.ndarray):
+    x = _f64(x)
+    F = np.empty_like(x)
+    E, Jmin = C.c_double(0.0), C.c_double(0.0)
+    _check(lib().ibref_fe_force(C.byref(mesh.s), _p(x), _p(F), C.byref(E), C.byref(Jmin)),
+           "fe_force")
+    return F, E.value, Jmin.value
+
+
+def pressure_load(faces: np.ndarray, x: np.ndarray, p: float, F: Optional[np.ndarray] = None):
+    faces, x = _i32(faces), _f64(x)
+    out = np.zeros_like(x) if F is None else _f64(F).copy()
+    lib().ibref_pressure_load(faces.shape[0], _p(faces), _p(x), float(p), _p(out))
+    return out
+
+
+def mg_solve(fl: Fluid, sigma: float, nu: float, poisson: bool, b: np.ndarray,
+             x0: Optional[np.ndarray] = None):
+    b = _f64(b)
+    x = np.zeros_like(b) if x0 is None else _f64(x0).copy()
+    cyc, rr = C.c_int32(0), C.c_double(0.0)
+    _check(lib().ibref_mg_solve(C.byref(fl), sigma, nu, int(poisson), _p(b), _p(x),
+                                C.byref(cyc), C.byref(rr)), "mg_solve")
+    return x, cyc.value, rr.value
+
+
+def ns_step(fl: Fluid, f: np.ndarray, u: np.ndarray, p: np.ndarray):
+    f, u, p = _f64(f), _f64(u).copy(), _f64(p).copy()
+    st = StepStats()
+    _check(lib().ibref_ns_step(C.byref(fl), _p(f), _p(u), _p(p), C.byref(st)), "ns_step")
+    return u, p, st
+
+
+def advance(fl: Fluid, mesh: MeshBuffers, u, p, X, t0: float, n_steps: int, p0=0.0, T=1.0):
+    u, p, X = _f64(u).copy(), _f64(p).copy(), _f64(X).copy()
+    stats = (StepStats * max(n_steps, 1))()
+    _check(lib().ibref_advance(C.byref(fl), C.byref(mesh.s), _p(u), _p(p), _p(X), t0, n_steps,
+                               p0, T, stats), "advance")
+    return u, p, X, [stats[i] for i in range(n_steps)]
+
+
+def run_problem(prob, n_steps: Optional[int] = None, **fluid_over):
+    """Advance a generated workload from its initial state; returns u, p, X, stats."""
+    fl = fluid_from_problem(prob, **fluid_over)
+    mesh = MeshBuffers.from_problem(prob)
+    u0 = prob.initial_velocity()
+    p0 = np.zeros((prob.n,) * 3)
+    steps = prob.n_steps if n_steps is None else n_steps
+    return advance(fl, mesh, u0, p0, prob.X0, 0.0, steps, prob.p0, prob.T)

@@ -1,0 +1,715 @@
+/*
+ * ibref.c -- plain FP64 CPU oracle of the matrix-free immersed-boundary step.
+ *
+ * TEST INFRASTRUCTURE ONLY (see ibref.h): loaded by the tests, the smoke check
+ * and the CPU-baseline leg of the benchmark, never by the product path.
+ *
+ * Written from the paper's equations, loop by loop, in FP64, with no blocking
+ * or fusion.  Build with -ffp-contract=off so every product and sum is rounded
+ * as written.  OpenMP (optional) only parallelises independent grid loops;
+ * reductions and scatters are serial so results do not depend on threads.
+ *
+ * Paper sections followed:
+ *   "Temporal Discretization"    backward Euler with explicit coupling
+ *   "Spatial Discretization"     Chorin split: Helmholtz solve, Poisson solve,
+ *                                velocity correction, weak-form nodal force,
+ *                                spreading at X^n, interpolation of u^{n+1}
+ *   "Discretization of the Navier-Stokes equations"   MAC staggered grid
+ *   "Eulerian-Lagrangian coupling operators"          spreading, interpolation,
+ *                                nodal quadrature rule, nodal force formula
+ *   "Constitutive laws"          Psi = W + U(J), U = (kappa/2)(ln J)^2,
+ *                                modified invariant I1bar, HO model Psi_4
+ *   "Mitral valve model"         neo-Hookean chordae law
+ *   Abstract                     geometric multigrid for the fluid solves
+ */
+#include "ibref.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* grid helpers                                                              */
+/* ------------------------------------------------------------------------- */
+
+static inline int wrap(int i, int n) { int r = i % n; return r < 0 ? r + n : r; }
+static inline long gidx(int i, int j, int k, int n) {
+    return (long)wrap(i, n) + (long)n * ((long)wrap(j, n) + (long)n * (long)wrap(k, n));
+}
+/* shift (i,j,k) by s along axis d */
+static inline long gidx_s(int i, int j, int k, int n, int d, int s) {
+    if (d == 0) i += s; else if (d == 1) j += s; else k += s;
+    return gidx(i, j, k, n);
+}
+
+/* MAC discrete Laplacian, the 7-point second difference on each lattice. */
+void ibref_laplacian(int32_t n, const double* q, double* out) {
+    const double h = 1.0 / n, ih2 = 1.0 / (h * h);
+#pragma omp parallel for
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                double c = q[gidx(i, j, k, n)];
+                double s = 0.0;
+                for (int d = 0; d < 3; ++d)
+                    s += (q[gidx_s(i, j, k, n, d, 1)] - 2.0 * c + q[gidx_s(i, j, k, n, d, -1)]) * ih2;
+                out[gidx(i, j, k, n)] = s;
+            }
+}
+
+/* (D u)[c] = sum_d (u^d[c + e_d] - u^d[c]) / h : divergence at cell centres. */
+void ibref_divergence(int32_t n, const double* u, double* out) {
+    const double h = 1.0 / n;
+    const long N3 = (long)n * n * n;
+#pragma omp parallel for
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                double s = 0.0;
+                for (int d = 0; d < 3; ++d)
+                    s += (u[d * N3 + gidx_s(i, j, k, n, d, 1)] - u[d * N3 + gidx(i, j, k, n)]) / h;
+                out[gidx(i, j, k, n)] = s;
+            }
+}
+
+/* (G p)^d[c] = (p[c] - p[c - e_d]) / h : gradient on the faces. */
+void ibref_gradient(int32_t n, const double* p, double* out) {
+    const double h = 1.0 / n;
+    const long N3 = (long)n * n * n;
+#pragma omp parallel for
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i)
+                for (int d = 0; d < 3; ++d)
+                    out[d * N3 + gidx(i, j, k, n)] =
+                        (p[gidx(i, j, k, n)] - p[gidx_s(i, j, k, n, d, -1)]) / h;
+}
+
+/*
+ * Convective term C(u) = div(u (x) u) in conservative (flux) form on the MAC
+ * grid, centred.  The paper times a separate "convective term" but does not
+ * print its discretisation; this is the standard Harlow-Welch flux form.
+ * For component d at its face c:
+ *   normal flux   Fdd at the cell centre c:   ((u^d[c] + u^d[c+e_d]) / 2)^2
+ *   tangential    Ede at the edge below c:    ((u^d[c-e_e] + u^d[c]) / 2)
+ *                                           * ((u^e[c-e_d] + u^e[c]) / 2)
+ *   C^d[c] = (Fdd[c] - Fdd[c-e_d]) / h + sum_{e != d} (Ede[c+e_e] - Ede[c]) / h
+ */
+static double conv_normal_flux(const double* ud, int n, int i, int j, int k, int d) {
+    double a = 0.5 * (ud[gidx(i, j, k, n)] + ud[gidx_s(i, j, k, n, d, 1)]);
+    return a * a;
+}
+static double conv_edge_flux(const double* ud, const double* ue, int n, int i, int j, int k,
+                             int d, int e) {
+    double ad = 0.5 * (ud[gidx_s(i, j, k, n, e, -1)] + ud[gidx(i, j, k, n)]);
+    double ae = 0.5 * (ue[gidx_s(i, j, k, n, d, -1)] + ue[gidx(i, j, k, n)]);
+    return ad * ae;
+}
+void ibref_convection(int32_t n, const double* u, double* out) {
+    const double h = 1.0 / n;
+    const long N3 = (long)n * n * n;
+#pragma omp parallel for
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i)
+                for (int d = 0; d < 3; ++d) {
+                    const double* ud = u + d * N3;
+                    int im[3] = {i, j, k};
+                    im[d] -= 1;
+                    double s = (conv_normal_flux(ud, n, i, j, k, d) -
+                                conv_normal_flux(ud, n, im[0], im[1], im[2], d)) / h;
+                    for (int e = 0; e < 3; ++e) {
+                        if (e == d) continue;
+                        const double* ue = u + e * N3;
+                        int ip[3] = {i, j, k};
+                        ip[e] += 1;
+                        s += (conv_edge_flux(ud, ue, n, ip[0], ip[1], ip[2], d, e) -
+                              conv_edge_flux(ud, ue, n, i, j, k, d, e)) / h;
+                    }
+                    out[d * N3 + gidx(i, j, k, n)] = s;
+                }
+}
+
+/* ------------------------------------------------------------------------- */
+/* regularized delta function and the coupling operators                     */
+/* ------------------------------------------------------------------------- */
+
+/* Peskin's four-point kernel phi(r) (the paper cites Peskin 2002 for delta_h);
+ * delta_h(x) = prod_d phi(x_d / h) / h^3. */
+double ibref_phi(double r) {
+    double a = fabs(r);
+    if (a < 1.0) return (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a)) / 8.0;
+    if (a < 2.0) return (5.0 - 2.0 * a - sqrt(-7.0 + 12.0 * a - 4.0 * a * a)) / 8.0;
+    return 0.0;
+}
+
+/* Lattice coordinate of position x along axis e for the lattice of component d:
+ * the face lattice d has points at i*h along d and (i+1/2)*h along the others. */
+static inline double lattice_coord(double x, double h, int d, int e) {
+    return x / h - (e == d ? 0.0 : 0.5);
+}
+
+/* The four lattice indices b-1..b+2 (b = floor(r)) carry all of phi's support. */
+static void stencil_1d(double r, int* first, double w[4]) {
+    int b = (int)floor(r);
+    *first = b - 1;
+    for (int m = 0; m < 4; ++m) w[m] = ibref_phi(r - (double)(b - 1 + m));
+}
+
+/*
+ * Spreading ("Eulerian-Lagrangian coupling operators"):
+ *   f^d[idx] += sum_q F^d_q delta_h(x^d_idx - X_q)
+ * F_q is the nodal force already integrated against the basis (the nodal
+ * quadrature rule carries the weights), so no extra w_q appears.
+ */
+void ibref_spread(int32_t n, int32_t n_nodes, const double* X, const double* F, double* f) {
+    const double h = 1.0 / n, ih3 = 1.0 / (h * h * h);
+    const long N3 = (long)n * n * n;
+    for (int q = 0; q < n_nodes; ++q) {
+        for (int d = 0; d < 3; ++d) {
+            int s0[3];
+            double w[3][4];
+            for (int e = 0; e < 3; ++e) stencil_1d(lattice_coord(X[3 * q + e], h, d, e), &s0[e], w[e]);
+            for (int c = 0; c < 4; ++c)
+                for (int b = 0; b < 4; ++b)
+                    for (int a = 0; a < 4; ++a) {
+                        double wt = w[0][a] * w[1][b] * w[2][c] * ih3;
+                        f[d * N3 + gidx(s0[0] + a, s0[1] + b, s0[2] + c, n)] += F[3 * q + d] * wt;
+                    }
+        }
+    }
+}
+
+/*
+ * Interpolation: U^d_q = sum_idx u^d[idx] delta_h(x^d_idx - X_q) h^3.  With the
+ * nodal quadrature rule the L2 projection onto the nodal space is the identity
+ * at the nodes, so U_q is the nodal velocity.
+ */
+void ibref_interpolate(int32_t n, int32_t n_nodes, const double* X, const double* u, double* U) {
+    const double h = 1.0 / n;
+    const long N3 = (long)n * n * n;
+    for (int q = 0; q < n_nodes; ++q) {
+        for (int d = 0; d < 3; ++d) {
+            int s0[3];
+            double w[3][4];
+            for (int e = 0; e < 3; ++e) stencil_1d(lattice_coord(X[3 * q + e], h, d, e), &s0[e], w[e]);
+            double acc = 0.0;
+            for (int c = 0; c < 4; ++c)
+                for (int b = 0; b < 4; ++b)
+                    for (int a = 0; a < 4; ++a)
+                        acc += u[d * N3 + gidx(s0[0] + a, s0[1] + b, s0[2] + c, n)] *
+                               (w[0][a] * w[1][b] * w[2][c]);
+            U[3 * q + d] = acc;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* constitutive laws ("Constitutive laws")                                   */
+/* ------------------------------------------------------------------------- */
+
+static double det3(const double* A) {
+    return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+           A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+/* cofactor matrix: cof(A) = det(A) A^{-T} */
+static void cof3(const double* A, double* C) {
+    C[0] = A[4] * A[8] - A[5] * A[7];
+    C[1] = A[5] * A[6] - A[3] * A[8];
+    C[2] = A[3] * A[7] - A[4] * A[6];
+    C[3] = A[2] * A[7] - A[1] * A[8];
+    C[4] = A[0] * A[8] - A[2] * A[6];
+    C[5] = A[1] * A[6] - A[0] * A[7];
+    C[6] = A[1] * A[5] - A[2] * A[4];
+    C[7] = A[2] * A[3] - A[0] * A[5];
+    C[8] = A[0] * A[4] - A[1] * A[3];
+}
+
+/*
+ * First Piola-Kirchhoff stress P = dPsi/dF and the energy density Psi.
+ *   common:  J = det F, I1 = tr(F^T F), I1bar = J^{-2/3} I1,
+ *            volumetric U(J) = (kappa/2)(ln J)^2 -> kappa ln J F^{-T}
+ *   neo-Hookean (params mu_s, kappa), the chordae law of the mitral-valve model
+ *            with coefficient a = mu_s / 2:
+ *            Psi = (mu_s/2)(I1bar - 3) + U(J)
+ *            P   = mu_s J^{-2/3} (F - (I1/3) F^{-T}) + kappa ln J F^{-T}
+ *   Holzapfel-Ogden Psi_4 restricted to the isotropic and fibre terms
+ *   (params a, b, a_f, b_f, kappa), I4f = e_f . C e_f, I4f* = max(I4f, 1):
+ *            Psi = a/(2b) (exp(b (I1bar - 3)) - 1)
+ *                + a_f/(2 b_f) (exp(b_f (I4f* - 1)^2) - 1) + U(J)
+ *            P   = a exp(b (I1bar-3)) J^{-2/3} (F - (I1/3) F^{-T})
+ *                + 2 a_f (I4f* - 1) exp(b_f (I4f* - 1)^2) (F e_f) (x) e_f
+ *                + kappa ln J F^{-T}
+ *   (the printed P_4 has F^T in the isotropic bracket where F^{-T} is the
+ *   derivative of Psi_4, and its isotropic energy lacks the -1 offset; both
+ *   are read as corrected here.)
+ * Returns IBREF_E_NUMERIC when J <= 0.
+ */
+int ibref_pk1(int32_t model, const double* par, const double* Fm, const double* ef, double* P,
+              double* psi) {
+    double J = det3(Fm);
+    if (!(J > 0.0)) return IBREF_E_NUMERIC;
+    double cof[9], FiT[9];
+    cof3(Fm, cof);
+    for (int r = 0; r < 9; ++r) FiT[r] = cof[r] / J;
+    double I1 = 0.0;
+    for (int r = 0; r < 9; ++r) I1 += Fm[r] * Fm[r];
+    double Jm23 = pow(J, -2.0 / 3.0);
+    double lnJ = log(J);
+    double kappa, iso_coef, energy;
+    double fib_coef = 0.0;
+    double Fe[3] = {0.0, 0.0, 0.0};
+    if (model == IBREF_NEO_HOOKEAN) {
+        double mu_s = par[0];
+        kappa = par[1];
+        iso_coef = mu_s;
+        energy = 0.5 * mu_s * (Jm23 * I1 - 3.0);
+    } else if (model == IBREF_HOLZAPFEL_OGDEN) {
+        double a = par[0], b = par[1], af = par[2], bf = par[3];
+        kappa = par[4];
+        double E1 = exp(b * (Jm23 * I1 - 3.0));
+        iso_coef = a * E1;
+        energy = a / (2.0 * b) * (E1 - 1.0);
+        for (int r = 0; r < 3; ++r) Fe[r] = Fm[3 * r] * ef[0] + Fm[3 * r + 1] * ef[1] + Fm[3 * r + 2] * ef[2];
+        double I4 = Fe[0] * Fe[0] + Fe[1] * Fe[1] + Fe[2] * Fe[2];
+        double I4s = I4 > 1.0 ? I4 : 1.0;
+        double Ef = exp(bf * (I4s - 1.0) * (I4s - 1.0));
+        fib_coef = 2.0 * af * (I4s - 1.0) * Ef;
+        energy += af / (2.0 * bf) * (Ef - 1.0);
+    } else {
+        return IBREF_E_INVAL;
+    }
+    energy += 0.5 * kappa * lnJ * lnJ;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            P[3 * r + c] = iso_coef * Jm23 * (Fm[3 * r + c] - I1 / 3.0 * FiT[3 * r + c]) +
+                           fib_coef * Fe[r] * ef[c] + kappa * lnJ * FiT[3 * r + c];
+    if (psi) *psi = energy;
+    return IBREF_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* matrix-free nodal forces                                                  */
+/* ------------------------------------------------------------------------- */
+
+/* trilinear hex: local node a = i + 2j + 4k at reference (2i-1, 2j-1, 2k-1) */
+static void hex_dshape(const double xi[3], double dN[8][3]) {
+    for (int a = 0; a < 8; ++a) {
+        double s0 = (a & 1) ? 1.0 : -1.0, s1 = (a & 2) ? 1.0 : -1.0, s2 = (a & 4) ? 1.0 : -1.0;
+        double f0 = 1.0 + s0 * xi[0], f1 = 1.0 + s1 * xi[1], f2 = 1.0 + s2 * xi[2];
+        dN[a][0] = s0 * f1 * f2 / 8.0;
+        dN[a][1] = f0 * s1 * f2 / 8.0;
+        dN[a][2] = f0 * f1 * s2 / 8.0;
+    }
+}
+
+/*
+ * Nodal force from the weak form ("Spatial Discretization" and the mean force
+ * contribution formula of the coupling section):
+ *   F_a = - sum_e sum_g P(F_g) : grad_X N_a(g) w_g
+ * The element rule H_q is left unspecified by the paper; 2x2x2 Gauss points at
+ * +-1/sqrt(3) with unit weights are used, w_g = det(dX/dxi) at the point.
+ * F_g = sum_a x_a (x) grad_X N_a(g).  Also returns E = sum_e sum_g Psi w_g and
+ * the smallest J.  F is overwritten.
+ */
+int ibref_fe_force(const ibref_mesh* m, const double* x, double* F, double* energy,
+                   double* min_J) {
+    const double gp = 1.0 / sqrt(3.0);
+    double E = 0.0, Jmin = INFINITY;
+    for (long r = 0; r < 3L * m->n_nodes; ++r) F[r] = 0.0;
+    for (int e = 0; e < m->n_elems; ++e) {
+        const int32_t* cn = m->conn + 8L * e;
+        int mid = m->mat_id[e];
+        if (mid < 0 || mid >= m->n_mats) return IBREF_E_INVAL;
+        const double* par = m->mat_params + 5L * mid;
+        int model = m->mat_model[mid];
+        const double* ef = m->fibre + 3L * e;
+        double Xe[8][3], xe[8][3], Fe[8][3];
+        for (int a = 0; a < 8; ++a) {
+            if (cn[a] < 0 || cn[a] >= m->n_nodes) return IBREF_E_INVAL;
+            for (int r = 0; r < 3; ++r) {
+                Xe[a][r] = m->X_ref[3L * cn[a] + r];
+                xe[a][r] = x[3L * cn[a] + r];
+                Fe[a][r] = 0.0;
+            }
+        }
+        for (int g = 0; g < 8; ++g) {
+            double xi[3] = {(g & 1) ? gp : -gp, (g & 2) ? gp : -gp, (g & 4) ? gp : -gp};
+            double dN[8][3];
+            hex_dshape(xi, dN);
+            double J0[9] = {0};
+            for (int a = 0; a < 8; ++a)
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) J0[3 * r + c] += Xe[a][r] * dN[a][c];
+            double w = det3(J0);
+            if (!(w > 0.0)) return IBREF_E_NUMERIC;
+            double cof[9], J0inv[9];
+            cof3(J0, cof); /* cof = w J0^{-T}  ->  J0^{-1}[r][c] = cof[c][r] / w */
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) J0inv[3 * r + c] = cof[3 * c + r] / w;
+            double gN[8][3];
+            for (int a = 0; a < 8; ++a)
+                for (int c = 0; c < 3; ++c) {
+                    double s = 0.0;
+                    for (int r = 0; r < 3; ++r) s += dN[a][r] * J0inv[3 * r + c];
+                    gN[a][c] = s;
+                }
+            double Fm[9] = {0};
+            for (int a = 0; a < 8; ++a)
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) Fm[3 * r + c] += xe[a][r] * gN[a][c];
+            double J = det3(Fm);
+            if (J < Jmin) Jmin = J;
+            double P[9], psi;
+            int rc = ibref_pk1(model, par, Fm, ef, P, &psi);
+            if (rc) return rc;
+            E += psi * w;
+            for (int a = 0; a < 8; ++a)
+                for (int r = 0; r < 3; ++r) {
+                    double s = 0.0;
+                    for (int c = 0; c < 3; ++c) s += P[3 * r + c] * gN[a][c];
+                    Fe[a][r] -= s * w;
+                }
+        }
+        for (int a = 0; a < 8; ++a)
+            for (int r = 0; r < 3; ++r) F[3L * cn[a] + r] += Fe[a][r];
+    }
+    if (energy) *energy = E;
+    if (min_J) *min_J = Jmin;
+    return IBREF_OK;
+}
+
+/*
+ * Uniform pressure on a surface (the left-ventricle model loads its
+ * endocardium with a spatially uniform pressure), as a follower load on the
+ * current configuration:
+ *   F_a += -p * integral over the quad of N_a (dx/dxi x dx/deta) dxi deta
+ * with 2x2 Gauss points (exact for the bilinear integrand).  The quads are
+ * oriented so dx/dxi x dx/deta points out of the solid into the cavity; the
+ * load therefore pushes the wall away from the cavity.
+ */
+void ibref_pressure_load(int32_t n_faces, const int32_t* faces, const double* x, double p,
+                         double* F) {
+    const double gp = 1.0 / sqrt(3.0);
+    for (int f = 0; f < n_faces; ++f) {
+        const int32_t* fn = faces + 4L * f;
+        for (int g = 0; g < 4; ++g) {
+            double s = (g & 1) ? gp : -gp, t = (g & 2) ? gp : -gp;
+            double N[4], dNs[4], dNt[4];
+            for (int a = 0; a < 4; ++a) {
+                double sa = (a & 1) ? 1.0 : -1.0, ta = (a & 2) ? 1.0 : -1.0;
+                N[a] = (1.0 + sa * s) * (1.0 + ta * t) / 4.0;
+                dNs[a] = sa * (1.0 + ta * t) / 4.0;
+                dNt[a] = (1.0 + sa * s) * ta / 4.0;
+            }
+            double xs[3] = {0, 0, 0}, xt[3] = {0, 0, 0};
+            for (int a = 0; a < 4; ++a)
+                for (int r = 0; r < 3; ++r) {
+                    xs[r] += x[3L * fn[a] + r] * dNs[a];
+                    xt[r] += x[3L * fn[a] + r] * dNt[a];
+                }
+            double nA[3] = {xs[1] * xt[2] - xs[2] * xt[1], xs[2] * xt[0] - xs[0] * xt[2],
+                            xs[0] * xt[1] - xs[1] * xt[0]};
+            for (int a = 0; a < 4; ++a)
+                for (int r = 0; r < 3; ++r) F[3L * fn[a] + r] -= p * N[a] * nA[r];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* geometric multigrid for (sigma I - nu Lap_h) x = b, periodic              */
+/* ------------------------------------------------------------------------- */
+/*
+ * The paper names a geometric multigrid solver but gives no details; the
+ * algorithm below is this implementation's reading (cell-centred, symmetric):
+ *   V(pre, post) cycle; in-place red-black Gauss-Seidel, red = (i+j+k) even;
+ *   pre-smoothing red then black, post-smoothing black then red;
+ *   restriction: per axis weights (1,3,3,1)/8 over fine cells 2I-1 .. 2I+2;
+ *   prolongation: cell-centred trilinear (3/4, 1/4 per axis), added to x;
+ *   coarse operators rediscretised at 2h; the coarsest level is the first
+ *   with fewer than 8 cells per side, solved by mg_coarse_sweeps red+black
+ *   sweeps; Poisson (sigma = 0): the mean is removed after the coarse solve
+ *   and after each top-level cycle.
+ * Stop rule: ||b - A x||_2 <= max(rtol, 1e3 eps) ||b||_2, tested before the
+ * first cycle and after every cycle; ||b|| = 0 gives x = 0.
+ */
+
+static void gs_colour(int n, double sigma, double nu, const double* b, double* x, int colour) {
+    const double h = 1.0 / n, c = nu / (h * h), diag = sigma + 6.0 * c;
+#pragma omp parallel for
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = ((j + k + colour) & 1); i < n; i += 2) {
+                double s = x[gidx(i + 1, j, k, n)] + x[gidx(i - 1, j, k, n)] +
+                           x[gidx(i, j + 1, k, n)] + x[gidx(i, j - 1, k, n)] +
+                           x[gidx(i, j, k + 1, n)] + x[gidx(i, j, k - 1, n)];
+                x[gidx(i, j, k, n)] = (b[gidx(i, j, k, n)] + c * s) / diag;
+            }
+}
+
+/* r = b - (sigma x - nu Lap_h x) */
+static void residual(int n, double sigma, double nu, const double* b, const double* x, double* r) {
+    const double h = 1.0 / n, c = nu / (h * h);
+#pragma omp parallel for
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                double xc = x[gidx(i, j, k, n)];
+                double s = x[gidx(i + 1, j, k, n)] + x[gidx(i - 1, j, k, n)] +
+                           x[gidx(i, j + 1, k, n)] + x[gidx(i, j - 1, k, n)] +
+                           x[gidx(i, j, k + 1, n)] + x[gidx(i, j, k - 1, n)];
+                double Ax = sigma * xc - c * (s - 6.0 * xc);
+                r[gidx(i, j, k, n)] = b[gidx(i, j, k, n)] - Ax;
+            }
+}
+
+static double norm2(long N, const double* v) {
+    double s = 0.0;
+    for (long i = 0; i < N; ++i) s += v[i] * v[i];
+    return sqrt(s);
+}
+static void remove_mean(long N, double* v) {
+    double s = 0.0;
+    for (long i = 0; i < N; ++i) s += v[i];
+    double m = s / (double)N;
+    for (long i = 0; i < N; ++i) v[i] -= m;
+}
+
+/* coarse[I,J,K] = sum of (w_a w_b w_c / 512) fine[2I-1+a, 2J-1+b, 2K-1+c], w = 1,3,3,1 */
+static void restrict_fw(int nf, const double* fine, double* coarse) {
+    const int nc = nf / 2;
+    static const double w[4] = {1.0, 3.0, 3.0, 1.0};
+#pragma omp parallel for
+    for (int K = 0; K < nc; ++K)
+        for (int J = 0; J < nc; ++J)
+            for (int I = 0; I < nc; ++I) {
+                double s = 0.0;
+                for (int c = 0; c < 4; ++c)
+                    for (int b = 0; b < 4; ++b)
+                        for (int a = 0; a < 4; ++a)
+                            s += w[a] * w[b] * w[c] / 512.0 *
+                                 fine[gidx(2 * I - 1 + a, 2 * J - 1 + b, 2 * K - 1 + c, nf)];
+                coarse[gidx(I, J, K, nc)] = s;
+            }
+}
+
+/* fine[i] += trilinear interpolation of coarse; fine cell i = 2I + s takes
+ * 3/4 of coarse I and 1/4 of coarse I-1 (s = 0) or I+1 (s = 1), per axis. */
+static void prolong_add(int nf, const double* coarse, double* fine) {
+    const int nc = nf / 2;
+#pragma omp parallel for
+    for (int k = 0; k < nf; ++k)
+        for (int j = 0; j < nf; ++j)
+            for (int i = 0; i < nf; ++i) {
+                int ijk[3] = {i, j, k};
+                int base[3][2];
+                double wt[3][2];
+                for (int d = 0; d < 3; ++d) {
+                    int I = ijk[d] >> 1, s = ijk[d] & 1;
+                    base[d][0] = I;
+                    wt[d][0] = 0.75;
+                    base[d][1] = s ? I + 1 : I - 1;
+                    wt[d][1] = 0.25;
+                }
+                double v = 0.0;
+                for (int c = 0; c < 2; ++c)
+                    for (int b = 0; b < 2; ++b)
+                        for (int a = 0; a < 2; ++a)
+                            v += wt[0][a] * wt[1][b] * wt[2][c] *
+                                 coarse[gidx(base[0][a], base[1][b], base[2][c], nc)];
+                fine[gidx(i, j, k, nf)] += v;
+            }
+}
+
+typedef struct {
+    int L;            /* number of levels */
+    int n[32];
+    double* x[32];
+    double* b[32];
+    double* r[32];
+} mg_levels;
+
+static int mg_alloc(int n, mg_levels* lv) {
+    memset(lv, 0, sizeof(*lv));
+    int m = n, L = 0;
+    while (1) {
+        if (m % 2) return IBREF_E_INVAL; /* red-black colouring needs even sizes */
+        lv->n[L] = m;
+        long N3 = (long)m * m * m;
+        lv->x[L] = (double*)calloc((size_t)N3, sizeof(double));
+        lv->b[L] = (double*)calloc((size_t)N3, sizeof(double));
+        lv->r[L] = (double*)calloc((size_t)N3, sizeof(double));
+        ++L;
+        lv->L = L;
+        if (m < 8) break;
+        m /= 2;
+    }
+    lv->L = L;
+    return IBREF_OK;
+}
+static void mg_free(mg_levels* lv) {
+    for (int l = 0; l < lv->L; ++l) { free(lv->x[l]); free(lv->b[l]); free(lv->r[l]); }
+}
+
+static void vcycle(const ibref_fluid* fl, mg_levels* lv, int l, double sigma, double nu,
+                   int poisson, const double* b, double* x) {
+    int n = lv->n[l];
+    long N3 = (long)n * n * n;
+    if (l == lv->L - 1) {
+        for (int s = 0; s < fl->mg_coarse_sweeps; ++s) {
+            gs_colour(n, sigma, nu, b, x, 0);
+            gs_colour(n, sigma, nu, b, x, 1);
+        }
+        if (poisson) remove_mean(N3, x);
+        return;
+    }
+    for (int s = 0; s < fl->mg_pre; ++s) {
+        gs_colour(n, sigma, nu, b, x, 0);
+        gs_colour(n, sigma, nu, b, x, 1);
+    }
+    residual(n, sigma, nu, b, x, lv->r[l]);
+    restrict_fw(n, lv->r[l], lv->b[l + 1]);
+    int nc = lv->n[l + 1];
+    memset(lv->x[l + 1], 0, sizeof(double) * (size_t)nc * nc * nc);
+    vcycle(fl, lv, l + 1, sigma, nu, poisson, lv->b[l + 1], lv->x[l + 1]);
+    prolong_add(n, lv->x[l + 1], x);
+    for (int s = 0; s < fl->mg_post; ++s) {
+        gs_colour(n, sigma, nu, b, x, 1);
+        gs_colour(n, sigma, nu, b, x, 0);
+    }
+}
+
+int ibref_mg_solve(const ibref_fluid* fl, double sigma, double nu, int32_t poisson,
+                   const double* b, double* x, int32_t* cycles, double* relres) {
+    const int n = fl->n;
+    const long N3 = (long)n * n * n;
+    mg_levels lv;
+    int rc = mg_alloc(n, &lv);
+    if (rc) { mg_free(&lv); return rc; }
+    double bn = norm2(N3, b);
+    int k = 0;
+    double rn = 0.0;
+    if (!isfinite(bn)) { mg_free(&lv); return IBREF_E_NUMERIC; }
+    if (bn == 0.0) {
+        for (long i = 0; i < N3; ++i) x[i] = 0.0;
+    } else {
+        double tol = (fl->mg_rtol > 1e3 * DBL_EPSILON ? fl->mg_rtol : 1e3 * DBL_EPSILON) * bn;
+        residual(n, sigma, nu, b, x, lv.r[0]);
+        rn = norm2(N3, lv.r[0]);
+        while (1) {
+            if (!isfinite(rn)) { rc = IBREF_E_NUMERIC; break; }
+            if (fl->mg_fixed_cycles > 0) {
+                if (k == fl->mg_fixed_cycles) break;
+            } else {
+                if (rn <= tol) break;
+                if (k == fl->mg_max_cycles) { rc = IBREF_E_NOCONV; break; }
+            }
+            vcycle(fl, &lv, 0, sigma, nu, poisson, b, x);
+            if (poisson) remove_mean(N3, x);
+            ++k;
+            residual(n, sigma, nu, b, x, lv.r[0]);
+            rn = norm2(N3, lv.r[0]);
+        }
+        rn /= bn;
+    }
+    if (cycles) *cycles = k;
+    if (relres) *relres = rn;
+    mg_free(&lv);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* time step ("Temporal Discretization", "Spatial Discretization")           */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Chorin projection step with explicit convection:
+ *   g   = (rho/dt) u^n - rho C(u^n) + f
+ *   ((rho/dt) I - mu Lap_h) u* = g               (per component, guess u^n)
+ *   Lap_h p = (rho/dt) D u*                      (mean-free, guess p^{n-1})
+ *   u^{n+1} = u* - (dt/rho) G p
+ * The Poisson equation is solved as (-Lap_h) p = -(rho/dt) D u*, with the
+ * discrete mean of the right-hand side removed (periodic null space).
+ */
+int ibref_ns_step(const ibref_fluid* fl, const double* f, double* u, double* p,
+                  ibref_step_stats* st) {
+    const int n = fl->n;
+    const long N3 = (long)n * n * n;
+    const double rho = fl->rho, dt = fl->dt, mu = fl->mu;
+    double* g = (double*)malloc(sizeof(double) * 3 * (size_t)N3);
+    double* c = (double*)calloc(3 * (size_t)N3, sizeof(double));
+    double* b = (double*)malloc(sizeof(double) * (size_t)N3);
+    double* gp = (double*)malloc(sizeof(double) * 3 * (size_t)N3);
+    int rc = IBREF_OK;
+    if (fl->convection) ibref_convection(n, u, c);
+    for (long i = 0; i < 3 * N3; ++i) g[i] = rho / dt * u[i] - rho * c[i] + f[i];
+    for (int d = 0; d < 3 && !rc; ++d) {
+        int32_t cyc = 0;
+        double rr = 0.0;
+        rc = ibref_mg_solve(fl, rho / dt, mu, 0, g + d * N3, u + d * N3, &cyc, &rr);
+        if (st) { st->cycles[d] = cyc; st->relres[d] = rr; }
+    }
+    if (!rc) {
+        ibref_divergence(n, u, b);
+        for (long i = 0; i < N3; ++i) b[i] = -(rho / dt) * b[i];
+        remove_mean(N3, b);
+        int32_t cyc = 0;
+        double rr = 0.0;
+        rc = ibref_mg_solve(fl, 0.0, 1.0, 1, b, p, &cyc, &rr);
+        if (st) { st->cycles[3] = cyc; st->relres[3] = rr; }
+    }
+    if (!rc) {
+        ibref_gradient(n, p, gp);
+        for (long i = 0; i < 3 * N3; ++i) u[i] = u[i] - dt / rho * gp[i];
+    }
+    free(g); free(c); free(b); free(gp);
+    return rc;
+}
+
+/*
+ * One immersed-boundary step with explicit coupling:
+ *   F = F_el(X^n) + F_pressure(X^n)          (force for the step n -> n+1)
+ *   f = S(X^n) F ;  NS step -> u^{n+1}, p^{n+1}
+ *   X^{n+1} = X^n + dt J(X^n) u^{n+1}
+ * The fully discrete scheme interpolates u^{n+1} (the semi-discrete display
+ * writes u^n; the fully discrete statement is followed).
+ */
+int ibref_ib_step(const ibref_fluid* fl, const ibref_mesh* m, double* u, double* p, double* X,
+                  double pressure, ibref_step_stats* st) {
+    const int n = fl->n;
+    const long N3 = (long)n * n * n;
+    double* F = (double*)malloc(sizeof(double) * 3 * (size_t)m->n_nodes);
+    double* U = (double*)malloc(sizeof(double) * 3 * (size_t)m->n_nodes);
+    double* f = (double*)calloc(3 * (size_t)N3, sizeof(double));
+    double E = 0.0, Jmin = 0.0;
+    int rc = ibref_fe_force(m, X, F, &E, &Jmin);
+    if (!rc) {
+        if (m->n_faces > 0 && pressure != 0.0) ibref_pressure_load(m->n_faces, m->faces, X, pressure, F);
+        ibref_spread(n, m->n_nodes, X, F, f);
+        rc = ibref_ns_step(fl, f, u, p, st);
+    }
+    if (!rc) {
+        ibref_interpolate(n, m->n_nodes, X, u, U);
+        for (long r = 0; r < 3L * m->n_nodes; ++r) X[r] = X[r] + fl->dt * U[r];
+    }
+    if (st) { st->min_J = Jmin; st->energy = E; }
+    free(F); free(U); free(f);
+    return rc;
+}
+
+int ibref_advance(const ibref_fluid* fl, const ibref_mesh* m, double* u, double* p, double* X,
+                  double t0, int32_t n_steps, double p0, double T, ibref_step_stats* stats) {
+    const double pi = 3.14159265358979323846;
+    for (int s = 0; s < n_steps; ++s) {
+        double t = t0 + s * fl->dt;
+        double pr = 0.0;
+        if (p0 != 0.0 && T > 0.0) {
+            double sn = sin(pi * t / T);
+            pr = p0 * sn * sn;
+        }
+        int rc = ibref_ib_step(fl, m, u, p, X, pr, stats ? stats + s : NULL);
+        if (rc) return rc;
+    }
+    return IBREF_OK;
+}

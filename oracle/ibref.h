@@ -1,0 +1,104 @@
+/*
+ * ibref -- plain FP64 CPU implementation of the matrix-free immersed-boundary
+ * timestep (Ma, Cai, Wang, Luo, Gao, "Fully GPU-Accelerated Immersed Boundary
+ * Method for Fluid-Structure Interaction in Complex Cardiac Models").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the slow, obviously-correct reference the
+ * GPU library is checked against.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load it.  It shares no source with the GPU
+ * library and must never be called from the product path.
+ *
+ * Conventions (all arrays host memory, caller-owned, C order):
+ *   grid     periodic unit cube, n cells per side, h = 1/n.  Scalars are
+ *            [n][n][n] with x fastest: idx = i + n*(j + n*k).  Vector fields
+ *            are [3][n][n][n].  u^d[i,j,k] lives on the face at coordinate
+ *            i*h along d and cell centres ((.+1/2)h) along the other axes;
+ *            pressure lives at cell centres.
+ *   nodes    X[n_nodes][3], unwrapped positions (only stencil indices wrap).
+ *   hexes    conn[n_elems][8], local node a = i + 2j + 4k at (2i-1,2j-1,2k-1).
+ *   quads    faces[n_faces][4], local node a = i + 2j at (2i-1,2j-1).
+ *
+ * Return codes: 0 ok, 1 invalid argument, 4 no convergence, 5 numeric
+ * (non-finite residual or J <= 0).
+ */
+#ifndef IBREF_H
+#define IBREF_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { IBREF_OK = 0, IBREF_E_INVAL = 1, IBREF_E_NOCONV = 4, IBREF_E_NUMERIC = 5 };
+enum { IBREF_NEO_HOOKEAN = 0, IBREF_HOLZAPFEL_OGDEN = 1 };
+
+typedef struct {
+    int32_t n;                 /* cells per side */
+    double rho, mu, dt;
+    int32_t mg_pre, mg_post;   /* smoothing sweeps (red+black pairs) */
+    int32_t mg_max_cycles;     /* > this many V-cycles: no convergence */
+    int32_t mg_fixed_cycles;   /* > 0: run exactly this many cycles, no stop test */
+    int32_t mg_coarse_sweeps;  /* red+black sweeps on the coarsest level */
+    double mg_rtol;            /* stop when ||r|| <= rtol ||b|| */
+    int32_t convection;        /* 1: explicit flux-form convection, 0: Stokes */
+} ibref_fluid;
+
+typedef struct {
+    int32_t n_nodes;
+    const double* X_ref;       /* [n_nodes][3] reference configuration */
+    int32_t n_elems;
+    const int32_t* conn;       /* [n_elems][8] */
+    const double* fibre;       /* [n_elems][3] unit fibre e_f (reference) */
+    const int32_t* mat_id;     /* [n_elems] */
+    int32_t n_mats;
+    const int32_t* mat_model;  /* [n_mats] IBREF_NEO_HOOKEAN / IBREF_HOLZAPFEL_OGDEN */
+    const double* mat_params;  /* [n_mats][5]: NH (mu_s, kappa); HO (a, b, a_f, b_f, kappa) */
+    int32_t n_faces;
+    const int32_t* faces;      /* [n_faces][4] pressure-loaded quads */
+} ibref_mesh;
+
+typedef struct {
+    int32_t cycles[4];         /* Helmholtz x, y, z, Poisson */
+    double relres[4];
+    double min_J;              /* smallest Jacobian over all Gauss points */
+    double energy;             /* elastic energy at X^n */
+} ibref_step_stats;
+
+/* --- discrete operators on the MAC grid --- */
+void ibref_laplacian(int32_t n, const double* q, double* out);        /* out = Lap_h q */
+void ibref_divergence(int32_t n, const double* u, double* out);       /* out = D u */
+void ibref_gradient(int32_t n, const double* p, double* out);         /* out = G p */
+void ibref_convection(int32_t n, const double* u, double* out);       /* out = C(u) */
+
+/* --- regularized delta and coupling --- */
+double ibref_phi(double r);                                            /* 4-point Peskin kernel */
+void ibref_spread(int32_t n, int32_t n_nodes, const double* X, const double* F, double* f); /* f += S(X)F */
+void ibref_interpolate(int32_t n, int32_t n_nodes, const double* X, const double* u, double* U); /* U = J(X)u */
+
+/* --- solid mechanics --- */
+int ibref_pk1(int32_t model, const double* params, const double* Fm /*[3][3] row-major*/,
+              const double* ef, double* P /*[3][3]*/, double* psi);
+int ibref_fe_force(const ibref_mesh* m, const double* x, double* F /*[n_nodes][3], :=*/,
+                   double* energy, double* min_J);
+void ibref_pressure_load(int32_t n_faces, const int32_t* faces, const double* x, double p,
+                         double* F /* += */);
+
+/* --- multigrid: solves (sigma I - nu Lap_h) x = b on the periodic grid --- */
+int ibref_mg_solve(const ibref_fluid* fl, double sigma, double nu, int32_t poisson,
+                   const double* b, double* x /* guess -> solution */,
+                   int32_t* cycles, double* relres);
+
+/* --- one fluid step (given the Eulerian force density f) and one IB step --- */
+int ibref_ns_step(const ibref_fluid* fl, const double* f, double* u, double* p,
+                  ibref_step_stats* st);
+int ibref_ib_step(const ibref_fluid* fl, const ibref_mesh* m, double* u, double* p, double* X,
+                  double pressure, ibref_step_stats* st);
+/* n_steps IB steps from t0; endocardial pressure p0 sin^2(pi t_n / T) at t_n = t0 + n dt.
+ * stats (may be NULL) receives one record per step. */
+int ibref_advance(const ibref_fluid* fl, const ibref_mesh* m, double* u, double* p, double* X,
+                  double t0, int32_t n_steps, double p0, double T, ibref_step_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,391 @@
+"""Seeded synthetic inputs for the immersed-boundary timestep.
+
+This module builds problem descriptions only: grid size and fluid constants,
+hexahedral Lagrangian meshes, fibre fields, material records, endocardial
+pressure faces and initial velocity fields.  It contains none of the method's
+arithmetic (no delta kernel, no finite-element force, no solver), so both the
+GPU library and the independent CPU checker can take their inputs from here.
+
+Geometry follows the paper's cardiac workloads in shape and size only (the
+image-based left ventricle and valve meshes are not available):
+
+* ``block``  -- a cube of trilinear hexes, stretched 1.1x in x and jittered;
+* ``shell``  -- a truncated ellipsoidal shell (left-ventricle stand-in) with a
+  transmural fibre rotation from -60 deg (epicardium) to +60 deg (endocardium)
+  and an endocardial pressure surface;
+* ``leaflets`` -- two one-element-thick half-annular sheets across the shell
+  base (valve stand-in).
+
+Hex local node ``a = i + 2 j + 4 k`` sits at reference coordinates
+``(xi, eta, zeta) = (2i-1, 2j-1, 2k-1)``; every element is oriented so its
+reference Jacobian is positive.  Quad local node ``a = i + 2 j`` sits at
+``(2i-1, 2j-1)``; every pressure quad is oriented so that
+``dx/dxi x dx/deta`` points out of the solid, into the cavity.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+# material model ids (shared convention of the C interfaces)
+NEO_HOOKEAN = 0
+HOLZAPFEL_OGDEN = 1
+
+HEX_CORNERS = np.array([[i, j, k] for k in (0, 1) for j in (0, 1) for i in (0, 1)],
+                       dtype=np.int64)  # a = i + 2j + 4k
+
+
+@dataclasses.dataclass
+class Material:
+    model: int
+    params: Tuple[float, ...]  # NH: (mu_s, kappa); HO: (a, b, a_f, b_f, kappa)
+
+    def padded(self) -> List[float]:
+        p = list(self.params) + [0.0] * (5 - len(self.params))
+        return p[:5]
+
+
+@dataclasses.dataclass
+class Problem:
+    """One immersed-boundary workload: fluid box, solid mesh and run length."""
+    name: str
+    n: int
+    rho: float
+    mu: float
+    dt: float
+    n_steps: int
+    X_ref: np.ndarray          # [n_nodes, 3] float64, reference configuration
+    X0: np.ndarray             # [n_nodes, 3] float64, initial positions (unwrapped)
+    conn: np.ndarray           # [n_elems, 8] int32
+    fibre: np.ndarray          # [n_elems, 3] float64, unit, reference configuration
+    mat_id: np.ndarray         # [n_elems] int32
+    materials: List[Material]
+    faces: np.ndarray          # [n_faces, 4] int32 endocardial quads (may be empty)
+    p0: float = 0.0            # endocardial pressure amplitude
+    T: float = 1.0             # pressure pulse period: p(t) = p0 sin^2(pi t / T)
+    u0: Optional[np.ndarray] = None   # [3, n, n, n] float64 initial velocity (None = rest)
+    mg_rtol: float = 1e-10
+    mg_pre: int = 2
+    mg_post: int = 2
+    mg_max_cycles: int = 50
+    convection: int = 1
+    precision: str = "fp64"
+
+    @property
+    def h(self) -> float:
+        return 1.0 / self.n
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.X_ref.shape[0])
+
+    @property
+    def n_elems(self) -> int:
+        return int(self.conn.shape[0])
+
+    @property
+    def n_faces(self) -> int:
+        return int(self.faces.shape[0])
+
+    def initial_velocity(self) -> np.ndarray:
+        if self.u0 is None:
+            return np.zeros((3, self.n, self.n, self.n), dtype=np.float64)
+        return self.u0.copy()
+
+    def material_arrays(self) -> Tuple[np.ndarray, np.ndarray]:
+        models = np.array([m.model for m in self.materials], dtype=np.int32)
+        params = np.array([m.padded() for m in self.materials], dtype=np.float64)
+        return models, params
+
+
+# ----------------------------------------------------------------------------
+# structured hex meshing helpers
+# ----------------------------------------------------------------------------
+
+def _signed_volume_at_centre(P: np.ndarray) -> np.ndarray:
+    """Triple product of the three mean edge vectors of each hex ([e, 8, 3])."""
+    ex = (P[:, 1] - P[:, 0] + P[:, 3] - P[:, 2] + P[:, 5] - P[:, 4] + P[:, 7] - P[:, 6])
+    ey = (P[:, 2] - P[:, 0] + P[:, 3] - P[:, 1] + P[:, 6] - P[:, 4] + P[:, 7] - P[:, 5])
+    ez = (P[:, 4] - P[:, 0] + P[:, 5] - P[:, 1] + P[:, 6] - P[:, 2] + P[:, 7] - P[:, 3])
+    return np.einsum("ei,ei->e", ex, np.cross(ey, ez))
+
+
+def _swap_ij(conn: np.ndarray) -> np.ndarray:
+    """Exchange local axes xi and eta (mirrors the element, flips orientation)."""
+    perm = [0, 2, 1, 3, 4, 6, 5, 7]
+    return conn[:, perm]
+
+
+def _orient(conn: np.ndarray, X: np.ndarray) -> np.ndarray:
+    vol = _signed_volume_at_centre(X[conn])
+    conn = conn.copy()
+    neg = vol < 0
+    conn[neg] = _swap_ij(conn[neg])
+    vol2 = _signed_volume_at_centre(X[conn])
+    assert np.all(vol2 > 0), "degenerate hex in generated mesh"
+    return conn
+
+
+def _structured_conn(node_id, ne: Tuple[int, int, int]) -> np.ndarray:
+    """Connectivity of an (ne0, ne1, ne2) block; node_id(i0, i1, i2) -> int arrays."""
+    e0, e1, e2 = np.meshgrid(np.arange(ne[0]), np.arange(ne[1]), np.arange(ne[2]),
+                             indexing="ij")
+    e0, e1, e2 = e0.ravel(order="F"), e1.ravel(order="F"), e2.ravel(order="F")
+    conn = np.empty((e0.size, 8), dtype=np.int64)
+    for a, (i, j, k) in enumerate(HEX_CORNERS):
+        conn[:, a] = node_id(e0 + i, e1 + j, e2 + k)
+    return conn
+
+
+# ----------------------------------------------------------------------------
+# shapes
+# ----------------------------------------------------------------------------
+
+def block_mesh(n_el: int, side: float, centre=(0.5, 0.5, 0.5)):
+    """Regular cube of n_el^3 hexes; returns X_ref [(n_el+1)^3, 3], conn [n_el^3, 8]."""
+    m = n_el + 1
+    t = np.linspace(-0.5 * side, 0.5 * side, m)
+    gx, gy, gz = np.meshgrid(t, t, t, indexing="ij")
+    # node id = i + m (j + m k), x fastest
+    X = np.stack([gx.ravel(order="F"), gy.ravel(order="F"), gz.ravel(order="F")], axis=1)
+    X = X + np.asarray(centre, dtype=np.float64)[None, :]
+
+    def nid(i, j, k):
+        return i + m * (j + m * k)
+    conn = _structured_conn(nid, (n_el, n_el, n_el))
+    return X, _orient(conn, X)
+
+
+def shell_mesh(n_theta: int, n_psi: int, n_tau: int, h: float, cx: float = 0.325):
+    """Truncated ellipsoidal shell.
+
+    Node (it, ip, iq) with theta = 2 pi it / n_theta, psi linear in ip from the
+    apex-hole angle psi_a to pi/2, tau = iq / n_tau (0 = endocardium):
+        X = (cx + A cos psi, 0.5 + B sin psi cos theta, 0.5 + B sin psi sin theta)
+        A = 0.31 + 0.04 tau,  B = 0.21 + 0.04 tau.
+    The apex hole has endocardial radius 2h.  Returns X_ref, conn, fibre, faces.
+    """
+    psi_a = math.asin(2.0 * h / 0.21)
+    th = 2.0 * math.pi * np.arange(n_theta) / n_theta
+    ps = psi_a + (0.5 * math.pi - psi_a) * np.arange(n_psi + 1) / n_psi
+    ta = np.arange(n_tau + 1) / n_tau
+    T3, P3, Q3 = np.meshgrid(th, ps, ta, indexing="ij")
+    A = 0.31 + 0.04 * Q3
+    B = 0.21 + 0.04 * Q3
+    X = np.stack([cx + A * np.cos(P3),
+                  0.5 + B * np.sin(P3) * np.cos(T3),
+                  0.5 + B * np.sin(P3) * np.sin(T3)], axis=-1)
+    X = X.reshape(-1, 3, order="F")
+    nt, npn = n_theta, n_psi + 1
+
+    def nid(it, ip, iq):
+        return (it % nt) + nt * (ip + npn * iq)
+    conn = _structured_conn(nid, (n_theta, n_psi, n_tau))
+    conn = _orient(conn, X)
+
+    # fibre at each element centroid in parameter space
+    e0, e1, e2 = np.meshgrid(np.arange(n_theta), np.arange(n_psi), np.arange(n_tau),
+                             indexing="ij")
+    e0, e1, e2 = e0.ravel(order="F"), e1.ravel(order="F"), e2.ravel(order="F")
+    thc = 2.0 * math.pi * (e0 + 0.5) / n_theta
+    psc = psi_a + (0.5 * math.pi - psi_a) * (e1 + 0.5) / n_psi
+    tac = (e2 + 0.5) / n_tau
+    Ac, Bc = 0.31 + 0.04 * tac, 0.21 + 0.04 * tac
+    d_theta = np.stack([np.zeros_like(thc), -Bc * np.sin(psc) * np.sin(thc),
+                        Bc * np.sin(psc) * np.cos(thc)], axis=1)
+    d_psi = np.stack([-Ac * np.sin(psc), Bc * np.cos(psc) * np.cos(thc),
+                      Bc * np.cos(psc) * np.sin(thc)], axis=1)
+    e_th = d_theta / np.linalg.norm(d_theta, axis=1, keepdims=True)
+    e_ps = d_psi / np.linalg.norm(d_psi, axis=1, keepdims=True)
+    alpha = np.deg2rad(60.0 - 120.0 * tac)        # +60 endo (tau=0) .. -60 epi (tau=1)
+    fibre = np.cos(alpha)[:, None] * e_th + np.sin(alpha)[:, None] * e_ps
+    fibre /= np.linalg.norm(fibre, axis=1, keepdims=True)
+
+    # endocardial quads (iq = 0), oriented to point into the cavity (towards -d/dtau)
+    f0, f1 = np.meshgrid(np.arange(n_theta), np.arange(n_psi), indexing="ij")
+    f0, f1 = f0.ravel(order="F"), f1.ravel(order="F")
+    faces = np.stack([nid(f0, f1, 0), nid(f0 + 1, f1, 0), nid(f0, f1 + 1, 0),
+                      nid(f0 + 1, f1 + 1, 0)], axis=1)
+    faces = _orient_faces(faces, X, inward_ref=nid(f0, f1, 1))
+    return X, conn, fibre, faces
+
+
+def _orient_faces(faces: np.ndarray, X: np.ndarray, inward_ref: np.ndarray) -> np.ndarray:
+    """Orient quads so (x1-x0 + x3-x2) x (x2-x0 + x3-x1) points away from inward_ref."""
+    P = X[faces]
+    exi = P[:, 1] - P[:, 0] + P[:, 3] - P[:, 2]
+    eet = P[:, 2] - P[:, 0] + P[:, 3] - P[:, 1]
+    nrm = np.cross(exi, eet)
+    into_solid = X[inward_ref] - P.mean(axis=1)
+    flip = np.einsum("fi,fi->f", nrm, into_solid) > 0
+    faces = faces.copy()
+    faces[flip] = faces[flip][:, [0, 2, 1, 3]]
+    return faces
+
+
+def leaflet_mesh(k: int, n_theta: int = 64, n_r: int = 32, cx: float = 0.325,
+                 r0: float = 0.03, r1: float = 0.21, thick: float = 0.01):
+    """Half-annular sheet theta in [k pi, (k+1) pi], r in [r0, r1], x in [cx-thick, cx]."""
+    th = math.pi * (k + np.arange(n_theta + 1) / n_theta)
+    rr = r0 + (r1 - r0) * np.arange(n_r + 1) / n_r
+    xx = np.array([cx - thick, cx])
+    T3, R3, X3 = np.meshgrid(th, rr, xx, indexing="ij")
+    X = np.stack([X3, 0.5 + R3 * np.cos(T3), 0.5 + R3 * np.sin(T3)], axis=-1)
+    X = X.reshape(-1, 3, order="F")
+    m0, m1 = n_theta + 1, n_r + 1
+
+    def nid(i, j, q):
+        return i + m0 * (j + m1 * q)
+    conn = _structured_conn(nid, (n_theta, n_r, 1))
+    conn = _orient(conn, X)
+    e0, e1 = np.meshgrid(np.arange(n_theta), np.arange(n_r), indexing="ij")
+    thc = math.pi * (k + (e0.ravel(order="F") + 0.5) / n_theta)
+    fibre = np.stack([np.zeros_like(thc), -np.sin(thc), np.cos(thc)], axis=1)
+    return X, conn, fibre
+
+
+def solenoidal_velocity(n: int, seed: int, amplitude: float, kmax: int = 4) -> np.ndarray:
+    """Random divergence-free MAC velocity [3, n, n, n] (index [d, k, j, i]).
+
+    A smooth random vector potential A (Fourier modes with |k_i| <= kmax) is
+    sampled on cell edges and u = curl A is taken with one-sided differences
+    along the edges, which makes every cell's net face flux vanish identically.
+    Scaled so max |u| = amplitude.
+    """
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    ks = np.arange(-kmax, kmax + 1)
+    modes = [(a, b, c) for a in ks for b in ks for c in ks if (a, b, c) != (0, 0, 0)]
+    coef = rng.standard_normal((3, len(modes), 2))
+    idx = np.arange(n)
+    # edge e carries A_e at: coordinate e at cell centre, the other two at faces (ih)
+    Apot = []
+    for e in range(3):
+        off = [0.0, 0.0, 0.0]
+        off[e] = 0.5
+        xs = [(idx + off[0]) * h, (idx + off[1]) * h, (idx + off[2]) * h]
+        Z, Y, Xg = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+        acc = np.zeros((n, n, n))
+        for m, (a, b, c) in enumerate(modes):
+            ph = 2.0 * math.pi * (a * Xg + b * Y + c * Z)
+            w = 1.0 / (1.0 + a * a + b * b + c * c)
+            acc += w * (coef[e, m, 0] * np.cos(ph) + coef[e, m, 1] * np.sin(ph))
+        Apot.append(acc)
+    Ax, Ay, Az = Apot
+
+    def dfw(q, axis):  # forward difference along array axis (0=z, 1=y, 2=x)
+        return (np.roll(q, -1, axis=axis) - q) / h
+    # u_x at (i h, (j+1/2) h, (k+1/2) h) = dAz/dy - dAy/dz
+    ux = dfw(Az, 1) - dfw(Ay, 0)
+    uy = dfw(Ax, 0) - dfw(Az, 2)
+    uz = dfw(Ay, 2) - dfw(Ax, 1)
+    u = np.stack([ux, uy, uz])
+    u *= amplitude / np.max(np.abs(u))
+    return np.ascontiguousarray(u)
+
+
+# ----------------------------------------------------------------------------
+# the workloads
+# ----------------------------------------------------------------------------
+
+HO_PARAMS = (0.5, 5.0, 1.5, 8.0, 7.0)      # a, b, a_f, b_f, kappa (kappa = 14 a)
+NH_BLOCK = (10.0, 100.0)                   # mu_s, kappa
+
+
+def _block_problem(name, n, n_el, dt, n_steps, material, fibre_seed=None,
+                   seed=0) -> Problem:
+    h = 1.0 / n
+    X_ref, conn = block_mesh(n_el, 0.3)
+    c = np.array([0.5, 0.5, 0.5])
+    rng = np.random.default_rng(seed)
+    X0 = c + (X_ref - c) * np.array([1.1, 1.0, 1.0])
+    X0 = X0 + rng.uniform(-0.05 * h, 0.05 * h, size=X0.shape)
+    ne = conn.shape[0]
+    if fibre_seed is None:
+        fibre = np.tile([1.0, 0.0, 0.0], (ne, 1))
+    else:
+        g = np.random.default_rng(fibre_seed).uniform(-0.25 * math.pi, 0.25 * math.pi, ne)
+        fibre = np.stack([np.cos(g), np.sin(g), np.zeros(ne)], axis=1)
+    return Problem(name=name, n=n, rho=1.0, mu=0.01, dt=dt, n_steps=n_steps,
+                   X_ref=X_ref, X0=X0, conn=conn.astype(np.int32),
+                   fibre=np.ascontiguousarray(fibre, dtype=np.float64),
+                   mat_id=np.zeros(ne, dtype=np.int32), materials=[material],
+                   faces=np.zeros((0, 4), dtype=np.int32))
+
+
+def neo_hookean_block(n: int = 32, n_steps: int = 10, seed: int = 0) -> Problem:
+    """Neo-Hookean 6^3-hex block (343 nodes), side 0.3, 1.1x x-stretch, rest fluid."""
+    return _block_problem("nh_block_32", n, 6, 1e-3, n_steps,
+                          Material(NEO_HOOKEAN, NH_BLOCK), seed=seed)
+
+
+def ho_block(n: int = 64, n_el: int = 12, n_steps: int = 50, seed: int = 0,
+             fibre_seed: int = 1, params=HO_PARAMS) -> Problem:
+    """Holzapfel-Ogden block with fibres (cos g, sin g, 0), g ~ U(-pi/4, pi/4)."""
+    return _block_problem(f"ho_block_{n}", n, n_el, 1e-3, n_steps,
+                          Material(HOLZAPFEL_OGDEN, tuple(params)),
+                          fibre_seed=fibre_seed, seed=seed)
+
+
+def ho_shell(n: int = 128, n_theta: int = 224, n_psi: int = 80, n_tau: int = 6,
+             n_steps: int = 100, dt: float = 5e-4) -> Problem:
+    """Holzapfel-Ogden truncated-ellipsoid shell with endocardial pressure pulse."""
+    h = 1.0 / n
+    X, conn, fibre, faces = shell_mesh(n_theta, n_psi, n_tau, h)
+    ne = conn.shape[0]
+    return Problem(name=f"ho_shell_{n}", n=n, rho=1.0, mu=0.01, dt=dt, n_steps=n_steps,
+                   X_ref=X, X0=X.copy(), conn=conn.astype(np.int32),
+                   fibre=np.ascontiguousarray(fibre), mat_id=np.zeros(ne, dtype=np.int32),
+                   materials=[Material(HOLZAPFEL_OGDEN, HO_PARAMS)],
+                   faces=faces.astype(np.int32), p0=1.0, T=n_steps * dt)
+
+
+def shell_with_leaflets(n: int = 192, n_steps: int = 50, dt: float = 5e-4,
+                        seed: int = 0) -> Problem:
+    """The shell (288 x 104 x 8 hexes) plus two neo-Hookean leaflets and a random
+    divergence-free initial velocity of max amplitude 0.1."""
+    h = 1.0 / n
+    Xs, cs, fs, faces = shell_mesh(288, 104, 8, h)
+    parts_X, parts_c, parts_f, parts_m = [Xs], [cs], [fs], [np.zeros(cs.shape[0], np.int32)]
+    off = Xs.shape[0]
+    for k in (0, 1):
+        Xl, cl, fl = leaflet_mesh(k)
+        parts_X.append(Xl)
+        parts_c.append(cl + off)
+        parts_f.append(fl)
+        parts_m.append(np.ones(cl.shape[0], np.int32))
+        off += Xl.shape[0]
+    X = np.concatenate(parts_X)
+    conn = np.concatenate(parts_c).astype(np.int32)
+    return Problem(name=f"shell_leaflets_{n}", n=n, rho=1.0, mu=0.01, dt=dt,
+                   n_steps=n_steps, X_ref=X, X0=X.copy(), conn=conn,
+                   fibre=np.ascontiguousarray(np.concatenate(parts_f)),
+                   mat_id=np.concatenate(parts_m),
+                   materials=[Material(HOLZAPFEL_OGDEN, HO_PARAMS),
+                              Material(NEO_HOOKEAN, NH_BLOCK)],
+                   faces=faces.astype(np.int32), p0=1.0, T=n_steps * dt,
+                   u0=solenoidal_velocity(n, seed, 0.1))
+
+
+def workload(name: str) -> Problem:
+    """The five named workloads (sizes as in the benchmark table)."""
+    if name == "nh_block_32":        # FP64, 32^3, 10 steps
+        return neo_hookean_block()
+    if name == "ho_shell_128":       # FP64, 128^3, 100 steps (headline)
+        return ho_shell()
+    if name == "shell_leaflets_192":  # FP64, 192^3, 50 steps
+        return shell_with_leaflets()
+    if name == "nh_block_32_mixed":  # mixed precision, 32^3, 100 steps
+        p = neo_hookean_block(n_steps=100)
+        p.name, p.precision = "nh_block_32_mixed", "mixed"
+        return p
+    if name == "ho_block_64":        # adjoint workload, 64^3, 50 steps
+        return ho_block()
+    raise KeyError(name)
+
+
+WORKLOADS = ("nh_block_32", "ho_shell_128", "shell_leaflets_192",
+             "nh_block_32_mixed", "ho_block_64")

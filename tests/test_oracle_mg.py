@@ -1,0 +1,111 @@
+"""Pins of the oracle's geometric multigrid solver (the paper's abstract names a
+geometric multigrid for the fluid solves; the V-cycle itself is this
+implementation's reading).  Checked against closed-form eigen-solutions and an
+independent FFT diagonalisation of the periodic 7-point operator."""
+import math
+
+import numpy as np
+import pytest
+
+from tests.test_oracle_grid import centre_coords
+
+
+def fft_solve(b, sigma, nu):
+    """Solve (sigma - nu Lap_h) x = b on the periodic grid with numpy.fft, using
+    the textbook symbol of the 7-point Laplacian."""
+    n = b.shape[-1]
+    h = 1.0 / n
+    k = np.fft.fftfreq(n) * n
+    s = (4.0 / h ** 2) * np.sin(np.pi * k / n) ** 2
+    lam = s[None, None, :] + s[None, :, None] + s[:, None, None]     # -symbol >= 0
+    den = sigma + nu * lam
+    bh = np.fft.fftn(b)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        xh = np.where(den == 0, 0.0, bh / den)
+    return np.real(np.fft.ifftn(xh))
+
+
+@pytest.mark.parametrize("n", [16, 24, 32])
+def test_poisson_manufactured_eigenmode(ref, n):
+    fl = ref.fluid(n, rtol=1e-12)
+    X, Y, Z = centre_coords(n)
+    mode = np.sin(2 * math.pi * X) * np.sin(2 * math.pi * Y) * np.sin(2 * math.pi * Z)
+    h = 1.0 / n
+    lam = -3 * (4 / h ** 2) * math.sin(math.pi * h) ** 2
+    x, cyc, rr = ref.mg_solve(fl, 0.0, 1.0, True, -lam * mode)
+    assert rr <= 1e-12 and cyc <= 25
+    assert np.max(np.abs(x - mode)) < 1e-10
+
+
+def test_helmholtz_single_mode_factor(ref):
+    n = 32
+    fl = ref.fluid(n, rtol=1e-13)
+    X, Y, Z = centre_coords(n)
+    mode = np.cos(2 * math.pi * (X + 2 * Y)) * np.sin(2 * math.pi * Z)
+    h = 1.0 / n
+    lam = -(4 / h ** 2) * (math.sin(math.pi * h) ** 2 + math.sin(2 * math.pi * h) ** 2
+                           + math.sin(math.pi * h) ** 2)
+    sigma, nu = 1000.0, 0.01
+    x, cyc, rr = ref.mg_solve(fl, sigma, nu, False, mode)
+    assert np.max(np.abs(x - mode / (sigma - nu * lam))) < 1e-15 * 1e3
+
+
+@pytest.mark.parametrize("n,sigma,nu,poisson", [(32, 0.0, 1.0, True), (24, 0.0, 1.0, True),
+                                                (32, 2000.0, 0.01, False), (16, 5.0, 1.0, False)])
+def test_matches_fft_solution(ref, n, sigma, nu, poisson):
+    rng = np.random.default_rng(n)
+    b = rng.standard_normal((n, n, n))
+    if poisson:
+        b -= b.mean()
+    fl = ref.fluid(n, rtol=1e-10)
+    x, cyc, rr = ref.mg_solve(fl, sigma, nu, poisson, b)
+    xf = fft_solve(b, sigma, nu)
+    assert rr <= 1e-10
+    assert np.max(np.abs(x - xf)) <= 1e-8 * np.max(np.abs(xf))
+    if poisson:
+        assert abs(x.mean()) < 1e-14 * np.abs(x).max()
+
+
+def test_vcycle_contraction(ref):
+    """Residual reduction per V(2,2) cycle on a rough right-hand side."""
+    n = 32
+    rng = np.random.default_rng(0)
+    b = rng.standard_normal((n, n, n))
+    b -= b.mean()
+    rr = []
+    for k in (1, 2, 3, 4):
+        fl = ref.fluid(n, fixed_cycles=k)
+        _, cyc, r = ref.mg_solve(fl, 0.0, 1.0, True, b)
+        assert cyc == k
+        rr.append(r)
+    rates = [rr[i + 1] / rr[i] for i in range(3)]
+    assert max(rates) < 0.25, rates   # asymptotic rate of this cycle is about 0.21
+
+
+def test_zero_rhs_and_error_paths(ref):
+    import oracle
+    n = 16
+    fl = ref.fluid(n)
+    x, cyc, rr = ref.mg_solve(fl, 0.0, 1.0, True, np.zeros((n, n, n)), np.ones((n, n, n)))
+    assert cyc == 0 and np.all(x == 0)
+    b = np.random.default_rng(1).standard_normal((n, n, n))
+    b -= b.mean()
+    with pytest.raises(oracle.OracleError) as e:
+        ref.mg_solve(ref.fluid(n, max_cycles=1), 0.0, 1.0, True, b)
+    assert e.value.rc == oracle.E_NOCONV
+    b[3, 2, 1] = np.nan
+    with pytest.raises(oracle.OracleError) as e:
+        ref.mg_solve(fl, 0.0, 1.0, True, b)
+    assert e.value.rc == oracle.E_NUMERIC
+    with pytest.raises(oracle.OracleError) as e:
+        ref.mg_solve(ref.fluid(20), 0.0, 1.0, True, np.ones((20, 20, 20)))
+    assert e.value.rc == oracle.E_INVAL   # 20 -> 10 -> 5: odd level breaks red-black
+
+
+def test_initial_guess_at_solution_needs_no_cycle(ref):
+    n = 16
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal((n, n, n))
+    xs = fft_solve(b, 50.0, 1.0)
+    x, cyc, rr = ref.mg_solve(ref.fluid(n), 50.0, 1.0, False, b, xs)
+    assert cyc == 0 and np.array_equal(x, xs)
