@@ -1,0 +1,144 @@
+#!/usr/bin/env python3
+"""Throughput of the matrix-free immersed-boundary step on one MI355X.
+
+Workload: the 128^3 Holzapfel-Ogden truncated-ellipsoid shell (127,008 nodes,
+107,520 trilinear hexes, 17,920 endocardial pressure quads), dt = 5e-4,
+p(t) = sin^2(pi t / T) with T = 100 dt, FP64, synthetic inputs from
+paper_2503_22695_amd.inputs.  One step = FE force + pressure load, explicit
+convection right-hand side, spreading, three Helmholtz and one Poisson
+multigrid solve (V(2,2) to 1e-10), projection, interpolation and position
+update, all in libhipib's HIP kernels.
+
+Prints one JSON line.  `value` is steps/s over the timed steps with every input
+already resident in HBM.  `roofline` is for the dominant kernel (the finest
+level red/black Gauss-Seidel sweep of the Poisson solve), timed with HIP events
+on the launch stream during the timed region.  `cpu_baseline` is the FP64 CPU
+checker timed on this host on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "IB steps/s at 128^3 HO shell: FP64 vs mixed-prec (err≤1e-6); adjoint/fwd time"
+
+
+def cpu_threads() -> int:
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(prob, seconds: float):
+    """The CPU checker as it stands, timed on consecutive steps of the same
+    workload from its initial state until `seconds` have elapsed."""
+    import numpy as np
+    import oracle
+    fl = oracle.fluid_from_problem(prob)
+    mesh = oracle.MeshBuffers.from_problem(prob)
+    u = prob.initial_velocity()
+    p = np.zeros((prob.n,) * 3)
+    X = prob.X0.copy()
+    steps, t = 0, 0.0
+    start = time.perf_counter()
+    while steps < 1 or time.perf_counter() - start < seconds:
+        u, p, X, _ = oracle.advance(fl, mesh, u, p, X, t, 1, prob.p0, prob.T)
+        t += prob.dt
+        steps += 1
+    el = time.perf_counter() - start
+    return {"value": steps / el, "unit": "steps/s", "cores": cpu_threads(), "kind": "oracle",
+            "sample": f"first {steps} steps of the 128^3 shell workload from t=0 "
+                      f"({el:.1f} s, FP64 C with OpenMP grid loops)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs one GPU only (the step is not sharded across GPUs); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2503_22695_amd import hipib, inputs
+
+    torch.cuda.set_device(0)
+    prob = inputs.ho_shell()
+    sim = hipib.Simulation(prob)
+    ctx = sim.ctx
+
+    # warm-up on a copy of the initial state (also settles the predicted cycle counts)
+    u, p, X = sim.u.clone(), sim.p.clone(), sim.X.clone()
+    if args.warmup > 0:
+        ctx.advance(u, p, X, 0.0, args.warmup, prob.p0, prob.T)
+    torch.cuda.synchronize()
+    del u, p, X
+
+    ctx.timer_enable(hipib.TIMER_SMOOTH_FINE_POISSON)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.advance(sim.u, sim.p, sim.X, 0.0, args.steps, prob.p0, prob.T)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launches, kernel_ms, bytes_per_launch = ctx.timer_read()
+    ctx.timer_enable(hipib.TIMER_OFF)
+    cyc, _ = ctx.step_stats()
+
+    elapsed = t1 - t0
+    steps_per_s = args.steps / elapsed
+    if not (torch.isfinite(sim.u).all() and torch.isfinite(sim.X).all()):
+        raise RuntimeError("non-finite state after the timed run")
+
+    avg_s = kernel_ms * 1e-3 / max(launches, 1)
+    achieved = bytes_per_launch / avg_s / 1e9 if launches else 0.0
+    roofline = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "kernel": "k_gs_colour<2>: finest-level red or black Gauss-Seidel sweep of the Poisson solve",
+        "bytes_per_launch": bytes_per_launch, "launches": launches,
+        "avg_launch_us": round(avg_s * 1e6, 3),
+    }
+    out = {
+        "metric": METRIC,
+        "value": round(steps_per_s, 3),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "ho_shell_128", "grid": prob.n, "nodes": prob.n_nodes,
+                   "hexes": prob.n_elems, "pressure_quads": prob.n_faces, "dt": prob.dt,
+                   "mg": "V(2,2) red-black GS, rtol 1e-10",
+                   "mg_cycles_per_step": {"helmholtz_max_component": float(np.mean(cyc[:, :3].max(1))),
+                                          "poisson": float(np.mean(cyc[:, 3]))}},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,161 @@
+/*
+ * hipib -- matrix-free immersed-boundary timestep on AMD Instinct MI355X (gfx950).
+ *
+ * Implements the fully discrete scheme of Ma, Cai, Wang, Luo and Gao, "Fully
+ * GPU-Accelerated Immersed Boundary Method for Fluid-Structure Interaction in
+ * Complex Cardiac Models": given u^n and X^n, find u^{n+1}, p^{n+1}, X^{n+1}
+ * (section "Spatial Discretization") with
+ *   - nodal forces F_i = -sum_q P(X_q) : grad N_i(X_q) w_q, evaluated element by
+ *     element without any assembled matrix ("Eulerian-Lagrangian coupling
+ *     operators"; laws from "Constitutive laws");
+ *   - spreading f = S(X^n) F and interpolation U = J(X^n) u^{n+1} through the
+ *     4-point Peskin delta on the staggered (MAC) grid;
+ *   - a Chorin projection step (Helmholtz solve, Poisson solve, velocity
+ *     correction) whose solves use geometric multigrid (named in the abstract).
+ *
+ * Layout (all device arrays contiguous, FP64, caller-owned):
+ *   grid     periodic unit cube, n cells per side, h = 1/n; scalars [n][n][n]
+ *            with x fastest (idx = i + n*(j + n*k)); vectors [3][n][n][n];
+ *            u^d[i,j,k] sits at coordinate i*h along d and (.+1/2)h along the
+ *            other two axes, p at cell centres.
+ *   nodes    X[n_nodes][3], unwrapped positions (stencil indices wrap).
+ *   hexes    conn[n_elems][8], local node a = i + 2j + 4k at (2i-1,2j-1,2k-1).
+ *   quads    faces[n_faces][4], local node a = i + 2j; dx/dxi x dx/deta points
+ *            out of the solid into the loaded cavity.
+ *
+ * Streams: every call is enqueued on the context's stream and returns without
+ * waiting, except calls that return host values (hipib_mg_solve,
+ * hipib_ns_step, hipib_ib_step, hipib_advance: they wait for the multigrid
+ * stop decisions).  The context keeps no pointer to caller arrays after a call.
+ *
+ * Errors: every call returns a status and never aborts across the boundary;
+ * hipib_last_error() returns a message for the calling thread's last failure.
+ * Argument errors (null or misaligned pointer, bad size, index out of range)
+ * return HIPIB_E_INVAL before anything is enqueued.  A HIP runtime failure
+ * makes the context unusable (HIPIB_E_HIP from then on).  After any error the
+ * contents of output arrays are unspecified.
+ */
+#ifndef HIPIB_H
+#define HIPIB_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hipib_ctx hipib_ctx;
+
+typedef enum {
+    HIPIB_OK = 0,
+    HIPIB_E_INVAL = 1,    /* bad argument; nothing was enqueued */
+    HIPIB_E_NOMEM = 2,    /* device allocation failed */
+    HIPIB_E_HIP = 3,      /* HIP runtime error; the context is unusable */
+    HIPIB_E_NOCONV = 4,   /* multigrid reached mg_max_cycles */
+    HIPIB_E_NUMERIC = 5,  /* non-finite residual, or J <= 0 at a Gauss point */
+    HIPIB_E_STATE = 6     /* call before hipib_set_mesh / missing material */
+} hipib_status;
+
+typedef enum { HIPIB_FP64 = 0, HIPIB_MIXED = 1 } hipib_precision;
+typedef enum { HIPIB_NEO_HOOKEAN = 0, HIPIB_HOLZAPFEL_OGDEN = 1 } hipib_model;
+typedef enum { HIPIB_OP_HELMHOLTZ = 0, HIPIB_OP_POISSON = 1 } hipib_op;
+
+#define HIPIB_MAX_MATERIALS 8
+
+typedef struct {
+    int32_t n;                /* cells per side: c * 2^k, c in {4, 6}, n >= 8 */
+    double rho, mu, dt;       /* density, viscosity, time step (all > 0) */
+    int32_t mg_pre, mg_post;  /* red+black smoothing sweeps before / after the
+                                 coarse-grid correction (V(2,2): 2, 2) */
+    int32_t mg_max_cycles;    /* more cycles than this: HIPIB_E_NOCONV */
+    int32_t mg_fixed_cycles;  /* > 0: exactly this many cycles, no stop test */
+    int32_t mg_coarse_sweeps; /* red+black sweeps on the coarsest level (64) */
+    double mg_rtol;           /* stop when ||b - A x||_2 <= rtol ||b||_2 */
+    int32_t convection;       /* 1: explicit flux-form convection; 0: Stokes */
+    int32_t precision;        /* hipib_precision */
+    int32_t deterministic;    /* 1: atomic-free, bitwise run-to-run reproducible */
+} hipib_config;
+
+/* Fills cfg with the defaults: V(2,2), 64 coarse sweeps, rtol 1e-10, 50 cycles,
+ * convection on, FP64, atomic mode; n/rho/mu/dt are set to 32/1/0.01/1e-3. */
+void hipib_default_config(hipib_config* cfg);
+
+/* Creates a context for one grid on the current HIP device.  stream is a
+ * hipStream_t (NULL: the null stream).  Allocates every grid workspace. */
+hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out);
+hipib_status hipib_destroy(hipib_ctx* ctx);
+hipib_status hipib_set_stream(hipib_ctx* ctx, void* stream);
+const char* hipib_last_error(void);
+
+/* --- set-up (host arrays, copied into the context) ---------------------- */
+/* Lagrangian mesh: X_ref [n_nodes][3], conn [n_elems][8] (0 <= conn < n_nodes),
+ * fibre [n_elems][3] (unit e_f in the reference configuration), mat_id
+ * [n_elems] (0 <= mat_id < HIPIB_MAX_MATERIALS).  n_nodes may be 0. */
+hipib_status hipib_set_mesh(hipib_ctx* ctx, int32_t n_nodes, const double* X_ref,
+                            int32_t n_elems, const int32_t* conn, const double* fibre,
+                            const int32_t* mat_id);
+/* Material law of one id ("Constitutive laws"): neo-Hookean params
+ * (mu_s, kappa), Psi = mu_s/2 (I1bar - 3) + kappa/2 (ln J)^2; Holzapfel-Ogden
+ * params (a, b, a_f, b_f, kappa), Psi = a/(2b)(e^{b(I1bar-3)} - 1)
+ * + a_f/(2b_f)(e^{b_f (I4f*-1)^2} - 1) + kappa/2 (ln J)^2, I4f* = max(I4f, 1). */
+hipib_status hipib_set_material(hipib_ctx* ctx, int32_t mat_id, int32_t model,
+                                const double* params, int32_t n_params);
+/* Quads loaded by the uniform cavity pressure (host [n_faces][4]). */
+hipib_status hipib_set_pressure_faces(hipib_ctx* ctx, int32_t n_faces, const int32_t* faces);
+
+/* --- hot path (device arrays) -------------------------------------------- */
+/* F := -sum_e sum_g P(F_g) : grad N_a w_g  (2x2x2 Gauss)  +  the follower load
+ * -pressure * integral N_a (dx/dxi x dx/deta) over the pressure faces.
+ * X, F: [n_nodes][3]. */
+hipib_status hipib_fe_force(hipib_ctx* ctx, const double* X, double pressure, double* F);
+/* f += S(X) F:  f^d[idx] += sum_q F^d_q delta_h(x^d_idx - X_q).  f: [3][n^3]. */
+hipib_status hipib_spread(hipib_ctx* ctx, const double* X, const double* F, double* f);
+/* U := J(X) u:  U^d_q = sum_idx u^d[idx] delta_h(x^d_idx - X_q) h^3. */
+hipib_status hipib_interpolate(hipib_ctx* ctx, const double* X, const double* u, double* U);
+/* Solves (sigma I - nu Lap_h) x = b for ncomp independent components
+ * (component stride n^3): Helmholtz sigma = rho/dt, nu = mu; Poisson sigma = 0,
+ * nu = 1 (right-hand side must have zero mean; x is returned mean-free).
+ * x holds the initial guess on entry.  cycles/relres: host arrays [ncomp]
+ * (may be NULL).  Waits for completion. */
+hipib_status hipib_mg_solve(hipib_ctx* ctx, int32_t op, int32_t ncomp, const double* b,
+                            double* x, int32_t* cycles, double* relres);
+/* One fluid step with force density f ([3][n^3], may be NULL = 0):
+ *   ((rho/dt) I - mu Lap_h) u* = (rho/dt) u - rho C(u) + f   (guess u)
+ *   (-Lap_h) p = -(rho/dt) D u* (mean removed)                 (guess p)
+ *   u := u* - (dt/rho) G p.        u: [3][n^3] in/out, p: [n^3] in/out. */
+hipib_status hipib_ns_step(hipib_ctx* ctx, const double* f, double* u, double* p);
+/* One immersed-boundary step with explicit coupling: F(X^n) incl. pressure,
+ * f = S(X^n)F, ns_step, X += dt J(X^n) u^{n+1}.  X: [n_nodes][3] in/out. */
+hipib_status hipib_ib_step(hipib_ctx* ctx, double* u, double* p, double* X, double pressure);
+/* n_steps IB steps from time t0 with cavity pressure p0 sin^2(pi t_n / T)
+ * (0 when T <= 0), t_n = t0 + n dt. */
+hipib_status hipib_advance(hipib_ctx* ctx, double* u, double* p, double* X, double t0,
+                           int32_t n_steps, double p0, double T);
+
+/* Per-step records of the last hipib_advance / hipib_ib_step / hipib_ns_step
+ * call: cycles[s][4] and relres[s][4] (Helmholtz x, y, z, Poisson) for
+ * s < min(max_steps, steps recorded).  Returns the number of records. */
+int32_t hipib_get_step_stats(hipib_ctx* ctx, int32_t* cycles, double* relres,
+                             int32_t max_steps);
+
+/* --- measurement -------------------------------------------------------- */
+/* Kernel classes that can be timed with HIP events (each launch is bracketed
+ * by a pair of events recorded on the context's stream). */
+typedef enum {
+    HIPIB_TIMER_OFF = 0,
+    /* one red or black Gauss-Seidel sweep on the finest level of a Poisson
+     * solve; algorithmic traffic 12 bytes per cell (read the other colour's
+     * half of x and this colour's half of b, write this colour's half of x) */
+    HIPIB_TIMER_SMOOTH_FINE_POISSON = 1
+} hipib_timer;
+/* Selects the timed kernel class and clears earlier timings. */
+hipib_status hipib_timer_enable(hipib_ctx* ctx, int32_t which);
+/* Waits for the stream, then returns the number of timed launches, their total
+ * duration in milliseconds and the algorithmic bytes one launch moves; clears
+ * the accumulated timings. */
+hipib_status hipib_timer_read(hipib_ctx* ctx, int32_t* launches, double* total_ms,
+                              double* bytes_per_launch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -257,11 +257,12 @@ def advance(fl: Fluid, mesh: MeshBuffers, u, p, X, t0: float, n_steps: int, p0=0
     return u, p, X, [stats[i] for i in range(n_steps)]
 
 
-def run_problem(prob, n_steps: Optional[int] = None, **fluid_over):
-    """Advance a generated workload from its initial state; returns u, p, X, stats."""
+def run_problem(prob, n_steps: Optional[int] = None, t0: float = 0.0, **fluid_over):
+    """Advance a generated workload from its initial state (at time t0);
+    returns u, p, X, stats."""
     fl = fluid_from_problem(prob, **fluid_over)
     mesh = MeshBuffers.from_problem(prob)
     u0 = prob.initial_velocity()
     p0 = np.zeros((prob.n,) * 3)
     steps = prob.n_steps if n_steps is None else n_steps
-    return advance(fl, mesh, u0, p0, prob.X0, 0.0, steps, prob.p0, prob.T)
+    return advance(fl, mesh, u0, p0, prob.X0, t0, steps, prob.p0, prob.T)

@@ -1,0 +1,450 @@
+// C-ABI entry points of libhipib: argument validation, context lifetime and
+// the order of one immersed-boundary step ("Spatial Discretization"):
+//   F = F_el(X^n) + F_pressure(X^n);  g = (rho/dt) u^n - rho C(u^n) + S(X^n) F;
+//   ((rho/dt) - mu Lap_h) u* = g;  (-Lap_h) p = -(rho/dt) D u*;
+//   u^{n+1} = u* - (dt/rho) G p;  X^{n+1} = X^n + dt J(X^n) u^{n+1}.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.h"
+
+namespace hipib {
+
+static thread_local char g_err[512] = "";
+
+hipib_status fail(hipib_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+hipib_status hip_fail(hipib_ctx* ctx, hipError_t e, const char* what, const char* file, int line) {
+    if (ctx) ctx->broken = true;
+    return fail(HIPIB_E_HIP, "HIP error %d (%s) in %s at %s:%d", (int)e, hipGetErrorString(e), what,
+                file, line);
+}
+
+}  // namespace hipib
+
+using namespace hipib;
+
+namespace {
+
+bool aligned8(const void* p) { return p != nullptr && (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+hipib_status check_ctx(hipib_ctx* ctx) {
+    if (!ctx) return fail(HIPIB_E_INVAL, "null context");
+    if (ctx->broken) return fail(HIPIB_E_HIP, "context unusable after an earlier HIP error");
+    return HIPIB_OK;
+}
+
+hipib_status check_mesh_ready(hipib_ctx* ctx) {
+    if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
+    const uint32_t missing = ctx->mat_used & ~ctx->mat_set;
+    if (missing) {
+        for (int m = 0; m < HIPIB_MAX_MATERIALS; ++m)
+            if (missing & (1u << m)) return fail(HIPIB_E_STATE, "material %d is used but not set", m);
+    }
+    return HIPIB_OK;
+}
+
+template <typename T>
+hipib_status dev_alloc(hipib_ctx* ctx, T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HIPIB_E_NOMEM, "hipMalloc of %zu bytes failed", count * sizeof(T));
+    }
+    (void)ctx;
+    return HIPIB_OK;
+}
+
+void free_mesh(hipib_ctx* ctx) {
+    (void)hipFree(ctx->Xref);
+    (void)hipFree(ctx->conn);
+    (void)hipFree(ctx->fibre);
+    (void)hipFree(ctx->mat_id);
+    (void)hipFree(ctx->F);
+    ctx->Xref = nullptr;
+    ctx->conn = nullptr;
+    ctx->fibre = nullptr;
+    ctx->mat_id = nullptr;
+    ctx->F = nullptr;
+    ctx->mesh_set = false;
+    ctx->nn = ctx->ne = 0;
+    ctx->mat_used = 0;
+}
+
+void free_all(hipib_ctx* ctx) {
+    free_mesh(ctx);
+    (void)hipFree(ctx->faces);
+    for (int l = 0; l < kMaxLevels; ++l) {
+        (void)hipFree(ctx->lv[l].x);
+        (void)hipFree(ctx->lv[l].b);
+    }
+    (void)hipFree(ctx->r0);
+    (void)hipFree(ctx->g);
+    (void)hipFree(ctx->bp);
+    (void)hipFree(ctx->part);
+    (void)hipFree(ctx->st);
+    if (ctx->st_host) (void)hipHostFree(ctx->st_host);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    ctx->ev_pool.clear();
+}
+
+void record_step(hipib_ctx* ctx, const int32_t* cyc, const double* rr) {
+    StepRecord r;
+    for (int t = 0; t < 4; ++t) {
+        r.cycles[t] = cyc[t];
+        r.relres[t] = rr[t];
+    }
+    ctx->recs.push_back(r);
+}
+
+// fluid part of a step: g holds the Helmholtz right-hand side on entry
+hipib_status fluid_solves(hipib_ctx* ctx, double* u, double* p) {
+    int32_t cyc[4] = {0, 0, 0, 0};
+    double rr[4] = {0, 0, 0, 0};
+    HIPIB_TRY(mg_solve(ctx, HIPIB_OP_HELMHOLTZ, 3, ctx->g, u, cyc, rr));
+    HIPIB_TRY(launch_divergence_rhs(ctx, u, ctx->bp));
+    HIPIB_TRY(mg_remove_mean(ctx, ctx->bp, 0));
+    HIPIB_TRY(mg_solve(ctx, HIPIB_OP_POISSON, 1, ctx->bp, p, cyc + 3, rr + 3));
+    HIPIB_TRY(launch_project(ctx, u, p));
+    record_step(ctx, cyc, rr);
+    return HIPIB_OK;
+}
+
+hipib_status ib_step(hipib_ctx* ctx, double* u, double* p, double* X, double pressure) {
+    HIPIB_TRY(launch_fe_force(ctx, X, pressure, ctx->F));
+    HIPIB_TRY(launch_rhs_build(ctx, u, nullptr, ctx->g));
+    HIPIB_TRY(launch_spread(ctx, X, ctx->F, ctx->g));
+    HIPIB_TRY(fluid_solves(ctx, u, p));
+    if (ctx->st_host->numeric)
+        return fail(HIPIB_E_NUMERIC, "non-positive Jacobian at a Gauss point (inverted element)");
+    HIPIB_TRY(launch_interpolate(ctx, X, u, nullptr, X, ctx->cfg.dt));
+    return HIPIB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hipib_default_config(hipib_config* cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->n = 32;
+    cfg->rho = 1.0;
+    cfg->mu = 0.01;
+    cfg->dt = 1e-3;
+    cfg->mg_pre = 2;
+    cfg->mg_post = 2;
+    cfg->mg_max_cycles = 50;
+    cfg->mg_fixed_cycles = 0;
+    cfg->mg_coarse_sweeps = 64;
+    cfg->mg_rtol = 1e-10;
+    cfg->convection = 1;
+    cfg->precision = HIPIB_FP64;
+    cfg->deterministic = 0;
+}
+
+const char* hipib_last_error(void) { return g_err; }
+
+hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out) {
+    if (!cfg || !out) return fail(HIPIB_E_INVAL, "null argument");
+    *out = nullptr;
+    const int n = cfg->n;
+    if (n < 8 || n > 1024) return fail(HIPIB_E_INVAL, "n = %d outside [8, 1024]", n);
+    {
+        int m = n;
+        while (m >= 8) {
+            if (m % 2) return fail(HIPIB_E_INVAL, "n = %d: a multigrid level has odd size %d", n, m);
+            m /= 2;
+        }
+        if (m != 4 && m != 6) return fail(HIPIB_E_INVAL, "n = %d is not 4*2^k or 6*2^k", n);
+    }
+    if (!(cfg->rho > 0) || !(cfg->mu > 0) || !(cfg->dt > 0))
+        return fail(HIPIB_E_INVAL, "rho, mu and dt must be positive");
+    if (cfg->mg_pre < 0 || cfg->mg_post < 0 || cfg->mg_max_cycles < 1 || cfg->mg_fixed_cycles < 0 ||
+        cfg->mg_coarse_sweeps < 1 || !(cfg->mg_rtol >= 0))
+        return fail(HIPIB_E_INVAL, "invalid multigrid parameters");
+    if (cfg->precision != HIPIB_FP64)
+        return fail(HIPIB_E_INVAL, "precision %d is not available in this build", cfg->precision);
+    if (cfg->deterministic != 0)
+        return fail(HIPIB_E_INVAL, "deterministic mode is not available in this build");
+
+    hipib_ctx* ctx = new hipib_ctx();
+    ctx->cfg = *cfg;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    (void)hipGetDevice(&ctx->device);
+    ctx->n = n;
+    ctx->n3 = (int64_t)n * n * n;
+    ctx->h = 1.0 / n;
+    int L = 0, m = n;
+    while (true) {
+        ctx->lv[L].n = m;
+        ctx->lv[L].n3 = (int64_t)m * m * m;
+        ++L;
+        if (m < 8) break;
+        m /= 2;
+    }
+    ctx->L = L;
+    ctx->small_start = L - 1;
+    for (int l = 0; l < L; ++l)
+        if (ctx->lv[l].n <= kSmallMax) { ctx->small_start = l; break; }
+    size_t lds = 0;
+    for (int l = ctx->small_start; l < L; ++l) lds += 3 * (size_t)ctx->lv[l].n3 * sizeof(double);
+    ctx->small_lds = lds;
+
+    hipib_status s = HIPIB_OK;
+    for (int l = 1; l < L && s == HIPIB_OK; ++l) {
+        s = dev_alloc(ctx, &ctx->lv[l].x, 3 * (size_t)ctx->lv[l].n3);
+        if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->lv[l].b, 3 * (size_t)ctx->lv[l].n3);
+    }
+    if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->r0, 3 * (size_t)ctx->n3);
+    if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->g, 3 * (size_t)ctx->n3);
+    if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->bp, (size_t)ctx->n3);
+    ctx->part_cap = 3 * (((int64_t)(n + 63) / 64) * ((n + 3) / 4) * n + 1024);
+    if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->part, (size_t)ctx->part_cap);
+    if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->st, 1);
+    if (s == HIPIB_OK) {
+        hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&ctx->st_host), sizeof(MGState));
+        if (e != hipSuccess) s = fail(HIPIB_E_NOMEM, "pinned host allocation failed");
+        else std::memset(ctx->st_host, 0, sizeof(MGState));
+    }
+    if (s == HIPIB_OK) s = mg_prepare(ctx);
+    if (s == HIPIB_OK) {
+        hipError_t e = hipMemsetAsync(ctx->st, 0, sizeof(MGState), ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) s = fail(HIPIB_E_HIP, "HIP error %d initialising the context", (int)e);
+    }
+    if (s != HIPIB_OK) {
+        free_all(ctx);
+        delete ctx;
+        return s;
+    }
+    *out = ctx;
+    return HIPIB_OK;
+}
+
+hipib_status hipib_destroy(hipib_ctx* ctx) {
+    if (!ctx) return HIPIB_OK;
+    (void)hipStreamSynchronize(ctx->stream);
+    free_all(ctx);
+    delete ctx;
+    return HIPIB_OK;
+}
+
+hipib_status hipib_set_stream(hipib_ctx* ctx, void* stream) {
+    if (!ctx) return fail(HIPIB_E_INVAL, "null context");
+    ctx->stream = static_cast<hipStream_t>(stream);
+    return HIPIB_OK;
+}
+
+hipib_status hipib_set_mesh(hipib_ctx* ctx, int32_t n_nodes, const double* X_ref, int32_t n_elems,
+                            const int32_t* conn, const double* fibre, const int32_t* mat_id) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (n_nodes < 0 || n_elems < 0) return fail(HIPIB_E_INVAL, "negative mesh size");
+    if (n_elems > 0 && n_nodes == 0) return fail(HIPIB_E_INVAL, "elements without nodes");
+    if (n_nodes > 0 && !X_ref) return fail(HIPIB_E_INVAL, "null X_ref");
+    if (n_elems > 0 && (!conn || !fibre || !mat_id)) return fail(HIPIB_E_INVAL, "null element array");
+    uint32_t used = 0;
+    for (int64_t t = 0; t < 8 * (int64_t)n_elems; ++t)
+        if (conn[t] < 0 || conn[t] >= n_nodes)
+            return fail(HIPIB_E_INVAL, "conn[%lld] = %d out of range", (long long)t, conn[t]);
+    for (int32_t e = 0; e < n_elems; ++e) {
+        if (mat_id[e] < 0 || mat_id[e] >= HIPIB_MAX_MATERIALS)
+            return fail(HIPIB_E_INVAL, "mat_id[%d] = %d out of range", e, mat_id[e]);
+        used |= 1u << mat_id[e];
+    }
+    for (int64_t t = 0; t < 3 * (int64_t)n_nodes; ++t)
+        if (!std::isfinite(X_ref[t])) return fail(HIPIB_E_INVAL, "non-finite X_ref");
+    for (int64_t t = 0; t < 3 * (int64_t)n_elems; ++t)
+        if (!std::isfinite(fibre[t])) return fail(HIPIB_E_INVAL, "non-finite fibre");
+    HIPIB_HIP(hipStreamSynchronize(ctx->stream));
+    free_mesh(ctx);
+    // pressure faces refer to the previous mesh's nodes: drop them
+    (void)hipFree(ctx->faces);
+    ctx->faces = nullptr;
+    ctx->nf = 0;
+    HIPIB_TRY(dev_alloc(ctx, &ctx->Xref, 3 * (size_t)n_nodes));
+    HIPIB_TRY(dev_alloc(ctx, &ctx->F, 3 * (size_t)n_nodes));
+    HIPIB_TRY(dev_alloc(ctx, &ctx->conn, 8 * (size_t)n_elems));
+    HIPIB_TRY(dev_alloc(ctx, &ctx->fibre, 3 * (size_t)n_elems));
+    HIPIB_TRY(dev_alloc(ctx, &ctx->mat_id, (size_t)n_elems));
+    if (n_nodes > 0)
+        HIPIB_HIP(hipMemcpy(ctx->Xref, X_ref, 3 * sizeof(double) * n_nodes, hipMemcpyHostToDevice));
+    if (n_elems > 0) {
+        HIPIB_HIP(hipMemcpy(ctx->conn, conn, 8 * sizeof(int32_t) * n_elems, hipMemcpyHostToDevice));
+        HIPIB_HIP(hipMemcpy(ctx->fibre, fibre, 3 * sizeof(double) * n_elems, hipMemcpyHostToDevice));
+        HIPIB_HIP(hipMemcpy(ctx->mat_id, mat_id, sizeof(int32_t) * n_elems, hipMemcpyHostToDevice));
+    }
+    ctx->nn = n_nodes;
+    ctx->ne = n_elems;
+    ctx->mat_used = used;
+    ctx->mesh_set = true;
+    return HIPIB_OK;
+}
+
+hipib_status hipib_set_material(hipib_ctx* ctx, int32_t mat_id, int32_t model, const double* params,
+                                int32_t n_params) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (mat_id < 0 || mat_id >= HIPIB_MAX_MATERIALS) return fail(HIPIB_E_INVAL, "mat_id out of range");
+    if (!params) return fail(HIPIB_E_INVAL, "null params");
+    double p[5] = {0, 0, 0, 0, 0};
+    if (model == HIPIB_NEO_HOOKEAN) {
+        if (n_params != 2) return fail(HIPIB_E_INVAL, "neo-Hookean takes (mu_s, kappa)");
+        if (!(params[0] >= 0) || !(params[1] >= 0)) return fail(HIPIB_E_INVAL, "negative modulus");
+    } else if (model == HIPIB_HOLZAPFEL_OGDEN) {
+        if (n_params != 5) return fail(HIPIB_E_INVAL, "Holzapfel-Ogden takes (a, b, a_f, b_f, kappa)");
+        if (!(params[0] >= 0) || !(params[1] > 0) || !(params[2] >= 0) || !(params[3] > 0) ||
+            !(params[4] >= 0))
+            return fail(HIPIB_E_INVAL, "Holzapfel-Ogden needs a, a_f, kappa >= 0 and b, b_f > 0");
+    } else {
+        return fail(HIPIB_E_INVAL, "unknown material model %d", model);
+    }
+    for (int t = 0; t < n_params; ++t) {
+        if (!std::isfinite(params[t])) return fail(HIPIB_E_INVAL, "non-finite parameter");
+        p[t] = params[t];
+    }
+    ctx->mats.model[mat_id] = model;
+    for (int t = 0; t < 5; ++t) ctx->mats.p[mat_id][t] = p[t];
+    ctx->mat_set |= 1u << mat_id;
+    return HIPIB_OK;
+}
+
+hipib_status hipib_set_pressure_faces(hipib_ctx* ctx, int32_t n_faces, const int32_t* faces) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
+    if (n_faces < 0 || (n_faces > 0 && !faces)) return fail(HIPIB_E_INVAL, "bad faces");
+    for (int64_t t = 0; t < 4 * (int64_t)n_faces; ++t)
+        if (faces[t] < 0 || faces[t] >= ctx->nn)
+            return fail(HIPIB_E_INVAL, "faces[%lld] = %d out of range", (long long)t, faces[t]);
+    HIPIB_HIP(hipStreamSynchronize(ctx->stream));
+    (void)hipFree(ctx->faces);
+    ctx->faces = nullptr;
+    ctx->nf = 0;
+    HIPIB_TRY(dev_alloc(ctx, &ctx->faces, 4 * (size_t)n_faces));
+    if (n_faces > 0)
+        HIPIB_HIP(hipMemcpy(ctx->faces, faces, 4 * sizeof(int32_t) * n_faces, hipMemcpyHostToDevice));
+    ctx->nf = n_faces;
+    return HIPIB_OK;
+}
+
+hipib_status hipib_fe_force(hipib_ctx* ctx, const double* X, double pressure, double* F) {
+    HIPIB_TRY(check_ctx(ctx));
+    HIPIB_TRY(check_mesh_ready(ctx));
+    if (ctx->nn > 0 && (!aligned8(X) || !aligned8(F))) return fail(HIPIB_E_INVAL, "bad X or F pointer");
+    if (!std::isfinite(pressure)) return fail(HIPIB_E_INVAL, "non-finite pressure");
+    return launch_fe_force(ctx, X, pressure, F);
+}
+
+hipib_status hipib_spread(hipib_ctx* ctx, const double* X, const double* F, double* f) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
+    if (!aligned8(f) || (ctx->nn > 0 && (!aligned8(X) || !aligned8(F))))
+        return fail(HIPIB_E_INVAL, "bad pointer");
+    return launch_spread(ctx, X, F, f);
+}
+
+hipib_status hipib_interpolate(hipib_ctx* ctx, const double* X, const double* u, double* U) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
+    if (!aligned8(u) || (ctx->nn > 0 && (!aligned8(X) || !aligned8(U))))
+        return fail(HIPIB_E_INVAL, "bad pointer");
+    return launch_interpolate(ctx, X, u, U, nullptr, 0.0);
+}
+
+hipib_status hipib_mg_solve(hipib_ctx* ctx, int32_t op, int32_t ncomp, const double* b, double* x,
+                            int32_t* cycles, double* relres) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (op != HIPIB_OP_HELMHOLTZ && op != HIPIB_OP_POISSON) return fail(HIPIB_E_INVAL, "unknown op");
+    if (ncomp < 1 || ncomp > 3) return fail(HIPIB_E_INVAL, "ncomp must be 1..3");
+    if (!aligned8(b) || !aligned8(x)) return fail(HIPIB_E_INVAL, "bad pointer");
+    return mg_solve(ctx, op, ncomp, b, x, cycles, relres);
+}
+
+hipib_status hipib_ns_step(hipib_ctx* ctx, const double* f, double* u, double* p) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (!aligned8(u) || !aligned8(p) || (f && !aligned8(f))) return fail(HIPIB_E_INVAL, "bad pointer");
+    ctx->recs.clear();
+    HIPIB_TRY(launch_rhs_build(ctx, u, f, ctx->g));
+    return fluid_solves(ctx, u, p);
+}
+
+hipib_status hipib_ib_step(hipib_ctx* ctx, double* u, double* p, double* X, double pressure) {
+    HIPIB_TRY(check_ctx(ctx));
+    HIPIB_TRY(check_mesh_ready(ctx));
+    if (!aligned8(u) || !aligned8(p) || (ctx->nn > 0 && !aligned8(X)))
+        return fail(HIPIB_E_INVAL, "bad pointer");
+    if (!std::isfinite(pressure)) return fail(HIPIB_E_INVAL, "non-finite pressure");
+    ctx->recs.clear();
+    return ib_step(ctx, u, p, X, pressure);
+}
+
+hipib_status hipib_advance(hipib_ctx* ctx, double* u, double* p, double* X, double t0,
+                           int32_t n_steps, double p0, double T) {
+    HIPIB_TRY(check_ctx(ctx));
+    HIPIB_TRY(check_mesh_ready(ctx));
+    if (!aligned8(u) || !aligned8(p) || (ctx->nn > 0 && !aligned8(X)))
+        return fail(HIPIB_E_INVAL, "bad pointer");
+    if (n_steps < 0 || !std::isfinite(t0) || !std::isfinite(p0) || !std::isfinite(T))
+        return fail(HIPIB_E_INVAL, "bad time arguments");
+    ctx->recs.clear();
+    const double pi = 3.14159265358979323846;
+    for (int32_t s = 0; s < n_steps; ++s) {
+        const double t = t0 + s * ctx->cfg.dt;
+        double pr = 0.0;
+        if (p0 != 0.0 && T > 0.0) {
+            const double sn = std::sin(pi * t / T);
+            pr = p0 * sn * sn;
+        }
+        HIPIB_TRY(ib_step(ctx, u, p, X, pr));
+    }
+    return HIPIB_OK;
+}
+
+hipib_status hipib_timer_enable(hipib_ctx* ctx, int32_t which) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (which != HIPIB_TIMER_OFF && which != HIPIB_TIMER_SMOOTH_FINE_POISSON)
+        return fail(HIPIB_E_INVAL, "unknown timer %d", which);
+    HIPIB_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->timer_which = which;
+    ctx->ev_used = 0;
+    return HIPIB_OK;
+}
+
+hipib_status hipib_timer_read(hipib_ctx* ctx, int32_t* launches, double* total_ms,
+                              double* bytes_per_launch) {
+    HIPIB_TRY(check_ctx(ctx));
+    HIPIB_HIP(hipStreamSynchronize(ctx->stream));
+    double tot = 0.0;
+    for (size_t i = 0; i < ctx->ev_used; ++i) {
+        float ms = 0.0f;
+        HIPIB_HIP(hipEventElapsedTime(&ms, ctx->ev_pool[2 * i], ctx->ev_pool[2 * i + 1]));
+        tot += ms;
+    }
+    if (launches) *launches = (int32_t)ctx->ev_used;
+    if (total_ms) *total_ms = tot;
+    if (bytes_per_launch) *bytes_per_launch = ctx->timer_bytes;
+    ctx->ev_used = 0;
+    return HIPIB_OK;
+}
+
+int32_t hipib_get_step_stats(hipib_ctx* ctx, int32_t* cycles, double* relres, int32_t max_steps) {
+    if (!ctx || max_steps < 0) return 0;
+    const int32_t n = (int32_t)ctx->recs.size() < max_steps ? (int32_t)ctx->recs.size() : max_steps;
+    for (int32_t s = 0; s < n; ++s)
+        for (int t = 0; t < 4; ++t) {
+            if (cycles) cycles[4 * s + t] = ctx->recs[s].cycles[t];
+            if (relres) relres[4 * s + t] = ctx->recs[s].relres[t];
+        }
+    return n;
+}
+
+}  // extern "C"

@@ -1,0 +1,160 @@
+// Internal declarations of the hipib library (gfx950).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hipib.h"
+
+namespace hipib {
+
+constexpr int kMaxLevels = 16;
+constexpr int kSmallMax = 16;       // levels with n <= 16 run in one workgroup (LDS)
+constexpr int kReduceBlock = 256;
+
+// Material table passed by value to the force kernels.
+struct MatTable {
+    int32_t model[HIPIB_MAX_MATERIALS];
+    double p[HIPIB_MAX_MATERIALS][5];
+};
+
+// Multigrid stop-decision state, kept on the device and mirrored to pinned host
+// memory at each synchronisation point.
+struct MGState {
+    double bn[3];       // ||b||_2 per component
+    double rn[3];       // ||r||_2 per component after the latest cycle
+    double mean[3];     // Poisson: mean removed by the latest mean step
+    int32_t active[3];  // 1 while the component still needs cycles
+    int32_t cycles[3];  // cycles done
+    int32_t zero_req[3];// ||b|| = 0: the solution is x = 0
+    int32_t status;     // HIPIB_OK / HIPIB_E_NOCONV / HIPIB_E_NUMERIC
+    int32_t numeric;    // set by the force kernel when J <= 0
+    int32_t pad[3];
+};
+
+struct Level {
+    int n = 0;
+    int64_t n3 = 0;
+    double* x = nullptr;   // [3][n3] for l >= 1 (level 0 uses caller arrays)
+    double* b = nullptr;
+};
+
+struct StepRecord {
+    int32_t cycles[4];
+    double relres[4];
+};
+
+}  // namespace hipib
+
+struct hipib_ctx {
+    hipib_config cfg{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int n = 0;
+    int64_t n3 = 0;
+    double h = 0.0;
+
+    // multigrid hierarchy
+    int L = 0;              // number of levels
+    int small_start = 0;    // first level run by the single-workgroup kernel
+    size_t small_lds = 0;   // its dynamic LDS bytes
+    hipib::Level lv[hipib::kMaxLevels];
+    double* r0 = nullptr;   // [3][n3] residual scratch (any level)
+    double* g = nullptr;    // [3][n3] Helmholtz right-hand side
+    double* bp = nullptr;   // [n3] Poisson right-hand side
+    double* part = nullptr; // reduction partials
+    int64_t part_cap = 0;
+    hipib::MGState* st = nullptr;       // device
+    hipib::MGState* st_host = nullptr;  // pinned host mirror
+    int predicted[2] = {1, 1};          // cycles enqueued before the first check
+
+    // Lagrangian mesh
+    int32_t nn = 0, ne = 0, nf = 0;
+    bool mesh_set = false;
+    double* Xref = nullptr;
+    int32_t* conn = nullptr;
+    double* fibre = nullptr;
+    int32_t* mat_id = nullptr;
+    int32_t* faces = nullptr;
+    double* F = nullptr;      // [nn][3] nodal force scratch
+    uint32_t mat_used = 0;    // bit m: some element uses material m
+    uint32_t mat_set = 0;     // bit m: material m defined
+    hipib::MatTable mats{};
+
+    std::vector<hipib::StepRecord> recs;
+    bool broken = false;
+
+    // event timing of one kernel class (hipib_timer)
+    int timer_which = 0;
+    std::vector<hipEvent_t> ev_pool;   // pairs: start 2i, stop 2i+1
+    size_t ev_used = 0;                // pairs recorded since the last read
+    double timer_bytes = 0.0;          // algorithmic bytes per timed launch
+};
+
+namespace hipib {
+
+// ---- error reporting (thread-local message) --------------------------------
+hipib_status fail(hipib_status s, const char* fmt, ...);
+hipib_status hip_fail(hipib_ctx* ctx, hipError_t e, const char* what, const char* file, int line);
+
+#define HIPIB_HIP(call)                                                          \
+    do {                                                                         \
+        hipError_t e_ = (call);                                                  \
+        if (e_ != hipSuccess) return ::hipib::hip_fail(ctx, e_, #call, __FILE__, __LINE__); \
+    } while (0)
+
+#define HIPIB_TRY(call)                      \
+    do {                                     \
+        hipib_status s_ = (call);            \
+        if (s_ != HIPIB_OK) return s_;       \
+    } while (0)
+
+// ---- launchers (each file owns its kernels) ---------------------------------
+// grid.hip
+hipib_status launch_rhs_build(hipib_ctx* ctx, const double* u, const double* f, double* g);
+hipib_status launch_divergence_rhs(hipib_ctx* ctx, const double* u, double* b);
+hipib_status launch_project(hipib_ctx* ctx, double* u, const double* p);
+hipib_status launch_zero(hipib_ctx* ctx, double* p, int64_t count);
+// mg.hip
+hipib_status mg_solve(hipib_ctx* ctx, int op, int ncomp, const double* b, double* x,
+                      int32_t* cycles, double* relres);
+hipib_status mg_remove_mean(hipib_ctx* ctx, double* v, int slot);
+hipib_status mg_prepare(hipib_ctx* ctx);
+hipib_status sync_state(hipib_ctx* ctx);
+// ib.hip
+hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, double* f);
+hipib_status launch_interpolate(hipib_ctx* ctx, const double* X, const double* u, double* U,
+                                double* Xupd, double dt);
+// fe.hip
+hipib_status launch_fe_force(hipib_ctx* ctx, const double* X, double pressure, double* F);
+
+// ---- event timing --------------------------------------------------------------
+// Returns the pair index to close with timer_stop, or -1 when `kind` is not timed.
+int timer_start(hipib_ctx* ctx, int kind, double bytes);
+void timer_stop(hipib_ctx* ctx, int pair);
+
+// ---- small device helpers ----------------------------------------------------
+__device__ __forceinline__ int wrap_idx(int i, int n) {
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+// Sum over a workgroup of blockDim.x (multiple of 64, <= 1024) threads.
+// Deterministic: fixed shuffle tree within each wavefront, fixed order across waves.
+__device__ __forceinline__ double block_sum(double v, double* lds /*[16]*/) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) s += lds[w];
+    }
+    __syncthreads();
+    return s;  // valid in thread 0
+}
+
+}  // namespace hipib

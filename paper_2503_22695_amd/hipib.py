@@ -1,0 +1,276 @@
+"""Python binding of libhipib (the C-ABI in include/hipib.h).
+
+Argument marshalling only: every step of the timestep runs in the HIP kernels
+of libhipib.so.  Device arrays are torch tensors (float64, contiguous, on the
+current HIP device); host set-up arrays are numpy.  Work is enqueued on torch's
+current stream.  There is no fallback: if the library is missing, importing
+the context fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhipib.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "hipib.h")
+
+OK, E_INVAL, E_NOMEM, E_HIP, E_NOCONV, E_NUMERIC, E_STATE = range(7)
+FP64, MIXED = 0, 1
+NEO_HOOKEAN, HOLZAPFEL_OGDEN = 0, 1
+OP_HELMHOLTZ, OP_POISSON = 0, 1
+TIMER_OFF, TIMER_SMOOTH_FINE_POISSON = 0, 1
+MAX_MATERIALS = 8
+
+
+class HipIBError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: status {status}: {message}")
+        self.status = status
+
+
+class Config(C.Structure):
+    _fields_ = [("n", C.c_int32), ("rho", C.c_double), ("mu", C.c_double), ("dt", C.c_double),
+                ("mg_pre", C.c_int32), ("mg_post", C.c_int32), ("mg_max_cycles", C.c_int32),
+                ("mg_fixed_cycles", C.c_int32), ("mg_coarse_sweeps", C.c_int32),
+                ("mg_rtol", C.c_double), ("convection", C.c_int32), ("precision", C.c_int32),
+                ("deterministic", C.c_int32)]
+
+
+_lib = None
+
+
+def exported_names():
+    """Function names declared by include/hipib.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(hipib_[a-z0-9_]+)\s*\(", txt)))
+
+
+def lib():
+    """Loads libhipib.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                              "(or python paper_2503_22695_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        P, i32, f64 = C.c_void_p, C.c_int32, C.c_double
+        st = C.c_int
+        sig = {
+            "hipib_default_config": (None, [P]),
+            "hipib_create": (st, [P, P, P]),
+            "hipib_destroy": (st, [P]),
+            "hipib_set_stream": (st, [P, P]),
+            "hipib_last_error": (C.c_char_p, []),
+            "hipib_set_mesh": (st, [P, i32, P, i32, P, P, P]),
+            "hipib_set_material": (st, [P, i32, i32, P, i32]),
+            "hipib_set_pressure_faces": (st, [P, i32, P]),
+            "hipib_fe_force": (st, [P, P, f64, P]),
+            "hipib_spread": (st, [P, P, P, P]),
+            "hipib_interpolate": (st, [P, P, P, P]),
+            "hipib_mg_solve": (st, [P, i32, i32, P, P, P, P]),
+            "hipib_ns_step": (st, [P, P, P, P]),
+            "hipib_ib_step": (st, [P, P, P, P, f64]),
+            "hipib_advance": (st, [P, P, P, P, f64, i32, f64, f64]),
+            "hipib_get_step_stats": (i32, [P, P, P, i32]),
+            "hipib_timer_enable": (st, [P, i32]),
+            "hipib_timer_read": (st, [P, P, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def default_config(**over) -> Config:
+    cfg = Config()
+    lib().hipib_default_config(C.byref(cfg))
+    for k, v in over.items():
+        if not hasattr(cfg, k):
+            raise KeyError(k)
+        setattr(cfg, k, v)
+    return cfg
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        msg = lib().hipib_last_error()
+        raise HipIBError(status, where, msg.decode() if msg else "")
+
+
+def _dev(t, shape=None, name="array"):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_ptr():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """One grid plus (optionally) one Lagrangian mesh on the current HIP device."""
+
+    def __init__(self, cfg: Config):
+        self._h = C.c_void_p()
+        self.cfg = cfg
+        _check(lib().hipib_create(C.byref(cfg), _stream_ptr(), C.byref(self._h)), "hipib_create")
+        self.n = cfg.n
+        self.n_nodes = 0
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if self._h:
+            lib().hipib_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync_stream(self):
+        _check(lib().hipib_set_stream(self._h, _stream_ptr()), "hipib_set_stream")
+
+    # -- set-up (host arrays) ---------------------------------------------
+    def set_mesh(self, X_ref, conn, fibre, mat_id):
+        X_ref = np.ascontiguousarray(X_ref, dtype=np.float64).reshape(-1, 3)
+        conn = np.ascontiguousarray(conn, dtype=np.int32).reshape(-1, 8)
+        fibre = np.ascontiguousarray(fibre, dtype=np.float64).reshape(-1, 3)
+        mat_id = np.ascontiguousarray(mat_id, dtype=np.int32).reshape(-1)
+        if fibre.shape[0] != conn.shape[0] or mat_id.shape[0] != conn.shape[0]:
+            raise ValueError("fibre / mat_id must have one row per element")
+        _check(lib().hipib_set_mesh(self._h, X_ref.shape[0], X_ref.ctypes.data, conn.shape[0],
+                                    conn.ctypes.data, fibre.ctypes.data, mat_id.ctypes.data),
+               "hipib_set_mesh")
+        self.n_nodes = X_ref.shape[0]
+
+    def set_material(self, mat_id: int, model: int, params):
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        _check(lib().hipib_set_material(self._h, mat_id, model, p.ctypes.data, p.size),
+               "hipib_set_material")
+
+    def set_pressure_faces(self, faces):
+        f = np.ascontiguousarray(faces, dtype=np.int32).reshape(-1, 4)
+        _check(lib().hipib_set_pressure_faces(self._h, f.shape[0], f.ctypes.data),
+               "hipib_set_pressure_faces")
+
+    # -- hot path (device tensors) ----------------------------------------
+    def _grid_shape(self, comps):
+        n = self.n
+        return (comps, n, n, n) if comps else (n, n, n)
+
+    def fe_force(self, X, pressure: float = 0.0, F=None):
+        import torch
+        if F is None:
+            F = torch.empty_like(X)
+        _check(lib().hipib_fe_force(self._h, _dev(X, (self.n_nodes, 3), "X"), float(pressure),
+                                    _dev(F, (self.n_nodes, 3), "F")), "hipib_fe_force")
+        return F
+
+    def spread(self, X, F, f):
+        _check(lib().hipib_spread(self._h, _dev(X, (self.n_nodes, 3), "X"),
+                                  _dev(F, (self.n_nodes, 3), "F"), _dev(f, self._grid_shape(3), "f")),
+               "hipib_spread")
+        return f
+
+    def interpolate(self, X, u, U=None):
+        import torch
+        if U is None:
+            U = torch.empty_like(X)
+        _check(lib().hipib_interpolate(self._h, _dev(X, (self.n_nodes, 3), "X"),
+                                       _dev(u, self._grid_shape(3), "u"),
+                                       _dev(U, (self.n_nodes, 3), "U")), "hipib_interpolate")
+        return U
+
+    def mg_solve(self, op: int, b, x) -> Tuple[np.ndarray, np.ndarray]:
+        ncomp = 1 if b.dim() == 3 else b.shape[0]
+        shape = self._grid_shape(0 if b.dim() == 3 else ncomp)
+        cyc = np.zeros(ncomp, dtype=np.int32)
+        rr = np.zeros(ncomp, dtype=np.float64)
+        _check(lib().hipib_mg_solve(self._h, op, ncomp, _dev(b, shape, "b"), _dev(x, shape, "x"),
+                                    cyc.ctypes.data, rr.ctypes.data), "hipib_mg_solve")
+        return cyc, rr
+
+    def ns_step(self, f, u, p):
+        fp = C.c_void_p(0) if f is None else _dev(f, self._grid_shape(3), "f")
+        _check(lib().hipib_ns_step(self._h, fp, _dev(u, self._grid_shape(3), "u"),
+                                   _dev(p, self._grid_shape(0), "p")), "hipib_ns_step")
+
+    def ib_step(self, u, p, X, pressure: float = 0.0):
+        _check(lib().hipib_ib_step(self._h, _dev(u, self._grid_shape(3), "u"),
+                                   _dev(p, self._grid_shape(0), "p"),
+                                   _dev(X, (self.n_nodes, 3), "X"), float(pressure)), "hipib_ib_step")
+
+    def advance(self, u, p, X, t0: float, n_steps: int, p0: float = 0.0, T: float = 0.0):
+        _check(lib().hipib_advance(self._h, _dev(u, self._grid_shape(3), "u"),
+                                   _dev(p, self._grid_shape(0), "p"),
+                                   _dev(X, (self.n_nodes, 3), "X"), float(t0), int(n_steps),
+                                   float(p0), float(T)), "hipib_advance")
+
+    def timer_enable(self, which: int):
+        _check(lib().hipib_timer_enable(self._h, which), "hipib_timer_enable")
+
+    def timer_read(self):
+        """(launches, total_ms, algorithmic bytes per launch) since the last read."""
+        k, ms, by = C.c_int32(0), C.c_double(0.0), C.c_double(0.0)
+        _check(lib().hipib_timer_read(self._h, C.byref(k), C.byref(ms), C.byref(by)),
+               "hipib_timer_read")
+        return k.value, ms.value, by.value
+
+    def step_stats(self, max_steps: int = 100000):
+        cyc = np.zeros((max_steps, 4), dtype=np.int32)
+        rr = np.zeros((max_steps, 4), dtype=np.float64)
+        k = lib().hipib_get_step_stats(self._h, cyc.ctypes.data, rr.ctypes.data, max_steps)
+        return cyc[:k], rr[:k]
+
+
+def config_for_problem(prob, **over) -> Config:
+    kw = dict(n=prob.n, rho=prob.rho, mu=prob.mu, dt=prob.dt, mg_pre=prob.mg_pre,
+              mg_post=prob.mg_post, mg_max_cycles=prob.mg_max_cycles, mg_rtol=prob.mg_rtol,
+              convection=prob.convection, precision=MIXED if prob.precision == "mixed" else FP64)
+    kw.update(over)
+    return default_config(**kw)
+
+
+def context_for_problem(prob, **over) -> Context:
+    """A context holding the problem's grid, mesh, materials and pressure faces."""
+    ctx = Context(config_for_problem(prob, **over))
+    ctx.set_mesh(prob.X_ref, prob.conn, prob.fibre, prob.mat_id)
+    for m, mat in enumerate(prob.materials):
+        ctx.set_material(m, mat.model, mat.params)
+    if prob.n_faces:
+        ctx.set_pressure_faces(prob.faces)
+    return ctx
+
+
+class Simulation:
+    """Device state (u, p, X) of one workload plus its context."""
+
+    def __init__(self, prob, **over):
+        import torch
+        self.prob = prob
+        self.ctx = context_for_problem(prob, **over)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.u = torch.tensor(prob.initial_velocity(), dtype=torch.float64, device=dev).contiguous()
+        self.p = torch.zeros((prob.n,) * 3, dtype=torch.float64, device=dev)
+        self.X = torch.tensor(prob.X0, dtype=torch.float64, device=dev).contiguous()
+        self.t = 0.0
+
+    def advance(self, n_steps: int):
+        self.ctx.advance(self.u, self.p, self.X, self.t, n_steps, self.prob.p0, self.prob.T)
+        self.t += n_steps * self.prob.dt
+        return self
