@@ -71,6 +71,10 @@ void free_mesh(hipib_ctx* ctx) {
     (void)hipFree(ctx->fibre);
     (void)hipFree(ctx->mat_id);
     (void)hipFree(ctx->F);
+    (void)hipFree(ctx->node_tile);
+    (void)hipFree(ctx->node_rank);
+    (void)hipFree(ctx->perm);
+    ctx->node_tile = ctx->node_rank = ctx->perm = nullptr;
     ctx->Xref = nullptr;
     ctx->conn = nullptr;
     ctx->fibre = nullptr;
@@ -92,6 +96,10 @@ void free_all(hipib_ctx* ctx) {
     (void)hipFree(ctx->g);
     (void)hipFree(ctx->bp);
     (void)hipFree(ctx->part);
+    (void)hipFree(ctx->bin_count);
+    (void)hipFree(ctx->bin_off);
+    (void)hipFree(ctx->tile_list);
+    (void)hipFree(ctx->n_list);
     (void)hipFree(ctx->st);
     if (ctx->st_host) (void)hipHostFree(ctx->st_host);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
@@ -121,6 +129,7 @@ hipib_status fluid_solves(hipib_ctx* ctx, double* u, double* p) {
 }
 
 hipib_status ib_step(hipib_ctx* ctx, double* u, double* p, double* X, double pressure) {
+    HIPIB_TRY(launch_bin(ctx, X));
     HIPIB_TRY(launch_fe_force(ctx, X, pressure, ctx->F));
     HIPIB_TRY(launch_rhs_build(ctx, u, nullptr, ctx->g));
     HIPIB_TRY(launch_spread(ctx, X, ctx->F, ctx->g));
@@ -209,6 +218,13 @@ hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->r0, 3 * (size_t)ctx->n3);
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->g, 3 * (size_t)ctx->n3);
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->bp, (size_t)ctx->n3);
+    ctx->tile = (n % 8 == 0) ? 8 : 4;
+    ctx->tiles_axis = n / ctx->tile;
+    ctx->ntiles = (int64_t)ctx->tiles_axis * ctx->tiles_axis * ctx->tiles_axis;
+    if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->bin_count, (size_t)ctx->ntiles);
+    if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->bin_off, (size_t)ctx->ntiles + 1);
+    if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->tile_list, (size_t)ctx->ntiles);
+    if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->n_list, 1);
     ctx->part_cap = 3 * (((int64_t)(n + 63) / 64) * ((n + 3) / 4) * n + 1024);
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->part, (size_t)ctx->part_cap);
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->st, 1);
@@ -220,6 +236,9 @@ hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out
     if (s == HIPIB_OK) s = mg_prepare(ctx);
     if (s == HIPIB_OK) {
         hipError_t e = hipMemsetAsync(ctx->st, 0, sizeof(MGState), ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(ctx->bin_count, 0, sizeof(int32_t) * (size_t)ctx->ntiles, ctx->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(ctx->n_list, 0, sizeof(int32_t), ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) s = fail(HIPIB_E_HIP, "HIP error %d initialising the context", (int)e);
     }
@@ -277,6 +296,9 @@ hipib_status hipib_set_mesh(hipib_ctx* ctx, int32_t n_nodes, const double* X_ref
     HIPIB_TRY(dev_alloc(ctx, &ctx->conn, 8 * (size_t)n_elems));
     HIPIB_TRY(dev_alloc(ctx, &ctx->fibre, 3 * (size_t)n_elems));
     HIPIB_TRY(dev_alloc(ctx, &ctx->mat_id, (size_t)n_elems));
+    HIPIB_TRY(dev_alloc(ctx, &ctx->node_tile, (size_t)n_nodes));
+    HIPIB_TRY(dev_alloc(ctx, &ctx->node_rank, (size_t)n_nodes));
+    HIPIB_TRY(dev_alloc(ctx, &ctx->perm, (size_t)n_nodes));
     if (n_nodes > 0)
         HIPIB_HIP(hipMemcpy(ctx->Xref, X_ref, 3 * sizeof(double) * n_nodes, hipMemcpyHostToDevice));
     if (n_elems > 0) {
@@ -349,6 +371,7 @@ hipib_status hipib_spread(hipib_ctx* ctx, const double* X, const double* F, doub
     if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
     if (!aligned8(f) || (ctx->nn > 0 && (!aligned8(X) || !aligned8(F))))
         return fail(HIPIB_E_INVAL, "bad pointer");
+    HIPIB_TRY(launch_bin(ctx, X));
     return launch_spread(ctx, X, F, f);
 }
 
@@ -357,6 +380,7 @@ hipib_status hipib_interpolate(hipib_ctx* ctx, const double* X, const double* u,
     if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
     if (!aligned8(u) || (ctx->nn > 0 && (!aligned8(X) || !aligned8(U))))
         return fail(HIPIB_E_INVAL, "bad pointer");
+    HIPIB_TRY(launch_bin(ctx, X));
     return launch_interpolate(ctx, X, u, U, nullptr, 0.0);
 }
 

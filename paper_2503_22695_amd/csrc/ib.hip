@@ -7,6 +7,16 @@
 // b = floor(r), f = r - b, s = sqrt(1 + 4 f (1 - f)) and weights
 //   ((3 - 2f - s), (3 - 2f + s), (1 + 2f + s), (1 + 2f - s)) / 8,
 // which is phi evaluated at f+1, f, 1-f, 2-f.
+//
+// Spreading is binned: nodes are counting-sorted by the Eulerian tile (T^3
+// cells) holding floor(X/h); every stencil point of a node in tile t lies in
+// the (T+4)^3 box starting two cells below the tile, on all three lattices.
+// One workgroup per occupied tile accumulates its box in LDS with FP64 LDS
+// atomics, then adds the box to the grid with one coalesced pass of global
+// atomics (boxes of neighbouring tiles overlap by four cells).  Interpolation
+// walks the nodes in the same tile order so a wavefront gathers from a small
+// neighbourhood.  Summation order is not fixed, so results agree with a serial
+// sum to rounding.
 #include "internal.h"
 
 namespace hipib {
@@ -34,40 +44,149 @@ __device__ __forceinline__ Stencil1 peskin4(double r, int n) {
 
 __device__ __forceinline__ int step_wrap(int i, int n) { return i >= n ? i - n : i; }
 
-// one thread per node; 3 x 64 atomic adds of F^d w into the face lattices
+__device__ __forceinline__ double safe_coord(double r) { return fabs(r) < 1.0e9 ? r : 0.0; }
+
+__device__ __forceinline__ int wrap_mod(int i, int n) {
+    const int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// tile of each node and its rank inside the tile
 __global__ void __launch_bounds__(256)
-k_spread_atomic(const double* __restrict__ X, const double* __restrict__ F, double* __restrict__ f,
-                int nn, int n, int64_t n3, double inv_h, double ih3) {
+k_bin_count(const double* __restrict__ X, int nn, int n, int T, int ta, double inv_h,
+            int32_t* __restrict__ node_tile, int32_t* __restrict__ node_rank,
+            int32_t* __restrict__ count) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nn) return;
-    const double x[3] = {X[3 * q] * inv_h, X[3 * q + 1] * inv_h, X[3 * q + 2] * inv_h};
-    for (int d = 0; d < 3; ++d) {
-        const double val = F[3 * q + d] * ih3;
-        const Stencil1 sx = peskin4(x[0] - (d == 0 ? 0.0 : 0.5), n);
-        const Stencil1 sy = peskin4(x[1] - (d == 1 ? 0.0 : 0.5), n);
-        const Stencil1 sz = peskin4(x[2] - (d == 2 ? 0.0 : 0.5), n);
-        double* fd = f + d * n3;
-        for (int c = 0; c < 4; ++c) {
-            const int kk = step_wrap(sz.i0 + c, n);
-            for (int b = 0; b < 4; ++b) {
-                const int jj = step_wrap(sy.i0 + b, n);
-                const double wyz = sy.w[b] * sz.w[c];
-                const int64_t row = (int64_t)n * ((int64_t)jj + (int64_t)n * kk);
-                for (int a = 0; a < 4; ++a) {
-                    const int ii = step_wrap(sx.i0 + a, n);
-                    atomicAdd(fd + row + ii, val * (sx.w[a] * wyz));
+    int t[3];
+    for (int e = 0; e < 3; ++e) {
+        const int c = (int)floor(safe_coord(X[3 * q + e] * inv_h));
+        t[e] = wrap_mod(c, n) / T;
+    }
+    const int tile = t[0] + ta * (t[1] + ta * t[2]);
+    node_tile[q] = tile;
+    node_rank[q] = atomicAdd(count + tile, 1);
+}
+
+// exclusive scan of the tile counts, list of occupied tiles; counts reset to 0
+__global__ void __launch_bounds__(1024)
+k_bin_scan(int32_t* __restrict__ count, int64_t ntiles, int32_t* __restrict__ off,
+           int32_t* __restrict__ list, int32_t* __restrict__ nlist) {
+    __shared__ int32_t s_sum[1024], s_nz[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (ntiles + 1023) / 1024;
+    const int64_t beg = tid * per < ntiles ? tid * per : ntiles;
+    const int64_t end = beg + per < ntiles ? beg + per : ntiles;
+    int32_t sum = 0, nz = 0;
+    for (int64_t i = beg; i < end; ++i) {
+        sum += count[i];
+        nz += count[i] > 0;
+    }
+    s_sum[tid] = sum;
+    s_nz[tid] = nz;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int32_t a = tid >= o ? s_sum[tid - o] : 0;
+        const int32_t b = tid >= o ? s_nz[tid - o] : 0;
+        __syncthreads();
+        s_sum[tid] += a;
+        s_nz[tid] += b;
+        __syncthreads();
+    }
+    int32_t run = s_sum[tid] - sum, lrun = s_nz[tid] - nz;
+    for (int64_t i = beg; i < end; ++i) {
+        off[i] = run;
+        const int32_t c = count[i];
+        run += c;
+        if (c > 0) list[lrun++] = (int32_t)i;
+        count[i] = 0;
+    }
+    if (tid == 1023) {
+        off[ntiles] = s_sum[1023];
+        *nlist = s_nz[1023];
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_bin_scatter(const int32_t* __restrict__ node_tile, const int32_t* __restrict__ node_rank,
+              const int32_t* __restrict__ off, int32_t* __restrict__ perm, int nn) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nn) return;
+    perm[off[node_tile[q]] + node_rank[q]] = q;
+}
+
+// one workgroup per occupied tile (grid-stride over the list); LDS box of
+// E^3 cells per lattice, E = T + 4, starting at T * tile - 2
+template <int T>
+__global__ void __launch_bounds__(256)
+k_spread_tiles(const double* __restrict__ X, const double* __restrict__ F, double* __restrict__ f,
+               const int32_t* __restrict__ perm, const int32_t* __restrict__ off,
+               const int32_t* __restrict__ list, const int32_t* __restrict__ nlist, int n, int ta,
+               int64_t n3, double inv_h, double ih3) {
+    constexpr int E = T + 4, E3 = E * E * E;
+    __shared__ double box[3 * E3];
+    const int ntl = *nlist;
+    for (int li = blockIdx.x; li < ntl; li += gridDim.x) {
+        const int tile = list[li];
+        const int tb[3] = {T * (tile % ta), T * ((tile / ta) % ta), T * (tile / (ta * ta))};
+        for (int e = threadIdx.x; e < 3 * E3; e += blockDim.x) box[e] = 0.0;
+        __syncthreads();
+        for (int idx = off[tile] + threadIdx.x; idx < off[tile + 1]; idx += blockDim.x) {
+            const int q = perm[idx];
+            double xs[3];
+            int cw[3];
+            for (int e = 0; e < 3; ++e) {
+                xs[e] = safe_coord(X[3 * q + e] * inv_h);
+                cw[e] = wrap_mod((int)floor(xs[e]), n);
+            }
+            for (int d = 0; d < 3; ++d) {
+                const double val = F[3 * q + d] * ih3;
+                int ls[3];
+                double w[3][4];
+                for (int e = 0; e < 3; ++e) {
+                    const double r = xs[e] - (e == d ? 0.0 : 0.5);
+                    const double bf = floor(r);
+                    const double fr = r - bf;
+                    const double sq = sqrt(1.0 + 4.0 * fr * (1.0 - fr));
+                    w[e][0] = (3.0 - 2.0 * fr - sq) * 0.125;
+                    w[e][1] = (3.0 - 2.0 * fr + sq) * 0.125;
+                    w[e][2] = (1.0 + 2.0 * fr + sq) * 0.125;
+                    w[e][3] = (1.0 + 2.0 * fr - sq) * 0.125;
+                    // stencil start relative to the node's cell is -1 or -2
+                    const int ds = (int)bf - 1 - (int)floor(xs[e]);
+                    ls[e] = cw[e] - tb[e] + 2 + ds;
                 }
+                double* bd = box + d * E3;
+                for (int c = 0; c < 4; ++c)
+                    for (int b = 0; b < 4; ++b) {
+                        const double wyz = w[1][b] * w[2][c];
+                        const int row = (ls[0]) + E * ((ls[1] + b) + E * (ls[2] + c));
+                        for (int a = 0; a < 4; ++a) atomicAdd(bd + row + a, val * (w[0][a] * wyz));
+                    }
             }
         }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 3 * E3; e += blockDim.x) {
+            const double v = box[e];
+            if (v != 0.0) {
+                const int d = e / E3, r = e - d * E3;
+                const int lx = r % E, ly = (r / E) % E, lz = r / (E * E);
+                const int gx = wrap_mod(tb[0] - 2 + lx, n), gy = wrap_mod(tb[1] - 2 + ly, n),
+                          gz = wrap_mod(tb[2] - 2 + lz, n);
+                atomicAdd(f + d * n3 + gx + (int64_t)n * (gy + (int64_t)n * gz), v);
+            }
+        }
+        __syncthreads();
     }
 }
 
 // one thread per node: gather 3 x 64 values; optionally X += dt U (in place)
 __global__ void __launch_bounds__(256)
 k_interp(const double* X, const double* __restrict__ u, double* __restrict__ U, double* Xupd,
-         double dt, int nn, int n, int64_t n3, double inv_h) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nn) return;
+         double dt, int nn, int n, int64_t n3, double inv_h, const int32_t* __restrict__ perm) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nn) return;
+    const int q = perm ? perm[t] : t;
     const double X0 = X[3 * q], X1 = X[3 * q + 1], X2 = X[3 * q + 2];
     const double x[3] = {X0 * inv_h, X1 * inv_h, X2 * inv_h};
     double Uq[3];
@@ -105,20 +224,43 @@ k_interp(const double* X, const double* __restrict__ u, double* __restrict__ U, 
 
 }  // namespace
 
-hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, double* f) {
+hipib_status launch_bin(hipib_ctx* ctx, const double* X) {
     if (ctx->nn == 0) return HIPIB_OK;
-    const double h = ctx->h;
-    k_spread_atomic<<<(ctx->nn + 255) / 256, 256, 0, ctx->stream>>>(X, F, f, ctx->nn, ctx->n, ctx->n3,
-                                                                    1.0 / h, 1.0 / (h * h * h));
+    const int nb = (ctx->nn + 255) / 256;
+    k_bin_count<<<nb, 256, 0, ctx->stream>>>(X, ctx->nn, ctx->n, ctx->tile, ctx->tiles_axis,
+                                             1.0 / ctx->h, ctx->node_tile, ctx->node_rank,
+                                             ctx->bin_count);
+    k_bin_scan<<<1, 1024, 0, ctx->stream>>>(ctx->bin_count, ctx->ntiles, ctx->bin_off,
+                                            ctx->tile_list, ctx->n_list);
+    k_bin_scatter<<<nb, 256, 0, ctx->stream>>>(ctx->node_tile, ctx->node_rank, ctx->bin_off,
+                                               ctx->perm, ctx->nn);
     HIPIB_HIP(hipGetLastError());
     return HIPIB_OK;
 }
 
+// expects launch_bin(ctx, X) to have been enqueued for the same X
+hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, double* f) {
+    if (ctx->nn == 0) return HIPIB_OK;
+    const double h = ctx->h;
+    const int blocks = (int)(ctx->ntiles < 4096 ? ctx->ntiles : 4096);
+    if (ctx->tile == 8)
+        k_spread_tiles<8><<<blocks, 256, 0, ctx->stream>>>(
+            X, F, f, ctx->perm, ctx->bin_off, ctx->tile_list, ctx->n_list, ctx->n, ctx->tiles_axis,
+            ctx->n3, 1.0 / h, 1.0 / (h * h * h));
+    else
+        k_spread_tiles<4><<<blocks, 256, 0, ctx->stream>>>(
+            X, F, f, ctx->perm, ctx->bin_off, ctx->tile_list, ctx->n_list, ctx->n, ctx->tiles_axis,
+            ctx->n3, 1.0 / h, 1.0 / (h * h * h));
+    HIPIB_HIP(hipGetLastError());
+    return HIPIB_OK;
+}
+
+// expects launch_bin(ctx, X) to have been enqueued for the same X
 hipib_status launch_interpolate(hipib_ctx* ctx, const double* X, const double* u, double* U,
                                 double* Xupd, double dt) {
     if (ctx->nn == 0) return HIPIB_OK;
     k_interp<<<(ctx->nn + 255) / 256, 256, 0, ctx->stream>>>(X, u, U, Xupd, dt, ctx->nn, ctx->n,
-                                                             ctx->n3, 1.0 / ctx->h);
+                                                             ctx->n3, 1.0 / ctx->h, ctx->perm);
     HIPIB_HIP(hipGetLastError());
     return HIPIB_OK;
 }

@@ -80,6 +80,18 @@ struct hipib_ctx {
     int32_t* mat_id = nullptr;
     int32_t* faces = nullptr;
     double* F = nullptr;      // [nn][3] nodal force scratch
+
+    // Eulerian tile bins of the nodes (counting sort by tile of T^3 cells)
+    int tile = 8;             // T: 8 when n % 8 == 0, else 4
+    int tiles_axis = 0;       // n / T
+    int64_t ntiles = 0;
+    int32_t* bin_count = nullptr;   // [ntiles] (kept zero between uses)
+    int32_t* bin_off = nullptr;     // [ntiles + 1]
+    int32_t* tile_list = nullptr;   // [ntiles] occupied tiles
+    int32_t* n_list = nullptr;      // [1] number of occupied tiles
+    int32_t* node_tile = nullptr;   // [nn]
+    int32_t* node_rank = nullptr;   // [nn]
+    int32_t* perm = nullptr;        // [nn] nodes grouped by tile
     uint32_t mat_used = 0;    // bit m: some element uses material m
     uint32_t mat_set = 0;     // bit m: material m defined
     hipib::MatTable mats{};
@@ -125,6 +137,7 @@ hipib_status mg_remove_mean(hipib_ctx* ctx, double* v, int slot);
 hipib_status mg_prepare(hipib_ctx* ctx);
 hipib_status sync_state(hipib_ctx* ctx);
 // ib.hip
+hipib_status launch_bin(hipib_ctx* ctx, const double* X);
 hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, double* f);
 hipib_status launch_interpolate(hipib_ctx* ctx, const double* X, const double* u, double* U,
                                 double* Xupd, double dt);

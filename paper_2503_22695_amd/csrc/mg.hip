@@ -272,159 +272,210 @@ __global__ void k_state_reset(MGState* st, int ncomp) {
 
 // ---------------------------------------------------------------------------
 // all levels with n <= 16 in one workgroup, arrays in LDS
+//
+// The level chain is a compile-time constant (16-8-4, 12-6 or 8-4), so every
+// index split is a multiply/shift.  Levels above the coarsest use all 1024
+// threads with a workgroup barrier between stages; the coarsest level (4^3 or
+// 6^3, many sweeps) runs on wavefront 0 alone: LDS operations of one wavefront
+// complete in program order, so a wavefront-scope fence between half-sweeps
+// replaces the barrier.
 // ---------------------------------------------------------------------------
 
-struct SmallPlan {
-    int nl;               // levels handled (>= 1); level 0 here = first small level
-    int n[6];
-    int off[6];           // offset (in doubles) of level l's x; b at off + n^3, r at off + 2 n^3
+struct SmallArgs {
     int pre, post, sweeps, poisson, zero_init;
     double sigma, nu;
 };
 
-__device__ void s_gs(double* x, const double* b, int n, double c, double diag, int colour) {
-    const int half = n >> 1, cnt = half * n * n;
-    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-        const int ih = t % half, rest = t / half;
-        const int j = rest % n, k = rest / n;
-        const int i = 2 * ih + ((j + k + colour) & 1);
-        const double s = x[wrap_idx(i + 1, n) + n * (j + n * k)] + x[wrap_idx(i - 1, n) + n * (j + n * k)] +
-                         x[i + n * (wrap_idx(j + 1, n) + n * k)] + x[i + n * (wrap_idx(j - 1, n) + n * k)] +
-                         x[i + n * (j + n * wrap_idx(k + 1, n))] + x[i + n * (j + n * wrap_idx(k - 1, n))];
-        const int o = i + n * (j + n * k);
-        x[o] = (b[o] + c * s) / diag;
-    }
-    __syncthreads();
+template <int N>
+__device__ __forceinline__ int wrapc(int i) {
+    return i < 0 ? i + N : (i >= N ? i - N : i);
 }
 
-__device__ void s_residual(const double* x, const double* b, double* r, int n, double sigma, double c) {
-    const int cnt = n * n * n;
-    for (int o = threadIdx.x; o < cnt; o += blockDim.x) {
-        const int i = o % n, j = (o / n) % n, k = o / (n * n);
+template <int N>
+__device__ __forceinline__ int at3(int i, int j, int k) {
+    return i + N * (j + N * k);
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// one colour of red-black Gauss-Seidel by threads t = t0, t0+nt, ...
+template <int N>
+__device__ __forceinline__ void s_gs(double* x, const double* b, double c, double diag, int colour,
+                                     int t0, int nt) {
+    constexpr int HALF = N / 2, CNT = HALF * N * N;
+    for (int t = t0; t < CNT; t += nt) {
+        const int ih = t % HALF, rest = t / HALF;
+        const int j = rest % N, k = rest / N;
+        const int i = 2 * ih + ((j + k + colour) & 1);
+        const double s = x[at3<N>(wrapc<N>(i + 1), j, k)] + x[at3<N>(wrapc<N>(i - 1), j, k)] +
+                         x[at3<N>(i, wrapc<N>(j + 1), k)] + x[at3<N>(i, wrapc<N>(j - 1), k)] +
+                         x[at3<N>(i, j, wrapc<N>(k + 1))] + x[at3<N>(i, j, wrapc<N>(k - 1))];
+        const int o = at3<N>(i, j, k);
+        x[o] = (b[o] + c * s) / diag;
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void s_residual(const double* x, const double* b, double* r, double sigma,
+                                           double c) {
+    constexpr int CNT = N * N * N;
+    for (int o = threadIdx.x; o < CNT; o += blockDim.x) {
+        const int i = o % N, j = (o / N) % N, k = o / (N * N);
         const double xo = x[o];
-        const double s = x[wrap_idx(i + 1, n) + n * (j + n * k)] + x[wrap_idx(i - 1, n) + n * (j + n * k)] +
-                         x[i + n * (wrap_idx(j + 1, n) + n * k)] + x[i + n * (wrap_idx(j - 1, n) + n * k)] +
-                         x[i + n * (j + n * wrap_idx(k + 1, n))] + x[i + n * (j + n * wrap_idx(k - 1, n))];
+        const double s = x[at3<N>(wrapc<N>(i + 1), j, k)] + x[at3<N>(wrapc<N>(i - 1), j, k)] +
+                         x[at3<N>(i, wrapc<N>(j + 1), k)] + x[at3<N>(i, wrapc<N>(j - 1), k)] +
+                         x[at3<N>(i, j, wrapc<N>(k + 1))] + x[at3<N>(i, j, wrapc<N>(k - 1))];
         const double Ax = sigma * xo - c * (s - 6.0 * xo);
         r[o] = b[o] - Ax;
     }
-    __syncthreads();
 }
 
-__device__ void s_restrict(const double* r, int nf, double* bc) {
-    const int nc = nf >> 1, cnt = nc * nc * nc;
+template <int NF>
+__device__ __forceinline__ void s_restrict(const double* r, double* bc) {
+    constexpr int NC = NF / 2, CNT = NC * NC * NC;
     const double w[4] = {1.0, 3.0, 3.0, 1.0};
-    for (int o = threadIdx.x; o < cnt; o += blockDim.x) {
-        const int I = o % nc, J = (o / nc) % nc, K = o / (nc * nc);
+    for (int o = threadIdx.x; o < CNT; o += blockDim.x) {
+        const int I = o % NC, J = (o / NC) % NC, K = o / (NC * NC);
         double s = 0.0;
         for (int cz = 0; cz < 4; ++cz)
             for (int cy = 0; cy < 4; ++cy)
                 for (int cx = 0; cx < 4; ++cx)
                     s += w[cx] * w[cy] * w[cz] / 512.0 *
-                         r[wrap_idx(2 * I - 1 + cx, nf) +
-                           nf * (wrap_idx(2 * J - 1 + cy, nf) + nf * wrap_idx(2 * K - 1 + cz, nf))];
+                         r[at3<NF>(wrapc<NF>(2 * I - 1 + cx), wrapc<NF>(2 * J - 1 + cy),
+                                   wrapc<NF>(2 * K - 1 + cz))];
         bc[o] = s;
     }
-    __syncthreads();
 }
 
-__device__ void s_prolong_add(double* x, int nf, const double* xc) {
-    const int nc = nf >> 1, cnt = nf * nf * nf;
+template <int NF>
+__device__ __forceinline__ void s_prolong_add(double* x, const double* xc) {
+    constexpr int NC = NF / 2, CNT = NF * NF * NF;
     const double wt[2] = {0.75, 0.25};
-    for (int o = threadIdx.x; o < cnt; o += blockDim.x) {
-        const int ijk[3] = {o % nf, (o / nf) % nf, o / (nf * nf)};
+    for (int o = threadIdx.x; o < CNT; o += blockDim.x) {
+        const int ijk[3] = {o % NF, (o / NF) % NF, o / (NF * NF)};
         int base[3][2];
         for (int d = 0; d < 3; ++d) {
             const int I = ijk[d] >> 1;
             base[d][0] = I;
-            base[d][1] = (ijk[d] & 1) ? wrap_idx(I + 1, nc) : wrap_idx(I - 1, nc);
+            base[d][1] = (ijk[d] & 1) ? wrapc<NC>(I + 1) : wrapc<NC>(I - 1);
         }
         double v = 0.0;
         for (int c = 0; c < 2; ++c)
             for (int b = 0; b < 2; ++b)
                 for (int a = 0; a < 2; ++a)
-                    v += wt[a] * wt[b] * wt[c] * xc[base[0][a] + nc * (base[1][b] + nc * base[2][c])];
+                    v += wt[a] * wt[b] * wt[c] * xc[at3<NC>(base[0][a], base[1][b], base[2][c])];
         x[o] += v;
     }
+}
+
+// coarsest level on wavefront 0: zero (optional), sweeps, Poisson mean removal
+template <int N>
+__device__ __forceinline__ void s_coarse_wave(double* x, const double* b, const SmallArgs& A,
+                                              bool zero) {
+    constexpr int CNT = N * N * N;
+    const int lane = threadIdx.x;
+    const double h = 1.0 / (double)N;
+    const double c = A.nu / (h * h), diag = A.sigma + 6.0 * c;
+    if (zero)
+        for (int o = lane; o < CNT; o += 64) x[o] = 0.0;
+    wave_sync();
+    for (int s = 0; s < A.sweeps; ++s) {
+        s_gs<N>(x, b, c, diag, 0, lane, 64);
+        wave_sync();
+        s_gs<N>(x, b, c, diag, 1, lane, 64);
+        wave_sync();
+    }
+    if (A.poisson) {
+        double v = 0.0;
+        for (int o = lane; o < CNT; o += 64) v += x[o];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        const double m = v / (double)CNT;
+        wave_sync();
+        for (int o = lane; o < CNT; o += 64) x[o] -= m;
+        wave_sync();
+    }
+}
+
+// one level above the coarsest: pre-smoothing, residual and restriction (down)
+template <int N>
+__device__ __forceinline__ void s_down(double* x, const double* b, double* r, double* bnext,
+                                       const SmallArgs& A, bool zero) {
+    constexpr int CNT = N * N * N;
+    const double h = 1.0 / (double)N;
+    const double c = A.nu / (h * h), diag = A.sigma + 6.0 * c;
+    if (zero) {
+        for (int o = threadIdx.x; o < CNT; o += blockDim.x) x[o] = 0.0;
+        __syncthreads();
+    }
+    for (int s = 0; s < A.pre; ++s) {
+        s_gs<N>(x, b, c, diag, 0, threadIdx.x, blockDim.x);
+        __syncthreads();
+        s_gs<N>(x, b, c, diag, 1, threadIdx.x, blockDim.x);
+        __syncthreads();
+    }
+    s_residual<N>(x, b, r, A.sigma, c);
+    __syncthreads();
+    s_restrict<N>(r, bnext);
     __syncthreads();
 }
 
-__device__ void s_fill(double* x, int cnt, double v) {
-    for (int o = threadIdx.x; o < cnt; o += blockDim.x) x[o] = v;
+// prolongation and post-smoothing (up)
+template <int N>
+__device__ __forceinline__ void s_up(double* x, const double* b, const double* xc, const SmallArgs& A) {
+    const double h = 1.0 / (double)N;
+    const double c = A.nu / (h * h), diag = A.sigma + 6.0 * c;
+    s_prolong_add<N>(x, xc);
     __syncthreads();
+    for (int s = 0; s < A.post; ++s) {
+        s_gs<N>(x, b, c, diag, 1, threadIdx.x, blockDim.x);
+        __syncthreads();
+        s_gs<N>(x, b, c, diag, 0, threadIdx.x, blockDim.x);
+        __syncthreads();
+    }
 }
 
-__device__ void s_remove_mean(double* x, int cnt, double* red) {
-    double s = 0.0;
-    // fixed per-thread chunking then the fixed block tree
-    for (int o = threadIdx.x; o < cnt; o += blockDim.x) s += x[o];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) red[16] = s / (double)cnt;
-    __syncthreads();
-    const double m = red[16];
-    for (int o = threadIdx.x; o < cnt; o += blockDim.x) x[o] -= m;
-    __syncthreads();
-}
-
+// One V-cycle over the levels N0 (, N0/2, ...) down to the coarsest (< 8).
+// Level arrays in LDS: [x, b, r] per level, consecutive.
+template <int N0>
 __global__ void __launch_bounds__(kSmallThreads)
-k_small_vcycle(double* __restrict__ xg, const double* __restrict__ bg, int64_t cs, SmallPlan P,
+k_small_vcycle(double* __restrict__ xg, const double* __restrict__ bg, int64_t cs, SmallArgs A,
                const int32_t* __restrict__ active) {
     extern __shared__ double lds[];
-    __shared__ double red[17];
     const int comp = blockIdx.x;
     if (!active[comp]) return;
-    const int n0 = P.n[0], c0 = n0 * n0 * n0;
-    double* x0 = lds + P.off[0];
-    double* b0 = x0 + c0;
-    for (int o = threadIdx.x; o < c0; o += blockDim.x) {
+    constexpr int N1 = N0 / 2;
+    constexpr int C0 = N0 * N0 * N0, C1 = N1 * N1 * N1;
+    double* x0 = lds;
+    double* b0 = x0 + C0;
+    double* r0 = b0 + C0;
+    double* x1 = r0 + C0;
+    double* b1 = x1 + C1;
+    double* r1 = b1 + C1;
+    for (int o = threadIdx.x; o < C0; o += blockDim.x) {
         b0[o] = bg[comp * cs + o];
-        x0[o] = P.zero_init ? 0.0 : xg[comp * cs + o];
+        x0[o] = A.zero_init ? 0.0 : xg[comp * cs + o];
     }
     __syncthreads();
-    // down
-    for (int l = 0; l < P.nl - 1; ++l) {
-        const int n = P.n[l], cnt = n * n * n;
-        double* x = lds + P.off[l];
-        double* b = x + cnt;
-        double* r = b + cnt;
-        const double h = 1.0 / (double)n;  // level spacing relative to the unit box
-        const double c = P.nu / (h * h), diag = P.sigma + 6.0 * c;
-        if (l > 0) s_fill(x, cnt, 0.0);
-        for (int s = 0; s < P.pre; ++s) {
-            s_gs(x, b, n, c, diag, 0);
-            s_gs(x, b, n, c, diag, 1);
-        }
-        s_residual(x, b, r, n, P.sigma, c);
-        double* bnext = lds + P.off[l + 1] + P.n[l + 1] * P.n[l + 1] * P.n[l + 1];
-        s_restrict(r, n, bnext);
+    s_down<N0>(x0, b0, r0, b1, A, false);
+    if constexpr (N1 >= 8) {
+        constexpr int N2 = N1 / 2;
+        constexpr int C2 = N2 * N2 * N2;
+        double* x2 = r1 + C1;
+        double* b2 = x2 + C2;
+        s_down<N1>(x1, b1, r1, b2, A, true);
+        if (threadIdx.x < 64) s_coarse_wave<N2>(x2, b2, A, true);
+        __syncthreads();
+        s_up<N1>(x1, b1, x2, A);
+    } else {
+        (void)r1;
+        if (threadIdx.x < 64) s_coarse_wave<N1>(x1, b1, A, true);
+        __syncthreads();
     }
-    {
-        const int l = P.nl - 1, n = P.n[l], cnt = n * n * n;
-        double* x = lds + P.off[l];
-        double* b = x + cnt;
-        const double h = 1.0 / (double)n;
-        const double c = P.nu / (h * h), diag = P.sigma + 6.0 * c;
-        if (l > 0) s_fill(x, cnt, 0.0);
-        for (int s = 0; s < P.sweeps; ++s) {
-            s_gs(x, b, n, c, diag, 0);
-            s_gs(x, b, n, c, diag, 1);
-        }
-        if (P.poisson) s_remove_mean(x, cnt, red);
-    }
-    // up
-    for (int l = P.nl - 2; l >= 0; --l) {
-        const int n = P.n[l], cnt = n * n * n;
-        double* x = lds + P.off[l];
-        double* b = x + cnt;
-        const double h = 1.0 / (double)n;
-        const double c = P.nu / (h * h), diag = P.sigma + 6.0 * c;
-        s_prolong_add(x, n, lds + P.off[l + 1]);
-        for (int s = 0; s < P.post; ++s) {
-            s_gs(x, b, n, c, diag, 1);
-            s_gs(x, b, n, c, diag, 0);
-        }
-    }
-    for (int o = threadIdx.x; o < c0; o += blockDim.x) xg[comp * cs + o] = x0[o];
+    s_up<N0>(x0, b0, x1, A);
+    for (int o = threadIdx.x; o < C0; o += blockDim.x) xg[comp * cs + o] = x0[o];
 }
 
 dim3 tiles(int n, int ncomp, bool colour) {
@@ -464,24 +515,24 @@ struct LevelPtr {
 
 hipib_status small_vcycle(hipib_ctx* ctx, int l, LevelPtr p, int ncomp, const OpCoef& oc,
                           bool zero_init) {
-    SmallPlan P{};
-    P.nl = ctx->L - l;
-    int off = 0;
-    for (int m = 0; m < P.nl; ++m) {
-        const int n = ctx->lv[l + m].n;
-        P.n[m] = n;
-        P.off[m] = off;
-        off += 3 * n * n * n;
-    }
-    P.pre = ctx->cfg.mg_pre;
-    P.post = ctx->cfg.mg_post;
-    P.sweeps = ctx->cfg.mg_coarse_sweeps;
-    P.poisson = oc.poisson;
-    P.zero_init = zero_init ? 1 : 0;
-    P.sigma = oc.sigma;
-    P.nu = oc.nu;
-    k_small_vcycle<<<ncomp, kSmallThreads, ctx->small_lds, ctx->stream>>>(
-        p.x, p.b, p.cs, P, ctx->st->active);
+    SmallArgs A{};
+    A.pre = ctx->cfg.mg_pre;
+    A.post = ctx->cfg.mg_post;
+    A.sweeps = ctx->cfg.mg_coarse_sweeps;
+    A.poisson = oc.poisson;
+    A.zero_init = zero_init ? 1 : 0;
+    A.sigma = oc.sigma;
+    A.nu = oc.nu;
+    const int n = ctx->lv[l].n;
+    const dim3 grid(ncomp), blk(kSmallThreads);
+    if (n == 16)
+        k_small_vcycle<16><<<grid, blk, ctx->small_lds, ctx->stream>>>(p.x, p.b, p.cs, A, ctx->st->active);
+    else if (n == 12)
+        k_small_vcycle<12><<<grid, blk, ctx->small_lds, ctx->stream>>>(p.x, p.b, p.cs, A, ctx->st->active);
+    else if (n == 8)
+        k_small_vcycle<8><<<grid, blk, ctx->small_lds, ctx->stream>>>(p.x, p.b, p.cs, A, ctx->st->active);
+    else
+        return fail(HIPIB_E_INVAL, "no coarse-level kernel for n = %d", n);
     HIPIB_HIP(hipGetLastError());
     return HIPIB_OK;
 }
@@ -575,9 +626,12 @@ void timer_stop(hipib_ctx* ctx, int pair) {
 hipib_status mg_prepare(hipib_ctx* ctx) {
     if (ctx->small_lds > 160 * 1024)
         return fail(HIPIB_E_INVAL, "coarse levels need %zu bytes of LDS", ctx->small_lds);
-    HIPIB_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_vcycle),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)ctx->small_lds));
+    HIPIB_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_vcycle<16>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)ctx->small_lds));
+    HIPIB_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_vcycle<12>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)ctx->small_lds));
+    HIPIB_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_vcycle<8>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)ctx->small_lds));
     return HIPIB_OK;
 }
 
