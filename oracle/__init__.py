@@ -80,6 +80,17 @@ def lib():
             "ibref_ns_step": (C.c_int, [P, P, P, P, P]),
             "ibref_ib_step": (C.c_int, [P, P, P, P, P, f64, P]),
             "ibref_advance": (C.c_int, [P, P, P, P, P, f64, i32, f64, f64, P]),
+            "ibref_convection_vjp": (None, [i32, P, P, P]),
+            "ibref_dphi": (f64, [f64]),
+            "ibref_spread_vjp_X": (None, [i32, i32, P, P, P, P]),
+            "ibref_interp_vjp_X": (None, [i32, i32, P, P, P, P]),
+            "ibref_pk1_tangent": (C.c_int, [i32, P, P, P, P, P]),
+            "ibref_fe_hvp": (C.c_int, [P, P, P, P]),
+            "ibref_fe_param_vjp": (C.c_int, [P, P, P, P]),
+            "ibref_pressure_vjp": (None, [i32, P, P, f64, P, P]),
+            "ibref_project": (C.c_int, [P, P]),
+            "ibref_adjoint_step": (C.c_int, [P, P, P, P, P, f64, P, P, P]),
+            "ibref_rollout_grad": (C.c_int, [P, P, P, P, f64, i32, f64, f64, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -266,3 +277,88 @@ def run_problem(prob, n_steps: Optional[int] = None, t0: float = 0.0, **fluid_ov
     p0 = np.zeros((prob.n,) * 3)
     steps = prob.n_steps if n_steps is None else n_steps
     return advance(fl, mesh, u0, p0, prob.X0, t0, steps, prob.p0, prob.T)
+
+
+# --------------------------------------------------------------------------
+# discrete adjoint
+# --------------------------------------------------------------------------
+
+def convection_vjp(u: np.ndarray, lam: np.ndarray) -> np.ndarray:
+    u, lam = _f64(u), _f64(lam)
+    out = np.empty_like(u)
+    lib().ibref_convection_vjp(u.shape[-1], _p(u), _p(lam), _p(out))
+    return out
+
+
+def dphi(r: float) -> float:
+    return lib().ibref_dphi(float(r))
+
+
+def spread_vjp_X(n, X, F, lam_f, lamX=None):
+    X, F, lam_f = _f64(X), _f64(F), _f64(lam_f)
+    out = np.zeros_like(X) if lamX is None else _f64(lamX).copy()
+    lib().ibref_spread_vjp_X(n, X.shape[0], _p(X), _p(F), _p(lam_f), _p(out))
+    return out
+
+
+def interp_vjp_X(X, u, lamU, lamX=None):
+    X, u, lamU = _f64(X), _f64(u), _f64(lamU)
+    out = np.zeros_like(X) if lamX is None else _f64(lamX).copy()
+    lib().ibref_interp_vjp_X(u.shape[-1], X.shape[0], _p(X), _p(u), _p(lamU), _p(out))
+    return out
+
+
+def pk1_tangent(model, params, Fm, dFm, ef=(1.0, 0.0, 0.0)):
+    par = _f64(list(params) + [0.0] * (5 - len(params)))
+    Fm, dFm, ef = _f64(Fm).reshape(3, 3), _f64(dFm).reshape(3, 3), _f64(ef)
+    dP = np.empty((3, 3))
+    _check(lib().ibref_pk1_tangent(model, _p(par), _p(Fm), _p(ef), _p(dFm), _p(dP)), "pk1_tangent")
+    return dP
+
+
+def fe_hvp(mesh: MeshBuffers, x, V):
+    x, V = _f64(x), _f64(V)
+    HV = np.empty_like(x)
+    _check(lib().ibref_fe_hvp(C.byref(mesh.s), _p(x), _p(V), _p(HV)), "fe_hvp")
+    return HV
+
+
+def fe_param_vjp(mesh: MeshBuffers, x, lamF):
+    x, lamF = _f64(x), _f64(lamF)
+    dth = np.zeros((mesh.mat_model.shape[0], 4))
+    _check(lib().ibref_fe_param_vjp(C.byref(mesh.s), _p(x), _p(lamF), _p(dth)), "fe_param_vjp")
+    return dth
+
+
+def pressure_vjp(faces, x, p, lamF):
+    faces, x, lamF = _i32(faces), _f64(x), _f64(lamF)
+    out = np.zeros_like(x)
+    lib().ibref_pressure_vjp(faces.shape[0], _p(faces), _p(x), float(p), _p(lamF), _p(out))
+    return out
+
+
+def project(fl: Fluid, v):
+    v = _f64(v).copy()
+    _check(lib().ibref_project(C.byref(fl), _p(v)), "project")
+    return v
+
+
+def adjoint_step(fl: Fluid, mesh: MeshBuffers, u_n, X_n, u_np1, pressure, lam_u, lam_X,
+                 dtheta=None):
+    u_n, X_n, u_np1 = _f64(u_n), _f64(X_n), _f64(u_np1)
+    lu, lX = _f64(lam_u).copy(), _f64(lam_X).copy()
+    dth = np.zeros((mesh.mat_model.shape[0], 4)) if dtheta is None else _f64(dtheta).copy()
+    _check(lib().ibref_adjoint_step(C.byref(fl), C.byref(mesh.s), _p(u_n), _p(X_n), _p(u_np1),
+                                    float(pressure), _p(lu), _p(lX), _p(dth)), "adjoint_step")
+    return lu, lX, dth
+
+
+def rollout_grad(fl: Fluid, mesh: MeshBuffers, u0, X0, t0, n_steps, p0, T, X_target):
+    u0, X0, Xt = _f64(u0), _f64(X0), _f64(X_target)
+    L = C.c_double(0.0)
+    dX = np.empty_like(X0)
+    dth = np.zeros((mesh.mat_model.shape[0], 4))
+    _check(lib().ibref_rollout_grad(C.byref(fl), C.byref(mesh.s), _p(u0), _p(X0), float(t0),
+                                    int(n_steps), float(p0), float(T), _p(Xt), C.byref(L), _p(dX),
+                                    _p(dth)), "rollout_grad")
+    return L.value, dX, dth

@@ -713,3 +713,468 @@ int ibref_advance(const ibref_fluid* fl, const ibref_mesh* m, double* u, double*
     }
     return IBREF_OK;
 }
+
+/* ------------------------------------------------------------------------- */
+/* discrete adjoint                                                          */
+/* ------------------------------------------------------------------------- */
+/*
+ * Reverse mode of the step above, written as the transpose of each linear map
+ * and the chain rule through each nonlinear one.  lam denotes dL/d(entry).
+ * With Xn+1 = Xn + dt J(Xn) u^{n+1},  u^{n+1} = P H^{-1} g,
+ * g = (rho/dt) u^n - rho C(u^n) + S(Xn) F(Xn; theta):
+ *   lam_tot = lam_u' + dt J(Xn)^T lam_X'            (J^T = h^3 S)
+ *   lam_X   = lam_X' + dt [d_X J(X)u^{n+1}]^T lam_X'
+ *   lam_*   = P lam_tot                              (P symmetric)
+ *   lam_g   = H^{-1} lam_*                           (H symmetric)
+ *   lam_u^n = (rho/dt) lam_g - rho C'(u^n)^T lam_g
+ *   lam_F   = S(Xn)^T lam_g = J(Xn) lam_g / h^3
+ *   lam_X  += [d_X S(X)F]^T lam_g + (dF/dX)^T lam_F   ((dF_el/dX) is symmetric)
+ *   dtheta += (dF/dtheta)^T lam_F
+ */
+
+/* reverse of ibref_convection: the same loops with every product differentiated */
+void ibref_convection_vjp(int32_t n, const double* u, const double* lam, double* out) {
+    const double h = 1.0 / n;
+    const long N3 = (long)n * n * n;
+    for (long t = 0; t < 3 * N3; ++t) out[t] = 0.0;
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i)
+                for (int d = 0; d < 3; ++d) {
+                    const double* ud = u + d * N3;
+                    double* od = out + d * N3;
+                    const double lc = lam[d * N3 + gidx(i, j, k, n)] / h;
+                    int p[3] = {i, j, k};
+                    /* normal flux at c (+) and at c - e_d (-) */
+                    for (int sgn = 1; sgn >= -1; sgn -= 2) {
+                        int c0[3] = {p[0], p[1], p[2]};
+                        if (sgn < 0) c0[d] -= 1;
+                        int c1[3] = {c0[0], c0[1], c0[2]};
+                        c1[d] += 1;
+                        long a0 = gidx(c0[0], c0[1], c0[2], n), a1 = gidx(c1[0], c1[1], c1[2], n);
+                        double A = 0.5 * (ud[a0] + ud[a1]);
+                        double gA = sgn * 2.0 * A * lc;
+                        od[a0] += 0.5 * gA;
+                        od[a1] += 0.5 * gA;
+                    }
+                    for (int e = 0; e < 3; ++e) {
+                        if (e == d) continue;
+                        const double* ue = u + e * N3;
+                        double* oe = out + e * N3;
+                        /* edge flux at c + e_e (+) and at c (-) */
+                        for (int sgn = 1; sgn >= -1; sgn -= 2) {
+                            int cc[3] = {p[0], p[1], p[2]};
+                            if (sgn > 0) cc[e] += 1;
+                            int me[3] = {cc[0], cc[1], cc[2]};
+                            me[e] -= 1;
+                            int md[3] = {cc[0], cc[1], cc[2]};
+                            md[d] -= 1;
+                            long ic = gidx(cc[0], cc[1], cc[2], n);
+                            long ime = gidx(me[0], me[1], me[2], n);
+                            long imd = gidx(md[0], md[1], md[2], n);
+                            double a = 0.5 * (ud[ime] + ud[ic]);
+                            double b = 0.5 * (ue[imd] + ue[ic]);
+                            double gE = sgn * lc;
+                            od[ime] += 0.5 * gE * b;
+                            od[ic] += 0.5 * gE * b;
+                            oe[imd] += 0.5 * gE * a;
+                            oe[ic] += 0.5 * gE * a;
+                        }
+                    }
+                }
+}
+
+/* derivative of Peskin's four-point kernel (phi is C^1) */
+double ibref_dphi(double r) {
+    double a = fabs(r), s = r < 0.0 ? -1.0 : 1.0;
+    if (a < 1.0) return s * (-2.0 + (2.0 - 4.0 * a) / sqrt(1.0 + 4.0 * a - 4.0 * a * a)) / 8.0;
+    if (a < 2.0) return s * (-2.0 - (6.0 - 4.0 * a) / sqrt(-7.0 + 12.0 * a - 4.0 * a * a)) / 8.0;
+    return 0.0;
+}
+
+static void stencil_1d_d(double r, int* first, double w[4], double dw[4]) {
+    int b = (int)floor(r);
+    *first = b - 1;
+    for (int m = 0; m < 4; ++m) {
+        w[m] = ibref_phi(r - (double)(b - 1 + m));
+        dw[m] = ibref_dphi(r - (double)(b - 1 + m));
+    }
+}
+
+/* lamX_q,e += sum_d F^d_q sum_idx lam_f^d[idx] d/dX_e delta_h(x_idx - X_q)
+ * with d/dX_e prod phi = phi'(r_e)/h prod_{other} phi */
+void ibref_spread_vjp_X(int32_t n, int32_t n_nodes, const double* X, const double* F,
+                        const double* lam_f, double* lamX) {
+    const double h = 1.0 / n, ih3 = 1.0 / (h * h * h);
+    const long N3 = (long)n * n * n;
+    for (int q = 0; q < n_nodes; ++q)
+        for (int d = 0; d < 3; ++d) {
+            int s0[3];
+            double w[3][4], dw[3][4];
+            for (int e = 0; e < 3; ++e)
+                stencil_1d_d(lattice_coord(X[3 * q + e], h, d, e), &s0[e], w[e], dw[e]);
+            double g[3] = {0.0, 0.0, 0.0};
+            for (int c = 0; c < 4; ++c)
+                for (int b = 0; b < 4; ++b)
+                    for (int a = 0; a < 4; ++a) {
+                        double l = lam_f[d * N3 + gidx(s0[0] + a, s0[1] + b, s0[2] + c, n)];
+                        g[0] += l * dw[0][a] * w[1][b] * w[2][c];
+                        g[1] += l * w[0][a] * dw[1][b] * w[2][c];
+                        g[2] += l * w[0][a] * w[1][b] * dw[2][c];
+                    }
+            for (int e = 0; e < 3; ++e) lamX[3 * q + e] += F[3 * q + d] * ih3 * g[e] / h;
+        }
+}
+
+/* lamX_q,e += sum_d lamU_q,d sum_idx u^d[idx] d/dX_e (prod phi) */
+void ibref_interp_vjp_X(int32_t n, int32_t n_nodes, const double* X, const double* u,
+                        const double* lamU, double* lamX) {
+    const double h = 1.0 / n;
+    const long N3 = (long)n * n * n;
+    for (int q = 0; q < n_nodes; ++q)
+        for (int d = 0; d < 3; ++d) {
+            int s0[3];
+            double w[3][4], dw[3][4];
+            for (int e = 0; e < 3; ++e)
+                stencil_1d_d(lattice_coord(X[3 * q + e], h, d, e), &s0[e], w[e], dw[e]);
+            double g[3] = {0.0, 0.0, 0.0};
+            for (int c = 0; c < 4; ++c)
+                for (int b = 0; b < 4; ++b)
+                    for (int a = 0; a < 4; ++a) {
+                        double v = u[d * N3 + gidx(s0[0] + a, s0[1] + b, s0[2] + c, n)];
+                        g[0] += v * dw[0][a] * w[1][b] * w[2][c];
+                        g[1] += v * w[0][a] * dw[1][b] * w[2][c];
+                        g[2] += v * w[0][a] * w[1][b] * dw[2][c];
+                    }
+            for (int e = 0; e < 3; ++e) lamX[3 * q + e] += lamU[3 * q + d] * g[e] / h;
+        }
+}
+
+/*
+ * Directional derivative of P (the laws of ibref_pk1) along dF:
+ *   d(F^{-T}) = -F^{-T} dF^T F^{-T},  d ln J = F^{-T} : dF,
+ *   dI1 = 2 F : dF,  d J^{-2/3} = -(2/3) J^{-2/3} d ln J,  dI4f = 2 (F e) . (dF e),
+ *   iso coefficient alpha = mu_s (NH) or a exp(b (I1bar - 3)) (HO),
+ *   fibre coefficient f(I4) = 2 a_f (I4-1) exp(b_f (I4-1)^2) for I4 > 1, with
+ *   f'(I4) = 2 a_f exp(b_f (I4-1)^2) (1 + 2 b_f (I4-1)^2).
+ */
+int ibref_pk1_tangent(int32_t model, const double* par, const double* Fm, const double* ef,
+                      const double* dFm, double* dP) {
+    double J = det3(Fm);
+    if (!(J > 0.0)) return IBREF_E_NUMERIC;
+    double cof[9], FiT[9], dFiT[9];
+    cof3(Fm, cof);
+    for (int r = 0; r < 9; ++r) FiT[r] = cof[r] / J;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) s += FiT[3 * r + a] * dFm[3 * b + a] * FiT[3 * b + c];
+            dFiT[3 * r + c] = -s;
+        }
+    double I1 = 0.0, dI1 = 0.0, dlnJ = 0.0;
+    for (int r = 0; r < 9; ++r) {
+        I1 += Fm[r] * Fm[r];
+        dI1 += 2.0 * Fm[r] * dFm[r];
+        dlnJ += FiT[r] * dFm[r];
+    }
+    double Jm23 = pow(J, -2.0 / 3.0), dJm23 = -2.0 / 3.0 * Jm23 * dlnJ;
+    double lnJ = log(J);
+    double alpha, dalpha, kappa;
+    double fib = 0.0, dfib = 0.0, Fe[3] = {0, 0, 0}, dFe[3] = {0, 0, 0};
+    if (model == IBREF_NEO_HOOKEAN) {
+        alpha = par[0];
+        dalpha = 0.0;
+        kappa = par[1];
+    } else if (model == IBREF_HOLZAPFEL_OGDEN) {
+        double a = par[0], b = par[1], af = par[2], bf = par[3];
+        kappa = par[4];
+        double E1 = exp(b * (Jm23 * I1 - 3.0));
+        alpha = a * E1;
+        dalpha = a * E1 * b * (dJm23 * I1 + Jm23 * dI1);
+        for (int r = 0; r < 3; ++r) {
+            Fe[r] = Fm[3 * r] * ef[0] + Fm[3 * r + 1] * ef[1] + Fm[3 * r + 2] * ef[2];
+            dFe[r] = dFm[3 * r] * ef[0] + dFm[3 * r + 1] * ef[1] + dFm[3 * r + 2] * ef[2];
+        }
+        double I4 = Fe[0] * Fe[0] + Fe[1] * Fe[1] + Fe[2] * Fe[2];
+        if (I4 > 1.0) {
+            double dI4 = 2.0 * (Fe[0] * dFe[0] + Fe[1] * dFe[1] + Fe[2] * dFe[2]);
+            double Ef = exp(bf * (I4 - 1.0) * (I4 - 1.0));
+            fib = 2.0 * af * (I4 - 1.0) * Ef;
+            dfib = 2.0 * af * Ef * (1.0 + 2.0 * bf * (I4 - 1.0) * (I4 - 1.0)) * dI4;
+        }
+    } else {
+        return IBREF_E_INVAL;
+    }
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            int o = 3 * r + c;
+            double M = Fm[o] - I1 / 3.0 * FiT[o];
+            double dM = dFm[o] - dI1 / 3.0 * FiT[o] - I1 / 3.0 * dFiT[o];
+            dP[o] = (dalpha * Jm23 + alpha * dJm23) * M + alpha * Jm23 * dM +
+                    dfib * Fe[r] * ef[c] + fib * dFe[r] * ef[c] +
+                    kappa * dlnJ * FiT[o] + kappa * lnJ * dFiT[o];
+        }
+    return IBREF_OK;
+}
+
+/* shared element loop for the force derivatives: per Gauss point returns the
+ * shape gradients, the weight and F; mode 0: HV -= dP grad N w; mode 1:
+ * dtheta += -w dP/dtheta : (sum_a lam_a (x) grad N_a) */
+static int fe_derivative_loop(const ibref_mesh* m, const double* x, const double* V, double* out,
+                              int mode) {
+    const double gp = 1.0 / sqrt(3.0);
+    for (int e = 0; e < m->n_elems; ++e) {
+        const int32_t* cn = m->conn + 8L * e;
+        int mid = m->mat_id[e];
+        if (mid < 0 || mid >= m->n_mats) return IBREF_E_INVAL;
+        const double* par = m->mat_params + 5L * mid;
+        int model = m->mat_model[mid];
+        const double* ef = m->fibre + 3L * e;
+        double Xe[8][3], xe[8][3], ve[8][3], He[8][3];
+        for (int a = 0; a < 8; ++a)
+            for (int r = 0; r < 3; ++r) {
+                Xe[a][r] = m->X_ref[3L * cn[a] + r];
+                xe[a][r] = x[3L * cn[a] + r];
+                ve[a][r] = V[3L * cn[a] + r];
+                He[a][r] = 0.0;
+            }
+        for (int g = 0; g < 8; ++g) {
+            double xi[3] = {(g & 1) ? gp : -gp, (g & 2) ? gp : -gp, (g & 4) ? gp : -gp};
+            double dN[8][3];
+            hex_dshape(xi, dN);
+            double J0[9] = {0};
+            for (int a = 0; a < 8; ++a)
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) J0[3 * r + c] += Xe[a][r] * dN[a][c];
+            double w = det3(J0);
+            if (!(w > 0.0)) return IBREF_E_NUMERIC;
+            double cof[9], J0inv[9];
+            cof3(J0, cof);
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) J0inv[3 * r + c] = cof[3 * c + r] / w;
+            double gN[8][3];
+            for (int a = 0; a < 8; ++a)
+                for (int c = 0; c < 3; ++c) {
+                    double s = 0.0;
+                    for (int r = 0; r < 3; ++r) s += dN[a][r] * J0inv[3 * r + c];
+                    gN[a][c] = s;
+                }
+            double Fm[9] = {0}, dF[9] = {0};
+            for (int a = 0; a < 8; ++a)
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) {
+                        Fm[3 * r + c] += xe[a][r] * gN[a][c];
+                        dF[3 * r + c] += ve[a][r] * gN[a][c];
+                    }
+            if (mode == 0) {
+                double dP[9];
+                int rc = ibref_pk1_tangent(model, par, Fm, ef, dF, dP);
+                if (rc) return rc;
+                for (int a = 0; a < 8; ++a)
+                    for (int r = 0; r < 3; ++r) {
+                        double s = 0.0;
+                        for (int c = 0; c < 3; ++c) s += dP[3 * r + c] * gN[a][c];
+                        He[a][r] -= s * w;
+                    }
+            } else if (model == IBREF_HOLZAPFEL_OGDEN) {
+                /* dP/da, dP/db (isotropic), dP/da_f, dP/db_f (fibre), contracted with dF */
+                double J = det3(Fm);
+                if (!(J > 0.0)) return IBREF_E_NUMERIC;
+                double cofF[9];
+                cof3(Fm, cofF);
+                double I1 = 0.0;
+                for (int r = 0; r < 9; ++r) I1 += Fm[r] * Fm[r];
+                double Jm23 = pow(J, -2.0 / 3.0);
+                double b = par[1], af = par[2], bf = par[3], a0 = par[0];
+                double E1 = exp(b * (Jm23 * I1 - 3.0));
+                double Miso = 0.0, Mfib = 0.0;
+                double Fe[3];
+                for (int r = 0; r < 3; ++r)
+                    Fe[r] = Fm[3 * r] * ef[0] + Fm[3 * r + 1] * ef[1] + Fm[3 * r + 2] * ef[2];
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) {
+                        int o = 3 * r + c;
+                        Miso += Jm23 * (Fm[o] - I1 / 3.0 * cofF[o] / J) * dF[o];
+                        Mfib += Fe[r] * ef[c] * dF[o];
+                    }
+                double I4 = Fe[0] * Fe[0] + Fe[1] * Fe[1] + Fe[2] * Fe[2];
+                double* dt = out + 4L * mid;
+                dt[0] += -w * E1 * Miso;
+                dt[1] += -w * a0 * (Jm23 * I1 - 3.0) * E1 * Miso;
+                if (I4 > 1.0) {
+                    double Ef = exp(bf * (I4 - 1.0) * (I4 - 1.0));
+                    dt[2] += -w * 2.0 * (I4 - 1.0) * Ef * Mfib;
+                    dt[3] += -w * 2.0 * af * (I4 - 1.0) * (I4 - 1.0) * (I4 - 1.0) * Ef * Mfib;
+                }
+                (void)af;
+            }
+        }
+        if (mode == 0)
+            for (int a = 0; a < 8; ++a)
+                for (int r = 0; r < 3; ++r) out[3L * cn[a] + r] += He[a][r];
+    }
+    return IBREF_OK;
+}
+
+int ibref_fe_hvp(const ibref_mesh* m, const double* x, const double* V, double* HV) {
+    for (long r = 0; r < 3L * m->n_nodes; ++r) HV[r] = 0.0;
+    return fe_derivative_loop(m, x, V, HV, 0);
+}
+
+int ibref_fe_param_vjp(const ibref_mesh* m, const double* x, const double* lamF, double* dtheta) {
+    return fe_derivative_loop(m, x, lamF, dtheta, 1);
+}
+
+/* lamX_b += -p sum_g [dN_b/dxi (x_eta x mu) + dN_b/deta (mu x x_xi)],  mu = sum_a N_a lamF_a */
+void ibref_pressure_vjp(int32_t n_faces, const int32_t* faces, const double* x, double p,
+                        const double* lamF, double* lamX) {
+    const double gp = 1.0 / sqrt(3.0);
+    for (int f = 0; f < n_faces; ++f) {
+        const int32_t* fn = faces + 4L * f;
+        for (int g = 0; g < 4; ++g) {
+            double s = (g & 1) ? gp : -gp, t = (g & 2) ? gp : -gp;
+            double N[4], dNs[4], dNt[4];
+            for (int a = 0; a < 4; ++a) {
+                double sa = (a & 1) ? 1.0 : -1.0, ta = (a & 2) ? 1.0 : -1.0;
+                N[a] = (1.0 + sa * s) * (1.0 + ta * t) / 4.0;
+                dNs[a] = sa * (1.0 + ta * t) / 4.0;
+                dNt[a] = (1.0 + sa * s) * ta / 4.0;
+            }
+            double xs[3] = {0, 0, 0}, xt[3] = {0, 0, 0}, mu[3] = {0, 0, 0};
+            for (int a = 0; a < 4; ++a)
+                for (int r = 0; r < 3; ++r) {
+                    xs[r] += x[3L * fn[a] + r] * dNs[a];
+                    xt[r] += x[3L * fn[a] + r] * dNt[a];
+                    mu[r] += N[a] * lamF[3L * fn[a] + r];
+                }
+            double A[3] = {xt[1] * mu[2] - xt[2] * mu[1], xt[2] * mu[0] - xt[0] * mu[2],
+                           xt[0] * mu[1] - xt[1] * mu[0]};          /* x_eta x mu */
+            double B[3] = {mu[1] * xs[2] - mu[2] * xs[1], mu[2] * xs[0] - mu[0] * xs[2],
+                           mu[0] * xs[1] - mu[1] * xs[0]};          /* mu x x_xi */
+            for (int b = 0; b < 4; ++b)
+                for (int r = 0; r < 3; ++r) lamX[3L * fn[b] + r] -= p * (dNs[b] * A[r] + dNt[b] * B[r]);
+        }
+    }
+}
+
+/* the projection of ibref_ns_step applied to v (b = -(rho/dt) D v, Poisson,
+ * v -= (dt/rho) G p): the result is P v for any positive scale rho/dt */
+int ibref_project(const ibref_fluid* fl, double* v) {
+    const int n = fl->n;
+    const long N3 = (long)n * n * n;
+    const double rho = fl->rho, dt = fl->dt;
+    double* b = (double*)malloc(sizeof(double) * (size_t)N3);
+    double* p = (double*)calloc((size_t)N3, sizeof(double));
+    double* gp = (double*)malloc(sizeof(double) * 3 * (size_t)N3);
+    ibref_divergence(n, v, b);
+    for (long i = 0; i < N3; ++i) b[i] = -(rho / dt) * b[i];
+    remove_mean(N3, b);
+    int32_t cyc;
+    double rr;
+    int rc = ibref_mg_solve(fl, 0.0, 1.0, 1, b, p, &cyc, &rr);
+    if (!rc) {
+        ibref_gradient(n, p, gp);
+        for (long i = 0; i < 3 * N3; ++i) v[i] = v[i] - dt / rho * gp[i];
+    }
+    free(b); free(p); free(gp);
+    return rc;
+}
+
+int ibref_adjoint_step(const ibref_fluid* fl, const ibref_mesh* m, const double* u_n,
+                       const double* X_n, const double* u_np1, double pressure, double* lam_u,
+                       double* lam_X, double* dtheta) {
+    const int n = fl->n;
+    const long N3 = (long)n * n * n;
+    const long nn3 = 3L * m->n_nodes;
+    const double h = 1.0 / n, h3 = h * h * h, rho = fl->rho, dt = fl->dt, mu = fl->mu;
+    double* tot = (double*)calloc(3 * (size_t)N3, sizeof(double));
+    double* lg = (double*)calloc(3 * (size_t)N3, sizeof(double));
+    double* cv = (double*)calloc(3 * (size_t)N3, sizeof(double));
+    double* lamXn = (double*)malloc(sizeof(double) * (size_t)(nn3 > 0 ? nn3 : 1));
+    double* sX = (double*)malloc(sizeof(double) * (size_t)(nn3 > 0 ? nn3 : 1));
+    double* F = (double*)malloc(sizeof(double) * (size_t)(nn3 > 0 ? nn3 : 1));
+    double* lamF = (double*)malloc(sizeof(double) * (size_t)(nn3 > 0 ? nn3 : 1));
+    double* HV = (double*)malloc(sizeof(double) * (size_t)(nn3 > 0 ? nn3 : 1));
+    int rc = IBREF_OK;
+    /* X^{n+1} = X^n + dt J(X^n) u^{n+1} */
+    for (long r = 0; r < nn3; ++r) {
+        lamXn[r] = lam_X[r];
+        sX[r] = dt * lam_X[r];
+    }
+    ibref_spread(n, m->n_nodes, X_n, sX, tot);               /* tot = S(X^n) (dt lam_X') */
+    for (long i = 0; i < 3 * N3; ++i) tot[i] = lam_u[i] + h3 * tot[i];
+    ibref_interp_vjp_X(n, m->n_nodes, X_n, u_np1, sX, lamXn);
+    /* u^{n+1} = P u*,  u* = H^{-1} g */
+    rc = ibref_project(fl, tot);
+    for (int d = 0; d < 3 && !rc; ++d) {
+        int32_t cyc;
+        double rr;
+        rc = ibref_mg_solve(fl, rho / dt, mu, 0, tot + d * N3, lg + d * N3, &cyc, &rr);
+    }
+    if (!rc) {
+        /* g = (rho/dt) u^n - rho C(u^n) + S(X^n) F */
+        if (fl->convection) ibref_convection_vjp(n, u_n, lg, cv);
+        for (long i = 0; i < 3 * N3; ++i) lam_u[i] = rho / dt * lg[i] - rho * cv[i];
+        ibref_interpolate(n, m->n_nodes, X_n, lg, lamF);
+        for (long r = 0; r < nn3; ++r) lamF[r] /= h3;
+        rc = ibref_fe_force(m, X_n, F, NULL, NULL);
+    }
+    if (!rc) {
+        if (m->n_faces > 0 && pressure != 0.0) ibref_pressure_load(m->n_faces, m->faces, X_n, pressure, F);
+        ibref_spread_vjp_X(n, m->n_nodes, X_n, F, lg, lamXn);
+        rc = ibref_fe_hvp(m, X_n, lamF, HV);
+    }
+    if (!rc) {
+        for (long r = 0; r < nn3; ++r) lamXn[r] += HV[r];
+        if (m->n_faces > 0 && pressure != 0.0)
+            ibref_pressure_vjp(m->n_faces, m->faces, X_n, pressure, lamF, lamXn);
+        if (dtheta) rc = ibref_fe_param_vjp(m, X_n, lamF, dtheta);
+        for (long r = 0; r < nn3; ++r) lam_X[r] = lamXn[r];
+    }
+    free(tot); free(lg); free(cv); free(lamXn); free(sX); free(F); free(lamF); free(HV);
+    return rc;
+}
+
+int ibref_rollout_grad(const ibref_fluid* fl, const ibref_mesh* m, const double* u0,
+                       const double* X0, double t0, int32_t n_steps, double p0, double T,
+                       const double* X_target, double* loss, double* dLdX0, double* dtheta) {
+    const double pi = 3.14159265358979323846;
+    const int n = fl->n;
+    const long N3 = (long)n * n * n, nn3 = 3L * m->n_nodes;
+    double* us = (double*)malloc(sizeof(double) * 3 * (size_t)N3 * (size_t)(n_steps + 1));
+    double* Xs = (double*)malloc(sizeof(double) * (size_t)(nn3 > 0 ? nn3 : 1) * (size_t)(n_steps + 1));
+    double* p = (double*)calloc((size_t)N3, sizeof(double));
+    double* pr = (double*)malloc(sizeof(double) * (size_t)(n_steps > 0 ? n_steps : 1));
+    int rc = IBREF_OK;
+    memcpy(us, u0, sizeof(double) * 3 * (size_t)N3);
+    memcpy(Xs, X0, sizeof(double) * (size_t)nn3);
+    for (int s = 0; s < n_steps && !rc; ++s) {
+        double t = t0 + s * fl->dt;
+        pr[s] = 0.0;
+        if (p0 != 0.0 && T > 0.0) {
+            double sn = sin(pi * t / T);
+            pr[s] = p0 * sn * sn;
+        }
+        memcpy(us + 3 * N3 * (s + 1), us + 3 * N3 * s, sizeof(double) * 3 * (size_t)N3);
+        memcpy(Xs + nn3 * (s + 1), Xs + nn3 * s, sizeof(double) * (size_t)nn3);
+        rc = ibref_ib_step(fl, m, us + 3 * N3 * (s + 1), p, Xs + nn3 * (s + 1), pr[s], NULL);
+    }
+    if (!rc) {
+        const double* XN = Xs + nn3 * n_steps;
+        double L = 0.0;
+        for (long r = 0; r < nn3; ++r) {
+            double d = XN[r] - X_target[r];
+            L += d * d;
+            dLdX0[r] = 2.0 * d;
+        }
+        *loss = L;
+        double* lam_u = (double*)calloc(3 * (size_t)N3, sizeof(double));
+        for (int s = n_steps - 1; s >= 0 && !rc; --s)
+            rc = ibref_adjoint_step(fl, m, us + 3 * N3 * s, Xs + nn3 * s, us + 3 * N3 * (s + 1), pr[s],
+                                    lam_u, dLdX0, dtheta);
+        free(lam_u);
+    }
+    free(us); free(Xs); free(p); free(pr);
+    return rc;
+}

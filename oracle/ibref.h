@@ -98,6 +98,44 @@ int ibref_ib_step(const ibref_fluid* fl, const ibref_mesh* m, double* u, double*
 int ibref_advance(const ibref_fluid* fl, const ibref_mesh* m, double* u, double* p, double* X,
                   double t0, int32_t n_steps, double p0, double T, ibref_step_stats* stats);
 
+/* --- discrete adjoint (reverse mode of one IB step) ---------------------
+ * Gradients are taken with respect to the plain entries of the arrays
+ * (lam = dL/d(array)).  The multigrid solves are treated as exact inverses of
+ * their symmetric operators. */
+void ibref_convection_vjp(int32_t n, const double* u, const double* lam, double* out); /* out = C'(u)^T lam */
+double ibref_dphi(double r);                                           /* d phi / d r */
+/* lamX += [d/dX (S(X) F)]^T lam_f */
+void ibref_spread_vjp_X(int32_t n, int32_t n_nodes, const double* X, const double* F,
+                        const double* lam_f, double* lamX);
+/* lamX += [d/dX (J(X) u)]^T lamU */
+void ibref_interp_vjp_X(int32_t n, int32_t n_nodes, const double* X, const double* u,
+                        const double* lamU, double* lamX);
+/* dP = dP/dF : dF (directional derivative of the first Piola-Kirchhoff stress) */
+int ibref_pk1_tangent(int32_t model, const double* params, const double* Fm, const double* ef,
+                      const double* dFm, double* dP);
+/* HV = (dF/dx) V, the directional derivative of the elastic nodal force
+ * (minus the strain-energy Hessian times V); overwritten */
+int ibref_fe_hvp(const ibref_mesh* m, const double* x, const double* V, double* HV);
+/* dtheta[m][0..3] += lamF . dF/d(a, b, a_f, b_f) for Holzapfel-Ogden materials */
+int ibref_fe_param_vjp(const ibref_mesh* m, const double* x, const double* lamF, double* dtheta);
+/* lamX += [d/dx F_pressure(x)]^T lamF */
+void ibref_pressure_vjp(int32_t n_faces, const int32_t* faces, const double* x, double p,
+                        const double* lamF, double* lamX);
+/* v := P v, the discrete projection onto solenoidal fields (Poisson solve) */
+int ibref_project(const ibref_fluid* fl, double* v);
+/* Reverse of one ibref_ib_step from (u_n, X_n) to u_np1:
+ * in: lam_u = dL/du^{n+1}, lam_X = dL/dX^{n+1};  out: lam_u = dL/du^n,
+ * lam_X = dL/dX^n;  dtheta[n_mats][4] += dL/d(a, b, a_f, b_f) of this step. */
+int ibref_adjoint_step(const ibref_fluid* fl, const ibref_mesh* m, const double* u_n,
+                       const double* X_n, const double* u_np1, double pressure, double* lam_u,
+                       double* lam_X, double* dtheta);
+/* Loss L = sum_q |X^N_q - X_target_q|^2 after n_steps from (u0, X0) at t0 (p0 sin^2
+ * pressure as ibref_advance), its gradient with respect to X0 and the HO
+ * parameters, by storing every state and running ibref_adjoint_step backwards. */
+int ibref_rollout_grad(const ibref_fluid* fl, const ibref_mesh* m, const double* u0,
+                       const double* X0, double t0, int32_t n_steps, double p0, double T,
+                       const double* X_target, double* loss, double* dLdX0, double* dtheta);
+
 #ifdef __cplusplus
 }
 #endif
