@@ -68,6 +68,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -81,37 +82,60 @@ def main():
 
     torch.cuda.set_device(0)
     prob = inputs.ho_shell()
-    sim = hipib.Simulation(prob)
-    ctx = sim.ctx
 
-    # warm-up on a copy of the initial state (also settles the predicted cycle counts)
-    u, p, X = sim.u.clone(), sim.p.clone(), sim.X.clone()
-    if args.warmup > 0:
-        ctx.advance(u, p, X, 0.0, args.warmup, prob.p0, prob.T)
-    torch.cuda.synchronize()
-    del u, p, X
+    def run(precision, timer):
+        sim = hipib.Simulation(prob, precision=precision)
+        ctx = sim.ctx
+        # warm-up on a copy of the initial state (also settles the predicted cycle counts)
+        u, p, X = sim.u.clone(), sim.p.clone(), sim.X.clone()
+        if args.warmup > 0:
+            ctx.advance(u, p, X, 0.0, args.warmup, prob.p0, prob.T)
+        torch.cuda.synchronize()
+        del u, p, X
+        if timer:
+            ctx.timer_enable(hipib.TIMER_SMOOTH_FINE_POISSON)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.advance(sim.u, sim.p, sim.X, 0.0, args.steps, prob.p0, prob.T)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tim = ctx.timer_read() if timer else (0, 0.0, 0.0)
+        ctx.timer_enable(hipib.TIMER_OFF)
+        cyc, _ = ctx.step_stats()
+        if not (torch.isfinite(sim.u).all() and torch.isfinite(sim.X).all()):
+            raise RuntimeError("non-finite state after the timed run")
+        return sim, t1 - t0, tim, cyc
 
-    ctx.timer_enable(hipib.TIMER_SMOOTH_FINE_POISSON)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.advance(sim.u, sim.p, sim.X, 0.0, args.steps, prob.p0, prob.T)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    launches, kernel_ms, bytes_per_launch = ctx.timer_read()
-    ctx.timer_enable(hipib.TIMER_OFF)
-    cyc, _ = ctx.step_stats()
-
-    elapsed = t1 - t0
+    sim, elapsed, (launches, kernel_ms, bytes_per_launch), cyc = run(hipib.FP64, True)
     steps_per_s = args.steps / elapsed
-    if not (torch.isfinite(sim.u).all() and torch.isfinite(sim.X).all()):
-        raise RuntimeError("non-finite state after the timed run")
+
+    mixed = None
+    if not args.no_mixed:
+        msim, melapsed, _, mcyc = run(hipib.MIXED, False)
+
+        def rel(a, b):
+            return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+        dX = sim.X - torch.tensor(prob.X0, dtype=torch.float64, device=sim.X.device)
+        mixed = {
+            "value": round(args.steps / melapsed, 3), "unit": "steps/s",
+            "ms_per_step": round(1e3 * melapsed / args.steps, 4),
+            "dtype": "f32 V-cycles, spread weights and interpolation; f64 FE force, outer residual and updates",
+            "error_vs_fp64_path": {
+                "e_u": rel(msim.u, sim.u),
+                "e_p": rel(msim.p - msim.p.mean(), sim.p - sim.p.mean()),
+                "e_X": float((msim.X - sim.X).abs().max() / dX.abs().max()),
+            },
+            "mg_cycles_per_step": {"helmholtz_max_component": float(np.mean(mcyc[:, :3].max(1))),
+                                   "poisson": float(np.mean(mcyc[:, 3]))},
+        }
+        del msim
 
     avg_s = kernel_ms * 1e-3 / max(launches, 1)
     achieved = bytes_per_launch / avg_s / 1e9 if launches else 0.0
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-        "kernel": "k_gs_colour<2>: finest-level red or black Gauss-Seidel sweep of the Poisson solve",
+        "kernel": "k_gs<double,2>: finest-level red or black Gauss-Seidel half-sweep of the Poisson solve (packed layout)",
         "bytes_per_launch": bytes_per_launch, "launches": launches,
         "avg_launch_us": round(avg_s * 1e6, 3),
     }
@@ -134,6 +158,8 @@ def main():
                    "mg_cycles_per_step": {"helmholtz_max_component": float(np.mean(cyc[:, :3].max(1))),
                                           "poisson": float(np.mean(cyc[:, 3]))}},
         "roofline": roofline,
+        "mixed_precision": mixed,
+        "adjoint_over_forward": None,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)

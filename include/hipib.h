@@ -137,6 +137,38 @@ hipib_status hipib_advance(hipib_ctx* ctx, double* u, double* p, double* X, doub
 int32_t hipib_get_step_stats(hipib_ctx* ctx, int32_t* cycles, double* relres,
                              int32_t max_steps);
 
+/* --- discrete adjoint ----------------------------------------------------
+ * Reverse mode of hipib_ib_step for gradients of a loss L with respect to the
+ * node positions and the Holzapfel-Ogden parameters (a, b, a_f, b_f) of each
+ * material.  lam_* are dL/d(array entry) in the layout of the array.  The
+ * multigrid solves are treated as exact inverses of their symmetric operators
+ * (H = (rho/dt) I - mu Lap_h, and the projection P = I - G Lap_h^+ D), so the
+ * transposed step runs the same solvers: interpolation is the transpose of
+ * spreading, the force's transpose product is the strain-energy Hessian-vector
+ * product, the projection's adjoint is the projection.  dtheta is a device
+ * array [HIPIB_MAX_MATERIALS][4] that is accumulated into (+=); entries of
+ * neo-Hookean materials stay unchanged. */
+/* Reverse of one hipib_ib_step from (u_n, X_n) at cavity pressure `pressure`,
+ * whose result velocity was u_np1.  lam_u in: dL/du^{n+1}, out: dL/du^n;
+ * lam_X in: dL/dX^{n+1}, out: dL/dX^n.  Waits for completion. */
+hipib_status hipib_adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n,
+                                const double* u_np1, double pressure, double* lam_u,
+                                double* lam_X, double* dtheta);
+/* HV := (dF_el/dX) V, the directional derivative of the elastic nodal force
+ * (minus the strain-energy Hessian times V). */
+hipib_status hipib_fe_hvp(hipib_ctx* ctx, const double* X, const double* V, double* HV);
+/* dtheta += (dF_el/dtheta)^T lamF. */
+hipib_status hipib_fe_param_vjp(hipib_ctx* ctx, const double* X, const double* lamF,
+                                double* dtheta);
+/* lamX += [d/dX (S(X) F)]^T lam_f   (lam_f: [3][n^3]). */
+hipib_status hipib_spread_vjp_X(hipib_ctx* ctx, const double* X, const double* F,
+                                const double* lam_f, double* lamX);
+/* lamX += [d/dX (J(X) u)]^T lamU. */
+hipib_status hipib_interp_vjp_X(hipib_ctx* ctx, const double* X, const double* u,
+                                const double* lamU, double* lamX);
+/* out := C'(u)^T lam, the transpose of the convection Jacobian ([3][n^3]). */
+hipib_status hipib_convection_vjp(hipib_ctx* ctx, const double* u, const double* lam, double* out);
+
 /* --- measurement -------------------------------------------------------- */
 /* Kernel classes that can be timed with HIP events (each launch is bracketed
  * by a pair of events recorded on the context's stream). */

@@ -93,6 +93,10 @@ void free_all(hipib_ctx* ctx) {
         (void)hipFree(ctx->lv[l].b);
     }
     (void)hipFree(ctx->r0);
+    (void)hipFree(ctx->xp);
+    (void)hipFree(ctx->bpk);
+    (void)hipFree(ctx->e32);
+    (void)hipFree(ctx->r32);
     (void)hipFree(ctx->g);
     (void)hipFree(ctx->bp);
     (void)hipFree(ctx->part);
@@ -102,6 +106,11 @@ void free_all(hipib_ctx* ctx) {
     (void)hipFree(ctx->n_list);
     (void)hipFree(ctx->st);
     if (ctx->st_host) (void)hipHostFree(ctx->st_host);
+    (void)hipFree(ctx->adj_tot);
+    (void)hipFree(ctx->adj_lg);
+    (void)hipFree(ctx->adj_p);
+    (void)hipFree(ctx->adj_sX);
+    (void)hipFree(ctx->adj_lamF);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     ctx->ev_pool.clear();
 }
@@ -182,8 +191,8 @@ hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out
     if (cfg->mg_pre < 0 || cfg->mg_post < 0 || cfg->mg_max_cycles < 1 || cfg->mg_fixed_cycles < 0 ||
         cfg->mg_coarse_sweeps < 1 || !(cfg->mg_rtol >= 0))
         return fail(HIPIB_E_INVAL, "invalid multigrid parameters");
-    if (cfg->precision != HIPIB_FP64)
-        return fail(HIPIB_E_INVAL, "precision %d is not available in this build", cfg->precision);
+    if (cfg->precision != HIPIB_FP64 && cfg->precision != HIPIB_MIXED)
+        return fail(HIPIB_E_INVAL, "unknown precision %d", cfg->precision);
     if (cfg->deterministic != 0)
         return fail(HIPIB_E_INVAL, "deterministic mode is not available in this build");
 
@@ -206,16 +215,28 @@ hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out
     ctx->small_start = L - 1;
     for (int l = 0; l < L; ++l)
         if (ctx->lv[l].n <= kSmallMax) { ctx->small_start = l; break; }
-    size_t lds = 0;
-    for (int l = ctx->small_start; l < L; ++l) lds += 3 * (size_t)ctx->lv[l].n3 * sizeof(double);
-    ctx->small_lds = lds;
-
     hipib_status s = HIPIB_OK;
-    for (int l = 1; l < L && s == HIPIB_OK; ++l) {
-        s = dev_alloc(ctx, &ctx->lv[l].x, 3 * (size_t)ctx->lv[l].n3);
-        if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->lv[l].b, 3 * (size_t)ctx->lv[l].n3);
+    const size_t esz = mg_level_elem_size(ctx);
+    auto alloc_bytes = [&](void** p, size_t bytes) {
+        if (s != HIPIB_OK) return;
+        hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            s = fail(HIPIB_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+        }
+    };
+    for (int l = 1; l < L; ++l) {
+        alloc_bytes(&ctx->lv[l].x, 3 * (size_t)ctx->lv[l].n3 * esz);
+        alloc_bytes(&ctx->lv[l].b, 3 * (size_t)ctx->lv[l].n3 * esz);
     }
-    if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->r0, 3 * (size_t)ctx->n3);
+    alloc_bytes(&ctx->r0, 3 * (size_t)ctx->n3 * esz);
+    if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->xp, 3 * (size_t)ctx->n3);
+    if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->bpk, 3 * (size_t)ctx->n3);
+    if (cfg->precision == HIPIB_MIXED) {
+        if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->e32, 3 * (size_t)ctx->n3);
+        if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->r32, 3 * (size_t)ctx->n3);
+    }
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->g, 3 * (size_t)ctx->n3);
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->bp, (size_t)ctx->n3);
     ctx->tile = (n % 8 == 0) ? 8 : 4;
@@ -225,7 +246,7 @@ hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->bin_off, (size_t)ctx->ntiles + 1);
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->tile_list, (size_t)ctx->ntiles);
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->n_list, 1);
-    ctx->part_cap = 3 * (((int64_t)(n + 63) / 64) * ((n + 3) / 4) * n + 1024);
+    ctx->part_cap = mg_partials_needed(n);
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->part, (size_t)ctx->part_cap);
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->st, 1);
     if (s == HIPIB_OK) {
@@ -433,6 +454,60 @@ hipib_status hipib_advance(hipib_ctx* ctx, double* u, double* p, double* X, doub
     return HIPIB_OK;
 }
 
+hipib_status hipib_adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n,
+                                const double* u_np1, double pressure, double* lam_u,
+                                double* lam_X, double* dtheta) {
+    HIPIB_TRY(check_ctx(ctx));
+    HIPIB_TRY(check_mesh_ready(ctx));
+    if (!aligned8(u_n) || !aligned8(u_np1) || !aligned8(lam_u) || !aligned8(dtheta) ||
+        (ctx->nn > 0 && (!aligned8(X_n) || !aligned8(lam_X))))
+        return fail(HIPIB_E_INVAL, "bad pointer");
+    if (!std::isfinite(pressure)) return fail(HIPIB_E_INVAL, "non-finite pressure");
+    return adjoint_step(ctx, u_n, X_n, u_np1, pressure, lam_u, lam_X, dtheta);
+}
+
+hipib_status hipib_fe_hvp(hipib_ctx* ctx, const double* X, const double* V, double* HV) {
+    HIPIB_TRY(check_ctx(ctx));
+    HIPIB_TRY(check_mesh_ready(ctx));
+    if (ctx->nn > 0 && (!aligned8(X) || !aligned8(V) || !aligned8(HV)))
+        return fail(HIPIB_E_INVAL, "bad pointer");
+    return launch_fe_hvp(ctx, X, V, HV);
+}
+
+hipib_status hipib_fe_param_vjp(hipib_ctx* ctx, const double* X, const double* lamF,
+                                double* dtheta) {
+    HIPIB_TRY(check_ctx(ctx));
+    HIPIB_TRY(check_mesh_ready(ctx));
+    if (!aligned8(dtheta) || (ctx->nn > 0 && (!aligned8(X) || !aligned8(lamF))))
+        return fail(HIPIB_E_INVAL, "bad pointer");
+    return launch_fe_param_vjp(ctx, X, lamF, dtheta);
+}
+
+hipib_status hipib_spread_vjp_X(hipib_ctx* ctx, const double* X, const double* F,
+                                const double* lam_f, double* lamX) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
+    if (!aligned8(lam_f) || (ctx->nn > 0 && (!aligned8(X) || !aligned8(F) || !aligned8(lamX))))
+        return fail(HIPIB_E_INVAL, "bad pointer");
+    const double h = ctx->h;
+    return launch_vjp_X(ctx, X, lam_f, F, lamX, 1.0 / (h * h * h * h));
+}
+
+hipib_status hipib_interp_vjp_X(hipib_ctx* ctx, const double* X, const double* u,
+                                const double* lamU, double* lamX) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
+    if (!aligned8(u) || (ctx->nn > 0 && (!aligned8(X) || !aligned8(lamU) || !aligned8(lamX))))
+        return fail(HIPIB_E_INVAL, "bad pointer");
+    return launch_vjp_X(ctx, X, u, lamU, lamX, 1.0 / ctx->h);
+}
+
+hipib_status hipib_convection_vjp(hipib_ctx* ctx, const double* u, const double* lam, double* out) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (!aligned8(u) || !aligned8(lam) || !aligned8(out)) return fail(HIPIB_E_INVAL, "bad pointer");
+    return launch_conv_vjp(ctx, u, lam, out, 0.0, 1.0);
+}
+
 hipib_status hipib_timer_enable(hipib_ctx* ctx, int32_t which) {
     HIPIB_TRY(check_ctx(ctx));
     if (which != HIPIB_TIMER_OFF && which != HIPIB_TIMER_SMOOTH_FINE_POISSON)
@@ -440,6 +515,7 @@ hipib_status hipib_timer_enable(hipib_ctx* ctx, int32_t which) {
     HIPIB_HIP(hipStreamSynchronize(ctx->stream));
     ctx->timer_which = which;
     ctx->ev_used = 0;
+    ctx->timer_launches = 0;
     return HIPIB_OK;
 }
 
@@ -453,10 +529,11 @@ hipib_status hipib_timer_read(hipib_ctx* ctx, int32_t* launches, double* total_m
         HIPIB_HIP(hipEventElapsedTime(&ms, ctx->ev_pool[2 * i], ctx->ev_pool[2 * i + 1]));
         tot += ms;
     }
-    if (launches) *launches = (int32_t)ctx->ev_used;
+    if (launches) *launches = (int32_t)ctx->timer_launches;
     if (total_ms) *total_ms = tot;
     if (bytes_per_launch) *bytes_per_launch = ctx->timer_bytes;
     ctx->ev_used = 0;
+    ctx->timer_launches = 0;
     return HIPIB_OK;
 }
 

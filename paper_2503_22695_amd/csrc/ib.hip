@@ -17,39 +17,13 @@
 // walks the nodes in the same tile order so a wavefront gathers from a small
 // neighbourhood.  Summation order is not fixed, so results agree with a serial
 // sum to rounding.
-#include "internal.h"
+#include "delta.h"
 
 namespace hipib {
 namespace {
 
-struct Stencil1 {
-    int i0;        // first index, wrapped into [0, n)
-    double w[4];
-};
 
-__device__ __forceinline__ Stencil1 peskin4(double r, int n) {
-    if (!(fabs(r) < 1.0e9)) r = 0.0;   // non-finite or absurd positions never index out of range
-    const double b = floor(r);
-    const double f = r - b;
-    const double s = sqrt(1.0 + 4.0 * f * (1.0 - f));
-    Stencil1 st;
-    st.w[0] = (3.0 - 2.0 * f - s) * 0.125;
-    st.w[1] = (3.0 - 2.0 * f + s) * 0.125;
-    st.w[2] = (1.0 + 2.0 * f + s) * 0.125;
-    st.w[3] = (1.0 + 2.0 * f - s) * 0.125;
-    int i0 = ((int)b - 1) % n;
-    st.i0 = i0 < 0 ? i0 + n : i0;
-    return st;
-}
 
-__device__ __forceinline__ int step_wrap(int i, int n) { return i >= n ? i - n : i; }
-
-__device__ __forceinline__ double safe_coord(double r) { return fabs(r) < 1.0e9 ? r : 0.0; }
-
-__device__ __forceinline__ int wrap_mod(int i, int n) {
-    const int r = i % n;
-    return r < 0 ? r + n : r;
-}
 
 // tile of each node and its rank inside the tile
 __global__ void __launch_bounds__(256)
@@ -116,8 +90,11 @@ k_bin_scatter(const int32_t* __restrict__ node_tile, const int32_t* __restrict__
 }
 
 // one workgroup per occupied tile (grid-stride over the list); LDS box of
-// E^3 cells per lattice, E = T + 4, starting at T * tile - 2
-template <int T>
+// E^3 cells per lattice, E = T + 4, starting at T * tile - 2.  TW: type of the
+// weights and their products (the lattice coordinate, its floor and the
+// fractional offset are always FP64); the LDS box and the grid accumulate in
+// FP64, since neighbouring nodes' forces partly cancel there.
+template <int T, typename TW>
 __global__ void __launch_bounds__(256)
 k_spread_tiles(const double* __restrict__ X, const double* __restrict__ F, double* __restrict__ f,
                const int32_t* __restrict__ perm, const int32_t* __restrict__ off,
@@ -140,18 +117,18 @@ k_spread_tiles(const double* __restrict__ X, const double* __restrict__ F, doubl
                 cw[e] = wrap_mod((int)floor(xs[e]), n);
             }
             for (int d = 0; d < 3; ++d) {
-                const double val = F[3 * q + d] * ih3;
+                const TW val = (TW)(F[3 * q + d] * ih3);
                 int ls[3];
-                double w[3][4];
+                TW w[3][4];
                 for (int e = 0; e < 3; ++e) {
                     const double r = xs[e] - (e == d ? 0.0 : 0.5);
                     const double bf = floor(r);
-                    const double fr = r - bf;
-                    const double sq = sqrt(1.0 + 4.0 * fr * (1.0 - fr));
-                    w[e][0] = (3.0 - 2.0 * fr - sq) * 0.125;
-                    w[e][1] = (3.0 - 2.0 * fr + sq) * 0.125;
-                    w[e][2] = (1.0 + 2.0 * fr + sq) * 0.125;
-                    w[e][3] = (1.0 + 2.0 * fr - sq) * 0.125;
+                    const TW fr = (TW)(r - bf);
+                    const TW sq = sqrt(TW(1) + TW(4) * fr * (TW(1) - fr));
+                    w[e][0] = (TW(3) - TW(2) * fr - sq) * TW(0.125);
+                    w[e][1] = (TW(3) - TW(2) * fr + sq) * TW(0.125);
+                    w[e][2] = (TW(1) + TW(2) * fr + sq) * TW(0.125);
+                    w[e][3] = (TW(1) + TW(2) * fr - sq) * TW(0.125);
                     // stencil start relative to the node's cell is -1 or -2
                     const int ds = (int)bf - 1 - (int)floor(xs[e]);
                     ls[e] = cw[e] - tb[e] + 2 + ds;
@@ -159,9 +136,9 @@ k_spread_tiles(const double* __restrict__ X, const double* __restrict__ F, doubl
                 double* bd = box + d * E3;
                 for (int c = 0; c < 4; ++c)
                     for (int b = 0; b < 4; ++b) {
-                        const double wyz = w[1][b] * w[2][c];
+                        const TW wyz = w[1][b] * w[2][c];
                         const int row = (ls[0]) + E * ((ls[1] + b) + E * (ls[2] + c));
-                        for (int a = 0; a < 4; ++a) atomicAdd(bd + row + a, val * (w[0][a] * wyz));
+                        for (int a = 0; a < 4; ++a) atomicAdd(bd + row + a, (double)(val * (w[0][a] * wyz)));
                     }
             }
         }
@@ -180,7 +157,9 @@ k_spread_tiles(const double* __restrict__ X, const double* __restrict__ F, doubl
     }
 }
 
-// one thread per node: gather 3 x 64 values; optionally X += dt U (in place)
+// one thread per node: gather 3 x 64 values; optionally X += dt U (in place,
+// FP64).  TW: type of the weights and the accumulation.
+template <typename TW>
 __global__ void __launch_bounds__(256)
 k_interp(const double* X, const double* __restrict__ u, double* __restrict__ U, double* Xupd,
          double dt, int nn, int n, int64_t n3, double inv_h, const int32_t* __restrict__ perm) {
@@ -191,24 +170,34 @@ k_interp(const double* X, const double* __restrict__ u, double* __restrict__ U, 
     const double x[3] = {X0 * inv_h, X1 * inv_h, X2 * inv_h};
     double Uq[3];
     for (int d = 0; d < 3; ++d) {
-        const Stencil1 sx = peskin4(x[0] - (d == 0 ? 0.0 : 0.5), n);
-        const Stencil1 sy = peskin4(x[1] - (d == 1 ? 0.0 : 0.5), n);
-        const Stencil1 sz = peskin4(x[2] - (d == 2 ? 0.0 : 0.5), n);
+        int i0[3];
+        TW w[3][4];
+        for (int e = 0; e < 3; ++e) {
+            const double r = safe_coord(x[e] - (e == d ? 0.0 : 0.5));
+            const double bf = floor(r);
+            const TW fr = (TW)(r - bf);
+            const TW sq = sqrt(TW(1) + TW(4) * fr * (TW(1) - fr));
+            w[e][0] = (TW(3) - TW(2) * fr - sq) * TW(0.125);
+            w[e][1] = (TW(3) - TW(2) * fr + sq) * TW(0.125);
+            w[e][2] = (TW(1) + TW(2) * fr + sq) * TW(0.125);
+            w[e][3] = (TW(1) + TW(2) * fr - sq) * TW(0.125);
+            i0[e] = wrap_mod((int)bf - 1, n);
+        }
         const double* ud = u + d * n3;
-        double acc = 0.0;
+        TW acc = TW(0);
         for (int c = 0; c < 4; ++c) {
-            const int kk = step_wrap(sz.i0 + c, n);
+            const int kk = step_wrap(i0[2] + c, n);
             for (int b = 0; b < 4; ++b) {
-                const int jj = step_wrap(sy.i0 + b, n);
-                const double wyz = sy.w[b] * sz.w[c];
+                const int jj = step_wrap(i0[1] + b, n);
+                const TW wyz = w[1][b] * w[2][c];
                 const int64_t row = (int64_t)n * ((int64_t)jj + (int64_t)n * kk);
                 for (int a = 0; a < 4; ++a) {
-                    const int ii = step_wrap(sx.i0 + a, n);
-                    acc += ud[row + ii] * (sx.w[a] * wyz);
+                    const int ii = step_wrap(i0[0] + a, n);
+                    acc += (TW)ud[row + ii] * (w[0][a] * wyz);
                 }
             }
         }
-        Uq[d] = acc;
+        Uq[d] = (double)acc;
     }
     if (U) {
         U[3 * q] = Uq[0];
@@ -243,14 +232,17 @@ hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, dou
     if (ctx->nn == 0) return HIPIB_OK;
     const double h = ctx->h;
     const int blocks = (int)(ctx->ntiles < 4096 ? ctx->ntiles : 4096);
-    if (ctx->tile == 8)
-        k_spread_tiles<8><<<blocks, 256, 0, ctx->stream>>>(
-            X, F, f, ctx->perm, ctx->bin_off, ctx->tile_list, ctx->n_list, ctx->n, ctx->tiles_axis,
-            ctx->n3, 1.0 / h, 1.0 / (h * h * h));
-    else
-        k_spread_tiles<4><<<blocks, 256, 0, ctx->stream>>>(
-            X, F, f, ctx->perm, ctx->bin_off, ctx->tile_list, ctx->n_list, ctx->n, ctx->tiles_axis,
-            ctx->n3, 1.0 / h, 1.0 / (h * h * h));
+    const bool mixed = ctx->cfg.precision == HIPIB_MIXED;
+#define HIPIB_SPREAD(TT, TW)                                                                       \
+    k_spread_tiles<TT, TW><<<blocks, 256, 0, ctx->stream>>>(                                        \
+        X, F, f, ctx->perm, ctx->bin_off, ctx->tile_list, ctx->n_list, ctx->n, ctx->tiles_axis,     \
+        ctx->n3, 1.0 / h, 1.0 / (h * h * h))
+    if (ctx->tile == 8) {
+        if (mixed) HIPIB_SPREAD(8, float); else HIPIB_SPREAD(8, double);
+    } else {
+        if (mixed) HIPIB_SPREAD(4, float); else HIPIB_SPREAD(4, double);
+    }
+#undef HIPIB_SPREAD
     HIPIB_HIP(hipGetLastError());
     return HIPIB_OK;
 }
@@ -259,8 +251,12 @@ hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, dou
 hipib_status launch_interpolate(hipib_ctx* ctx, const double* X, const double* u, double* U,
                                 double* Xupd, double dt) {
     if (ctx->nn == 0) return HIPIB_OK;
-    k_interp<<<(ctx->nn + 255) / 256, 256, 0, ctx->stream>>>(X, u, U, Xupd, dt, ctx->nn, ctx->n,
-                                                             ctx->n3, 1.0 / ctx->h, ctx->perm);
+    if (ctx->cfg.precision == HIPIB_MIXED)
+        k_interp<float><<<(ctx->nn + 255) / 256, 256, 0, ctx->stream>>>(
+            X, u, U, Xupd, dt, ctx->nn, ctx->n, ctx->n3, 1.0 / ctx->h, ctx->perm);
+    else
+        k_interp<double><<<(ctx->nn + 255) / 256, 256, 0, ctx->stream>>>(
+            X, u, U, Xupd, dt, ctx->nn, ctx->n, ctx->n3, 1.0 / ctx->h, ctx->perm);
     HIPIB_HIP(hipGetLastError());
     return HIPIB_OK;
 }

@@ -38,8 +38,8 @@ struct MGState {
 struct Level {
     int n = 0;
     int64_t n3 = 0;
-    double* x = nullptr;   // [3][n3] for l >= 1 (level 0 uses caller arrays)
-    double* b = nullptr;
+    void* x = nullptr;     // [3][n3] packed, l >= 1, element type of the V-cycle
+    void* b = nullptr;
 };
 
 struct StepRecord {
@@ -62,7 +62,11 @@ struct hipib_ctx {
     int small_start = 0;    // first level run by the single-workgroup kernel
     size_t small_lds = 0;   // its dynamic LDS bytes
     hipib::Level lv[hipib::kMaxLevels];
-    double* r0 = nullptr;   // [3][n3] residual scratch (any level)
+    void* r0 = nullptr;     // [3][n3] residual scratch of the V-cycle type (any level)
+    double* xp = nullptr;   // [3][n3] packed FP64 solution of the current solve
+    double* bpk = nullptr;  // [3][n3] packed FP64 right-hand side
+    float* e32 = nullptr;   // [3][n3] packed FP32 correction (mixed precision)
+    float* r32 = nullptr;   // [3][n3] packed FP32 scaled residual (mixed precision)
     double* g = nullptr;    // [3][n3] Helmholtz right-hand side
     double* bp = nullptr;   // [n3] Poisson right-hand side
     double* part = nullptr; // reduction partials
@@ -99,11 +103,21 @@ struct hipib_ctx {
     std::vector<hipib::StepRecord> recs;
     bool broken = false;
 
+    // adjoint workspaces (allocated on the first adjoint call)
+    double* adj_tot = nullptr;   // [3][n3]
+    double* adj_lg = nullptr;    // [3][n3]
+    double* adj_p = nullptr;     // [n3]
+    double* adj_sX = nullptr;    // [nn][3]
+    double* adj_lamF = nullptr;  // [nn][3]
+    int32_t adj_ready_nn = -1;
+
     // event timing of one kernel class (hipib_timer)
     int timer_which = 0;
     std::vector<hipEvent_t> ev_pool;   // pairs: start 2i, stop 2i+1
     size_t ev_used = 0;                // pairs recorded since the last read
     double timer_bytes = 0.0;          // algorithmic bytes per timed launch
+    int timer_pending = 0;             // launches inside the open event pair
+    int64_t timer_launches = 0;        // launches timed since the last read
 };
 
 namespace hipib {
@@ -135,6 +149,8 @@ hipib_status mg_solve(hipib_ctx* ctx, int op, int ncomp, const double* b, double
                       int32_t* cycles, double* relres);
 hipib_status mg_remove_mean(hipib_ctx* ctx, double* v, int slot);
 hipib_status mg_prepare(hipib_ctx* ctx);
+size_t mg_level_elem_size(const hipib_ctx* ctx);
+int64_t mg_partials_needed(int n);
 hipib_status sync_state(hipib_ctx* ctx);
 // ib.hip
 hipib_status launch_bin(hipib_ctx* ctx, const double* X);
@@ -143,10 +159,19 @@ hipib_status launch_interpolate(hipib_ctx* ctx, const double* X, const double* u
                                 double* Xupd, double dt);
 // fe.hip
 hipib_status launch_fe_force(hipib_ctx* ctx, const double* X, double pressure, double* F);
+// adjoint.hip
+hipib_status adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n, const double* u_np1,
+                          double pressure, double* lam_u, double* lam_X, double* dtheta);
+hipib_status launch_conv_vjp(hipib_ctx* ctx, const double* u, const double* lam, double* out,
+                             double a, double b);
+hipib_status launch_fe_hvp(hipib_ctx* ctx, const double* X, const double* V, double* out);
+hipib_status launch_fe_param_vjp(hipib_ctx* ctx, const double* X, const double* lamF, double* dtheta);
+hipib_status launch_vjp_X(hipib_ctx* ctx, const double* X, const double* field, const double* coef,
+                          double* lamX, double scale);
 
 // ---- event timing --------------------------------------------------------------
 // Returns the pair index to close with timer_stop, or -1 when `kind` is not timed.
-int timer_start(hipib_ctx* ctx, int kind, double bytes);
+int timer_start(hipib_ctx* ctx, int kind, double bytes, int launches);
 void timer_stop(hipib_ctx* ctx, int pair);
 
 // ---- small device helpers ----------------------------------------------------

@@ -9,15 +9,32 @@
 //   number of red+black sweeps, Poisson means removed after the coarse solve
 //   and after each top-level cycle.  Stop: ||r||_2 <= max(rtol, 1e3 eps) ||b||_2.
 //
-// GPU mapping: every fine-level stage is one bandwidth-bound stencil kernel
-// (64x4 thread tiles, one thread per cell; colour sweeps one thread per cell of
-// the colour).  All levels with at most 16 cells per side run inside ONE
-// workgroup of 1024 threads with the level arrays in LDS (112 KB for 16^3),
-// which removes ~25 tiny launches per cycle.  Up to three independent
-// components (the three velocity lattices) are solved in the same launches;
-// each kernel block first reads its component's `active` flag, so components
-// stop independently.  Stop decisions are taken on the device; the host
-// enqueues the predicted number of cycles and synchronises once to read them.
+// Storage: every solver array is kept in a packed red-black layout.  For a
+// level of n cells per side (n even) and H = n/2, component c, colour
+// q = (i+j+k) & 1, cell (i,j,k) sits at
+//     c * n^3 + q * n^3/2 + (i >> 1) + H * (j + n * k).
+// A cell's six neighbours all have the other colour; with p = i & 1 =
+// (j+k+q) & 1 its x-neighbours sit at packed positions ih+p-1 and ih+p of the
+// other colour's row (j,k) and its y/z neighbours at ih of rows (j+-1,k),
+// (j,k+-1).  A half-sweep therefore streams exactly what it needs: the other
+// colour of x, its own colour of b, its own colour of x written (12 B/cell in
+// FP64), with unit-stride rows.  The caller's arrays are packed on entry to a
+// solve and the solution unpacked on exit.
+//
+// Precision: in FP64 mode the V-cycles run on the FP64 solution.  In mixed
+// mode the outer loop stays in FP64 (residual, norm, stop test, solution
+// update, Poisson mean) and each cycle computes the correction e of the scaled
+// residual r / ||b|| with one FP32 V-cycle from e = 0:  x += ||b|| e.  For a
+// linear smoother this is the same cycle as the FP64 one, with the correction
+// rounded to FP32 (iterative refinement with a V-cycle preconditioner).
+//
+// GPU mapping: one bandwidth-bound kernel per fine-level stage (64x4 thread
+// tiles); all levels with at most 16 cells per side run inside ONE workgroup
+// of 1024 threads with the arrays in LDS; up to three components (the three
+// velocity lattices) share every launch and stop independently through
+// per-component `active` flags read at block start.  Stop decisions are made
+// on the device; the host enqueues the predicted number of cycles and waits
+// once to read them.
 #include <cfloat>
 
 #include "internal.h"
@@ -30,88 +47,213 @@ constexpr int kSmallThreads = 1024;
 
 enum FinalizeMode { FIN_BNORM = 0, FIN_INIT_R = 1, FIN_CYCLE_R = 2, FIN_MEAN = 3 };
 
-struct LevelGeom {
-    int n;
-    int64_t cs;  // component stride
-    __device__ __forceinline__ int64_t at(int i, int j, int k) const {
-        return (int64_t)i + (int64_t)n * ((int64_t)j + (int64_t)n * k);
-    }
-};
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// ---------------------------------------------------------------------------
-// fine-level stencil kernels; grid (x tiles, y tiles, n * ncomp)
-// ---------------------------------------------------------------------------
-
-// TAG only separates launches in profiles: 0 coarse levels, 1 finest level of a
-// Helmholtz solve, 2 finest level of a Poisson solve.
-template <int TAG>
-__global__ void __launch_bounds__(TX * TY)
-k_gs_colour(double* __restrict__ x, const double* __restrict__ b, LevelGeom G, double c,
-            double diag, int colour, const int32_t* __restrict__ active) {
-    const int comp = blockIdx.z / G.n, k = blockIdx.z - comp * G.n;
-    if (!active[comp]) return;
-    const int n = G.n;
-    const int j = blockIdx.y * TY + threadIdx.y;
-    const int i = 2 * (blockIdx.x * TX + threadIdx.x) + ((j + k + colour) & 1);
-    if (i >= n || j >= n) return;
-    double* xc = x + comp * G.cs;
-    const double* bc = b + comp * G.cs;
-    const double s = xc[G.at(wrap_idx(i + 1, n), j, k)] + xc[G.at(wrap_idx(i - 1, n), j, k)] +
-                     xc[G.at(i, wrap_idx(j + 1, n), k)] + xc[G.at(i, wrap_idx(j - 1, n), k)] +
-                     xc[G.at(i, j, wrap_idx(k + 1, n))] + xc[G.at(i, j, wrap_idx(k - 1, n))];
-    const int64_t o = G.at(i, j, k);
-    xc[o] = (bc[o] + c * s) / diag;
+// packed offset of cell (i,j,k) (any colour) inside one component
+__device__ __forceinline__ int64_t pk(int i, int j, int k, int n) {
+    const int q = (i + j + k) & 1;
+    const int H = n >> 1;
+    return (int64_t)q * ((int64_t)H * n * n) + (i >> 1) + (int64_t)H * ((int64_t)j + (int64_t)n * k);
 }
 
-__device__ __forceinline__ double residual_at(const double* __restrict__ xc,
-                                              const double* __restrict__ bc, const LevelGeom& G,
-                                              int i, int j, int k, double sigma, double c) {
-    const int n = G.n;
-    const int64_t o = G.at(i, j, k);
-    const double xo = xc[o];
-    const double s = xc[G.at(wrap_idx(i + 1, n), j, k)] + xc[G.at(wrap_idx(i - 1, n), j, k)] +
-                     xc[G.at(i, wrap_idx(j + 1, n), k)] + xc[G.at(i, wrap_idx(j - 1, n), k)] +
-                     xc[G.at(i, j, wrap_idx(k + 1, n))] + xc[G.at(i, j, wrap_idx(k - 1, n))];
-    const double Ax = sigma * xo - c * (s - 6.0 * xo);
-    return bc[o] - Ax;
+// Sum of the six neighbours of the colour-q cell at packed (ih, j, k), read
+// from the other colour's array xo, in the order i+1, i-1, j+1, j-1, k+1, k-1.
+template <typename T>
+__device__ __forceinline__ T nbr_sum(const T* __restrict__ xo, int ih, int j, int k, int n, int q) {
+    const int H = n >> 1;
+    const int p = (j + k + q) & 1;
+    int ip = ih + p, im = ih + p - 1;
+    if (ip >= H) ip -= H;
+    if (im < 0) im += H;
+    const int jp = wrapi(j + 1, n), jm = wrapi(j - 1, n), kp = wrapi(k + 1, n), km = wrapi(k - 1, n);
+    const int64_t row = (int64_t)H * ((int64_t)j + (int64_t)n * k);
+    return xo[row + ip] + xo[row + im] + xo[(int64_t)H * (jp + (int64_t)n * k) + ih] +
+           xo[(int64_t)H * (jm + (int64_t)n * k) + ih] + xo[(int64_t)H * (j + (int64_t)n * kp) + ih] +
+           xo[(int64_t)H * (j + (int64_t)n * km) + ih];
 }
 
+// grid for one colour of a level: (packed x tiles, y tiles, n * ncomp)
+dim3 colour_grid(int n, int ncomp) {
+    return dim3((n / 2 + TX - 1) / TX, (n + TY - 1) / TY, n * ncomp);
+}
+// grid for both colours: z = (comp * 2 + q) * n + k
+dim3 packed_grid(int n, int ncomp) {
+    return dim3((n / 2 + TX - 1) / TX, (n + TY - 1) / TY, 2 * n * ncomp);
+}
+// grid over natural cells: z = comp * n + k
+dim3 natural_grid(int n, int ncomp) {
+    return dim3((n + TX - 1) / TX, (n + TY - 1) / TY, n * ncomp);
+}
+
+// ---------------------------------------------------------------------------
+// layout conversion
+// ---------------------------------------------------------------------------
+
 __global__ void __launch_bounds__(TX * TY)
-k_residual(const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ r,
-           LevelGeom G, int64_t rcs, double sigma, double c, const int32_t* __restrict__ active) {
-    const int comp = blockIdx.z / G.n, k = blockIdx.z - comp * G.n;
-    if (!active[comp]) return;
+k_pack(const double* __restrict__ src, double* __restrict__ dst, int n, int64_t n3) {
+    const int comp = blockIdx.z / n, k = blockIdx.z - comp * n;
     const int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y;
-    if (i >= G.n || j >= G.n) return;
-    r[comp * rcs + G.at(i, j, k)] =
-        residual_at(x + comp * G.cs, b + comp * G.cs, G, i, j, k, sigma, c);
+    if (i >= n || j >= n) return;
+    dst[comp * n3 + pk(i, j, k, n)] = src[comp * n3 + i + (int64_t)n * (j + (int64_t)n * k)];
 }
 
-// sum of r^2 per block (one partial per block, all threads participate)
 __global__ void __launch_bounds__(TX * TY)
-k_resid_norm(const double* __restrict__ x, const double* __restrict__ b, LevelGeom G,
-             double sigma, double c, const int32_t* __restrict__ active,
+k_unpack(const double* __restrict__ src, double* __restrict__ dst, int n, int64_t n3) {
+    const int comp = blockIdx.z / n, k = blockIdx.z - comp * n;
+    const int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y;
+    if (i >= n || j >= n) return;
+    dst[comp * n3 + i + (int64_t)n * (j + (int64_t)n * k)] = src[comp * n3 + pk(i, j, k, n)];
+}
+
+// ---------------------------------------------------------------------------
+// stencil kernels on packed levels
+// ---------------------------------------------------------------------------
+
+// One colour q of red-black Gauss-Seidel: x_q = (b_q + c * sum_nbr x) / diag.
+// TAG only separates launches in profiles: 0 coarse levels, 1 finest level of
+// a Helmholtz solve, 2 finest level of a Poisson solve.
+template <typename T, int TAG>
+__global__ void __launch_bounds__(TX * TY)
+k_gs(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, T c, T inv_diag, int q,
+     const int32_t* __restrict__ active) {
+    const int comp = blockIdx.z / n, k = blockIdx.z - comp * n;
+    if (!active[comp]) return;
+    const int H = n >> 1;
+    const int ih = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y;
+    if (ih >= H || j >= n) return;
+    const int64_t half3 = (int64_t)H * n * n;
+    T* xq = x + comp * cs + q * half3;
+    const T* xo = x + comp * cs + (1 - q) * half3;
+    const T s = nbr_sum(xo, ih, j, k, n, q);
+    const int64_t o = ih + (int64_t)H * ((int64_t)j + (int64_t)n * k);
+    xq[o] = (b[comp * cs + q * half3 + o] + c * s) * inv_diag;
+}
+
+// r = b - (sigma x - c (sum_nbr x - 6 x)), both colours
+template <typename T>
+__global__ void __launch_bounds__(TX * TY)
+k_residual(const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ r, int n, int64_t cs,
+           T sigma, T c, const int32_t* __restrict__ active) {
+    const int z = blockIdx.z, comp = z / (2 * n), rem = z - comp * 2 * n, q = rem / n, k = rem - q * n;
+    if (!active[comp]) return;
+    const int H = n >> 1;
+    const int ih = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y;
+    if (ih >= H || j >= n) return;
+    const int64_t half3 = (int64_t)H * n * n;
+    const int64_t o = comp * cs + q * half3 + ih + (int64_t)H * ((int64_t)j + (int64_t)n * k);
+    const T xo = x[o];
+    const T s = nbr_sum(x + comp * cs + (1 - q) * half3, ih, j, k, n, q);
+    const T Ax = sigma * xo - c * (s - T(6) * xo);
+    r[o] = b[o] - Ax;
+}
+
+// coarse b[I,J,K] = sum_{a,b,c} (w_a w_b w_c / 512) r[2I-1+a, 2J-1+b, 2K-1+c], w = 1,3,3,1
+template <typename T>
+__global__ void __launch_bounds__(TX * TY)
+k_restrict(const T* __restrict__ r, int nf, int64_t fcs, T* __restrict__ bc, int nc, int64_t ccs,
+           const int32_t* __restrict__ active) {
+    const int z = blockIdx.z, comp = z / (2 * nc), rem = z - comp * 2 * nc, Q = rem / nc, K = rem - Q * nc;
+    if (!active[comp]) return;
+    const int Hc = nc >> 1;
+    const int IH = blockIdx.x * TX + threadIdx.x, J = blockIdx.y * TY + threadIdx.y;
+    if (IH >= Hc || J >= nc) return;
+    const int I = 2 * IH + ((J + K + Q) & 1);
+    const T w[4] = {T(1), T(3), T(3), T(1)};
+    const T* rc = r + comp * fcs;
+    T s = T(0);
+    for (int cz = 0; cz < 4; ++cz) {
+        const int kk = wrapi(2 * K - 1 + cz, nf);
+        for (int cy = 0; cy < 4; ++cy) {
+            const int jj = wrapi(2 * J - 1 + cy, nf);
+            for (int cx = 0; cx < 4; ++cx) {
+                const int ii = wrapi(2 * I - 1 + cx, nf);
+                s += w[cx] * w[cy] * w[cz] / T(512) * rc[pk(ii, jj, kk, nf)];
+            }
+        }
+    }
+    bc[comp * ccs + (int64_t)Q * ((int64_t)Hc * nc * nc) + IH + (int64_t)Hc * ((int64_t)J + (int64_t)nc * K)] = s;
+}
+
+// fine x += trilinear interpolation of coarse x (3/4 nearest, 1/4 next, per axis)
+template <typename T>
+__global__ void __launch_bounds__(TX * TY)
+k_prolong_add(T* __restrict__ x, int nf, int64_t fcs, const T* __restrict__ xc, int nc, int64_t ccs,
+              const int32_t* __restrict__ active) {
+    const int z = blockIdx.z, comp = z / (2 * nf), rem = z - comp * 2 * nf, q = rem / nf, k = rem - q * nf;
+    if (!active[comp]) return;
+    const int H = nf >> 1;
+    const int ih = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y;
+    if (ih >= H || j >= nf) return;
+    const int i = 2 * ih + ((j + k + q) & 1);
+    const int ijk[3] = {i, j, k};
+    int base[3][2];
+    for (int d = 0; d < 3; ++d) {
+        const int I = ijk[d] >> 1;
+        base[d][0] = I;
+        base[d][1] = (ijk[d] & 1) ? wrapi(I + 1, nc) : wrapi(I - 1, nc);
+    }
+    const T wt[2] = {T(0.75), T(0.25)};
+    const T* xcc = xc + comp * ccs;
+    T v = T(0);
+    for (int c = 0; c < 2; ++c)
+        for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a)
+                v += wt[a] * wt[b] * wt[c] * xcc[pk(base[0][a], base[1][b], base[2][c], nc)];
+    x[comp * fcs + (int64_t)q * ((int64_t)H * nf * nf) + ih + (int64_t)H * ((int64_t)j + (int64_t)nf * k)] += v;
+}
+
+template <typename T>
+__global__ void k_zero_t(T* __restrict__ p, int64_t count) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count;
+         t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = T(0);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 outer loop: residual norm (and FP32 scaled residual), update, means
+// ---------------------------------------------------------------------------
+
+// sum of r^2 per block; TO32: also r32 = (float)(r / ||b||)
+template <bool TO32>
+__global__ void __launch_bounds__(TX * TY)
+k_resid_norm(const double* __restrict__ x, const double* __restrict__ b, int n, int64_t cs,
+             double sigma, double c, const MGState* __restrict__ st, float* __restrict__ r32,
              double* __restrict__ part, int64_t pstride) {
     __shared__ double red[16];
-    const int comp = blockIdx.z / G.n, k = blockIdx.z - comp * G.n;
-    if (!active[comp]) return;  // block-uniform
-    const int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y;
+    const int z = blockIdx.z, comp = z / (2 * n), rem = z - comp * 2 * n, q = rem / n, k = rem - q * n;
+    if (!st->active[comp]) return;  // block-uniform
+    const int H = n >> 1;
+    const int ih = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y;
     double v = 0.0;
-    if (i < G.n && j < G.n) {
-        const double r = residual_at(x + comp * G.cs, b + comp * G.cs, G, i, j, k, 0.0 + sigma, c);
+    if (ih < H && j < n) {
+        const int64_t half3 = (int64_t)H * n * n;
+        const int64_t o = comp * cs + q * half3 + ih + (int64_t)H * ((int64_t)j + (int64_t)n * k);
+        const double xo = x[o];
+        const double s = nbr_sum(x + comp * cs + (1 - q) * half3, ih, j, k, n, q);
+        const double r = b[o] - (sigma * xo - c * (s - 6.0 * xo));
         v = r * r;
+        if (TO32) r32[o] = (float)(r * (1.0 / st->bn[comp]));
     }
     const int tid = threadIdx.x + TX * threadIdx.y;
-    // flatten the 2-D block for the reduction
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
     if ((tid & 63) == 0) red[tid >> 6] = v;
     __syncthreads();
     if (tid == 0) {
         double s = 0.0;
         for (int w = 0; w < (TX * TY) / 64; ++w) s += red[w];
-        const int64_t blk = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * k);
+        const int64_t blk = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * rem);
         part[comp * pstride + blk] = s;
     }
+}
+
+// x += ||b|| e (mixed mode)
+__global__ void k_update(double* __restrict__ x, const float* __restrict__ e, int64_t cs,
+                         const MGState* __restrict__ st) {
+    const int comp = blockIdx.y;
+    if (!st->active[comp]) return;
+    const double s = st->bn[comp];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < cs; t += (int64_t)gridDim.x * blockDim.x)
+        x[comp * cs + t] += s * (double)e[comp * cs + t];
 }
 
 // sum (square = 1: of squares) of a contiguous component array; fixed chunking
@@ -129,56 +271,6 @@ k_sum_partials(const double* __restrict__ v, int64_t cs, int64_t count, int squa
     }
     s = block_sum(s, red);
     if (threadIdx.x == 0) part[comp * pstride + blockIdx.x] = s;
-}
-
-__global__ void __launch_bounds__(TX * TY)
-k_restrict(const double* __restrict__ r, int nf, int64_t rcs, double* __restrict__ bc,
-           LevelGeom C, const int32_t* __restrict__ active) {
-    const int comp = blockIdx.z / C.n, K = blockIdx.z - comp * C.n;
-    if (!active[comp]) return;
-    const int I = blockIdx.x * TX + threadIdx.x, J = blockIdx.y * TY + threadIdx.y;
-    if (I >= C.n || J >= C.n) return;
-    const double w[4] = {1.0, 3.0, 3.0, 1.0};
-    const double* rc = r + comp * rcs;
-    double s = 0.0;
-    for (int cz = 0; cz < 4; ++cz) {
-        const int kk = wrap_idx(2 * K - 1 + cz, nf);
-        for (int cy = 0; cy < 4; ++cy) {
-            const int jj = wrap_idx(2 * J - 1 + cy, nf);
-            const int64_t row = (int64_t)nf * ((int64_t)jj + (int64_t)nf * kk);
-            for (int cx = 0; cx < 4; ++cx) {
-                const int ii = wrap_idx(2 * I - 1 + cx, nf);
-                s += w[cx] * w[cy] * w[cz] / 512.0 * rc[row + ii];
-            }
-        }
-    }
-    bc[comp * C.cs + C.at(I, J, K)] = s;
-}
-
-__global__ void __launch_bounds__(TX * TY)
-k_prolong_add(double* __restrict__ x, LevelGeom F, const double* __restrict__ xc, LevelGeom C,
-              const int32_t* __restrict__ active) {
-    const int comp = blockIdx.z / F.n, k = blockIdx.z - comp * F.n;
-    if (!active[comp]) return;
-    const int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y;
-    if (i >= F.n || j >= F.n) return;
-    const int nc = C.n;
-    const int ijk[3] = {i, j, k};
-    int base[3][2];
-    for (int d = 0; d < 3; ++d) {
-        const int I = ijk[d] >> 1;
-        base[d][0] = I;
-        base[d][1] = (ijk[d] & 1) ? wrap_idx(I + 1, nc) : wrap_idx(I - 1, nc);
-    }
-    const double wt[2] = {0.75, 0.25};
-    const double* xcc = xc + comp * C.cs;
-    double v = 0.0;
-    for (int c = 0; c < 2; ++c)
-        for (int b = 0; b < 2; ++b)
-            for (int a = 0; a < 2; ++a)
-                v += wt[a] * wt[b] * wt[c] * xcc[C.at(base[0][a], base[1][b], base[2][c])];
-    const int64_t o = comp * F.cs + F.at(i, j, k);
-    x[o] += v;
 }
 
 __global__ void k_sub_mean(double* __restrict__ v, int64_t cs, int64_t count,
@@ -271,7 +363,7 @@ __global__ void k_state_reset(MGState* st, int ncomp) {
 }
 
 // ---------------------------------------------------------------------------
-// all levels with n <= 16 in one workgroup, arrays in LDS
+// all levels with n <= 16 in one workgroup, arrays in LDS (natural layout)
 //
 // The level chain is a compile-time constant (16-8-4, 12-6 or 8-4), so every
 // index split is a multiply/shift.  Levels above the coarsest use all 1024
@@ -281,9 +373,10 @@ __global__ void k_state_reset(MGState* st, int ncomp) {
 // replaces the barrier.
 // ---------------------------------------------------------------------------
 
+template <typename T>
 struct SmallArgs {
     int pre, post, sweeps, poisson, zero_init;
-    double sigma, nu;
+    T sigma, nu;
 };
 
 template <int N>
@@ -301,59 +394,56 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// one colour of red-black Gauss-Seidel by threads t = t0, t0+nt, ...
-template <int N>
-__device__ __forceinline__ void s_gs(double* x, const double* b, double c, double diag, int colour,
-                                     int t0, int nt) {
+template <int N, typename T>
+__device__ __forceinline__ void s_gs(T* x, const T* b, T c, T inv_diag, int colour, int t0, int nt) {
     constexpr int HALF = N / 2, CNT = HALF * N * N;
     for (int t = t0; t < CNT; t += nt) {
         const int ih = t % HALF, rest = t / HALF;
         const int j = rest % N, k = rest / N;
         const int i = 2 * ih + ((j + k + colour) & 1);
-        const double s = x[at3<N>(wrapc<N>(i + 1), j, k)] + x[at3<N>(wrapc<N>(i - 1), j, k)] +
-                         x[at3<N>(i, wrapc<N>(j + 1), k)] + x[at3<N>(i, wrapc<N>(j - 1), k)] +
-                         x[at3<N>(i, j, wrapc<N>(k + 1))] + x[at3<N>(i, j, wrapc<N>(k - 1))];
+        const T s = x[at3<N>(wrapc<N>(i + 1), j, k)] + x[at3<N>(wrapc<N>(i - 1), j, k)] +
+                    x[at3<N>(i, wrapc<N>(j + 1), k)] + x[at3<N>(i, wrapc<N>(j - 1), k)] +
+                    x[at3<N>(i, j, wrapc<N>(k + 1))] + x[at3<N>(i, j, wrapc<N>(k - 1))];
         const int o = at3<N>(i, j, k);
-        x[o] = (b[o] + c * s) / diag;
+        x[o] = (b[o] + c * s) * inv_diag;
     }
 }
 
-template <int N>
-__device__ __forceinline__ void s_residual(const double* x, const double* b, double* r, double sigma,
-                                           double c) {
+template <int N, typename T>
+__device__ __forceinline__ void s_residual(const T* x, const T* b, T* r, T sigma, T c) {
     constexpr int CNT = N * N * N;
     for (int o = threadIdx.x; o < CNT; o += blockDim.x) {
         const int i = o % N, j = (o / N) % N, k = o / (N * N);
-        const double xo = x[o];
-        const double s = x[at3<N>(wrapc<N>(i + 1), j, k)] + x[at3<N>(wrapc<N>(i - 1), j, k)] +
-                         x[at3<N>(i, wrapc<N>(j + 1), k)] + x[at3<N>(i, wrapc<N>(j - 1), k)] +
-                         x[at3<N>(i, j, wrapc<N>(k + 1))] + x[at3<N>(i, j, wrapc<N>(k - 1))];
-        const double Ax = sigma * xo - c * (s - 6.0 * xo);
+        const T xo = x[o];
+        const T s = x[at3<N>(wrapc<N>(i + 1), j, k)] + x[at3<N>(wrapc<N>(i - 1), j, k)] +
+                    x[at3<N>(i, wrapc<N>(j + 1), k)] + x[at3<N>(i, wrapc<N>(j - 1), k)] +
+                    x[at3<N>(i, j, wrapc<N>(k + 1))] + x[at3<N>(i, j, wrapc<N>(k - 1))];
+        const T Ax = sigma * xo - c * (s - T(6) * xo);
         r[o] = b[o] - Ax;
     }
 }
 
-template <int NF>
-__device__ __forceinline__ void s_restrict(const double* r, double* bc) {
+template <int NF, typename T>
+__device__ __forceinline__ void s_restrict(const T* r, T* bc) {
     constexpr int NC = NF / 2, CNT = NC * NC * NC;
-    const double w[4] = {1.0, 3.0, 3.0, 1.0};
+    const T w[4] = {T(1), T(3), T(3), T(1)};
     for (int o = threadIdx.x; o < CNT; o += blockDim.x) {
         const int I = o % NC, J = (o / NC) % NC, K = o / (NC * NC);
-        double s = 0.0;
+        T s = T(0);
         for (int cz = 0; cz < 4; ++cz)
             for (int cy = 0; cy < 4; ++cy)
                 for (int cx = 0; cx < 4; ++cx)
-                    s += w[cx] * w[cy] * w[cz] / 512.0 *
+                    s += w[cx] * w[cy] * w[cz] / T(512) *
                          r[at3<NF>(wrapc<NF>(2 * I - 1 + cx), wrapc<NF>(2 * J - 1 + cy),
                                    wrapc<NF>(2 * K - 1 + cz))];
         bc[o] = s;
     }
 }
 
-template <int NF>
-__device__ __forceinline__ void s_prolong_add(double* x, const double* xc) {
+template <int NF, typename T>
+__device__ __forceinline__ void s_prolong_add(T* x, const T* xc) {
     constexpr int NC = NF / 2, CNT = NF * NF * NF;
-    const double wt[2] = {0.75, 0.25};
+    const T wt[2] = {T(0.75), T(0.25)};
     for (int o = threadIdx.x; o < CNT; o += blockDim.x) {
         const int ijk[3] = {o % NF, (o / NF) % NF, o / (NF * NF)};
         int base[3][2];
@@ -362,7 +452,7 @@ __device__ __forceinline__ void s_prolong_add(double* x, const double* xc) {
             base[d][0] = I;
             base[d][1] = (ijk[d] & 1) ? wrapc<NC>(I + 1) : wrapc<NC>(I - 1);
         }
-        double v = 0.0;
+        T v = T(0);
         for (int c = 0; c < 2; ++c)
             for (int b = 0; b < 2; ++b)
                 for (int a = 0; a < 2; ++a)
@@ -371,28 +461,34 @@ __device__ __forceinline__ void s_prolong_add(double* x, const double* xc) {
     }
 }
 
+template <int N, typename T>
+__device__ __forceinline__ void level_coef(const SmallArgs<T>& A, T& c, T& inv_diag) {
+    const T h = T(1) / T(N);
+    c = A.nu / (h * h);
+    inv_diag = T(1) / (A.sigma + T(6) * c);
+}
+
 // coarsest level on wavefront 0: zero (optional), sweeps, Poisson mean removal
-template <int N>
-__device__ __forceinline__ void s_coarse_wave(double* x, const double* b, const SmallArgs& A,
-                                              bool zero) {
+template <int N, typename T>
+__device__ __forceinline__ void s_coarse_wave(T* x, const T* b, const SmallArgs<T>& A, bool zero) {
     constexpr int CNT = N * N * N;
     const int lane = threadIdx.x;
-    const double h = 1.0 / (double)N;
-    const double c = A.nu / (h * h), diag = A.sigma + 6.0 * c;
+    T c, inv_diag;
+    level_coef<N>(A, c, inv_diag);
     if (zero)
-        for (int o = lane; o < CNT; o += 64) x[o] = 0.0;
+        for (int o = lane; o < CNT; o += 64) x[o] = T(0);
     wave_sync();
     for (int s = 0; s < A.sweeps; ++s) {
-        s_gs<N>(x, b, c, diag, 0, lane, 64);
+        s_gs<N>(x, b, c, inv_diag, 0, lane, 64);
         wave_sync();
-        s_gs<N>(x, b, c, diag, 1, lane, 64);
+        s_gs<N>(x, b, c, inv_diag, 1, lane, 64);
         wave_sync();
     }
     if (A.poisson) {
-        double v = 0.0;
+        T v = T(0);
         for (int o = lane; o < CNT; o += 64) v += x[o];
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        const double m = v / (double)CNT;
+        const T m = v / T(CNT);
         wave_sync();
         for (int o = lane; o < CNT; o += 64) x[o] -= m;
         wave_sync();
@@ -400,20 +496,19 @@ __device__ __forceinline__ void s_coarse_wave(double* x, const double* b, const 
 }
 
 // one level above the coarsest: pre-smoothing, residual and restriction (down)
-template <int N>
-__device__ __forceinline__ void s_down(double* x, const double* b, double* r, double* bnext,
-                                       const SmallArgs& A, bool zero) {
+template <int N, typename T>
+__device__ __forceinline__ void s_down(T* x, const T* b, T* r, T* bnext, const SmallArgs<T>& A, bool zero) {
     constexpr int CNT = N * N * N;
-    const double h = 1.0 / (double)N;
-    const double c = A.nu / (h * h), diag = A.sigma + 6.0 * c;
+    T c, inv_diag;
+    level_coef<N>(A, c, inv_diag);
     if (zero) {
-        for (int o = threadIdx.x; o < CNT; o += blockDim.x) x[o] = 0.0;
+        for (int o = threadIdx.x; o < CNT; o += blockDim.x) x[o] = T(0);
         __syncthreads();
     }
     for (int s = 0; s < A.pre; ++s) {
-        s_gs<N>(x, b, c, diag, 0, threadIdx.x, blockDim.x);
+        s_gs<N>(x, b, c, inv_diag, 0, threadIdx.x, blockDim.x);
         __syncthreads();
-        s_gs<N>(x, b, c, diag, 1, threadIdx.x, blockDim.x);
+        s_gs<N>(x, b, c, inv_diag, 1, threadIdx.x, blockDim.x);
         __syncthreads();
     }
     s_residual<N>(x, b, r, A.sigma, c);
@@ -423,48 +518,51 @@ __device__ __forceinline__ void s_down(double* x, const double* b, double* r, do
 }
 
 // prolongation and post-smoothing (up)
-template <int N>
-__device__ __forceinline__ void s_up(double* x, const double* b, const double* xc, const SmallArgs& A) {
-    const double h = 1.0 / (double)N;
-    const double c = A.nu / (h * h), diag = A.sigma + 6.0 * c;
+template <int N, typename T>
+__device__ __forceinline__ void s_up(T* x, const T* b, const T* xc, const SmallArgs<T>& A) {
+    T c, inv_diag;
+    level_coef<N>(A, c, inv_diag);
     s_prolong_add<N>(x, xc);
     __syncthreads();
     for (int s = 0; s < A.post; ++s) {
-        s_gs<N>(x, b, c, diag, 1, threadIdx.x, blockDim.x);
+        s_gs<N>(x, b, c, inv_diag, 1, threadIdx.x, blockDim.x);
         __syncthreads();
-        s_gs<N>(x, b, c, diag, 0, threadIdx.x, blockDim.x);
+        s_gs<N>(x, b, c, inv_diag, 0, threadIdx.x, blockDim.x);
         __syncthreads();
     }
 }
 
 // One V-cycle over the levels N0 (, N0/2, ...) down to the coarsest (< 8).
-// Level arrays in LDS: [x, b, r] per level, consecutive.
-template <int N0>
+// Global arrays are packed; LDS holds [x, b, r] per level in natural order.
+template <int N0, typename T>
 __global__ void __launch_bounds__(kSmallThreads)
-k_small_vcycle(double* __restrict__ xg, const double* __restrict__ bg, int64_t cs, SmallArgs A,
+k_small_vcycle(T* __restrict__ xg, const T* __restrict__ bg, int64_t cs, SmallArgs<T> A,
                const int32_t* __restrict__ active) {
-    extern __shared__ double lds[];
+    extern __shared__ unsigned char lds_raw[];
+    T* lds = reinterpret_cast<T*>(lds_raw);
     const int comp = blockIdx.x;
     if (!active[comp]) return;
     constexpr int N1 = N0 / 2;
     constexpr int C0 = N0 * N0 * N0, C1 = N1 * N1 * N1;
-    double* x0 = lds;
-    double* b0 = x0 + C0;
-    double* r0 = b0 + C0;
-    double* x1 = r0 + C0;
-    double* b1 = x1 + C1;
-    double* r1 = b1 + C1;
+    T* x0 = lds;
+    T* b0 = x0 + C0;
+    T* r0 = b0 + C0;
+    T* x1 = r0 + C0;
+    T* b1 = x1 + C1;
+    T* r1 = b1 + C1;
     for (int o = threadIdx.x; o < C0; o += blockDim.x) {
-        b0[o] = bg[comp * cs + o];
-        x0[o] = A.zero_init ? 0.0 : xg[comp * cs + o];
+        const int i = o % N0, j = (o / N0) % N0, k = o / (N0 * N0);
+        const int64_t g = comp * cs + pk(i, j, k, N0);
+        b0[o] = bg[g];
+        x0[o] = A.zero_init ? T(0) : xg[g];
     }
     __syncthreads();
     s_down<N0>(x0, b0, r0, b1, A, false);
     if constexpr (N1 >= 8) {
         constexpr int N2 = N1 / 2;
         constexpr int C2 = N2 * N2 * N2;
-        double* x2 = r1 + C1;
-        double* b2 = x2 + C2;
+        T* x2 = r1 + C1;
+        T* b2 = x2 + C2;
         s_down<N1>(x1, b1, r1, b2, A, true);
         if (threadIdx.x < 64) s_coarse_wave<N2>(x2, b2, A, true);
         __syncthreads();
@@ -475,16 +573,23 @@ k_small_vcycle(double* __restrict__ xg, const double* __restrict__ bg, int64_t c
         __syncthreads();
     }
     s_up<N0>(x0, b0, x1, A);
-    for (int o = threadIdx.x; o < C0; o += blockDim.x) xg[comp * cs + o] = x0[o];
+    for (int o = threadIdx.x; o < C0; o += blockDim.x) {
+        const int i = o % N0, j = (o / N0) % N0, k = o / (N0 * N0);
+        xg[comp * cs + pk(i, j, k, N0)] = x0[o];
+    }
 }
 
-dim3 tiles(int n, int ncomp, bool colour) {
-    const int nx = colour ? n / 2 : n;
-    return dim3((nx + TX - 1) / TX, (n + TY - 1) / TY, n * ncomp);
-}
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
 
 int64_t norm_parts(int n) {
-    return (int64_t)((n + TX - 1) / TX) * ((n + TY - 1) / TY) * n;
+    return (int64_t)((n / 2 + TX - 1) / TX) * ((n + TY - 1) / TY) * 2 * n;
+}
+
+int sum_blocks(int64_t count) {
+    int64_t b = (count + 255) / 256;
+    return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
 }
 
 struct OpCoef {
@@ -506,106 +611,165 @@ hipib_status finalize(hipib_ctx* ctx, int64_t nparts, int64_t pstride, int ncomp
     return HIPIB_OK;
 }
 
-// component pointers: level 0 = caller arrays (stride n3), others = workspaces
+template <typename T>
+hipib_status zero_t(hipib_ctx* ctx, T* p, int64_t count) {
+    if (count <= 0) return HIPIB_OK;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    k_zero_t<T><<<(unsigned)blocks, 256, 0, ctx->stream>>>(p, count);
+    HIPIB_HIP(hipGetLastError());
+    return HIPIB_OK;
+}
+
+// level arrays of the V-cycle type T: level 0 given by the caller of vcycle
+template <typename T>
 struct LevelPtr {
-    double* x;
-    const double* b;
+    T* x;
+    const T* b;
     int64_t cs;
 };
 
-hipib_status small_vcycle(hipib_ctx* ctx, int l, LevelPtr p, int ncomp, const OpCoef& oc,
+template <typename T>
+T* level_x(hipib_ctx* ctx, int l) { return static_cast<T*>(ctx->lv[l].x); }
+template <typename T>
+T* level_b(hipib_ctx* ctx, int l) { return static_cast<T*>(ctx->lv[l].b); }
+
+template <typename T>
+hipib_status small_vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef& oc,
                           bool zero_init) {
-    SmallArgs A{};
+    SmallArgs<T> A{};
     A.pre = ctx->cfg.mg_pre;
     A.post = ctx->cfg.mg_post;
     A.sweeps = ctx->cfg.mg_coarse_sweeps;
     A.poisson = oc.poisson;
     A.zero_init = zero_init ? 1 : 0;
-    A.sigma = oc.sigma;
-    A.nu = oc.nu;
+    A.sigma = (T)oc.sigma;
+    A.nu = (T)oc.nu;
     const int n = ctx->lv[l].n;
     const dim3 grid(ncomp), blk(kSmallThreads);
+    const int32_t* act = ctx->st->active;
     if (n == 16)
-        k_small_vcycle<16><<<grid, blk, ctx->small_lds, ctx->stream>>>(p.x, p.b, p.cs, A, ctx->st->active);
+        k_small_vcycle<16, T><<<grid, blk, ctx->small_lds, ctx->stream>>>(p.x, p.b, p.cs, A, act);
     else if (n == 12)
-        k_small_vcycle<12><<<grid, blk, ctx->small_lds, ctx->stream>>>(p.x, p.b, p.cs, A, ctx->st->active);
+        k_small_vcycle<12, T><<<grid, blk, ctx->small_lds, ctx->stream>>>(p.x, p.b, p.cs, A, act);
     else if (n == 8)
-        k_small_vcycle<8><<<grid, blk, ctx->small_lds, ctx->stream>>>(p.x, p.b, p.cs, A, ctx->st->active);
+        k_small_vcycle<8, T><<<grid, blk, ctx->small_lds, ctx->stream>>>(p.x, p.b, p.cs, A, act);
     else
         return fail(HIPIB_E_INVAL, "no coarse-level kernel for n = %d", n);
     HIPIB_HIP(hipGetLastError());
     return HIPIB_OK;
 }
 
-hipib_status gs_sweep(hipib_ctx* ctx, int l, LevelPtr p, int ncomp, const OpCoef& oc, double c,
-                      double diag, int colour) {
+template <typename T>
+hipib_status gs_sweep(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef& oc, T c,
+                      T inv_diag, int colour) {
     const int n = ctx->lv[l].n;
-    const LevelGeom G{n, p.cs};
     const int32_t* act = ctx->st->active;
-    const dim3 grid = tiles(n, ncomp, true), blk(TX, TY);
+    const dim3 grid = colour_grid(n, ncomp), blk(TX, TY);
     if (l > 0) {
-        k_gs_colour<0><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, G, c, diag, colour, act);
+        k_gs<T, 0><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, colour, act);
     } else if (!oc.poisson) {
-        k_gs_colour<1><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, G, c, diag, colour, act);
+        k_gs<T, 1><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, colour, act);
     } else {
-        const int pair = timer_start(ctx, HIPIB_TIMER_SMOOTH_FINE_POISSON, 12.0 * (double)ctx->n3);
-        k_gs_colour<2><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, G, c, diag, colour, act);
-        timer_stop(ctx, pair);
+        k_gs<T, 2><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, colour, act);
     }
     HIPIB_HIP(hipGetLastError());
     return HIPIB_OK;
 }
 
-hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr p, int ncomp, const OpCoef& oc) {
-    if (l == ctx->small_start) return small_vcycle(ctx, l, p, ncomp, oc, l > 0);
+// `sweeps` red+black sweeps starting with colour `first`; the finest-level
+// Poisson group is timed as one unit when the timer is on
+template <typename T>
+hipib_status smooth(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef& oc, int sweeps,
+                    int first) {
+    if (sweeps <= 0) return HIPIB_OK;
     const int n = ctx->lv[l].n;
-    const double h = 1.0 / n, c = oc.nu / (h * h), diag = oc.sigma + 6.0 * c;
+    const T h = T(1) / T(n);
+    const T c = (T)oc.nu / (h * h);
+    const T inv_diag = T(1) / ((T)oc.sigma + T(6) * c);
+    const bool timed = l == 0 && oc.poisson;
+    const int pair = timed ? timer_start(ctx, HIPIB_TIMER_SMOOTH_FINE_POISSON,
+                                         1.5 * sizeof(T) * (double)ctx->n3, 2 * sweeps)
+                           : -1;
+    for (int s = 0; s < sweeps; ++s) {
+        HIPIB_TRY(gs_sweep<T>(ctx, l, p, ncomp, oc, c, inv_diag, first));
+        HIPIB_TRY(gs_sweep<T>(ctx, l, p, ncomp, oc, c, inv_diag, 1 - first));
+    }
+    timer_stop(ctx, pair);
+    return HIPIB_OK;
+}
+
+template <typename T>
+hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef& oc) {
+    if (l == ctx->small_start) return small_vcycle<T>(ctx, l, p, ncomp, oc, false);
+    const int n = ctx->lv[l].n;
     const int32_t* act = ctx->st->active;
-    const LevelGeom G{n, p.cs};
-    for (int s = 0; s < ctx->cfg.mg_pre; ++s) {
-        HIPIB_TRY(gs_sweep(ctx, l, p, ncomp, oc, c, diag, 0));
-        HIPIB_TRY(gs_sweep(ctx, l, p, ncomp, oc, c, diag, 1));
-    }
-    const int64_t rcs = (int64_t)n * n * n;
-    k_residual<<<tiles(n, ncomp, false), dim3(TX, TY), 0, ctx->stream>>>(p.x, p.b, ctx->r0, G, rcs,
-                                                                          oc.sigma, c, act);
-    hipib::Level& C = ctx->lv[l + 1];
-    const LevelGeom GC{C.n, C.n3};
-    k_restrict<<<tiles(C.n, ncomp, false), dim3(TX, TY), 0, ctx->stream>>>(ctx->r0, n, rcs, C.b, GC, act);
-    LevelPtr pc{C.x, C.b, C.n3};
+    const T h = T(1) / T(n);
+    const T c = (T)oc.nu / (h * h);
+    HIPIB_TRY(smooth<T>(ctx, l, p, ncomp, oc, ctx->cfg.mg_pre, 0));
+    T* r = static_cast<T*>(ctx->r0);
+    k_residual<T><<<packed_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(
+        p.x, p.b, r, n, p.cs, (T)oc.sigma, c, act);
+    const Level& C = ctx->lv[l + 1];
+    T* xc = level_x<T>(ctx, l + 1);
+    T* bc = level_b<T>(ctx, l + 1);
+    k_restrict<T><<<packed_grid(C.n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(r, n, p.cs, bc, C.n,
+                                                                               C.n3, act);
+    LevelPtr<T> pc{xc, bc, C.n3};
     if (l + 1 == ctx->small_start) {
-        HIPIB_TRY(small_vcycle(ctx, l + 1, pc, ncomp, oc, true));
+        HIPIB_TRY(small_vcycle<T>(ctx, l + 1, pc, ncomp, oc, true));
     } else {
-        HIPIB_TRY(launch_zero(ctx, C.x, ncomp * C.n3));
-        HIPIB_TRY(vcycle(ctx, l + 1, pc, ncomp, oc));
+        HIPIB_TRY(zero_t<T>(ctx, xc, ncomp * C.n3));
+        HIPIB_TRY(vcycle<T>(ctx, l + 1, pc, ncomp, oc));
     }
-    k_prolong_add<<<tiles(n, ncomp, false), dim3(TX, TY), 0, ctx->stream>>>(p.x, G, C.x, GC, act);
-    for (int s = 0; s < ctx->cfg.mg_post; ++s) {
-        HIPIB_TRY(gs_sweep(ctx, l, p, ncomp, oc, c, diag, 1));
-        HIPIB_TRY(gs_sweep(ctx, l, p, ncomp, oc, c, diag, 0));
-    }
+    k_prolong_add<T><<<packed_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(p.x, n, p.cs, xc, C.n,
+                                                                                C.n3, act);
+    HIPIB_TRY(smooth<T>(ctx, l, p, ncomp, oc, ctx->cfg.mg_post, 1));
     HIPIB_HIP(hipGetLastError());
     return HIPIB_OK;
 }
 
-hipib_status resid_norm(hipib_ctx* ctx, LevelPtr p, int ncomp, const OpCoef& oc, int mode) {
+// ||b - A x|| per component into the state (mode FIN_INIT_R / FIN_CYCLE_R);
+// in mixed mode also writes the scaled FP32 residual of every active component
+hipib_status resid_norm(hipib_ctx* ctx, int ncomp, const OpCoef& oc, int mode) {
     const int n = ctx->n;
     const double h = 1.0 / n, c = oc.nu / (h * h);
     const int64_t np = norm_parts(n);
-    k_resid_norm<<<tiles(n, ncomp, false), dim3(TX, TY), 0, ctx->stream>>>(
-        p.x, p.b, LevelGeom{n, p.cs}, oc.sigma, c, ctx->st->active, ctx->part, np);
+    if (ctx->cfg.precision == HIPIB_MIXED)
+        k_resid_norm<true><<<packed_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(
+            ctx->xp, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, ctx->r32, ctx->part, np);
+    else
+        k_resid_norm<false><<<packed_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(
+            ctx->xp, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, nullptr, ctx->part, np);
     HIPIB_HIP(hipGetLastError());
     return finalize(ctx, np, np, ncomp, mode, 0.0);
 }
 
-int sum_blocks(int64_t count) {
-    int64_t b = (count + 255) / 256;
-    return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
+// one top-level cycle on the packed FP64 solution
+hipib_status cycle(hipib_ctx* ctx, int ncomp, const OpCoef& oc) {
+    const int nb = sum_blocks(ctx->n3);
+    if (ctx->cfg.precision == HIPIB_MIXED) {
+        HIPIB_TRY(zero_t<float>(ctx, ctx->e32, ncomp * ctx->n3));
+        HIPIB_TRY(vcycle<float>(ctx, 0, LevelPtr<float>{ctx->e32, ctx->r32, ctx->n3}, ncomp, oc));
+        k_update<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->xp, ctx->e32, ctx->n3, ctx->st);
+        HIPIB_HIP(hipGetLastError());
+    } else {
+        HIPIB_TRY(vcycle<double>(ctx, 0, LevelPtr<double>{ctx->xp, ctx->bpk, ctx->n3}, ncomp, oc));
+    }
+    if (oc.poisson) {
+        k_sum_partials<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->xp, ctx->n3, ctx->n3, 0,
+                                                                  ctx->st->active, ctx->part, nb);
+        HIPIB_HIP(hipGetLastError());
+        HIPIB_TRY(finalize(ctx, nb, nb, ncomp, FIN_MEAN, 1.0 / (double)ctx->n3));
+        k_sub_mean<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->xp, ctx->n3, ctx->n3, ctx->st);
+        HIPIB_HIP(hipGetLastError());
+    }
+    return resid_norm(ctx, ncomp, oc, FIN_CYCLE_R);
 }
 
 }  // namespace
 
-int timer_start(hipib_ctx* ctx, int kind, double bytes) {
+int timer_start(hipib_ctx* ctx, int kind, double bytes, int launches) {
     if (ctx->timer_which != kind) return -1;
     const size_t pair = ctx->ev_used;
     while (ctx->ev_pool.size() < 2 * (pair + 1)) {
@@ -615,24 +779,40 @@ int timer_start(hipib_ctx* ctx, int kind, double bytes) {
     }
     if (hipEventRecord(ctx->ev_pool[2 * pair], ctx->stream) != hipSuccess) return -1;
     ctx->timer_bytes = bytes;
+    ctx->timer_pending = launches;
     return (int)pair;
 }
 
 void timer_stop(hipib_ctx* ctx, int pair) {
     if (pair < 0) return;
-    if (hipEventRecord(ctx->ev_pool[2 * pair + 1], ctx->stream) == hipSuccess) ctx->ev_used = pair + 1;
+    if (hipEventRecord(ctx->ev_pool[2 * pair + 1], ctx->stream) == hipSuccess) {
+        ctx->ev_used = pair + 1;
+        ctx->timer_launches += ctx->timer_pending;
+    }
 }
 
 hipib_status mg_prepare(hipib_ctx* ctx) {
-    if (ctx->small_lds > 160 * 1024)
-        return fail(HIPIB_E_INVAL, "coarse levels need %zu bytes of LDS", ctx->small_lds);
-    HIPIB_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_vcycle<16>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)ctx->small_lds));
-    HIPIB_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_vcycle<12>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)ctx->small_lds));
-    HIPIB_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_vcycle<8>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)ctx->small_lds));
+    const size_t tsz = mg_level_elem_size(ctx);
+    size_t lds = 0;
+    for (int l = ctx->small_start; l < ctx->L; ++l) lds += 3 * (size_t)ctx->lv[l].n3 * tsz;
+    ctx->small_lds = lds;
+    if (lds > 160 * 1024) return fail(HIPIB_E_INVAL, "coarse levels need %zu bytes of LDS", lds);
+    const void* ks[] = {
+        reinterpret_cast<const void*>(&k_small_vcycle<16, double>),
+        reinterpret_cast<const void*>(&k_small_vcycle<12, double>),
+        reinterpret_cast<const void*>(&k_small_vcycle<8, double>),
+        reinterpret_cast<const void*>(&k_small_vcycle<16, float>),
+        reinterpret_cast<const void*>(&k_small_vcycle<12, float>),
+        reinterpret_cast<const void*>(&k_small_vcycle<8, float>)};
+    for (const void* k : ks)
+        HIPIB_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     return HIPIB_OK;
+}
+
+int64_t mg_partials_needed(int n) { return 3 * (norm_parts(n) + 1024); }
+
+size_t mg_level_elem_size(const hipib_ctx* ctx) {
+    return ctx->cfg.precision == HIPIB_MIXED ? sizeof(float) : sizeof(double);
 }
 
 hipib_status sync_state(hipib_ctx* ctx) {
@@ -658,33 +838,26 @@ hipib_status mg_remove_mean(hipib_ctx* ctx, double* v, int /*slot*/) {
 hipib_status mg_solve(hipib_ctx* ctx, int op, int ncomp, const double* b, double* x,
                       int32_t* cycles, double* relres) {
     const OpCoef oc = op_coef(ctx, op);
-    LevelPtr p{x, b, ctx->n3};
+    const int n = ctx->n;
     const int nb = sum_blocks(ctx->n3);
+    // pack the caller's b and initial guess
+    k_pack<<<natural_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(b, ctx->bpk, n, ctx->n3);
+    k_pack<<<natural_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(x, ctx->xp, n, ctx->n3);
     k_state_reset<<<1, 64, 0, ctx->stream>>>(ctx->st, ncomp);
-    k_sum_partials<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(b, ctx->n3, ctx->n3, 1, nullptr,
+    k_sum_partials<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->bpk, ctx->n3, ctx->n3, 1, nullptr,
                                                              ctx->part, nb);
     HIPIB_HIP(hipGetLastError());
     HIPIB_TRY(finalize(ctx, nb, nb, ncomp, FIN_BNORM, 0.0));
-    HIPIB_TRY(resid_norm(ctx, p, ncomp, oc, FIN_INIT_R));
-    k_zero_requested<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(x, ctx->n3, ctx->n3, ctx->st);
+    HIPIB_TRY(resid_norm(ctx, ncomp, oc, FIN_INIT_R));
+    k_zero_requested<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->xp, ctx->n3, ctx->n3, ctx->st);
     HIPIB_HIP(hipGetLastError());
 
     int enqueue = ctx->predicted[op] > 0 ? ctx->predicted[op] : 1;
     int total = 0;
-    const int limit = (ctx->cfg.mg_fixed_cycles > 0 ? ctx->cfg.mg_fixed_cycles : ctx->cfg.mg_max_cycles) + 1;
+    const int limit =
+        (ctx->cfg.mg_fixed_cycles > 0 ? ctx->cfg.mg_fixed_cycles : ctx->cfg.mg_max_cycles) + 1;
     while (true) {
-        for (int e = 0; e < enqueue; ++e) {
-            HIPIB_TRY(vcycle(ctx, 0, p, ncomp, oc));
-            if (oc.poisson) {
-                k_sum_partials<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(
-                    x, ctx->n3, ctx->n3, 0, ctx->st->active, ctx->part, nb);
-                HIPIB_HIP(hipGetLastError());
-                HIPIB_TRY(finalize(ctx, nb, nb, ncomp, FIN_MEAN, 1.0 / (double)ctx->n3));
-                k_sub_mean<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(x, ctx->n3, ctx->n3, ctx->st);
-                HIPIB_HIP(hipGetLastError());
-            }
-            HIPIB_TRY(resid_norm(ctx, p, ncomp, oc, FIN_CYCLE_R));
-        }
+        for (int e = 0; e < enqueue; ++e) HIPIB_TRY(cycle(ctx, ncomp, oc));
         total += enqueue;
         HIPIB_TRY(sync_state(ctx));
         const MGState& s = *ctx->st_host;
@@ -695,6 +868,8 @@ hipib_status mg_solve(hipib_ctx* ctx, int op, int ncomp, const double* b, double
         if (total > limit) return fail(HIPIB_E_NOCONV, "multigrid: stop state did not settle");
         enqueue = 1;
     }
+    k_unpack<<<natural_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(ctx->xp, x, n, ctx->n3);
+    HIPIB_HIP(hipGetLastError());
     const MGState& s = *ctx->st_host;
     int mx = 1;
     for (int c = 0; c < ncomp; ++c) {

@@ -1,0 +1,184 @@
+// Device helpers for the hexahedral solid: 3x3 algebra, the first
+// Piola-Kirchhoff stress of the constitutive laws ("Constitutive laws") and its
+// directional derivative.  Shared by the force kernels and their adjoints.
+#pragma once
+
+#include "internal.h"
+
+namespace hipib {
+
+template <typename T>
+__device__ __forceinline__ T det3(const T* A) {
+    return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+           A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+// cofactor matrix, cof(A) = det(A) A^{-T}
+template <typename T>
+__device__ __forceinline__ void cof3(const T* A, T* C) {
+    C[0] = A[4] * A[8] - A[5] * A[7];
+    C[1] = A[5] * A[6] - A[3] * A[8];
+    C[2] = A[3] * A[7] - A[4] * A[6];
+    C[3] = A[2] * A[7] - A[1] * A[8];
+    C[4] = A[0] * A[8] - A[2] * A[6];
+    C[5] = A[1] * A[6] - A[0] * A[7];
+    C[6] = A[1] * A[5] - A[2] * A[4];
+    C[7] = A[2] * A[3] - A[0] * A[5];
+    C[8] = A[0] * A[4] - A[1] * A[3];
+}
+
+// First Piola-Kirchhoff stress:
+//   neo-Hookean (mu_s, kappa):  mu_s J^{-2/3}(F - I1/3 F^{-T}) + kappa ln J F^{-T}
+//   Holzapfel-Ogden (a, b, a_f, b_f, kappa):
+//     a e^{b(I1bar-3)} J^{-2/3}(F - I1/3 F^{-T})
+//     + 2 a_f (I4f*-1) e^{b_f (I4f*-1)^2} (F e_f) (x) e_f + kappa ln J F^{-T}
+// Returns false when J <= 0.
+template <typename T>
+__device__ __forceinline__ bool pk1(int model, const T* par, const T* Fm, const T* ef, T* P) {
+    const T J = det3(Fm);
+    if (!(J > T(0))) return false;
+    T cof[9];
+    cof3(Fm, cof);
+    const T invJ = T(1) / J;
+    T I1 = T(0);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) I1 += Fm[r] * Fm[r];
+    const T cb = cbrt(J);
+    const T Jm23 = T(1) / (cb * cb);
+    const T lnJ = log(J);
+    T iso, kappa, fib = T(0);
+    T Fe[3] = {T(0), T(0), T(0)};
+    if (model == HIPIB_NEO_HOOKEAN) {
+        iso = par[0];
+        kappa = par[1];
+    } else {
+        kappa = par[4];
+        iso = par[0] * exp(par[1] * (Jm23 * I1 - T(3)));
+#pragma unroll
+        for (int r = 0; r < 3; ++r) Fe[r] = Fm[3 * r] * ef[0] + Fm[3 * r + 1] * ef[1] + Fm[3 * r + 2] * ef[2];
+        const T I4 = Fe[0] * Fe[0] + Fe[1] * Fe[1] + Fe[2] * Fe[2];
+        if (I4 > T(1)) fib = T(2) * par[2] * (I4 - T(1)) * exp(par[3] * (I4 - T(1)) * (I4 - T(1)));
+    }
+    const T a = iso * Jm23, third = I1 / T(3), vol = kappa * lnJ;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T FiT = cof[3 * r + c] * invJ;
+            P[3 * r + c] = a * (Fm[3 * r + c] - third * FiT) + fib * Fe[r] * ef[c] + vol * FiT;
+        }
+    return true;
+}
+
+// dP = dP/dF : dF.  With G = F^{-T}: dG = -G dF^T G, d ln J = G : dF,
+// dI1 = 2 F : dF, d J^{-2/3} = -(2/3) J^{-2/3} d ln J, dI4 = 2 (F e).(dF e);
+// iso coefficient alpha (mu_s, or a e^{b(I1bar-3)}), fibre coefficient
+// f(I4) = 2 a_f (I4-1) e^{b_f (I4-1)^2} with f' = 2 a_f e^{..}(1 + 2 b_f (I4-1)^2).
+template <typename T>
+__device__ __forceinline__ bool pk1_tangent(int model, const T* par, const T* Fm, const T* ef,
+                                            const T* dF, T* dP) {
+    const T J = det3(Fm);
+    if (!(J > T(0))) return false;
+    T G[9], dG[9];
+    cof3(Fm, G);
+    const T invJ = T(1) / J;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) G[r] *= invJ;
+    // dG = -G dF^T G: (dF^T G)[s][c] = sum_t dF[t][s] G[t][c]
+    T M[9];
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) M[3 * s + c] = dF[s] * G[c] + dF[3 + s] * G[3 + c] + dF[6 + s] * G[6 + c];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            dG[3 * r + c] = -(G[3 * r] * M[c] + G[3 * r + 1] * M[3 + c] + G[3 * r + 2] * M[6 + c]);
+    T I1 = T(0), dI1 = T(0), dlnJ = T(0);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        I1 += Fm[r] * Fm[r];
+        dI1 += T(2) * Fm[r] * dF[r];
+        dlnJ += G[r] * dF[r];
+    }
+    const T cb = cbrt(J);
+    const T Jm23 = T(1) / (cb * cb);
+    const T dJm23 = -T(2) / T(3) * Jm23 * dlnJ;
+    const T lnJ = log(J);
+    T alpha, dalpha, kappa, fib = T(0), dfib = T(0);
+    T Fe[3] = {T(0), T(0), T(0)}, dFe[3] = {T(0), T(0), T(0)};
+    if (model == HIPIB_NEO_HOOKEAN) {
+        alpha = par[0];
+        dalpha = T(0);
+        kappa = par[1];
+    } else {
+        kappa = par[4];
+        const T E1 = exp(par[1] * (Jm23 * I1 - T(3)));
+        alpha = par[0] * E1;
+        dalpha = alpha * par[1] * (dJm23 * I1 + Jm23 * dI1);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            Fe[r] = Fm[3 * r] * ef[0] + Fm[3 * r + 1] * ef[1] + Fm[3 * r + 2] * ef[2];
+            dFe[r] = dF[3 * r] * ef[0] + dF[3 * r + 1] * ef[1] + dF[3 * r + 2] * ef[2];
+        }
+        const T I4 = Fe[0] * Fe[0] + Fe[1] * Fe[1] + Fe[2] * Fe[2];
+        if (I4 > T(1)) {
+            const T dI4 = T(2) * (Fe[0] * dFe[0] + Fe[1] * dFe[1] + Fe[2] * dFe[2]);
+            const T q = I4 - T(1);
+            const T Ef = exp(par[3] * q * q);
+            fib = T(2) * par[2] * q * Ef;
+            dfib = T(2) * par[2] * Ef * (T(1) + T(2) * par[3] * q * q) * dI4;
+        }
+    }
+    const T c1 = dalpha * Jm23 + alpha * dJm23, c2 = alpha * Jm23;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int o = 3 * r + c;
+            const T Mo = Fm[o] - I1 / T(3) * G[o];
+            const T dMo = dF[o] - dI1 / T(3) * G[o] - I1 / T(3) * dG[o];
+            dP[o] = c1 * Mo + c2 * dMo + dfib * Fe[r] * ef[c] + fib * dFe[r] * ef[c] +
+                    kappa * dlnJ * G[o] + kappa * lnJ * dG[o];
+        }
+    return true;
+}
+
+// derivative of the trilinear shape function a = i + 2j + 4k at reference point xi
+template <typename T>
+__device__ __forceinline__ void hex_dN(const T* xi, T dN[8][3]) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        const T s0 = (a & 1) ? T(1) : T(-1), s1 = (a & 2) ? T(1) : T(-1), s2 = (a & 4) ? T(1) : T(-1);
+        const T f0 = T(1) + s0 * xi[0], f1 = T(1) + s1 * xi[1], f2 = T(1) + s2 * xi[2];
+        dN[a][0] = s0 * f1 * f2 * T(0.125);
+        dN[a][1] = f0 * s1 * f2 * T(0.125);
+        dN[a][2] = f0 * f1 * s2 * T(0.125);
+    }
+}
+
+// sum_a v_a (x) dN_a  (3x3, row r = component of v, column c = reference axis)
+template <typename T>
+__device__ __forceinline__ void gather_jac(const T v[8][3], const T dN[8][3], T* Jm) {
+#pragma unroll
+    for (int t = 0; t < 9; ++t) Jm[t] = T(0);
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Jm[3 * r + c] += v[a][r] * dN[a][c];
+}
+
+// A B (3x3 row-major)
+template <typename T>
+__device__ __forceinline__ void matmul3(const T* A, const T* B, T* C) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            C[3 * r + c] = A[3 * r] * B[c] + A[3 * r + 1] * B[3 + c] + A[3 * r + 2] * B[6 + c];
+}
+
+}  // namespace hipib

@@ -1,0 +1,82 @@
+"""Mixed precision (FP32 V-cycles as the correction inside the FP64 residual /
+update loop) against the FP64 oracle.
+
+Error measures: e_u = ||u - u_ref||_2 / ||u_ref||_2, e_p likewise on the
+mean-free pressure, e_X = ||X - X_ref||_inf / ||X_ref - X0||_inf (relative to
+the displacement: relative to the positions themselves it would be trivially
+small).  Target: all three <= 1e-6 after the 100-step neo-Hookean run.
+"""
+import numpy as np
+import pytest
+
+from paper_2503_22695_amd import inputs
+from tests.test_gpu_parity import host, plain_ctx, rel, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    return torch
+
+
+@pytest.fixture(scope="module")
+def hp():
+    from paper_2503_22695_amd import hipib
+    hipib.lib()
+    return hipib
+
+
+@pytest.mark.parametrize("n", [16, 32, 48])
+def test_mixed_poisson_matches_fp64_solution(torch_dev, hp, ref, n):
+    torch = torch_dev
+    say("mixed poisson", n)
+    rng = np.random.default_rng(200 + n)
+    b = rng.standard_normal((n, n, n))
+    b -= b.mean()
+    ctx = plain_ctx(hp, n, precision=hp.MIXED)
+    xd = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    cyc, rr = ctx.mg_solve(hp.OP_POISSON, to_dev(torch, b), xd)
+    xr, cr, _ = ref.mg_solve(ref.fluid(n), 0.0, 1.0, True, b)
+    assert rr[0] <= 1e-10                       # FP64 residual reaches the tolerance
+    assert abs(int(cyc[0]) - cr) <= 1           # same contraction up to FP32 rounding
+    assert rel(host(xd), xr) <= 1e-8
+
+
+def test_mixed_helmholtz_three_components(torch_dev, hp, ref):
+    torch = torch_dev
+    n = 32
+    say("mixed helmholtz", n)
+    rng = np.random.default_rng(7)
+    b = rng.standard_normal((3, n, n, n))
+    ctx = plain_ctx(hp, n, precision=hp.MIXED)
+    xd = torch.zeros((3, n, n, n), dtype=torch.float64, device="cuda")
+    cyc, rr = ctx.mg_solve(hp.OP_HELMHOLTZ, to_dev(torch, b), xd)
+    fl = ref.fluid(n)
+    for d in range(3):
+        xr, cr, _ = ref.mg_solve(fl, 1.0 / 1e-3, 0.01, False, b[d])
+        assert rr[d] <= 1e-10 and abs(int(cyc[d]) - cr) <= 1
+        assert rel(host(xd)[d], xr) <= 1e-8
+
+
+def errors(u, p, X, ur, pr, Xr, X0):
+    e_u = rel(u, ur)
+    e_p = rel(p - p.mean(), pr - pr.mean())
+    e_X = float(np.max(np.abs(X - Xr)) / np.max(np.abs(Xr - X0)))
+    return e_u, e_p, e_X
+
+
+def test_mixed_nh_block_100_steps(torch_dev, hp, ref):
+    torch = torch_dev
+    prob = inputs.workload("nh_block_32_mixed")
+    say("mixed advance", prob.name, prob.n_steps)
+    sim = hp.Simulation(prob)
+    sim.advance(prob.n_steps)
+    torch.cuda.synchronize()
+    ur, pr, Xr, _ = ref.run_problem(prob)
+    e_u, e_p, e_X = errors(host(sim.u), host(sim.p), host(sim.X), ur, pr, Xr, prob.X0)
+    say("mixed errors", e_u, e_p, e_X)
+    assert e_u <= 1e-6 and e_p <= 1e-6 and e_X <= 1e-6
