@@ -68,14 +68,14 @@ typedef struct {
                                  coarse-grid correction (V(2,2): 2, 2) */
     int32_t mg_max_cycles;    /* more cycles than this: HIPIB_E_NOCONV */
     int32_t mg_fixed_cycles;  /* > 0: exactly this many cycles, no stop test */
-    int32_t mg_coarse_sweeps; /* red+black sweeps on the coarsest level (64) */
+    int32_t mg_coarse_sweeps; /* red+black sweeps on the coarsest level (16) */
     double mg_rtol;           /* stop when ||b - A x||_2 <= rtol ||b||_2 */
     int32_t convection;       /* 1: explicit flux-form convection; 0: Stokes */
     int32_t precision;        /* hipib_precision */
     int32_t deterministic;    /* 1: atomic-free, bitwise run-to-run reproducible */
 } hipib_config;
 
-/* Fills cfg with the defaults: V(2,2), 64 coarse sweeps, rtol 1e-10, 50 cycles,
+/* Fills cfg with the defaults: V(2,2), 16 coarse sweeps, rtol 1e-10, 50 cycles,
  * convection on, FP64, atomic mode; n/rho/mu/dt are set to 32/1/0.01/1e-3. */
 void hipib_default_config(hipib_config* cfg);
 

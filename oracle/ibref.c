@@ -430,7 +430,8 @@ void ibref_pressure_load(int32_t n_faces, const int32_t* faces, const double* x,
  *   coarse operators rediscretised at 2h; the coarsest level is the first
  *   with fewer than 8 cells per side, solved by mg_coarse_sweeps red+black
  *   sweeps; Poisson (sigma = 0): the mean is removed after the coarse solve
- *   and after each top-level cycle.
+ *   and once from the final solution (the residual and the sweeps are
+ *   invariant to adding a constant, so the iterates need no mean removal).
  * Stop rule: ||b - A x||_2 <= max(rtol, 1e3 eps) ||b||_2, tested before the
  * first cycle and after every cycle; ||b|| = 0 gives x = 0.
  */
@@ -606,12 +607,12 @@ int ibref_mg_solve(const ibref_fluid* fl, double sigma, double nu, int32_t poiss
                 if (k == fl->mg_max_cycles) { rc = IBREF_E_NOCONV; break; }
             }
             vcycle(fl, &lv, 0, sigma, nu, poisson, b, x);
-            if (poisson) remove_mean(N3, x);
             ++k;
             residual(n, sigma, nu, b, x, lv.r[0]);
             rn = norm2(N3, lv.r[0]);
         }
         rn /= bn;
+        if (poisson) remove_mean(N3, x);
     }
     if (cycles) *cycles = k;
     if (relres) *relres = rn;

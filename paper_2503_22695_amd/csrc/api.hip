@@ -164,7 +164,7 @@ void hipib_default_config(hipib_config* cfg) {
     cfg->mg_post = 2;
     cfg->mg_max_cycles = 50;
     cfg->mg_fixed_cycles = 0;
-    cfg->mg_coarse_sweeps = 64;
+    cfg->mg_coarse_sweeps = 16;
     cfg->mg_rtol = 1e-10;
     cfg->convection = 1;
     cfg->precision = HIPIB_FP64;

@@ -7,7 +7,8 @@
 //   coarse operators rediscretised at 2h, cell-centred trilinear prolongation
 //   added to x, coarsest level (first with < 8 cells per side) solved by a fixed
 //   number of red+black sweeps, Poisson means removed after the coarse solve
-//   and after each top-level cycle.  Stop: ||r||_2 <= max(rtol, 1e3 eps) ||b||_2.
+//   and once from the final solution (residual and sweeps are invariant to a
+//   constant shift).  Stop: ||r||_2 <= max(rtol, 1e3 eps) ||b||_2.
 //
 // Storage: every solver array is kept in a packed red-black layout.  For a
 // level of n cells per side (n even) and H = n/2, component c, colour
@@ -45,7 +46,7 @@ namespace {
 constexpr int TX = 64, TY = 4;
 constexpr int kSmallThreads = 1024;
 
-enum FinalizeMode { FIN_BNORM = 0, FIN_INIT_R = 1, FIN_CYCLE_R = 2, FIN_MEAN = 3 };
+enum FinalizeMode { FIN_BNORM = 0, FIN_INIT_R = 1, FIN_CYCLE_R = 2, FIN_MEAN = 3, FIN_MEAN_ALL = 4 };
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
@@ -274,9 +275,9 @@ k_sum_partials(const double* __restrict__ v, int64_t cs, int64_t count, int squa
 }
 
 __global__ void k_sub_mean(double* __restrict__ v, int64_t cs, int64_t count,
-                           const MGState* __restrict__ st) {
+                           const MGState* __restrict__ st, int all) {
     const int comp = blockIdx.y;
-    if (!st->active[comp]) return;
+    if (!all && !st->active[comp]) return;
     const double m = st->mean[comp];
     double* vc = v + comp * cs;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count;
@@ -308,7 +309,7 @@ k_finalize(const double* __restrict__ part, int64_t nparts, int64_t pstride, int
         if (threadIdx.x == 0) {
             if (mode == FIN_BNORM) {
                 st->bn[comp] = sqrt(s);
-            } else if (mode == FIN_MEAN) {
+            } else if (mode == FIN_MEAN || mode == FIN_MEAN_ALL) {
                 st->mean[comp] = s * inv_count;
             } else {
                 const double bn = st->bn[comp];
@@ -756,14 +757,6 @@ hipib_status cycle(hipib_ctx* ctx, int ncomp, const OpCoef& oc) {
     } else {
         HIPIB_TRY(vcycle<double>(ctx, 0, LevelPtr<double>{ctx->xp, ctx->bpk, ctx->n3}, ncomp, oc));
     }
-    if (oc.poisson) {
-        k_sum_partials<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->xp, ctx->n3, ctx->n3, 0,
-                                                                  ctx->st->active, ctx->part, nb);
-        HIPIB_HIP(hipGetLastError());
-        HIPIB_TRY(finalize(ctx, nb, nb, ncomp, FIN_MEAN, 1.0 / (double)ctx->n3));
-        k_sub_mean<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->xp, ctx->n3, ctx->n3, ctx->st);
-        HIPIB_HIP(hipGetLastError());
-    }
     return resid_norm(ctx, ncomp, oc, FIN_CYCLE_R);
 }
 
@@ -830,7 +823,7 @@ hipib_status mg_remove_mean(hipib_ctx* ctx, double* v, int /*slot*/) {
     k_sum_partials<<<dim3(nb, 1), 256, 0, ctx->stream>>>(v, ctx->n3, ctx->n3, 0, nullptr, ctx->part, nb);
     HIPIB_HIP(hipGetLastError());
     HIPIB_TRY(finalize(ctx, nb, nb, 1, FIN_MEAN, 1.0 / (double)ctx->n3));
-    k_sub_mean<<<dim3(sum_blocks(ctx->n3), 1), 256, 0, ctx->stream>>>(v, ctx->n3, ctx->n3, ctx->st);
+    k_sub_mean<<<dim3(sum_blocks(ctx->n3), 1), 256, 0, ctx->stream>>>(v, ctx->n3, ctx->n3, ctx->st, 0);
     HIPIB_HIP(hipGetLastError());
     return HIPIB_OK;
 }
@@ -867,6 +860,15 @@ hipib_status mg_solve(hipib_ctx* ctx, int op, int ncomp, const double* b, double
         if (!any) break;
         if (total > limit) return fail(HIPIB_E_NOCONV, "multigrid: stop state did not settle");
         enqueue = 1;
+    }
+    if (oc.poisson && ctx->st_host->status == HIPIB_OK) {
+        // the solution's mean (the null space of the periodic Laplacian) is removed once
+        k_sum_partials<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->xp, ctx->n3, ctx->n3, 0,
+                                                                  nullptr, ctx->part, nb);
+        HIPIB_HIP(hipGetLastError());
+        HIPIB_TRY(finalize(ctx, nb, nb, ncomp, FIN_MEAN_ALL, 1.0 / (double)ctx->n3));
+        k_sub_mean<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->xp, ctx->n3, ctx->n3, ctx->st, 1);
+        HIPIB_HIP(hipGetLastError());
     }
     k_unpack<<<natural_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(ctx->xp, x, n, ctx->n3);
     HIPIB_HIP(hipGetLastError());
