@@ -61,6 +61,37 @@ def cpu_baseline(prob, seconds: float):
                       f"({el:.1f} s, FP64 C with OpenMP grid loops)"}
 
 
+def adjoint_ratio(torch, hipib, inputs):
+    """Adjoint workload: 64^3 grid, Holzapfel-Ogden block of 12^3 hexes, 50
+    steps, loss |X^N - X_target|^2 with X_target from a run at perturbed
+    parameters; (checkpointed forward + backward) time over plain forward time,
+    FP64, checkpoints every 10 steps."""
+    prob = inputs.workload("ho_block_64")
+    dev = torch.device("cuda", 0)
+    theta = torch.tensor(prob.materials[0].params[:4], dtype=torch.float64)
+    X0 = torch.tensor(prob.X0, dtype=torch.float64, device=dev)
+    ro = hipib.Rollout(prob, checkpoint_every=10)
+    Xt = ro.forward(theta * torch.tensor([1.1, 0.9, 1.1, 0.9], dtype=torch.float64), X0,
+                    keep_checkpoints=False).clone()
+    ro.forward(theta, X0, keep_checkpoints=False)        # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ro.forward(theta, X0, keep_checkpoints=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    th = theta.clone().requires_grad_(True)
+    X0r = X0.clone().requires_grad_(True)
+    L = ((hipib.IBRollout().apply(th, X0r, ro) - Xt) ** 2).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fwd, both = t1 - t0, t2 - t1
+    return {"ratio": round(both / fwd, 3), "forward_ms": round(1e3 * fwd, 2),
+            "forward_plus_backward_ms": round(1e3 * both, 2),
+            "workload": "ho_block_64: 64^3 grid, 12^3 HO hexes, 50 steps, checkpoints every 10, FP64",
+            "grad_theta": [float(v) for v in th.grad]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +100,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -130,6 +162,10 @@ def main():
         }
         del msim
 
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = adjoint_ratio(torch, hipib, inputs)
+
     avg_s = kernel_ms * 1e-3 / max(launches, 1)
     achieved = bytes_per_launch / avg_s / 1e9 if launches else 0.0
     roofline = {
@@ -159,7 +195,7 @@ def main():
                                           "poisson": float(np.mean(cyc[:, 3]))}},
         "roofline": roofline,
         "mixed_precision": mixed,
-        "adjoint_over_forward": None,
+        "adjoint_over_forward": adjoint,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)

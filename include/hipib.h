@@ -150,7 +150,10 @@ int32_t hipib_get_step_stats(hipib_ctx* ctx, int32_t* cycles, double* relres,
  * neo-Hookean materials stay unchanged. */
 /* Reverse of one hipib_ib_step from (u_n, X_n) at cavity pressure `pressure`,
  * whose result velocity was u_np1.  lam_u in: dL/du^{n+1}, out: dL/du^n;
- * lam_X in: dL/dX^{n+1}, out: dL/dX^n.  Waits for completion. */
+ * lam_X in: dL/dX^{n+1}, out: dL/dX^n.  The adjoint Poisson and Helmholtz
+ * solves start from the previous call's solutions (zero on a context's first
+ * call), as the forward solves start from the previous step's; results depend
+ * on that start only within the multigrid tolerance.  Waits for completion. */
 hipib_status hipib_adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n,
                                 const double* u_np1, double pressure, double* lam_u,
                                 double* lam_X, double* dtheta);

@@ -364,9 +364,14 @@ hipib_status ensure_adjoint_scratch(hipib_ctx* ctx) {
         }
         return HIPIB_OK;
     };
+    const bool fresh = ctx->adj_lg == nullptr;
     HIPIB_TRY(alloc(&ctx->adj_tot, 3 * (size_t)ctx->n3));
     HIPIB_TRY(alloc(&ctx->adj_lg, 3 * (size_t)ctx->n3));
     HIPIB_TRY(alloc(&ctx->adj_p, (size_t)ctx->n3));
+    if (fresh) {  // the adjoint solves' first initial guesses
+        HIPIB_TRY(launch_zero(ctx, ctx->adj_lg, 3 * ctx->n3));
+        HIPIB_TRY(launch_zero(ctx, ctx->adj_p, ctx->n3));
+    }
     HIPIB_TRY(alloc(&ctx->adj_sX, 3 * (size_t)ctx->nn));
     HIPIB_TRY(alloc(&ctx->adj_lamF, 3 * (size_t)ctx->nn));
     ctx->adj_ready_nn = ctx->nn;
@@ -389,11 +394,10 @@ hipib_status adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n, 
     // u^{n+1} = P u*: lam_* = P lam_tot
     HIPIB_TRY(launch_divergence_rhs(ctx, ctx->adj_tot, ctx->bp));
     HIPIB_TRY(mg_remove_mean(ctx, ctx->bp, 0));
-    HIPIB_TRY(launch_zero(ctx, ctx->adj_p, ctx->n3));
+    // warm start: the previous reverse step's adjoint pressure (zero on the first call)
     HIPIB_TRY(mg_solve(ctx, HIPIB_OP_POISSON, 1, ctx->bp, ctx->adj_p, nullptr, nullptr));
     HIPIB_TRY(launch_project(ctx, ctx->adj_tot, ctx->adj_p));
-    // u* = H^{-1} g: lam_g = H^{-1} lam_*
-    HIPIB_TRY(launch_zero(ctx, ctx->adj_lg, g3));
+    // u* = H^{-1} g: lam_g = H^{-1} lam_*  (warm start: the previous call's lam_g)
     HIPIB_TRY(mg_solve(ctx, HIPIB_OP_HELMHOLTZ, 3, ctx->adj_tot, ctx->adj_lg, nullptr, nullptr));
     // g = (rho/dt) u^n - rho C(u^n) + S F
     {

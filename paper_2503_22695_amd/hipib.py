@@ -77,6 +77,12 @@ def lib():
             "hipib_ib_step": (st, [P, P, P, P, f64]),
             "hipib_advance": (st, [P, P, P, P, f64, i32, f64, f64]),
             "hipib_get_step_stats": (i32, [P, P, P, i32]),
+            "hipib_adjoint_step": (st, [P, P, P, P, f64, P, P, P]),
+            "hipib_fe_hvp": (st, [P, P, P, P]),
+            "hipib_fe_param_vjp": (st, [P, P, P, P]),
+            "hipib_spread_vjp_X": (st, [P, P, P, P, P]),
+            "hipib_interp_vjp_X": (st, [P, P, P, P, P]),
+            "hipib_convection_vjp": (st, [P, P, P, P]),
             "hipib_timer_enable": (st, [P, i32]),
             "hipib_timer_read": (st, [P, P, P, P]),
         }
@@ -221,6 +227,55 @@ class Context:
                                    _dev(X, (self.n_nodes, 3), "X"), float(t0), int(n_steps),
                                    float(p0), float(T)), "hipib_advance")
 
+    # -- discrete adjoint ---------------------------------------------------
+    def adjoint_step(self, u_n, X_n, u_np1, pressure, lam_u, lam_X, dtheta):
+        """Reverse of one ib_step: lam_u, lam_X in/out; dtheta [8, 4] += (device)."""
+        g3, nn = self._grid_shape(3), (self.n_nodes, 3)
+        _check(lib().hipib_adjoint_step(self._h, _dev(u_n, g3, "u_n"), _dev(X_n, nn, "X_n"),
+                                        _dev(u_np1, g3, "u_np1"), float(pressure),
+                                        _dev(lam_u, g3, "lam_u"), _dev(lam_X, nn, "lam_X"),
+                                        _dev(dtheta, (MAX_MATERIALS, 4), "dtheta")),
+               "hipib_adjoint_step")
+
+    def fe_hvp(self, X, V, HV=None):
+        import torch
+        if HV is None:
+            HV = torch.empty_like(X)
+        nn = (self.n_nodes, 3)
+        _check(lib().hipib_fe_hvp(self._h, _dev(X, nn, "X"), _dev(V, nn, "V"), _dev(HV, nn, "HV")),
+               "hipib_fe_hvp")
+        return HV
+
+    def fe_param_vjp(self, X, lamF, dtheta):
+        nn = (self.n_nodes, 3)
+        _check(lib().hipib_fe_param_vjp(self._h, _dev(X, nn, "X"), _dev(lamF, nn, "lamF"),
+                                        _dev(dtheta, (MAX_MATERIALS, 4), "dtheta")),
+               "hipib_fe_param_vjp")
+        return dtheta
+
+    def spread_vjp_X(self, X, F, lam_f, lamX):
+        nn = (self.n_nodes, 3)
+        _check(lib().hipib_spread_vjp_X(self._h, _dev(X, nn, "X"), _dev(F, nn, "F"),
+                                        _dev(lam_f, self._grid_shape(3), "lam_f"),
+                                        _dev(lamX, nn, "lamX")), "hipib_spread_vjp_X")
+        return lamX
+
+    def interp_vjp_X(self, X, u, lamU, lamX):
+        nn = (self.n_nodes, 3)
+        _check(lib().hipib_interp_vjp_X(self._h, _dev(X, nn, "X"), _dev(u, self._grid_shape(3), "u"),
+                                        _dev(lamU, nn, "lamU"), _dev(lamX, nn, "lamX")),
+               "hipib_interp_vjp_X")
+        return lamX
+
+    def convection_vjp(self, u, lam, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(u)
+        g3 = self._grid_shape(3)
+        _check(lib().hipib_convection_vjp(self._h, _dev(u, g3, "u"), _dev(lam, g3, "lam"),
+                                          _dev(out, g3, "out")), "hipib_convection_vjp")
+        return out
+
     def timer_enable(self, which: int):
         _check(lib().hipib_timer_enable(self._h, which), "hipib_timer_enable")
 
@@ -274,3 +329,108 @@ class Simulation:
         self.ctx.advance(self.u, self.p, self.X, self.t, n_steps, self.prob.p0, self.prob.T)
         self.t += n_steps * self.prob.dt
         return self
+
+
+# ---------------------------------------------------------------------------
+# differentiable rollout
+# ---------------------------------------------------------------------------
+
+class Rollout:
+    """n_steps immersed-boundary steps of a workload from (u0, X0) at time t0,
+    with the Holzapfel-Ogden parameters (a, b, a_f, b_f) of material `mat`
+    as inputs; the backward pass runs the discrete adjoint, recomputing each
+    segment of `checkpoint_every` steps from a stored (u, p, X) checkpoint."""
+
+    def __init__(self, prob, n_steps=None, checkpoint_every=10, mat=0, t0=0.0, **cfg_over):
+        import torch
+        self.prob = prob
+        self.ctx = context_for_problem(prob, **cfg_over)
+        self.n_steps = prob.n_steps if n_steps is None else int(n_steps)
+        self.k = max(1, int(checkpoint_every))
+        self.mat = mat
+        self.t0 = t0
+        self.dev = torch.device("cuda", torch.cuda.current_device())
+        self.u0 = torch.tensor(prob.initial_velocity(), dtype=torch.float64, device=self.dev)
+        self.kappa = float(prob.materials[mat].params[4])
+        self.checkpoints = []
+
+    def pressure(self, s: int) -> float:
+        import math
+        p0, T = self.prob.p0, self.prob.T
+        if p0 == 0.0 or T <= 0.0:
+            return 0.0
+        t = self.t0 + s * self.prob.dt
+        return p0 * math.sin(math.pi * t / T) ** 2
+
+    def set_theta(self, theta):
+        th = [float(v) for v in theta.detach().cpu().reshape(-1)]
+        self.ctx.set_material(self.mat, HOLZAPFEL_OGDEN, th[:4] + [self.kappa])
+
+    def forward(self, theta, X0, keep_checkpoints=True):
+        import torch
+        self.set_theta(theta)
+        u = self.u0.clone()
+        p = torch.zeros((self.prob.n,) * 3, dtype=torch.float64, device=self.dev)
+        X = X0.detach().to(self.dev, torch.float64).contiguous().clone()
+        self.checkpoints = []
+        s = 0
+        while s < self.n_steps:
+            if keep_checkpoints:
+                self.checkpoints.append((s, u.clone(), p.clone(), X.clone()))
+            m = min(self.k, self.n_steps - s)
+            self.ctx.advance(u, p, X, self.t0 + s * self.prob.dt, m, self.prob.p0, self.prob.T)
+            s += m
+        return X
+
+    def backward(self, grad_XN):
+        import torch
+        lam_X = grad_XN.detach().to(self.dev, torch.float64).contiguous().clone()
+        lam_u = torch.zeros_like(self.u0)
+        dtheta = torch.zeros((MAX_MATERIALS, 4), dtype=torch.float64, device=self.dev)
+        for (s0, uc, pc, Xc) in reversed(self.checkpoints):
+            m = min(self.k, self.n_steps - s0)
+            us, Xs = [uc.clone()], [Xc.clone()]
+            u, p, X = uc.clone(), pc.clone(), Xc.clone()
+            for s in range(s0, s0 + m):
+                self.ctx.ib_step(u, p, X, self.pressure(s))
+                us.append(u.clone())
+                Xs.append(X.clone())
+            for s in range(s0 + m - 1, s0 - 1, -1):
+                i = s - s0
+                self.ctx.adjoint_step(us[i], Xs[i], us[i + 1], self.pressure(s), lam_u, lam_X, dtheta)
+        return dtheta[self.mat].clone(), lam_X, lam_u
+
+
+def _ibrollout_class():
+    import torch
+
+    class IBRollout(torch.autograd.Function):
+        """X^N = IBRollout.apply(theta, X0, rollout): differentiable in the four
+        Holzapfel-Ogden parameters theta (float64, shape [4]) and the initial
+        node positions X0 ([n_nodes, 3], device float64)."""
+
+        @staticmethod
+        def forward(fctx, theta, X0, rollout):
+            XN = rollout.forward(theta, X0)
+            fctx.rollout = rollout
+            fctx.theta_device = theta.device
+            return XN
+
+        @staticmethod
+        def backward(fctx, grad_XN):
+            dth, dX0, _ = fctx.rollout.backward(grad_XN.contiguous())
+            return dth.to(fctx.theta_device), dX0, None
+
+    return IBRollout
+
+
+_IBR = None
+
+
+def IBRollout():
+    """The torch.autograd.Function class (created on first use so importing this
+    module does not require torch)."""
+    global _IBR
+    if _IBR is None:
+        _IBR = _ibrollout_class()
+    return _IBR
