@@ -86,10 +86,46 @@ def adjoint_ratio(torch, hipib, inputs):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     fwd, both = t1 - t0, t2 - t1
-    return {"ratio": round(both / fwd, 3), "forward_ms": round(1e3 * fwd, 2),
+    return {"ratio": round(both / fwd, 3), "definition": "(checkpointed forward + backward) / plain forward",
+            "backward_over_forward": round((both - fwd) / fwd, 3), "forward_ms": round(1e3 * fwd, 2),
             "forward_plus_backward_ms": round(1e3 * both, 2),
             "workload": "ho_block_64: 64^3 grid, 12^3 HO hexes, 50 steps, checkpoints every 10, FP64",
             "grad_theta": [float(v) for v in th.grad]}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gs_poisson_fine_128_hbm_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2503_22695_amd", "csrc", "mg.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the roofline kernel from the committed counter
+    summary, or None when the kernel source has changed since it was taken."""
+    import hashlib
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    vals = {}
+    for ln in lines:
+        if ln.startswith("- ") and ": " in ln:
+            k, v = ln[2:].split(": ", 1)
+            vals[k.strip("`")] = v.strip().strip("`")
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256") != src or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
+def copy_calibration(torch, mib: int):
+    """A plain device-to-device copy of `mib` MiB, three times: the reference
+    kernel for scaling the memory counters of a profiled run."""
+    n = mib * 1024 * 1024 // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def main():
@@ -101,6 +137,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device (memory-counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -113,6 +151,8 @@ def main():
     from paper_2503_22695_amd import hipib, inputs
 
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib > 0:
+        copy_calibration(torch, args.copy_calibration_mib)
     prob = inputs.ho_shell()
 
     def run(precision, timer):
@@ -170,7 +210,7 @@ def main():
     achieved = bytes_per_launch / avg_s / 1e9 if launches else 0.0
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
         "kernel": "k_gs<double,2>: finest-level red or black Gauss-Seidel half-sweep of the Poisson solve (packed layout)",
         "bytes_per_launch": bytes_per_launch, "launches": launches,
         "avg_launch_us": round(avg_s * 1e6, 3),

@@ -111,12 +111,14 @@ k_unpack(const double* __restrict__ src, double* __restrict__ dst, int n, int64_
 // ---------------------------------------------------------------------------
 
 // One colour q of red-black Gauss-Seidel: x_q = (b_q + c * sum_nbr x) / diag.
+// zg: the other colour is known to be zero (first half-sweep from a zero
+// guess), so its neighbours are not read; the result is the same to the bit.
 // TAG only separates launches in profiles: 0 coarse levels, 1 finest level of
 // a Helmholtz solve, 2 finest level of a Poisson solve.
 template <typename T, int TAG>
 __global__ void __launch_bounds__(TX * TY)
 k_gs(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, T c, T inv_diag, int q,
-     const int32_t* __restrict__ active) {
+     int zg, const int32_t* __restrict__ active) {
     const int comp = blockIdx.z / n, k = blockIdx.z - comp * n;
     if (!active[comp]) return;
     const int H = n >> 1;
@@ -125,7 +127,7 @@ k_gs(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, T c, T inv_d
     const int64_t half3 = (int64_t)H * n * n;
     T* xq = x + comp * cs + q * half3;
     const T* xo = x + comp * cs + (1 - q) * half3;
-    const T s = nbr_sum(xo, ih, j, k, n, q);
+    const T s = zg ? T(0) : nbr_sum(xo, ih, j, k, n, q);
     const int64_t o = ih + (int64_t)H * ((int64_t)j + (int64_t)n * k);
     xq[o] = (b[comp * cs + q * half3 + o] + c * s) * inv_diag;
 }
@@ -175,12 +177,88 @@ k_restrict(const T* __restrict__ r, int nf, int64_t fcs, T* __restrict__ bc, int
     bc[comp * ccs + (int64_t)Q * ((int64_t)Hc * nc * nc) + IH + (int64_t)Hc * ((int64_t)J + (int64_t)nc * K)] = s;
 }
 
-// fine x += trilinear interpolation of coarse x (3/4 nearest, 1/4 next, per axis)
+// Restriction of the residual right after a pre-smoothing that ended with a
+// black half-sweep.  There the black residual b - A x is zero in exact
+// arithmetic (each black value was just set to solve its own row), so only
+// red cells contribute: coarse b[I,J,K] = sum over the red cells of the
+// 4x4x4 window 2I-1..2I+2 (per axis) of (w_a w_b w_c / 512) r, w = 1,3,3,1.
+// One workgroup per coarse tile of RCX x RCY x RCZ cells: the red residuals
+// of its fine window go to LDS once (no residual array in HBM), then each
+// thread sums its window from LDS.
+constexpr int RCX = 32, RCY = 4, RCZ = 4;
+constexpr int RWY = 2 * RCY + 2, RWZ = 2 * RCZ + 2;  // fine window rows and planes
+constexpr int RRED = RCX + 1;                        // red cells per window row
+constexpr int RTHREADS = RCX * RCY * 2;              // two threads per coarse column
+
+dim3 resid_restrict_grid(int nc, int ncomp) {
+    return dim3((nc + RCX - 1) / RCX, (nc + RCY - 1) / RCY, ((nc + RCZ - 1) / RCZ) * ncomp);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RTHREADS)
+k_resid_restrict(const T* __restrict__ x, const T* __restrict__ b, int nf, int64_t fcs,
+                 T* __restrict__ bc, int nc, int64_t ccs, T sigma, T c,
+                 const int32_t* __restrict__ active) {
+    __shared__ T rr[RWZ][RWY][RRED];
+    const int nzb = (nc + RCZ - 1) / RCZ;
+    const int comp = blockIdx.z / nzb, kb = blockIdx.z - comp * nzb;
+    if (!active[comp]) return;
+    const int I0 = blockIdx.x * RCX, J0 = blockIdx.y * RCY, K0 = kb * RCZ;
+    // window extent actually needed (partial tiles at the high edges)
+    const int ni = min(RCX, nc - I0), nj = min(RCY, nc - J0), nk = min(RCZ, nc - K0);
+    const int xs = 2 * I0 - 1, ys = 2 * J0 - 1, zs = 2 * K0 - 1;
+    const int H = nf >> 1;
+    const int64_t half3 = (int64_t)H * nf * nf;
+    const T* xr = x + comp * fcs;
+    const T* xb = xr + half3;
+    const T* br = b + comp * fcs;
+    const int rows = 2 * nj + 2, planes = 2 * nk + 2, reds = ni + 1;
+    const int cnt = planes * rows * reds;
+    for (int t = threadIdx.x; t < cnt; t += RTHREADS) {
+        const int m = t % reds, rest = t / reds;
+        const int ly = rest % rows, lz = rest / rows;
+        const int yu = ys + ly, zu = zs + lz;
+        // red cells of this row sit at xs + off + 2m (parity is unchanged by
+        // the periodic wrap because nf is even)
+        const int off = (xs + yu + zu) & 1;
+        const int i = wrapi(xs + off + 2 * m, nf), j = wrapi(yu, nf), k = wrapi(zu, nf);
+        const int ih = i >> 1;
+        const int64_t o = ih + (int64_t)H * ((int64_t)j + (int64_t)nf * k);
+        const T xo = xr[o];
+        const T s = nbr_sum(xb, ih, j, k, nf, 0);
+        rr[lz][ly][m] = br[o] - (sigma * xo - c * (s - T(6) * xo));
+    }
+    __syncthreads();
+    const int col = threadIdx.x % (RCX * RCY), half = threadIdx.x / (RCX * RCY);
+    const int tx = col % RCX, ty = col / RCX;
+    if (tx >= ni || ty >= nj) return;
+    const T w[4] = {T(1), T(3), T(3), T(1)};
+    for (int kk = half; kk < nk; kk += 2) {
+        T acc = T(0);
+        for (int cz = 0; cz < 4; ++cz) {
+            const int lz = 2 * kk + cz;
+            T pl = T(0);
+            for (int cy = 0; cy < 4; ++cy) {
+                const int ly = 2 * ty + cy;
+                const int off = (xs + ys + ly + zs + lz) & 1;
+                // the thread's window 2I-1..2I+2 holds red cells at a = off, off + 2
+                pl += w[cy] * (w[off] * rr[lz][ly][tx] + w[off + 2] * rr[lz][ly][tx + 1]);
+            }
+            acc += w[cz] * pl;
+        }
+        const int I = I0 + tx, J = J0 + ty, K = K0 + kk;
+        bc[comp * ccs + pk(I, J, K, nc)] = acc * T(1.0 / 512.0);
+    }
+}
+
+// fine x += trilinear interpolation of coarse x (3/4 nearest, 1/4 next, per
+// axis) on the first nq colours: nq = 1 (red only) when the next operation is
+// a black half-sweep, which overwrites the black cells without reading them
 template <typename T>
 __global__ void __launch_bounds__(TX * TY)
 k_prolong_add(T* __restrict__ x, int nf, int64_t fcs, const T* __restrict__ xc, int nc, int64_t ccs,
-              const int32_t* __restrict__ active) {
-    const int z = blockIdx.z, comp = z / (2 * nf), rem = z - comp * 2 * nf, q = rem / nf, k = rem - q * nf;
+              int nq, const int32_t* __restrict__ active) {
+    const int z = blockIdx.z, comp = z / (nq * nf), rem = z - comp * nq * nf, q = rem / nf, k = rem - q * nf;
     if (!active[comp]) return;
     const int H = nf >> 1;
     const int ih = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y;
@@ -663,70 +741,80 @@ hipib_status small_vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const
 
 template <typename T>
 hipib_status gs_sweep(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef& oc, T c,
-                      T inv_diag, int colour) {
+                      T inv_diag, int colour, int zg) {
     const int n = ctx->lv[l].n;
     const int32_t* act = ctx->st->active;
     const dim3 grid = colour_grid(n, ncomp), blk(TX, TY);
     if (l > 0) {
-        k_gs<T, 0><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, colour, act);
+        k_gs<T, 0><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, colour, zg, act);
     } else if (!oc.poisson) {
-        k_gs<T, 1><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, colour, act);
+        k_gs<T, 1><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, colour, zg, act);
     } else {
-        k_gs<T, 2><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, colour, act);
+        k_gs<T, 2><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, colour, zg, act);
     }
     HIPIB_HIP(hipGetLastError());
     return HIPIB_OK;
 }
 
-// `sweeps` red+black sweeps starting with colour `first`; the finest-level
-// Poisson group is timed as one unit when the timer is on
+// `sweeps` red+black sweeps starting with colour `first`; zero_guess: x is
+// zero on entry (its first half-sweep reads no neighbours).  Each finest-level
+// Poisson half-sweep is timed on its own when the timer is on.
 template <typename T>
 hipib_status smooth(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef& oc, int sweeps,
-                    int first) {
+                    int first, bool zero_guess) {
     if (sweeps <= 0) return HIPIB_OK;
     const int n = ctx->lv[l].n;
     const T h = T(1) / T(n);
     const T c = (T)oc.nu / (h * h);
     const T inv_diag = T(1) / ((T)oc.sigma + T(6) * c);
     const bool timed = l == 0 && oc.poisson;
-    const int pair = timed ? timer_start(ctx, HIPIB_TIMER_SMOOTH_FINE_POISSON,
-                                         1.5 * sizeof(T) * (double)ctx->n3, 2 * sweeps)
-                           : -1;
-    for (int s = 0; s < sweeps; ++s) {
-        HIPIB_TRY(gs_sweep<T>(ctx, l, p, ncomp, oc, c, inv_diag, first));
-        HIPIB_TRY(gs_sweep<T>(ctx, l, p, ncomp, oc, c, inv_diag, 1 - first));
+    for (int s = 0; s < 2 * sweeps; ++s) {
+        const int zg = (s == 0 && zero_guess) ? 1 : 0;
+        const int pair = timed ? timer_start(ctx, HIPIB_TIMER_SMOOTH_FINE_POISSON,
+                                             (zg ? 1.0 : 1.5) * sizeof(T) * (double)ctx->n3, 1)
+                               : -1;
+        HIPIB_TRY(gs_sweep<T>(ctx, l, p, ncomp, oc, c, inv_diag, (s & 1) ? 1 - first : first, zg));
+        timer_stop(ctx, pair);
     }
-    timer_stop(ctx, pair);
     return HIPIB_OK;
 }
 
+// One V-cycle from level l.  zero_guess: x is taken as zero on entry (its
+// contents are never read).  With at least one pre-smoothing sweep (ending
+// black) the residual is restricted from the red cells only, and with at
+// least one post-smoothing sweep (starting black) the correction is
+// prolongated to the red cells only.
 template <typename T>
-hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef& oc) {
-    if (l == ctx->small_start) return small_vcycle<T>(ctx, l, p, ncomp, oc, false);
+hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef& oc,
+                    bool zero_guess) {
+    if (l == ctx->small_start) return small_vcycle<T>(ctx, l, p, ncomp, oc, zero_guess);
     const int n = ctx->lv[l].n;
     const int32_t* act = ctx->st->active;
     const T h = T(1) / T(n);
     const T c = (T)oc.nu / (h * h);
-    HIPIB_TRY(smooth<T>(ctx, l, p, ncomp, oc, ctx->cfg.mg_pre, 0));
-    T* r = static_cast<T*>(ctx->r0);
-    k_residual<T><<<packed_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(
-        p.x, p.b, r, n, p.cs, (T)oc.sigma, c, act);
+    const int pre = ctx->cfg.mg_pre, post = ctx->cfg.mg_post;
+    if (zero_guess && pre == 0) HIPIB_TRY(zero_t<T>(ctx, p.x, ncomp * p.cs));
+    HIPIB_TRY(smooth<T>(ctx, l, p, ncomp, oc, pre, 0, zero_guess));
     const Level& C = ctx->lv[l + 1];
     T* xc = level_x<T>(ctx, l + 1);
     T* bc = level_b<T>(ctx, l + 1);
-    k_restrict<T><<<packed_grid(C.n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(r, n, p.cs, bc, C.n,
-                                                                               C.n3, act);
-    LevelPtr<T> pc{xc, bc, C.n3};
-    if (l + 1 == ctx->small_start) {
-        HIPIB_TRY(small_vcycle<T>(ctx, l + 1, pc, ncomp, oc, true));
+    if (pre > 0) {
+        k_resid_restrict<T><<<resid_restrict_grid(C.n, ncomp), RTHREADS, 0, ctx->stream>>>(
+            p.x, p.b, n, p.cs, bc, C.n, C.n3, (T)oc.sigma, c, act);
     } else {
-        HIPIB_TRY(zero_t<T>(ctx, xc, ncomp * C.n3));
-        HIPIB_TRY(vcycle<T>(ctx, l + 1, pc, ncomp, oc));
+        T* r = static_cast<T*>(ctx->r0);
+        k_residual<T><<<packed_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(
+            p.x, p.b, r, n, p.cs, (T)oc.sigma, c, act);
+        k_restrict<T><<<packed_grid(C.n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(r, n, p.cs, bc, C.n,
+                                                                                   C.n3, act);
     }
-    k_prolong_add<T><<<packed_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(p.x, n, p.cs, xc, C.n,
-                                                                                C.n3, act);
-    HIPIB_TRY(smooth<T>(ctx, l, p, ncomp, oc, ctx->cfg.mg_post, 1));
     HIPIB_HIP(hipGetLastError());
+    HIPIB_TRY(vcycle<T>(ctx, l + 1, LevelPtr<T>{xc, bc, C.n3}, ncomp, oc, true));
+    const int nq = post > 0 ? 1 : 2;
+    k_prolong_add<T><<<dim3((n / 2 + TX - 1) / TX, (n + TY - 1) / TY, nq * n * ncomp), dim3(TX, TY), 0,
+                       ctx->stream>>>(p.x, n, p.cs, xc, C.n, C.n3, nq, act);
+    HIPIB_HIP(hipGetLastError());
+    HIPIB_TRY(smooth<T>(ctx, l, p, ncomp, oc, post, 1, false));
     return HIPIB_OK;
 }
 
@@ -750,12 +838,11 @@ hipib_status resid_norm(hipib_ctx* ctx, int ncomp, const OpCoef& oc, int mode) {
 hipib_status cycle(hipib_ctx* ctx, int ncomp, const OpCoef& oc) {
     const int nb = sum_blocks(ctx->n3);
     if (ctx->cfg.precision == HIPIB_MIXED) {
-        HIPIB_TRY(zero_t<float>(ctx, ctx->e32, ncomp * ctx->n3));
-        HIPIB_TRY(vcycle<float>(ctx, 0, LevelPtr<float>{ctx->e32, ctx->r32, ctx->n3}, ncomp, oc));
+        HIPIB_TRY(vcycle<float>(ctx, 0, LevelPtr<float>{ctx->e32, ctx->r32, ctx->n3}, ncomp, oc, true));
         k_update<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->xp, ctx->e32, ctx->n3, ctx->st);
         HIPIB_HIP(hipGetLastError());
     } else {
-        HIPIB_TRY(vcycle<double>(ctx, 0, LevelPtr<double>{ctx->xp, ctx->bpk, ctx->n3}, ncomp, oc));
+        HIPIB_TRY(vcycle<double>(ctx, 0, LevelPtr<double>{ctx->xp, ctx->bpk, ctx->n3}, ncomp, oc, false));
     }
     return resid_norm(ctx, ncomp, oc, FIN_CYCLE_R);
 }

@@ -354,50 +354,73 @@ class Rollout:
         self.kappa = float(prob.materials[mat].params[4])
         self.checkpoints = []
 
-    def pressure(self, s: int) -> float:
+    def pressure(self, s0: int, i: int) -> float:
+        """Cavity pressure at step s0 + i, with the time rounded exactly as
+        hipib_advance rounds it when called at the start of step s0."""
         import math
         p0, T = self.prob.p0, self.prob.T
         if p0 == 0.0 or T <= 0.0:
             return 0.0
-        t = self.t0 + s * self.prob.dt
-        return p0 * math.sin(math.pi * t / T) ** 2
+        t = (self.t0 + s0 * self.prob.dt) + i * self.prob.dt
+        sn = math.sin(math.pi * t / T)
+        return p0 * sn * sn
 
     def set_theta(self, theta):
         th = [float(v) for v in theta.detach().cpu().reshape(-1)]
         self.ctx.set_material(self.mat, HOLZAPFEL_OGDEN, th[:4] + [self.kappa])
 
     def forward(self, theta, X0, keep_checkpoints=True):
+        """X^N from X0.  With keep_checkpoints, (u, p, X) is stored at the start
+        of every segment, and the states of the last segment are kept whole as
+        they are computed, so the backward pass recomputes every segment but
+        the last."""
         import torch
         self.set_theta(theta)
         u = self.u0.clone()
         p = torch.zeros((self.prob.n,) * 3, dtype=torch.float64, device=self.dev)
         X = X0.detach().to(self.dev, torch.float64).contiguous().clone()
         self.checkpoints = []
+        self.tail = None
         s = 0
         while s < self.n_steps:
-            if keep_checkpoints:
-                self.checkpoints.append((s, u.clone(), p.clone(), X.clone()))
             m = min(self.k, self.n_steps - s)
-            self.ctx.advance(u, p, X, self.t0 + s * self.prob.dt, m, self.prob.p0, self.prob.T)
+            if keep_checkpoints and s + m == self.n_steps:
+                self.tail = (s, self._run_segment(u, p, X, s, m))
+                u, X = self.tail[1][0][-1], self.tail[1][1][-1]
+            else:
+                if keep_checkpoints:
+                    self.checkpoints.append((s, u.clone(), p.clone(), X.clone()))
+                self.ctx.advance(u, p, X, self.t0 + s * self.prob.dt, m, self.prob.p0, self.prob.T)
             s += m
-        return X
+        return X.clone() if keep_checkpoints else X
+
+    def _run_segment(self, u, p, X, s0, m):
+        """m steps from (u, p, X) at step s0 (not modified); every u and X."""
+        us, Xs = [u.clone()], [X.clone()]
+        u, p, X = u.clone(), p.clone(), X.clone()
+        for i in range(m):
+            self.ctx.ib_step(u, p, X, self.pressure(s0, i))
+            us.append(u.clone())
+            Xs.append(X.clone())
+        return us, Xs
+
+    def _reverse_segment(self, s0, us, Xs, lam_u, lam_X, dtheta):
+        for i in range(len(us) - 2, -1, -1):
+            self.ctx.adjoint_step(us[i], Xs[i], us[i + 1], self.pressure(s0, i), lam_u, lam_X, dtheta)
 
     def backward(self, grad_XN):
         import torch
         lam_X = grad_XN.detach().to(self.dev, torch.float64).contiguous().clone()
         lam_u = torch.zeros_like(self.u0)
         dtheta = torch.zeros((MAX_MATERIALS, 4), dtype=torch.float64, device=self.dev)
+        if self.tail is not None:
+            s0, (us, Xs) = self.tail
+            self._reverse_segment(s0, us, Xs, lam_u, lam_X, dtheta)
+            self.tail = None
         for (s0, uc, pc, Xc) in reversed(self.checkpoints):
             m = min(self.k, self.n_steps - s0)
-            us, Xs = [uc.clone()], [Xc.clone()]
-            u, p, X = uc.clone(), pc.clone(), Xc.clone()
-            for s in range(s0, s0 + m):
-                self.ctx.ib_step(u, p, X, self.pressure(s))
-                us.append(u.clone())
-                Xs.append(X.clone())
-            for s in range(s0 + m - 1, s0 - 1, -1):
-                i = s - s0
-                self.ctx.adjoint_step(us[i], Xs[i], us[i + 1], self.pressure(s), lam_u, lam_X, dtheta)
+            us, Xs = self._run_segment(uc, pc, Xc, s0, m)
+            self._reverse_segment(s0, us, Xs, lam_u, lam_X, dtheta)
         return dtheta[self.mat].clone(), lam_X, lam_u
 
 

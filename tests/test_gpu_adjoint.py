@@ -240,3 +240,26 @@ def test_mixed_precision_adjoint_matches_fp64(torch_dev, hp, ref):
     say("mixed grads", grads[hp.MIXED][0], grads[hp.FP64][0])
     assert_rel("dL/dtheta", grads[hp.MIXED][0], grads[hp.FP64][0], 1e-6)
     assert_rel("dL/dX0", grads[hp.MIXED][1], grads[hp.FP64][1], 1e-6)
+
+
+def test_checkpointing_matches_store_all_on_gpu(torch_dev, hp):
+    """Checkpoints every 10 steps (segments recomputed in the backward pass)
+    against keeping all 50 steps' states: the recomputed states differ from the
+    stored ones only by the order of floating-point atomic additions, so the
+    gradients agree to near rounding."""
+    torch = torch_dev
+    prob = inputs.workload("ho_block_64")
+    say("checkpointing vs store-all", prob.name)
+    theta = np.array(prob.materials[0].params[:4])
+    Xt = target_positions(torch, hp, prob, theta * [1.1, 0.9, 1.1, 0.9], prob.n_steps)
+    grads = []
+    for k in (10, prob.n_steps):
+        ro = hp.Rollout(prob, checkpoint_every=k)
+        th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+        X0 = to_dev(torch, prob.X0).requires_grad_(True)
+        L = ((hp.IBRollout().apply(th, X0, ro) - Xt) ** 2).sum()
+        L.backward()
+        grads.append((th.grad.numpy().copy(), host(X0.grad)))
+    e_th, e_X = rel(grads[0][0], grads[1][0]), rel(grads[0][1], grads[1][1])
+    say("checkpointed vs store-all", e_th, e_X)
+    assert e_th <= 1e-12 and e_X <= 1e-12, (e_th, e_X)
