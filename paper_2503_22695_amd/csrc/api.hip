@@ -244,7 +244,7 @@ hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out
     ctx->ntiles = (int64_t)ctx->tiles_axis * ctx->tiles_axis * ctx->tiles_axis;
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->bin_count, (size_t)ctx->ntiles);
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->bin_off, (size_t)ctx->ntiles + 1);
-    if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->tile_list, (size_t)ctx->ntiles);
+    if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->tile_list, 2 * (size_t)spread_list_cap(ctx->ntiles, 0));
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->n_list, 1);
     ctx->part_cap = mg_partials_needed(n);
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->part, (size_t)ctx->part_cap);
@@ -320,6 +320,9 @@ hipib_status hipib_set_mesh(hipib_ctx* ctx, int32_t n_nodes, const double* X_ref
     HIPIB_TRY(dev_alloc(ctx, &ctx->node_tile, (size_t)n_nodes));
     HIPIB_TRY(dev_alloc(ctx, &ctx->node_rank, (size_t)n_nodes));
     HIPIB_TRY(dev_alloc(ctx, &ctx->perm, (size_t)n_nodes));
+    (void)hipFree(ctx->tile_list);
+    ctx->tile_list = nullptr;
+    HIPIB_TRY(dev_alloc(ctx, &ctx->tile_list, 2 * (size_t)spread_list_cap(ctx->ntiles, n_nodes)));
     if (n_nodes > 0)
         HIPIB_HIP(hipMemcpy(ctx->Xref, X_ref, 3 * sizeof(double) * n_nodes, hipMemcpyHostToDevice));
     if (n_elems > 0) {

@@ -25,24 +25,47 @@ namespace {
 
 
 
-// tile of each node and its rank inside the tile
+// tile of each node and its rank inside the tile.  Consecutive nodes of a
+// mesh mostly share a tile, so the lanes of a wavefront with equal tiles are
+// grouped and one lane adds the group's size to the count (one atomic per
+// distinct tile per wavefront instead of one per node).
 __global__ void __launch_bounds__(256)
 k_bin_count(const double* __restrict__ X, int nn, int n, int T, int ta, double inv_h,
             int32_t* __restrict__ node_tile, int32_t* __restrict__ node_rank,
             int32_t* __restrict__ count) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nn) return;
-    int t[3];
-    for (int e = 0; e < 3; ++e) {
-        const int c = (int)floor(safe_coord(X[3 * q + e] * inv_h));
-        t[e] = wrap_mod(c, n) / T;
+    const bool valid = q < nn;
+    int tile = -1;
+    if (valid) {
+        int t[3];
+        for (int e = 0; e < 3; ++e) {
+            const int c = (int)floor(safe_coord(X[3 * q + e] * inv_h));
+            t[e] = wrap_mod(c, n) / T;
+        }
+        tile = t[0] + ta * (t[1] + ta * t[2]);
+        node_tile[q] = tile;
     }
-    const int tile = t[0] + ta * (t[1] + ta * t[2]);
-    node_tile[q] = tile;
-    node_rank[q] = atomicAdd(count + tile, 1);
+    const int lane = (int)__lane_id();
+    unsigned long long pending = __ballot(valid);
+    int rank = 0;
+    while (pending) {  // uniform over the wavefront
+        const int leader = __ffsll((long long)pending) - 1;
+        const int key = __shfl(tile, leader, 64);
+        const bool mine = valid && tile == key;
+        const unsigned long long m = __ballot(mine);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(count + key, __popcll(m));
+        base = __shfl(base, leader, 64);
+        if (mine) rank = base + __popcll(m & ((1ull << lane) - 1ull));
+        pending &= ~m;
+    }
+    if (valid) node_rank[q] = rank;
 }
 
-// exclusive scan of the tile counts, list of occupied tiles; counts reset to 0
+// Exclusive scan of the tile counts and the list of work items: each
+// occupied tile is cut into chunks of at most kSpreadChunk nodes, listed as
+// (tile, first rank) pairs, so a tile crowded with nodes is spread by several
+// workgroups.  Counts are reset to 0 for the next binning.
 __global__ void __launch_bounds__(1024)
 k_bin_scan(int32_t* __restrict__ count, int64_t ntiles, int32_t* __restrict__ off,
            int32_t* __restrict__ list, int32_t* __restrict__ nlist) {
@@ -54,7 +77,7 @@ k_bin_scan(int32_t* __restrict__ count, int64_t ntiles, int32_t* __restrict__ of
     int32_t sum = 0, nz = 0;
     for (int64_t i = beg; i < end; ++i) {
         sum += count[i];
-        nz += count[i] > 0;
+        nz += (count[i] + kSpreadChunk - 1) / kSpreadChunk;
     }
     s_sum[tid] = sum;
     s_nz[tid] = nz;
@@ -72,7 +95,11 @@ k_bin_scan(int32_t* __restrict__ count, int64_t ntiles, int32_t* __restrict__ of
         off[i] = run;
         const int32_t c = count[i];
         run += c;
-        if (c > 0) list[lrun++] = (int32_t)i;
+        for (int32_t r = 0; r < c; r += kSpreadChunk) {
+            list[2 * lrun] = (int32_t)i;
+            list[2 * lrun + 1] = r;
+            ++lrun;
+        }
         count[i] = 0;
     }
     if (tid == 1023) {
@@ -89,13 +116,17 @@ k_bin_scatter(const int32_t* __restrict__ node_tile, const int32_t* __restrict__
     perm[off[node_tile[q]] + node_rank[q]] = q;
 }
 
-// one workgroup per occupied tile (grid-stride over the list); LDS box of
-// E^3 cells per lattice, E = T + 4, starting at T * tile - 2.  TW: type of the
+// one workgroup per work item (grid-stride over the list): up to
+// kSpreadChunk nodes of one tile, one node per thread; LDS box of E^3 cells
+// per lattice, E = T + 4, starting at T * tile - 2.  Ranks inside the chunk
+// are dealt to threads with an odd stride, so the lanes of a wavefront take
+// nodes that are far apart in mesh order, which keeps apart the LDS addresses
+// they add to in the same instruction.  TW: type of the
 // weights and their products (the lattice coordinate, its floor and the
 // fractional offset are always FP64); the LDS box and the grid accumulate in
 // FP64, since neighbouring nodes' forces partly cancel there.
 template <int T, typename TW>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kSpreadChunk)
 k_spread_tiles(const double* __restrict__ X, const double* __restrict__ F, double* __restrict__ f,
                const int32_t* __restrict__ perm, const int32_t* __restrict__ off,
                const int32_t* __restrict__ list, const int32_t* __restrict__ nlist, int n, int ta,
@@ -104,11 +135,12 @@ k_spread_tiles(const double* __restrict__ X, const double* __restrict__ F, doubl
     __shared__ double box[3 * E3];
     const int ntl = *nlist;
     for (int li = blockIdx.x; li < ntl; li += gridDim.x) {
-        const int tile = list[li];
+        const int tile = list[2 * li];
         const int tb[3] = {T * (tile % ta), T * ((tile / ta) % ta), T * (tile / (ta * ta))};
         for (int e = threadIdx.x; e < 3 * E3; e += blockDim.x) box[e] = 0.0;
         __syncthreads();
-        for (int idx = off[tile] + threadIdx.x; idx < off[tile + 1]; idx += blockDim.x) {
+        const int idx = off[tile] + list[2 * li + 1] + ((threadIdx.x * 109) & (kSpreadChunk - 1));
+        if (idx < off[tile + 1]) {
             const int q = perm[idx];
             double xs[3];
             int cw[3];
@@ -231,10 +263,11 @@ hipib_status launch_bin(hipib_ctx* ctx, const double* X) {
 hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, double* f) {
     if (ctx->nn == 0) return HIPIB_OK;
     const double h = ctx->h;
-    const int blocks = (int)(ctx->ntiles < 4096 ? ctx->ntiles : 4096);
+    const int64_t cap = spread_list_cap(ctx->ntiles, ctx->nn);
+    const int blocks = (int)(cap < 8192 ? cap : 8192);
     const bool mixed = ctx->cfg.precision == HIPIB_MIXED;
 #define HIPIB_SPREAD(TT, TW)                                                                       \
-    k_spread_tiles<TT, TW><<<blocks, 256, 0, ctx->stream>>>(                                        \
+    k_spread_tiles<TT, TW><<<blocks, kSpreadChunk, 0, ctx->stream>>>(                                        \
         X, F, f, ctx->perm, ctx->bin_off, ctx->tile_list, ctx->n_list, ctx->n, ctx->tiles_axis,     \
         ctx->n3, 1.0 / h, 1.0 / (h * h * h))
     if (ctx->tile == 8) {

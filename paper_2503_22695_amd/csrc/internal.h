@@ -14,6 +14,12 @@ namespace hipib {
 constexpr int kMaxLevels = 16;
 constexpr int kSmallMax = 16;       // levels with n <= 16 run in one workgroup (LDS)
 constexpr int kReduceBlock = 256;
+constexpr int kSpreadChunk = 256;   // nodes per spreading work item (= its threads)
+
+// upper bound on the number of spreading work items
+inline int64_t spread_list_cap(int64_t ntiles, int64_t nn) {
+    return ntiles + (nn + kSpreadChunk - 1) / kSpreadChunk + 1;
+}
 
 // Material table passed by value to the force kernels.
 struct MatTable {
@@ -91,8 +97,8 @@ struct hipib_ctx {
     int64_t ntiles = 0;
     int32_t* bin_count = nullptr;   // [ntiles] (kept zero between uses)
     int32_t* bin_off = nullptr;     // [ntiles + 1]
-    int32_t* tile_list = nullptr;   // [ntiles] occupied tiles
-    int32_t* n_list = nullptr;      // [1] number of occupied tiles
+    int32_t* tile_list = nullptr;   // [spread_list_cap][2] spreading work items (tile, first rank)
+    int32_t* n_list = nullptr;      // [1] number of work items
     int32_t* node_tile = nullptr;   // [nn]
     int32_t* node_rank = nullptr;   // [nn]
     int32_t* perm = nullptr;        // [nn] nodes grouped by tile

@@ -73,6 +73,18 @@ __device__ __forceinline__ T nbr_sum(const T* __restrict__ xo, int ih, int j, in
            xo[(int64_t)H * (j + (int64_t)n * km) + ih];
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Renumbering so that XCD x runs the x-th contiguous eighth of the grid (in
+// x-fastest order: a slab of z-planes) keeps a stencil's neighbouring planes
+// in the same L2.  Identity when the grid is not a multiple of 8.
+__device__ __forceinline__ uint3 xcd_block() {
+    const unsigned gx = gridDim.x, gy = gridDim.y;
+    const unsigned nb = gx * gy * gridDim.z;
+    unsigned b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    if ((nb & 7u) == 0) b = (b & 7u) * (nb >> 3) + (b >> 3);
+    return make_uint3(b % gx, (b / gx) % gy, b / (gx * gy));
+}
+
 // grid for one colour of a level: (packed x tiles, y tiles, n * ncomp)
 dim3 colour_grid(int n, int ncomp) {
     return dim3((n / 2 + TX - 1) / TX, (n + TY - 1) / TY, n * ncomp);
@@ -119,10 +131,11 @@ template <typename T, int TAG>
 __global__ void __launch_bounds__(TX * TY)
 k_gs(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, T c, T inv_diag, int q,
      int zg, const int32_t* __restrict__ active) {
-    const int comp = blockIdx.z / n, k = blockIdx.z - comp * n;
+    const uint3 bid = xcd_block();
+    const int comp = bid.z / n, k = bid.z - comp * n;
     if (!active[comp]) return;
     const int H = n >> 1;
-    const int ih = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y;
+    const int ih = bid.x * TX + threadIdx.x, j = bid.y * TY + threadIdx.y;
     if (ih >= H || j >= n) return;
     const int64_t half3 = (int64_t)H * n * n;
     T* xq = x + comp * cs + q * half3;
