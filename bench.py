@@ -226,7 +226,7 @@ def main():
         "kernel": "k_gs<double,2>: finest-level red or black Gauss-Seidel half-sweep of the Poisson solve (packed layout)",
         "bytes_per_launch": bytes_per_launch, "launches": launches,
         "avg_launch_us": round(avg_s * 1e6, 3),
-        "timing": f"HIP event pair around each launch on the library's stream, during {args.roofline_steps} "
+        "timing": f"HIP start/stop events stamped by each dispatch (hipExtLaunchKernel) on the library's stream, during {args.roofline_steps} "
                   "further steps run after the timed region",
     }
     out = {

@@ -173,8 +173,9 @@ hipib_status hipib_interp_vjp_X(hipib_ctx* ctx, const double* X, const double* u
 hipib_status hipib_convection_vjp(hipib_ctx* ctx, const double* u, const double* lam, double* out);
 
 /* --- measurement -------------------------------------------------------- */
-/* Kernel classes that can be timed with HIP events (each launch is bracketed
- * by a pair of events recorded on the context's stream). */
+/* Kernel classes that can be timed with HIP events: each timed launch goes
+ * through hipExtLaunchKernel with a start and a stop event, which take the
+ * dispatch's own start and end timestamps on the context's stream. */
 typedef enum {
     HIPIB_TIMER_OFF = 0,
     /* one red or black Gauss-Seidel sweep on the finest level of a Poisson

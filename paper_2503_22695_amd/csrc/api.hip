@@ -91,6 +91,7 @@ void free_all(hipib_ctx* ctx) {
     for (int l = 0; l < kMaxLevels; ++l) {
         (void)hipFree(ctx->lv[l].x);
         (void)hipFree(ctx->lv[l].b);
+        (void)hipFree(ctx->lv[l].x2);
     }
     (void)hipFree(ctx->r0);
     (void)hipFree(ctx->xp);
@@ -229,6 +230,8 @@ hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out
     for (int l = 1; l < L; ++l) {
         alloc_bytes(&ctx->lv[l].x, 3 * (size_t)ctx->lv[l].n3 * esz);
         alloc_bytes(&ctx->lv[l].b, 3 * (size_t)ctx->lv[l].n3 * esz);
+        if (l < ctx->small_start && ctx->lv[l].n % 8 == 0)
+            alloc_bytes(&ctx->lv[l].x2, 3 * (size_t)ctx->lv[l].n3 * esz);
     }
     alloc_bytes(&ctx->r0, 3 * (size_t)ctx->n3 * esz);
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->xp, 3 * (size_t)ctx->n3);

@@ -46,6 +46,7 @@ struct Level {
     int64_t n3 = 0;
     void* x = nullptr;     // [3][n3] packed, l >= 1, element type of the V-cycle
     void* b = nullptr;
+    void* x2 = nullptr;    // [3][n3] x after pre-smoothing (levels run as fused halves)
 };
 
 struct StepRecord {
@@ -122,7 +123,6 @@ struct hipib_ctx {
     std::vector<hipEvent_t> ev_pool;   // pairs: start 2i, stop 2i+1
     size_t ev_used = 0;                // pairs recorded since the last read
     double timer_bytes = 0.0;          // algorithmic bytes per timed launch
-    int timer_pending = 0;             // launches inside the open event pair
     int64_t timer_launches = 0;        // launches timed since the last read
 };
 
@@ -176,9 +176,10 @@ hipib_status launch_vjp_X(hipib_ctx* ctx, const double* X, const double* field, 
                           double* lamX, double scale);
 
 // ---- event timing --------------------------------------------------------------
-// Returns the pair index to close with timer_stop, or -1 when `kind` is not timed.
-int timer_start(hipib_ctx* ctx, int kind, double bytes, int launches);
-void timer_stop(hipib_ctx* ctx, int pair);
+// When launches of `kind` are being timed: takes the next event pair from the
+// pool (the caller launches with hipExtLaunchKernelGGL, which stamps the
+// dispatch's own start and end into them), counts the launch and returns true.
+bool timer_events(hipib_ctx* ctx, int kind, double bytes, hipEvent_t* start, hipEvent_t* stop);
 
 // ---- small device helpers ----------------------------------------------------
 __device__ __forceinline__ int wrap_idx(int i, int n) {

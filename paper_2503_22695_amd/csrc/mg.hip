@@ -38,6 +38,8 @@
 // once to read them.
 #include <cfloat>
 
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 
 namespace hipib {
@@ -672,6 +674,175 @@ k_small_vcycle(T* __restrict__ xg, const T* __restrict__ bg, int64_t cs, SmallAr
 }
 
 // ---------------------------------------------------------------------------
+// coarse levels above the single-workgroup ones: one launch per half of the
+// V-cycle on a level.  Used for V(2,2) with a zero guess (always the case
+// below the finest level) on levels with n a multiple of 8.
+//
+// A workgroup owns an 8^3 block of the level (a 4^3 block of the next one)
+// and recomputes in LDS every cell its result depends on, with the arithmetic
+// of the separate kernels in the same order:
+//   k_level_down: red (from x = 0), black, red, black half-sweeps on boxes
+//     reaching 5, 4, 3, 2 cells beyond the block; red-cell residuals on the
+//     restriction window (1 cell beyond; black residuals are zero after the
+//     black half-sweep); restriction into the next level's b; the smoothed x
+//     of the block is kept for k_level_up.
+//   k_level_up: x_red += prolongated coarse correction on a box reaching 4
+//     cells beyond the block; black, red, black, red half-sweeps on boxes
+//     reaching 3, 2, 1, 0 cells; the block's x is stored.
+// Blocks read neighbours' cells only from arrays no launch of the pair writes,
+// so there is no ordering between workgroups.
+// ---------------------------------------------------------------------------
+
+constexpr int KB = 8;                                 // owned cells per axis
+constexpr int KDH = 5, KUH = 4;                       // halos of the down / up kernels
+constexpr int KDE = KB + 2 * KDH, KUE = KB + 2 * KUH; // LDS box sides (18, 16)
+constexpr int KW = KB + 2;                            // restriction window side
+constexpr int KTHREADS = 256;
+
+template <int E>
+__device__ __forceinline__ int lix(int a, int b, int c) { return a + E * (b + E * c); }
+
+// packed offset inside a component of the cell at unwrapped (gi, gj, gk)
+__device__ __forceinline__ int64_t pkw(int gi, int gj, int gk, int n) {
+    return pk(wrapi(gi, n), wrapi(gj, n), wrapi(gk, n), n);
+}
+
+// Colour-q cells of the box reaching d cells beyond the owned block (local
+// origin: global cell (g0x, g0y, g0z) at LDS index 0, block at HH):
+// x = (b + c * neighbour sum) * inv_diag; zg: neighbours are zero.
+template <int E, int HH, typename T>
+__device__ __forceinline__ void box_gs(T* xs, const T* __restrict__ bg, int n, int g0x, int g0y,
+                                       int g0z, int d, int q, T c, T inv_diag, bool zg) {
+    const int lo = HH - d, S = KB + 2 * d, S2 = S / 2;
+    const int cnt = S2 * S * S;
+    for (int u = threadIdx.x; u < cnt; u += KTHREADS) {
+        const int ah = u % S2, rest = u / S2;
+        const int lb = lo + rest % S, lc = lo + rest / S;
+        const int la = lo + 2 * ah + ((q + g0x + lo + g0y + lb + g0z + lc) & 1);
+        const int o = lix<E>(la, lb, lc);
+        const T bv = bg[pkw(g0x + la, g0y + lb, g0z + lc, n)];
+        T sum = T(0);
+        if (!zg)
+            sum = xs[o + 1] + xs[o - 1] + xs[o + E] + xs[o - E] + xs[o + E * E] + xs[o - E * E];
+        xs[o] = (bv + c * sum) * inv_diag;
+    }
+}
+
+__device__ __forceinline__ void level_block(int n, int& comp, int& i0, int& j0, int& k0) {
+    const int nb = n / KB, nb3 = nb * nb * nb;
+    comp = blockIdx.x / nb3;
+    const int r = blockIdx.x - comp * nb3;
+    i0 = KB * (r % nb);
+    j0 = KB * ((r / nb) % nb);
+    k0 = KB * (r / (nb * nb));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(KTHREADS)
+k_level_down(const T* __restrict__ b, T* __restrict__ xpre, int n, int64_t cs, T* __restrict__ bc,
+             int64_t ccs, T sigma, T c, T inv_diag, const int32_t* __restrict__ active) {
+    __shared__ T xs[KDE * KDE * KDE];
+    __shared__ T rw[KW * KW * KW];
+    int comp, i0, j0, k0;
+    level_block(n, comp, i0, j0, k0);
+    if (!active[comp]) return;
+    const int g0x = i0 - KDH, g0y = j0 - KDH, g0z = k0 - KDH;
+    const T* bcp = b + comp * cs;
+    box_gs<KDE, KDH>(xs, bcp, n, g0x, g0y, g0z, 5, 0, c, inv_diag, true);
+    __syncthreads();
+    box_gs<KDE, KDH>(xs, bcp, n, g0x, g0y, g0z, 4, 1, c, inv_diag, false);
+    __syncthreads();
+    box_gs<KDE, KDH>(xs, bcp, n, g0x, g0y, g0z, 3, 0, c, inv_diag, false);
+    __syncthreads();
+    box_gs<KDE, KDH>(xs, bcp, n, g0x, g0y, g0z, 2, 1, c, inv_diag, false);
+    __syncthreads();
+    // red residuals on the window, black entries zero
+    for (int u = threadIdx.x; u < KW * KW * KW; u += KTHREADS) {
+        const int la = KDH - 1 + u % KW, lb = KDH - 1 + (u / KW) % KW, lc = KDH - 1 + u / (KW * KW);
+        T r = T(0);
+        if (((g0x + la + g0y + lb + g0z + lc) & 1) == 0) {
+            const int o = lix<KDE>(la, lb, lc);
+            const T xo = xs[o];
+            const T sum = xs[o + 1] + xs[o - 1] + xs[o + KDE] + xs[o - KDE] + xs[o + KDE * KDE] +
+                          xs[o - KDE * KDE];
+            r = bcp[pkw(g0x + la, g0y + lb, g0z + lc, n)] - (sigma * xo - c * (sum - T(6) * xo));
+        }
+        rw[u] = r;
+    }
+    // the block's smoothed x
+    T* xp = xpre + comp * cs;
+    for (int u = threadIdx.x; u < KB * KB * KB; u += KTHREADS) {
+        const int a = u % KB, bb = (u / KB) % KB, cc = u / (KB * KB);
+        xp[pk(i0 + a, j0 + bb, k0 + cc, n)] = xs[lix<KDE>(KDH + a, KDH + bb, KDH + cc)];
+    }
+    __syncthreads();
+    constexpr int KC = KB / 2;
+    if (threadIdx.x < KC * KC * KC) {
+        const int ci = threadIdx.x % KC, cj = (threadIdx.x / KC) % KC, ck = threadIdx.x / (KC * KC);
+        const T w[4] = {T(1), T(3), T(3), T(1)};
+        T sum = T(0);
+        for (int cz = 0; cz < 4; ++cz)
+            for (int cy = 0; cy < 4; ++cy)
+                for (int cx = 0; cx < 4; ++cx)
+                    sum += w[cx] * w[cy] * w[cz] / T(512) * rw[lix<KW>(2 * ci + cx, 2 * cj + cy, 2 * ck + cz)];
+        bc[comp * ccs + pk(i0 / 2 + ci, j0 / 2 + cj, k0 / 2 + ck, n / 2)] = sum;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(KTHREADS)
+k_level_up(const T* __restrict__ b, const T* __restrict__ xpre, const T* __restrict__ xc,
+           T* __restrict__ x, int n, int64_t cs, int64_t ccs, T c, T inv_diag,
+           const int32_t* __restrict__ active) {
+    __shared__ T xs[KUE * KUE * KUE];
+    int comp, i0, j0, k0;
+    level_block(n, comp, i0, j0, k0);
+    if (!active[comp]) return;
+    const int g0x = i0 - KUH, g0y = j0 - KUH, g0z = k0 - KUH;
+    const int nc = n / 2;
+    const T* bcp = b + comp * cs;
+    const T* xpp = xpre + comp * cs;
+    const T* xcc = xc + comp * ccs;
+    // red cells of the whole box: smoothed x plus the trilinear correction
+    {
+        constexpr int S = KUE, S2 = S / 2;
+        const T wt[2] = {T(0.75), T(0.25)};
+        for (int u = threadIdx.x; u < S2 * S * S; u += KTHREADS) {
+            const int ah = u % S2, rest = u / S2;
+            const int lb = rest % S, lc = rest / S;
+            const int la = 2 * ah + ((g0x + g0y + lb + g0z + lc) & 1);
+            const int ijk[3] = {wrapi(g0x + la, n), wrapi(g0y + lb, n), wrapi(g0z + lc, n)};
+            int base[3][2];
+            for (int d = 0; d < 3; ++d) {
+                const int I = ijk[d] >> 1;
+                base[d][0] = I;
+                base[d][1] = (ijk[d] & 1) ? wrapi(I + 1, nc) : wrapi(I - 1, nc);
+            }
+            T v = T(0);
+            for (int cz = 0; cz < 2; ++cz)
+                for (int cy = 0; cy < 2; ++cy)
+                    for (int cx = 0; cx < 2; ++cx)
+                        v += wt[cx] * wt[cy] * wt[cz] * xcc[pk(base[0][cx], base[1][cy], base[2][cz], nc)];
+            xs[lix<KUE>(la, lb, lc)] = xpp[pk(ijk[0], ijk[1], ijk[2], n)] + v;
+        }
+    }
+    __syncthreads();
+    box_gs<KUE, KUH>(xs, bcp, n, g0x, g0y, g0z, 3, 1, c, inv_diag, false);
+    __syncthreads();
+    box_gs<KUE, KUH>(xs, bcp, n, g0x, g0y, g0z, 2, 0, c, inv_diag, false);
+    __syncthreads();
+    box_gs<KUE, KUH>(xs, bcp, n, g0x, g0y, g0z, 1, 1, c, inv_diag, false);
+    __syncthreads();
+    box_gs<KUE, KUH>(xs, bcp, n, g0x, g0y, g0z, 0, 0, c, inv_diag, false);
+    __syncthreads();
+    T* xo = x + comp * cs;
+    for (int u = threadIdx.x; u < KB * KB * KB; u += KTHREADS) {
+        const int a = u % KB, bb = (u / KB) % KB, cc = u / (KB * KB);
+        xo[pk(i0 + a, j0 + bb, k0 + cc, n)] = xs[lix<KUE>(KUH + a, KUH + bb, KUH + cc)];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 
@@ -752,16 +923,28 @@ hipib_status small_vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const
     return HIPIB_OK;
 }
 
+// levels run as one k_level_down / k_level_up pair per V-cycle
+bool level_fused(const hipib_ctx* ctx, int l) {
+    return l >= 1 && l < ctx->small_start && ctx->lv[l].n % KB == 0 && ctx->lv[l].x2 != nullptr &&
+           ctx->cfg.mg_pre == 2 && ctx->cfg.mg_post == 2;
+}
+
 template <typename T>
 hipib_status gs_sweep(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef& oc, T c,
                       T inv_diag, int colour, int zg) {
     const int n = ctx->lv[l].n;
     const int32_t* act = ctx->st->active;
     const dim3 grid = colour_grid(n, ncomp), blk(TX, TY);
+    hipEvent_t t0, t1;
     if (l > 0) {
         k_gs<T, 0><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, colour, zg, act);
     } else if (!oc.poisson) {
         k_gs<T, 1><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, colour, zg, act);
+    } else if (timer_events(ctx, HIPIB_TIMER_SMOOTH_FINE_POISSON,
+                            (zg ? 1.0 : 1.5) * sizeof(T) * (double)ctx->n3, &t0, &t1)) {
+        // the events take the dispatch's own start and end timestamps
+        hipExtLaunchKernelGGL(k_gs<T, 2>, grid, blk, 0, ctx->stream, t0, t1, 0, p.x, p.b, n, p.cs, c,
+                              inv_diag, colour, zg, act);
     } else {
         k_gs<T, 2><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, colour, zg, act);
     }
@@ -780,14 +963,9 @@ hipib_status smooth(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
     const T h = T(1) / T(n);
     const T c = (T)oc.nu / (h * h);
     const T inv_diag = T(1) / ((T)oc.sigma + T(6) * c);
-    const bool timed = l == 0 && oc.poisson;
     for (int s = 0; s < 2 * sweeps; ++s) {
         const int zg = (s == 0 && zero_guess) ? 1 : 0;
-        const int pair = timed ? timer_start(ctx, HIPIB_TIMER_SMOOTH_FINE_POISSON,
-                                             (zg ? 1.0 : 1.5) * sizeof(T) * (double)ctx->n3, 1)
-                               : -1;
         HIPIB_TRY(gs_sweep<T>(ctx, l, p, ncomp, oc, c, inv_diag, (s & 1) ? 1 - first : first, zg));
-        timer_stop(ctx, pair);
     }
     return HIPIB_OK;
 }
@@ -806,6 +984,23 @@ hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
     const T h = T(1) / T(n);
     const T c = (T)oc.nu / (h * h);
     const int pre = ctx->cfg.mg_pre, post = ctx->cfg.mg_post;
+    if (zero_guess && level_fused(ctx, l)) {
+        const T inv_diag = T(1) / ((T)oc.sigma + T(6) * c);
+        const Level& C = ctx->lv[l + 1];
+        T* xc = level_x<T>(ctx, l + 1);
+        T* bc = level_b<T>(ctx, l + 1);
+        T* x2 = static_cast<T*>(ctx->lv[l].x2);
+        const int nb = n / KB;
+        const unsigned blocks = (unsigned)(nb * nb * nb * ncomp);
+        k_level_down<T><<<blocks, KTHREADS, 0, ctx->stream>>>(p.b, x2, n, p.cs, bc, C.n3,
+                                                              (T)oc.sigma, c, inv_diag, act);
+        HIPIB_HIP(hipGetLastError());
+        HIPIB_TRY(vcycle<T>(ctx, l + 1, LevelPtr<T>{xc, bc, C.n3}, ncomp, oc, true));
+        k_level_up<T><<<blocks, KTHREADS, 0, ctx->stream>>>(p.b, x2, xc, p.x, n, p.cs, C.n3, c,
+                                                            inv_diag, act);
+        HIPIB_HIP(hipGetLastError());
+        return HIPIB_OK;
+    }
     if (zero_guess && pre == 0) HIPIB_TRY(zero_t<T>(ctx, p.x, ncomp * p.cs));
     HIPIB_TRY(smooth<T>(ctx, l, p, ncomp, oc, pre, 0, zero_guess));
     const Level& C = ctx->lv[l + 1];
@@ -862,26 +1057,20 @@ hipib_status cycle(hipib_ctx* ctx, int ncomp, const OpCoef& oc) {
 
 }  // namespace
 
-int timer_start(hipib_ctx* ctx, int kind, double bytes, int launches) {
-    if (ctx->timer_which != kind) return -1;
+bool timer_events(hipib_ctx* ctx, int kind, double bytes, hipEvent_t* start, hipEvent_t* stop) {
+    if (ctx->timer_which != kind) return false;
     const size_t pair = ctx->ev_used;
     while (ctx->ev_pool.size() < 2 * (pair + 1)) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return -1;
+        if (hipEventCreate(&e) != hipSuccess) return false;
         ctx->ev_pool.push_back(e);
     }
-    if (hipEventRecord(ctx->ev_pool[2 * pair], ctx->stream) != hipSuccess) return -1;
+    *start = ctx->ev_pool[2 * pair];
+    *stop = ctx->ev_pool[2 * pair + 1];
+    ctx->ev_used = pair + 1;
     ctx->timer_bytes = bytes;
-    ctx->timer_pending = launches;
-    return (int)pair;
-}
-
-void timer_stop(hipib_ctx* ctx, int pair) {
-    if (pair < 0) return;
-    if (hipEventRecord(ctx->ev_pool[2 * pair + 1], ctx->stream) == hipSuccess) {
-        ctx->ev_used = pair + 1;
-        ctx->timer_launches += ctx->timer_pending;
-    }
+    ctx->timer_launches += 1;
+    return true;
 }
 
 hipib_status mg_prepare(hipib_ctx* ctx) {
