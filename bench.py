@@ -95,16 +95,18 @@ def adjoint_ratio(torch, hipib, inputs):
             "grad_theta": [float(v) for v in th.grad]}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_gs_poisson_fine_128_hbm_traffic.md")
+KERNELS = {}  # timer id -> description, filled once the library is loaded
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2503_22695_amd", "csrc", "mg.hip")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the roofline kernel from the committed counter
-    summary, or None when the kernel source has changed since it was taken."""
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of the roofline kernel (e.g. "k_level_down") from the
+    committed counter summary profiles/<kernel>_poisson_fine_128_hbm_traffic.md,
+    or None when the kernel source has changed since it was taken."""
     import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_poisson_fine_128_hbm_traffic.md")
     try:
-        lines = open(TRAFFIC_FILE).read().splitlines()
+        lines = open(path).read().splitlines()
     except OSError:
         return None
     vals = {}
@@ -174,23 +176,32 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         cyc, _ = ctx.step_stats()
-        tim = (0, 0.0, 0.0)
+        tim = {}
         if timer:
-            # roofline pass: the next steps of the same run, on copies, with a
-            # HIP event pair around every finest-level Poisson half-sweep
-            u, p, X = sim.u.clone(), sim.p.clone(), sim.X.clone()
+            # roofline passes: the next steps of the same run, on copies, with
+            # dispatch-stamped events on every launch of one finest-level
+            # Poisson kernel class per pass
             t_end = args.steps * prob.dt
-            ctx.timer_enable(hipib.TIMER_SMOOTH_FINE_POISSON)
-            ctx.advance(u, p, X, t_end, args.roofline_steps, prob.p0, prob.T)
-            torch.cuda.synchronize()
-            tim = ctx.timer_read()
-            ctx.timer_enable(hipib.TIMER_OFF)
-            del u, p, X
+            for kind in KERNELS:
+                u, p, X = sim.u.clone(), sim.p.clone(), sim.X.clone()
+                ctx.timer_enable(kind)
+                ctx.advance(u, p, X, t_end, args.roofline_steps, prob.p0, prob.T)
+                torch.cuda.synchronize()
+                tim[kind] = ctx.timer_read()
+                ctx.timer_enable(hipib.TIMER_OFF)
+                del u, p, X
         if not (torch.isfinite(sim.u).all() and torch.isfinite(sim.X).all()):
             raise RuntimeError("non-finite state after the timed run")
         return sim, t1 - t0, tim, cyc
 
-    sim, elapsed, (launches, kernel_ms, bytes_per_launch), cyc = run(hipib.FP64, True)
+    KERNELS.update({
+        hipib.TIMER_SMOOTH_FINE_POISSON: "k_gs<double,2>: finest-level red or black Gauss-Seidel half-sweep "
+                                         "of the Poisson solve (packed layout, 12 B/cell)",
+    })
+    sim, elapsed, tim, cyc = run(hipib.FP64, True)
+    # the dominant kernel: the timed class with the most total time
+    dom = max(tim, key=lambda k: tim[k][1])
+    launches, kernel_ms, bytes_per_launch = tim[dom]
     steps_per_s = args.steps / elapsed
 
     mixed = None
@@ -222,12 +233,15 @@ def main():
     achieved = bytes_per_launch / avg_s / 1e9 if launches else 0.0
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-        "kernel": "k_gs<double,2>: finest-level red or black Gauss-Seidel half-sweep of the Poisson solve (packed layout)",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(KERNELS[dom].split("<")[0]),
+        "kernel": KERNELS[dom],
         "bytes_per_launch": bytes_per_launch, "launches": launches,
         "avg_launch_us": round(avg_s * 1e6, 3),
         "timing": f"HIP start/stop events stamped by each dispatch (hipExtLaunchKernel) on the library's stream, during {args.roofline_steps} "
                   "further steps run after the timed region",
+        "other_kernels": {KERNELS[k].split(":")[0]: {"launches": v[0], "avg_launch_us": round(1e3 * v[1] / v[0], 3),
+                                                     "achieved_GBs": round(v[2] * v[0] / (v[1] * 1e-3) / 1e9, 1)}
+                          for k, v in tim.items() if k != dom and v[0] > 0},
     }
     out = {
         "metric": METRIC,

@@ -230,9 +230,10 @@ hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out
     for (int l = 1; l < L; ++l) {
         alloc_bytes(&ctx->lv[l].x, 3 * (size_t)ctx->lv[l].n3 * esz);
         alloc_bytes(&ctx->lv[l].b, 3 * (size_t)ctx->lv[l].n3 * esz);
-        if (l < ctx->small_start && ctx->lv[l].n % 8 == 0)
-            alloc_bytes(&ctx->lv[l].x2, 3 * (size_t)ctx->lv[l].n3 * esz);
     }
+    // pre-smoothing arrays of the levels run as fused down/up halves
+    for (int l = 1; l < ctx->small_start; ++l)
+        if (ctx->lv[l].n % 8 == 0) alloc_bytes(&ctx->lv[l].x2, 3 * (size_t)ctx->lv[l].n3 * esz);
     alloc_bytes(&ctx->r0, 3 * (size_t)ctx->n3 * esz);
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->xp, 3 * (size_t)ctx->n3);
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->bpk, 3 * (size_t)ctx->n3);

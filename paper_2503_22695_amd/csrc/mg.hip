@@ -87,10 +87,8 @@ __device__ __forceinline__ uint3 xcd_block() {
     return make_uint3(b % gx, (b / gx) % gy, b / (gx * gy));
 }
 
-// grid for one colour of a level: (packed x tiles, y tiles, n * ncomp)
-dim3 colour_grid(int n, int ncomp) {
-    return dim3((n / 2 + TX - 1) / TX, (n + TY - 1) / TY, n * ncomp);
-}
+// grid of a half-sweep: (packed x tiles, y tiles, z columns of KPT cells * ncomp)
+dim3 gs_grid(int n, int ncomp);
 // grid for both colours: z = (comp * 2 + q) * n + k
 dim3 packed_grid(int n, int ncomp) {
     return dim3((n / 2 + TX - 1) / TX, (n + TY - 1) / TY, 2 * n * ncomp);
@@ -125,16 +123,28 @@ k_unpack(const double* __restrict__ src, double* __restrict__ dst, int n, int64_
 // ---------------------------------------------------------------------------
 
 // One colour q of red-black Gauss-Seidel: x_q = (b_q + c * sum_nbr x) / diag.
+// Each thread updates a column of KPT cells along z: the other colour's
+// values at (ih, j) on planes k0-1 .. k0+KPT serve as the z-neighbours of the
+// column and as one of each cell's two x-neighbours, and all of the thread's
+// loads are issued before the first update.  Neighbours are summed in the
+// order i+1, i-1, j+1, j-1, k+1, k-1.
 // zg: the other colour is known to be zero (first half-sweep from a zero
 // guess), so its neighbours are not read; the result is the same to the bit.
 // TAG only separates launches in profiles: 0 coarse levels, 1 finest level of
 // a Helmholtz solve, 2 finest level of a Poisson solve.
+constexpr int KPT = 4;
+
+dim3 gs_grid(int n, int ncomp) {
+    return dim3((n / 2 + TX - 1) / TX, (n + TY - 1) / TY, ((n + KPT - 1) / KPT) * ncomp);
+}
+
 template <typename T, int TAG>
 __global__ void __launch_bounds__(TX * TY)
 k_gs(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, T c, T inv_diag, int q,
      int zg, const int32_t* __restrict__ active) {
     const uint3 bid = xcd_block();
-    const int comp = bid.z / n, k = bid.z - comp * n;
+    const int nkb = (n + KPT - 1) / KPT;
+    const int comp = bid.z / nkb, k0 = (bid.z - comp * nkb) * KPT;
     if (!active[comp]) return;
     const int H = n >> 1;
     const int ih = bid.x * TX + threadIdx.x, j = bid.y * TY + threadIdx.y;
@@ -142,9 +152,46 @@ k_gs(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, T c, T inv_d
     const int64_t half3 = (int64_t)H * n * n;
     T* xq = x + comp * cs + q * half3;
     const T* xo = x + comp * cs + (1 - q) * half3;
-    const T s = zg ? T(0) : nbr_sum(xo, ih, j, k, n, q);
-    const int64_t o = ih + (int64_t)H * ((int64_t)j + (int64_t)n * k);
-    xq[o] = (b[comp * cs + q * half3 + o] + c * s) * inv_diag;
+    const T* bq = b + comp * cs + q * half3;
+    const int jp = wrapi(j + 1, n), jm = wrapi(j - 1, n);
+    const int ihp = ih + 1 < H ? ih + 1 : 0, ihm = ih > 0 ? ih - 1 : H - 1;
+    T col[KPT + 2], side[KPT], yp[KPT], ym[KPT], bv[KPT];
+    if (!zg) {
+#pragma unroll
+        for (int r = 0; r < KPT + 2; ++r) {
+            const int kk = wrapi(k0 - 1 + r, n);
+            col[r] = xo[ih + (int64_t)H * ((int64_t)j + (int64_t)n * kk)];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < KPT; ++r) {
+        const int k = k0 + r;
+        if (k < n) {
+            const int64_t row = (int64_t)H * ((int64_t)j + (int64_t)n * k);
+            bv[r] = bq[row + ih];
+            if (!zg) {
+                const int p = (j + k + q) & 1;
+                side[r] = xo[row + (p ? ihp : ihm)];
+                yp[r] = xo[(int64_t)H * ((int64_t)jp + (int64_t)n * k) + ih];
+                ym[r] = xo[(int64_t)H * ((int64_t)jm + (int64_t)n * k) + ih];
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < KPT; ++r) {
+        const int k = k0 + r;
+        if (k < n) {
+            T s = T(0);
+            if (!zg) {
+                // x-neighbours: p = 1 -> (ih+1, ih), p = 0 -> (ih, ih-1)
+                const int p = (j + k + q) & 1;
+                const T a_ip = p ? side[r] : col[r + 1];
+                const T a_im = p ? col[r + 1] : side[r];
+                s = a_ip + a_im + yp[r] + ym[r] + col[r + 2] + col[r];
+            }
+            xq[(int64_t)H * ((int64_t)j + (int64_t)n * k) + ih] = (bv[r] + c * s) * inv_diag;
+        }
+    }
 }
 
 // r = b - (sigma x - c (sum_nbr x - 6 x)), both colours
@@ -203,7 +250,7 @@ k_restrict(const T* __restrict__ r, int nf, int64_t fcs, T* __restrict__ bc, int
 constexpr int RCX = 32, RCY = 4, RCZ = 4;
 constexpr int RWY = 2 * RCY + 2, RWZ = 2 * RCZ + 2;  // fine window rows and planes
 constexpr int RRED = RCX + 1;                        // red cells per window row
-constexpr int RTHREADS = RCX * RCY * 2;              // two threads per coarse column
+constexpr int RTHREADS = RCX * RCY * RCZ;            // one thread per coarse cell
 
 dim3 resid_restrict_grid(int nc, int ncomp) {
     return dim3((nc + RCX - 1) / RCX, (nc + RCY - 1) / RCY, ((nc + RCZ - 1) / RCZ) * ncomp);
@@ -229,26 +276,41 @@ k_resid_restrict(const T* __restrict__ x, const T* __restrict__ b, int nf, int64
     const T* br = b + comp * fcs;
     const int rows = 2 * nj + 2, planes = 2 * nk + 2, reds = ni + 1;
     const int cnt = planes * rows * reds;
-    for (int t = threadIdx.x; t < cnt; t += RTHREADS) {
-        const int m = t % reds, rest = t / reds;
-        const int ly = rest % rows, lz = rest / rows;
-        const int yu = ys + ly, zu = zs + lz;
-        // red cells of this row sit at xs + off + 2m (parity is unchanged by
-        // the periodic wrap because nf is even)
-        const int off = (xs + yu + zu) & 1;
-        const int i = wrapi(xs + off + 2 * m, nf), j = wrapi(yu, nf), k = wrapi(zu, nf);
-        const int ih = i >> 1;
-        const int64_t o = ih + (int64_t)H * ((int64_t)j + (int64_t)nf * k);
-        const T xo = xr[o];
-        const T s = nbr_sum(xb, ih, j, k, nf, 0);
-        rr[lz][ly][m] = br[o] - (sigma * xo - c * (s - T(6) * xo));
+    // batches of 4 cells per thread: all their loads are issued before any use
+    constexpr int RB = 4;
+    for (int t0 = threadIdx.x; t0 < cnt; t0 += RB * RTHREADS) {
+        T xv[RB], sv[RB], bv[RB];
+        int dst[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int t = t0 + r * RTHREADS;
+            dst[r] = -1;
+            if (t < cnt) {
+                const int m = t % reds, rest = t / reds;
+                const int ly = rest % rows, lz = rest / rows;
+                const int yu = ys + ly, zu = zs + lz;
+                // red cells of this row sit at xs + off + 2m (parity is unchanged
+                // by the periodic wrap because nf is even)
+                const int off = (xs + yu + zu) & 1;
+                const int i = wrapi(xs + off + 2 * m, nf), j = wrapi(yu, nf), k = wrapi(zu, nf);
+                const int ih = i >> 1;
+                const int64_t o = ih + (int64_t)H * ((int64_t)j + (int64_t)nf * k);
+                xv[r] = xr[o];
+                sv[r] = nbr_sum(xb, ih, j, k, nf, 0);
+                bv[r] = br[o];
+                dst[r] = m + RRED * (ly + RWY * lz);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            if (dst[r] >= 0) (&rr[0][0][0])[dst[r]] = bv[r] - (sigma * xv[r] - c * (sv[r] - T(6) * xv[r]));
     }
     __syncthreads();
-    const int col = threadIdx.x % (RCX * RCY), half = threadIdx.x / (RCX * RCY);
+    const int col = threadIdx.x % (RCX * RCY), kk = threadIdx.x / (RCX * RCY);
     const int tx = col % RCX, ty = col / RCX;
-    if (tx >= ni || ty >= nj) return;
+    if (tx >= ni || ty >= nj || kk >= nk) return;
     const T w[4] = {T(1), T(3), T(3), T(1)};
-    for (int kk = half; kk < nk; kk += 2) {
+    {
         T acc = T(0);
         for (int cz = 0; cz < 4; ++cz) {
             const int lz = 2 * kk + cz;
@@ -359,9 +421,16 @@ k_sum_partials(const double* __restrict__ v, int64_t cs, int64_t count, int squa
     if (active && !active[comp]) return;
     const double* vc = v + comp * cs;
     double s = 0.0;
-    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < count; t += (int64_t)gridDim.x * 256) {
-        const double a = vc[t];
-        s += square ? a * a : a;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t t0 = (int64_t)blockIdx.x * 256 + threadIdx.x; t0 < count; t0 += 4 * stride) {
+        double v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t t = t0 + r * stride;
+            v[r] = t < count ? vc[t] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s += square ? v[r] * v[r] : v[r];
     }
     s = block_sum(s, red);
     if (threadIdx.x == 0) part[comp * pstride + blockIdx.x] = s;
@@ -397,7 +466,17 @@ k_finalize(const double* __restrict__ part, int64_t nparts, int64_t pstride, int
         const bool skip = (mode == FIN_CYCLE_R || mode == FIN_MEAN) && !st->active[comp];
         if (skip) continue;  // uniform across the block
         double s = 0.0;
-        for (int64_t t = threadIdx.x; t < nparts; t += blockDim.x) s += part[comp * pstride + t];
+        // loads in batches of 8, summed in index order
+        for (int64_t t0 = threadIdx.x; t0 < nparts; t0 += 8 * (int64_t)blockDim.x) {
+            double v[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int64_t t = t0 + r * (int64_t)blockDim.x;
+                v[r] = t < nparts ? part[comp * pstride + t] : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < 8; ++r) s += v[r];
+        }
         s = block_sum(s, red);
         if (threadIdx.x == 0) {
             if (mode == FIN_BNORM) {
@@ -457,14 +536,20 @@ __global__ void k_state_reset(MGState* st, int ncomp) {
 }
 
 // ---------------------------------------------------------------------------
-// all levels with n <= 16 in one workgroup, arrays in LDS (natural layout)
+// all levels with n <= 16 in one workgroup, arrays in LDS in the packed
+// red-black layout of the global arrays: a half-sweep reads the other colour
+// with unit stride across a wavefront's lanes, and loading or storing a level
+// is a straight copy.
 //
-// The level chain is a compile-time constant (16-8-4, 12-6 or 8-4), so every
-// index split is a multiply/shift.  Levels above the coarsest use all 1024
-// threads with a workgroup barrier between stages; the coarsest level (4^3 or
-// 6^3, many sweeps) runs on wavefront 0 alone: LDS operations of one wavefront
-// complete in program order, so a wavefront-scope fence between half-sweeps
-// replaces the barrier.
+// The level chain is a compile-time constant (16-8-4, 12-6 or 8-4).  Levels
+// above the coarsest use all threads with a workgroup barrier between stages;
+// the coarsest level (4^3 or 6^3, many sweeps) runs on wavefront 0 alone: LDS
+// operations of one wavefront complete in program order, so a wavefront-scope
+// fence between half-sweeps replaces the barrier.  As on the larger levels,
+// the first half-sweep from a zero guess reads no neighbours, only red
+// residuals are restricted after a pre-smoothing that ends black, and the
+// correction is prolongated to red cells only before a post-smoothing that
+// starts black.
 // ---------------------------------------------------------------------------
 
 template <typename T>
@@ -478,9 +563,10 @@ __device__ __forceinline__ int wrapc(int i) {
     return i < 0 ? i + N : (i >= N ? i - N : i);
 }
 
+// packed offset of cell (i, j, k) of a level with N cells per side
 template <int N>
-__device__ __forceinline__ int at3(int i, int j, int k) {
-    return i + N * (j + N * k);
+__device__ __forceinline__ int pkc(int i, int j, int k) {
+    return ((i + j + k) & 1) * ((N / 2) * N * N) + (i >> 1) + (N / 2) * (j + N * k);
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -488,58 +574,87 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// sum of the six neighbours (order i+1, i-1, j+1, j-1, k+1, k-1) of the
+// colour-q cell at packed position (ih, j, k), from the other colour's half xo
 template <int N, typename T>
-__device__ __forceinline__ void s_gs(T* x, const T* b, T c, T inv_diag, int colour, int t0, int nt) {
-    constexpr int HALF = N / 2, CNT = HALF * N * N;
-    for (int t = t0; t < CNT; t += nt) {
-        const int ih = t % HALF, rest = t / HALF;
+__device__ __forceinline__ T s_nbr(const T* xo, int ih, int j, int k, int q) {
+    constexpr int H = N / 2;
+    const int p = (j + k + q) & 1;
+    int ip = ih + p, im = ih + p - 1;
+    if (ip >= H) ip -= H;
+    if (im < 0) im += H;
+    const int row = H * (j + N * k);
+    return xo[row + ip] + xo[row + im] + xo[H * (wrapc<N>(j + 1) + N * k) + ih] +
+           xo[H * (wrapc<N>(j - 1) + N * k) + ih] + xo[H * (j + N * wrapc<N>(k + 1)) + ih] +
+           xo[H * (j + N * wrapc<N>(k - 1)) + ih];
+}
+
+// colour-q half-sweep over packed cells t0, t0 + nt, ...; zg: the other colour is zero
+template <int N, typename T>
+__device__ __forceinline__ void s_gs(T* x, const T* b, T c, T inv_diag, int q, int t0, int nt,
+                                     bool zg = false) {
+    constexpr int H = N / 2, HALF = H * N * N;
+    const T* xo = x + (1 - q) * HALF;
+    for (int t = t0; t < HALF; t += nt) {
+        const int ih = t % H, rest = t / H;
         const int j = rest % N, k = rest / N;
-        const int i = 2 * ih + ((j + k + colour) & 1);
-        const T s = x[at3<N>(wrapc<N>(i + 1), j, k)] + x[at3<N>(wrapc<N>(i - 1), j, k)] +
-                    x[at3<N>(i, wrapc<N>(j + 1), k)] + x[at3<N>(i, wrapc<N>(j - 1), k)] +
-                    x[at3<N>(i, j, wrapc<N>(k + 1))] + x[at3<N>(i, j, wrapc<N>(k - 1))];
-        const int o = at3<N>(i, j, k);
-        x[o] = (b[o] + c * s) * inv_diag;
+        const T s = zg ? T(0) : s_nbr<N>(xo, ih, j, k, q);
+        x[q * HALF + t] = (b[q * HALF + t] + c * s) * inv_diag;
     }
 }
 
+// residual of the colour-q cells into r
 template <int N, typename T>
-__device__ __forceinline__ void s_residual(const T* x, const T* b, T* r, T sigma, T c) {
-    constexpr int CNT = N * N * N;
-    for (int o = threadIdx.x; o < CNT; o += blockDim.x) {
-        const int i = o % N, j = (o / N) % N, k = o / (N * N);
-        const T xo = x[o];
-        const T s = x[at3<N>(wrapc<N>(i + 1), j, k)] + x[at3<N>(wrapc<N>(i - 1), j, k)] +
-                    x[at3<N>(i, wrapc<N>(j + 1), k)] + x[at3<N>(i, wrapc<N>(j - 1), k)] +
-                    x[at3<N>(i, j, wrapc<N>(k + 1))] + x[at3<N>(i, j, wrapc<N>(k - 1))];
-        const T Ax = sigma * xo - c * (s - T(6) * xo);
-        r[o] = b[o] - Ax;
+__device__ __forceinline__ void s_residual(const T* x, const T* b, T* r, T sigma, T c, int q) {
+    constexpr int H = N / 2, HALF = H * N * N;
+    const T* xo = x + (1 - q) * HALF;
+    for (int t = threadIdx.x; t < HALF; t += blockDim.x) {
+        const int ih = t % H, rest = t / H;
+        const int j = rest % N, k = rest / N;
+        const T xv = x[q * HALF + t];
+        const T s = s_nbr<N>(xo, ih, j, k, q);
+        r[q * HALF + t] = b[q * HALF + t] - (sigma * xv - c * (s - T(6) * xv));
     }
 }
 
+// coarse b (packed order) = restriction of r; red_only: black residuals are
+// zero and not read
 template <int NF, typename T>
-__device__ __forceinline__ void s_restrict(const T* r, T* bc) {
-    constexpr int NC = NF / 2, CNT = NC * NC * NC;
+__device__ __forceinline__ void s_restrict(const T* r, T* bc, bool red_only) {
+    constexpr int NC = NF / 2, HC = NC / 2, HALFC = HC * NC * NC;
     const T w[4] = {T(1), T(3), T(3), T(1)};
-    for (int o = threadIdx.x; o < CNT; o += blockDim.x) {
-        const int I = o % NC, J = (o / NC) % NC, K = o / (NC * NC);
+    for (int o = threadIdx.x; o < 2 * HALFC; o += blockDim.x) {
+        const int Q = o / HALFC, t = o - Q * HALFC;
+        const int Ih = t % HC, rest = t / HC;
+        const int J = rest % NC, K = rest / NC;
+        const int I = 2 * Ih + ((J + K + Q) & 1);
         T s = T(0);
-        for (int cz = 0; cz < 4; ++cz)
-            for (int cy = 0; cy < 4; ++cy)
-                for (int cx = 0; cx < 4; ++cx)
-                    s += w[cx] * w[cy] * w[cz] / T(512) *
-                         r[at3<NF>(wrapc<NF>(2 * I - 1 + cx), wrapc<NF>(2 * J - 1 + cy),
-                                   wrapc<NF>(2 * K - 1 + cz))];
+        for (int cz = 0; cz < 4; ++cz) {
+            const int k = wrapc<NF>(2 * K - 1 + cz);
+            for (int cy = 0; cy < 4; ++cy) {
+                const int j = wrapc<NF>(2 * J - 1 + cy);
+                for (int cx = 0; cx < 4; ++cx) {
+                    const int i = wrapc<NF>(2 * I - 1 + cx);
+                    if (red_only && ((i + j + k) & 1)) continue;
+                    s += w[cx] * w[cy] * w[cz] / T(512) * r[pkc<NF>(i, j, k)];
+                }
+            }
+        }
         bc[o] = s;
     }
 }
 
+// fine x += trilinear prolongation of xc on the red cells (red_only) or all
 template <int NF, typename T>
-__device__ __forceinline__ void s_prolong_add(T* x, const T* xc) {
-    constexpr int NC = NF / 2, CNT = NF * NF * NF;
+__device__ __forceinline__ void s_prolong_add(T* x, const T* xc, bool red_only) {
+    constexpr int NC = NF / 2, H = NF / 2, HALF = H * NF * NF;
     const T wt[2] = {T(0.75), T(0.25)};
-    for (int o = threadIdx.x; o < CNT; o += blockDim.x) {
-        const int ijk[3] = {o % NF, (o / NF) % NF, o / (NF * NF)};
+    const int cnt = red_only ? HALF : 2 * HALF;
+    for (int o = threadIdx.x; o < cnt; o += blockDim.x) {
+        const int q = o / HALF, t = o - q * HALF;
+        const int ih = t % H, rest = t / H;
+        const int j = rest % NF, k = rest / NF;
+        const int ijk[3] = {2 * ih + ((j + k + q) & 1), j, k};
         int base[3][2];
         for (int d = 0; d < 3; ++d) {
             const int I = ijk[d] >> 1;
@@ -547,10 +662,10 @@ __device__ __forceinline__ void s_prolong_add(T* x, const T* xc) {
             base[d][1] = (ijk[d] & 1) ? wrapc<NC>(I + 1) : wrapc<NC>(I - 1);
         }
         T v = T(0);
-        for (int c = 0; c < 2; ++c)
-            for (int b = 0; b < 2; ++b)
-                for (int a = 0; a < 2; ++a)
-                    v += wt[a] * wt[b] * wt[c] * xc[at3<NC>(base[0][a], base[1][b], base[2][c])];
+        for (int cz = 0; cz < 2; ++cz)
+            for (int cy = 0; cy < 2; ++cy)
+                for (int cx = 0; cx < 2; ++cx)
+                    v += wt[cx] * wt[cy] * wt[cz] * xc[pkc<NC>(base[0][cx], base[1][cy], base[2][cz])];
         x[o] += v;
     }
 }
@@ -562,18 +677,18 @@ __device__ __forceinline__ void level_coef(const SmallArgs<T>& A, T& c, T& inv_d
     inv_diag = T(1) / (A.sigma + T(6) * c);
 }
 
-// coarsest level on wavefront 0: zero (optional), sweeps, Poisson mean removal
+// coarsest level on wavefront 0 from a zero guess: sweeps, Poisson mean removal
 template <int N, typename T>
-__device__ __forceinline__ void s_coarse_wave(T* x, const T* b, const SmallArgs<T>& A, bool zero) {
+__device__ __forceinline__ void s_coarse_wave(T* x, const T* b, const SmallArgs<T>& A) {
     constexpr int CNT = N * N * N;
     const int lane = threadIdx.x;
     T c, inv_diag;
     level_coef<N>(A, c, inv_diag);
-    if (zero)
+    if (A.sweeps <= 0)
         for (int o = lane; o < CNT; o += 64) x[o] = T(0);
     wave_sync();
     for (int s = 0; s < A.sweeps; ++s) {
-        s_gs<N>(x, b, c, inv_diag, 0, lane, 64);
+        s_gs<N>(x, b, c, inv_diag, 0, lane, 64, s == 0);
         wave_sync();
         s_gs<N>(x, b, c, inv_diag, 1, lane, 64);
         wave_sync();
@@ -589,25 +704,28 @@ __device__ __forceinline__ void s_coarse_wave(T* x, const T* b, const SmallArgs<
     }
 }
 
-// one level above the coarsest: pre-smoothing, residual and restriction (down)
+// one level above the coarsest: pre-smoothing, residual and restriction
+// (down); zero: x is zero on entry (its contents are not read)
 template <int N, typename T>
 __device__ __forceinline__ void s_down(T* x, const T* b, T* r, T* bnext, const SmallArgs<T>& A, bool zero) {
     constexpr int CNT = N * N * N;
     T c, inv_diag;
     level_coef<N>(A, c, inv_diag);
-    if (zero) {
+    if (zero && A.pre <= 0) {
         for (int o = threadIdx.x; o < CNT; o += blockDim.x) x[o] = T(0);
         __syncthreads();
     }
     for (int s = 0; s < A.pre; ++s) {
-        s_gs<N>(x, b, c, inv_diag, 0, threadIdx.x, blockDim.x);
+        s_gs<N>(x, b, c, inv_diag, 0, threadIdx.x, blockDim.x, zero && s == 0);
         __syncthreads();
         s_gs<N>(x, b, c, inv_diag, 1, threadIdx.x, blockDim.x);
         __syncthreads();
     }
-    s_residual<N>(x, b, r, A.sigma, c);
+    const bool red_only = A.pre > 0;
+    s_residual<N>(x, b, r, A.sigma, c, 0);
+    if (!red_only) s_residual<N>(x, b, r, A.sigma, c, 1);
     __syncthreads();
-    s_restrict<N>(r, bnext);
+    s_restrict<N>(r, bnext, red_only);
     __syncthreads();
 }
 
@@ -616,7 +734,7 @@ template <int N, typename T>
 __device__ __forceinline__ void s_up(T* x, const T* b, const T* xc, const SmallArgs<T>& A) {
     T c, inv_diag;
     level_coef<N>(A, c, inv_diag);
-    s_prolong_add<N>(x, xc);
+    s_prolong_add<N>(x, xc, A.post > 0);
     __syncthreads();
     for (int s = 0; s < A.post; ++s) {
         s_gs<N>(x, b, c, inv_diag, 1, threadIdx.x, blockDim.x);
@@ -627,7 +745,7 @@ __device__ __forceinline__ void s_up(T* x, const T* b, const T* xc, const SmallA
 }
 
 // One V-cycle over the levels N0 (, N0/2, ...) down to the coarsest (< 8).
-// Global arrays are packed; LDS holds [x, b, r] per level in natural order.
+// LDS holds [x, b, r] per level, packed like the global arrays.
 template <int N0, typename T>
 __global__ void __launch_bounds__(kSmallThreads)
 k_small_vcycle(T* __restrict__ xg, const T* __restrict__ bg, int64_t cs, SmallArgs<T> A,
@@ -644,33 +762,46 @@ k_small_vcycle(T* __restrict__ xg, const T* __restrict__ bg, int64_t cs, SmallAr
     T* x1 = r0 + C0;
     T* b1 = x1 + C1;
     T* r1 = b1 + C1;
-    for (int o = threadIdx.x; o < C0; o += blockDim.x) {
-        const int i = o % N0, j = (o / N0) % N0, k = o / (N0 * N0);
-        const int64_t g = comp * cs + pk(i, j, k, N0);
-        b0[o] = bg[g];
-        x0[o] = A.zero_init ? T(0) : xg[g];
+    {
+        // all of a thread's loads are issued before the first LDS store
+        constexpr int R = (C0 + kSmallThreads - 1) / kSmallThreads;
+        const bool load_x = !A.zero_init;
+        T bv[R], xv[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int o = threadIdx.x + r * kSmallThreads;
+            if (o < C0) {
+                bv[r] = bg[comp * cs + o];
+                if (load_x) xv[r] = xg[comp * cs + o];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int o = threadIdx.x + r * kSmallThreads;
+            if (o < C0) {
+                b0[o] = bv[r];
+                if (load_x) x0[o] = xv[r];
+            }
+        }
     }
     __syncthreads();
-    s_down<N0>(x0, b0, r0, b1, A, false);
+    s_down<N0>(x0, b0, r0, b1, A, A.zero_init != 0);
     if constexpr (N1 >= 8) {
         constexpr int N2 = N1 / 2;
         constexpr int C2 = N2 * N2 * N2;
         T* x2 = r1 + C1;
         T* b2 = x2 + C2;
         s_down<N1>(x1, b1, r1, b2, A, true);
-        if (threadIdx.x < 64) s_coarse_wave<N2>(x2, b2, A, true);
+        if (threadIdx.x < 64) s_coarse_wave<N2>(x2, b2, A);
         __syncthreads();
         s_up<N1>(x1, b1, x2, A);
     } else {
         (void)r1;
-        if (threadIdx.x < 64) s_coarse_wave<N1>(x1, b1, A, true);
+        if (threadIdx.x < 64) s_coarse_wave<N1>(x1, b1, A);
         __syncthreads();
     }
     s_up<N0>(x0, b0, x1, A);
-    for (int o = threadIdx.x; o < C0; o += blockDim.x) {
-        const int i = o % N0, j = (o / N0) % N0, k = o / (N0 * N0);
-        xg[comp * cs + pk(i, j, k, N0)] = x0[o];
-    }
+    for (int o = threadIdx.x; o < C0; o += blockDim.x) xg[comp * cs + o] = x0[o];
 }
 
 // ---------------------------------------------------------------------------
@@ -697,7 +828,7 @@ constexpr int KB = 8;                                 // owned cells per axis
 constexpr int KDH = 5, KUH = 4;                       // halos of the down / up kernels
 constexpr int KDE = KB + 2 * KDH, KUE = KB + 2 * KUH; // LDS box sides (18, 16)
 constexpr int KW = KB + 2;                            // restriction window side
-constexpr int KTHREADS = 256;
+constexpr int KTHREADS = 512;
 
 template <int E>
 __device__ __forceinline__ int lix(int a, int b, int c) { return a + E * (b + E * c); }
@@ -707,24 +838,38 @@ __device__ __forceinline__ int64_t pkw(int gi, int gj, int gk, int n) {
     return pk(wrapi(gi, n), wrapi(gj, n), wrapi(gk, n), n);
 }
 
-// Colour-q cells of the box reaching d cells beyond the owned block (local
+// Colour-q cells of the box reaching D cells beyond the owned block (local
 // origin: global cell (g0x, g0y, g0z) at LDS index 0, block at HH):
-// x = (b + c * neighbour sum) * inv_diag; zg: neighbours are zero.
-template <int E, int HH, typename T>
+// x = (b + c * neighbour sum) * inv_diag; zg: neighbours are zero.  Each
+// thread first loads b for all its cells (all loads in flight), then updates.
+template <int E, int HH, int D, typename T>
 __device__ __forceinline__ void box_gs(T* xs, const T* __restrict__ bg, int n, int g0x, int g0y,
-                                       int g0z, int d, int q, T c, T inv_diag, bool zg) {
-    const int lo = HH - d, S = KB + 2 * d, S2 = S / 2;
-    const int cnt = S2 * S * S;
-    for (int u = threadIdx.x; u < cnt; u += KTHREADS) {
-        const int ah = u % S2, rest = u / S2;
-        const int lb = lo + rest % S, lc = lo + rest / S;
-        const int la = lo + 2 * ah + ((q + g0x + lo + g0y + lb + g0z + lc) & 1);
-        const int o = lix<E>(la, lb, lc);
-        const T bv = bg[pkw(g0x + la, g0y + lb, g0z + lc, n)];
-        T sum = T(0);
-        if (!zg)
-            sum = xs[o + 1] + xs[o - 1] + xs[o + E] + xs[o - E] + xs[o + E * E] + xs[o - E * E];
-        xs[o] = (bv + c * sum) * inv_diag;
+                                       int g0z, int q, T c, T inv_diag, bool zg) {
+    constexpr int lo = HH - D, S = KB + 2 * D, S2 = S / 2;
+    constexpr int cnt = S2 * S * S, R = (cnt + KTHREADS - 1) / KTHREADS;
+    T bv[R];
+    int oo[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int u = threadIdx.x + r * KTHREADS;
+        oo[r] = -1;
+        if (u < cnt) {
+            const int ah = u % S2, rest = u / S2;
+            const int lb = lo + rest % S, lc = lo + rest / S;
+            const int la = lo + 2 * ah + ((q + g0x + lo + g0y + lb + g0z + lc) & 1);
+            oo[r] = lix<E>(la, lb, lc);
+            bv[r] = bg[pkw(g0x + la, g0y + lb, g0z + lc, n)];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int o = oo[r];
+        if (o >= 0) {
+            T sum = T(0);
+            if (!zg)
+                sum = xs[o + 1] + xs[o - 1] + xs[o + E] + xs[o - E] + xs[o + E * E] + xs[o - E * E];
+            xs[o] = (bv[r] + c * sum) * inv_diag;
+        }
     }
 }
 
@@ -748,26 +893,47 @@ k_level_down(const T* __restrict__ b, T* __restrict__ xpre, int n, int64_t cs, T
     if (!active[comp]) return;
     const int g0x = i0 - KDH, g0y = j0 - KDH, g0z = k0 - KDH;
     const T* bcp = b + comp * cs;
-    box_gs<KDE, KDH>(xs, bcp, n, g0x, g0y, g0z, 5, 0, c, inv_diag, true);
+    box_gs<KDE, KDH, 5>(xs, bcp, n, g0x, g0y, g0z, 0, c, inv_diag, true);
     __syncthreads();
-    box_gs<KDE, KDH>(xs, bcp, n, g0x, g0y, g0z, 4, 1, c, inv_diag, false);
+    box_gs<KDE, KDH, 4>(xs, bcp, n, g0x, g0y, g0z, 1, c, inv_diag, false);
     __syncthreads();
-    box_gs<KDE, KDH>(xs, bcp, n, g0x, g0y, g0z, 3, 0, c, inv_diag, false);
+    box_gs<KDE, KDH, 3>(xs, bcp, n, g0x, g0y, g0z, 0, c, inv_diag, false);
     __syncthreads();
-    box_gs<KDE, KDH>(xs, bcp, n, g0x, g0y, g0z, 2, 1, c, inv_diag, false);
+    box_gs<KDE, KDH, 2>(xs, bcp, n, g0x, g0y, g0z, 1, c, inv_diag, false);
     __syncthreads();
     // red residuals on the window, black entries zero
-    for (int u = threadIdx.x; u < KW * KW * KW; u += KTHREADS) {
-        const int la = KDH - 1 + u % KW, lb = KDH - 1 + (u / KW) % KW, lc = KDH - 1 + u / (KW * KW);
-        T r = T(0);
-        if (((g0x + la + g0y + lb + g0z + lc) & 1) == 0) {
-            const int o = lix<KDE>(la, lb, lc);
-            const T xo = xs[o];
-            const T sum = xs[o + 1] + xs[o - 1] + xs[o + KDE] + xs[o - KDE] + xs[o + KDE * KDE] +
-                          xs[o - KDE * KDE];
-            r = bcp[pkw(g0x + la, g0y + lb, g0z + lc, n)] - (sigma * xo - c * (sum - T(6) * xo));
+    {
+        constexpr int CW = KW * KW * KW, R = (CW + KTHREADS - 1) / KTHREADS;
+        T bv[R];
+        int oo[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int u = threadIdx.x + r * KTHREADS;
+            oo[r] = -1;
+            bv[r] = T(0);
+            if (u < CW) {
+                const int la = KDH - 1 + u % KW, lb = KDH - 1 + (u / KW) % KW, lc = KDH - 1 + u / (KW * KW);
+                if (((g0x + la + g0y + lb + g0z + lc) & 1) == 0) {
+                    oo[r] = lix<KDE>(la, lb, lc);
+                    bv[r] = bcp[pkw(g0x + la, g0y + lb, g0z + lc, n)];
+                }
+            }
         }
-        rw[u] = r;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int u = threadIdx.x + r * KTHREADS;
+            if (u < CW) {
+                T res = T(0);
+                const int o = oo[r];
+                if (o >= 0) {
+                    const T xo = xs[o];
+                    const T sum = xs[o + 1] + xs[o - 1] + xs[o + KDE] + xs[o - KDE] + xs[o + KDE * KDE] +
+                                  xs[o - KDE * KDE];
+                    res = bv[r] - (sigma * xo - c * (sum - T(6) * xo));
+                }
+                rw[u] = res;
+            }
+        }
     }
     // the block's smoothed x
     T* xp = xpre + comp * cs;
@@ -805,35 +971,57 @@ k_level_up(const T* __restrict__ b, const T* __restrict__ xpre, const T* __restr
     const T* xcc = xc + comp * ccs;
     // red cells of the whole box: smoothed x plus the trilinear correction
     {
-        constexpr int S = KUE, S2 = S / 2;
+        constexpr int S = KUE, S2 = S / 2, CNT = S2 * S * S;
         const T wt[2] = {T(0.75), T(0.25)};
-        for (int u = threadIdx.x; u < S2 * S * S; u += KTHREADS) {
-            const int ah = u % S2, rest = u / S2;
-            const int lb = rest % S, lc = rest / S;
-            const int la = 2 * ah + ((g0x + g0y + lb + g0z + lc) & 1);
-            const int ijk[3] = {wrapi(g0x + la, n), wrapi(g0y + lb, n), wrapi(g0z + lc, n)};
-            int base[3][2];
-            for (int d = 0; d < 3; ++d) {
-                const int I = ijk[d] >> 1;
-                base[d][0] = I;
-                base[d][1] = (ijk[d] & 1) ? wrapi(I + 1, nc) : wrapi(I - 1, nc);
+        // two passes of half the cells each keep the loads of a pass in flight
+        for (int pass = 0; pass < 2; ++pass) {
+            constexpr int R = (CNT / 2 + KTHREADS - 1) / KTHREADS;
+            T cv[R][8], xv[R];
+            int oo[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int u = pass * (CNT / 2) + threadIdx.x + r * KTHREADS;
+                oo[r] = -1;
+                if (u < (pass + 1) * (CNT / 2)) {
+                    const int ah = u % S2, rest = u / S2;
+                    const int lb = rest % S, lc = rest / S;
+                    const int la = 2 * ah + ((g0x + g0y + lb + g0z + lc) & 1);
+                    const int ijk[3] = {wrapi(g0x + la, n), wrapi(g0y + lb, n), wrapi(g0z + lc, n)};
+                    int base[3][2];
+                    for (int d = 0; d < 3; ++d) {
+                        const int I = ijk[d] >> 1;
+                        base[d][0] = I;
+                        base[d][1] = (ijk[d] & 1) ? wrapi(I + 1, nc) : wrapi(I - 1, nc);
+                    }
+                    for (int cz = 0; cz < 2; ++cz)
+                        for (int cy = 0; cy < 2; ++cy)
+                            for (int cx = 0; cx < 2; ++cx)
+                                cv[r][cx + 2 * (cy + 2 * cz)] = xcc[pk(base[0][cx], base[1][cy], base[2][cz], nc)];
+                    xv[r] = xpp[pk(ijk[0], ijk[1], ijk[2], n)];
+                    oo[r] = lix<KUE>(la, lb, lc);
+                }
             }
-            T v = T(0);
-            for (int cz = 0; cz < 2; ++cz)
-                for (int cy = 0; cy < 2; ++cy)
-                    for (int cx = 0; cx < 2; ++cx)
-                        v += wt[cx] * wt[cy] * wt[cz] * xcc[pk(base[0][cx], base[1][cy], base[2][cz], nc)];
-            xs[lix<KUE>(la, lb, lc)] = xpp[pk(ijk[0], ijk[1], ijk[2], n)] + v;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (oo[r] >= 0) {
+                    T v = T(0);
+                    for (int cz = 0; cz < 2; ++cz)
+                        for (int cy = 0; cy < 2; ++cy)
+                            for (int cx = 0; cx < 2; ++cx)
+                                v += wt[cx] * wt[cy] * wt[cz] * cv[r][cx + 2 * (cy + 2 * cz)];
+                    xs[oo[r]] = xv[r] + v;
+                }
+            }
         }
     }
     __syncthreads();
-    box_gs<KUE, KUH>(xs, bcp, n, g0x, g0y, g0z, 3, 1, c, inv_diag, false);
+    box_gs<KUE, KUH, 3>(xs, bcp, n, g0x, g0y, g0z, 1, c, inv_diag, false);
     __syncthreads();
-    box_gs<KUE, KUH>(xs, bcp, n, g0x, g0y, g0z, 2, 0, c, inv_diag, false);
+    box_gs<KUE, KUH, 2>(xs, bcp, n, g0x, g0y, g0z, 0, c, inv_diag, false);
     __syncthreads();
-    box_gs<KUE, KUH>(xs, bcp, n, g0x, g0y, g0z, 1, 1, c, inv_diag, false);
+    box_gs<KUE, KUH, 1>(xs, bcp, n, g0x, g0y, g0z, 1, c, inv_diag, false);
     __syncthreads();
-    box_gs<KUE, KUH>(xs, bcp, n, g0x, g0y, g0z, 0, 0, c, inv_diag, false);
+    box_gs<KUE, KUH, 0>(xs, bcp, n, g0x, g0y, g0z, 0, c, inv_diag, false);
     __syncthreads();
     T* xo = x + comp * cs;
     for (int u = threadIdx.x; u < KB * KB * KB; u += KTHREADS) {
@@ -923,7 +1111,10 @@ hipib_status small_vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const
     return HIPIB_OK;
 }
 
-// levels run as one k_level_down / k_level_up pair per V-cycle
+// levels run as one k_level_down / k_level_up pair per V-cycle: the levels
+// below the finest and above the single-workgroup ones with n a multiple of
+// 8, for V(2,2) (there the guess is always zero).  On the finest level the
+// blocks' recomputed halos cost more than the launches they save.
 bool level_fused(const hipib_ctx* ctx, int l) {
     return l >= 1 && l < ctx->small_start && ctx->lv[l].n % KB == 0 && ctx->lv[l].x2 != nullptr &&
            ctx->cfg.mg_pre == 2 && ctx->cfg.mg_post == 2;
@@ -934,7 +1125,7 @@ hipib_status gs_sweep(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpC
                       T inv_diag, int colour, int zg) {
     const int n = ctx->lv[l].n;
     const int32_t* act = ctx->st->active;
-    const dim3 grid = colour_grid(n, ncomp), blk(TX, TY);
+    const dim3 grid = gs_grid(n, ncomp), blk(TX, TY);
     hipEvent_t t0, t1;
     if (l > 0) {
         k_gs<T, 0><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, colour, zg, act);
@@ -992,8 +1183,8 @@ hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
         T* x2 = static_cast<T*>(ctx->lv[l].x2);
         const int nb = n / KB;
         const unsigned blocks = (unsigned)(nb * nb * nb * ncomp);
-        k_level_down<T><<<blocks, KTHREADS, 0, ctx->stream>>>(p.b, x2, n, p.cs, bc, C.n3,
-                                                              (T)oc.sigma, c, inv_diag, act);
+        k_level_down<T><<<blocks, KTHREADS, 0, ctx->stream>>>(p.b, x2, n, p.cs, bc, C.n3, (T)oc.sigma,
+                                                              c, inv_diag, act);
         HIPIB_HIP(hipGetLastError());
         HIPIB_TRY(vcycle<T>(ctx, l + 1, LevelPtr<T>{xc, bc, C.n3}, ncomp, oc, true));
         k_level_up<T><<<blocks, KTHREADS, 0, ctx->stream>>>(p.b, x2, xc, p.x, n, p.cs, C.n3, c,
