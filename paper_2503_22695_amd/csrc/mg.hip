@@ -87,8 +87,6 @@ __device__ __forceinline__ uint3 xcd_block() {
     return make_uint3(b % gx, (b / gx) % gy, b / (gx * gy));
 }
 
-// grid of a half-sweep: (packed x tiles, y tiles, z columns of KPT cells * ncomp)
-dim3 gs_grid(int n, int ncomp);
 // grid for both colours: z = (comp * 2 + q) * n + k
 dim3 packed_grid(int n, int ncomp) {
     return dim3((n / 2 + TX - 1) / TX, (n + TY - 1) / TY, 2 * n * ncomp);
@@ -123,7 +121,7 @@ k_unpack(const double* __restrict__ src, double* __restrict__ dst, int n, int64_
 // ---------------------------------------------------------------------------
 
 // One colour q of red-black Gauss-Seidel: x_q = (b_q + c * sum_nbr x) / diag.
-// Each thread updates a column of KPT cells along z: the other colour's
+// Each thread updates a column of KPT = gs_kpt<T>() cells along z: the other colour's
 // values at (ih, j) on planes k0-1 .. k0+KPT serve as the z-neighbours of the
 // column and as one of each cell's two x-neighbours, and all of the thread's
 // loads are issued before the first update.  Neighbours are summed in the
@@ -132,16 +130,25 @@ k_unpack(const double* __restrict__ src, double* __restrict__ dst, int n, int64_
 // guess), so its neighbours are not read; the result is the same to the bit.
 // TAG only separates launches in profiles: 0 coarse levels, 1 finest level of
 // a Helmholtz solve, 2 finest level of a Poisson solve.
-constexpr int KPT = 4;
+constexpr int KPT = 4;  // column length of the residual norm
 
+// column length of a half-sweep: 2 cells in FP64, 4 in FP32 (measured best
+// on the 128^3 workload)
+template <typename T>
+constexpr int gs_kpt() { return sizeof(T) == 8 ? 2 : 4; }
+
+// grid of a half-sweep: (packed x tiles, y tiles, z columns * ncomp)
+template <typename T>
 dim3 gs_grid(int n, int ncomp) {
-    return dim3((n / 2 + TX - 1) / TX, (n + TY - 1) / TY, ((n + KPT - 1) / KPT) * ncomp);
+    constexpr int K = gs_kpt<T>();
+    return dim3((n / 2 + TX - 1) / TX, (n + TY - 1) / TY, ((n + K - 1) / K) * ncomp);
 }
 
 template <typename T, int TAG>
 __global__ void __launch_bounds__(TX * TY)
 k_gs(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, T c, T inv_diag, int q,
      int zg, const int32_t* __restrict__ active) {
+    constexpr int KPT = gs_kpt<T>();
     const uint3 bid = xcd_block();
     const int nkb = (n + KPT - 1) / KPT;
     const int comp = bid.z / nkb, k0 = (bid.z - comp * nkb) * KPT;
@@ -369,26 +376,62 @@ __global__ void k_zero_t(T* __restrict__ p, int64_t count) {
 // FP64 outer loop: residual norm (and FP32 scaled residual), update, means
 // ---------------------------------------------------------------------------
 
-// sum of r^2 per block; TO32: also r32 = (float)(r / ||b||)
+// sum of r^2 per block; TO32: also r32 = (float)(r / ||b||).  Grid: (packed
+// x tiles, y tiles, (comp * 2 + q) * z-columns); each thread takes a column of
+// KPT cells of colour q along z with the loads of k_gs.
 template <bool TO32>
 __global__ void __launch_bounds__(TX * TY)
 k_resid_norm(const double* __restrict__ x, const double* __restrict__ b, int n, int64_t cs,
              double sigma, double c, const MGState* __restrict__ st, float* __restrict__ r32,
              double* __restrict__ part, int64_t pstride) {
     __shared__ double red[16];
-    const int z = blockIdx.z, comp = z / (2 * n), rem = z - comp * 2 * n, q = rem / n, k = rem - q * n;
+    const int nkb = (n + KPT - 1) / KPT;
+    const int z = blockIdx.z, comp = z / (2 * nkb), rem = z - comp * 2 * nkb, q = rem / nkb;
+    const int k0 = (rem - q * nkb) * KPT;
     if (!st->active[comp]) return;  // block-uniform
     const int H = n >> 1;
     const int ih = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y;
     double v = 0.0;
     if (ih < H && j < n) {
         const int64_t half3 = (int64_t)H * n * n;
-        const int64_t o = comp * cs + q * half3 + ih + (int64_t)H * ((int64_t)j + (int64_t)n * k);
-        const double xo = x[o];
-        const double s = nbr_sum(x + comp * cs + (1 - q) * half3, ih, j, k, n, q);
-        const double r = b[o] - (sigma * xo - c * (s - 6.0 * xo));
-        v = r * r;
-        if (TO32) r32[o] = (float)(r * (1.0 / st->bn[comp]));
+        const double* xq = x + comp * cs + q * half3;
+        const double* xo = x + comp * cs + (1 - q) * half3;
+        const double* bq = b + comp * cs + q * half3;
+        const int jp = wrapi(j + 1, n), jm = wrapi(j - 1, n);
+        const int ihp = ih + 1 < H ? ih + 1 : 0, ihm = ih > 0 ? ih - 1 : H - 1;
+        double col[KPT + 2], side[KPT], yp[KPT], ym[KPT], bv[KPT], xv[KPT];
+#pragma unroll
+        for (int r = 0; r < KPT + 2; ++r)
+            col[r] = xo[ih + (int64_t)H * ((int64_t)j + (int64_t)n * wrapi(k0 - 1 + r, n))];
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) {
+            const int k = k0 + r;
+            if (k < n) {
+                const int64_t row = (int64_t)H * ((int64_t)j + (int64_t)n * k);
+                const int p = (j + k + q) & 1;
+                bv[r] = bq[row + ih];
+                xv[r] = xq[row + ih];
+                side[r] = xo[row + (p ? ihp : ihm)];
+                yp[r] = xo[(int64_t)H * ((int64_t)jp + (int64_t)n * k) + ih];
+                ym[r] = xo[(int64_t)H * ((int64_t)jm + (int64_t)n * k) + ih];
+            }
+        }
+        const double inv_bn = TO32 ? 1.0 / st->bn[comp] : 0.0;
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) {
+            const int k = k0 + r;
+            if (k < n) {
+                const int p = (j + k + q) & 1;
+                const double a_ip = p ? side[r] : col[r + 1];
+                const double a_im = p ? col[r + 1] : side[r];
+                const double s = a_ip + a_im + yp[r] + ym[r] + col[r + 2] + col[r];
+                const double rr = bv[r] - (sigma * xv[r] - c * (s - 6.0 * xv[r]));
+                v += rr * rr;
+                if (TO32)
+                    r32[comp * cs + q * half3 + (int64_t)H * ((int64_t)j + (int64_t)n * k) + ih] =
+                        (float)(rr * inv_bn);
+            }
+        }
     }
     const int tid = threadIdx.x + TX * threadIdx.y;
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -1035,7 +1078,11 @@ k_level_up(const T* __restrict__ b, const T* __restrict__ xpre, const T* __restr
 // ---------------------------------------------------------------------------
 
 int64_t norm_parts(int n) {
-    return (int64_t)((n / 2 + TX - 1) / TX) * ((n + TY - 1) / TY) * 2 * n;
+    return (int64_t)((n / 2 + TX - 1) / TX) * ((n + TY - 1) / TY) * 2 * ((n + KPT - 1) / KPT);
+}
+
+dim3 norm_grid(int n, int ncomp) {
+    return dim3((n / 2 + TX - 1) / TX, (n + TY - 1) / TY, 2 * ((n + KPT - 1) / KPT) * ncomp);
 }
 
 int sum_blocks(int64_t count) {
@@ -1125,7 +1172,7 @@ hipib_status gs_sweep(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpC
                       T inv_diag, int colour, int zg) {
     const int n = ctx->lv[l].n;
     const int32_t* act = ctx->st->active;
-    const dim3 grid = gs_grid(n, ncomp), blk(TX, TY);
+    const dim3 grid = gs_grid<T>(n, ncomp), blk(TX, TY);
     hipEvent_t t0, t1;
     if (l > 0) {
         k_gs<T, 0><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, colour, zg, act);
@@ -1224,10 +1271,10 @@ hipib_status resid_norm(hipib_ctx* ctx, int ncomp, const OpCoef& oc, int mode) {
     const double h = 1.0 / n, c = oc.nu / (h * h);
     const int64_t np = norm_parts(n);
     if (ctx->cfg.precision == HIPIB_MIXED)
-        k_resid_norm<true><<<packed_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(
+        k_resid_norm<true><<<norm_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(
             ctx->xp, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, ctx->r32, ctx->part, np);
     else
-        k_resid_norm<false><<<packed_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(
+        k_resid_norm<false><<<norm_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(
             ctx->xp, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, nullptr, ctx->part, np);
     HIPIB_HIP(hipGetLastError());
     return finalize(ctx, np, np, ncomp, mode, 0.0);

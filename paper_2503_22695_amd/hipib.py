@@ -341,10 +341,18 @@ class Rollout:
     as inputs; the backward pass runs the discrete adjoint, recomputing each
     segment of `checkpoint_every` steps from a stored (u, p, X) checkpoint."""
 
-    def __init__(self, prob, n_steps=None, checkpoint_every=10, mat=0, t0=0.0, **cfg_over):
+    def __init__(self, prob, n_steps=None, checkpoint_every=10, mat=0, t0=0.0, overlap=True,
+                 **cfg_over):
         import torch
         self.prob = prob
+        self.cfg_over = cfg_over
         self.ctx = context_for_problem(prob, **cfg_over)
+        # overlap: the backward pass recomputes the next segment on a second
+        # context and stream, from a worker thread, while the current segment's
+        # adjoint steps run (both are latency-bound at moderate grid sizes)
+        self.overlap = overlap
+        self._rctx = None
+        self._rstream = None
         self.n_steps = prob.n_steps if n_steps is None else int(n_steps)
         self.k = max(1, int(checkpoint_every))
         self.mat = mat
@@ -367,6 +375,7 @@ class Rollout:
 
     def set_theta(self, theta):
         th = [float(v) for v in theta.detach().cpu().reshape(-1)]
+        self._theta = th
         self.ctx.set_material(self.mat, HOLZAPFEL_OGDEN, th[:4] + [self.kappa])
 
     def forward(self, theta, X0, keep_checkpoints=True):
@@ -396,31 +405,66 @@ class Rollout:
 
     def _run_segment(self, u, p, X, s0, m):
         """m steps from (u, p, X) at step s0 (not modified); every u and X."""
-        us, Xs = [u.clone()], [X.clone()]
-        u, p, X = u.clone(), p.clone(), X.clone()
-        for i in range(m):
-            self.ctx.ib_step(u, p, X, self.pressure(s0, i))
-            us.append(u.clone())
-            Xs.append(X.clone())
-        return us, Xs
+        return self._run_segment_on(self.ctx, u, p, X, s0, m)
 
     def _reverse_segment(self, s0, us, Xs, lam_u, lam_X, dtheta):
         for i in range(len(us) - 2, -1, -1):
             self.ctx.adjoint_step(us[i], Xs[i], us[i + 1], self.pressure(s0, i), lam_u, lam_X, dtheta)
+
+    def _recompute(self, seg):
+        """Worker-thread body: the segment's states on the second context."""
+        import torch
+        s0, uc, pc, Xc = seg
+        with torch.cuda.stream(self._rstream):
+            self._rstream.wait_stream(self._main_stream)   # checkpoints are written on the main stream
+            out = self._run_segment_on(self._rctx, uc, pc, Xc, s0, min(self.k, self.n_steps - s0))
+        self._rstream.synchronize()
+        return out
+
+    def _run_segment_on(self, ctx, u, p, X, s0, m):
+        us, Xs = [u.clone()], [X.clone()]
+        u, p, X = u.clone(), p.clone(), X.clone()
+        for i in range(m):
+            ctx.ib_step(u, p, X, self.pressure(s0, i))
+            us.append(u.clone())
+            Xs.append(X.clone())
+        return us, Xs
 
     def backward(self, grad_XN):
         import torch
         lam_X = grad_XN.detach().to(self.dev, torch.float64).contiguous().clone()
         lam_u = torch.zeros_like(self.u0)
         dtheta = torch.zeros((MAX_MATERIALS, 4), dtype=torch.float64, device=self.dev)
-        if self.tail is not None:
-            s0, (us, Xs) = self.tail
-            self._reverse_segment(s0, us, Xs, lam_u, lam_X, dtheta)
-            self.tail = None
-        for (s0, uc, pc, Xc) in reversed(self.checkpoints):
-            m = min(self.k, self.n_steps - s0)
-            us, Xs = self._run_segment(uc, pc, Xc, s0, m)
-            self._reverse_segment(s0, us, Xs, lam_u, lam_X, dtheta)
+        segs = list(reversed(self.checkpoints))
+        pending = None
+        if self.overlap and segs:
+            from concurrent.futures import ThreadPoolExecutor
+            self._main_stream = torch.cuda.current_stream()
+            if self._rctx is None:
+                self._rstream = torch.cuda.Stream()          # default priority
+                with torch.cuda.stream(self._rstream):
+                    self._rctx = context_for_problem(self.prob, **self.cfg_over)
+            th = self._theta
+            self._rctx.set_material(self.mat, HOLZAPFEL_OGDEN, th[:4] + [self.kappa])
+            pool = ThreadPoolExecutor(max_workers=1)
+            pending = pool.submit(self._recompute, segs[0])
+        try:
+            if self.tail is not None:
+                s0, (us, Xs) = self.tail
+                self._reverse_segment(s0, us, Xs, lam_u, lam_X, dtheta)
+                self.tail = None
+            for idx, (s0, uc, pc, Xc) in enumerate(segs):
+                if pending is not None:
+                    us, Xs = pending.result()
+                    pending = pool.submit(self._recompute, segs[idx + 1]) if idx + 1 < len(segs) else None
+                else:
+                    us, Xs = self._run_segment(uc, pc, Xc, s0, min(self.k, self.n_steps - s0))
+                self._reverse_segment(s0, us, Xs, lam_u, lam_X, dtheta)
+        finally:
+            if self.overlap and segs:
+                if pending is not None:
+                    pending.result()
+                pool.shutdown(wait=True)
         return dtheta[self.mat].clone(), lam_X, lam_u
 
 
