@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(128)
 k_fe_hvp(const double* __restrict__ X, const double* __restrict__ Xref,
          const int32_t* __restrict__ conn, const double* __restrict__ fibre,
          const int32_t* __restrict__ mat_id, MatTable mats, int ne, const double* __restrict__ V,
-         double* __restrict__ out, MGState* st) {
+         double* __restrict__ out, MGState* st, double* __restrict__ contrib) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
     int nd[8];
@@ -182,6 +182,11 @@ k_fe_hvp(const double* __restrict__ X, const double* __restrict__ Xref,
                 he[a][r] -= Q[3 * r] * dN[a][0] + Q[3 * r + 1] * dN[a][1] + Q[3 * r + 2] * dN[a][2];
     }
     if (bad) atomicOr(&st->numeric, 1);
+    if (contrib) {  // deterministic mode: gathered per node in element order
+        for (int a = 0; a < 8; ++a)
+            for (int r = 0; r < 3; ++r) contrib[24 * (int64_t)e + 3 * a + r] = he[a][r];
+        return;
+    }
     for (int a = 0; a < 8; ++a)
         for (int r = 0; r < 3; ++r) atomicAdd(out + 3 * nd[a] + r, he[a][r]);
 }
@@ -190,16 +195,21 @@ k_fe_hvp(const double* __restrict__ X, const double* __restrict__ Xref,
 // Holzapfel-Ogden parameters (a, b, a_f, b_f):
 //   dP/da   = e^{b(I1bar-3)} J^{-2/3}(F - I1/3 F^{-T}),   dP/db = a (I1bar-3) dP/da,
 //   dP/da_f = 2 (I4-1) e^{b_f (I4-1)^2} (F e)(x)e,        dP/db_f = a_f (I4-1)^2 dP/da_f
-// Per-block sums in LDS, then one global atomic per block and entry.
+// Per-block sums in LDS, then one global atomic per block and entry; in
+// deterministic mode (part != null) the per-element terms go to part[e][4]
+// for a fixed-order reduction.
 __global__ void __launch_bounds__(128)
 k_fe_param_vjp(const double* __restrict__ X, const double* __restrict__ Xref,
                const int32_t* __restrict__ conn, const double* __restrict__ fibre,
                const int32_t* __restrict__ mat_id, MatTable mats, int ne,
-               const double* __restrict__ lam, double* __restrict__ dtheta) {
+               const double* __restrict__ lam, double* __restrict__ dtheta,
+               double* __restrict__ part) {
     __shared__ double acc[HIPIB_MAX_MATERIALS * 4];
     for (int t = threadIdx.x; t < HIPIB_MAX_MATERIALS * 4; t += blockDim.x) acc[t] = 0.0;
     __syncthreads();
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < ne && part)
+        for (int k = 0; k < 4; ++k) part[4 * (int64_t)e + k] = 0.0;
     if (e < ne) {
         const int m = mat_id[e];
         if (mats.model[m] == HIPIB_HOLZAPFEL_OGDEN) {
@@ -259,13 +269,21 @@ k_fe_param_vjp(const double* __restrict__ X, const double* __restrict__ Xref,
                     d3 -= w * 2.0 * par[2] * q * q * q * Ef * Mfib;
                 }
             }
-            atomicAdd(&acc[4 * m + 0], d0);
-            atomicAdd(&acc[4 * m + 1], d1);
-            atomicAdd(&acc[4 * m + 2], d2);
-            atomicAdd(&acc[4 * m + 3], d3);
+            if (part) {
+                part[4 * (int64_t)e + 0] = d0;
+                part[4 * (int64_t)e + 1] = d1;
+                part[4 * (int64_t)e + 2] = d2;
+                part[4 * (int64_t)e + 3] = d3;
+            } else {
+                atomicAdd(&acc[4 * m + 0], d0);
+                atomicAdd(&acc[4 * m + 1], d1);
+                atomicAdd(&acc[4 * m + 2], d2);
+                atomicAdd(&acc[4 * m + 3], d3);
+            }
         }
     }
     __syncthreads();
+    if (part) return;
     for (int t = threadIdx.x; t < HIPIB_MAX_MATERIALS * 4; t += blockDim.x)
         if (acc[t] != 0.0) atomicAdd(dtheta + t, acc[t]);
 }
@@ -273,7 +291,7 @@ k_fe_param_vjp(const double* __restrict__ X, const double* __restrict__ Xref,
 // lamX_b += -p sum_g [dN_b/dxi (x_eta x mu) + dN_b/deta (mu x x_xi)], mu = sum_a N_a lamF_a
 __global__ void __launch_bounds__(256)
 k_pressure_vjp(const double* __restrict__ X, const int32_t* __restrict__ faces, int nf, double p,
-               const double* __restrict__ lamF, double* __restrict__ lamX) {
+               const double* __restrict__ lamF, double* __restrict__ lamX, double* __restrict__ contrib) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nf) return;
     int nd[4];
@@ -309,6 +327,11 @@ k_pressure_vjp(const double* __restrict__ X, const int32_t* __restrict__ faces, 
                              mu[0] * xs[1] - mu[1] * xs[0]};
         for (int b = 0; b < 4; ++b)
             for (int r = 0; r < 3; ++r) out[b][r] -= p * (dS[b] * A[r] + dT[b] * B[r]);
+    }
+    if (contrib) {  // deterministic mode: gathered per node in face order
+        for (int a = 0; a < 4; ++a)
+            for (int r = 0; r < 3; ++r) contrib[12 * (int64_t)f + 3 * a + r] = out[a][r];
+        return;
     }
     for (int a = 0; a < 4; ++a)
         for (int r = 0; r < 3; ++r) atomicAdd(lamX + 3 * nd[a] + r, out[a][r]);
@@ -383,6 +406,7 @@ hipib_status ensure_adjoint_scratch(hipib_ctx* ctx) {
 hipib_status adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n, const double* u_np1,
                           double pressure, double* lam_u, double* lam_X, double* dtheta) {
     HIPIB_TRY(ensure_adjoint_scratch(ctx));
+    const bool det = ctx->cfg.deterministic != 0;
     const double h = ctx->h, h3 = h * h * h, rho = ctx->cfg.rho, dt = ctx->cfg.dt;
     const int64_t nn3 = 3 * (int64_t)ctx->nn, g3 = 3 * ctx->n3;
     HIPIB_TRY(launch_bin(ctx, X_n));
@@ -416,16 +440,21 @@ hipib_status adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n, 
         if (ctx->ne > 0) {
             k_fe_hvp<<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
                 X_n, ctx->Xref, ctx->conn, ctx->fibre, ctx->mat_id, ctx->mats, ctx->ne,
-                ctx->adj_lamF, lam_X, ctx->st);
+                ctx->adj_lamF, lam_X, ctx->st, det ? ctx->det_contrib : nullptr);
+            HIPIB_HIP(hipGetLastError());
+            if (det) HIPIB_TRY(det_gather_nodes(ctx, false, true, lam_X));
             k_fe_param_vjp<<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
                 X_n, ctx->Xref, ctx->conn, ctx->fibre, ctx->mat_id, ctx->mats, ctx->ne,
-                ctx->adj_lamF, dtheta);
+                ctx->adj_lamF, dtheta, det ? ctx->det_param : nullptr);
             HIPIB_HIP(hipGetLastError());
+            if (det) HIPIB_TRY(det_param_reduce(ctx, dtheta));
         }
         if (ctx->nf > 0 && pressure != 0.0) {
             k_pressure_vjp<<<(ctx->nf + 255) / 256, 256, 0, ctx->stream>>>(
-                X_n, ctx->faces, ctx->nf, pressure, ctx->adj_lamF, lam_X);
+                X_n, ctx->faces, ctx->nf, pressure, ctx->adj_lamF, lam_X,
+                det ? ctx->det_face_contrib : nullptr);
             HIPIB_HIP(hipGetLastError());
+            if (det) HIPIB_TRY(det_gather_nodes(ctx, true, true, lam_X));
         }
     }
     HIPIB_TRY(sync_state(ctx));
@@ -448,18 +477,23 @@ hipib_status launch_conv_vjp(hipib_ctx* ctx, const double* u, const double* lam,
 hipib_status launch_fe_hvp(hipib_ctx* ctx, const double* X, const double* V, double* out) {
     HIPIB_TRY(launch_zero(ctx, out, 3 * (int64_t)ctx->nn));
     if (ctx->ne == 0) return HIPIB_OK;
+    const bool det = ctx->cfg.deterministic != 0;
     k_fe_hvp<<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(X, ctx->Xref, ctx->conn, ctx->fibre,
                                                              ctx->mat_id, ctx->mats, ctx->ne, V, out,
-                                                             ctx->st);
+                                                             ctx->st, det ? ctx->det_contrib : nullptr);
     HIPIB_HIP(hipGetLastError());
+    if (det) HIPIB_TRY(det_gather_nodes(ctx, false, true, out));
     return HIPIB_OK;
 }
 
 hipib_status launch_fe_param_vjp(hipib_ctx* ctx, const double* X, const double* lamF, double* dtheta) {
     if (ctx->ne == 0) return HIPIB_OK;
+    const bool det = ctx->cfg.deterministic != 0;
     k_fe_param_vjp<<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
-        X, ctx->Xref, ctx->conn, ctx->fibre, ctx->mat_id, ctx->mats, ctx->ne, lamF, dtheta);
+        X, ctx->Xref, ctx->conn, ctx->fibre, ctx->mat_id, ctx->mats, ctx->ne, lamF, dtheta,
+        det ? ctx->det_param : nullptr);
     HIPIB_HIP(hipGetLastError());
+    if (det) HIPIB_TRY(det_param_reduce(ctx, dtheta));
     return HIPIB_OK;
 }
 

@@ -75,6 +75,8 @@ void free_mesh(hipib_ctx* ctx) {
     (void)hipFree(ctx->node_rank);
     (void)hipFree(ctx->perm);
     ctx->node_tile = ctx->node_rank = ctx->perm = nullptr;
+    det_free(ctx);
+    det_free_faces(ctx);
     ctx->Xref = nullptr;
     ctx->conn = nullptr;
     ctx->fibre = nullptr;
@@ -194,8 +196,8 @@ hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out
         return fail(HIPIB_E_INVAL, "invalid multigrid parameters");
     if (cfg->precision != HIPIB_FP64 && cfg->precision != HIPIB_MIXED)
         return fail(HIPIB_E_INVAL, "unknown precision %d", cfg->precision);
-    if (cfg->deterministic != 0)
-        return fail(HIPIB_E_INVAL, "deterministic mode is not available in this build");
+    if (cfg->deterministic != 0 && cfg->deterministic != 1)
+        return fail(HIPIB_E_INVAL, "deterministic must be 0 or 1");
 
     hipib_ctx* ctx = new hipib_ctx();
     ctx->cfg = *cfg;
@@ -337,6 +339,14 @@ hipib_status hipib_set_mesh(hipib_ctx* ctx, int32_t n_nodes, const double* X_ref
     ctx->nn = n_nodes;
     ctx->ne = n_elems;
     ctx->mat_used = used;
+    if (ctx->cfg.deterministic) {
+        hipib_status sd = det_prepare_mesh(ctx, conn);
+        if (sd == HIPIB_OK) sd = det_prepare_faces(ctx, nullptr, 0);
+        if (sd != HIPIB_OK) {
+            free_mesh(ctx);
+            return sd;
+        }
+    }
     ctx->mesh_set = true;
     return HIPIB_OK;
 }
@@ -382,6 +392,7 @@ hipib_status hipib_set_pressure_faces(hipib_ctx* ctx, int32_t n_faces, const int
     HIPIB_TRY(dev_alloc(ctx, &ctx->faces, 4 * (size_t)n_faces));
     if (n_faces > 0)
         HIPIB_HIP(hipMemcpy(ctx->faces, faces, 4 * sizeof(int32_t) * n_faces, hipMemcpyHostToDevice));
+    if (ctx->cfg.deterministic) HIPIB_TRY(det_prepare_faces(ctx, faces, n_faces));
     ctx->nf = n_faces;
     return HIPIB_OK;
 }

@@ -10,7 +10,8 @@
 // element does two 8-node gathers of 3x3 Jacobians, one 3x3 inverse, the law,
 // one 3x3 product and a 24-entry update, all in registers.  Element rule:
 // 2x2x2 Gauss points at +-1/sqrt(3), unit weights.  Node accumulation uses
-// hardware FP64 atomics.
+// hardware FP64 atomics, or in deterministic mode per-element contributions
+// gathered per node in element order.
 #include "solid.h"
 
 namespace hipib {
@@ -25,7 +26,7 @@ __global__ void __launch_bounds__(128)
 k_fe_force(const double* __restrict__ X, const double* __restrict__ Xref,
            const int32_t* __restrict__ conn, const double* __restrict__ fibre,
            const int32_t* __restrict__ mat_id, MatTable mats, int ne, double* __restrict__ F,
-           MGState* st) {
+           MGState* st, double* __restrict__ contrib) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
     int nd[8];
@@ -104,6 +105,13 @@ k_fe_force(const double* __restrict__ X, const double* __restrict__ Xref,
                 fe[a][r] -= Q[3 * r] * dN[a][0] + Q[3 * r + 1] * dN[a][1] + Q[3 * r + 2] * dN[a][2];
     }
     if (bad) atomicOr(&st->numeric, 1);
+    if (contrib) {  // deterministic mode: gathered per node in element order
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) contrib[24 * (int64_t)e + 3 * a + r] = (double)fe[a][r];
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < 8; ++a)
 #pragma unroll
@@ -113,7 +121,7 @@ k_fe_force(const double* __restrict__ X, const double* __restrict__ Xref,
 // F_a -= p * sum over 2x2 Gauss points of N_a (dx/dxi x dx/deta)
 __global__ void __launch_bounds__(256)
 k_pressure_load(const double* __restrict__ X, const int32_t* __restrict__ faces, int nf, double p,
-                double* __restrict__ F) {
+                double* __restrict__ F, double* __restrict__ contrib) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nf) return;
     int nd[4];
@@ -152,6 +160,13 @@ k_pressure_load(const double* __restrict__ X, const int32_t* __restrict__ faces,
 #pragma unroll
             for (int r = 0; r < 3; ++r) fa[a][r] -= p * N[a] * nA[r];
     }
+    if (contrib) {  // deterministic mode: gathered per node in face order
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) contrib[12 * (int64_t)f + 3 * a + r] = fa[a][r];
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -166,6 +181,25 @@ __global__ void k_clear_numeric(MGState* st) {
 
 hipib_status launch_fe_force(hipib_ctx* ctx, const double* X, double pressure, double* F) {
     k_clear_numeric<<<1, 64, 0, ctx->stream>>>(ctx->st);
+    const bool det = ctx->cfg.deterministic != 0;
+    if (det) {
+        if (ctx->ne > 0) {
+            k_fe_force<double><<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
+                X, ctx->Xref, ctx->conn, ctx->fibre, ctx->mat_id, ctx->mats, ctx->ne, F, ctx->st,
+                ctx->det_contrib);
+            HIPIB_HIP(hipGetLastError());
+            HIPIB_TRY(det_gather_nodes(ctx, false, false, F));
+        } else {
+            HIPIB_TRY(launch_zero(ctx, F, 3 * (int64_t)ctx->nn));
+        }
+        if (ctx->nf > 0 && pressure != 0.0) {
+            k_pressure_load<<<(ctx->nf + 255) / 256, 256, 0, ctx->stream>>>(
+                X, ctx->faces, ctx->nf, pressure, F, ctx->det_face_contrib);
+            HIPIB_HIP(hipGetLastError());
+            HIPIB_TRY(det_gather_nodes(ctx, true, true, F));
+        }
+        return HIPIB_OK;
+    }
     HIPIB_TRY(launch_zero(ctx, F, 3 * (int64_t)ctx->nn));
     if (ctx->ne > 0) {
         // FP64 in both precision modes: at interior nodes the element
@@ -174,12 +208,12 @@ hipib_status launch_fe_force(hipib_ctx* ctx, const double* X, double pressure, d
         // element forces, which exceeds the mixed mode's 1e-6 error budget over
         // a run; the force kernel is ~1% of a step.
         k_fe_force<double><<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
-            X, ctx->Xref, ctx->conn, ctx->fibre, ctx->mat_id, ctx->mats, ctx->ne, F, ctx->st);
+            X, ctx->Xref, ctx->conn, ctx->fibre, ctx->mat_id, ctx->mats, ctx->ne, F, ctx->st, nullptr);
         HIPIB_HIP(hipGetLastError());
     }
     if (ctx->nf > 0 && pressure != 0.0) {
         k_pressure_load<<<(ctx->nf + 255) / 256, 256, 0, ctx->stream>>>(X, ctx->faces, ctx->nf,
-                                                                         pressure, F);
+                                                                         pressure, F, nullptr);
         HIPIB_HIP(hipGetLastError());
     }
     return HIPIB_OK;

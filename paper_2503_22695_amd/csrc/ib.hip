@@ -262,6 +262,7 @@ hipib_status launch_bin(hipib_ctx* ctx, const double* X) {
 // expects launch_bin(ctx, X) to have been enqueued for the same X
 hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, double* f) {
     if (ctx->nn == 0) return HIPIB_OK;
+    if (ctx->cfg.deterministic) return det_spread(ctx, X, F, f);
     const double h = ctx->h;
     const int64_t cap = spread_list_cap(ctx->ntiles, ctx->nn);
     const int blocks = (int)(cap < 8192 ? cap : 8192);

@@ -110,6 +110,21 @@ struct hipib_ctx {
     std::vector<hipib::StepRecord> recs;
     bool broken = false;
 
+    // deterministic mode (allocated by set_mesh / set_pressure_faces)
+    int32_t* det_node_off = nullptr;   // [nn + 1] CSR: node -> (element, local node) in element order
+    int32_t* det_node_inc = nullptr;   // [8 ne] entries e * 8 + a
+    double* det_contrib = nullptr;     // [ne][8][3] per-element nodal contributions
+    double* det_param = nullptr;       // [ne][4] per-element parameter-gradient terms
+    int32_t* det_face_off = nullptr;   // [nn + 1] CSR: node -> (face, local node)
+    int32_t* det_face_inc = nullptr;   // [4 nf] entries f * 4 + a
+    double* det_face_contrib = nullptr;  // [nf][4][3]
+    int64_t det_pairs = 0;             // 192 nn spreading pairs
+    uint32_t* det_keys[2] = {nullptr, nullptr};  // pair grid indices (unsorted, sorted)
+    double* det_vals[2] = {nullptr, nullptr};    // pair values
+    void* det_temp = nullptr;          // radix-sort workspace
+    size_t det_temp_bytes = 0;
+    int det_end_bit = 0;               // bits of the largest grid index
+
     // adjoint workspaces (allocated on the first adjoint call)
     double* adj_tot = nullptr;   // [3][n3]
     double* adj_lg = nullptr;    // [3][n3]
@@ -165,6 +180,15 @@ hipib_status launch_interpolate(hipib_ctx* ctx, const double* X, const double* u
                                 double* Xupd, double dt);
 // fe.hip
 hipib_status launch_fe_force(hipib_ctx* ctx, const double* X, double pressure, double* F);
+// det.hip (deterministic mode)
+hipib_status det_prepare_mesh(hipib_ctx* ctx, const int32_t* conn);
+hipib_status det_prepare_faces(hipib_ctx* ctx, const int32_t* faces, int nf);
+hipib_status det_spread(hipib_ctx* ctx, const double* X, const double* F, double* f);
+// out (= or +=) per-node sums of det_contrib (faces: det_face_contrib) in element order
+hipib_status det_gather_nodes(hipib_ctx* ctx, bool faces, bool accumulate, double* out);
+hipib_status det_param_reduce(hipib_ctx* ctx, double* dtheta);
+void det_free(hipib_ctx* ctx);
+void det_free_faces(hipib_ctx* ctx);
 // adjoint.hip
 hipib_status adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n, const double* u_np1,
                           double pressure, double* lam_u, double* lam_X, double* dtheta);
