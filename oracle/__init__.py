@@ -39,7 +39,7 @@ class Fluid(C.Structure):
                 ("dt", C.c_double), ("mg_pre", C.c_int32), ("mg_post", C.c_int32),
                 ("mg_max_cycles", C.c_int32), ("mg_fixed_cycles", C.c_int32),
                 ("mg_coarse_sweeps", C.c_int32), ("mg_rtol", C.c_double),
-                ("convection", C.c_int32)]
+                ("convection", C.c_int32), ("mg_krylov", C.c_int32)]
 
 
 class Mesh(C.Structure):
@@ -215,14 +215,15 @@ class MeshBuffers:
 
 
 def fluid(n, rho=1.0, mu=0.01, dt=1e-3, rtol=1e-10, pre=2, post=2, max_cycles=50,
-          fixed_cycles=0, coarse_sweeps=16, convection=1) -> Fluid:
+          fixed_cycles=0, coarse_sweeps=16, convection=1, krylov=1) -> Fluid:
     return Fluid(n, rho, mu, dt, pre, post, max_cycles, fixed_cycles, coarse_sweeps, rtol,
-                 convection)
+                 convection, krylov)
 
 
 def fluid_from_problem(prob, **over) -> Fluid:
     kw = dict(rho=prob.rho, mu=prob.mu, dt=prob.dt, rtol=prob.mg_rtol, pre=prob.mg_pre,
-              post=prob.mg_post, max_cycles=prob.mg_max_cycles, convection=prob.convection)
+              post=prob.mg_post, max_cycles=prob.mg_max_cycles, convection=prob.convection,
+              krylov=prob.mg_krylov)
     kw.update(over)
     return fluid(prob.n, **kw)
 

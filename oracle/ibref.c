@@ -581,6 +581,83 @@ static void vcycle(const ibref_fluid* fl, mg_levels* lv, int l, double sigma, do
     }
 }
 
+static double dot(long N, const double* a, const double* b) {
+    double s = 0.0;
+    for (long i = 0; i < N; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* q = A p = sigma p - nu Lap_h p, written through the residual of a zero
+ * right-hand side so the stencil is the smoother's */
+static void apply_op(int n, double sigma, double nu, const double* p, double* zero, double* q) {
+    const long N3 = (long)n * n * n;
+    residual(n, sigma, nu, zero, p, q);
+    for (long i = 0; i < N3; ++i) q[i] = -q[i];
+}
+
+/*
+ * The "combined" multigrid reading for the Poisson equation (the paper names
+ * a combined geometric multigrid solver and gives no algorithm): conjugate
+ * gradients on A x = b preconditioned with z = M r, one V-cycle from a zero
+ * guess.  The search direction uses the flexible (Polak-Ribiere) update, which
+ * tolerates a preconditioner that is not exactly symmetric or linear:
+ *   r = b - A x, z = M r, p = z, rz = r.z
+ *   repeat:  q = A p,  alpha = rz / (p.q),  x += alpha p,  r -= alpha q,
+ *            stop test on ||r|| (as the plain iteration, one iteration = one cycle),
+ *            z = M r,  beta = z.(r_new - r_old) / rz = -alpha (z.q) / rz,
+ *            rz = r.z,  p = z + beta p
+ */
+static int pcg_solve(const ibref_fluid* fl, mg_levels* lv, double sigma, double nu,
+                     const double* b, double* x, double bn, int* kout, double* rnout) {
+    const int n = fl->n;
+    const long N3 = (long)n * n * n;
+    double* r = (double*)malloc(sizeof(double) * (size_t)N3);
+    double* z = (double*)malloc(sizeof(double) * (size_t)N3);
+    double* p = (double*)malloc(sizeof(double) * (size_t)N3);
+    double* q = (double*)malloc(sizeof(double) * (size_t)N3);
+    double* zero = (double*)calloc((size_t)N3, sizeof(double));
+    int rc = IBREF_OK, k = 0;
+    if (!r || !z || !p || !q || !zero) rc = IBREF_E_INVAL;
+    double tol = (fl->mg_rtol > 1e3 * DBL_EPSILON ? fl->mg_rtol : 1e3 * DBL_EPSILON) * bn;
+    double rn = 0.0, rz = 0.0, alpha = 0.0;
+    if (!rc) {
+        residual(n, sigma, nu, b, x, r);
+        rn = norm2(N3, r);
+    }
+    while (!rc) {
+        if (!isfinite(rn)) { rc = IBREF_E_NUMERIC; break; }
+        if (fl->mg_fixed_cycles > 0) {
+            if (k == fl->mg_fixed_cycles) break;
+        } else {
+            if (rn <= tol) break;
+            if (k == fl->mg_max_cycles) { rc = IBREF_E_NOCONV; break; }
+        }
+        memset(z, 0, sizeof(double) * (size_t)N3);
+        vcycle(fl, lv, 0, sigma, nu, 1, r, z);
+        if (k == 0) {
+            rz = dot(N3, r, z);
+            memcpy(p, z, sizeof(double) * (size_t)N3);
+        } else {
+            /* q and alpha are still those of the previous iteration */
+            double beta = -alpha * dot(N3, z, q) / rz;
+            rz = dot(N3, r, z);
+            for (long i = 0; i < N3; ++i) p[i] = z[i] + beta * p[i];
+        }
+        apply_op(n, sigma, nu, p, zero, q);
+        alpha = rz / dot(N3, p, q);
+        for (long i = 0; i < N3; ++i) {
+            x[i] += alpha * p[i];
+            r[i] -= alpha * q[i];
+        }
+        ++k;
+        rn = norm2(N3, r);
+    }
+    free(r); free(z); free(p); free(q); free(zero);
+    *kout = k;
+    *rnout = rn;
+    return rc;
+}
+
 int ibref_mg_solve(const ibref_fluid* fl, double sigma, double nu, int32_t poisson,
                    const double* b, double* x, int32_t* cycles, double* relres) {
     const int n = fl->n;
@@ -594,6 +671,10 @@ int ibref_mg_solve(const ibref_fluid* fl, double sigma, double nu, int32_t poiss
     if (!isfinite(bn)) { mg_free(&lv); return IBREF_E_NUMERIC; }
     if (bn == 0.0) {
         for (long i = 0; i < N3; ++i) x[i] = 0.0;
+    } else if (poisson && fl->mg_krylov) {
+        rc = pcg_solve(fl, &lv, sigma, nu, b, x, bn, &k, &rn);
+        rn /= bn;
+        remove_mean(N3, x);
     } else {
         double tol = (fl->mg_rtol > 1e3 * DBL_EPSILON ? fl->mg_rtol : 1e3 * DBL_EPSILON) * bn;
         residual(n, sigma, nu, b, x, lv.r[0]);

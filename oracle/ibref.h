@@ -41,6 +41,8 @@ typedef struct {
     int32_t mg_coarse_sweeps;  /* red+black sweeps on the coarsest level */
     double mg_rtol;            /* stop when ||r|| <= rtol ||b|| */
     int32_t convection;        /* 1: explicit flux-form convection, 0: Stokes */
+    int32_t mg_krylov;         /* 1: Poisson solves by conjugate gradients preconditioned
+                                  with one V-cycle; 0: plain V-cycle iteration */
 } ibref_fluid;
 
 typedef struct {
@@ -83,7 +85,9 @@ int ibref_fe_force(const ibref_mesh* m, const double* x, double* F /*[n_nodes][3
 void ibref_pressure_load(int32_t n_faces, const int32_t* faces, const double* x, double p,
                          double* F /* += */);
 
-/* --- multigrid: solves (sigma I - nu Lap_h) x = b on the periodic grid --- */
+/* --- multigrid: solves (sigma I - nu Lap_h) x = b on the periodic grid; with
+ * mg_krylov the Poisson case (poisson = 1) runs preconditioned conjugate
+ * gradients, counting one iteration as one cycle --- */
 int ibref_mg_solve(const ibref_fluid* fl, double sigma, double nu, int32_t poisson,
                    const double* b, double* x /* guess -> solution */,
                    int32_t* cycles, double* relres);

@@ -71,6 +71,7 @@ class Problem:
     mg_pre: int = 2
     mg_post: int = 2
     mg_max_cycles: int = 50
+    mg_krylov: int = 1          # Poisson by V-cycle-preconditioned conjugate gradients
     convection: int = 1
     precision: str = "fp64"
 

@@ -50,14 +50,15 @@ def test_helmholtz_single_mode_factor(ref):
     assert np.max(np.abs(x - mode / (sigma - nu * lam))) < 1e-15 * 1e3
 
 
-@pytest.mark.parametrize("n,sigma,nu,poisson", [(32, 0.0, 1.0, True), (24, 0.0, 1.0, True),
-                                                (32, 2000.0, 0.01, False), (16, 5.0, 1.0, False)])
-def test_matches_fft_solution(ref, n, sigma, nu, poisson):
+@pytest.mark.parametrize("n,sigma,nu,poisson,krylov", [
+    (32, 0.0, 1.0, True, 1), (32, 0.0, 1.0, True, 0), (24, 0.0, 1.0, True, 1),
+    (24, 0.0, 1.0, True, 0), (32, 2000.0, 0.01, False, 1), (16, 5.0, 1.0, False, 0)])
+def test_matches_fft_solution(ref, n, sigma, nu, poisson, krylov):
     rng = np.random.default_rng(n)
     b = rng.standard_normal((n, n, n))
     if poisson:
         b -= b.mean()
-    fl = ref.fluid(n, rtol=1e-10)
+    fl = ref.fluid(n, rtol=1e-10, krylov=krylov)
     x, cyc, rr = ref.mg_solve(fl, sigma, nu, poisson, b)
     xf = fft_solve(b, sigma, nu)
     assert rr <= 1e-10
@@ -74,7 +75,7 @@ def test_vcycle_contraction(ref):
     b -= b.mean()
     rr = []
     for k in (1, 2, 3, 4):
-        fl = ref.fluid(n, fixed_cycles=k)
+        fl = ref.fluid(n, fixed_cycles=k, krylov=0)
         _, cyc, r = ref.mg_solve(fl, 0.0, 1.0, True, b)
         assert cyc == k
         rr.append(r)
@@ -109,3 +110,38 @@ def test_initial_guess_at_solution_needs_no_cycle(ref):
     xs = fft_solve(b, 50.0, 1.0)
     x, cyc, rr = ref.mg_solve(ref.fluid(n), 50.0, 1.0, False, b, xs)
     assert cyc == 0 and np.array_equal(x, xs)
+
+
+def neg_lap(x):
+    """-Lap_h on the periodic grid (h = 1/n), written with numpy shifts."""
+    n = x.shape[0]
+    s = sum(np.roll(x, sh, ax) for ax in range(3) for sh in (1, -1))
+    return -(s - 6.0 * x) * n * n
+
+
+def test_krylov_first_step_is_energy_optimal_multiple_of_the_vcycle(ref):
+    """One preconditioned-CG iteration from x = 0 is alpha z with z one V-cycle
+    applied to b and alpha = (b.z)/(z.Az), the energy-minimising step."""
+    n = 16
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal((n, n, n))
+    b -= b.mean()
+    z, cyc, _ = ref.mg_solve(ref.fluid(n, fixed_cycles=1, krylov=0), 0.0, 1.0, True, b)
+    x1, cyc1, _ = ref.mg_solve(ref.fluid(n, fixed_cycles=1, krylov=1), 0.0, 1.0, True, b)
+    assert cyc == 1 and cyc1 == 1
+    alpha = np.sum(b * z) / np.sum(z * neg_lap(z))
+    want = alpha * z
+    want -= want.mean()
+    assert np.max(np.abs(x1 - want)) <= 1e-12 * np.max(np.abs(want))
+    assert abs(alpha - 1.0) > 1e-3      # the step is not the plain V-cycle's
+
+
+def test_krylov_needs_fewer_cycles_than_the_plain_iteration(ref):
+    n = 32
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal((n, n, n))
+    b -= b.mean()
+    _, k_plain, _ = ref.mg_solve(ref.fluid(n, krylov=0), 0.0, 1.0, True, b)
+    x, k_cg, rr = ref.mg_solve(ref.fluid(n, krylov=1), 0.0, 1.0, True, b)
+    assert rr <= 1e-10
+    assert k_cg <= 0.7 * k_plain, (k_cg, k_plain)
