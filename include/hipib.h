@@ -73,10 +73,16 @@ typedef struct {
     int32_t convection;       /* 1: explicit flux-form convection; 0: Stokes */
     int32_t precision;        /* hipib_precision */
     int32_t deterministic;    /* 1: atomic-free, bitwise run-to-run reproducible */
+    int32_t mg_krylov;        /* 1: Poisson solves by conjugate gradients preconditioned
+                                 with one V-cycle (the "combined" multigrid reading of
+                                 the abstract; one iteration counts as one cycle);
+                                 0: plain V-cycle iteration.  Helmholtz solves always
+                                 use the plain iteration. */
 } hipib_config;
 
 /* Fills cfg with the defaults: V(2,2), 16 coarse sweeps, rtol 1e-10, 50 cycles,
- * convection on, FP64, atomic mode; n/rho/mu/dt are set to 32/1/0.01/1e-3. */
+ * convection on, FP64, atomic mode, Krylov Poisson solves; n/rho/mu/dt are set
+ * to 32/1/0.01/1e-3. */
 void hipib_default_config(hipib_config* cfg);
 
 /* Creates a context for one grid on the current HIP device.  stream is a

@@ -99,6 +99,7 @@ void free_all(hipib_ctx* ctx) {
     (void)hipFree(ctx->xp);
     (void)hipFree(ctx->bpk);
     (void)hipFree(ctx->e32);
+    for (int v = 0; v < 4; ++v) (void)hipFree(ctx->kv[v]);
     (void)hipFree(ctx->r32);
     (void)hipFree(ctx->g);
     (void)hipFree(ctx->bp);
@@ -172,6 +173,7 @@ void hipib_default_config(hipib_config* cfg) {
     cfg->convection = 1;
     cfg->precision = HIPIB_FP64;
     cfg->deterministic = 0;
+    cfg->mg_krylov = 1;
 }
 
 const char* hipib_last_error(void) { return g_err; }
@@ -198,6 +200,8 @@ hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out
         return fail(HIPIB_E_INVAL, "unknown precision %d", cfg->precision);
     if (cfg->deterministic != 0 && cfg->deterministic != 1)
         return fail(HIPIB_E_INVAL, "deterministic must be 0 or 1");
+    if (cfg->mg_krylov != 0 && cfg->mg_krylov != 1)
+        return fail(HIPIB_E_INVAL, "mg_krylov must be 0 or 1");
 
     hipib_ctx* ctx = new hipib_ctx();
     ctx->cfg = *cfg;
@@ -244,6 +248,8 @@ hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out
         if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->r32, 3 * (size_t)ctx->n3);
     }
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->g, 3 * (size_t)ctx->n3);
+    if (cfg->mg_krylov)   // conjugate-gradient vectors r, z, p, q of the Poisson solve
+        for (int v = 0; v < 4 && s == HIPIB_OK; ++v) s = dev_alloc(ctx, &ctx->kv[v], (size_t)ctx->n3);
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->bp, (size_t)ctx->n3);
     ctx->tile = (n % 8 == 0) ? 8 : 4;
     ctx->tiles_axis = n / ctx->tile;

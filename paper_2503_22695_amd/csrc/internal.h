@@ -39,6 +39,8 @@ struct MGState {
     int32_t status;     // HIPIB_OK / HIPIB_E_NOCONV / HIPIB_E_NUMERIC
     int32_t numeric;    // set by the force kernel when J <= 0
     int32_t pad[3];
+    // conjugate gradients (component 0): r.z, step alpha, direction update beta
+    double rz, alpha, beta;
 };
 
 struct Level {
@@ -71,6 +73,7 @@ struct hipib_ctx {
     hipib::Level lv[hipib::kMaxLevels];
     void* r0 = nullptr;     // [3][n3] residual scratch of the V-cycle type (any level)
     double* xp = nullptr;   // [3][n3] packed FP64 solution of the current solve
+    double* kv[4] = {nullptr, nullptr, nullptr, nullptr};  // [n3] packed CG vectors r, z, p, q
     double* bpk = nullptr;  // [3][n3] packed FP64 right-hand side
     float* e32 = nullptr;   // [3][n3] packed FP32 correction (mixed precision)
     float* r32 = nullptr;   // [3][n3] packed FP32 scaled residual (mixed precision)

@@ -383,7 +383,7 @@ template <bool TO32>
 __global__ void __launch_bounds__(TX * TY)
 k_resid_norm(const double* __restrict__ x, const double* __restrict__ b, int n, int64_t cs,
              double sigma, double c, const MGState* __restrict__ st, float* __restrict__ r32,
-             double* __restrict__ part, int64_t pstride) {
+             double* __restrict__ part, int64_t pstride, double* __restrict__ rstore) {
     __shared__ double red[16];
     const int nkb = (n + KPT - 1) / KPT;
     const int z = blockIdx.z, comp = z / (2 * nkb), rem = z - comp * 2 * nkb, q = rem / nkb;
@@ -427,6 +427,7 @@ k_resid_norm(const double* __restrict__ x, const double* __restrict__ b, int n, 
                 const double s = a_ip + a_im + yp[r] + ym[r] + col[r + 2] + col[r];
                 const double rr = bv[r] - (sigma * xv[r] - c * (s - 6.0 * xv[r]));
                 v += rr * rr;
+                if (rstore) rstore[comp * cs + q * half3 + (int64_t)H * ((int64_t)j + (int64_t)n * k) + ih] = rr;
                 if (TO32)
                     r32[comp * cs + q * half3 + (int64_t)H * ((int64_t)j + (int64_t)n * k) + ih] =
                         (float)(rr * inv_bn);
@@ -442,6 +443,184 @@ k_resid_norm(const double* __restrict__ x, const double* __restrict__ b, int n, 
         for (int w = 0; w < (TX * TY) / 64; ++w) s += red[w];
         const int64_t blk = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * rem);
         part[comp * pstride + blk] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Poisson by V-cycle-preconditioned conjugate gradients (mg_krylov; one
+// component).  Vectors r, z, p, q are packed like x; the scalars live in the
+// device state.  One iteration: z = M r (one V-cycle from a zero guess; in
+// mixed mode the FP32 V-cycle of r / ||b||, z = ||b|| e), the dots r.z and
+// z.q, beta = -alpha (z.q) / (r.z)_old (0 on the first iteration, the
+// flexible Polak-Ribiere update), p = z + beta p together with
+// q = A p = A z + beta q and p.q, alpha = (r.z) / (p.q), then x += alpha p and
+// r -= alpha q with ||r||^2 for the stop test.
+// ---------------------------------------------------------------------------
+
+// per-block partial sums of r.z (slot 0) and z.q (slot 1); z = zs * z32 in mixed mode
+template <typename TZ>
+__global__ void __launch_bounds__(256)
+k_cg_dots(const double* __restrict__ r, const TZ* __restrict__ z, const double* __restrict__ q,
+          int64_t n3, const MGState* __restrict__ st, double* __restrict__ part, int64_t pstride) {
+    __shared__ double red[16];
+    if (!st->active[0]) return;  // uniform
+    const double zs = sizeof(TZ) == 4 ? st->bn[0] : 1.0;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    double a = 0.0, b = 0.0;
+    for (int64_t t0 = (int64_t)blockIdx.x * 256 + threadIdx.x; t0 < n3; t0 += 4 * stride) {
+        double rv[4], zv[4], qv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t t = t0 + u * stride;
+            const bool in = t < n3;
+            rv[u] = in ? r[t] : 0.0;
+            zv[u] = in ? zs * (double)z[t] : 0.0;
+            qv[u] = in ? q[t] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a += rv[u] * zv[u];
+            b += zv[u] * qv[u];
+        }
+    }
+    a = block_sum(a, red);
+    b = block_sum(b, red);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = a;
+        part[pstride + blockIdx.x] = b;
+    }
+}
+
+// p = z + beta p and q = A z + beta q (= A p), partial p.q per block; grid and
+// columns as k_resid_norm
+template <typename TZ>
+__global__ void __launch_bounds__(TX * TY)
+k_cg_dir(const TZ* __restrict__ z, double* __restrict__ p, double* __restrict__ q, int n,
+         double sigma, double c, const MGState* __restrict__ st, double* __restrict__ part) {
+    __shared__ double red[16];
+    const int nkb = (n + KPT - 1) / KPT;
+    const int rem = blockIdx.z, qc = rem / nkb, k0 = (rem - qc * nkb) * KPT;
+    if (!st->active[0]) return;  // uniform
+    const double beta = st->beta, zs = sizeof(TZ) == 4 ? st->bn[0] : 1.0;
+    const int H = n >> 1;
+    const int ih = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y;
+    double v = 0.0;
+    if (ih < H && j < n) {
+        const int64_t half3 = (int64_t)H * n * n;
+        const TZ* zq = z + qc * half3;
+        const TZ* zo = z + (1 - qc) * half3;
+        double* pq = p + qc * half3;
+        double* qq = q + qc * half3;
+        const int jp = wrapi(j + 1, n), jm = wrapi(j - 1, n);
+        const int ihp = ih + 1 < H ? ih + 1 : 0, ihm = ih > 0 ? ih - 1 : H - 1;
+        double col[KPT + 2], side[KPT], yp[KPT], ym[KPT], zv[KPT], pv[KPT], qv[KPT];
+#pragma unroll
+        for (int r = 0; r < KPT + 2; ++r)
+            col[r] = zs * (double)zo[ih + (int64_t)H * ((int64_t)j + (int64_t)n * wrapi(k0 - 1 + r, n))];
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) {
+            const int k = k0 + r;
+            if (k < n) {
+                const int64_t row = (int64_t)H * ((int64_t)j + (int64_t)n * k);
+                const int pp = (j + k + qc) & 1;
+                zv[r] = zs * (double)zq[row + ih];
+                side[r] = zs * (double)zo[row + (pp ? ihp : ihm)];
+                yp[r] = zs * (double)zo[(int64_t)H * ((int64_t)jp + (int64_t)n * k) + ih];
+                ym[r] = zs * (double)zo[(int64_t)H * ((int64_t)jm + (int64_t)n * k) + ih];
+                pv[r] = beta != 0.0 ? pq[row + ih] : 0.0;
+                qv[r] = beta != 0.0 ? qq[row + ih] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) {
+            const int k = k0 + r;
+            if (k < n) {
+                const int pp = (j + k + qc) & 1;
+                const double a_ip = pp ? side[r] : col[r + 1];
+                const double a_im = pp ? col[r + 1] : side[r];
+                const double sn = a_ip + a_im + yp[r] + ym[r] + col[r + 2] + col[r];
+                const double Az = sigma * zv[r] - c * (sn - 6.0 * zv[r]);
+                const double pn = zv[r] + beta * pv[r];
+                const double qn = Az + beta * qv[r];
+                const int64_t row = (int64_t)H * ((int64_t)j + (int64_t)n * k);
+                pq[row + ih] = pn;
+                qq[row + ih] = qn;
+                v += pn * qn;
+            }
+        }
+    }
+    const int tid = threadIdx.x + TX * threadIdx.y;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+        double s = 0.0;
+        for (int w = 0; w < (TX * TY) / 64; ++w) s += red[w];
+        part[blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * rem)] = s;
+    }
+}
+
+// x += alpha p, r -= alpha q, partial ||r||^2 per block; r32 (mixed) = r / ||b||
+__global__ void __launch_bounds__(256)
+k_cg_update(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+            const double* __restrict__ q, int64_t n3, const MGState* __restrict__ st,
+            float* __restrict__ r32, double* __restrict__ part) {
+    __shared__ double red[16];
+    if (!st->active[0]) return;  // uniform
+    const double alpha = st->alpha, inv_bn = r32 ? 1.0 / st->bn[0] : 0.0;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    double v = 0.0;
+    for (int64_t t0 = (int64_t)blockIdx.x * 256 + threadIdx.x; t0 < n3; t0 += 4 * stride) {
+        double xv[4], rv[4], pv[4], qv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t t = t0 + u * stride;
+            if (t < n3) {
+                xv[u] = x[t];
+                rv[u] = r[t];
+                pv[u] = p[t];
+                qv[u] = q[t];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t t = t0 + u * stride;
+            if (t < n3) {
+                const double rn = rv[u] - alpha * qv[u];
+                x[t] = xv[u] + alpha * pv[u];
+                r[t] = rn;
+                v += rn * rn;
+                if (r32) r32[t] = (float)(rn * inv_bn);
+            }
+        }
+    }
+    v = block_sum(v, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+enum CgMode { CG_BETA = 0, CG_ALPHA = 1 };
+
+// reduce the partials in a fixed order and update the CG scalars
+__global__ void __launch_bounds__(1024)
+k_cg_scalars(const double* __restrict__ part, int64_t nparts, int64_t pstride, int mode,
+             MGState* st) {
+    __shared__ double red[16];
+    if (!st->active[0]) return;  // uniform
+    double a = 0.0, b = 0.0;
+    for (int64_t t = threadIdx.x; t < nparts; t += blockDim.x) {
+        a += part[t];
+        if (mode == CG_BETA) b += part[pstride + t];
+    }
+    a = block_sum(a, red);
+    b = block_sum(b, red);
+    if (threadIdx.x == 0) {
+        if (mode == CG_BETA) {
+            // a = r.z (new), b = z.q with q = A p of the previous iteration
+            st->beta = (st->cycles[0] == 0 || st->rz == 0.0) ? 0.0 : -st->alpha * b / st->rz;
+            st->rz = a;
+        } else {
+            st->alpha = a != 0.0 ? st->rz / a : 0.0;   // a = p.q
+        }
     }
 }
 
@@ -1178,8 +1357,9 @@ hipib_status gs_sweep(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpC
         k_gs<T, 0><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, colour, zg, act);
     } else if (!oc.poisson) {
         k_gs<T, 1><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, colour, zg, act);
-    } else if (timer_events(ctx, HIPIB_TIMER_SMOOTH_FINE_POISSON,
-                            (zg ? 1.0 : 1.5) * sizeof(T) * (double)ctx->n3, &t0, &t1)) {
+    } else if (!zg && timer_events(ctx, HIPIB_TIMER_SMOOTH_FINE_POISSON,
+                                   1.5 * sizeof(T) * (double)ctx->n3, &t0, &t1)) {
+        // (only the 12 B/cell half-sweeps; a zero-guess first half-sweep moves 8)
         // the events take the dispatch's own start and end timestamps
         hipExtLaunchKernelGGL(k_gs<T, 2>, grid, blk, 0, ctx->stream, t0, t1, 0, p.x, p.b, n, p.cs, c,
                               inv_diag, colour, zg, act);
@@ -1266,22 +1446,60 @@ hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
 
 // ||b - A x|| per component into the state (mode FIN_INIT_R / FIN_CYCLE_R);
 // in mixed mode also writes the scaled FP32 residual of every active component
-hipib_status resid_norm(hipib_ctx* ctx, int ncomp, const OpCoef& oc, int mode) {
+hipib_status resid_norm(hipib_ctx* ctx, int ncomp, const OpCoef& oc, int mode,
+                        double* rstore = nullptr) {
     const int n = ctx->n;
     const double h = 1.0 / n, c = oc.nu / (h * h);
     const int64_t np = norm_parts(n);
     if (ctx->cfg.precision == HIPIB_MIXED)
         k_resid_norm<true><<<norm_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(
-            ctx->xp, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, ctx->r32, ctx->part, np);
+            ctx->xp, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, ctx->r32, ctx->part, np, rstore);
     else
         k_resid_norm<false><<<norm_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(
-            ctx->xp, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, nullptr, ctx->part, np);
+            ctx->xp, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, nullptr, ctx->part, np, rstore);
     HIPIB_HIP(hipGetLastError());
     return finalize(ctx, np, np, ncomp, mode, 0.0);
 }
 
+// one preconditioned conjugate-gradient iteration of the Poisson solve
+hipib_status cg_iteration(hipib_ctx* ctx, const OpCoef& oc) {
+    const int n = ctx->n;
+    const int64_t n3 = ctx->n3;
+    const double h = 1.0 / n, c = oc.nu / (h * h);
+    const int nb = sum_blocks(n3);
+    double *r = ctx->kv[0], *z = ctx->kv[1], *p = ctx->kv[2], *q = ctx->kv[3];
+    const bool mixed = ctx->cfg.precision == HIPIB_MIXED;
+    const int64_t np = norm_parts(n);
+    if (mixed) {
+        HIPIB_TRY(vcycle<float>(ctx, 0, LevelPtr<float>{ctx->e32, ctx->r32, n3}, 1, oc, true));
+        k_cg_dots<float><<<nb, 256, 0, ctx->stream>>>(r, ctx->e32, q, n3, ctx->st, ctx->part, nb);
+    } else {
+        HIPIB_TRY(vcycle<double>(ctx, 0, LevelPtr<double>{z, r, n3}, 1, oc, true));
+        k_cg_dots<double><<<nb, 256, 0, ctx->stream>>>(r, z, q, n3, ctx->st, ctx->part, nb);
+    }
+    HIPIB_HIP(hipGetLastError());
+    k_cg_scalars<<<1, 1024, 0, ctx->stream>>>(ctx->part, nb, nb, CG_BETA, ctx->st);
+    if (mixed)
+        k_cg_dir<float><<<norm_grid(n, 1), dim3(TX, TY), 0, ctx->stream>>>(ctx->e32, p, q, n, oc.sigma, c,
+                                                                           ctx->st, ctx->part);
+    else
+        k_cg_dir<double><<<norm_grid(n, 1), dim3(TX, TY), 0, ctx->stream>>>(z, p, q, n, oc.sigma, c,
+                                                                            ctx->st, ctx->part);
+    HIPIB_HIP(hipGetLastError());
+    k_cg_scalars<<<1, 1024, 0, ctx->stream>>>(ctx->part, np, np, CG_ALPHA, ctx->st);
+    k_cg_update<<<nb, 256, 0, ctx->stream>>>(ctx->xp, r, p, q, n3, ctx->st, mixed ? ctx->r32 : nullptr,
+                                             ctx->part);
+    HIPIB_HIP(hipGetLastError());
+    return finalize(ctx, nb, nb, 1, FIN_CYCLE_R, 0.0);
+}
+
+bool use_cg(const hipib_ctx* ctx, const OpCoef& oc, int ncomp) {
+    return oc.poisson && ncomp == 1 && ctx->cfg.mg_krylov && ctx->kv[0] != nullptr;
+}
+
 // one top-level cycle on the packed FP64 solution
 hipib_status cycle(hipib_ctx* ctx, int ncomp, const OpCoef& oc) {
+    if (use_cg(ctx, oc, ncomp)) return cg_iteration(ctx, oc);
     const int nb = sum_blocks(ctx->n3);
     if (ctx->cfg.precision == HIPIB_MIXED) {
         HIPIB_TRY(vcycle<float>(ctx, 0, LevelPtr<float>{ctx->e32, ctx->r32, ctx->n3}, ncomp, oc, true));
@@ -1368,7 +1586,8 @@ hipib_status mg_solve(hipib_ctx* ctx, int op, int ncomp, const double* b, double
                                                              ctx->part, nb);
     HIPIB_HIP(hipGetLastError());
     HIPIB_TRY(finalize(ctx, nb, nb, ncomp, FIN_BNORM, 0.0));
-    HIPIB_TRY(resid_norm(ctx, ncomp, oc, FIN_INIT_R));
+    // (conjugate gradients keep the initial residual as their r)
+    HIPIB_TRY(resid_norm(ctx, ncomp, oc, FIN_INIT_R, use_cg(ctx, oc, ncomp) ? ctx->kv[0] : nullptr));
     k_zero_requested<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->xp, ctx->n3, ctx->n3, ctx->st);
     HIPIB_HIP(hipGetLastError());
 

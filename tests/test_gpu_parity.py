@@ -146,18 +146,21 @@ def test_fe_force_leaflets_mixed_materials(torch_dev, hp, ref):
 # multigrid
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n", [16, 24, 32, 48, 64])
-def test_mg_poisson(torch_dev, hp, ref, n):
+@pytest.mark.parametrize("n,krylov", [(16, 1), (24, 1), (32, 1), (48, 1), (64, 1), (16, 0),
+                                      (32, 0), (48, 0)])
+def test_mg_poisson(torch_dev, hp, ref, n, krylov):
+    """Poisson solve: V-cycle-preconditioned conjugate gradients (krylov = 1,
+    the default) and the plain V-cycle iteration, against the oracle."""
     torch = torch_dev
-    say("mg poisson", n)
+    say("mg poisson", n, "krylov", krylov)
     rng = np.random.default_rng(n)
     b = rng.standard_normal((n, n, n))
     b -= b.mean()
     x0 = 0.1 * rng.standard_normal((n, n, n))
-    ctx = plain_ctx(hp, n)
+    ctx = plain_ctx(hp, n, mg_krylov=krylov)
     xd = to_dev(torch, x0)
     cyc, rr = ctx.mg_solve(hp.OP_POISSON, to_dev(torch, b), xd)
-    xr, cr, rrr = ref.mg_solve(ref.fluid(n), 0.0, 1.0, True, b, x0)
+    xr, cr, rrr = ref.mg_solve(ref.fluid(n, krylov=krylov), 0.0, 1.0, True, b, x0)
     assert int(cyc[0]) == cr
     assert abs(rr[0] - rrr) <= 1e-3 * rrr
     assert_close("x", host(xd), xr)
