@@ -285,6 +285,26 @@ def test_advance_shell_128_first_steps(torch_dev, hp, ref):
     assert_close("X - X0", host(sim.X) - prob.X0, Xr - prob.X0)
 
 
+def test_advance_shell_leaflets_192_first_steps(torch_dev, hp, ref):
+    """The 192^3 shell + neo-Hookean leaflets with the random divergence-free
+    initial velocity (max 0.1), 2 steps.  The shell starts 2% inflated at
+    t0 = dt for conditioning, as in the 128^3 case; the leaflets move with the
+    initial flow."""
+    torch = torch_dev
+    prob = inputs.workload("shell_leaflets_192")
+    ns = prob.n_nodes - 2 * 4_290   # the shell's nodes come first, then two leaflets of 4,290
+    c = np.array([0.0, 0.5, 0.5])
+    X0 = prob.X0.copy()
+    X0[:ns] = c + (prob.X_ref[:ns] - c) * np.array([1.0, 1.02, 1.02])
+    prob.X0 = X0
+    say("advance", prob.name, "inflated shell", 2)
+    sim, cyc, (ur, pr, Xr, st) = run_both(torch, hp, ref, prob, 2, t0=prob.dt)
+    assert [list(c) for c in cyc] == [list(s.cycles) for s in st]
+    assert_close("u", host(sim.u), ur)
+    assert_close("p", host(sim.p), pr)
+    assert_close("X - X0", host(sim.X) - prob.X0, Xr - prob.X0)
+
+
 # ---------------------------------------------------------------------------
 # errors
 # ---------------------------------------------------------------------------
