@@ -46,7 +46,16 @@ class Mesh(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("X_ref", C.c_void_p), ("n_elems", C.c_int32),
                 ("conn", C.c_void_p), ("fibre", C.c_void_p), ("mat_id", C.c_void_p),
                 ("n_mats", C.c_int32), ("mat_model", C.c_void_p), ("mat_params", C.c_void_p),
-                ("n_faces", C.c_int32), ("faces", C.c_void_p)]
+                ("n_faces", C.c_int32), ("faces", C.c_void_p), ("sheet", C.c_void_p),
+                ("active_tension", C.c_double), ("ta_max", C.c_double), ("ta_t_on", C.c_double),
+                ("ta_duration", C.c_double)]
+
+
+MAT_PARAMS = 9   # parameter slots per material (IBREF_MAT_PARAMS)
+
+
+def _pad(params):
+    return list(params) + [0.0] * (MAT_PARAMS - len(params))
 
 
 class StepStats(C.Structure):
@@ -73,7 +82,8 @@ def lib():
             "ibref_phi": (f64, [f64]),
             "ibref_spread": (None, [i32, i32, P, P, P]),
             "ibref_interpolate": (None, [i32, i32, P, P, P]),
-            "ibref_pk1": (C.c_int, [i32, P, P, P, P, P]),
+            "ibref_pk1": (C.c_int, [i32, P, P, P, P, f64, P, P]),
+            "ibref_active_tension": (f64, [f64, f64, f64, f64]),
             "ibref_fe_force": (C.c_int, [P, P, P, P, P]),
             "ibref_pressure_load": (None, [i32, P, P, f64, P]),
             "ibref_mg_solve": (C.c_int, [P, f64, f64, i32, P, P, P, P]),
@@ -84,7 +94,7 @@ def lib():
             "ibref_dphi": (f64, [f64]),
             "ibref_spread_vjp_X": (None, [i32, i32, P, P, P, P]),
             "ibref_interp_vjp_X": (None, [i32, i32, P, P, P, P]),
-            "ibref_pk1_tangent": (C.c_int, [i32, P, P, P, P, P]),
+            "ibref_pk1_tangent": (C.c_int, [i32, P, P, P, P, f64, P, P]),
             "ibref_fe_hvp": (C.c_int, [P, P, P, P]),
             "ibref_fe_param_vjp": (C.c_int, [P, P, P, P]),
             "ibref_pressure_vjp": (None, [i32, P, P, f64, P, P]),
@@ -178,14 +188,22 @@ def interpolate(X: np.ndarray, u: np.ndarray) -> np.ndarray:
     return U
 
 
-def pk1(model: int, params, Fm, ef=(1.0, 0.0, 0.0)):
-    par = _f64(list(params) + [0.0] * (5 - len(params)))
+def pk1(model: int, params, Fm, ef=(1.0, 0.0, 0.0), es=None, Ta=0.0):
+    """P and Psi of one law; params padded to the 9 slots; es may be None while
+    a_s = a_fs = 0; Ta is the active tension of HO materials."""
+    par = _f64(_pad(params))
     Fm = _f64(Fm).reshape(3, 3)
     ef = _f64(ef)
+    esp = None if es is None else _f64(es)
     P = np.empty((3, 3))
     psi = C.c_double(0.0)
-    _check(lib().ibref_pk1(model, _p(par), _p(Fm), _p(ef), _p(P), C.byref(psi)), "pk1")
+    _check(lib().ibref_pk1(model, _p(par), _p(Fm), _p(ef), None if esp is None else _p(esp),
+                           float(Ta), _p(P), C.byref(psi)), "pk1")
     return P, psi.value
+
+
+def active_tension(ta_max: float, t_on: float, duration: float, t: float) -> float:
+    return lib().ibref_active_tension(float(ta_max), float(t_on), float(duration), float(t))
 
 
 # --------------------------------------------------------------------------
@@ -193,25 +211,40 @@ def pk1(model: int, params, Fm, ef=(1.0, 0.0, 0.0)):
 # --------------------------------------------------------------------------
 
 class MeshBuffers:
-    """Keeps numpy buffers alive for an ibref_mesh struct."""
+    """Keeps numpy buffers alive for an ibref_mesh struct.  mat_params rows are
+    padded to the 9 slots; sheet may be None while every a_s and a_fs is 0;
+    active = (ta_max, t_on, duration) sets the active-tension waveform that
+    advance and rollout_grad follow; active_tension is the fixed T_a of the
+    single-call functions (fe_force, fe_hvp, ib_step, adjoint_step)."""
 
-    def __init__(self, X_ref, conn, fibre, mat_id, mat_model, mat_params, faces=None):
+    def __init__(self, X_ref, conn, fibre, mat_id, mat_model, mat_params, faces=None,
+                 sheet=None, active_tension=0.0, active=(0.0, 0.0, 0.0)):
         self.X_ref = _f64(X_ref)
         self.conn = _i32(conn)
         self.fibre = _f64(fibre)
         self.mat_id = _i32(mat_id)
         self.mat_model = _i32(mat_model)
-        self.mat_params = _f64(mat_params).reshape(-1, 5)
+        self.mat_params = _f64([_pad(r) for r in np.asarray(mat_params, dtype=np.float64).reshape(
+            len(self.mat_model), -1)])
         self.faces = _i32(np.zeros((0, 4)) if faces is None else faces)
+        self.sheet = None if sheet is None else _f64(sheet)
         self.s = Mesh(self.X_ref.shape[0], self.X_ref.ctypes.data, self.conn.shape[0],
                       self.conn.ctypes.data, self.fibre.ctypes.data, self.mat_id.ctypes.data,
                       self.mat_model.shape[0], self.mat_model.ctypes.data,
-                      self.mat_params.ctypes.data, self.faces.shape[0], self.faces.ctypes.data)
+                      self.mat_params.ctypes.data, self.faces.shape[0], self.faces.ctypes.data,
+                      None if self.sheet is None else self.sheet.ctypes.data,
+                      float(active_tension), *[float(v) for v in active])
+
+    def set_active_tension(self, Ta: float):
+        self.s.active_tension = float(Ta)
+        return self
 
     @classmethod
-    def from_problem(cls, prob):
+    def from_problem(cls, prob, active_tension=0.0):
         models, params = prob.material_arrays()
-        return cls(prob.X_ref, prob.conn, prob.fibre, prob.mat_id, models, params, prob.faces)
+        return cls(prob.X_ref, prob.conn, prob.fibre, prob.mat_id, models, params, prob.faces,
+                   sheet=prob.sheet, active_tension=active_tension,
+                   active=(prob.ta_max, prob.ta_t_on, prob.ta_duration))
 
 
 def fluid(n, rho=1.0, mu=0.01, dt=1e-3, rtol=1e-10, pre=2, post=2, max_cycles=50,
@@ -309,11 +342,14 @@ def interp_vjp_X(X, u, lamU, lamX=None):
     return out
 
 
-def pk1_tangent(model, params, Fm, dFm, ef=(1.0, 0.0, 0.0)):
-    par = _f64(list(params) + [0.0] * (5 - len(params)))
+def pk1_tangent(model, params, Fm, dFm, ef=(1.0, 0.0, 0.0), es=None, Ta=0.0):
+    par = _f64(_pad(params))
     Fm, dFm, ef = _f64(Fm).reshape(3, 3), _f64(dFm).reshape(3, 3), _f64(ef)
+    esp = None if es is None else _f64(es)
     dP = np.empty((3, 3))
-    _check(lib().ibref_pk1_tangent(model, _p(par), _p(Fm), _p(ef), _p(dFm), _p(dP)), "pk1_tangent")
+    _check(lib().ibref_pk1_tangent(model, _p(par), _p(Fm), _p(ef),
+                                   None if esp is None else _p(esp), float(Ta), _p(dFm), _p(dP)),
+           "pk1_tangent")
     return dP
 
 

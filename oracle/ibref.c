@@ -227,27 +227,40 @@ static void cof3(const double* A, double* C) {
 }
 
 /*
- * First Piola-Kirchhoff stress P = dPsi/dF and the energy density Psi.
+ * First Piola-Kirchhoff stress P = dPsi/dF and the energy density Psi
+ * ("Constitutive laws").
  *   common:  J = det F, I1 = tr(F^T F), I1bar = J^{-2/3} I1,
  *            volumetric U(J) = (kappa/2)(ln J)^2 -> kappa ln J F^{-T}
  *   neo-Hookean (params mu_s, kappa), the chordae law of the mitral-valve model
  *            with coefficient a = mu_s / 2:
  *            Psi = (mu_s/2)(I1bar - 3) + U(J)
  *            P   = mu_s J^{-2/3} (F - (I1/3) F^{-T}) + kappa ln J F^{-T}
- *   Holzapfel-Ogden Psi_4 restricted to the isotropic and fibre terms
- *   (params a, b, a_f, b_f, kappa), I4f = e_f . C e_f, I4f* = max(I4f, 1):
+ *   Holzapfel-Ogden Psi_4 (params a, b, a_f, b_f, kappa, a_s, b_s, a_fs, b_fs),
+ *   I4i = e_i . C e_i (i = f, s), I4i* = max(I4i, 1), I8fs = e_f . C e_s:
  *            Psi = a/(2b) (exp(b (I1bar - 3)) - 1)
- *                + a_f/(2 b_f) (exp(b_f (I4f* - 1)^2) - 1) + U(J)
+ *                + sum_i a_i/(2 b_i) (exp(b_i (I4i* - 1)^2) - 1)
+ *                + a_fs/(2 b_fs) (exp(b_fs I8fs^2) - 1) + U(J)
  *            P   = a exp(b (I1bar-3)) J^{-2/3} (F - (I1/3) F^{-T})
- *                + 2 a_f (I4f* - 1) exp(b_f (I4f* - 1)^2) (F e_f) (x) e_f
+ *                + sum_i 2 a_i (I4i* - 1) exp(b_i (I4i* - 1)^2) (F e_i) (x) e_i
+ *                + a_fs I8fs exp(b_fs I8fs^2) ((F e_f) (x) e_s + (F e_s) (x) e_f)
  *                + kappa ln J F^{-T}
  *   (the printed P_4 has F^T in the isotropic bracket where F^{-T} is the
- *   derivative of Psi_4, and its isotropic energy lacks the -1 offset; both
- *   are read as corrected here.)
- * Returns IBREF_E_NUMERIC when J <= 0.
+ *   derivative of Psi_4, its isotropic energy lacks the -1 offset, and its
+ *   fibre-sheet term 2 a_fs I8 e^{..} (F e_f) (x) e_s is not the derivative of
+ *   the printed energy, whose dI8fs/dF = (F e_f) (x) e_s + (F e_s) (x) e_f; all
+ *   three are read as corrected here.)
+ *   Active stress of the myocardium (left-ventricle model): the second
+ *   Piola-Kirchhoff stress S_a = T e_f (x) e_f with T = T_a (1 + 4.9 (sqrt(I4f) - 1))
+ *   is added to HO materials as P_a = F S_a = T (F e_f) (x) e_f (the model
+ *   introduces S_a and then adds it as a first Piola-Kirchhoff stress; the
+ *   push-forward by F is the reading taken).  At frozen T_a it has the potential
+ *   W_a = (T_a/2) ((1 - 4.9)(I4f - 1) + (2/3) 4.9 (I4f^{3/2} - 1)), which is added
+ *   to Psi so that the nodal force stays minus the energy gradient.
+ * Returns IBREF_E_NUMERIC when J <= 0, IBREF_E_INVAL for an unknown model or a
+ * sheet term without es.
  */
-int ibref_pk1(int32_t model, const double* par, const double* Fm, const double* ef, double* P,
-              double* psi) {
+int ibref_pk1(int32_t model, const double* par, const double* Fm, const double* ef,
+              const double* es, double Ta, double* P, double* psi) {
     double J = det3(Fm);
     if (!(J > 0.0)) return IBREF_E_NUMERIC;
     double cof[9], FiT[9];
@@ -258,8 +271,9 @@ int ibref_pk1(int32_t model, const double* par, const double* Fm, const double* 
     double Jm23 = pow(J, -2.0 / 3.0);
     double lnJ = log(J);
     double kappa, iso_coef, energy;
-    double fib_coef = 0.0;
-    double Fe[3] = {0.0, 0.0, 0.0};
+    double fib_coef = 0.0, sh_coef = 0.0, fs_coef = 0.0;
+    double Fe[3] = {0.0, 0.0, 0.0}, Fs[3] = {0.0, 0.0, 0.0};
+    double esv[3] = {0.0, 0.0, 0.0};
     if (model == IBREF_NEO_HOOKEAN) {
         double mu_s = par[0];
         kappa = par[1];
@@ -267,6 +281,7 @@ int ibref_pk1(int32_t model, const double* par, const double* Fm, const double* 
         energy = 0.5 * mu_s * (Jm23 * I1 - 3.0);
     } else if (model == IBREF_HOLZAPFEL_OGDEN) {
         double a = par[0], b = par[1], af = par[2], bf = par[3];
+        double as = par[5], bs = par[6], afs = par[7], bfs = par[8];
         kappa = par[4];
         double E1 = exp(b * (Jm23 * I1 - 3.0));
         iso_coef = a * E1;
@@ -276,7 +291,28 @@ int ibref_pk1(int32_t model, const double* par, const double* Fm, const double* 
         double I4s = I4 > 1.0 ? I4 : 1.0;
         double Ef = exp(bf * (I4s - 1.0) * (I4s - 1.0));
         fib_coef = 2.0 * af * (I4s - 1.0) * Ef;
-        energy += af / (2.0 * bf) * (Ef - 1.0);
+        if (af != 0.0) energy += af / (2.0 * bf) * (Ef - 1.0);
+        if (as != 0.0 || afs != 0.0) {
+            if (!es) return IBREF_E_INVAL;
+            for (int r = 0; r < 3; ++r) {
+                esv[r] = es[r];
+                Fs[r] = Fm[3 * r] * es[0] + Fm[3 * r + 1] * es[1] + Fm[3 * r + 2] * es[2];
+            }
+            double I4sh = Fs[0] * Fs[0] + Fs[1] * Fs[1] + Fs[2] * Fs[2];
+            double I4shs = I4sh > 1.0 ? I4sh : 1.0;
+            double Es = exp(bs * (I4shs - 1.0) * (I4shs - 1.0));
+            sh_coef = 2.0 * as * (I4shs - 1.0) * Es;
+            if (as != 0.0) energy += as / (2.0 * bs) * (Es - 1.0);
+            double I8 = Fe[0] * Fs[0] + Fe[1] * Fs[1] + Fe[2] * Fs[2];
+            double Efs = exp(bfs * I8 * I8);
+            fs_coef = afs * I8 * Efs;
+            if (afs != 0.0) energy += afs / (2.0 * bfs) * (Efs - 1.0);
+        }
+        if (Ta != 0.0) {
+            double r4 = sqrt(I4);
+            fib_coef += Ta * (1.0 + 4.9 * (r4 - 1.0));
+            energy += 0.5 * Ta * ((1.0 - 4.9) * (I4 - 1.0) + (2.0 / 3.0) * 4.9 * (I4 * r4 - 1.0));
+        }
     } else {
         return IBREF_E_INVAL;
     }
@@ -284,9 +320,26 @@ int ibref_pk1(int32_t model, const double* par, const double* Fm, const double* 
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c)
             P[3 * r + c] = iso_coef * Jm23 * (Fm[3 * r + c] - I1 / 3.0 * FiT[3 * r + c]) +
-                           fib_coef * Fe[r] * ef[c] + kappa * lnJ * FiT[3 * r + c];
+                           fib_coef * Fe[r] * ef[c] + sh_coef * Fs[r] * esv[c] +
+                           fs_coef * (Fe[r] * esv[c] + Fs[r] * ef[c]) +
+                           kappa * lnJ * FiT[3 * r + c];
     if (psi) *psi = energy;
     return IBREF_OK;
+}
+
+/*
+ * Active tension waveform of the left-ventricle model: T_a = ta_max (1 -
+ * exp(-(s - 0.5)^2 / 0.005)) for 0.5 < s < 0.65, ta_max (1 - exp(-(0.8 - s)^2 /
+ * 0.005)) for 0.65 <= s < 0.8 (both branches agree at 0.65), 0 otherwise, in
+ * the model's time s (seconds).  Here s = 0.5 + 0.3 (t - t_on) / duration maps
+ * the active window onto [t_on, t_on + duration] of the simulation clock.
+ */
+double ibref_active_tension(double ta_max, double t_on, double duration, double t) {
+    if (ta_max == 0.0 || !(duration > 0.0)) return 0.0;
+    double s = 0.5 + 0.3 * (t - t_on) / duration;
+    if (s > 0.5 && s < 0.65) return ta_max * (1.0 - exp(-(s - 0.5) * (s - 0.5) / 0.005));
+    if (s >= 0.65 && s < 0.8) return ta_max * (1.0 - exp(-(0.8 - s) * (0.8 - s) / 0.005));
+    return 0.0;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -322,9 +375,10 @@ int ibref_fe_force(const ibref_mesh* m, const double* x, double* F, double* ener
         const int32_t* cn = m->conn + 8L * e;
         int mid = m->mat_id[e];
         if (mid < 0 || mid >= m->n_mats) return IBREF_E_INVAL;
-        const double* par = m->mat_params + 5L * mid;
+        const double* par = m->mat_params + (long)IBREF_MAT_PARAMS * mid;
         int model = m->mat_model[mid];
         const double* ef = m->fibre + 3L * e;
+        const double* es = m->sheet ? m->sheet + 3L * e : NULL;
         double Xe[8][3], xe[8][3], Fe[8][3];
         for (int a = 0; a < 8; ++a) {
             if (cn[a] < 0 || cn[a] >= m->n_nodes) return IBREF_E_INVAL;
@@ -362,7 +416,7 @@ int ibref_fe_force(const ibref_mesh* m, const double* x, double* F, double* ener
             double J = det3(Fm);
             if (J < Jmin) Jmin = J;
             double P[9], psi;
-            int rc = ibref_pk1(model, par, Fm, ef, P, &psi);
+            int rc = ibref_pk1(model, par, Fm, ef, es, m->active_tension, P, &psi);
             if (rc) return rc;
             E += psi * w;
             for (int a = 0; a < 8; ++a)
@@ -780,6 +834,13 @@ int ibref_ib_step(const ibref_fluid* fl, const ibref_mesh* m, double* u, double*
     return rc;
 }
 
+/* the solid at time t: the active tension follows the waveform when one is set */
+static ibref_mesh mesh_at(const ibref_mesh* m, double t) {
+    ibref_mesh ms = *m;
+    if (m->ta_max != 0.0) ms.active_tension = ibref_active_tension(m->ta_max, m->ta_t_on, m->ta_duration, t);
+    return ms;
+}
+
 int ibref_advance(const ibref_fluid* fl, const ibref_mesh* m, double* u, double* p, double* X,
                   double t0, int32_t n_steps, double p0, double T, ibref_step_stats* stats) {
     const double pi = 3.14159265358979323846;
@@ -790,7 +851,8 @@ int ibref_advance(const ibref_fluid* fl, const ibref_mesh* m, double* u, double*
             double sn = sin(pi * t / T);
             pr = p0 * sn * sn;
         }
-        int rc = ibref_ib_step(fl, m, u, p, X, pr, stats ? stats + s : NULL);
+        ibref_mesh ms = mesh_at(m, t);
+        int rc = ibref_ib_step(fl, &ms, u, p, X, pr, stats ? stats + s : NULL);
         if (rc) return rc;
     }
     return IBREF_OK;
@@ -935,13 +997,17 @@ void ibref_interp_vjp_X(int32_t n, int32_t n_nodes, const double* X, const doubl
 /*
  * Directional derivative of P (the laws of ibref_pk1) along dF:
  *   d(F^{-T}) = -F^{-T} dF^T F^{-T},  d ln J = F^{-T} : dF,
- *   dI1 = 2 F : dF,  d J^{-2/3} = -(2/3) J^{-2/3} d ln J,  dI4f = 2 (F e) . (dF e),
+ *   dI1 = 2 F : dF,  d J^{-2/3} = -(2/3) J^{-2/3} d ln J,  dI4i = 2 (F e_i) . (dF e_i),
+ *   dI8fs = (dF e_f) . (F e_s) + (F e_f) . (dF e_s),
  *   iso coefficient alpha = mu_s (NH) or a exp(b (I1bar - 3)) (HO),
- *   fibre coefficient f(I4) = 2 a_f (I4-1) exp(b_f (I4-1)^2) for I4 > 1, with
- *   f'(I4) = 2 a_f exp(b_f (I4-1)^2) (1 + 2 b_f (I4-1)^2).
+ *   fibre / sheet coefficient f_i(I4) = 2 a_i (I4-1) exp(b_i (I4-1)^2) for I4 > 1,
+ *   f_i'(I4) = 2 a_i exp(b_i (I4-1)^2) (1 + 2 b_i (I4-1)^2),
+ *   fibre-sheet coefficient g(I8) = a_fs I8 exp(b_fs I8^2),
+ *   g'(I8) = a_fs exp(b_fs I8^2) (1 + 2 b_fs I8^2),
+ *   active coefficient T_a (1 + 4.9 (sqrt(I4f) - 1)), derivative T_a 4.9 / (2 sqrt(I4f)).
  */
 int ibref_pk1_tangent(int32_t model, const double* par, const double* Fm, const double* ef,
-                      const double* dFm, double* dP) {
+                      const double* es, double Ta, const double* dFm, double* dP) {
     double J = det3(Fm);
     if (!(J > 0.0)) return IBREF_E_NUMERIC;
     double cof[9], FiT[9], dFiT[9];
@@ -964,12 +1030,15 @@ int ibref_pk1_tangent(int32_t model, const double* par, const double* Fm, const 
     double lnJ = log(J);
     double alpha, dalpha, kappa;
     double fib = 0.0, dfib = 0.0, Fe[3] = {0, 0, 0}, dFe[3] = {0, 0, 0};
+    double sh = 0.0, dsh = 0.0, Fs[3] = {0, 0, 0}, dFs[3] = {0, 0, 0};
+    double fs = 0.0, dfs = 0.0, esv[3] = {0, 0, 0};
     if (model == IBREF_NEO_HOOKEAN) {
         alpha = par[0];
         dalpha = 0.0;
         kappa = par[1];
     } else if (model == IBREF_HOLZAPFEL_OGDEN) {
         double a = par[0], b = par[1], af = par[2], bf = par[3];
+        double as = par[5], bs = par[6], afs = par[7], bfs = par[8];
         kappa = par[4];
         double E1 = exp(b * (Jm23 * I1 - 3.0));
         alpha = a * E1;
@@ -979,11 +1048,37 @@ int ibref_pk1_tangent(int32_t model, const double* par, const double* Fm, const 
             dFe[r] = dFm[3 * r] * ef[0] + dFm[3 * r + 1] * ef[1] + dFm[3 * r + 2] * ef[2];
         }
         double I4 = Fe[0] * Fe[0] + Fe[1] * Fe[1] + Fe[2] * Fe[2];
+        double dI4 = 2.0 * (Fe[0] * dFe[0] + Fe[1] * dFe[1] + Fe[2] * dFe[2]);
         if (I4 > 1.0) {
-            double dI4 = 2.0 * (Fe[0] * dFe[0] + Fe[1] * dFe[1] + Fe[2] * dFe[2]);
             double Ef = exp(bf * (I4 - 1.0) * (I4 - 1.0));
             fib = 2.0 * af * (I4 - 1.0) * Ef;
             dfib = 2.0 * af * Ef * (1.0 + 2.0 * bf * (I4 - 1.0) * (I4 - 1.0)) * dI4;
+        }
+        if (as != 0.0 || afs != 0.0) {
+            if (!es) return IBREF_E_INVAL;
+            for (int r = 0; r < 3; ++r) {
+                esv[r] = es[r];
+                Fs[r] = Fm[3 * r] * es[0] + Fm[3 * r + 1] * es[1] + Fm[3 * r + 2] * es[2];
+                dFs[r] = dFm[3 * r] * es[0] + dFm[3 * r + 1] * es[1] + dFm[3 * r + 2] * es[2];
+            }
+            double I4s = Fs[0] * Fs[0] + Fs[1] * Fs[1] + Fs[2] * Fs[2];
+            if (I4s > 1.0) {
+                double dI4s = 2.0 * (Fs[0] * dFs[0] + Fs[1] * dFs[1] + Fs[2] * dFs[2]);
+                double Es = exp(bs * (I4s - 1.0) * (I4s - 1.0));
+                sh = 2.0 * as * (I4s - 1.0) * Es;
+                dsh = 2.0 * as * Es * (1.0 + 2.0 * bs * (I4s - 1.0) * (I4s - 1.0)) * dI4s;
+            }
+            double I8 = Fe[0] * Fs[0] + Fe[1] * Fs[1] + Fe[2] * Fs[2];
+            double dI8 = dFe[0] * Fs[0] + dFe[1] * Fs[1] + dFe[2] * Fs[2] +
+                         Fe[0] * dFs[0] + Fe[1] * dFs[1] + Fe[2] * dFs[2];
+            double Efs = exp(bfs * I8 * I8);
+            fs = afs * I8 * Efs;
+            dfs = afs * Efs * (1.0 + 2.0 * bfs * I8 * I8) * dI8;
+        }
+        if (Ta != 0.0) {
+            double r4 = sqrt(I4);
+            fib += Ta * (1.0 + 4.9 * (r4 - 1.0));
+            dfib += Ta * 4.9 / (2.0 * r4) * dI4;
         }
     } else {
         return IBREF_E_INVAL;
@@ -995,6 +1090,8 @@ int ibref_pk1_tangent(int32_t model, const double* par, const double* Fm, const 
             double dM = dFm[o] - dI1 / 3.0 * FiT[o] - I1 / 3.0 * dFiT[o];
             dP[o] = (dalpha * Jm23 + alpha * dJm23) * M + alpha * Jm23 * dM +
                     dfib * Fe[r] * ef[c] + fib * dFe[r] * ef[c] +
+                    dsh * Fs[r] * esv[c] + sh * dFs[r] * esv[c] +
+                    dfs * (Fe[r] * esv[c] + Fs[r] * ef[c]) + fs * (dFe[r] * esv[c] + dFs[r] * ef[c]) +
                     kappa * dlnJ * FiT[o] + kappa * lnJ * dFiT[o];
         }
     return IBREF_OK;
@@ -1010,9 +1107,10 @@ static int fe_derivative_loop(const ibref_mesh* m, const double* x, const double
         const int32_t* cn = m->conn + 8L * e;
         int mid = m->mat_id[e];
         if (mid < 0 || mid >= m->n_mats) return IBREF_E_INVAL;
-        const double* par = m->mat_params + 5L * mid;
+        const double* par = m->mat_params + (long)IBREF_MAT_PARAMS * mid;
         int model = m->mat_model[mid];
         const double* ef = m->fibre + 3L * e;
+        const double* es = m->sheet ? m->sheet + 3L * e : NULL;
         double Xe[8][3], xe[8][3], ve[8][3], He[8][3];
         for (int a = 0; a < 8; ++a)
             for (int r = 0; r < 3; ++r) {
@@ -1051,7 +1149,7 @@ static int fe_derivative_loop(const ibref_mesh* m, const double* x, const double
                     }
             if (mode == 0) {
                 double dP[9];
-                int rc = ibref_pk1_tangent(model, par, Fm, ef, dF, dP);
+                int rc = ibref_pk1_tangent(model, par, Fm, ef, es, m->active_tension, dF, dP);
                 if (rc) return rc;
                 for (int a = 0; a < 8; ++a)
                     for (int r = 0; r < 3; ++r) {
@@ -1240,7 +1338,8 @@ int ibref_rollout_grad(const ibref_fluid* fl, const ibref_mesh* m, const double*
         }
         memcpy(us + 3 * N3 * (s + 1), us + 3 * N3 * s, sizeof(double) * 3 * (size_t)N3);
         memcpy(Xs + nn3 * (s + 1), Xs + nn3 * s, sizeof(double) * (size_t)nn3);
-        rc = ibref_ib_step(fl, m, us + 3 * N3 * (s + 1), p, Xs + nn3 * (s + 1), pr[s], NULL);
+        ibref_mesh ms = mesh_at(m, t);
+        rc = ibref_ib_step(fl, &ms, us + 3 * N3 * (s + 1), p, Xs + nn3 * (s + 1), pr[s], NULL);
     }
     if (!rc) {
         const double* XN = Xs + nn3 * n_steps;
@@ -1252,9 +1351,11 @@ int ibref_rollout_grad(const ibref_fluid* fl, const ibref_mesh* m, const double*
         }
         *loss = L;
         double* lam_u = (double*)calloc(3 * (size_t)N3, sizeof(double));
-        for (int s = n_steps - 1; s >= 0 && !rc; --s)
-            rc = ibref_adjoint_step(fl, m, us + 3 * N3 * s, Xs + nn3 * s, us + 3 * N3 * (s + 1), pr[s],
-                                    lam_u, dLdX0, dtheta);
+        for (int s = n_steps - 1; s >= 0 && !rc; --s) {
+            ibref_mesh ms = mesh_at(m, t0 + s * fl->dt);
+            rc = ibref_adjoint_step(fl, &ms, us + 3 * N3 * s, Xs + nn3 * s, us + 3 * N3 * (s + 1),
+                                    pr[s], lam_u, dLdX0, dtheta);
+        }
         free(lam_u);
     }
     free(us); free(Xs); free(p); free(pr);

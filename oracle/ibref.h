@@ -31,6 +31,7 @@ extern "C" {
 
 enum { IBREF_OK = 0, IBREF_E_INVAL = 1, IBREF_E_NOCONV = 4, IBREF_E_NUMERIC = 5 };
 enum { IBREF_NEO_HOOKEAN = 0, IBREF_HOLZAPFEL_OGDEN = 1 };
+#define IBREF_MAT_PARAMS 9         /* parameter slots per material */
 
 typedef struct {
     int32_t n;                 /* cells per side */
@@ -54,9 +55,16 @@ typedef struct {
     const int32_t* mat_id;     /* [n_elems] */
     int32_t n_mats;
     const int32_t* mat_model;  /* [n_mats] IBREF_NEO_HOOKEAN / IBREF_HOLZAPFEL_OGDEN */
-    const double* mat_params;  /* [n_mats][5]: NH (mu_s, kappa); HO (a, b, a_f, b_f, kappa) */
+    const double* mat_params;  /* [n_mats][IBREF_MAT_PARAMS]: NH (mu_s, kappa, 0...);
+                                  HO (a, b, a_f, b_f, kappa, a_s, b_s, a_fs, b_fs) */
     int32_t n_faces;
     const int32_t* faces;      /* [n_faces][4] pressure-loaded quads */
+    const double* sheet;       /* [n_elems][3] unit sheet e_s (reference, orthogonal to e_f);
+                                  NULL allowed while every a_s and a_fs is 0 */
+    double active_tension;     /* T_a of the active fibre stress of HO materials (force,
+                                  Hessian product); ibref_advance and ibref_rollout_grad set
+                                  it per step from the waveform below when ta_max != 0 */
+    double ta_max, ta_t_on, ta_duration;  /* active-tension waveform (ibref_active_tension) */
 } ibref_mesh;
 
 typedef struct {
@@ -78,8 +86,13 @@ void ibref_spread(int32_t n, int32_t n_nodes, const double* X, const double* F, 
 void ibref_interpolate(int32_t n, int32_t n_nodes, const double* X, const double* u, double* U); /* U = J(X)u */
 
 /* --- solid mechanics --- */
+/* P = dPsi/dF (+ the active stress for HO) and Psi (+ the active potential);
+ * es may be NULL when a_s = a_fs = 0; Ta is the active tension T_a(t) */
 int ibref_pk1(int32_t model, const double* params, const double* Fm /*[3][3] row-major*/,
-              const double* ef, double* P /*[3][3]*/, double* psi);
+              const double* ef, const double* es, double Ta, double* P /*[3][3]*/, double* psi);
+/* T_a(t): ta_max times the left-ventricle activation shape, whose window
+ * (0.5, 0.8) is mapped onto [t_on, t_on + duration] */
+double ibref_active_tension(double ta_max, double t_on, double duration, double t);
 int ibref_fe_force(const ibref_mesh* m, const double* x, double* F /*[n_nodes][3], :=*/,
                    double* energy, double* min_J);
 void ibref_pressure_load(int32_t n_faces, const int32_t* faces, const double* x, double p,
@@ -116,7 +129,7 @@ void ibref_interp_vjp_X(int32_t n, int32_t n_nodes, const double* X, const doubl
                         const double* lamU, double* lamX);
 /* dP = dP/dF : dF (directional derivative of the first Piola-Kirchhoff stress) */
 int ibref_pk1_tangent(int32_t model, const double* params, const double* Fm, const double* ef,
-                      const double* dFm, double* dP);
+                      const double* es, double Ta, const double* dFm, double* dP);
 /* HV = (dF/dx) V, the directional derivative of the elastic nodal force
  * (minus the strain-energy Hessian times V); overwritten */
 int ibref_fe_hvp(const ibref_mesh* m, const double* x, const double* V, double* HV);

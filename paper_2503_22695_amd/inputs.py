@@ -14,7 +14,10 @@ image-based left ventricle and valve meshes are not available):
   transmural fibre rotation from -60 deg (epicardium) to +60 deg (endocardium)
   and an endocardial pressure surface;
 * ``leaflets`` -- two one-element-thick half-annular sheets across the shell
-  base (valve stand-in).
+  base (valve stand-in);
+* ``lv`` -- the shell (or a block) with the full Holzapfel-Ogden law of the
+  left-ventricle model (sheet and fibre-sheet terms, parameter ratios of its
+  table), transmural sheet directions and an active-tension pulse.
 
 Hex local node ``a = i + 2 j + 4 k`` sits at reference coordinates
 ``(xi, eta, zeta) = (2i-1, 2j-1, 2k-1)``; every element is oriented so its
@@ -34,6 +37,8 @@ import numpy as np
 NEO_HOOKEAN = 0
 HOLZAPFEL_OGDEN = 1
 
+MAT_PARAMS = 9   # parameter slots per material
+
 HEX_CORNERS = np.array([[i, j, k] for k in (0, 1) for j in (0, 1) for i in (0, 1)],
                        dtype=np.int64)  # a = i + 2j + 4k
 
@@ -41,11 +46,11 @@ HEX_CORNERS = np.array([[i, j, k] for k in (0, 1) for j in (0, 1) for i in (0, 1
 @dataclasses.dataclass
 class Material:
     model: int
-    params: Tuple[float, ...]  # NH: (mu_s, kappa); HO: (a, b, a_f, b_f, kappa)
+    params: Tuple[float, ...]  # NH: (mu_s, kappa); HO: (a, b, a_f, b_f, kappa[, a_s, b_s, a_fs, b_fs])
 
     def padded(self) -> List[float]:
-        p = list(self.params) + [0.0] * (5 - len(self.params))
-        return p[:5]
+        p = list(self.params) + [0.0] * (MAT_PARAMS - len(self.params))
+        return p[:MAT_PARAMS]
 
 
 @dataclasses.dataclass
@@ -67,6 +72,10 @@ class Problem:
     p0: float = 0.0            # endocardial pressure amplitude
     T: float = 1.0             # pressure pulse period: p(t) = p0 sin^2(pi t / T)
     u0: Optional[np.ndarray] = None   # [3, n, n, n] float64 initial velocity (None = rest)
+    sheet: Optional[np.ndarray] = None  # [n_elems, 3] unit sheet e_s (orthogonal to e_f)
+    ta_max: float = 0.0        # active tension amplitude (0: passive)
+    ta_t_on: float = 0.0       # the activation window [ta_t_on, ta_t_on + ta_duration]
+    ta_duration: float = 0.0
     mg_rtol: float = 1e-10
     mg_pre: int = 2
     mg_post: int = 2
@@ -160,14 +169,16 @@ def block_mesh(n_el: int, side: float, centre=(0.5, 0.5, 0.5)):
     return X, _orient(conn, X)
 
 
-def shell_mesh(n_theta: int, n_psi: int, n_tau: int, h: float, cx: float = 0.325):
+def shell_mesh(n_theta: int, n_psi: int, n_tau: int, h: float, cx: float = 0.325,
+               with_sheet: bool = False):
     """Truncated ellipsoidal shell.
 
     Node (it, ip, iq) with theta = 2 pi it / n_theta, psi linear in ip from the
     apex-hole angle psi_a to pi/2, tau = iq / n_tau (0 = endocardium):
         X = (cx + A cos psi, 0.5 + B sin psi cos theta, 0.5 + B sin psi sin theta)
         A = 0.31 + 0.04 tau,  B = 0.21 + 0.04 tau.
-    The apex hole has endocardial radius 2h.  Returns X_ref, conn, fibre, faces.
+    The apex hole has endocardial radius 2h.  Returns X_ref, conn, fibre, faces
+    (and the transmural sheet field when with_sheet).
     """
     psi_a = math.asin(2.0 * h / 0.21)
     th = 2.0 * math.pi * np.arange(n_theta) / n_theta
@@ -204,6 +215,10 @@ def shell_mesh(n_theta: int, n_psi: int, n_tau: int, h: float, cx: float = 0.325
     alpha = np.deg2rad(60.0 - 120.0 * tac)        # +60 endo (tau=0) .. -60 epi (tau=1)
     fibre = np.cos(alpha)[:, None] * e_th + np.sin(alpha)[:, None] * e_ps
     fibre /= np.linalg.norm(fibre, axis=1, keepdims=True)
+    # transmural sheet direction: normal to the wall, Gram-Schmidt against the fibre
+    sheet = np.cross(e_th, e_ps)
+    sheet -= np.einsum("ei,ei->e", sheet, fibre)[:, None] * fibre
+    sheet /= np.linalg.norm(sheet, axis=1, keepdims=True)
 
     # endocardial quads (iq = 0), oriented to point into the cavity (towards -d/dtau)
     f0, f1 = np.meshgrid(np.arange(n_theta), np.arange(n_psi), indexing="ij")
@@ -211,6 +226,8 @@ def shell_mesh(n_theta: int, n_psi: int, n_tau: int, h: float, cx: float = 0.325
     faces = np.stack([nid(f0, f1, 0), nid(f0 + 1, f1, 0), nid(f0, f1 + 1, 0),
                       nid(f0 + 1, f1 + 1, 0)], axis=1)
     faces = _orient_faces(faces, X, inward_ref=nid(f0, f1, 1))
+    if with_sheet:
+        return X, conn, fibre, faces, np.ascontiguousarray(sheet)
     return X, conn, fibre, faces
 
 
@@ -295,6 +312,18 @@ def solenoidal_velocity(n: int, seed: int, amplitude: float, kmax: int = 4) -> n
 HO_PARAMS = (0.5, 5.0, 1.5, 8.0, 7.0)      # a, b, a_f, b_f, kappa (kappa = 14 a)
 NH_BLOCK = (10.0, 100.0)                   # mu_s, kappa
 
+# Left-ventricle table (a, b, a_f, b_f, a_s, b_s, a_fs, b_fs in dyn/cm^2 and 1),
+# scaled so that a matches HO_PARAMS; kappa = 14 a as for HO_PARAMS.
+_LV_TABLE = dict(a=2244.87, b=1.6215, af=24267.0, bf=1.8268, as_=5562.38, bs=0.7746,
+                 afs=3905.16, bfs=1.695)
+_LV_SCALE = HO_PARAMS[0] / _LV_TABLE["a"]
+LV_PARAMS = (HO_PARAMS[0], _LV_TABLE["b"], _LV_TABLE["af"] * _LV_SCALE, _LV_TABLE["bf"],
+             14.0 * HO_PARAMS[0], _LV_TABLE["as_"] * _LV_SCALE, _LV_TABLE["bs"],
+             _LV_TABLE["afs"] * _LV_SCALE, _LV_TABLE["bfs"])
+# active tension amplitude relative to the peak cavity pressure: 84260 Pa against
+# the 14530 Pa systolic maximum of the left-ventricle model
+LV_TA_OVER_P = 84260.0 / 14530.0
+
 
 def _block_problem(name, n, n_el, dt, n_steps, material, fibre_seed=None,
                    seed=0) -> Problem:
@@ -344,6 +373,41 @@ def ho_shell(n: int = 128, n_theta: int = 224, n_psi: int = 80, n_tau: int = 6,
                    faces=faces.astype(np.int32), p0=1.0, T=n_steps * dt)
 
 
+def lv_shell(n: int = 128, n_theta: int = 224, n_psi: int = 80, n_tau: int = 6,
+             n_steps: int = 100, dt: float = 5e-4) -> Problem:
+    """The shell with the full Holzapfel-Ogden law (LV_PARAMS), transmural
+    sheets and one active-tension pulse over the run, peak at mid-run like the
+    cavity pressure pulse."""
+    h = 1.0 / n
+    X, conn, fibre, faces, sheet = shell_mesh(n_theta, n_psi, n_tau, h, with_sheet=True)
+    ne = conn.shape[0]
+    p0 = 1.0
+    return Problem(name=f"lv_shell_{n}", n=n, rho=1.0, mu=0.01, dt=dt, n_steps=n_steps,
+                   X_ref=X, X0=X.copy(), conn=conn.astype(np.int32),
+                   fibre=np.ascontiguousarray(fibre), mat_id=np.zeros(ne, dtype=np.int32),
+                   materials=[Material(HOLZAPFEL_OGDEN, LV_PARAMS)],
+                   faces=faces.astype(np.int32), p0=p0, T=n_steps * dt, sheet=sheet,
+                   ta_max=LV_TA_OVER_P * p0, ta_t_on=0.0, ta_duration=n_steps * dt)
+
+
+def lv_block(n: int = 32, n_el: int = 6, n_steps: int = 20, seed: int = 0,
+             frame_seed: int = 2) -> Problem:
+    """Block with the full Holzapfel-Ogden law (LV_PARAMS), a random orthonormal
+    fibre / sheet pair per element and an active-tension pulse over the run."""
+    p = _block_problem(f"lv_block_{n}", n, n_el, 1e-3, n_steps,
+                       Material(HOLZAPFEL_OGDEN, LV_PARAMS), seed=seed)
+    rng = np.random.default_rng(frame_seed)
+    ne = p.n_elems
+    f = rng.standard_normal((ne, 3))
+    f /= np.linalg.norm(f, axis=1, keepdims=True)
+    s = rng.standard_normal((ne, 3))
+    s -= np.einsum("ei,ei->e", s, f)[:, None] * f
+    s /= np.linalg.norm(s, axis=1, keepdims=True)
+    p.fibre, p.sheet = np.ascontiguousarray(f), np.ascontiguousarray(s)
+    p.ta_max, p.ta_t_on, p.ta_duration = 2.0, 0.0, n_steps * p.dt
+    return p
+
+
 def shell_with_leaflets(n: int = 192, n_steps: int = 50, dt: float = 5e-4,
                         seed: int = 0) -> Problem:
     """The shell (288 x 104 x 8 hexes) plus two neo-Hookean leaflets and a random
@@ -385,8 +449,12 @@ def workload(name: str) -> Problem:
         return p
     if name == "ho_block_64":        # adjoint workload, 64^3, 50 steps
         return ho_block()
+    if name == "lv_shell_128":       # full HO + active tension, 128^3, 100 steps
+        return lv_shell()
+    if name == "lv_block_32":        # full HO + active tension, 32^3, 20 steps
+        return lv_block()
     raise KeyError(name)
 
 
 WORKLOADS = ("nh_block_32", "ho_shell_128", "shell_leaflets_192",
-             "nh_block_32_mixed", "ho_block_64")
+             "nh_block_32_mixed", "ho_block_64", "lv_shell_128", "lv_block_32")
