@@ -101,10 +101,35 @@ hipib_status hipib_set_mesh(hipib_ctx* ctx, int32_t n_nodes, const double* X_ref
                             const int32_t* mat_id);
 /* Material law of one id ("Constitutive laws"): neo-Hookean params
  * (mu_s, kappa), Psi = mu_s/2 (I1bar - 3) + kappa/2 (ln J)^2; Holzapfel-Ogden
- * params (a, b, a_f, b_f, kappa), Psi = a/(2b)(e^{b(I1bar-3)} - 1)
- * + a_f/(2b_f)(e^{b_f (I4f*-1)^2} - 1) + kappa/2 (ln J)^2, I4f* = max(I4f, 1). */
+ * params (a, b, a_f, b_f, kappa[, a_s, b_s, a_fs, b_fs]) (n_params 5 or 9;
+ * 5 means a_s = a_fs = 0):
+ *   Psi = a/(2b)(e^{b(I1bar-3)} - 1) + sum_{i=f,s} a_i/(2b_i)(e^{b_i (I4i*-1)^2} - 1)
+ *       + a_fs/(2b_fs)(e^{b_fs I8fs^2} - 1) + kappa/2 (ln J)^2,
+ * I4i = e_i.C e_i, I4i* = max(I4i, 1), I8fs = e_f.C e_s; the fibre-sheet stress
+ * is the derivative of this energy, a_fs I8 e^{b_fs I8^2} F (e_f(x)e_s + e_s(x)e_f).
+ * Requires a, a_f, a_s, a_fs, kappa >= 0, b, b_f > 0, and b_s (b_fs) > 0 when
+ * a_s (a_fs) > 0.  A material with a_s or a_fs > 0 needs hipib_set_sheets. */
 hipib_status hipib_set_material(hipib_ctx* ctx, int32_t mat_id, int32_t model,
                                 const double* params, int32_t n_params);
+/* Sheet directions e_s of the elements (host [n_elems][3], unit, orthogonal to
+ * the fibre, reference configuration; n_elems must equal the mesh's).  Dropped
+ * by the next hipib_set_mesh. */
+hipib_status hipib_set_sheets(hipib_ctx* ctx, int32_t n_elems, const double* sheet);
+/* Active stress of the myocardium (the left-ventricle model): Holzapfel-Ogden
+ * materials get P_a = T (F e_f) (x) e_f, the push-forward of the second
+ * Piola-Kirchhoff stress S_a = T e_f (x) e_f, with T = T_a (1 + 4.9 (sqrt(I4f) - 1)).
+ * hipib_set_active_tension sets the T_a used by hipib_fe_force, hipib_ib_step,
+ * hipib_adjoint_step and hipib_fe_hvp (0 on creation; must be finite). */
+hipib_status hipib_set_active_tension(hipib_ctx* ctx, double Ta);
+/* T_a(t) of the left-ventricle model's activation, ta_max (1 - e^{-(s-0.5)^2/0.005})
+ * for 0.5 < s < 0.65 and ta_max (1 - e^{-(0.8-s)^2/0.005}) for 0.65 <= s < 0.8,
+ * 0 otherwise, with its window mapped onto the simulation clock by
+ * s = 0.5 + 0.3 (t - t_on) / duration (0 when duration <= 0). */
+double hipib_active_tension(double ta_max, double t_on, double duration, double t);
+/* Activation followed by hipib_advance: with ta_max != 0 each step n sets the
+ * active tension to hipib_active_tension(ta_max, t_on, duration, t_n) before it
+ * runs (the last step's value stays set).  ta_max = 0 switches this off. */
+hipib_status hipib_set_active_waveform(hipib_ctx* ctx, double ta_max, double t_on, double duration);
 /* Quads loaded by the uniform cavity pressure (host [n_faces][4]). */
 hipib_status hipib_set_pressure_faces(hipib_ctx* ctx, int32_t n_faces, const int32_t* faces);
 
@@ -133,7 +158,8 @@ hipib_status hipib_ns_step(hipib_ctx* ctx, const double* f, double* u, double* p
  * f = S(X^n)F, ns_step, X += dt J(X^n) u^{n+1}.  X: [n_nodes][3] in/out. */
 hipib_status hipib_ib_step(hipib_ctx* ctx, double* u, double* p, double* X, double pressure);
 /* n_steps IB steps from time t0 with cavity pressure p0 sin^2(pi t_n / T)
- * (0 when T <= 0), t_n = t0 + n dt. */
+ * (0 when T <= 0), t_n = t0 + n dt, and the active tension of
+ * hipib_set_active_waveform when one is set. */
 hipib_status hipib_advance(hipib_ctx* ctx, double* u, double* p, double* X, double t0,
                            int32_t n_steps, double p0, double T);
 
@@ -153,7 +179,9 @@ int32_t hipib_get_step_stats(hipib_ctx* ctx, int32_t* cycles, double* relres,
  * spreading, the force's transpose product is the strain-energy Hessian-vector
  * product, the projection's adjoint is the projection.  dtheta is a device
  * array [HIPIB_MAX_MATERIALS][4] that is accumulated into (+=); entries of
- * neo-Hookean materials stay unchanged. */
+ * neo-Hookean materials stay unchanged.  The sheet, fibre-sheet and active
+ * terms enter the Hessian products (so lam_X and lam_u are exact for the full
+ * law) but their constants get no gradient. */
 /* Reverse of one hipib_ib_step from (u_n, X_n) at cavity pressure `pressure`,
  * whose result velocity was u_np1.  lam_u in: dL/du^{n+1}, out: dL/du^n;
  * lam_X in: dL/dX^{n+1}, out: dL/dX^n.  The adjoint Poisson and Helmholtz

@@ -134,8 +134,9 @@ k_vjp_X(const double* __restrict__ X, const double* __restrict__ field,
 __global__ void __launch_bounds__(128)
 k_fe_hvp(const double* __restrict__ X, const double* __restrict__ Xref,
          const int32_t* __restrict__ conn, const double* __restrict__ fibre,
-         const int32_t* __restrict__ mat_id, MatTable mats, int ne, const double* __restrict__ V,
-         double* __restrict__ out, MGState* st, double* __restrict__ contrib) {
+         const double* __restrict__ sheet, const int32_t* __restrict__ mat_id, MatTable mats,
+         double Ta, int ne, const double* __restrict__ V, double* __restrict__ out, MGState* st,
+         double* __restrict__ contrib) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
     int nd[8];
@@ -152,6 +153,14 @@ k_fe_hvp(const double* __restrict__ X, const double* __restrict__ Xref,
     const int model = mats.model[m];
     const double* par = mats.p[m];
     const double ef[3] = {fibre[3 * e], fibre[3 * e + 1], fibre[3 * e + 2]};
+    const bool sh = mats.sheet[m] != 0;
+    double es[3] = {0.0, 0.0, 0.0};
+    if (sh) {
+        es[0] = sheet[3 * e];
+        es[1] = sheet[3 * e + 1];
+        es[2] = sheet[3 * e + 2];
+    }
+    const double ta = model == HIPIB_HOLZAPFEL_OGDEN ? Ta : 0.0;
     const double gp = 0.57735026918962576451;
     bool bad = false;
     for (int g = 0; g < 8; ++g) {
@@ -171,7 +180,7 @@ k_fe_hvp(const double* __restrict__ X, const double* __restrict__ Xref,
         double Fm[9], dF[9], dP[9];
         matmul3(Jx, Jri, Fm);
         matmul3(Jv, Jri, dF);
-        if (!pk1_tangent<double>(model, par, Fm, ef, dF, dP)) { bad = true; continue; }
+        if (!pk1_tangent<double>(model, par, Fm, ef, es, sh, ta, dF, dP)) { bad = true; continue; }
         double Q[9];
         for (int r = 0; r < 3; ++r)
             for (int s = 0; s < 3; ++s)
@@ -439,8 +448,9 @@ hipib_status adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n, 
         HIPIB_TRY(vjp_X(ctx, X_n, ctx->adj_lg, ctx->F, lam_X, 1.0 / (h * h3)));    // spreading term
         if (ctx->ne > 0) {
             k_fe_hvp<<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
-                X_n, ctx->Xref, ctx->conn, ctx->fibre, ctx->mat_id, ctx->mats, ctx->ne,
-                ctx->adj_lamF, lam_X, ctx->st, det ? ctx->det_contrib : nullptr);
+                X_n, ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats,
+                ctx->active_ta, ctx->ne, ctx->adj_lamF, lam_X, ctx->st,
+                det ? ctx->det_contrib : nullptr);
             HIPIB_HIP(hipGetLastError());
             if (det) HIPIB_TRY(det_gather_nodes(ctx, false, true, lam_X));
             k_fe_param_vjp<<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
@@ -478,9 +488,9 @@ hipib_status launch_fe_hvp(hipib_ctx* ctx, const double* X, const double* V, dou
     HIPIB_TRY(launch_zero(ctx, out, 3 * (int64_t)ctx->nn));
     if (ctx->ne == 0) return HIPIB_OK;
     const bool det = ctx->cfg.deterministic != 0;
-    k_fe_hvp<<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(X, ctx->Xref, ctx->conn, ctx->fibre,
-                                                             ctx->mat_id, ctx->mats, ctx->ne, V, out,
-                                                             ctx->st, det ? ctx->det_contrib : nullptr);
+    k_fe_hvp<<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
+        X, ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats, ctx->active_ta,
+        ctx->ne, V, out, ctx->st, det ? ctx->det_contrib : nullptr);
     HIPIB_HIP(hipGetLastError());
     if (det) HIPIB_TRY(det_gather_nodes(ctx, false, true, out));
     return HIPIB_OK;

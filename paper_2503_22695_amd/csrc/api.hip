@@ -49,6 +49,10 @@ hipib_status check_mesh_ready(hipib_ctx* ctx) {
         for (int m = 0; m < HIPIB_MAX_MATERIALS; ++m)
             if (missing & (1u << m)) return fail(HIPIB_E_STATE, "material %d is used but not set", m);
     }
+    if (!ctx->sheet && ctx->ne > 0)
+        for (int m = 0; m < HIPIB_MAX_MATERIALS; ++m)
+            if ((ctx->mat_used & (1u << m)) && ctx->mats.sheet[m])
+                return fail(HIPIB_E_STATE, "material %d has sheet terms but no sheets are set", m);
     return HIPIB_OK;
 }
 
@@ -69,6 +73,7 @@ void free_mesh(hipib_ctx* ctx) {
     (void)hipFree(ctx->Xref);
     (void)hipFree(ctx->conn);
     (void)hipFree(ctx->fibre);
+    (void)hipFree(ctx->sheet);
     (void)hipFree(ctx->mat_id);
     (void)hipFree(ctx->F);
     (void)hipFree(ctx->node_tile);
@@ -80,6 +85,7 @@ void free_mesh(hipib_ctx* ctx) {
     ctx->Xref = nullptr;
     ctx->conn = nullptr;
     ctx->fibre = nullptr;
+    ctx->sheet = nullptr;
     ctx->mat_id = nullptr;
     ctx->F = nullptr;
     ctx->mesh_set = false;
@@ -362,15 +368,13 @@ hipib_status hipib_set_material(hipib_ctx* ctx, int32_t mat_id, int32_t model, c
     HIPIB_TRY(check_ctx(ctx));
     if (mat_id < 0 || mat_id >= HIPIB_MAX_MATERIALS) return fail(HIPIB_E_INVAL, "mat_id out of range");
     if (!params) return fail(HIPIB_E_INVAL, "null params");
-    double p[5] = {0, 0, 0, 0, 0};
+    double p[kMatParams] = {};
     if (model == HIPIB_NEO_HOOKEAN) {
         if (n_params != 2) return fail(HIPIB_E_INVAL, "neo-Hookean takes (mu_s, kappa)");
-        if (!(params[0] >= 0) || !(params[1] >= 0)) return fail(HIPIB_E_INVAL, "negative modulus");
     } else if (model == HIPIB_HOLZAPFEL_OGDEN) {
-        if (n_params != 5) return fail(HIPIB_E_INVAL, "Holzapfel-Ogden takes (a, b, a_f, b_f, kappa)");
-        if (!(params[0] >= 0) || !(params[1] > 0) || !(params[2] >= 0) || !(params[3] > 0) ||
-            !(params[4] >= 0))
-            return fail(HIPIB_E_INVAL, "Holzapfel-Ogden needs a, a_f, kappa >= 0 and b, b_f > 0");
+        if (n_params != 5 && n_params != kMatParams)
+            return fail(HIPIB_E_INVAL,
+                        "Holzapfel-Ogden takes (a, b, a_f, b_f, kappa[, a_s, b_s, a_fs, b_fs])");
     } else {
         return fail(HIPIB_E_INVAL, "unknown material model %d", model);
     }
@@ -378,9 +382,67 @@ hipib_status hipib_set_material(hipib_ctx* ctx, int32_t mat_id, int32_t model, c
         if (!std::isfinite(params[t])) return fail(HIPIB_E_INVAL, "non-finite parameter");
         p[t] = params[t];
     }
+    if (model == HIPIB_NEO_HOOKEAN) {
+        if (!(p[0] >= 0) || !(p[1] >= 0)) return fail(HIPIB_E_INVAL, "negative modulus");
+    } else {
+        if (!(p[0] >= 0) || !(p[1] > 0) || !(p[2] >= 0) || !(p[3] > 0) || !(p[4] >= 0))
+            return fail(HIPIB_E_INVAL, "Holzapfel-Ogden needs a, a_f, kappa >= 0 and b, b_f > 0");
+        if (!(p[5] >= 0) || !(p[6] >= 0) || !(p[7] >= 0) || !(p[8] >= 0) ||
+            (p[5] > 0 && !(p[6] > 0)) || (p[7] > 0 && !(p[8] > 0)))
+            return fail(HIPIB_E_INVAL, "sheet terms need a_s, a_fs >= 0 and b_s, b_fs > 0 where used");
+    }
     ctx->mats.model[mat_id] = model;
-    for (int t = 0; t < 5; ++t) ctx->mats.p[mat_id][t] = p[t];
+    ctx->mats.sheet[mat_id] = (model == HIPIB_HOLZAPFEL_OGDEN && (p[5] > 0 || p[7] > 0)) ? 1 : 0;
+    for (int t = 0; t < kMatParams; ++t) ctx->mats.p[mat_id][t] = p[t];
     ctx->mat_set |= 1u << mat_id;
+    return HIPIB_OK;
+}
+
+hipib_status hipib_set_sheets(hipib_ctx* ctx, int32_t n_elems, const double* sheet) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
+    if (n_elems != ctx->ne) return fail(HIPIB_E_INVAL, "n_elems %d != mesh's %d", n_elems, ctx->ne);
+    if (n_elems > 0 && !sheet) return fail(HIPIB_E_INVAL, "null sheet");
+    for (int64_t t = 0; t < 3 * (int64_t)n_elems; ++t)
+        if (!std::isfinite(sheet[t])) return fail(HIPIB_E_INVAL, "non-finite sheet");
+    HIPIB_HIP(hipStreamSynchronize(ctx->stream));
+    (void)hipFree(ctx->sheet);
+    ctx->sheet = nullptr;
+    double* d = nullptr;
+    HIPIB_TRY(dev_alloc(ctx, &d, 3 * (size_t)n_elems));
+    if (n_elems > 0) {
+        hipError_t e = hipMemcpy(d, sheet, 3 * sizeof(double) * n_elems, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return hip_fail(ctx, e, "hipMemcpy(sheet)", __FILE__, __LINE__);
+        }
+    }
+    ctx->sheet = d;
+    return HIPIB_OK;
+}
+
+hipib_status hipib_set_active_tension(hipib_ctx* ctx, double Ta) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (!std::isfinite(Ta)) return fail(HIPIB_E_INVAL, "non-finite active tension");
+    ctx->active_ta = Ta;
+    return HIPIB_OK;
+}
+
+double hipib_active_tension(double ta_max, double t_on, double duration, double t) {
+    if (ta_max == 0.0 || !(duration > 0.0)) return 0.0;
+    const double s = 0.5 + 0.3 * (t - t_on) / duration;
+    if (s > 0.5 && s < 0.65) return ta_max * (1.0 - std::exp(-(s - 0.5) * (s - 0.5) / 0.005));
+    if (s >= 0.65 && s < 0.8) return ta_max * (1.0 - std::exp(-(0.8 - s) * (0.8 - s) / 0.005));
+    return 0.0;
+}
+
+hipib_status hipib_set_active_waveform(hipib_ctx* ctx, double ta_max, double t_on, double duration) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (!std::isfinite(ta_max) || !std::isfinite(t_on) || !std::isfinite(duration) || duration < 0)
+        return fail(HIPIB_E_INVAL, "bad active-tension waveform");
+    ctx->ta_max = ta_max;
+    ctx->ta_t_on = t_on;
+    ctx->ta_duration = duration;
     return HIPIB_OK;
 }
 
@@ -473,6 +535,8 @@ hipib_status hipib_advance(hipib_ctx* ctx, double* u, double* p, double* X, doub
             const double sn = std::sin(pi * t / T);
             pr = p0 * sn * sn;
         }
+        if (ctx->ta_max != 0.0)
+            ctx->active_ta = hipib_active_tension(ctx->ta_max, ctx->ta_t_on, ctx->ta_duration, t);
         HIPIB_TRY(ib_step(ctx, u, p, X, pr));
     }
     return HIPIB_OK;

@@ -1,7 +1,9 @@
 // Matrix-free nodal forces on trilinear hexahedra ("Eulerian-Lagrangian
 // coupling operators": F_i = -sum_q P(X_q) : grad N_i(X_q) w_q) and the
 // uniform cavity pressure on quads (the left-ventricle model's endocardial
-// load), as a follower load on the current configuration.
+// load), as a follower load on the current configuration.  Holzapfel-Ogden
+// materials may carry sheet and fibre-sheet terms (per-element sheet
+// directions) and the left-ventricle model's active fibre stress.
 //
 // One thread per element.  With Jr = dX/dxi and Jx = dx/dxi at a Gauss point,
 // F = Jx Jr^{-1}, grad_X N_a = Jr^{-T} grad_xi N_a and
@@ -25,8 +27,8 @@ template <typename T>
 __global__ void __launch_bounds__(128)
 k_fe_force(const double* __restrict__ X, const double* __restrict__ Xref,
            const int32_t* __restrict__ conn, const double* __restrict__ fibre,
-           const int32_t* __restrict__ mat_id, MatTable mats, int ne, double* __restrict__ F,
-           MGState* st, double* __restrict__ contrib) {
+           const double* __restrict__ sheet, const int32_t* __restrict__ mat_id, MatTable mats,
+           double Ta, int ne, double* __restrict__ F, MGState* st, double* __restrict__ contrib) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
     int nd[8];
@@ -45,10 +47,19 @@ k_fe_force(const double* __restrict__ X, const double* __restrict__ Xref,
         }
     const int m = mat_id[e];
     const int model = mats.model[m];
-    T par[5];
+    const bool sh = mats.sheet[m] != 0;
+    T par[kMatParams];
 #pragma unroll
-    for (int t = 0; t < 5; ++t) par[t] = (T)mats.p[m][t];
+    for (int t = 0; t < kMatParams; ++t) par[t] = (T)mats.p[m][t];
     const T ef[3] = {(T)fibre[3 * e], (T)fibre[3 * e + 1], (T)fibre[3 * e + 2]};
+    T es[3] = {T(0), T(0), T(0)};
+    if (sh) {
+        es[0] = (T)sheet[3 * e];
+        es[1] = (T)sheet[3 * e + 1];
+        es[2] = (T)sheet[3 * e + 2];
+    }
+    // the active stress acts on Holzapfel-Ogden (myocardium) materials only
+    const T ta = model == HIPIB_HOLZAPFEL_OGDEN ? (T)Ta : T(0);
     const T gp = T(0.57735026918962576451);  // 1/sqrt(3)
     bool bad = false;
     for (int g = 0; g < 8; ++g) {
@@ -90,7 +101,7 @@ k_fe_force(const double* __restrict__ X, const double* __restrict__ Xref,
             for (int c = 0; c < 3; ++c)
                 Fm[3 * r + c] = Jx[3 * r] * Jri[c] + Jx[3 * r + 1] * Jri[3 + c] + Jx[3 * r + 2] * Jri[6 + c];
         T P[9];
-        if (!pk1<T>(model, par, Fm, ef, P)) { bad = true; continue; }
+        if (!pk1<T>(model, par, Fm, ef, es, sh, ta, P)) { bad = true; continue; }
         T Q[9];   // w P Jr^{-T}
 #pragma unroll
         for (int r = 0; r < 3; ++r)
@@ -185,8 +196,8 @@ hipib_status launch_fe_force(hipib_ctx* ctx, const double* X, double pressure, d
     if (det) {
         if (ctx->ne > 0) {
             k_fe_force<double><<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
-                X, ctx->Xref, ctx->conn, ctx->fibre, ctx->mat_id, ctx->mats, ctx->ne, F, ctx->st,
-                ctx->det_contrib);
+                X, ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats,
+                ctx->active_ta, ctx->ne, F, ctx->st, ctx->det_contrib);
             HIPIB_HIP(hipGetLastError());
             HIPIB_TRY(det_gather_nodes(ctx, false, false, F));
         } else {
@@ -208,7 +219,8 @@ hipib_status launch_fe_force(hipib_ctx* ctx, const double* X, double pressure, d
         // element forces, which exceeds the mixed mode's 1e-6 error budget over
         // a run; the force kernel is ~1% of a step.
         k_fe_force<double><<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
-            X, ctx->Xref, ctx->conn, ctx->fibre, ctx->mat_id, ctx->mats, ctx->ne, F, ctx->st, nullptr);
+            X, ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats, ctx->active_ta,
+            ctx->ne, F, ctx->st, nullptr);
         HIPIB_HIP(hipGetLastError());
     }
     if (ctx->nf > 0 && pressure != 0.0) {

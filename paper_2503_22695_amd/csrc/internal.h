@@ -21,10 +21,13 @@ inline int64_t spread_list_cap(int64_t ntiles, int64_t nn) {
     return ntiles + (nn + kSpreadChunk - 1) / kSpreadChunk + 1;
 }
 
+constexpr int kMatParams = 9;       // (a, b, a_f, b_f, kappa, a_s, b_s, a_fs, b_fs)
+
 // Material table passed by value to the force kernels.
 struct MatTable {
     int32_t model[HIPIB_MAX_MATERIALS];
-    double p[HIPIB_MAX_MATERIALS][5];
+    int32_t sheet[HIPIB_MAX_MATERIALS];   // 1: Holzapfel-Ogden with a_s or a_fs > 0
+    double p[HIPIB_MAX_MATERIALS][kMatParams];
 };
 
 // Multigrid stop-decision state, kept on the device and mirrored to pinned host
@@ -109,6 +112,9 @@ struct hipib_ctx {
     uint32_t mat_used = 0;    // bit m: some element uses material m
     uint32_t mat_set = 0;     // bit m: material m defined
     hipib::MatTable mats{};
+    double* sheet = nullptr;  // [ne][3] sheet directions (hipib_set_sheets), else null
+    double active_ta = 0.0;   // T_a of the active fibre stress (Holzapfel-Ogden materials)
+    double ta_max = 0.0, ta_t_on = 0.0, ta_duration = 0.0;  // waveform followed by advance
 
     std::vector<hipib::StepRecord> recs;
     bool broken = false;

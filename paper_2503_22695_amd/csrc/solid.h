@@ -29,12 +29,19 @@ __device__ __forceinline__ void cof3(const T* A, T* C) {
 
 // First Piola-Kirchhoff stress:
 //   neo-Hookean (mu_s, kappa):  mu_s J^{-2/3}(F - I1/3 F^{-T}) + kappa ln J F^{-T}
-//   Holzapfel-Ogden (a, b, a_f, b_f, kappa):
+//   Holzapfel-Ogden (a, b, a_f, b_f, kappa, a_s, b_s, a_fs, b_fs):
 //     a e^{b(I1bar-3)} J^{-2/3}(F - I1/3 F^{-T})
-//     + 2 a_f (I4f*-1) e^{b_f (I4f*-1)^2} (F e_f) (x) e_f + kappa ln J F^{-T}
+//     + 2 a_f (I4f*-1) e^{b_f (I4f*-1)^2} (F e_f) (x) e_f
+//     + 2 a_s (I4s*-1) e^{b_s (I4s*-1)^2} (F e_s) (x) e_s          (sheet materials)
+//     + a_fs I8 e^{b_fs I8^2} ((F e_f) (x) e_s + (F e_s) (x) e_f)   (sheet materials)
+//     + T_a (1 + 4.9 (sqrt(I4f) - 1)) (F e_f) (x) e_f               (active stress)
+//     + kappa ln J F^{-T}
+// The fibre-sheet term is the derivative of a_fs/(2 b_fs)(e^{b_fs I8^2} - 1).
+// `sheet` selects the sheet terms (es is then read); Ta = 0 drops the active term.
 // Returns false when J <= 0.
 template <typename T>
-__device__ __forceinline__ bool pk1(int model, const T* par, const T* Fm, const T* ef, T* P) {
+__device__ __forceinline__ bool pk1(int model, const T* par, const T* Fm, const T* ef, const T* es,
+                                    bool sheet, T Ta, T* P) {
     const T J = det3(Fm);
     if (!(J > T(0))) return false;
     T cof[9];
@@ -46,8 +53,8 @@ __device__ __forceinline__ bool pk1(int model, const T* par, const T* Fm, const 
     const T cb = cbrt(J);
     const T Jm23 = T(1) / (cb * cb);
     const T lnJ = log(J);
-    T iso, kappa, fib = T(0);
-    T Fe[3] = {T(0), T(0), T(0)};
+    T iso, kappa, fib = T(0), sh = T(0), fs = T(0);
+    T Fe[3] = {T(0), T(0), T(0)}, Fs[3] = {T(0), T(0), T(0)};
     if (model == HIPIB_NEO_HOOKEAN) {
         iso = par[0];
         kappa = par[1];
@@ -58,6 +65,15 @@ __device__ __forceinline__ bool pk1(int model, const T* par, const T* Fm, const 
         for (int r = 0; r < 3; ++r) Fe[r] = Fm[3 * r] * ef[0] + Fm[3 * r + 1] * ef[1] + Fm[3 * r + 2] * ef[2];
         const T I4 = Fe[0] * Fe[0] + Fe[1] * Fe[1] + Fe[2] * Fe[2];
         if (I4 > T(1)) fib = T(2) * par[2] * (I4 - T(1)) * exp(par[3] * (I4 - T(1)) * (I4 - T(1)));
+        if (Ta != T(0)) fib += Ta * (T(1) + T(4.9) * (sqrt(I4) - T(1)));
+        if (sheet) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) Fs[r] = Fm[3 * r] * es[0] + Fm[3 * r + 1] * es[1] + Fm[3 * r + 2] * es[2];
+            const T I4s = Fs[0] * Fs[0] + Fs[1] * Fs[1] + Fs[2] * Fs[2];
+            if (I4s > T(1)) sh = T(2) * par[5] * (I4s - T(1)) * exp(par[6] * (I4s - T(1)) * (I4s - T(1)));
+            const T I8 = Fe[0] * Fs[0] + Fe[1] * Fs[1] + Fe[2] * Fs[2];
+            fs = par[7] * I8 * exp(par[8] * I8 * I8);
+        }
     }
     const T a = iso * Jm23, third = I1 / T(3), vol = kappa * lnJ;
 #pragma unroll
@@ -65,18 +81,23 @@ __device__ __forceinline__ bool pk1(int model, const T* par, const T* Fm, const 
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const T FiT = cof[3 * r + c] * invJ;
-            P[3 * r + c] = a * (Fm[3 * r + c] - third * FiT) + fib * Fe[r] * ef[c] + vol * FiT;
+            T v = a * (Fm[3 * r + c] - third * FiT) + fib * Fe[r] * ef[c] + vol * FiT;
+            if (sheet) v += sh * Fs[r] * es[c] + fs * (Fe[r] * es[c] + Fs[r] * ef[c]);
+            P[3 * r + c] = v;
         }
     return true;
 }
 
 // dP = dP/dF : dF.  With G = F^{-T}: dG = -G dF^T G, d ln J = G : dF,
-// dI1 = 2 F : dF, d J^{-2/3} = -(2/3) J^{-2/3} d ln J, dI4 = 2 (F e).(dF e);
-// iso coefficient alpha (mu_s, or a e^{b(I1bar-3)}), fibre coefficient
-// f(I4) = 2 a_f (I4-1) e^{b_f (I4-1)^2} with f' = 2 a_f e^{..}(1 + 2 b_f (I4-1)^2).
+// dI1 = 2 F : dF, d J^{-2/3} = -(2/3) J^{-2/3} d ln J, dI4i = 2 (F e_i).(dF e_i),
+// dI8 = (dF e_f).(F e_s) + (F e_f).(dF e_s); iso coefficient alpha (mu_s, or
+// a e^{b(I1bar-3)}), fibre / sheet coefficient f_i(I4) = 2 a_i (I4-1) e^{b_i (I4-1)^2}
+// with f_i' = 2 a_i e^{..}(1 + 2 b_i (I4-1)^2), fibre-sheet g(I8) = a_fs I8 e^{b_fs I8^2}
+// with g' = a_fs e^{..}(1 + 2 b_fs I8^2), active T_a (1 + 4.9 (sqrt(I4f) - 1)) with
+// derivative T_a 4.9 / (2 sqrt(I4f)).
 template <typename T>
 __device__ __forceinline__ bool pk1_tangent(int model, const T* par, const T* Fm, const T* ef,
-                                            const T* dF, T* dP) {
+                                            const T* es, bool sheet, T Ta, const T* dF, T* dP) {
     const T J = det3(Fm);
     if (!(J > T(0))) return false;
     T G[9], dG[9];
@@ -107,7 +128,9 @@ __device__ __forceinline__ bool pk1_tangent(int model, const T* par, const T* Fm
     const T dJm23 = -T(2) / T(3) * Jm23 * dlnJ;
     const T lnJ = log(J);
     T alpha, dalpha, kappa, fib = T(0), dfib = T(0);
+    T sh = T(0), dsh = T(0), fs = T(0), dfs = T(0);
     T Fe[3] = {T(0), T(0), T(0)}, dFe[3] = {T(0), T(0), T(0)};
+    T Fs[3] = {T(0), T(0), T(0)}, dFs[3] = {T(0), T(0), T(0)};
     if (model == HIPIB_NEO_HOOKEAN) {
         alpha = par[0];
         dalpha = T(0);
@@ -123,12 +146,38 @@ __device__ __forceinline__ bool pk1_tangent(int model, const T* par, const T* Fm
             dFe[r] = dF[3 * r] * ef[0] + dF[3 * r + 1] * ef[1] + dF[3 * r + 2] * ef[2];
         }
         const T I4 = Fe[0] * Fe[0] + Fe[1] * Fe[1] + Fe[2] * Fe[2];
+        const T dI4 = T(2) * (Fe[0] * dFe[0] + Fe[1] * dFe[1] + Fe[2] * dFe[2]);
         if (I4 > T(1)) {
-            const T dI4 = T(2) * (Fe[0] * dFe[0] + Fe[1] * dFe[1] + Fe[2] * dFe[2]);
             const T q = I4 - T(1);
             const T Ef = exp(par[3] * q * q);
             fib = T(2) * par[2] * q * Ef;
             dfib = T(2) * par[2] * Ef * (T(1) + T(2) * par[3] * q * q) * dI4;
+        }
+        if (Ta != T(0)) {
+            const T r4 = sqrt(I4);
+            fib += Ta * (T(1) + T(4.9) * (r4 - T(1)));
+            dfib += Ta * T(4.9) / (T(2) * r4) * dI4;
+        }
+        if (sheet) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                Fs[r] = Fm[3 * r] * es[0] + Fm[3 * r + 1] * es[1] + Fm[3 * r + 2] * es[2];
+                dFs[r] = dF[3 * r] * es[0] + dF[3 * r + 1] * es[1] + dF[3 * r + 2] * es[2];
+            }
+            const T I4s = Fs[0] * Fs[0] + Fs[1] * Fs[1] + Fs[2] * Fs[2];
+            if (I4s > T(1)) {
+                const T dI4s = T(2) * (Fs[0] * dFs[0] + Fs[1] * dFs[1] + Fs[2] * dFs[2]);
+                const T q = I4s - T(1);
+                const T Es = exp(par[6] * q * q);
+                sh = T(2) * par[5] * q * Es;
+                dsh = T(2) * par[5] * Es * (T(1) + T(2) * par[6] * q * q) * dI4s;
+            }
+            const T I8 = Fe[0] * Fs[0] + Fe[1] * Fs[1] + Fe[2] * Fs[2];
+            const T dI8 = dFe[0] * Fs[0] + dFe[1] * Fs[1] + dFe[2] * Fs[2] +
+                          Fe[0] * dFs[0] + Fe[1] * dFs[1] + Fe[2] * dFs[2];
+            const T Efs = exp(par[8] * I8 * I8);
+            fs = par[7] * I8 * Efs;
+            dfs = par[7] * Efs * (T(1) + T(2) * par[8] * I8 * I8) * dI8;
         }
     }
     const T c1 = dalpha * Jm23 + alpha * dJm23, c2 = alpha * Jm23;
@@ -139,8 +188,12 @@ __device__ __forceinline__ bool pk1_tangent(int model, const T* par, const T* Fm
             const int o = 3 * r + c;
             const T Mo = Fm[o] - I1 / T(3) * G[o];
             const T dMo = dF[o] - dI1 / T(3) * G[o] - I1 / T(3) * dG[o];
-            dP[o] = c1 * Mo + c2 * dMo + dfib * Fe[r] * ef[c] + fib * dFe[r] * ef[c] +
-                    kappa * dlnJ * G[o] + kappa * lnJ * dG[o];
+            T v = c1 * Mo + c2 * dMo + dfib * Fe[r] * ef[c] + fib * dFe[r] * ef[c] +
+                  kappa * dlnJ * G[o] + kappa * lnJ * dG[o];
+            if (sheet)
+                v += dsh * Fs[r] * es[c] + sh * dFs[r] * es[c] +
+                     dfs * (Fe[r] * es[c] + Fs[r] * ef[c]) + fs * (dFe[r] * es[c] + dFs[r] * ef[c]);
+            dP[o] = v;
         }
     return true;
 }

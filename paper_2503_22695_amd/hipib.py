@@ -69,6 +69,10 @@ def lib():
             "hipib_set_mesh": (st, [P, i32, P, i32, P, P, P]),
             "hipib_set_material": (st, [P, i32, i32, P, i32]),
             "hipib_set_pressure_faces": (st, [P, i32, P]),
+            "hipib_set_sheets": (st, [P, i32, P]),
+            "hipib_set_active_tension": (st, [P, f64]),
+            "hipib_active_tension": (f64, [f64, f64, f64, f64]),
+            "hipib_set_active_waveform": (st, [P, f64, f64, f64]),
             "hipib_fe_force": (st, [P, P, f64, P]),
             "hipib_spread": (st, [P, P, P, P]),
             "hipib_interpolate": (st, [P, P, P, P]),
@@ -173,6 +177,17 @@ class Context:
         f = np.ascontiguousarray(faces, dtype=np.int32).reshape(-1, 4)
         _check(lib().hipib_set_pressure_faces(self._h, f.shape[0], f.ctypes.data),
                "hipib_set_pressure_faces")
+
+    def set_sheets(self, sheet):
+        s = np.ascontiguousarray(sheet, dtype=np.float64).reshape(-1, 3)
+        _check(lib().hipib_set_sheets(self._h, s.shape[0], s.ctypes.data), "hipib_set_sheets")
+
+    def set_active_tension(self, Ta: float):
+        _check(lib().hipib_set_active_tension(self._h, float(Ta)), "hipib_set_active_tension")
+
+    def set_active_waveform(self, ta_max: float, t_on: float, duration: float):
+        _check(lib().hipib_set_active_waveform(self._h, float(ta_max), float(t_on), float(duration)),
+               "hipib_set_active_waveform")
 
     # -- hot path (device tensors) ----------------------------------------
     def _grid_shape(self, comps):
@@ -310,7 +325,16 @@ def context_for_problem(prob, **over) -> Context:
         ctx.set_material(m, mat.model, mat.params)
     if prob.n_faces:
         ctx.set_pressure_faces(prob.faces)
+    if prob.sheet is not None:
+        ctx.set_sheets(prob.sheet)
+    if prob.ta_max:
+        ctx.set_active_waveform(prob.ta_max, prob.ta_t_on, prob.ta_duration)
     return ctx
+
+
+def active_tension(ta_max: float, t_on: float, duration: float, t: float) -> float:
+    """T_a(t) of the activation waveform (hipib_active_tension)."""
+    return lib().hipib_active_tension(float(ta_max), float(t_on), float(duration), float(t))
 
 
 class Simulation:
@@ -361,6 +385,7 @@ class Rollout:
         self.dev = torch.device("cuda", torch.cuda.current_device())
         self.u0 = torch.tensor(prob.initial_velocity(), dtype=torch.float64, device=self.dev)
         self.kappa = float(prob.materials[mat].params[4])
+        self.sheet_params = [float(v) for v in prob.materials[mat].params[5:]]
         self.checkpoints = []
 
     def pressure(self, s0: int, i: int) -> float:
@@ -374,10 +399,18 @@ class Rollout:
         sn = math.sin(math.pi * t / T)
         return p0 * sn * sn
 
+    def active(self, s0: int, i: int) -> float:
+        """Active tension at step s0 + i, timed like pressure()."""
+        t = (self.t0 + s0 * self.prob.dt) + i * self.prob.dt
+        return active_tension(self.prob.ta_max, self.prob.ta_t_on, self.prob.ta_duration, t)
+
+    def _material(self, th):
+        return th[:4] + [self.kappa] + self.sheet_params
+
     def set_theta(self, theta):
         th = [float(v) for v in theta.detach().cpu().reshape(-1)]
         self._theta = th
-        self.ctx.set_material(self.mat, HOLZAPFEL_OGDEN, th[:4] + [self.kappa])
+        self.ctx.set_material(self.mat, HOLZAPFEL_OGDEN, self._material(th))
 
     def forward(self, theta, X0, keep_checkpoints=True):
         """X^N from X0.  With keep_checkpoints, (u, p, X) is stored at the start
@@ -410,6 +443,7 @@ class Rollout:
 
     def _reverse_segment(self, s0, us, Xs, lam_u, lam_X, dtheta):
         for i in range(len(us) - 2, -1, -1):
+            self.ctx.set_active_tension(self.active(s0, i))
             self.ctx.adjoint_step(us[i], Xs[i], us[i + 1], self.pressure(s0, i), lam_u, lam_X, dtheta)
 
     def _recompute(self, seg):
@@ -426,6 +460,7 @@ class Rollout:
         us, Xs = [u.clone()], [X.clone()]
         u, p, X = u.clone(), p.clone(), X.clone()
         for i in range(m):
+            ctx.set_active_tension(self.active(s0, i))
             ctx.ib_step(u, p, X, self.pressure(s0, i))
             us.append(u.clone())
             Xs.append(X.clone())
@@ -446,7 +481,7 @@ class Rollout:
                 with torch.cuda.stream(self._rstream):
                     self._rctx = context_for_problem(self.prob, **self.cfg_over)
             th = self._theta
-            self._rctx.set_material(self.mat, HOLZAPFEL_OGDEN, th[:4] + [self.kappa])
+            self._rctx.set_material(self.mat, HOLZAPFEL_OGDEN, self._material(th))
             pool = ThreadPoolExecutor(max_workers=1)
             pending = pool.submit(self._recompute, segs[0])
         try:
