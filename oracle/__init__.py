@@ -48,7 +48,8 @@ class Mesh(C.Structure):
                 ("n_mats", C.c_int32), ("mat_model", C.c_void_p), ("mat_params", C.c_void_p),
                 ("n_faces", C.c_int32), ("faces", C.c_void_p), ("sheet", C.c_void_p),
                 ("active_tension", C.c_double), ("ta_max", C.c_double), ("ta_t_on", C.c_double),
-                ("ta_duration", C.c_double)]
+                ("ta_duration", C.c_double), ("n_tethers", C.c_int32), ("tether_node", C.c_void_p),
+                ("tether_target", C.c_void_p), ("tether_K", C.c_void_p)]
 
 
 MAT_PARAMS = 9   # parameter slots per material (IBREF_MAT_PARAMS)
@@ -215,10 +216,11 @@ class MeshBuffers:
     padded to the 9 slots; sheet may be None while every a_s and a_fs is 0;
     active = (ta_max, t_on, duration) sets the active-tension waveform that
     advance and rollout_grad follow; active_tension is the fixed T_a of the
-    single-call functions (fe_force, fe_hvp, ib_step, adjoint_step)."""
+    single-call functions (fe_force, fe_hvp, ib_step, adjoint_step); tethers =
+    (node [t], target [t, 3], K [t, 6] as xx, yy, zz, xy, xz, yz) or None."""
 
     def __init__(self, X_ref, conn, fibre, mat_id, mat_model, mat_params, faces=None,
-                 sheet=None, active_tension=0.0, active=(0.0, 0.0, 0.0)):
+                 sheet=None, active_tension=0.0, active=(0.0, 0.0, 0.0), tethers=None):
         self.X_ref = _f64(X_ref)
         self.conn = _i32(conn)
         self.fibre = _f64(fibre)
@@ -234,6 +236,15 @@ class MeshBuffers:
                       self.mat_params.ctypes.data, self.faces.shape[0], self.faces.ctypes.data,
                       None if self.sheet is None else self.sheet.ctypes.data,
                       float(active_tension), *[float(v) for v in active])
+        if tethers is not None:
+            node, target, K = tethers
+            self.t_node = _i32(node).reshape(-1)
+            self.t_target = _f64(target).reshape(-1, 3)
+            self.t_K = _f64(K).reshape(-1, 6)
+            self.s.n_tethers = self.t_node.shape[0]
+            self.s.tether_node = self.t_node.ctypes.data
+            self.s.tether_target = self.t_target.ctypes.data
+            self.s.tether_K = self.t_K.ctypes.data
 
     def set_active_tension(self, Ta: float):
         self.s.active_tension = float(Ta)
@@ -244,7 +255,7 @@ class MeshBuffers:
         models, params = prob.material_arrays()
         return cls(prob.X_ref, prob.conn, prob.fibre, prob.mat_id, models, params, prob.faces,
                    sheet=prob.sheet, active_tension=active_tension,
-                   active=(prob.ta_max, prob.ta_t_on, prob.ta_duration))
+                   active=(prob.ta_max, prob.ta_t_on, prob.ta_duration), tethers=prob.tethers)
 
 
 def fluid(n, rho=1.0, mu=0.01, dt=1e-3, rtol=1e-10, pre=2, post=2, max_cycles=50,

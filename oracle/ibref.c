@@ -358,6 +358,35 @@ static void hex_dshape(const double xi[3], double dN[8][3]) {
 }
 
 /*
+ * Penalty tethers (the constrained faces of the benchmark and valve models and
+ * the base constraint of the left-ventricle model are enforced with a penalty
+ * parameter; the force law is not printed): a linear spring on each tethered
+ * node, F_a += -K (X_a - Y) with a symmetric K, energy (1/2)(X_a - Y).K(X_a - Y).
+ * With hvp set, V takes the place of X - Y (the force derivative along V).
+ */
+static int tether_apply(const ibref_mesh* m, const double* x, const double* V, double* F,
+                        double* energy) {
+    double E = 0.0;
+    for (int t = 0; t < m->n_tethers; ++t)
+        if (m->tether_node[t] < 0 || m->tether_node[t] >= m->n_nodes) return IBREF_E_INVAL;
+    for (int t = 0; t < m->n_tethers; ++t) {
+        long a = m->tether_node[t];
+        const double* K = m->tether_K + 6L * t;
+        double Km[3][3] = {{K[0], K[3], K[4]}, {K[3], K[1], K[5]}, {K[4], K[5], K[2]}};
+        double d[3];
+        for (int r = 0; r < 3; ++r) d[r] = V ? V[3 * a + r] : x[3 * a + r] - m->tether_target[3L * t + r];
+        for (int r = 0; r < 3; ++r) {
+            double s = 0.0;
+            for (int c = 0; c < 3; ++c) s += Km[r][c] * d[c];
+            F[3 * a + r] -= s;
+            E += 0.5 * d[r] * s;
+        }
+    }
+    if (energy) *energy += E;
+    return IBREF_OK;
+}
+
+/*
  * Nodal force from the weak form ("Spatial Discretization" and the mean force
  * contribution formula of the coupling section):
  *   F_a = - sum_e sum_g P(F_g) : grad_X N_a(g) w_g
@@ -429,6 +458,8 @@ int ibref_fe_force(const ibref_mesh* m, const double* x, double* F, double* ener
         for (int a = 0; a < 8; ++a)
             for (int r = 0; r < 3; ++r) F[3L * cn[a] + r] += Fe[a][r];
     }
+    int rc = tether_apply(m, x, NULL, F, &E);
+    if (rc) return rc;
     if (energy) *energy = E;
     if (min_J) *min_J = Jmin;
     return IBREF_OK;
@@ -1199,7 +1230,9 @@ static int fe_derivative_loop(const ibref_mesh* m, const double* x, const double
 
 int ibref_fe_hvp(const ibref_mesh* m, const double* x, const double* V, double* HV) {
     for (long r = 0; r < 3L * m->n_nodes; ++r) HV[r] = 0.0;
-    return fe_derivative_loop(m, x, V, HV, 0);
+    int rc = fe_derivative_loop(m, x, V, HV, 0);
+    if (!rc) rc = tether_apply(m, x, V, HV, NULL);
+    return rc;
 }
 
 int ibref_fe_param_vjp(const ibref_mesh* m, const double* x, const double* lamF, double* dtheta) {

@@ -65,6 +65,10 @@ typedef struct {
                                   Hessian product); ibref_advance and ibref_rollout_grad set
                                   it per step from the waveform below when ta_max != 0 */
     double ta_max, ta_t_on, ta_duration;  /* active-tension waveform (ibref_active_tension) */
+    int32_t n_tethers;         /* penalty tethers: F_a += -K (X_a - Y) at node a */
+    const int32_t* tether_node;     /* [n_tethers] distinct node indices */
+    const double* tether_target;    /* [n_tethers][3] Y */
+    const double* tether_K;         /* [n_tethers][6] symmetric K: xx, yy, zz, xy, xz, yz */
 } ibref_mesh;
 
 typedef struct {

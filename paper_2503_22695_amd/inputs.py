@@ -76,6 +76,9 @@ class Problem:
     ta_max: float = 0.0        # active tension amplitude (0: passive)
     ta_t_on: float = 0.0       # the activation window [ta_t_on, ta_t_on + ta_duration]
     ta_duration: float = 0.0
+    # penalty tethers (node [t] int32, target [t, 3], symmetric K [t, 6] as
+    # xx, yy, zz, xy, xz, yz) or None
+    tethers: Optional[Tuple[np.ndarray, np.ndarray, np.ndarray]] = None
     mg_rtol: float = 1e-10
     mg_pre: int = 2
     mg_post: int = 2
@@ -373,27 +376,48 @@ def ho_shell(n: int = 128, n_theta: int = 224, n_psi: int = 80, n_tau: int = 6,
                    faces=faces.astype(np.int32), p0=1.0, T=n_steps * dt)
 
 
+def shell_base_tethers(X: np.ndarray, n_theta: int, n_psi: int, n_tau: int, kappa: float):
+    """Base constraint of the left-ventricle model on the shell's base ring
+    (psi = pi/2, every wall layer): zero axial and circumferential displacement,
+    radial motion in the base plane free.  K = kappa (e_x e_x^T + c c^T) with
+    the circumferential c = (0, -sin theta, cos theta); target = X."""
+    npn = n_psi + 1
+    it, iq = np.meshgrid(np.arange(n_theta), np.arange(n_tau + 1), indexing="ij")
+    node = (it + n_theta * (n_psi + npn * iq)).ravel().astype(np.int32)
+    th = np.arctan2(X[node, 2] - 0.5, X[node, 1] - 0.5)
+    s, c = np.sin(th), np.cos(th)
+    z = np.zeros_like(th)
+    K = kappa * np.stack([1.0 + z, s * s, c * c, z, z, -s * c], axis=1)
+    return node, np.ascontiguousarray(X[node]), np.ascontiguousarray(K)
+
+
+LV_BASE_KAPPA = 1.0   # nodal penalty stiffness of the base constraint
+
+
 def lv_shell(n: int = 128, n_theta: int = 224, n_psi: int = 80, n_tau: int = 6,
              n_steps: int = 100, dt: float = 5e-4) -> Problem:
     """The shell with the full Holzapfel-Ogden law (LV_PARAMS), transmural
-    sheets and one active-tension pulse over the run, peak at mid-run like the
-    cavity pressure pulse."""
+    sheets, one active-tension pulse over the run (peak at mid-run like the
+    cavity pressure pulse) and the base constraint as penalty tethers."""
     h = 1.0 / n
     X, conn, fibre, faces, sheet = shell_mesh(n_theta, n_psi, n_tau, h, with_sheet=True)
     ne = conn.shape[0]
     p0 = 1.0
+    tethers = shell_base_tethers(X, n_theta, n_psi, n_tau, LV_BASE_KAPPA)
     return Problem(name=f"lv_shell_{n}", n=n, rho=1.0, mu=0.01, dt=dt, n_steps=n_steps,
                    X_ref=X, X0=X.copy(), conn=conn.astype(np.int32),
                    fibre=np.ascontiguousarray(fibre), mat_id=np.zeros(ne, dtype=np.int32),
                    materials=[Material(HOLZAPFEL_OGDEN, LV_PARAMS)],
                    faces=faces.astype(np.int32), p0=p0, T=n_steps * dt, sheet=sheet,
-                   ta_max=LV_TA_OVER_P * p0, ta_t_on=0.0, ta_duration=n_steps * dt)
+                   ta_max=LV_TA_OVER_P * p0, ta_t_on=0.0, ta_duration=n_steps * dt,
+                   tethers=tethers)
 
 
 def lv_block(n: int = 32, n_el: int = 6, n_steps: int = 20, seed: int = 0,
              frame_seed: int = 2) -> Problem:
     """Block with the full Holzapfel-Ogden law (LV_PARAMS), a random orthonormal
-    fibre / sheet pair per element and an active-tension pulse over the run."""
+    fibre / sheet pair per element, an active-tension pulse over the run and
+    its x-min face tethered (kappa = 1) at its initial position."""
     p = _block_problem(f"lv_block_{n}", n, n_el, 1e-3, n_steps,
                        Material(HOLZAPFEL_OGDEN, LV_PARAMS), seed=seed)
     rng = np.random.default_rng(frame_seed)
@@ -405,6 +429,10 @@ def lv_block(n: int = 32, n_el: int = 6, n_steps: int = 20, seed: int = 0,
     s /= np.linalg.norm(s, axis=1, keepdims=True)
     p.fibre, p.sheet = np.ascontiguousarray(f), np.ascontiguousarray(s)
     p.ta_max, p.ta_t_on, p.ta_duration = 2.0, 0.0, n_steps * p.dt
+    # the face of smallest x held at its initial position (kappa I tethers)
+    node = np.flatnonzero(p.X_ref[:, 0] <= p.X_ref[:, 0].min() + 1e-12).astype(np.int32)
+    K = np.tile([1.0, 1.0, 1.0, 0.0, 0.0, 0.0], (node.size, 1))
+    p.tethers = (node, np.ascontiguousarray(p.X0[node]), K)
     return p
 
 

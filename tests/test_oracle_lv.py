@@ -219,8 +219,8 @@ def test_lv_hvp_and_tangent_match_differences(ref, Ta):
 
 
 def test_lv_rollout_gradient_against_central_difference(ref):
-    """Full law, active pulse over the run: gradient of L = sum |X^N - X_t|^2
-    over 3 steps with respect to (a, b, a_f, b_f) and X0.  The parameter
+    """Full law, active pulse over the run, tethered face: gradient of
+    L = sum |X^N - X_t|^2 over 3 steps with respect to (a, b, a_f, b_f) and X0.  The parameter
     sensitivities are ~1e-10 against L ~ 1e-4, so the multigrid's stopping noise
     in L dominates steps below ~1e-2 relative; the Taylor remainder at 1e-2 is
     ~1e-8 relative."""
@@ -235,7 +235,8 @@ def test_lv_rollout_gradient_against_central_difference(ref):
 
     def loss(par, X0):
         m = ref.MeshBuffers(prob.X_ref, prob.conn, prob.fibre, prob.mat_id, [HO], [par],
-                            sheet=prob.sheet, active=(prob.ta_max, prob.ta_t_on, prob.ta_duration))
+                            sheet=prob.sheet, active=(prob.ta_max, prob.ta_t_on, prob.ta_duration),
+                            tethers=prob.tethers)
         _, _, XN, _ = ref.advance(fl, m, u0, np.zeros((n,) * 3), X0, 0.0, n_steps)
         return float(np.sum((XN - Xt) ** 2))
     assert abs(L - loss(list(LV), prob.X0)) <= 1e-14 * abs(L)
@@ -266,7 +267,7 @@ def test_lv_active_pulse_changes_the_run(ref):
 
     def run(active):
         m = ref.MeshBuffers(prob.X_ref, prob.conn, prob.fibre, prob.mat_id, [HO], [LV],
-                            sheet=prob.sheet, active=active)
+                            sheet=prob.sheet, active=active, tethers=prob.tethers)
         return ref.advance(fl, m, u, z, prob.X0, 0.0, n_steps)[2]
     X_on = run((prob.ta_max, 0.0, prob.ta_duration))
     X_off = run((0.0, 0.0, 0.0))
