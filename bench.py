@@ -63,11 +63,10 @@ def cpu_baseline(prob, seconds: float):
                       f"({el:.1f} s, FP64 C with OpenMP grid loops)"}
 
 
-def larger_workload(torch, hipib, inputs, steps):
-    """FP64 steps/s on the 192^3 shell with two neo-Hookean leaflets (280,740
-    nodes, 243,712 hexes, random divergence-free initial flow), where the
-    solver's working set no longer fits the last-level cache."""
-    prob = inputs.workload("shell_leaflets_192")
+def workload_leg(torch, hipib, inputs, name, steps):
+    """FP64 steps/s of another workload over its first `steps` steps from t = 0
+    (3 warm-up steps on a copy of the state first)."""
+    prob = inputs.workload(name)
     sim = hipib.Simulation(prob)
     u, p, X = sim.u.clone(), sim.p.clone(), sim.X.clone()
     sim.ctx.advance(u, p, X, 0.0, 3, prob.p0, prob.T)     # warm-up on a copy
@@ -83,6 +82,23 @@ def larger_workload(torch, hipib, inputs, steps):
             "ms_per_step": round(1e3 * el / steps, 4), "dtype": "f64",
             "mg_cycles_per_step": {"helmholtz_max_component": float(np.mean(cyc[:, :3].max(1))),
                                    "poisson": float(np.mean(cyc[:, 3]))}}
+
+
+def larger_workload(torch, hipib, inputs, steps):
+    """The 192^3 shell with two neo-Hookean leaflets (280,740 nodes, 243,712
+    hexes, random divergence-free initial flow), where the solver's working set
+    no longer fits the last-level cache."""
+    return workload_leg(torch, hipib, inputs, "shell_leaflets_192", steps)
+
+
+def lv_workload(torch, hipib, inputs):
+    """The 128^3 shell with the full Holzapfel-Ogden law (sheet and fibre-sheet
+    terms), transmural sheets, the active-tension pulse and the base constraint
+    (penalty tethers): its whole 100-step run."""
+    out = workload_leg(torch, hipib, inputs, "lv_shell_128", 100)
+    out["law"] = ("Holzapfel-Ogden with sheet and fibre-sheet terms + active fibre tension; "
+                  "base ring tethered axially and circumferentially")
+    return out
 
 
 def adjoint_ratio(torch, hipib, inputs):
@@ -165,6 +181,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-192", action="store_true", help="skip the 192^3 shell+leaflets leg")
     ap.add_argument("--steps-192", type=int, default=20)
+    ap.add_argument("--no-lv", action="store_true", help="skip the 128^3 left-ventricle-law leg")
     ap.add_argument("--roofline-steps", type=int, default=20,
                     help="steps of the separate pass that times the roofline kernel")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -257,6 +274,10 @@ def main():
     if not args.no_192:
         larger = larger_workload(torch, hipib, inputs, args.steps_192)
 
+    lv = None
+    if not args.no_lv:
+        lv = lv_workload(torch, hipib, inputs)
+
     avg_s = kernel_ms * 1e-3 / max(launches, 1)
     achieved = bytes_per_launch / avg_s / 1e9 if launches else 0.0
     roofline = {
@@ -293,6 +314,7 @@ def main():
         "mixed_precision": mixed,
         "adjoint_over_forward": adjoint,
         "shell_leaflets_192": larger,
+        "lv_shell_128": lv,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)

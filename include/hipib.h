@@ -111,6 +111,18 @@ hipib_status hipib_set_mesh(hipib_ctx* ctx, int32_t n_nodes, const double* X_ref
  * a_s (a_fs) > 0.  A material with a_s or a_fs > 0 needs hipib_set_sheets. */
 hipib_status hipib_set_material(hipib_ctx* ctx, int32_t mat_id, int32_t model,
                                 const double* params, int32_t n_params);
+/* Penalty tethers (the constrained faces of the benchmark and valve models and
+ * the base constraint of the left-ventricle model, enforced with a penalty
+ * parameter; "Solid boundary" of the profile table): each tethered node a
+ * gets the linear spring force F_a += -K_t (X_a - Y_t) in hipib_fe_force (and
+ * so in every step), -K_t V_a in hipib_fe_hvp and the adjoint step.  node:
+ * host [n_tethers] distinct indices < n_nodes; target Y: host [n_tethers][3];
+ * K: host [n_tethers][6] symmetric stiffness (xx, yy, zz, xy, xz, yz), e.g.
+ * kappa (1,1,1,0,0,0) to fix a node, kappa (n n^T + c c^T) to hold only the
+ * normal and circumferential displacement.  Replaces earlier tethers;
+ * dropped by the next hipib_set_mesh. */
+hipib_status hipib_set_tethers(hipib_ctx* ctx, int32_t n_tethers, const int32_t* node,
+                               const double* target, const double* K);
 /* Sheet directions e_s of the elements (host [n_elems][3], unit, orthogonal to
  * the fibre, reference configuration; n_elems must equal the mesh's).  Dropped
  * by the next hipib_set_mesh. */

@@ -459,6 +459,7 @@ hipib_status adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n, 
             HIPIB_HIP(hipGetLastError());
             if (det) HIPIB_TRY(det_param_reduce(ctx, dtheta));
         }
+        HIPIB_TRY(launch_tethers(ctx, X_n, ctx->adj_lamF, lam_X));   // K symmetric: K^T lamF = K lamF
         if (ctx->nf > 0 && pressure != 0.0) {
             k_pressure_vjp<<<(ctx->nf + 255) / 256, 256, 0, ctx->stream>>>(
                 X_n, ctx->faces, ctx->nf, pressure, ctx->adj_lamF, lam_X,
@@ -486,14 +487,15 @@ hipib_status launch_conv_vjp(hipib_ctx* ctx, const double* u, const double* lam,
 
 hipib_status launch_fe_hvp(hipib_ctx* ctx, const double* X, const double* V, double* out) {
     HIPIB_TRY(launch_zero(ctx, out, 3 * (int64_t)ctx->nn));
-    if (ctx->ne == 0) return HIPIB_OK;
-    const bool det = ctx->cfg.deterministic != 0;
-    k_fe_hvp<<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
-        X, ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats, ctx->active_ta,
-        ctx->ne, V, out, ctx->st, det ? ctx->det_contrib : nullptr);
-    HIPIB_HIP(hipGetLastError());
-    if (det) HIPIB_TRY(det_gather_nodes(ctx, false, true, out));
-    return HIPIB_OK;
+    if (ctx->ne > 0) {
+        const bool det = ctx->cfg.deterministic != 0;
+        k_fe_hvp<<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
+            X, ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats, ctx->active_ta,
+            ctx->ne, V, out, ctx->st, det ? ctx->det_contrib : nullptr);
+        HIPIB_HIP(hipGetLastError());
+        if (det) HIPIB_TRY(det_gather_nodes(ctx, false, true, out));
+    }
+    return launch_tethers(ctx, X, V, out);
 }
 
 hipib_status launch_fe_param_vjp(hipib_ctx* ctx, const double* X, const double* lamF, double* dtheta) {

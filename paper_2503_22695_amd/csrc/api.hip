@@ -74,6 +74,12 @@ void free_mesh(hipib_ctx* ctx) {
     (void)hipFree(ctx->conn);
     (void)hipFree(ctx->fibre);
     (void)hipFree(ctx->sheet);
+    (void)hipFree(ctx->tether_node);
+    (void)hipFree(ctx->tether_Y);
+    (void)hipFree(ctx->tether_K);
+    ctx->tether_node = nullptr;
+    ctx->tether_Y = ctx->tether_K = nullptr;
+    ctx->nt = 0;
     (void)hipFree(ctx->mat_id);
     (void)hipFree(ctx->F);
     (void)hipFree(ctx->node_tile);
@@ -418,6 +424,41 @@ hipib_status hipib_set_sheets(hipib_ctx* ctx, int32_t n_elems, const double* she
         }
     }
     ctx->sheet = d;
+    return HIPIB_OK;
+}
+
+hipib_status hipib_set_tethers(hipib_ctx* ctx, int32_t n_tethers, const int32_t* node,
+                               const double* target, const double* K) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
+    if (n_tethers < 0 || (n_tethers > 0 && (!node || !target || !K)))
+        return fail(HIPIB_E_INVAL, "bad tether arrays");
+    std::vector<char> seen((size_t)ctx->nn, 0);
+    for (int32_t t = 0; t < n_tethers; ++t) {
+        if (node[t] < 0 || node[t] >= ctx->nn)
+            return fail(HIPIB_E_INVAL, "tether node[%d] = %d out of range", t, node[t]);
+        if (seen[node[t]]) return fail(HIPIB_E_INVAL, "node %d tethered twice", node[t]);
+        seen[node[t]] = 1;
+    }
+    for (int64_t t = 0; t < 3 * (int64_t)n_tethers; ++t)
+        if (!std::isfinite(target[t])) return fail(HIPIB_E_INVAL, "non-finite tether target");
+    for (int64_t t = 0; t < 6 * (int64_t)n_tethers; ++t)
+        if (!std::isfinite(K[t])) return fail(HIPIB_E_INVAL, "non-finite tether stiffness");
+    HIPIB_HIP(hipStreamSynchronize(ctx->stream));
+    (void)hipFree(ctx->tether_node);
+    (void)hipFree(ctx->tether_Y);
+    (void)hipFree(ctx->tether_K);
+    ctx->tether_node = nullptr;
+    ctx->tether_Y = ctx->tether_K = nullptr;
+    ctx->nt = 0;
+    if (n_tethers == 0) return HIPIB_OK;
+    HIPIB_TRY(dev_alloc(ctx, &ctx->tether_node, (size_t)n_tethers));
+    HIPIB_TRY(dev_alloc(ctx, &ctx->tether_Y, 3 * (size_t)n_tethers));
+    HIPIB_TRY(dev_alloc(ctx, &ctx->tether_K, 6 * (size_t)n_tethers));
+    HIPIB_HIP(hipMemcpy(ctx->tether_node, node, sizeof(int32_t) * n_tethers, hipMemcpyHostToDevice));
+    HIPIB_HIP(hipMemcpy(ctx->tether_Y, target, 3 * sizeof(double) * n_tethers, hipMemcpyHostToDevice));
+    HIPIB_HIP(hipMemcpy(ctx->tether_K, K, 6 * sizeof(double) * n_tethers, hipMemcpyHostToDevice));
+    ctx->nt = n_tethers;
     return HIPIB_OK;
 }
 

@@ -3,7 +3,8 @@
 // uniform cavity pressure on quads (the left-ventricle model's endocardial
 // load), as a follower load on the current configuration.  Holzapfel-Ogden
 // materials may carry sheet and fibre-sheet terms (per-element sheet
-// directions) and the left-ventricle model's active fibre stress.
+// directions) and the left-ventricle model's active fibre stress; penalty
+// tethers add linear springs at constrained nodes.
 //
 // One thread per element.  With Jr = dX/dxi and Jx = dx/dxi at a Gauss point,
 // F = Jx Jr^{-1}, grad_X N_a = Jr^{-T} grad_xi N_a and
@@ -184,11 +185,38 @@ k_pressure_load(const double* __restrict__ X, const int32_t* __restrict__ faces,
         for (int r = 0; r < 3; ++r) atomicAdd(F + 3 * nd[a] + r, fa[a][r]);
 }
 
+// Penalty tethers, one thread per tether; the nodes are distinct, so the
+// read-modify-write of out needs no atomic (the force kernels before it on the
+// stream have finished).  V == null: d = X_a - Y_t, else d = V_a.
+__global__ void __launch_bounds__(256)
+k_tether(const double* __restrict__ X, const double* __restrict__ V,
+         const int32_t* __restrict__ node, const double* __restrict__ Y,
+         const double* __restrict__ K, int nt, double* __restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const int64_t a = node[t];
+    double d[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) d[r] = V ? V[3 * a + r] : X[3 * a + r] - Y[3 * (int64_t)t + r];
+    const double* k = K + 6 * (int64_t)t;   // xx, yy, zz, xy, xz, yz
+    out[3 * a] -= k[0] * d[0] + k[3] * d[1] + k[4] * d[2];
+    out[3 * a + 1] -= k[3] * d[0] + k[1] * d[1] + k[5] * d[2];
+    out[3 * a + 2] -= k[4] * d[0] + k[5] * d[1] + k[2] * d[2];
+}
+
 __global__ void k_clear_numeric(MGState* st) {
     if (threadIdx.x == 0) st->numeric = 0;
 }
 
 }  // namespace
+
+hipib_status launch_tethers(hipib_ctx* ctx, const double* X, const double* V, double* out) {
+    if (ctx->nt == 0) return HIPIB_OK;
+    k_tether<<<(ctx->nt + 255) / 256, 256, 0, ctx->stream>>>(X, V, ctx->tether_node, ctx->tether_Y,
+                                                             ctx->tether_K, ctx->nt, out);
+    HIPIB_HIP(hipGetLastError());
+    return HIPIB_OK;
+}
 
 hipib_status launch_fe_force(hipib_ctx* ctx, const double* X, double pressure, double* F) {
     k_clear_numeric<<<1, 64, 0, ctx->stream>>>(ctx->st);
@@ -209,7 +237,7 @@ hipib_status launch_fe_force(hipib_ctx* ctx, const double* X, double pressure, d
             HIPIB_HIP(hipGetLastError());
             HIPIB_TRY(det_gather_nodes(ctx, true, true, F));
         }
-        return HIPIB_OK;
+        return launch_tethers(ctx, X, nullptr, F);
     }
     HIPIB_TRY(launch_zero(ctx, F, 3 * (int64_t)ctx->nn));
     if (ctx->ne > 0) {
@@ -228,7 +256,7 @@ hipib_status launch_fe_force(hipib_ctx* ctx, const double* X, double pressure, d
                                                                          pressure, F, nullptr);
         HIPIB_HIP(hipGetLastError());
     }
-    return HIPIB_OK;
+    return launch_tethers(ctx, X, nullptr, F);
 }
 
 }  // namespace hipib

@@ -115,6 +115,10 @@ struct hipib_ctx {
     double* sheet = nullptr;  // [ne][3] sheet directions (hipib_set_sheets), else null
     double active_ta = 0.0;   // T_a of the active fibre stress (Holzapfel-Ogden materials)
     double ta_max = 0.0, ta_t_on = 0.0, ta_duration = 0.0;  // waveform followed by advance
+    int32_t nt = 0;                  // penalty tethers (hipib_set_tethers)
+    int32_t* tether_node = nullptr;  // [nt] distinct node indices
+    double* tether_Y = nullptr;      // [nt][3] targets
+    double* tether_K = nullptr;      // [nt][6] symmetric stiffness xx, yy, zz, xy, xz, yz
 
     std::vector<hipib::StepRecord> recs;
     bool broken = false;
@@ -189,6 +193,8 @@ hipib_status launch_interpolate(hipib_ctx* ctx, const double* X, const double* u
                                 double* Xupd, double dt);
 // fe.hip
 hipib_status launch_fe_force(hipib_ctx* ctx, const double* X, double pressure, double* F);
+// tethers: out_a -= K (X_a - Y) (V null), or out_a -= K V_a (their force derivative along V)
+hipib_status launch_tethers(hipib_ctx* ctx, const double* X, const double* V, double* out);
 // det.hip (deterministic mode)
 hipib_status det_prepare_mesh(hipib_ctx* ctx, const int32_t* conn);
 hipib_status det_prepare_faces(hipib_ctx* ctx, const int32_t* faces, int nf);

@@ -70,6 +70,7 @@ def lib():
             "hipib_set_material": (st, [P, i32, i32, P, i32]),
             "hipib_set_pressure_faces": (st, [P, i32, P]),
             "hipib_set_sheets": (st, [P, i32, P]),
+            "hipib_set_tethers": (st, [P, i32, P, P, P]),
             "hipib_set_active_tension": (st, [P, f64]),
             "hipib_active_tension": (f64, [f64, f64, f64, f64]),
             "hipib_set_active_waveform": (st, [P, f64, f64, f64]),
@@ -181,6 +182,15 @@ class Context:
     def set_sheets(self, sheet):
         s = np.ascontiguousarray(sheet, dtype=np.float64).reshape(-1, 3)
         _check(lib().hipib_set_sheets(self._h, s.shape[0], s.ctypes.data), "hipib_set_sheets")
+
+    def set_tethers(self, node, target, K):
+        node = np.ascontiguousarray(node, dtype=np.int32).reshape(-1)
+        target = np.ascontiguousarray(target, dtype=np.float64).reshape(-1, 3)
+        K = np.ascontiguousarray(K, dtype=np.float64).reshape(-1, 6)
+        if target.shape[0] != node.size or K.shape[0] != node.size:
+            raise ValueError("tether arrays must have one row per tethered node")
+        _check(lib().hipib_set_tethers(self._h, node.size, node.ctypes.data, target.ctypes.data,
+                                       K.ctypes.data), "hipib_set_tethers")
 
     def set_active_tension(self, Ta: float):
         _check(lib().hipib_set_active_tension(self._h, float(Ta)), "hipib_set_active_tension")
@@ -327,6 +337,8 @@ def context_for_problem(prob, **over) -> Context:
         ctx.set_pressure_faces(prob.faces)
     if prob.sheet is not None:
         ctx.set_sheets(prob.sheet)
+    if prob.tethers is not None:
+        ctx.set_tethers(*prob.tethers)
     if prob.ta_max:
         ctx.set_active_waveform(prob.ta_max, prob.ta_t_on, prob.ta_duration)
     return ctx

@@ -209,3 +209,41 @@ def test_sheet_state_and_argument_errors(torch_dev, hp, ref):
     # the library's waveform and the oracle's agree at a few times
     for t in (0.0, 0.004, 0.01, 0.013, 0.02, 0.03):
         assert hp.active_tension(2.0, 0.0, 0.02, t) == ref.active_tension(2.0, 0.0, 0.02, t)
+
+
+@pytest.mark.parametrize("det", [0, 1])
+def test_tethers_force_and_hessian(torch_dev, hp, ref, det):
+    """Random symmetric positive definite tethers on a third of the nodes of a
+    HO block (with its elements): force and Hessian product against the oracle,
+    in atomic and deterministic mode."""
+    torch = torch_dev
+    prob = inputs.ho_block(n=32, n_el=6)
+    say("tethers", det)
+    rng = np.random.default_rng(41)
+    node = rng.choice(prob.n_nodes, size=prob.n_nodes // 3, replace=False).astype(np.int32)
+    A = rng.standard_normal((node.size, 3, 3))
+    Km = np.einsum("tij,tkj->tik", A, A) + 0.5 * np.eye(3)
+    K = np.stack([Km[:, 0, 0], Km[:, 1, 1], Km[:, 2, 2], Km[:, 0, 1], Km[:, 0, 2], Km[:, 1, 2]], 1)
+    Y = prob.X_ref[node] + 0.01 * prob.h * rng.standard_normal((node.size, 3))
+    prob.tethers = (node, Y, K)
+    x = deformed(prob, 12, 0.03)
+    ctx = hp.context_for_problem(prob, deterministic=det)
+    mesh = ref.MeshBuffers.from_problem(prob)
+    F = host(ctx.fe_force(to_dev(torch, x), 0.0))
+    assert_close("F", F, ref.fe_force(mesh, x)[0])
+    V = rng.standard_normal(x.shape)
+    HV = host(ctx.fe_hvp(to_dev(torch, x), to_dev(torch, V)))
+    assert_close("HV", HV, ref.fe_hvp(mesh, x, V), 1e-10)
+    bad = node.copy()
+    bad[1] = bad[0]
+    with pytest.raises(hp.HipIBError) as ei:
+        ctx.set_tethers(bad, Y, K)
+    assert ei.value.status == 1
+    bad[1] = prob.n_nodes
+    with pytest.raises(hp.HipIBError):
+        ctx.set_tethers(bad, Y, K)
+    ctx.set_tethers(node[:0], Y[:0], K[:0])          # no tethers: elastic force only
+    F0 = host(ctx.fe_force(to_dev(torch, x), 0.0))
+    mesh0 = ref.MeshBuffers.from_problem(prob)
+    mesh0.s.n_tethers = 0
+    assert_close("F (no tethers)", F0, ref.fe_force(mesh0, x)[0])
