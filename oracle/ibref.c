@@ -249,6 +249,21 @@ static void cof3(const double* A, double* C) {
  *   fibre-sheet term 2 a_fs I8 e^{..} (F e_f) (x) e_s is not the derivative of
  *   the printed energy, whose dI8fs/dF = (F e_f) (x) e_s + (F e_s) (x) e_f; all
  *   three are read as corrected here.)
+ *   modified standard reinforcing Psi_1 (params G_T, G_L, E_L, kappa),
+ *   I5f = e_f . C^2 e_f = |C e_f|^2:
+ *            Psi = (G_T/2)(I1bar - 3) + ((G_T - G_L)/2)(2 I4f - I5f - 1)
+ *                + ((E_L + G_T - 4 G_L)/8)(I4f - 1)^2 + U(J)
+ *            P   = G_T J^{-2/3}(F - (I1/3) F^{-T})
+ *                + (2 (G_T - G_L) + ((E_L + G_T - 4 G_L)/2)(I4f - 1)) (F e_f) (x) e_f
+ *                - (G_T - G_L)((F e_f) (x) (C e_f) + (F C e_f) (x) e_f) + kappa ln J F^{-T}
+ *   fibre-reinforced model 1, Psi_2 (params C_1, a_f, b_f, kappa):
+ *            Psi = C_1 (I1bar - 3) + a_f/(2 b_f)(exp(b_f (I4f* - 1)^2) - 1) + U(J)
+ *   fibre-reinforced model 2, Psi_3 (params C_10, C_01, a_f, b_f, kappa), with the
+ *   plain I4f as printed (the fibre also resists compression):
+ *            Psi = C_10 (exp(C_01 (I1bar - 3)) - 1) + a_f/(2 b_f)(exp(b_f (I4f - 1)^2) - 1) + U(J)
+ *            P   = 2 C_10 C_01 exp(C_01 (I1bar - 3)) J^{-2/3}(F - (I1/3) F^{-T}) + ...
+ *   (the printed P_3 has C_10 in the exponent where the energy has C_01; the
+ *   derivative of the energy is taken).
  *   Active stress of the myocardium (left-ventricle model): the second
  *   Piola-Kirchhoff stress S_a = T e_f (x) e_f with T = T_a (1 + 4.9 (sqrt(I4f) - 1))
  *   is added to HO materials as P_a = F S_a = T (F e_f) (x) e_f (the model
@@ -271,9 +286,12 @@ int ibref_pk1(int32_t model, const double* par, const double* Fm, const double* 
     double Jm23 = pow(J, -2.0 / 3.0);
     double lnJ = log(J);
     double kappa, iso_coef, energy;
-    double fib_coef = 0.0, sh_coef = 0.0, fs_coef = 0.0;
+    double fib_coef = 0.0, sh_coef = 0.0, fs_coef = 0.0, i5_coef = 0.0;
     double Fe[3] = {0.0, 0.0, 0.0}, Fs[3] = {0.0, 0.0, 0.0};
-    double esv[3] = {0.0, 0.0, 0.0};
+    double esv[3] = {0.0, 0.0, 0.0}, Ce[3] = {0.0, 0.0, 0.0}, FCe[3] = {0.0, 0.0, 0.0};
+    if (model != IBREF_NEO_HOOKEAN)
+        for (int r = 0; r < 3; ++r) Fe[r] = Fm[3 * r] * ef[0] + Fm[3 * r + 1] * ef[1] + Fm[3 * r + 2] * ef[2];
+    const double I4 = Fe[0] * Fe[0] + Fe[1] * Fe[1] + Fe[2] * Fe[2];
     if (model == IBREF_NEO_HOOKEAN) {
         double mu_s = par[0];
         kappa = par[1];
@@ -286,8 +304,6 @@ int ibref_pk1(int32_t model, const double* par, const double* Fm, const double* 
         double E1 = exp(b * (Jm23 * I1 - 3.0));
         iso_coef = a * E1;
         energy = a / (2.0 * b) * (E1 - 1.0);
-        for (int r = 0; r < 3; ++r) Fe[r] = Fm[3 * r] * ef[0] + Fm[3 * r + 1] * ef[1] + Fm[3 * r + 2] * ef[2];
-        double I4 = Fe[0] * Fe[0] + Fe[1] * Fe[1] + Fe[2] * Fe[2];
         double I4s = I4 > 1.0 ? I4 : 1.0;
         double Ef = exp(bf * (I4s - 1.0) * (I4s - 1.0));
         fib_coef = 2.0 * af * (I4s - 1.0) * Ef;
@@ -313,6 +329,37 @@ int ibref_pk1(int32_t model, const double* par, const double* Fm, const double* 
             fib_coef += Ta * (1.0 + 4.9 * (r4 - 1.0));
             energy += 0.5 * Ta * ((1.0 - 4.9) * (I4 - 1.0) + (2.0 / 3.0) * 4.9 * (I4 * r4 - 1.0));
         }
+    } else if (model == IBREF_STANDARD_REINFORCING) {
+        double GT = par[0], GL = par[1], EL = par[2];
+        kappa = par[3];
+        /* C e_f = F^T (F e_f), I5f = |C e_f|^2, and F C e_f */
+        for (int c = 0; c < 3; ++c) Ce[c] = Fm[c] * Fe[0] + Fm[3 + c] * Fe[1] + Fm[6 + c] * Fe[2];
+        for (int r = 0; r < 3; ++r) FCe[r] = Fm[3 * r] * Ce[0] + Fm[3 * r + 1] * Ce[1] + Fm[3 * r + 2] * Ce[2];
+        double I5 = Ce[0] * Ce[0] + Ce[1] * Ce[1] + Ce[2] * Ce[2];
+        double cL = EL + GT - 4.0 * GL;
+        iso_coef = GT;
+        energy = 0.5 * GT * (Jm23 * I1 - 3.0) + 0.5 * (GT - GL) * (2.0 * I4 - I5 - 1.0) +
+                 cL / 8.0 * (I4 - 1.0) * (I4 - 1.0);
+        fib_coef = 2.0 * (GT - GL) + 0.5 * cL * (I4 - 1.0);
+        i5_coef = -(GT - GL);
+    } else if (model == IBREF_FIBRE_REINFORCED_1) {
+        double C1 = par[0], af = par[1], bf = par[2];
+        kappa = par[3];
+        iso_coef = 2.0 * C1;
+        energy = C1 * (Jm23 * I1 - 3.0);
+        double I4s = I4 > 1.0 ? I4 : 1.0;
+        double Ef = exp(bf * (I4s - 1.0) * (I4s - 1.0));
+        fib_coef = 2.0 * af * (I4s - 1.0) * Ef;
+        if (af != 0.0) energy += af / (2.0 * bf) * (Ef - 1.0);
+    } else if (model == IBREF_FIBRE_REINFORCED_2) {
+        double C10 = par[0], C01 = par[1], af = par[2], bf = par[3];
+        kappa = par[4];
+        double E1 = exp(C01 * (Jm23 * I1 - 3.0));
+        iso_coef = 2.0 * C10 * C01 * E1;
+        energy = C10 * (E1 - 1.0);
+        double Ef = exp(bf * (I4 - 1.0) * (I4 - 1.0));
+        fib_coef = 2.0 * af * (I4 - 1.0) * Ef;
+        if (af != 0.0) energy += af / (2.0 * bf) * (Ef - 1.0);
     } else {
         return IBREF_E_INVAL;
     }
@@ -322,6 +369,7 @@ int ibref_pk1(int32_t model, const double* par, const double* Fm, const double* 
             P[3 * r + c] = iso_coef * Jm23 * (Fm[3 * r + c] - I1 / 3.0 * FiT[3 * r + c]) +
                            fib_coef * Fe[r] * ef[c] + sh_coef * Fs[r] * esv[c] +
                            fs_coef * (Fe[r] * esv[c] + Fs[r] * ef[c]) +
+                           i5_coef * (Fe[r] * Ce[c] + FCe[r] * ef[c]) +
                            kappa * lnJ * FiT[3 * r + c];
     if (psi) *psi = energy;
     return IBREF_OK;
@@ -1035,7 +1083,12 @@ void ibref_interp_vjp_X(int32_t n, int32_t n_nodes, const double* X, const doubl
  *   f_i'(I4) = 2 a_i exp(b_i (I4-1)^2) (1 + 2 b_i (I4-1)^2),
  *   fibre-sheet coefficient g(I8) = a_fs I8 exp(b_fs I8^2),
  *   g'(I8) = a_fs exp(b_fs I8^2) (1 + 2 b_fs I8^2),
- *   active coefficient T_a (1 + 4.9 (sqrt(I4f) - 1)), derivative T_a 4.9 / (2 sqrt(I4f)).
+ *   active coefficient T_a (1 + 4.9 (sqrt(I4f) - 1)), derivative T_a 4.9 / (2 sqrt(I4f));
+ *   Psi_1: fibre coefficient 2 (G_T - G_L) + ((E_L + G_T - 4 G_L)/2)(I4f - 1) and the
+ *   I5 term c5 ((F e) (x) (C e) + (F C e) (x) e), c5 = -(G_T - G_L), with
+ *   d(C e) = dF^T (F e) + F^T (dF e) and d(F C e) = dF (C e) + F d(C e);
+ *   Psi_2: iso 2 C_1, fibre as HO; Psi_3: iso 2 C_10 C_01 exp(C_01 (I1bar - 3)) with
+ *   derivative C_01 alpha dI1bar, fibre without the max.
  */
 int ibref_pk1_tangent(int32_t model, const double* par, const double* Fm, const double* ef,
                       const double* es, double Ta, const double* dFm, double* dP) {
@@ -1063,23 +1116,61 @@ int ibref_pk1_tangent(int32_t model, const double* par, const double* Fm, const 
     double fib = 0.0, dfib = 0.0, Fe[3] = {0, 0, 0}, dFe[3] = {0, 0, 0};
     double sh = 0.0, dsh = 0.0, Fs[3] = {0, 0, 0}, dFs[3] = {0, 0, 0};
     double fs = 0.0, dfs = 0.0, esv[3] = {0, 0, 0};
+    double c5 = 0.0, Ce[3] = {0, 0, 0}, dCe[3] = {0, 0, 0}, dFCe[3] = {0, 0, 0};
+    const double dI1bar = dJm23 * I1 + Jm23 * dI1;
+    if (model != IBREF_NEO_HOOKEAN)
+        for (int r = 0; r < 3; ++r) {
+            Fe[r] = Fm[3 * r] * ef[0] + Fm[3 * r + 1] * ef[1] + Fm[3 * r + 2] * ef[2];
+            dFe[r] = dFm[3 * r] * ef[0] + dFm[3 * r + 1] * ef[1] + dFm[3 * r + 2] * ef[2];
+        }
+    const double I4 = Fe[0] * Fe[0] + Fe[1] * Fe[1] + Fe[2] * Fe[2];
+    const double dI4 = 2.0 * (Fe[0] * dFe[0] + Fe[1] * dFe[1] + Fe[2] * dFe[2]);
     if (model == IBREF_NEO_HOOKEAN) {
         alpha = par[0];
         dalpha = 0.0;
         kappa = par[1];
+    } else if (model == IBREF_STANDARD_REINFORCING) {
+        double GT = par[0], GL = par[1], EL = par[2], cL = EL + GT - 4.0 * GL;
+        kappa = par[3];
+        alpha = GT;
+        dalpha = 0.0;
+        fib = 2.0 * (GT - GL) + 0.5 * cL * (I4 - 1.0);
+        dfib = 0.5 * cL * dI4;
+        c5 = -(GT - GL);
+        for (int c = 0; c < 3; ++c) {
+            Ce[c] = Fm[c] * Fe[0] + Fm[3 + c] * Fe[1] + Fm[6 + c] * Fe[2];
+            dCe[c] = dFm[c] * Fe[0] + dFm[3 + c] * Fe[1] + dFm[6 + c] * Fe[2] +
+                     Fm[c] * dFe[0] + Fm[3 + c] * dFe[1] + Fm[6 + c] * dFe[2];
+        }
+        for (int r = 0; r < 3; ++r) {
+            dFCe[r] = dFm[3 * r] * Ce[0] + dFm[3 * r + 1] * Ce[1] + dFm[3 * r + 2] * Ce[2] +
+                      Fm[3 * r] * dCe[0] + Fm[3 * r + 1] * dCe[1] + Fm[3 * r + 2] * dCe[2];
+        }
+    } else if (model == IBREF_FIBRE_REINFORCED_1) {
+        double C1 = par[0], af = par[1], bf = par[2];
+        kappa = par[3];
+        alpha = 2.0 * C1;
+        dalpha = 0.0;
+        if (I4 > 1.0) {
+            double q = I4 - 1.0, Ef = exp(bf * q * q);
+            fib = 2.0 * af * q * Ef;
+            dfib = 2.0 * af * Ef * (1.0 + 2.0 * bf * q * q) * dI4;
+        }
+    } else if (model == IBREF_FIBRE_REINFORCED_2) {
+        double C10 = par[0], C01 = par[1], af = par[2], bf = par[3];
+        kappa = par[4];
+        alpha = 2.0 * C10 * C01 * exp(C01 * (Jm23 * I1 - 3.0));
+        dalpha = alpha * C01 * dI1bar;
+        double q = I4 - 1.0, Ef = exp(bf * q * q);
+        fib = 2.0 * af * q * Ef;
+        dfib = 2.0 * af * Ef * (1.0 + 2.0 * bf * q * q) * dI4;
     } else if (model == IBREF_HOLZAPFEL_OGDEN) {
         double a = par[0], b = par[1], af = par[2], bf = par[3];
         double as = par[5], bs = par[6], afs = par[7], bfs = par[8];
         kappa = par[4];
         double E1 = exp(b * (Jm23 * I1 - 3.0));
         alpha = a * E1;
-        dalpha = a * E1 * b * (dJm23 * I1 + Jm23 * dI1);
-        for (int r = 0; r < 3; ++r) {
-            Fe[r] = Fm[3 * r] * ef[0] + Fm[3 * r + 1] * ef[1] + Fm[3 * r + 2] * ef[2];
-            dFe[r] = dFm[3 * r] * ef[0] + dFm[3 * r + 1] * ef[1] + dFm[3 * r + 2] * ef[2];
-        }
-        double I4 = Fe[0] * Fe[0] + Fe[1] * Fe[1] + Fe[2] * Fe[2];
-        double dI4 = 2.0 * (Fe[0] * dFe[0] + Fe[1] * dFe[1] + Fe[2] * dFe[2]);
+        dalpha = a * E1 * b * dI1bar;
         if (I4 > 1.0) {
             double Ef = exp(bf * (I4 - 1.0) * (I4 - 1.0));
             fib = 2.0 * af * (I4 - 1.0) * Ef;
@@ -1123,6 +1214,7 @@ int ibref_pk1_tangent(int32_t model, const double* par, const double* Fm, const 
                     dfib * Fe[r] * ef[c] + fib * dFe[r] * ef[c] +
                     dsh * Fs[r] * esv[c] + sh * dFs[r] * esv[c] +
                     dfs * (Fe[r] * esv[c] + Fs[r] * ef[c]) + fs * (dFe[r] * esv[c] + dFs[r] * ef[c]) +
+                    c5 * (dFe[r] * Ce[c] + Fe[r] * dCe[c] + dFCe[r] * ef[c]) +
                     kappa * dlnJ * FiT[o] + kappa * lnJ * dFiT[o];
         }
     return IBREF_OK;

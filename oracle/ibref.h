@@ -30,7 +30,13 @@ extern "C" {
 #endif
 
 enum { IBREF_OK = 0, IBREF_E_INVAL = 1, IBREF_E_NOCONV = 4, IBREF_E_NUMERIC = 5 };
-enum { IBREF_NEO_HOOKEAN = 0, IBREF_HOLZAPFEL_OGDEN = 1 };
+enum {
+    IBREF_NEO_HOOKEAN = 0,         /* (mu_s, kappa) */
+    IBREF_HOLZAPFEL_OGDEN = 1,     /* Psi_4: (a, b, a_f, b_f, kappa, a_s, b_s, a_fs, b_fs) */
+    IBREF_STANDARD_REINFORCING = 2,/* Psi_1: (G_T, G_L, E_L, kappa) */
+    IBREF_FIBRE_REINFORCED_1 = 3,  /* Psi_2: (C_1, a_f, b_f, kappa) */
+    IBREF_FIBRE_REINFORCED_2 = 4   /* Psi_3: (C_10, C_01, a_f, b_f, kappa) */
+};
 #define IBREF_MAT_PARAMS 9         /* parameter slots per material */
 
 typedef struct {

@@ -34,8 +34,11 @@ from typing import List, Optional, Tuple
 import numpy as np
 
 # material model ids (shared convention of the C interfaces)
-NEO_HOOKEAN = 0
-HOLZAPFEL_OGDEN = 1
+NEO_HOOKEAN = 0                # (mu_s, kappa)
+HOLZAPFEL_OGDEN = 1            # (a, b, a_f, b_f, kappa[, a_s, b_s, a_fs, b_fs])
+STANDARD_REINFORCING = 2       # Psi_1: (G_T, G_L, E_L, kappa)
+FIBRE_REINFORCED_1 = 3         # Psi_2: (C_1, a_f, b_f, kappa)
+FIBRE_REINFORCED_2 = 4         # Psi_3: (C_10, C_01, a_f, b_f, kappa)
 
 MAT_PARAMS = 9   # parameter slots per material
 
@@ -361,6 +364,24 @@ def ho_block(n: int = 64, n_el: int = 12, n_steps: int = 50, seed: int = 0,
     return _block_problem(f"ho_block_{n}", n, n_el, 1e-3, n_steps,
                           Material(HOLZAPFEL_OGDEN, tuple(params)),
                           fibre_seed=fibre_seed, seed=seed)
+
+
+# the other laws' table constants (Cook's membrane divided by 16; the valve
+# laws' Pa values times 1e-4), kappa = 14 times the small-strain shear modulus
+LAW_PARAMS = {
+    STANDARD_REINFORCING: (0.5, 10.0, 75.0, 7.0),           # G_T, G_L, E_L, kappa
+    FIBRE_REINFORCED_1: (1.74, 3.13, 55.93, 48.7),          # C_1, a_f, b_f, kappa
+    FIBRE_REINFORCED_2: (0.121, 7.99, 2.423, 57.62, 27.1),  # C_10, C_01, a_f, b_f, kappa
+}
+
+
+def law_block(model: int, n: int = 32, n_steps: int = 10, seed: int = 0) -> Problem:
+    """The 6^3-hex block (stretched 1.1x in x, jittered) with one of the other
+    laws and the Cook's-membrane fibre (1, 1, 1)/sqrt(3) in every element."""
+    p = _block_problem(f"law{model}_block_{n}", n, 6, 1e-3, n_steps,
+                       Material(model, LAW_PARAMS[model]), seed=seed)
+    p.fibre = np.ascontiguousarray(np.tile(np.ones(3) / math.sqrt(3.0), (p.n_elems, 1)))
+    return p
 
 
 def ho_shell(n: int = 128, n_theta: int = 224, n_psi: int = 80, n_tau: int = 6,
