@@ -56,7 +56,13 @@ typedef enum {
 } hipib_status;
 
 typedef enum { HIPIB_FP64 = 0, HIPIB_MIXED = 1 } hipib_precision;
-typedef enum { HIPIB_NEO_HOOKEAN = 0, HIPIB_HOLZAPFEL_OGDEN = 1 } hipib_model;
+typedef enum {
+    HIPIB_NEO_HOOKEAN = 0,           /* (mu_s, kappa) */
+    HIPIB_HOLZAPFEL_OGDEN = 1,       /* Psi_4 (a, b, a_f, b_f, kappa[, a_s, b_s, a_fs, b_fs]) */
+    HIPIB_STANDARD_REINFORCING = 2,  /* Psi_1 (G_T, G_L, E_L, kappa) */
+    HIPIB_FIBRE_REINFORCED_1 = 3,    /* Psi_2 (C_1, a_f, b_f, kappa) */
+    HIPIB_FIBRE_REINFORCED_2 = 4     /* Psi_3 (C_10, C_01, a_f, b_f, kappa) */
+} hipib_model;
 typedef enum { HIPIB_OP_HELMHOLTZ = 0, HIPIB_OP_POISSON = 1 } hipib_op;
 
 #define HIPIB_MAX_MATERIALS 8
@@ -99,8 +105,17 @@ const char* hipib_last_error(void);
 hipib_status hipib_set_mesh(hipib_ctx* ctx, int32_t n_nodes, const double* X_ref,
                             int32_t n_elems, const int32_t* conn, const double* fibre,
                             const int32_t* mat_id);
-/* Material law of one id ("Constitutive laws"): neo-Hookean params
- * (mu_s, kappa), Psi = mu_s/2 (I1bar - 3) + kappa/2 (ln J)^2; Holzapfel-Ogden
+/* Material law of one id ("Constitutive laws"), U = kappa/2 (ln J)^2 throughout:
+ *   neo-Hookean (mu_s, kappa): Psi = mu_s/2 (I1bar - 3) + U;
+ *   modified standard reinforcing Psi_1 (G_T, G_L, E_L, kappa):
+ *     Psi = G_T/2 (I1bar - 3) + (G_T - G_L)/2 (2 I4f - I5f - 1)
+ *         + (E_L + G_T - 4 G_L)/8 (I4f - 1)^2 + U,   I5f = e_f.C^2 e_f;
+ *   fibre-reinforced 1, Psi_2 (C_1, a_f, b_f, kappa):
+ *     Psi = C_1 (I1bar - 3) + a_f/(2b_f)(e^{b_f (I4f*-1)^2} - 1) + U;
+ *   fibre-reinforced 2, Psi_3 (C_10, C_01, a_f, b_f, kappa), the plain I4f as
+ *     printed: Psi = C_10 (e^{C_01 (I1bar-3)} - 1) + a_f/(2b_f)(e^{b_f (I4f-1)^2} - 1) + U
+ *     (its stress is the derivative of this energy: C_01 in the exponent);
+ * requires non-negative moduli and kappa, and b_f, C_01 > 0.  Holzapfel-Ogden
  * params (a, b, a_f, b_f, kappa[, a_s, b_s, a_fs, b_fs]) (n_params 5 or 9;
  * 5 means a_s = a_fs = 0):
  *   Psi = a/(2b)(e^{b(I1bar-3)} - 1) + sum_{i=f,s} a_i/(2b_i)(e^{b_i (I4i*-1)^2} - 1)

@@ -377,6 +377,13 @@ hipib_status hipib_set_material(hipib_ctx* ctx, int32_t mat_id, int32_t model, c
     double p[kMatParams] = {};
     if (model == HIPIB_NEO_HOOKEAN) {
         if (n_params != 2) return fail(HIPIB_E_INVAL, "neo-Hookean takes (mu_s, kappa)");
+    } else if (model == HIPIB_STANDARD_REINFORCING) {
+        if (n_params != 4) return fail(HIPIB_E_INVAL, "standard reinforcing takes (G_T, G_L, E_L, kappa)");
+    } else if (model == HIPIB_FIBRE_REINFORCED_1) {
+        if (n_params != 4) return fail(HIPIB_E_INVAL, "fibre-reinforced 1 takes (C_1, a_f, b_f, kappa)");
+    } else if (model == HIPIB_FIBRE_REINFORCED_2) {
+        if (n_params != 5)
+            return fail(HIPIB_E_INVAL, "fibre-reinforced 2 takes (C_10, C_01, a_f, b_f, kappa)");
     } else if (model == HIPIB_HOLZAPFEL_OGDEN) {
         if (n_params != 5 && n_params != kMatParams)
             return fail(HIPIB_E_INVAL,
@@ -390,6 +397,15 @@ hipib_status hipib_set_material(hipib_ctx* ctx, int32_t mat_id, int32_t model, c
     }
     if (model == HIPIB_NEO_HOOKEAN) {
         if (!(p[0] >= 0) || !(p[1] >= 0)) return fail(HIPIB_E_INVAL, "negative modulus");
+    } else if (model == HIPIB_STANDARD_REINFORCING) {
+        if (!(p[0] >= 0) || !(p[1] >= 0) || !(p[2] >= 0) || !(p[3] >= 0))
+            return fail(HIPIB_E_INVAL, "negative modulus");
+    } else if (model == HIPIB_FIBRE_REINFORCED_1) {
+        if (!(p[0] >= 0) || !(p[1] >= 0) || !(p[2] > 0) || !(p[3] >= 0))
+            return fail(HIPIB_E_INVAL, "fibre-reinforced 1 needs C_1, a_f, kappa >= 0 and b_f > 0");
+    } else if (model == HIPIB_FIBRE_REINFORCED_2) {
+        if (!(p[0] >= 0) || !(p[1] > 0) || !(p[2] >= 0) || !(p[3] > 0) || !(p[4] >= 0))
+            return fail(HIPIB_E_INVAL, "fibre-reinforced 2 needs C_10, a_f, kappa >= 0 and C_01, b_f > 0");
     } else {
         if (!(p[0] >= 0) || !(p[1] > 0) || !(p[2] >= 0) || !(p[3] > 0) || !(p[4] >= 0))
             return fail(HIPIB_E_INVAL, "Holzapfel-Ogden needs a, a_f, kappa >= 0 and b, b_f > 0");

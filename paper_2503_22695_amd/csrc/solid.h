@@ -38,6 +38,12 @@ __device__ __forceinline__ void cof3(const T* A, T* C) {
 //     + kappa ln J F^{-T}
 // The fibre-sheet term is the derivative of a_fs/(2 b_fs)(e^{b_fs I8^2} - 1).
 // `sheet` selects the sheet terms (es is then read); Ta = 0 drops the active term.
+//   Psi_1 (G_T, G_L, E_L, kappa): G_T J^{-2/3}(F - I1/3 F^{-T})
+//     + (2 (G_T - G_L) + (E_L + G_T - 4 G_L)/2 (I4f - 1)) (F e_f) (x) e_f
+//     - (G_T - G_L) ((F e_f) (x) (C e_f) + (F C e_f) (x) e_f) + kappa ln J F^{-T}
+//   Psi_2 (C_1, a_f, b_f, kappa): 2 C_1 J^{-2/3}(..) + 2 a_f (I4f*-1) e^{b_f (I4f*-1)^2} (F e_f)(x)e_f + ..
+//   Psi_3 (C_10, C_01, a_f, b_f, kappa): 2 C_10 C_01 e^{C_01 (I1bar-3)} J^{-2/3}(..)
+//     + 2 a_f (I4f-1) e^{b_f (I4f-1)^2} (F e_f)(x)e_f + ..   (plain I4f)
 // Returns false when J <= 0.
 template <typename T>
 __device__ __forceinline__ bool pk1(int model, const T* par, const T* Fm, const T* ef, const T* es,
@@ -55,15 +61,29 @@ __device__ __forceinline__ bool pk1(int model, const T* par, const T* Fm, const 
     const T lnJ = log(J);
     T iso, kappa, fib = T(0), sh = T(0), fs = T(0);
     T Fe[3] = {T(0), T(0), T(0)}, Fs[3] = {T(0), T(0), T(0)};
+    if (model != HIPIB_NEO_HOOKEAN) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) Fe[r] = Fm[3 * r] * ef[0] + Fm[3 * r + 1] * ef[1] + Fm[3 * r + 2] * ef[2];
+    }
+    const T I4 = Fe[0] * Fe[0] + Fe[1] * Fe[1] + Fe[2] * Fe[2];
     if (model == HIPIB_NEO_HOOKEAN) {
         iso = par[0];
         kappa = par[1];
+    } else if (model == HIPIB_STANDARD_REINFORCING) {
+        iso = par[0];
+        kappa = par[3];
+        fib = T(2) * (par[0] - par[1]) + T(0.5) * (par[2] + par[0] - T(4) * par[1]) * (I4 - T(1));
+    } else if (model == HIPIB_FIBRE_REINFORCED_1) {
+        iso = T(2) * par[0];
+        kappa = par[3];
+        if (I4 > T(1)) fib = T(2) * par[1] * (I4 - T(1)) * exp(par[2] * (I4 - T(1)) * (I4 - T(1)));
+    } else if (model == HIPIB_FIBRE_REINFORCED_2) {
+        iso = T(2) * par[0] * par[1] * exp(par[1] * (Jm23 * I1 - T(3)));
+        kappa = par[4];
+        fib = T(2) * par[2] * (I4 - T(1)) * exp(par[3] * (I4 - T(1)) * (I4 - T(1)));
     } else {
         kappa = par[4];
         iso = par[0] * exp(par[1] * (Jm23 * I1 - T(3)));
-#pragma unroll
-        for (int r = 0; r < 3; ++r) Fe[r] = Fm[3 * r] * ef[0] + Fm[3 * r + 1] * ef[1] + Fm[3 * r + 2] * ef[2];
-        const T I4 = Fe[0] * Fe[0] + Fe[1] * Fe[1] + Fe[2] * Fe[2];
         if (I4 > T(1)) fib = T(2) * par[2] * (I4 - T(1)) * exp(par[3] * (I4 - T(1)) * (I4 - T(1)));
         if (Ta != T(0)) fib += Ta * (T(1) + T(4.9) * (sqrt(I4) - T(1)));
         if (sheet) {
@@ -85,6 +105,18 @@ __device__ __forceinline__ bool pk1(int model, const T* par, const T* Fm, const 
             if (sheet) v += sh * Fs[r] * es[c] + fs * (Fe[r] * es[c] + Fs[r] * ef[c]);
             P[3 * r + c] = v;
         }
+    if (model == HIPIB_STANDARD_REINFORCING) {   // the I5f term
+        T Ce[3], FCe[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Ce[c] = Fm[c] * Fe[0] + Fm[3 + c] * Fe[1] + Fm[6 + c] * Fe[2];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) FCe[r] = Fm[3 * r] * Ce[0] + Fm[3 * r + 1] * Ce[1] + Fm[3 * r + 2] * Ce[2];
+        const T c5 = par[1] - par[0];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) P[3 * r + c] += c5 * (Fe[r] * Ce[c] + FCe[r] * ef[c]);
+    }
     return true;
 }
 
@@ -131,22 +163,50 @@ __device__ __forceinline__ bool pk1_tangent(int model, const T* par, const T* Fm
     T sh = T(0), dsh = T(0), fs = T(0), dfs = T(0);
     T Fe[3] = {T(0), T(0), T(0)}, dFe[3] = {T(0), T(0), T(0)};
     T Fs[3] = {T(0), T(0), T(0)}, dFs[3] = {T(0), T(0), T(0)};
-    if (model == HIPIB_NEO_HOOKEAN) {
-        alpha = par[0];
-        dalpha = T(0);
-        kappa = par[1];
-    } else {
-        kappa = par[4];
-        const T E1 = exp(par[1] * (Jm23 * I1 - T(3)));
-        alpha = par[0] * E1;
-        dalpha = alpha * par[1] * (dJm23 * I1 + Jm23 * dI1);
+    if (model != HIPIB_NEO_HOOKEAN) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             Fe[r] = Fm[3 * r] * ef[0] + Fm[3 * r + 1] * ef[1] + Fm[3 * r + 2] * ef[2];
             dFe[r] = dF[3 * r] * ef[0] + dF[3 * r + 1] * ef[1] + dF[3 * r + 2] * ef[2];
         }
-        const T I4 = Fe[0] * Fe[0] + Fe[1] * Fe[1] + Fe[2] * Fe[2];
-        const T dI4 = T(2) * (Fe[0] * dFe[0] + Fe[1] * dFe[1] + Fe[2] * dFe[2]);
+    }
+    const T I4 = Fe[0] * Fe[0] + Fe[1] * Fe[1] + Fe[2] * Fe[2];
+    const T dI4 = T(2) * (Fe[0] * dFe[0] + Fe[1] * dFe[1] + Fe[2] * dFe[2]);
+    const T dI1bar = dJm23 * I1 + Jm23 * dI1;
+    if (model == HIPIB_NEO_HOOKEAN) {
+        alpha = par[0];
+        dalpha = T(0);
+        kappa = par[1];
+    } else if (model == HIPIB_STANDARD_REINFORCING) {
+        alpha = par[0];
+        dalpha = T(0);
+        kappa = par[3];
+        const T cL = par[2] + par[0] - T(4) * par[1];
+        fib = T(2) * (par[0] - par[1]) + T(0.5) * cL * (I4 - T(1));
+        dfib = T(0.5) * cL * dI4;
+    } else if (model == HIPIB_FIBRE_REINFORCED_1) {
+        alpha = T(2) * par[0];
+        dalpha = T(0);
+        kappa = par[3];
+        if (I4 > T(1)) {
+            const T q = I4 - T(1);
+            const T Ef = exp(par[2] * q * q);
+            fib = T(2) * par[1] * q * Ef;
+            dfib = T(2) * par[1] * Ef * (T(1) + T(2) * par[2] * q * q) * dI4;
+        }
+    } else if (model == HIPIB_FIBRE_REINFORCED_2) {
+        alpha = T(2) * par[0] * par[1] * exp(par[1] * (Jm23 * I1 - T(3)));
+        dalpha = alpha * par[1] * dI1bar;
+        kappa = par[4];
+        const T q = I4 - T(1);
+        const T Ef = exp(par[3] * q * q);
+        fib = T(2) * par[2] * q * Ef;
+        dfib = T(2) * par[2] * Ef * (T(1) + T(2) * par[3] * q * q) * dI4;
+    } else {
+        kappa = par[4];
+        const T E1 = exp(par[1] * (Jm23 * I1 - T(3)));
+        alpha = par[0] * E1;
+        dalpha = alpha * par[1] * dI1bar;
         if (I4 > T(1)) {
             const T q = I4 - T(1);
             const T Ef = exp(par[3] * q * q);
@@ -195,6 +255,27 @@ __device__ __forceinline__ bool pk1_tangent(int model, const T* par, const T* Fm
                      dfs * (Fe[r] * es[c] + Fs[r] * ef[c]) + fs * (dFe[r] * es[c] + dFs[r] * ef[c]);
             dP[o] = v;
         }
+    if (model == HIPIB_STANDARD_REINFORCING) {
+        // d[c5 ((F e)(x)(C e) + (F C e)(x)e)], d(C e) = dF^T (F e) + F^T (dF e),
+        // d(F C e) = dF (C e) + F d(C e)
+        T Ce[3], dCe[3], dFCe[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Ce[c] = Fm[c] * Fe[0] + Fm[3 + c] * Fe[1] + Fm[6 + c] * Fe[2];
+            dCe[c] = dF[c] * Fe[0] + dF[3 + c] * Fe[1] + dF[6 + c] * Fe[2] +
+                     Fm[c] * dFe[0] + Fm[3 + c] * dFe[1] + Fm[6 + c] * dFe[2];
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+            dFCe[r] = dF[3 * r] * Ce[0] + dF[3 * r + 1] * Ce[1] + dF[3 * r + 2] * Ce[2] +
+                      Fm[3 * r] * dCe[0] + Fm[3 * r + 1] * dCe[1] + Fm[3 * r + 2] * dCe[2];
+        const T c5 = par[1] - par[0];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                dP[3 * r + c] += c5 * (dFe[r] * Ce[c] + Fe[r] * dCe[c] + dFCe[r] * ef[c]);
+    }
     return true;
 }
 
