@@ -113,20 +113,34 @@ def adjoint_ratio(torch, hipib, inputs):
     ro = hipib.Rollout(prob, checkpoint_every=10)
     Xt = ro.forward(theta * torch.tensor([1.1, 0.9, 1.1, 0.9], dtype=torch.float64), X0,
                     keep_checkpoints=False).clone()
-    ro.forward(theta, X0, keep_checkpoints=False)        # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+
+    def grad_pass():
+        th = theta.clone().requires_grad_(True)
+        X0r = X0.clone().requires_grad_(True)
+        L = ((hipib.IBRollout().apply(th, X0r, ro) - Xt) ** 2).sum()
+        L.backward()
+        return th
+
+    # warm-up: one plain forward and one gradient pass (the first backward pass
+    # creates the rollout's second context and stream for the overlapped
+    # recomputation, a one-time set-up)
     ro.forward(theta, X0, keep_checkpoints=False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    th = theta.clone().requires_grad_(True)
-    X0r = X0.clone().requires_grad_(True)
-    L = ((hipib.IBRollout().apply(th, X0r, ro) - Xt) ** 2).sum()
-    L.backward()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    fwd, both = t1 - t0, t2 - t1
-    return {"ratio": round(both / fwd, 3), "definition": "(checkpointed forward + backward) / plain forward",
+    grad_pass()
+    fwds, boths = [], []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ro.forward(theta, X0, keep_checkpoints=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        th = grad_pass()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fwds.append(t1 - t0)
+        boths.append(t2 - t1)
+    fwd, both = sorted(fwds)[1], sorted(boths)[1]
+    return {"ratio": round(both / fwd, 3), "definition": "(checkpointed forward + backward) / plain forward, "
+                                                       "medians of 3 after a warm-up gradient pass",
             "backward_over_forward": round((both - fwd) / fwd, 3), "forward_ms": round(1e3 * fwd, 2),
             "forward_plus_backward_ms": round(1e3 * both, 2),
             "workload": "ho_block_64: 64^3 grid, 12^3 HO hexes, 50 steps, checkpoints every 10, FP64",
