@@ -49,7 +49,8 @@ class Mesh(C.Structure):
                 ("n_faces", C.c_int32), ("faces", C.c_void_p), ("sheet", C.c_void_p),
                 ("active_tension", C.c_double), ("ta_max", C.c_double), ("ta_t_on", C.c_double),
                 ("ta_duration", C.c_double), ("n_tethers", C.c_int32), ("tether_node", C.c_void_p),
-                ("tether_target", C.c_void_p), ("tether_K", C.c_void_p)]
+                ("tether_target", C.c_void_p), ("tether_K", C.c_void_p),
+                ("nodes_per_elem", C.c_int32)]
 
 
 MAT_PARAMS = 9   # parameter slots per material (IBREF_MAT_PARAMS)
@@ -236,6 +237,7 @@ class MeshBuffers:
                       self.mat_params.ctypes.data, self.faces.shape[0], self.faces.ctypes.data,
                       None if self.sheet is None else self.sheet.ctypes.data,
                       float(active_tension), *[float(v) for v in active])
+        self.s.nodes_per_elem = int(self.conn.shape[1]) if self.conn.ndim == 2 else 8
         if tethers is not None:
             node, target, K = tethers
             self.t_node = _i32(node).reshape(-1)

@@ -395,7 +395,7 @@ double ibref_active_tension(double ta_max, double t_on, double duration, double 
 /* ------------------------------------------------------------------------- */
 
 /* trilinear hex: local node a = i + 2j + 4k at reference (2i-1, 2j-1, 2k-1) */
-static void hex_dshape(const double xi[3], double dN[8][3]) {
+static void hex_dshape(const double xi[3], double dN[][3]) {
     for (int a = 0; a < 8; ++a) {
         double s0 = (a & 1) ? 1.0 : -1.0, s1 = (a & 2) ? 1.0 : -1.0, s2 = (a & 4) ? 1.0 : -1.0;
         double f0 = 1.0 + s0 * xi[0], f1 = 1.0 + s1 * xi[1], f2 = 1.0 + s2 * xi[2];
@@ -404,6 +404,58 @@ static void hex_dshape(const double xi[3], double dN[8][3]) {
         dN[a][2] = f0 * f1 * s2 / 8.0;
     }
 }
+
+/*
+ * Tetrahedra on the reference simplex xi, eta, zeta >= 0, xi + eta + zeta <= 1
+ * with barycentric l0 = 1 - xi - eta - zeta, l1 = xi, l2 = eta, l3 = zeta:
+ *   P1 (4 nodes): N_a = l_a;
+ *   P2 (10 nodes): vertices N_a = l_a (2 l_a - 1) (a < 4), edge nodes
+ *   N = 4 l_i l_j for (i, j) = (0,1), (1,2), (0,2), (0,3), (1,3), (2,3) (nodes 4..9).
+ */
+static const int tet_edge[6][2] = {{0, 1}, {1, 2}, {0, 2}, {0, 3}, {1, 3}, {2, 3}};
+
+static void tet_dshape(int npe, const double l[4], double dN[][3]) {
+    static const double gl[4][3] = {{-1, -1, -1}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    for (int a = 0; a < 4; ++a)
+        for (int k = 0; k < 3; ++k) dN[a][k] = npe == 4 ? gl[a][k] : (4.0 * l[a] - 1.0) * gl[a][k];
+    if (npe == 10)
+        for (int t = 0; t < 6; ++t) {
+            int i = tet_edge[t][0], j = tet_edge[t][1];
+            for (int k = 0; k < 3; ++k) dN[4 + t][k] = 4.0 * (l[j] * gl[i][k] + l[i] * gl[j][k]);
+        }
+}
+
+/* quadrature points of each element type */
+static int elem_nq(int npe) { return npe == 8 ? 8 : (npe == 4 ? 1 : 4); }
+
+/*
+ * Element rule H_q (left unspecified by the paper): hexes 2x2x2 Gauss points at
+ * +-1/sqrt(3) with unit weights; P1 tets one point at the centroid (exact: the
+ * deformation gradient is constant) with weight 1/6; P2 tets the symmetric
+ * 4-point rule of degree 2, barycentric (a, b, b, b) and permutations with
+ * a = (5 + 3 sqrt 5)/20, b = (5 - sqrt 5)/20, weights 1/24.  Returns the
+ * shape-function derivatives at point g and its weight on the reference cell.
+ */
+static double elem_rule(int npe, int g, double dN[][3]) {
+    if (npe == 8) {
+        const double gp = 1.0 / sqrt(3.0);
+        double xi[3] = {(g & 1) ? gp : -gp, (g & 2) ? gp : -gp, (g & 4) ? gp : -gp};
+        hex_dshape(xi, dN);
+        return 1.0;
+    }
+    double l[4];
+    if (npe == 4) {
+        for (int a = 0; a < 4; ++a) l[a] = 0.25;
+        tet_dshape(4, l, dN);
+        return 1.0 / 6.0;
+    }
+    const double qa = (5.0 + 3.0 * sqrt(5.0)) / 20.0, qb = (5.0 - sqrt(5.0)) / 20.0;
+    for (int a = 0; a < 4; ++a) l[a] = a == g ? qa : qb;
+    tet_dshape(10, l, dN);
+    return 1.0 / 24.0;
+}
+
+static int mesh_npe(const ibref_mesh* m) { return m->nodes_per_elem ? m->nodes_per_elem : 8; }
 
 /*
  * Penalty tethers (the constrained faces of the benchmark and valve models and
@@ -438,26 +490,27 @@ static int tether_apply(const ibref_mesh* m, const double* x, const double* V, d
  * Nodal force from the weak form ("Spatial Discretization" and the mean force
  * contribution formula of the coupling section):
  *   F_a = - sum_e sum_g P(F_g) : grad_X N_a(g) w_g
- * The element rule H_q is left unspecified by the paper; 2x2x2 Gauss points at
- * +-1/sqrt(3) with unit weights are used, w_g = det(dX/dxi) at the point.
+ * with the element rules of elem_rule (trilinear hexes, P1 or P2 tetrahedra),
+ * w_g = det(dX/dxi) at the point times the rule's weight.
  * F_g = sum_a x_a (x) grad_X N_a(g).  Also returns E = sum_e sum_g Psi w_g and
  * the smallest J.  F is overwritten.
  */
 int ibref_fe_force(const ibref_mesh* m, const double* x, double* F, double* energy,
                    double* min_J) {
-    const double gp = 1.0 / sqrt(3.0);
+    const int npe = mesh_npe(m);
+    if (npe != 8 && npe != 4 && npe != 10) return IBREF_E_INVAL;
     double E = 0.0, Jmin = INFINITY;
     for (long r = 0; r < 3L * m->n_nodes; ++r) F[r] = 0.0;
     for (int e = 0; e < m->n_elems; ++e) {
-        const int32_t* cn = m->conn + 8L * e;
+        const int32_t* cn = m->conn + (long)npe * e;
         int mid = m->mat_id[e];
         if (mid < 0 || mid >= m->n_mats) return IBREF_E_INVAL;
         const double* par = m->mat_params + (long)IBREF_MAT_PARAMS * mid;
         int model = m->mat_model[mid];
         const double* ef = m->fibre + 3L * e;
         const double* es = m->sheet ? m->sheet + 3L * e : NULL;
-        double Xe[8][3], xe[8][3], Fe[8][3];
-        for (int a = 0; a < 8; ++a) {
+        double Xe[10][3], xe[10][3], Fe[10][3];
+        for (int a = 0; a < npe; ++a) {
             if (cn[a] < 0 || cn[a] >= m->n_nodes) return IBREF_E_INVAL;
             for (int r = 0; r < 3; ++r) {
                 Xe[a][r] = m->X_ref[3L * cn[a] + r];
@@ -465,12 +518,11 @@ int ibref_fe_force(const ibref_mesh* m, const double* x, double* F, double* ener
                 Fe[a][r] = 0.0;
             }
         }
-        for (int g = 0; g < 8; ++g) {
-            double xi[3] = {(g & 1) ? gp : -gp, (g & 2) ? gp : -gp, (g & 4) ? gp : -gp};
-            double dN[8][3];
-            hex_dshape(xi, dN);
+        for (int g = 0; g < elem_nq(npe); ++g) {
+            double dN[10][3];
+            const double wq = elem_rule(npe, g, dN);
             double J0[9] = {0};
-            for (int a = 0; a < 8; ++a)
+            for (int a = 0; a < npe; ++a)
                 for (int r = 0; r < 3; ++r)
                     for (int c = 0; c < 3; ++c) J0[3 * r + c] += Xe[a][r] * dN[a][c];
             double w = det3(J0);
@@ -479,15 +531,16 @@ int ibref_fe_force(const ibref_mesh* m, const double* x, double* F, double* ener
             cof3(J0, cof); /* cof = w J0^{-T}  ->  J0^{-1}[r][c] = cof[c][r] / w */
             for (int r = 0; r < 3; ++r)
                 for (int c = 0; c < 3; ++c) J0inv[3 * r + c] = cof[3 * c + r] / w;
-            double gN[8][3];
-            for (int a = 0; a < 8; ++a)
+            const double wg = w * wq;   /* quadrature weight in the reference configuration */
+            double gN[10][3];
+            for (int a = 0; a < npe; ++a)
                 for (int c = 0; c < 3; ++c) {
                     double s = 0.0;
                     for (int r = 0; r < 3; ++r) s += dN[a][r] * J0inv[3 * r + c];
                     gN[a][c] = s;
                 }
             double Fm[9] = {0};
-            for (int a = 0; a < 8; ++a)
+            for (int a = 0; a < npe; ++a)
                 for (int r = 0; r < 3; ++r)
                     for (int c = 0; c < 3; ++c) Fm[3 * r + c] += xe[a][r] * gN[a][c];
             double J = det3(Fm);
@@ -495,15 +548,15 @@ int ibref_fe_force(const ibref_mesh* m, const double* x, double* F, double* ener
             double P[9], psi;
             int rc = ibref_pk1(model, par, Fm, ef, es, m->active_tension, P, &psi);
             if (rc) return rc;
-            E += psi * w;
-            for (int a = 0; a < 8; ++a)
+            E += psi * wg;
+            for (int a = 0; a < npe; ++a)
                 for (int r = 0; r < 3; ++r) {
                     double s = 0.0;
                     for (int c = 0; c < 3; ++c) s += P[3 * r + c] * gN[a][c];
-                    Fe[a][r] -= s * w;
+                    Fe[a][r] -= s * wg;
                 }
         }
-        for (int a = 0; a < 8; ++a)
+        for (int a = 0; a < npe; ++a)
             for (int r = 0; r < 3; ++r) F[3L * cn[a] + r] += Fe[a][r];
     }
     int rc = tether_apply(m, x, NULL, F, &E);
@@ -1225,29 +1278,29 @@ int ibref_pk1_tangent(int32_t model, const double* par, const double* Fm, const 
  * dtheta += -w dP/dtheta : (sum_a lam_a (x) grad N_a) */
 static int fe_derivative_loop(const ibref_mesh* m, const double* x, const double* V, double* out,
                               int mode) {
-    const double gp = 1.0 / sqrt(3.0);
+    const int npe = mesh_npe(m);
+    if (npe != 8 && npe != 4 && npe != 10) return IBREF_E_INVAL;
     for (int e = 0; e < m->n_elems; ++e) {
-        const int32_t* cn = m->conn + 8L * e;
+        const int32_t* cn = m->conn + (long)npe * e;
         int mid = m->mat_id[e];
         if (mid < 0 || mid >= m->n_mats) return IBREF_E_INVAL;
         const double* par = m->mat_params + (long)IBREF_MAT_PARAMS * mid;
         int model = m->mat_model[mid];
         const double* ef = m->fibre + 3L * e;
         const double* es = m->sheet ? m->sheet + 3L * e : NULL;
-        double Xe[8][3], xe[8][3], ve[8][3], He[8][3];
-        for (int a = 0; a < 8; ++a)
+        double Xe[10][3], xe[10][3], ve[10][3], He[10][3];
+        for (int a = 0; a < npe; ++a)
             for (int r = 0; r < 3; ++r) {
                 Xe[a][r] = m->X_ref[3L * cn[a] + r];
                 xe[a][r] = x[3L * cn[a] + r];
                 ve[a][r] = V[3L * cn[a] + r];
                 He[a][r] = 0.0;
             }
-        for (int g = 0; g < 8; ++g) {
-            double xi[3] = {(g & 1) ? gp : -gp, (g & 2) ? gp : -gp, (g & 4) ? gp : -gp};
-            double dN[8][3];
-            hex_dshape(xi, dN);
+        for (int g = 0; g < elem_nq(npe); ++g) {
+            double dN[10][3];
+            const double wq = elem_rule(npe, g, dN);
             double J0[9] = {0};
-            for (int a = 0; a < 8; ++a)
+            for (int a = 0; a < npe; ++a)
                 for (int r = 0; r < 3; ++r)
                     for (int c = 0; c < 3; ++c) J0[3 * r + c] += Xe[a][r] * dN[a][c];
             double w = det3(J0);
@@ -1256,15 +1309,16 @@ static int fe_derivative_loop(const ibref_mesh* m, const double* x, const double
             cof3(J0, cof);
             for (int r = 0; r < 3; ++r)
                 for (int c = 0; c < 3; ++c) J0inv[3 * r + c] = cof[3 * c + r] / w;
-            double gN[8][3];
-            for (int a = 0; a < 8; ++a)
+            const double wg = w * wq;
+            double gN[10][3];
+            for (int a = 0; a < npe; ++a)
                 for (int c = 0; c < 3; ++c) {
                     double s = 0.0;
                     for (int r = 0; r < 3; ++r) s += dN[a][r] * J0inv[3 * r + c];
                     gN[a][c] = s;
                 }
             double Fm[9] = {0}, dF[9] = {0};
-            for (int a = 0; a < 8; ++a)
+            for (int a = 0; a < npe; ++a)
                 for (int r = 0; r < 3; ++r)
                     for (int c = 0; c < 3; ++c) {
                         Fm[3 * r + c] += xe[a][r] * gN[a][c];
@@ -1274,11 +1328,11 @@ static int fe_derivative_loop(const ibref_mesh* m, const double* x, const double
                 double dP[9];
                 int rc = ibref_pk1_tangent(model, par, Fm, ef, es, m->active_tension, dF, dP);
                 if (rc) return rc;
-                for (int a = 0; a < 8; ++a)
+                for (int a = 0; a < npe; ++a)
                     for (int r = 0; r < 3; ++r) {
                         double s = 0.0;
                         for (int c = 0; c < 3; ++c) s += dP[3 * r + c] * gN[a][c];
-                        He[a][r] -= s * w;
+                        He[a][r] -= s * wg;
                     }
             } else if (model == IBREF_HOLZAPFEL_OGDEN) {
                 /* dP/da, dP/db (isotropic), dP/da_f, dP/db_f (fibre), contracted with dF */
@@ -1303,18 +1357,18 @@ static int fe_derivative_loop(const ibref_mesh* m, const double* x, const double
                     }
                 double I4 = Fe[0] * Fe[0] + Fe[1] * Fe[1] + Fe[2] * Fe[2];
                 double* dt = out + 4L * mid;
-                dt[0] += -w * E1 * Miso;
-                dt[1] += -w * a0 * (Jm23 * I1 - 3.0) * E1 * Miso;
+                dt[0] += -wg * E1 * Miso;
+                dt[1] += -wg * a0 * (Jm23 * I1 - 3.0) * E1 * Miso;
                 if (I4 > 1.0) {
                     double Ef = exp(bf * (I4 - 1.0) * (I4 - 1.0));
-                    dt[2] += -w * 2.0 * (I4 - 1.0) * Ef * Mfib;
-                    dt[3] += -w * 2.0 * af * (I4 - 1.0) * (I4 - 1.0) * (I4 - 1.0) * Ef * Mfib;
+                    dt[2] += -wg * 2.0 * (I4 - 1.0) * Ef * Mfib;
+                    dt[3] += -wg * 2.0 * af * (I4 - 1.0) * (I4 - 1.0) * (I4 - 1.0) * Ef * Mfib;
                 }
                 (void)af;
             }
         }
         if (mode == 0)
-            for (int a = 0; a < 8; ++a)
+            for (int a = 0; a < npe; ++a)
                 for (int r = 0; r < 3; ++r) out[3L * cn[a] + r] += He[a][r];
     }
     return IBREF_OK;

@@ -15,7 +15,8 @@
  *            i*h along d and cell centres ((.+1/2)h) along the other axes;
  *            pressure lives at cell centres.
  *   nodes    X[n_nodes][3], unwrapped positions (only stencil indices wrap).
- *   hexes    conn[n_elems][8], local node a = i + 2j + 4k at (2i-1,2j-1,2k-1).
+ *   hexes    conn[n_elems][8], local node a = i + 2j + 4k at (2i-1,2j-1,2k-1);
+ *            or tetrahedra, conn[n_elems][4 or 10] (see nodes_per_elem).
  *   quads    faces[n_faces][4], local node a = i + 2j at (2i-1,2j-1).
  *
  * Return codes: 0 ok, 1 invalid argument, 4 no convergence, 5 numeric
@@ -75,6 +76,9 @@ typedef struct {
     const int32_t* tether_node;     /* [n_tethers] distinct node indices */
     const double* tether_target;    /* [n_tethers][3] Y */
     const double* tether_K;         /* [n_tethers][6] symmetric K: xx, yy, zz, xy, xz, yz */
+    int32_t nodes_per_elem;    /* 8 (or 0): trilinear hexes; 4: P1 tetrahedra; 10: P2
+                                  tetrahedra (vertices 0-3, then edge nodes on (0,1), (1,2),
+                                  (0,2), (0,3), (1,3), (2,3)); conn is [n_elems][this] */
 } ibref_mesh;
 
 typedef struct {

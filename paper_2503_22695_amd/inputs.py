@@ -175,6 +175,44 @@ def block_mesh(n_el: int, side: float, centre=(0.5, 0.5, 0.5)):
     return X, _orient(conn, X)
 
 
+# edge nodes of the 10-node tetrahedron, in local order 4..9
+TET_EDGES = ((0, 1), (1, 2), (0, 2), (0, 3), (1, 3), (2, 3))
+
+
+def tet_block_mesh(n_el: int, side: float, order: int = 1, centre=(0.5, 0.5, 0.5)):
+    """Cube of n_el^3 cells, each split into 6 tetrahedra around its main
+    diagonal (Kuhn's subdivision: conforming on the grid), positively oriented.
+    order 1: 4-node tets on the (n_el+1)^3 grid nodes; order 2: 10-node tets
+    with one node per edge (at its midpoint), vertices first.  Returns X_ref
+    [n_nodes, 3] and conn [6 n_el^3, 4 or 10]."""
+    X, _ = block_mesh(n_el, side, centre)
+    m = n_el + 1
+    e0, e1, e2 = np.meshgrid(np.arange(n_el), np.arange(n_el), np.arange(n_el), indexing="ij")
+    base = np.stack([e0.ravel(order="F"), e1.ravel(order="F"), e2.ravel(order="F")], axis=1)
+    tets = []
+    for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        corner = np.zeros(3, dtype=np.int64)
+        verts = [base + corner]
+        for ax in perm:
+            corner = corner.copy()
+            corner[ax] = 1
+            verts.append(base + corner)
+        tets.append(np.stack([v[:, 0] + m * (v[:, 1] + m * v[:, 2]) for v in verts], axis=1))
+    conn = np.concatenate(tets)
+    P = X[conn]
+    vol = np.einsum("ei,ei->e", P[:, 1] - P[:, 0], np.cross(P[:, 2] - P[:, 0], P[:, 3] - P[:, 0]))
+    neg = vol < 0
+    conn[neg] = conn[neg][:, [0, 2, 1, 3]]
+    if order == 1:
+        return X, conn.astype(np.int32)
+    pairs = np.concatenate([np.sort(conn[:, [i, j]], axis=1) for i, j in TET_EDGES])
+    uniq, inv = np.unique(pairs, axis=0, return_inverse=True)
+    mid = 0.5 * (X[uniq[:, 0]] + X[uniq[:, 1]])
+    edge_node = X.shape[0] + inv.reshape(len(TET_EDGES), -1).T
+    conn10 = np.concatenate([conn, edge_node], axis=1)
+    return np.concatenate([X, mid]), conn10.astype(np.int32)
+
+
 def shell_mesh(n_theta: int, n_psi: int, n_tau: int, h: float, cx: float = 0.325,
                with_sheet: bool = False):
     """Truncated ellipsoidal shell.
@@ -384,6 +422,30 @@ def law_block(model: int, n: int = 32, n_steps: int = 10, seed: int = 0) -> Prob
     return p
 
 
+def tet_block(order: int, model: int = STANDARD_REINFORCING, n: int = 32, n_el: int = 4,
+              n_steps: int = 10, dt: float = 1e-3, seed: int = 0, kappa_tether: float = 1.0) -> Problem:
+    """Tetrahedral block (order 1: P1, order 2: P2), side 0.3, stretched 1.1x in
+    x and jittered, with one of the laws, the Cook's-membrane fibre (1, 1, 1)/sqrt(3),
+    and its x-min face held at its initial position by penalty tethers (the
+    benchmark's fixed face)."""
+    h = 1.0 / n
+    X_ref, conn = tet_block_mesh(n_el, 0.3, order)
+    c = np.array([0.5, 0.5, 0.5])
+    rng = np.random.default_rng(seed)
+    X0 = c + (X_ref - c) * np.array([1.1, 1.0, 1.0])
+    X0 = X0 + rng.uniform(-0.05 * h, 0.05 * h, size=X0.shape)
+    ne = conn.shape[0]
+    node = np.flatnonzero(X_ref[:, 0] <= X_ref[:, 0].min() + 1e-12).astype(np.int32)
+    K = np.tile([kappa_tether, kappa_tether, kappa_tether, 0.0, 0.0, 0.0], (node.size, 1))
+    params = HO_PARAMS if model == HOLZAPFEL_OGDEN else (NH_BLOCK if model == NEO_HOOKEAN
+                                                          else LAW_PARAMS[model])
+    return Problem(name=f"tet{4 if order == 1 else 10}_block_{n}", n=n, rho=1.0, mu=0.01, dt=dt,
+                   n_steps=n_steps, X_ref=X_ref, X0=X0, conn=conn,
+                   fibre=np.ascontiguousarray(np.tile(np.ones(3) / math.sqrt(3.0), (ne, 1))),
+                   mat_id=np.zeros(ne, dtype=np.int32), materials=[Material(model, params)],
+                   faces=np.zeros((0, 4), dtype=np.int32), tethers=(node, X0[node].copy(), K))
+
+
 def ho_shell(n: int = 128, n_theta: int = 224, n_psi: int = 80, n_tau: int = 6,
              n_steps: int = 100, dt: float = 5e-4) -> Problem:
     """Holzapfel-Ogden truncated-ellipsoid shell with endocardial pressure pulse."""
@@ -502,8 +564,11 @@ def workload(name: str) -> Problem:
         return lv_shell()
     if name == "lv_block_32":        # full HO + active tension, 32^3, 20 steps
         return lv_block()
+    if name == "tet10_block_64":     # P2 tets, Psi_1, tethered face: the benchmark's settings
+        p = tet_block(2, n=64, n_el=10, n_steps=20)
+        return p
     raise KeyError(name)
 
 
 WORKLOADS = ("nh_block_32", "ho_shell_128", "shell_leaflets_192",
-             "nh_block_32_mixed", "ho_block_64", "lv_shell_128", "lv_block_32")
+             "nh_block_32_mixed", "ho_block_64", "lv_shell_128", "lv_block_32", "tet10_block_64")
