@@ -105,6 +105,16 @@ const char* hipib_last_error(void);
 hipib_status hipib_set_mesh(hipib_ctx* ctx, int32_t n_nodes, const double* X_ref,
                             int32_t n_elems, const int32_t* conn, const double* fibre,
                             const int32_t* mat_id);
+/* As hipib_set_mesh for any element type (the benchmark discretises its solid
+ * with P2 tetrahedra): nodes_per_elem 8 = trilinear hexes (2x2x2 Gauss), 4 = P1
+ * tetrahedra (one point at the centroid), 10 = P2 tetrahedra (vertices 0-3, then
+ * edge nodes on (0,1), (1,2), (0,2), (0,3), (1,3), (2,3); the symmetric 4-point
+ * rule of degree 2); conn [n_elems][nodes_per_elem], each element positively
+ * oriented (det dX/dxi > 0 on the reference simplex xi, eta, zeta >= 0,
+ * xi + eta + zeta <= 1 with vertices at the origin and the unit axes). */
+hipib_status hipib_set_mesh_elements(hipib_ctx* ctx, int32_t n_nodes, const double* X_ref,
+                                     int32_t n_elems, int32_t nodes_per_elem, const int32_t* conn,
+                                     const double* fibre, const int32_t* mat_id);
 /* Material law of one id ("Constitutive laws"), U = kappa/2 (ln J)^2 throughout:
  *   neo-Hookean (mu_s, kappa): Psi = mu_s/2 (I1bar - 3) + U;
  *   modified standard reinforcing Psi_1 (G_T, G_L, E_L, kappa):

@@ -131,18 +131,20 @@ k_vjp_X(const double* __restrict__ X, const double* __restrict__ field,
 
 // out += (dF/dx) V per element: dF = Jv Jr^{-1}, dP = tangent of P along dF,
 // contribution -w dP grad N_a = -sum_s (w dP Jr^{-T})[r][s] dN_a/dxi_s
+template <typename S>
 __global__ void __launch_bounds__(128)
 k_fe_hvp(const double* __restrict__ X, const double* __restrict__ Xref,
          const int32_t* __restrict__ conn, const double* __restrict__ fibre,
          const double* __restrict__ sheet, const int32_t* __restrict__ mat_id, MatTable mats,
          double Ta, int ne, const double* __restrict__ V, double* __restrict__ out, MGState* st,
          double* __restrict__ contrib) {
+    constexpr int N = S::N;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
-    int nd[8];
-    for (int a = 0; a < 8; ++a) nd[a] = conn[8 * e + a];
-    double xr[8][3], xc[8][3], vv[8][3], he[8][3];
-    for (int a = 0; a < 8; ++a)
+    int nd[N];
+    for (int a = 0; a < N; ++a) nd[a] = conn[N * (int64_t)e + a];
+    double xr[N][3], xc[N][3], vv[N][3], he[N][3];
+    for (int a = 0; a < N; ++a)
         for (int r = 0; r < 3; ++r) {
             xr[a][r] = Xref[3 * nd[a] + r] - Xref[3 * nd[0] + r];
             xc[a][r] = X[3 * nd[a] + r] - X[3 * nd[0] + r];
@@ -161,16 +163,14 @@ k_fe_hvp(const double* __restrict__ X, const double* __restrict__ Xref,
         es[2] = sheet[3 * e + 2];
     }
     const double ta = model == HIPIB_HOLZAPFEL_OGDEN ? Ta : 0.0;
-    const double gp = 0.57735026918962576451;
     bool bad = false;
-    for (int g = 0; g < 8; ++g) {
-        const double xi[3] = {(g & 1) ? gp : -gp, (g & 2) ? gp : -gp, (g & 4) ? gp : -gp};
-        double dN[8][3];
-        hex_dN(xi, dN);
+    for (int g = 0; g < S::Q; ++g) {
+        double dN[N][3];
+        const double wq = elem_rule<S, double>(g, dN);
         double Jr[9], Jx[9], Jv[9];
-        gather_jac(xr, dN, Jr);
-        gather_jac(xc, dN, Jx);
-        gather_jac(vv, dN, Jv);
+        gather_jac<N>(xr, dN, Jr);
+        gather_jac<N>(xc, dN, Jx);
+        gather_jac<N>(vv, dN, Jv);
         const double w = det3(Jr);
         if (!(w > 0.0)) { bad = true; continue; }
         double cr[9], Jri[9];
@@ -181,22 +181,23 @@ k_fe_hvp(const double* __restrict__ X, const double* __restrict__ Xref,
         matmul3(Jx, Jri, Fm);
         matmul3(Jv, Jri, dF);
         if (!pk1_tangent<double>(model, par, Fm, ef, es, sh, ta, dF, dP)) { bad = true; continue; }
+        const double wg = w * wq;
         double Q[9];
         for (int r = 0; r < 3; ++r)
             for (int s = 0; s < 3; ++s)
-                Q[3 * r + s] = w * (dP[3 * r] * Jri[3 * s] + dP[3 * r + 1] * Jri[3 * s + 1] +
-                                    dP[3 * r + 2] * Jri[3 * s + 2]);
-        for (int a = 0; a < 8; ++a)
+                Q[3 * r + s] = wg * (dP[3 * r] * Jri[3 * s] + dP[3 * r + 1] * Jri[3 * s + 1] +
+                                     dP[3 * r + 2] * Jri[3 * s + 2]);
+        for (int a = 0; a < N; ++a)
             for (int r = 0; r < 3; ++r)
                 he[a][r] -= Q[3 * r] * dN[a][0] + Q[3 * r + 1] * dN[a][1] + Q[3 * r + 2] * dN[a][2];
     }
     if (bad) atomicOr(&st->numeric, 1);
     if (contrib) {  // deterministic mode: gathered per node in element order
-        for (int a = 0; a < 8; ++a)
-            for (int r = 0; r < 3; ++r) contrib[24 * (int64_t)e + 3 * a + r] = he[a][r];
+        for (int a = 0; a < N; ++a)
+            for (int r = 0; r < 3; ++r) contrib[3 * (N * (int64_t)e + a) + r] = he[a][r];
         return;
     }
-    for (int a = 0; a < 8; ++a)
+    for (int a = 0; a < N; ++a)
         for (int r = 0; r < 3; ++r) atomicAdd(out + 3 * nd[a] + r, he[a][r]);
 }
 
@@ -207,6 +208,7 @@ k_fe_hvp(const double* __restrict__ X, const double* __restrict__ Xref,
 // Per-block sums in LDS, then one global atomic per block and entry; in
 // deterministic mode (part != null) the per-element terms go to part[e][4]
 // for a fixed-order reduction.
+template <typename S>
 __global__ void __launch_bounds__(128)
 k_fe_param_vjp(const double* __restrict__ X, const double* __restrict__ Xref,
                const int32_t* __restrict__ conn, const double* __restrict__ fibre,
@@ -222,10 +224,11 @@ k_fe_param_vjp(const double* __restrict__ X, const double* __restrict__ Xref,
     if (e < ne) {
         const int m = mat_id[e];
         if (mats.model[m] == HIPIB_HOLZAPFEL_OGDEN) {
-            int nd[8];
-            for (int a = 0; a < 8; ++a) nd[a] = conn[8 * e + a];
-            double xr[8][3], xc[8][3], ll[8][3];
-            for (int a = 0; a < 8; ++a)
+            constexpr int N = S::N;
+            int nd[N];
+            for (int a = 0; a < N; ++a) nd[a] = conn[N * (int64_t)e + a];
+            double xr[N][3], xc[N][3], ll[N][3];
+            for (int a = 0; a < N; ++a)
                 for (int r = 0; r < 3; ++r) {
                     xr[a][r] = Xref[3 * nd[a] + r] - Xref[3 * nd[0] + r];
                     xc[a][r] = X[3 * nd[a] + r] - X[3 * nd[0] + r];
@@ -233,22 +236,21 @@ k_fe_param_vjp(const double* __restrict__ X, const double* __restrict__ Xref,
                 }
             const double* par = mats.p[m];
             const double ef[3] = {fibre[3 * e], fibre[3 * e + 1], fibre[3 * e + 2]};
-            const double gp = 0.57735026918962576451;
             double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
-            for (int g = 0; g < 8; ++g) {
-                const double xi[3] = {(g & 1) ? gp : -gp, (g & 2) ? gp : -gp, (g & 4) ? gp : -gp};
-                double dN[8][3];
-                hex_dN(xi, dN);
+            for (int g = 0; g < S::Q; ++g) {
+                double dN[N][3];
+                const double wq = elem_rule<S, double>(g, dN);
                 double Jr[9], Jx[9], Jl[9];
-                gather_jac(xr, dN, Jr);
-                gather_jac(xc, dN, Jx);
-                gather_jac(ll, dN, Jl);
-                const double w = det3(Jr);
-                if (!(w > 0.0)) continue;
+                gather_jac<N>(xr, dN, Jr);
+                gather_jac<N>(xc, dN, Jx);
+                gather_jac<N>(ll, dN, Jl);
+                const double w0 = det3(Jr);
+                if (!(w0 > 0.0)) continue;
+                const double w = w0 * wq;
                 double cr[9], Jri[9];
                 cof3(Jr, cr);
                 for (int r = 0; r < 3; ++r)
-                    for (int c = 0; c < 3; ++c) Jri[3 * r + c] = cr[3 * c + r] / w;
+                    for (int c = 0; c < 3; ++c) Jri[3 * r + c] = cr[3 * c + r] / w0;
                 double Fm[9], Gl[9];
                 matmul3(Jx, Jri, Fm);
                 matmul3(Jl, Jri, Gl);
@@ -410,6 +412,40 @@ hipib_status ensure_adjoint_scratch(hipib_ctx* ctx) {
     return HIPIB_OK;
 }
 
+// element-derivative kernels, one instantiation per element type
+template <typename S>
+hipib_status hvp_elements_t(hipib_ctx* ctx, const double* X, const double* V, double* out,
+                            double* contrib) {
+    k_fe_hvp<S><<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
+        X, ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats, ctx->active_ta,
+        ctx->ne, V, out, ctx->st, contrib);
+    HIPIB_HIP(hipGetLastError());
+    return HIPIB_OK;
+}
+
+hipib_status hvp_elements(hipib_ctx* ctx, const double* X, const double* V, double* out,
+                          double* contrib) {
+    if (ctx->npe == 4) return hvp_elements_t<Tet4>(ctx, X, V, out, contrib);
+    if (ctx->npe == 10) return hvp_elements_t<Tet10>(ctx, X, V, out, contrib);
+    return hvp_elements_t<Hex8>(ctx, X, V, out, contrib);
+}
+
+template <typename S>
+hipib_status param_vjp_elements_t(hipib_ctx* ctx, const double* X, const double* lamF,
+                                  double* dtheta, double* part) {
+    k_fe_param_vjp<S><<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
+        X, ctx->Xref, ctx->conn, ctx->fibre, ctx->mat_id, ctx->mats, ctx->ne, lamF, dtheta, part);
+    HIPIB_HIP(hipGetLastError());
+    return HIPIB_OK;
+}
+
+hipib_status param_vjp_elements(hipib_ctx* ctx, const double* X, const double* lamF,
+                                double* dtheta, double* part) {
+    if (ctx->npe == 4) return param_vjp_elements_t<Tet4>(ctx, X, lamF, dtheta, part);
+    if (ctx->npe == 10) return param_vjp_elements_t<Tet10>(ctx, X, lamF, dtheta, part);
+    return param_vjp_elements_t<Hex8>(ctx, X, lamF, dtheta, part);
+}
+
 }  // namespace
 
 hipib_status adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n, const double* u_np1,
@@ -447,16 +483,9 @@ hipib_status adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n, 
         HIPIB_TRY(launch_fe_force(ctx, X_n, pressure, ctx->F));                    // forward force
         HIPIB_TRY(vjp_X(ctx, X_n, ctx->adj_lg, ctx->F, lam_X, 1.0 / (h * h3)));    // spreading term
         if (ctx->ne > 0) {
-            k_fe_hvp<<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
-                X_n, ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats,
-                ctx->active_ta, ctx->ne, ctx->adj_lamF, lam_X, ctx->st,
-                det ? ctx->det_contrib : nullptr);
-            HIPIB_HIP(hipGetLastError());
+            HIPIB_TRY(hvp_elements(ctx, X_n, ctx->adj_lamF, lam_X, det ? ctx->det_contrib : nullptr));
             if (det) HIPIB_TRY(det_gather_nodes(ctx, false, true, lam_X));
-            k_fe_param_vjp<<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
-                X_n, ctx->Xref, ctx->conn, ctx->fibre, ctx->mat_id, ctx->mats, ctx->ne,
-                ctx->adj_lamF, dtheta, det ? ctx->det_param : nullptr);
-            HIPIB_HIP(hipGetLastError());
+            HIPIB_TRY(param_vjp_elements(ctx, X_n, ctx->adj_lamF, dtheta, det ? ctx->det_param : nullptr));
             if (det) HIPIB_TRY(det_param_reduce(ctx, dtheta));
         }
         HIPIB_TRY(launch_tethers(ctx, X_n, ctx->adj_lamF, lam_X));   // K symmetric: K^T lamF = K lamF
@@ -489,10 +518,7 @@ hipib_status launch_fe_hvp(hipib_ctx* ctx, const double* X, const double* V, dou
     HIPIB_TRY(launch_zero(ctx, out, 3 * (int64_t)ctx->nn));
     if (ctx->ne > 0) {
         const bool det = ctx->cfg.deterministic != 0;
-        k_fe_hvp<<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
-            X, ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats, ctx->active_ta,
-            ctx->ne, V, out, ctx->st, det ? ctx->det_contrib : nullptr);
-        HIPIB_HIP(hipGetLastError());
+        HIPIB_TRY(hvp_elements(ctx, X, V, out, det ? ctx->det_contrib : nullptr));
         if (det) HIPIB_TRY(det_gather_nodes(ctx, false, true, out));
     }
     return launch_tethers(ctx, X, V, out);
@@ -501,10 +527,7 @@ hipib_status launch_fe_hvp(hipib_ctx* ctx, const double* X, const double* V, dou
 hipib_status launch_fe_param_vjp(hipib_ctx* ctx, const double* X, const double* lamF, double* dtheta) {
     if (ctx->ne == 0) return HIPIB_OK;
     const bool det = ctx->cfg.deterministic != 0;
-    k_fe_param_vjp<<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
-        X, ctx->Xref, ctx->conn, ctx->fibre, ctx->mat_id, ctx->mats, ctx->ne, lamF, dtheta,
-        det ? ctx->det_param : nullptr);
-    HIPIB_HIP(hipGetLastError());
+    HIPIB_TRY(param_vjp_elements(ctx, X, lamF, dtheta, det ? ctx->det_param : nullptr));
     if (det) HIPIB_TRY(det_param_reduce(ctx, dtheta));
     return HIPIB_OK;
 }

@@ -312,13 +312,22 @@ hipib_status hipib_set_stream(hipib_ctx* ctx, void* stream) {
 
 hipib_status hipib_set_mesh(hipib_ctx* ctx, int32_t n_nodes, const double* X_ref, int32_t n_elems,
                             const int32_t* conn, const double* fibre, const int32_t* mat_id) {
+    return hipib_set_mesh_elements(ctx, n_nodes, X_ref, n_elems, 8, conn, fibre, mat_id);
+}
+
+hipib_status hipib_set_mesh_elements(hipib_ctx* ctx, int32_t n_nodes, const double* X_ref,
+                                     int32_t n_elems, int32_t nodes_per_elem, const int32_t* conn,
+                                     const double* fibre, const int32_t* mat_id) {
     HIPIB_TRY(check_ctx(ctx));
+    const int npe = nodes_per_elem;
+    if (npe != 8 && npe != 4 && npe != 10)
+        return fail(HIPIB_E_INVAL, "nodes_per_elem = %d (8, 4 or 10)", npe);
     if (n_nodes < 0 || n_elems < 0) return fail(HIPIB_E_INVAL, "negative mesh size");
     if (n_elems > 0 && n_nodes == 0) return fail(HIPIB_E_INVAL, "elements without nodes");
     if (n_nodes > 0 && !X_ref) return fail(HIPIB_E_INVAL, "null X_ref");
     if (n_elems > 0 && (!conn || !fibre || !mat_id)) return fail(HIPIB_E_INVAL, "null element array");
     uint32_t used = 0;
-    for (int64_t t = 0; t < 8 * (int64_t)n_elems; ++t)
+    for (int64_t t = 0; t < npe * (int64_t)n_elems; ++t)
         if (conn[t] < 0 || conn[t] >= n_nodes)
             return fail(HIPIB_E_INVAL, "conn[%lld] = %d out of range", (long long)t, conn[t]);
     for (int32_t e = 0; e < n_elems; ++e) {
@@ -338,7 +347,7 @@ hipib_status hipib_set_mesh(hipib_ctx* ctx, int32_t n_nodes, const double* X_ref
     ctx->nf = 0;
     HIPIB_TRY(dev_alloc(ctx, &ctx->Xref, 3 * (size_t)n_nodes));
     HIPIB_TRY(dev_alloc(ctx, &ctx->F, 3 * (size_t)n_nodes));
-    HIPIB_TRY(dev_alloc(ctx, &ctx->conn, 8 * (size_t)n_elems));
+    HIPIB_TRY(dev_alloc(ctx, &ctx->conn, npe * (size_t)n_elems));
     HIPIB_TRY(dev_alloc(ctx, &ctx->fibre, 3 * (size_t)n_elems));
     HIPIB_TRY(dev_alloc(ctx, &ctx->mat_id, (size_t)n_elems));
     HIPIB_TRY(dev_alloc(ctx, &ctx->node_tile, (size_t)n_nodes));
@@ -350,12 +359,13 @@ hipib_status hipib_set_mesh(hipib_ctx* ctx, int32_t n_nodes, const double* X_ref
     if (n_nodes > 0)
         HIPIB_HIP(hipMemcpy(ctx->Xref, X_ref, 3 * sizeof(double) * n_nodes, hipMemcpyHostToDevice));
     if (n_elems > 0) {
-        HIPIB_HIP(hipMemcpy(ctx->conn, conn, 8 * sizeof(int32_t) * n_elems, hipMemcpyHostToDevice));
+        HIPIB_HIP(hipMemcpy(ctx->conn, conn, npe * sizeof(int32_t) * n_elems, hipMemcpyHostToDevice));
         HIPIB_HIP(hipMemcpy(ctx->fibre, fibre, 3 * sizeof(double) * n_elems, hipMemcpyHostToDevice));
         HIPIB_HIP(hipMemcpy(ctx->mat_id, mat_id, sizeof(int32_t) * n_elems, hipMemcpyHostToDevice));
     }
     ctx->nn = n_nodes;
     ctx->ne = n_elems;
+    ctx->npe = npe;
     ctx->mat_used = used;
     if (ctx->cfg.deterministic) {
         hipib_status sd = det_prepare_mesh(ctx, conn);

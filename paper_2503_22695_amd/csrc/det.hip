@@ -122,12 +122,12 @@ k_det_param_reduce(const double* __restrict__ part, const int32_t* __restrict__ 
 
 hipib_status det_prepare_mesh(hipib_ctx* ctx, const int32_t* conn) {
     // node -> incident (element, local node) pairs in element order
-    const int nn = ctx->nn, ne = ctx->ne;
-    std::vector<int32_t> off(nn + 1, 0), inc(8 * (size_t)ne);
-    for (int64_t t = 0; t < 8 * (int64_t)ne; ++t) ++off[conn[t] + 1];
+    const int nn = ctx->nn, ne = ctx->ne, npe = ctx->npe;
+    std::vector<int32_t> off(nn + 1, 0), inc(npe * (size_t)ne);
+    for (int64_t t = 0; t < npe * (int64_t)ne; ++t) ++off[conn[t] + 1];
     for (int i = 0; i < nn; ++i) off[i + 1] += off[i];
     std::vector<int32_t> fill(off.begin(), off.end() - 1);
-    for (int64_t t = 0; t < 8 * (int64_t)ne; ++t) inc[fill[conn[t]]++] = (int32_t)t;
+    for (int64_t t = 0; t < npe * (int64_t)ne; ++t) inc[fill[conn[t]]++] = (int32_t)t;
     auto alloc = [&](void** p, size_t bytes) -> hipib_status {
         *p = nullptr;
         if (hipMalloc(p, bytes ? bytes : 1) != hipSuccess) {
@@ -141,7 +141,7 @@ hipib_status det_prepare_mesh(hipib_ctx* ctx, const int32_t* conn) {
     HIPIB_HIP(hipMemcpy(ctx->det_node_off, off.data(), sizeof(int32_t) * (nn + 1), hipMemcpyHostToDevice));
     if (!inc.empty())
         HIPIB_HIP(hipMemcpy(ctx->det_node_inc, inc.data(), sizeof(int32_t) * inc.size(), hipMemcpyHostToDevice));
-    HIPIB_TRY(alloc(reinterpret_cast<void**>(&ctx->det_contrib), sizeof(double) * 24 * (size_t)ne));
+    HIPIB_TRY(alloc(reinterpret_cast<void**>(&ctx->det_contrib), sizeof(double) * 3 * npe * (size_t)ne));
     HIPIB_TRY(alloc(reinterpret_cast<void**>(&ctx->det_param), sizeof(double) * 4 * (size_t)ne));
     // spreading pairs and sort workspace
     const int64_t np = 192 * (int64_t)nn;

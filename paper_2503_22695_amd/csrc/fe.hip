@@ -6,13 +6,14 @@
 // directions) and the left-ventricle model's active fibre stress; penalty
 // tethers add linear springs at constrained nodes.
 //
-// One thread per element.  With Jr = dX/dxi and Jx = dx/dxi at a Gauss point,
+// One thread per element (trilinear hexes, or P1 / P2 tetrahedra: the kernel is
+// instantiated per element type).  With Jr = dX/dxi and Jx = dx/dxi at a Gauss point,
 // F = Jx Jr^{-1}, grad_X N_a = Jr^{-T} grad_xi N_a and
 //   sum_c P[r][c] grad_X N_a[c] w = sum_s Q[r][s] dN_a/dxi_s,  Q = w P Jr^{-T},
 // so the shape-function gradients in X are never formed: per Gauss point the
-// element does two 8-node gathers of 3x3 Jacobians, one 3x3 inverse, the law,
-// one 3x3 product and a 24-entry update, all in registers.  Element rule:
-// 2x2x2 Gauss points at +-1/sqrt(3), unit weights.  Node accumulation uses
+// element does two N-node gathers of 3x3 Jacobians, one 3x3 inverse, the law,
+// one 3x3 product and a 3N-entry update, all in registers (rules in solid.h).
+// Node accumulation uses
 // hardware FP64 atomics, or in deterministic mode per-element contributions
 // gathered per node in element order.
 #include "solid.h"
@@ -20,26 +21,27 @@
 namespace hipib {
 namespace {
 
-// T: arithmetic type of the element computation.  Node positions are taken
-// relative to the element's first node in FP64 before rounding to T (the
-// Jacobians only see differences), and element forces are accumulated into the
-// FP64 nodal array.
-template <typename T>
+// T: arithmetic type of the element computation; S: element type (Hex8, Tet4,
+// Tet10).  Node positions are taken relative to the element's first node in
+// FP64 before rounding to T (the Jacobians only see differences), and element
+// forces are accumulated into the FP64 nodal array.
+template <typename T, typename S>
 __global__ void __launch_bounds__(128)
 k_fe_force(const double* __restrict__ X, const double* __restrict__ Xref,
            const int32_t* __restrict__ conn, const double* __restrict__ fibre,
            const double* __restrict__ sheet, const int32_t* __restrict__ mat_id, MatTable mats,
            double Ta, int ne, double* __restrict__ F, MGState* st, double* __restrict__ contrib) {
+    constexpr int N = S::N;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
-    int nd[8];
+    int nd[N];
 #pragma unroll
-    for (int a = 0; a < 8; ++a) nd[a] = conn[8 * e + a];
-    T xr[8][3], xc[8][3], fe[8][3];
+    for (int a = 0; a < N; ++a) nd[a] = conn[N * (int64_t)e + a];
+    T xr[N][3], xc[N][3], fe[N][3];
     const double r0[3] = {Xref[3 * nd[0]], Xref[3 * nd[0] + 1], Xref[3 * nd[0] + 2]};
     const double c0[3] = {X[3 * nd[0]], X[3 * nd[0] + 1], X[3 * nd[0] + 2]};
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+    for (int a = 0; a < N; ++a)
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             xr[a][r] = (T)(Xref[3 * nd[a] + r] - r0[r]);
@@ -61,24 +63,15 @@ k_fe_force(const double* __restrict__ X, const double* __restrict__ Xref,
     }
     // the active stress acts on Holzapfel-Ogden (myocardium) materials only
     const T ta = model == HIPIB_HOLZAPFEL_OGDEN ? (T)Ta : T(0);
-    const T gp = T(0.57735026918962576451);  // 1/sqrt(3)
     bool bad = false;
-    for (int g = 0; g < 8; ++g) {
-        const T xi[3] = {(g & 1) ? gp : -gp, (g & 2) ? gp : -gp, (g & 4) ? gp : -gp};
-        T dN[8][3];
-#pragma unroll
-        for (int a = 0; a < 8; ++a) {
-            const T s0 = (a & 1) ? T(1) : T(-1), s1 = (a & 2) ? T(1) : T(-1), s2 = (a & 4) ? T(1) : T(-1);
-            const T f0 = T(1) + s0 * xi[0], f1 = T(1) + s1 * xi[1], f2 = T(1) + s2 * xi[2];
-            dN[a][0] = s0 * f1 * f2 * T(0.125);
-            dN[a][1] = f0 * s1 * f2 * T(0.125);
-            dN[a][2] = f0 * f1 * s2 * T(0.125);
-        }
+    for (int g = 0; g < S::Q; ++g) {
+        T dN[N][3];
+        const T wq = elem_rule<S, T>(g, dN);
         T Jr[9], Jx[9];
 #pragma unroll
         for (int t = 0; t < 9; ++t) Jr[t] = Jx[t] = T(0);
 #pragma unroll
-        for (int a = 0; a < 8; ++a)
+        for (int a = 0; a < N; ++a)
 #pragma unroll
             for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -103,15 +96,16 @@ k_fe_force(const double* __restrict__ X, const double* __restrict__ Xref,
                 Fm[3 * r + c] = Jx[3 * r] * Jri[c] + Jx[3 * r + 1] * Jri[3 + c] + Jx[3 * r + 2] * Jri[6 + c];
         T P[9];
         if (!pk1<T>(model, par, Fm, ef, es, sh, ta, P)) { bad = true; continue; }
-        T Q[9];   // w P Jr^{-T}
+        const T wg = w * wq;
+        T Q[9];   // wg P Jr^{-T}
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
             for (int s = 0; s < 3; ++s)
-                Q[3 * r + s] = w * (P[3 * r] * Jri[3 * s] + P[3 * r + 1] * Jri[3 * s + 1] +
-                                    P[3 * r + 2] * Jri[3 * s + 2]);
+                Q[3 * r + s] = wg * (P[3 * r] * Jri[3 * s] + P[3 * r + 1] * Jri[3 * s + 1] +
+                                     P[3 * r + 2] * Jri[3 * s + 2]);
 #pragma unroll
-        for (int a = 0; a < 8; ++a)
+        for (int a = 0; a < N; ++a)
 #pragma unroll
             for (int r = 0; r < 3; ++r)
                 fe[a][r] -= Q[3 * r] * dN[a][0] + Q[3 * r + 1] * dN[a][1] + Q[3 * r + 2] * dN[a][2];
@@ -119,13 +113,13 @@ k_fe_force(const double* __restrict__ X, const double* __restrict__ Xref,
     if (bad) atomicOr(&st->numeric, 1);
     if (contrib) {  // deterministic mode: gathered per node in element order
 #pragma unroll
-        for (int a = 0; a < 8; ++a)
+        for (int a = 0; a < N; ++a)
 #pragma unroll
-            for (int r = 0; r < 3; ++r) contrib[24 * (int64_t)e + 3 * a + r] = (double)fe[a][r];
+            for (int r = 0; r < 3; ++r) contrib[3 * (N * (int64_t)e + a) + r] = (double)fe[a][r];
         return;
     }
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+    for (int a = 0; a < N; ++a)
 #pragma unroll
         for (int r = 0; r < 3; ++r) atomicAdd(F + 3 * nd[a] + r, (double)fe[a][r]);
 }
@@ -218,15 +212,30 @@ hipib_status launch_tethers(hipib_ctx* ctx, const double* X, const double* V, do
     return HIPIB_OK;
 }
 
+namespace {
+// one element kernel per element type
+template <typename S>
+hipib_status launch_elements(hipib_ctx* ctx, const double* X, double* F, double* contrib) {
+    k_fe_force<double, S><<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
+        X, ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats, ctx->active_ta,
+        ctx->ne, F, ctx->st, contrib);
+    HIPIB_HIP(hipGetLastError());
+    return HIPIB_OK;
+}
+
+hipib_status launch_element_forces(hipib_ctx* ctx, const double* X, double* F, double* contrib) {
+    if (ctx->npe == 4) return launch_elements<Tet4>(ctx, X, F, contrib);
+    if (ctx->npe == 10) return launch_elements<Tet10>(ctx, X, F, contrib);
+    return launch_elements<Hex8>(ctx, X, F, contrib);
+}
+}  // namespace
+
 hipib_status launch_fe_force(hipib_ctx* ctx, const double* X, double pressure, double* F) {
     k_clear_numeric<<<1, 64, 0, ctx->stream>>>(ctx->st);
     const bool det = ctx->cfg.deterministic != 0;
     if (det) {
         if (ctx->ne > 0) {
-            k_fe_force<double><<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
-                X, ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats,
-                ctx->active_ta, ctx->ne, F, ctx->st, ctx->det_contrib);
-            HIPIB_HIP(hipGetLastError());
+            HIPIB_TRY(launch_element_forces(ctx, X, F, ctx->det_contrib));
             HIPIB_TRY(det_gather_nodes(ctx, false, false, F));
         } else {
             HIPIB_TRY(launch_zero(ctx, F, 3 * (int64_t)ctx->nn));
@@ -246,10 +255,7 @@ hipib_status launch_fe_force(hipib_ctx* ctx, const double* X, double pressure, d
         // would leave rounding-size spurious forces of ~1e-7 relative to the
         // element forces, which exceeds the mixed mode's 1e-6 error budget over
         // a run; the force kernel is ~1% of a step.
-        k_fe_force<double><<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
-            X, ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats, ctx->active_ta,
-            ctx->ne, F, ctx->st, nullptr);
-        HIPIB_HIP(hipGetLastError());
+        HIPIB_TRY(launch_element_forces(ctx, X, F, nullptr));
     }
     if (ctx->nf > 0 && pressure != 0.0) {
         k_pressure_load<<<(ctx->nf + 255) / 256, 256, 0, ctx->stream>>>(X, ctx->faces, ctx->nf,

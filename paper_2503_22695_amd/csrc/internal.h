@@ -90,9 +90,10 @@ struct hipib_ctx {
 
     // Lagrangian mesh
     int32_t nn = 0, ne = 0, nf = 0;
+    int npe = 8;              // nodes per element: 8 hexes, 4 P1 tets, 10 P2 tets
     bool mesh_set = false;
     double* Xref = nullptr;
-    int32_t* conn = nullptr;
+    int32_t* conn = nullptr;  // [ne][npe]
     double* fibre = nullptr;
     int32_t* mat_id = nullptr;
     int32_t* faces = nullptr;
@@ -125,8 +126,8 @@ struct hipib_ctx {
 
     // deterministic mode (allocated by set_mesh / set_pressure_faces)
     int32_t* det_node_off = nullptr;   // [nn + 1] CSR: node -> (element, local node) in element order
-    int32_t* det_node_inc = nullptr;   // [8 ne] entries e * 8 + a
-    double* det_contrib = nullptr;     // [ne][8][3] per-element nodal contributions
+    int32_t* det_node_inc = nullptr;   // [npe ne] entries e * npe + a
+    double* det_contrib = nullptr;     // [ne][npe][3] per-element nodal contributions
     double* det_param = nullptr;       // [ne][4] per-element parameter-gradient terms
     int32_t* det_face_off = nullptr;   // [nn + 1] CSR: node -> (face, local node)
     int32_t* det_face_inc = nullptr;   // [4 nf] entries f * 4 + a

@@ -292,13 +292,60 @@ __device__ __forceinline__ void hex_dN(const T* xi, T dN[8][3]) {
     }
 }
 
+// Element types: node count N, quadrature points Q, and the rule (the paper
+// leaves it open): hexes 2x2x2 Gauss at +-1/sqrt(3) with unit weights; P1 tets
+// one point at the centroid, weight 1/6; P2 tets (vertices 0-3, edge nodes on
+// (0,1), (1,2), (0,2), (0,3), (1,3), (2,3)) the symmetric 4-point rule of degree 2,
+// barycentric (a, b, b, b) and permutations, a = (5 + 3 sqrt 5)/20, b = (5 - sqrt 5)/20,
+// weights 1/24.  Tets use barycentric l0 = 1 - xi - eta - zeta, l1..l3 = xi, eta, zeta.
+struct Hex8 { static constexpr int N = 8, Q = 8; };
+struct Tet4 { static constexpr int N = 4, Q = 1; };
+struct Tet10 { static constexpr int N = 10, Q = 4; };
+
+// dN_a/dxi at quadrature point g; returns the point's reference weight
+template <typename S, typename T>
+__device__ __forceinline__ T elem_rule(int g, T dN[S::N][3]) {
+    if constexpr (S::N == 8) {
+        const T gp = T(0.57735026918962576451);  // 1/sqrt(3)
+        const T xi[3] = {(g & 1) ? gp : -gp, (g & 2) ? gp : -gp, (g & 4) ? gp : -gp};
+        hex_dN(xi, dN);
+        return T(1);
+    } else {
+        // gradients of the barycentric coordinates
+        const T gl[4][3] = {{T(-1), T(-1), T(-1)}, {T(1), T(0), T(0)}, {T(0), T(1), T(0)}, {T(0), T(0), T(1)}};
+        if constexpr (S::N == 4) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) dN[a][k] = gl[a][k];
+            return T(1) / T(6);
+        } else {
+            const T qa = T(0.58541019662496845446), qb = T(0.13819660112501051518);
+            T l[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) l[a] = a == g ? qa : qb;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) dN[a][k] = (T(4) * l[a] - T(1)) * gl[a][k];
+            constexpr int ei[6] = {0, 1, 0, 0, 1, 2}, ej[6] = {1, 2, 2, 3, 3, 3};
+#pragma unroll
+            for (int t = 0; t < 6; ++t)
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    dN[4 + t][k] = T(4) * (l[ej[t]] * gl[ei[t]][k] + l[ei[t]] * gl[ej[t]][k]);
+            return T(1) / T(24);
+        }
+    }
+}
+
 // sum_a v_a (x) dN_a  (3x3, row r = component of v, column c = reference axis)
-template <typename T>
-__device__ __forceinline__ void gather_jac(const T v[8][3], const T dN[8][3], T* Jm) {
+template <int N, typename T>
+__device__ __forceinline__ void gather_jac(const T v[N][3], const T dN[N][3], T* Jm) {
 #pragma unroll
     for (int t = 0; t < 9; ++t) Jm[t] = T(0);
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+    for (int a = 0; a < N; ++a)
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll

@@ -67,6 +67,7 @@ def lib():
             "hipib_set_stream": (st, [P, P]),
             "hipib_last_error": (C.c_char_p, []),
             "hipib_set_mesh": (st, [P, i32, P, i32, P, P, P]),
+            "hipib_set_mesh_elements": (st, [P, i32, P, i32, i32, P, P, P]),
             "hipib_set_material": (st, [P, i32, i32, P, i32]),
             "hipib_set_pressure_faces": (st, [P, i32, P]),
             "hipib_set_sheets": (st, [P, i32, P]),
@@ -158,15 +159,19 @@ class Context:
 
     # -- set-up (host arrays) ---------------------------------------------
     def set_mesh(self, X_ref, conn, fibre, mat_id):
+        """conn [n_elems, 8] hexes, [n_elems, 4] P1 or [n_elems, 10] P2 tetrahedra."""
         X_ref = np.ascontiguousarray(X_ref, dtype=np.float64).reshape(-1, 3)
-        conn = np.ascontiguousarray(conn, dtype=np.int32).reshape(-1, 8)
+        conn = np.asarray(conn)
+        npe = int(conn.shape[1]) if conn.ndim == 2 else 8
+        conn = np.ascontiguousarray(conn, dtype=np.int32).reshape(-1, npe)
         fibre = np.ascontiguousarray(fibre, dtype=np.float64).reshape(-1, 3)
         mat_id = np.ascontiguousarray(mat_id, dtype=np.int32).reshape(-1)
         if fibre.shape[0] != conn.shape[0] or mat_id.shape[0] != conn.shape[0]:
             raise ValueError("fibre / mat_id must have one row per element")
-        _check(lib().hipib_set_mesh(self._h, X_ref.shape[0], X_ref.ctypes.data, conn.shape[0],
-                                    conn.ctypes.data, fibre.ctypes.data, mat_id.ctypes.data),
-               "hipib_set_mesh")
+        _check(lib().hipib_set_mesh_elements(self._h, X_ref.shape[0], X_ref.ctypes.data,
+                                             conn.shape[0], npe, conn.ctypes.data,
+                                             fibre.ctypes.data, mat_id.ctypes.data),
+               "hipib_set_mesh_elements")
         self.n_nodes = X_ref.shape[0]
 
     def set_material(self, mat_id: int, model: int, params):
