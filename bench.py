@@ -91,6 +91,15 @@ def larger_workload(torch, hipib, inputs, steps):
     return workload_leg(torch, hipib, inputs, "shell_leaflets_192", steps)
 
 
+def tet_workload(torch, hipib, inputs):
+    """P2 tetrahedra with the modified standard reinforcing law at the
+    benchmark's settings (64^3 grid, dt 1e-3, one face penalised): 6,000 tets,
+    9,261 nodes (27,783 solid DoFs), its 20-step run."""
+    out = workload_leg(torch, hipib, inputs, "tet10_block_64", 20)
+    out["elements"] = "P2 tetrahedra, 4-point rule"
+    return out
+
+
 def lv_workload(torch, hipib, inputs):
     """The 128^3 shell with the full Holzapfel-Ogden law (sheet and fibre-sheet
     terms), transmural sheets, the active-tension pulse and the base constraint
@@ -196,6 +205,7 @@ def main():
     ap.add_argument("--no-192", action="store_true", help="skip the 192^3 shell+leaflets leg")
     ap.add_argument("--steps-192", type=int, default=20)
     ap.add_argument("--no-lv", action="store_true", help="skip the 128^3 left-ventricle-law leg")
+    ap.add_argument("--no-tet", action="store_true", help="skip the 64^3 P2-tetrahedra leg")
     ap.add_argument("--roofline-steps", type=int, default=20,
                     help="steps of the separate pass that times the roofline kernel")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -292,6 +302,10 @@ def main():
     if not args.no_lv:
         lv = lv_workload(torch, hipib, inputs)
 
+    tet = None
+    if not args.no_tet:
+        tet = tet_workload(torch, hipib, inputs)
+
     avg_s = kernel_ms * 1e-3 / max(launches, 1)
     achieved = bytes_per_launch / avg_s / 1e9 if launches else 0.0
     roofline = {
@@ -329,6 +343,7 @@ def main():
         "adjoint_over_forward": adjoint,
         "shell_leaflets_192": larger,
         "lv_shell_128": lv,
+        "tet10_block_64": tet,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
