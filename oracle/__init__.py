@@ -39,7 +39,7 @@ class Fluid(C.Structure):
                 ("dt", C.c_double), ("mg_pre", C.c_int32), ("mg_post", C.c_int32),
                 ("mg_max_cycles", C.c_int32), ("mg_fixed_cycles", C.c_int32),
                 ("mg_coarse_sweeps", C.c_int32), ("mg_rtol", C.c_double),
-                ("convection", C.c_int32), ("mg_krylov", C.c_int32)]
+                ("convection", C.c_int32), ("mg_krylov", C.c_int32), ("walls", C.c_int32)]
 
 
 class Mesh(C.Structure):
@@ -103,6 +103,12 @@ def lib():
             "ibref_project": (C.c_int, [P, P]),
             "ibref_adjoint_step": (C.c_int, [P, P, P, P, P, f64, P, P, P]),
             "ibref_rollout_grad": (C.c_int, [P, P, P, P, f64, i32, f64, f64, P, P, P, P]),
+            "ibref_wall_extend": (None, [i32, i32, P, P]),
+            "ibref_wall_fold": (None, [i32, P, P]),
+            "ibref_wall_restrict": (None, [i32, i32, P, P]),
+            "ibref_walled_spread": (None, [i32, i32, P, P, P]),
+            "ibref_walled_interpolate": (None, [i32, i32, P, P, P]),
+            "ibref_walled_solve": (C.c_int, [P, f64, f64, i32, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -261,15 +267,15 @@ class MeshBuffers:
 
 
 def fluid(n, rho=1.0, mu=0.01, dt=1e-3, rtol=1e-10, pre=2, post=2, max_cycles=50,
-          fixed_cycles=0, coarse_sweeps=16, convection=1, krylov=1) -> Fluid:
+          fixed_cycles=0, coarse_sweeps=16, convection=1, krylov=1, walls=0) -> Fluid:
     return Fluid(n, rho, mu, dt, pre, post, max_cycles, fixed_cycles, coarse_sweeps, rtol,
-                 convection, krylov)
+                 convection, krylov, walls)
 
 
 def fluid_from_problem(prob, **over) -> Fluid:
     kw = dict(rho=prob.rho, mu=prob.mu, dt=prob.dt, rtol=prob.mg_rtol, pre=prob.mg_pre,
               post=prob.mg_post, max_cycles=prob.mg_max_cycles, convection=prob.convection,
-              krylov=prob.mg_krylov)
+              krylov=prob.mg_krylov, walls=prob.walls)
     kw.update(over)
     return fluid(prob.n, **kw)
 
@@ -412,3 +418,54 @@ def rollout_grad(fl: Fluid, mesh: MeshBuffers, u0, X0, t0, n_steps, p0, T, X_tar
                                     int(n_steps), float(p0), float(T), _p(Xt), C.byref(L), _p(dX),
                                     _p(dth)), "rollout_grad")
     return L.value, dX, dth
+
+
+# --------------------------------------------------------------------------
+# walled box (image construction)
+# --------------------------------------------------------------------------
+
+def wall_extend(box: np.ndarray, vector: bool) -> np.ndarray:
+    box = _f64(box)
+    n = box.shape[-1]
+    out = np.empty(((3,) if vector else ()) + (2 * n,) * 3)
+    lib().ibref_wall_extend(n, int(vector), _p(box), _p(out))
+    return out
+
+
+def wall_fold(img: np.ndarray) -> np.ndarray:
+    img = _f64(img)
+    n = img.shape[-1] // 2
+    out = np.empty((3, n, n, n))
+    lib().ibref_wall_fold(n, _p(img), _p(out))
+    return out
+
+
+def wall_restrict(img: np.ndarray, vector: bool) -> np.ndarray:
+    img = _f64(img)
+    n = img.shape[-1] // 2
+    out = np.empty(((3,) if vector else ()) + (n,) * 3)
+    lib().ibref_wall_restrict(n, int(vector), _p(img), _p(out))
+    return out
+
+
+def walled_spread(n: int, X, F, f0=None) -> np.ndarray:
+    X, F = _f64(X), _f64(F)
+    f = np.zeros((3, n, n, n)) if f0 is None else _f64(f0).copy()
+    lib().ibref_walled_spread(n, X.shape[0], _p(X), _p(F), _p(f))
+    return f
+
+
+def walled_interpolate(X, u) -> np.ndarray:
+    X, u = _f64(X), _f64(u)
+    U = np.empty_like(X)
+    lib().ibref_walled_interpolate(u.shape[-1], X.shape[0], _p(X), _p(u), _p(U))
+    return U
+
+
+def walled_solve(fl: Fluid, sigma: float, nu: float, poisson: bool, b, x0=None):
+    b = _f64(b)
+    x = np.zeros_like(b) if x0 is None else _f64(x0).copy()
+    cyc, rr = C.c_int32(0), C.c_double(0.0)
+    _check(lib().ibref_walled_solve(C.byref(fl), sigma, nu, int(poisson), _p(b), _p(x),
+                                    C.byref(cyc), C.byref(rr)), "walled_solve")
+    return x, cyc.value, rr.value

@@ -900,8 +900,219 @@ int ibref_mg_solve(const ibref_fluid* fl, double sigma, double nu, int32_t poiss
  * The Poisson equation is solved as (-Lap_h) p = -(rho/dt) D u*, with the
  * discrete mean of the right-hand side removed (periodic null space).
  */
+/* ------------------------------------------------------------------------- */
+/* walled box through its mirror image                                        */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * The boundary conditions u* = 0 and u^{n+1}.n = 0 on the box faces, with the
+ * MAC ghost-cell convention (tangential ghost = minus the interior value, the
+ * wall-normal component stored on the wall faces and held at zero), make the
+ * walled operators the restrictions of the periodic ones on the (2n)^3 grid
+ * of the box and its mirror images: pressure (Neumann) is mirrored evenly,
+ * every velocity component oddly.  On the image grid the spacing is the box's
+ * h; the routines below work on the unit-box image grid (spacing h/2), so
+ * every derivative carries its factor: Lap_h = Lap_{h/2} / 4, D_h, G_h and the
+ * convection C_h are half their h/2 versions, spreading at X/2 is 8 times the
+ * box's (delta_h scales as h^-3) and interpolation is unchanged.
+ *
+ * Index maps of the image grid (per axis, i' in 0..2n-1): a cell-centred
+ * axis maps i' >= n to 2n-1-i' (mirrored); the wall-normal axis of a velocity
+ * component is face-centred: faces 0 and n are the walls (value 0), i' > n
+ * maps to 2n-i' (mirrored).  A mirrored axis contributes a factor -1 for
+ * velocity (odd) and +1 for pressure (even).
+ */
+static int wall_map(int n, int ip, int face, int* src) {
+    if (face) {
+        if (ip == 0 || ip == n) return 0;        /* wall face */
+        if (ip < n) { *src = ip; return 1; }
+        *src = 2 * n - ip;
+        return -1;
+    }
+    if (ip < n) { *src = ip; return 1; }
+    *src = 2 * n - 1 - ip;
+    return -1;
+}
+
+void ibref_wall_extend(int32_t n, int32_t vector, const double* box, double* img) {
+    const int m = 2 * n;
+    const long M3 = (long)m * m * m, N3 = (long)n * n * n;
+    for (int d = 0; d < (vector ? 3 : 1); ++d)
+        for (int kp = 0; kp < m; ++kp)
+            for (int jp = 0; jp < m; ++jp)
+                for (int ip = 0; ip < m; ++ip) {
+                    int i = 0, j = 0, k = 0;
+                    int si = wall_map(n, ip, vector && d == 0, &i);
+                    int sj = wall_map(n, jp, vector && d == 1, &j);
+                    int sk = wall_map(n, kp, vector && d == 2, &k);
+                    double v = 0.0;
+                    if (si && sj && sk) {
+                        double sg = vector ? (double)(si * sj * sk) : 1.0;
+                        v = sg * box[d * N3 + i + (long)n * (j + (long)n * k)];
+                    }
+                    img[d * M3 + ip + (long)m * (jp + (long)m * kp)] = v;
+                }
+}
+
+void ibref_wall_fold(int32_t n, const double* img, double* box) {
+    const int m = 2 * n;
+    const long M3 = (long)m * m * m, N3 = (long)n * n * n;
+    for (long r = 0; r < 3 * N3; ++r) box[r] = 0.0;
+    for (int d = 0; d < 3; ++d)
+        for (int kp = 0; kp < m; ++kp)
+            for (int jp = 0; jp < m; ++jp)
+                for (int ip = 0; ip < m; ++ip) {
+                    int i = 0, j = 0, k = 0;
+                    int si = wall_map(n, ip, d == 0, &i);
+                    int sj = wall_map(n, jp, d == 1, &j);
+                    int sk = wall_map(n, kp, d == 2, &k);
+                    if (si && sj && sk)
+                        box[d * N3 + i + (long)n * (j + (long)n * k)] +=
+                            (double)(si * sj * sk) * img[d * M3 + ip + (long)m * (jp + (long)m * kp)];
+                }
+}
+
+void ibref_wall_restrict(int32_t n, int32_t vector, const double* img, double* box) {
+    const int m = 2 * n;
+    const long M3 = (long)m * m * m, N3 = (long)n * n * n;
+    for (int d = 0; d < (vector ? 3 : 1); ++d)
+        for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    int wall = vector && ((d == 0 && i == 0) || (d == 1 && j == 0) || (d == 2 && k == 0));
+                    box[d * N3 + i + (long)n * (j + (long)n * k)] =
+                        wall ? 0.0 : img[d * M3 + i + (long)m * (j + (long)m * k)];
+                }
+}
+
+void ibref_walled_spread(int32_t n, int32_t n_nodes, const double* X, const double* F, double* f) {
+    const long M3 = 8L * n * n * n, N3 = (long)n * n * n;
+    double* Xh = (double*)malloc(sizeof(double) * 3 * (size_t)(n_nodes > 0 ? n_nodes : 1));
+    double* fi = (double*)calloc(3 * (size_t)M3, sizeof(double));
+    double* fb = (double*)malloc(sizeof(double) * 3 * (size_t)N3);
+    for (long r = 0; r < 3L * n_nodes; ++r) Xh[r] = 0.5 * X[r];
+    ibref_spread(2 * n, n_nodes, Xh, F, fi);
+    ibref_wall_fold(n, fi, fb);
+    for (long r = 0; r < 3 * N3; ++r) f[r] += 0.125 * fb[r];
+    free(Xh); free(fi); free(fb);
+}
+
+void ibref_walled_interpolate(int32_t n, int32_t n_nodes, const double* X, const double* u, double* U) {
+    const long M3 = 8L * n * n * n;
+    double* Xh = (double*)malloc(sizeof(double) * 3 * (size_t)(n_nodes > 0 ? n_nodes : 1));
+    double* ui = (double*)malloc(sizeof(double) * 3 * (size_t)M3);
+    for (long r = 0; r < 3L * n_nodes; ++r) Xh[r] = 0.5 * X[r];
+    ibref_wall_extend(n, 1, u, ui);
+    ibref_interpolate(2 * n, n_nodes, Xh, ui, U);
+    free(Xh); free(ui);
+}
+
+/* the image grid's fluid: 2n cells on the unit box, the Helmholtz viscosity
+ * scaled by (h/2 / h)^2 */
+static ibref_fluid image_fluid(const ibref_fluid* fl) {
+    ibref_fluid f2 = *fl;
+    f2.n = 2 * fl->n;
+    f2.mu = 0.25 * fl->mu;
+    f2.walls = 0;
+    return f2;
+}
+
+int ibref_walled_solve(const ibref_fluid* fl, double sigma, double nu, int32_t poisson,
+                       const double* b, double* x, int32_t* cycles, double* relres) {
+    /* one cell-centred scalar field: mirrored evenly for Poisson (Neumann), oddly
+     * otherwise (Dirichlet with the ghost value minus the interior one); on the
+     * image grid the Helmholtz viscosity is nu/4 and the Poisson right-hand side
+     * is 4b for the unit-coefficient operator */
+    const int n = fl->n, m = 2 * n;
+    const long M3 = (long)m * m * m;
+    ibref_fluid f2 = image_fluid(fl);
+    double* bi = (double*)malloc(sizeof(double) * (size_t)M3);
+    double* xi = (double*)malloc(sizeof(double) * (size_t)M3);
+    for (int kp = 0; kp < m; ++kp)
+        for (int jp = 0; jp < m; ++jp)
+            for (int ip = 0; ip < m; ++ip) {
+                int i = 0, j = 0, k = 0;
+                int s = wall_map(n, ip, 0, &i) * wall_map(n, jp, 0, &j) * wall_map(n, kp, 0, &k);
+                long o = i + (long)n * (j + (long)n * k), oi = ip + (long)m * (jp + (long)m * kp);
+                double sg = poisson ? 1.0 : (double)s;
+                bi[oi] = sg * (poisson ? 4.0 : 1.0) * b[o];
+                xi[oi] = sg * x[o];
+            }
+    int rc = ibref_mg_solve(&f2, sigma, poisson ? 1.0 : 0.25 * nu, poisson, bi, xi, cycles, relres);
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) x[i + (long)n * (j + (long)n * k)] = xi[i + (long)m * (j + (long)m * k)];
+    free(bi); free(xi);
+    return rc;
+}
+
+/*
+ * One fluid step in the walled box (the periodic step's equations with the
+ * walls' boundary conditions), on the image grid:
+ *   g = (rho/dt) u - rho C_h(u) + f, restricted to the box (wall faces 0) and
+ *   mirrored back; Helmholtz on the image grid (viscosity mu/4 there) from the
+ *   mirrored u; u* restricted and mirrored; b = -(rho/dt) D_h u* on the box
+ *   (times 4 for the image grid's unit-coefficient Poisson operator), mirrored
+ *   evenly, mean removed; Poisson from the mirrored p; u = u* - (dt/rho) G_h p;
+ *   u and p restricted (the projection leaves the tangential velocity free at
+ *   the walls, as u^{n+1}.n = 0 asks).
+ */
+static int walled_ns_step(const ibref_fluid* fl, const double* f, double* u, double* p,
+                          ibref_step_stats* st) {
+    const int n = fl->n, m = 2 * n;
+    const long M3 = (long)m * m * m;
+    const double rho = fl->rho, dt = fl->dt;
+    ibref_fluid f2 = image_fluid(fl);
+    double* ui = (double*)malloc(sizeof(double) * 3 * (size_t)M3);
+    double* fi = (double*)malloc(sizeof(double) * 3 * (size_t)M3);
+    double* gi = (double*)malloc(sizeof(double) * 3 * (size_t)M3);
+    double* ci = (double*)calloc(3 * (size_t)M3, sizeof(double));
+    double* pi = (double*)malloc(sizeof(double) * (size_t)M3);
+    double* bi = (double*)malloc(sizeof(double) * (size_t)M3);
+    double* box = (double*)malloc(sizeof(double) * 3 * (size_t)fl->n * fl->n * fl->n);
+    int rc = IBREF_OK;
+    ibref_wall_extend(n, 1, u, ui);
+    ibref_wall_extend(n, 1, f, fi);
+    ibref_wall_extend(n, 0, p, pi);
+    if (fl->convection) ibref_convection(m, ui, ci);
+    for (long i = 0; i < 3 * M3; ++i) gi[i] = rho / dt * ui[i] - 0.5 * rho * ci[i] + fi[i];
+    ibref_wall_restrict(n, 1, gi, box);
+    ibref_wall_extend(n, 1, box, gi);
+    for (int d = 0; d < 3 && !rc; ++d) {
+        int32_t cyc = 0;
+        double rr = 0.0;
+        rc = ibref_mg_solve(&f2, rho / dt, f2.mu, 0, gi + d * M3, ui + d * M3, &cyc, &rr);
+        if (st) { st->cycles[d] = cyc; st->relres[d] = rr; }
+    }
+    if (!rc) {
+        ibref_wall_restrict(n, 1, ui, box);
+        ibref_wall_extend(n, 1, box, ui);
+        /* the box divergence (wall faces zero), mirrored evenly: the velocity
+         * images are odd in every component (no slip for u*), so the image
+         * divergence itself is not even across the walls */
+        ibref_divergence(m, ui, bi);
+        for (long i = 0; i < M3; ++i) bi[i] = -2.0 * (rho / dt) * bi[i];
+        ibref_wall_restrict(n, 0, bi, box);
+        ibref_wall_extend(n, 0, box, bi);
+        remove_mean(M3, bi);
+        int32_t cyc = 0;
+        double rr = 0.0;
+        rc = ibref_mg_solve(&f2, 0.0, 1.0, 1, bi, pi, &cyc, &rr);
+        if (st) { st->cycles[3] = cyc; st->relres[3] = rr; }
+    }
+    if (!rc) {
+        ibref_gradient(m, pi, gi);
+        for (long i = 0; i < 3 * M3; ++i) ui[i] = ui[i] - 0.5 * (dt / rho) * gi[i];
+        ibref_wall_restrict(n, 1, ui, u);
+        ibref_wall_restrict(n, 0, pi, p);
+    }
+    free(ui); free(fi); free(gi); free(ci); free(pi); free(bi); free(box);
+    return rc;
+}
+
 int ibref_ns_step(const ibref_fluid* fl, const double* f, double* u, double* p,
                   ibref_step_stats* st) {
+    if (fl->walls) return walled_ns_step(fl, f, u, p, st);
     const int n = fl->n;
     const long N3 = (long)n * n * n;
     const double rho = fl->rho, dt = fl->dt, mu = fl->mu;
@@ -954,11 +1165,13 @@ int ibref_ib_step(const ibref_fluid* fl, const ibref_mesh* m, double* u, double*
     int rc = ibref_fe_force(m, X, F, &E, &Jmin);
     if (!rc) {
         if (m->n_faces > 0 && pressure != 0.0) ibref_pressure_load(m->n_faces, m->faces, X, pressure, F);
-        ibref_spread(n, m->n_nodes, X, F, f);
+        if (fl->walls) ibref_walled_spread(n, m->n_nodes, X, F, f);
+        else ibref_spread(n, m->n_nodes, X, F, f);
         rc = ibref_ns_step(fl, f, u, p, st);
     }
     if (!rc) {
-        ibref_interpolate(n, m->n_nodes, X, u, U);
+        if (fl->walls) ibref_walled_interpolate(n, m->n_nodes, X, u, U);
+        else ibref_interpolate(n, m->n_nodes, X, u, U);
         for (long r = 0; r < 3L * m->n_nodes; ++r) X[r] = X[r] + fl->dt * U[r];
     }
     if (st) { st->min_J = Jmin; st->energy = E; }
@@ -1443,6 +1656,7 @@ int ibref_project(const ibref_fluid* fl, double* v) {
 int ibref_adjoint_step(const ibref_fluid* fl, const ibref_mesh* m, const double* u_n,
                        const double* X_n, const double* u_np1, double pressure, double* lam_u,
                        double* lam_X, double* dtheta) {
+    if (fl->walls) return IBREF_E_INVAL;   /* the adjoint covers the periodic box */
     const int n = fl->n;
     const long N3 = (long)n * n * n;
     const long nn3 = 3L * m->n_nodes;

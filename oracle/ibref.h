@@ -51,6 +51,8 @@ typedef struct {
     int32_t convection;        /* 1: explicit flux-form convection, 0: Stokes */
     int32_t mg_krylov;         /* 1: Poisson solves by conjugate gradients preconditioned
                                   with one V-cycle; 0: plain V-cycle iteration */
+    int32_t walls;             /* 0: periodic box; 1: walled box (u* = 0 and u.n = 0 on
+                                  every face), solved on its (2n)^3 mirror image */
 } ibref_fluid;
 
 typedef struct {
@@ -118,6 +120,23 @@ void ibref_pressure_load(int32_t n_faces, const int32_t* faces, const double* x,
 int ibref_mg_solve(const ibref_fluid* fl, double sigma, double nu, int32_t poisson,
                    const double* b, double* x /* guess -> solution */,
                    int32_t* cycles, double* relres);
+
+/* --- walled box: the image construction (n = cells per side of the box) ---
+ * A walled box is the (2n)^3 periodic box holding its mirror images: scalars
+ * (pressure) are even across every wall; velocity components are odd across
+ * every wall (the wall-normal face values vanish, the tangential ghost values
+ * are minus the interior ones: no slip).  ext: box -> image grid; fold: the
+ * transpose of ext; restrict: the box part of an image field, wall faces 0. */
+void ibref_wall_extend(int32_t n, int32_t vector, const double* box, double* img);
+void ibref_wall_fold(int32_t n, const double* img, double* box /* := */);
+void ibref_wall_restrict(int32_t n, int32_t vector, const double* img, double* box);
+/* f += S(X) F and U = J(X) u on the walled box, through the image grid */
+void ibref_walled_spread(int32_t n, int32_t n_nodes, const double* X, const double* F, double* f);
+void ibref_walled_interpolate(int32_t n, int32_t n_nodes, const double* X, const double* u, double* U);
+/* (sigma I - nu Lap_h) x = b for one cell-centred field on the walled box:
+ * Poisson (sigma = 0) with Neumann walls, else Dirichlet walls */
+int ibref_walled_solve(const ibref_fluid* fl, double sigma, double nu, int32_t poisson,
+                       const double* b, double* x, int32_t* cycles, double* relres);
 
 /* --- one fluid step (given the Eulerian force density f) and one IB step --- */
 int ibref_ns_step(const ibref_fluid* fl, const double* f, double* u, double* p,

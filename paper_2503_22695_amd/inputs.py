@@ -87,6 +87,7 @@ class Problem:
     mg_post: int = 2
     mg_max_cycles: int = 50
     mg_krylov: int = 1          # Poisson by V-cycle-preconditioned conjugate gradients
+    walls: int = 0              # 1: walled box (no slip, no penetration) instead of periodic
     convection: int = 1
     precision: str = "fp64"
 
@@ -477,6 +478,20 @@ def shell_base_tethers(X: np.ndarray, n_theta: int, n_psi: int, n_tau: int, kapp
 LV_BASE_KAPPA = 1.0   # nodal penalty stiffness of the base constraint
 
 
+def walled_shell(n: int = 64, n_theta: int = 224, n_psi: int = 80, n_tau: int = 6,
+                 n_steps: int = 50, dt: float = 5e-4) -> Problem:
+    """The Holzapfel-Ogden shell in a walled box (no slip, no penetration),
+    centred at c_x = 0.5 so that the apex keeps clear of the walls."""
+    h = 1.0 / n
+    X, conn, fibre, faces = shell_mesh(n_theta, n_psi, n_tau, h, cx=0.5)
+    ne = conn.shape[0]
+    return Problem(name=f"walled_shell_{n}", n=n, rho=1.0, mu=0.01, dt=dt, n_steps=n_steps,
+                   X_ref=X, X0=X.copy(), conn=conn.astype(np.int32),
+                   fibre=np.ascontiguousarray(fibre), mat_id=np.zeros(ne, dtype=np.int32),
+                   materials=[Material(HOLZAPFEL_OGDEN, HO_PARAMS)],
+                   faces=faces.astype(np.int32), p0=1.0, T=n_steps * dt, walls=1)
+
+
 def lv_shell(n: int = 128, n_theta: int = 224, n_psi: int = 80, n_tau: int = 6,
              n_steps: int = 100, dt: float = 5e-4) -> Problem:
     """The shell with the full Holzapfel-Ogden law (LV_PARAMS), transmural
@@ -564,6 +579,12 @@ def workload(name: str) -> Problem:
         return lv_shell()
     if name == "lv_block_32":        # full HO + active tension, 32^3, 20 steps
         return lv_block()
+    if name == "walled_block_32":    # walled box, NH block, 32^3, 10 steps
+        p = neo_hookean_block()
+        p.name, p.walls = "walled_block_32", 1
+        return p
+    if name == "walled_shell_64":    # walled box, HO shell, 64^3 (128^3 image grid), 50 steps
+        return walled_shell()
     if name == "tet10_block_64":     # P2 tets, Psi_1, tethered face: the benchmark's settings
         p = tet_block(2, n=64, n_el=10, n_steps=20)
         return p
@@ -571,4 +592,5 @@ def workload(name: str) -> Problem:
 
 
 WORKLOADS = ("nh_block_32", "ho_shell_128", "shell_leaflets_192",
-             "nh_block_32_mixed", "ho_block_64", "lv_shell_128", "lv_block_32", "tet10_block_64")
+             "nh_block_32_mixed", "ho_block_64", "lv_shell_128", "lv_block_32", "tet10_block_64",
+             "walled_block_32", "walled_shell_64")
