@@ -84,11 +84,23 @@ typedef struct {
                                  the abstract; one iteration counts as one cycle);
                                  0: plain V-cycle iteration.  Helmholtz solves always
                                  use the plain iteration. */
+    int32_t walls;            /* 0: periodic box.  1: walled box with the boundary
+                                 conditions u* = 0 and u^{n+1}.n = 0 on every face
+                                 ("Spatial Discretization"); the wall-normal velocity
+                                 of the faces at index 0 of its axis is zero (it
+                                 stands for both walls of that axis), tangential
+                                 ghosts are minus the interior values, pressure has
+                                 Neumann walls.  Solved on the (2n)^3 periodic grid of
+                                 the box and its mirror images (a second context the
+                                 library owns: 8 times the grid memory and work);
+                                 hipib_mg_solve takes each component as one
+                                 cell-centred field (Dirichlet, or Neumann for
+                                 Poisson).  The adjoint calls return HIPIB_E_STATE. */
 } hipib_config;
 
 /* Fills cfg with the defaults: V(2,2), 16 coarse sweeps, rtol 1e-10, 50 cycles,
- * convection on, FP64, atomic mode, Krylov Poisson solves; n/rho/mu/dt are set
- * to 32/1/0.01/1e-3. */
+ * convection on, FP64, atomic mode, Krylov Poisson solves, periodic box;
+ * n/rho/mu/dt are set to 32/1/0.01/1e-3. */
 void hipib_default_config(hipib_config* cfg);
 
 /* Creates a context for one grid on the current HIP device.  stream is a

@@ -100,6 +100,7 @@ void free_mesh(hipib_ctx* ctx) {
 }
 
 void free_all(hipib_ctx* ctx) {
+    walled_free(ctx);
     free_mesh(ctx);
     (void)hipFree(ctx->faces);
     for (int l = 0; l < kMaxLevels; ++l) {
@@ -154,6 +155,7 @@ hipib_status fluid_solves(hipib_ctx* ctx, double* u, double* p) {
 }
 
 hipib_status ib_step(hipib_ctx* ctx, double* u, double* p, double* X, double pressure) {
+    if (ctx->cfg.walls) return walled_ib_step(ctx, u, p, X, pressure);
     HIPIB_TRY(launch_bin(ctx, X));
     HIPIB_TRY(launch_fe_force(ctx, X, pressure, ctx->F));
     HIPIB_TRY(launch_rhs_build(ctx, u, nullptr, ctx->g));
@@ -186,6 +188,7 @@ void hipib_default_config(hipib_config* cfg) {
     cfg->precision = HIPIB_FP64;
     cfg->deterministic = 0;
     cfg->mg_krylov = 1;
+    cfg->walls = 0;
 }
 
 const char* hipib_last_error(void) { return g_err; }
@@ -214,6 +217,8 @@ hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out
         return fail(HIPIB_E_INVAL, "deterministic must be 0 or 1");
     if (cfg->mg_krylov != 0 && cfg->mg_krylov != 1)
         return fail(HIPIB_E_INVAL, "mg_krylov must be 0 or 1");
+    if (cfg->walls != 0 && cfg->walls != 1) return fail(HIPIB_E_INVAL, "walls must be 0 or 1");
+    if (cfg->walls && 2 * n > 1024) return fail(HIPIB_E_INVAL, "walled box: 2n = %d > 1024", 2 * n);
 
     hipib_ctx* ctx = new hipib_ctx();
     ctx->cfg = *cfg;
@@ -279,6 +284,7 @@ hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out
         else std::memset(ctx->st_host, 0, sizeof(MGState));
     }
     if (s == HIPIB_OK) s = mg_prepare(ctx);
+    if (s == HIPIB_OK && cfg->walls) s = walled_create(ctx);
     if (s == HIPIB_OK) {
         hipError_t e = hipMemsetAsync(ctx->st, 0, sizeof(MGState), ctx->stream);
         if (e == hipSuccess)
@@ -367,6 +373,13 @@ hipib_status hipib_set_mesh_elements(hipib_ctx* ctx, int32_t n_nodes, const doub
     ctx->ne = n_elems;
     ctx->npe = npe;
     ctx->mat_used = used;
+    if (ctx->cfg.walls) {
+        hipib_status sw = walled_set_nodes(ctx, X_ref);
+        if (sw != HIPIB_OK) {
+            free_mesh(ctx);
+            return sw;
+        }
+    }
     if (ctx->cfg.deterministic) {
         hipib_status sd = det_prepare_mesh(ctx, conn);
         if (sd == HIPIB_OK) sd = det_prepare_faces(ctx, nullptr, 0);
@@ -545,6 +558,7 @@ hipib_status hipib_spread(hipib_ctx* ctx, const double* X, const double* F, doub
     if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
     if (!aligned8(f) || (ctx->nn > 0 && (!aligned8(X) || !aligned8(F))))
         return fail(HIPIB_E_INVAL, "bad pointer");
+    if (ctx->cfg.walls) return walled_spread(ctx, X, F, f);
     HIPIB_TRY(launch_bin(ctx, X));
     return launch_spread(ctx, X, F, f);
 }
@@ -554,6 +568,7 @@ hipib_status hipib_interpolate(hipib_ctx* ctx, const double* X, const double* u,
     if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
     if (!aligned8(u) || (ctx->nn > 0 && (!aligned8(X) || !aligned8(U))))
         return fail(HIPIB_E_INVAL, "bad pointer");
+    if (ctx->cfg.walls) return walled_interpolate(ctx, X, u, U);
     HIPIB_TRY(launch_bin(ctx, X));
     return launch_interpolate(ctx, X, u, U, nullptr, 0.0);
 }
@@ -564,6 +579,7 @@ hipib_status hipib_mg_solve(hipib_ctx* ctx, int32_t op, int32_t ncomp, const dou
     if (op != HIPIB_OP_HELMHOLTZ && op != HIPIB_OP_POISSON) return fail(HIPIB_E_INVAL, "unknown op");
     if (ncomp < 1 || ncomp > 3) return fail(HIPIB_E_INVAL, "ncomp must be 1..3");
     if (!aligned8(b) || !aligned8(x)) return fail(HIPIB_E_INVAL, "bad pointer");
+    if (ctx->cfg.walls) return walled_solve(ctx, op, ncomp, b, x, cycles, relres);
     return mg_solve(ctx, op, ncomp, b, x, cycles, relres);
 }
 
@@ -571,6 +587,7 @@ hipib_status hipib_ns_step(hipib_ctx* ctx, const double* f, double* u, double* p
     HIPIB_TRY(check_ctx(ctx));
     if (!aligned8(u) || !aligned8(p) || (f && !aligned8(f))) return fail(HIPIB_E_INVAL, "bad pointer");
     ctx->recs.clear();
+    if (ctx->cfg.walls) return walled_ns_step(ctx, f, u, p);
     HIPIB_TRY(launch_rhs_build(ctx, u, f, ctx->g));
     return fluid_solves(ctx, u, p);
 }
@@ -618,6 +635,7 @@ hipib_status hipib_adjoint_step(hipib_ctx* ctx, const double* u_n, const double*
         (ctx->nn > 0 && (!aligned8(X_n) || !aligned8(lam_X))))
         return fail(HIPIB_E_INVAL, "bad pointer");
     if (!std::isfinite(pressure)) return fail(HIPIB_E_INVAL, "non-finite pressure");
+    if (ctx->cfg.walls) return fail(HIPIB_E_STATE, "the adjoint covers the periodic box only");
     return adjoint_step(ctx, u_n, X_n, u_np1, pressure, lam_u, lam_X, dtheta);
 }
 
@@ -644,6 +662,7 @@ hipib_status hipib_spread_vjp_X(hipib_ctx* ctx, const double* X, const double* F
     if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
     if (!aligned8(lam_f) || (ctx->nn > 0 && (!aligned8(X) || !aligned8(F) || !aligned8(lamX))))
         return fail(HIPIB_E_INVAL, "bad pointer");
+    if (ctx->cfg.walls) return fail(HIPIB_E_STATE, "the adjoint covers the periodic box only");
     const double h = ctx->h;
     return launch_vjp_X(ctx, X, lam_f, F, lamX, 1.0 / (h * h * h * h));
 }
@@ -654,12 +673,14 @@ hipib_status hipib_interp_vjp_X(hipib_ctx* ctx, const double* X, const double* u
     if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
     if (!aligned8(u) || (ctx->nn > 0 && (!aligned8(X) || !aligned8(lamU) || !aligned8(lamX))))
         return fail(HIPIB_E_INVAL, "bad pointer");
+    if (ctx->cfg.walls) return fail(HIPIB_E_STATE, "the adjoint covers the periodic box only");
     return launch_vjp_X(ctx, X, u, lamU, lamX, 1.0 / ctx->h);
 }
 
 hipib_status hipib_convection_vjp(hipib_ctx* ctx, const double* u, const double* lam, double* out) {
     HIPIB_TRY(check_ctx(ctx));
     if (!aligned8(u) || !aligned8(lam) || !aligned8(out)) return fail(HIPIB_E_INVAL, "bad pointer");
+    if (ctx->cfg.walls) return fail(HIPIB_E_STATE, "the adjoint covers the periodic box only");
     return launch_conv_vjp(ctx, u, lam, out, 0.0, 1.0);
 }
 

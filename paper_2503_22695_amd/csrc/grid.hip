@@ -107,29 +107,40 @@ dim3 plane_grid(int n) { return dim3((n + TX - 1) / TX, (n + TY - 1) / TY, n); }
 
 }  // namespace
 
-hipib_status launch_rhs_build(hipib_ctx* ctx, const double* u, const double* f, double* g) {
+hipib_status launch_rhs_build_coef(hipib_ctx* ctx, const double* u, const double* f, double* g,
+                                   double rho_dt, double rho_conv) {
     Grid3 G{ctx->n, ctx->n3};
-    const double rho = ctx->cfg.rho, dt = ctx->cfg.dt;
     k_rhs_build<<<plane_grid(ctx->n), dim3(TX, TY), 0, ctx->stream>>>(
-        u, f, g, G, rho / dt, rho, 1.0 / ctx->h, ctx->cfg.convection);
+        u, f, g, G, rho_dt, rho_conv, 1.0 / ctx->h, ctx->cfg.convection);
+    HIPIB_HIP(hipGetLastError());
+    return HIPIB_OK;
+}
+
+hipib_status launch_rhs_build(hipib_ctx* ctx, const double* u, const double* f, double* g) {
+    return launch_rhs_build_coef(ctx, u, f, g, ctx->cfg.rho / ctx->cfg.dt, ctx->cfg.rho);
+}
+
+hipib_status launch_divergence_rhs_coef(hipib_ctx* ctx, const double* u, double* b, double coef) {
+    Grid3 G{ctx->n, ctx->n3};
+    k_divergence_rhs<<<plane_grid(ctx->n), dim3(TX, TY), 0, ctx->stream>>>(u, b, G, coef,
+                                                                            1.0 / ctx->h);
     HIPIB_HIP(hipGetLastError());
     return HIPIB_OK;
 }
 
 hipib_status launch_divergence_rhs(hipib_ctx* ctx, const double* u, double* b) {
+    return launch_divergence_rhs_coef(ctx, u, b, ctx->cfg.rho / ctx->cfg.dt);
+}
+
+hipib_status launch_project_coef(hipib_ctx* ctx, double* u, const double* p, double coef) {
     Grid3 G{ctx->n, ctx->n3};
-    k_divergence_rhs<<<plane_grid(ctx->n), dim3(TX, TY), 0, ctx->stream>>>(
-        u, b, G, ctx->cfg.rho / ctx->cfg.dt, 1.0 / ctx->h);
+    k_project<<<plane_grid(ctx->n), dim3(TX, TY), 0, ctx->stream>>>(u, p, G, coef, 1.0 / ctx->h);
     HIPIB_HIP(hipGetLastError());
     return HIPIB_OK;
 }
 
 hipib_status launch_project(hipib_ctx* ctx, double* u, const double* p) {
-    Grid3 G{ctx->n, ctx->n3};
-    k_project<<<plane_grid(ctx->n), dim3(TX, TY), 0, ctx->stream>>>(
-        u, p, G, ctx->cfg.dt / ctx->cfg.rho, 1.0 / ctx->h);
-    HIPIB_HIP(hipGetLastError());
-    return HIPIB_OK;
+    return launch_project_coef(ctx, u, p, ctx->cfg.dt / ctx->cfg.rho);
 }
 
 hipib_status launch_zero(hipib_ctx* ctx, double* p, int64_t count) {

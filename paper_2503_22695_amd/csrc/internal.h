@@ -116,6 +116,18 @@ struct hipib_ctx {
     double* sheet = nullptr;  // [ne][3] sheet directions (hipib_set_sheets), else null
     double active_ta = 0.0;   // T_a of the active fibre stress (Holzapfel-Ogden materials)
     double ta_max = 0.0, ta_t_on = 0.0, ta_duration = 0.0;  // waveform followed by advance
+    // walled box (cfg.walls): the (2n)^3 periodic image context and its fields
+    hipib_ctx* img = nullptr;
+    double* w_u = nullptr;    // [3][M3] velocity image
+    double* w_f = nullptr;    // [3][M3] force image
+    double* w_g = nullptr;    // [3][M3] Helmholtz right-hand side image
+    double* w_p = nullptr;    // [M3] pressure image
+    double* w_b = nullptr;    // [M3] Poisson right-hand side image
+    double* w_box = nullptr;  // [3][n3] box scratch
+    double* w_fbox = nullptr; // [3][n3] folded force
+    double* w_Xh = nullptr;   // [nn][3] positions on the image grid's unit box (X / 2)
+    double* w_U = nullptr;    // [nn][3] interpolated velocity
+    int32_t w_nn = -1;        // node count the node buffers are sized for
     int32_t nt = 0;                  // penalty tethers (hipib_set_tethers)
     int32_t* tether_node = nullptr;  // [nt] distinct node indices
     double* tether_Y = nullptr;      // [nt][3] targets
@@ -179,6 +191,21 @@ hipib_status launch_rhs_build(hipib_ctx* ctx, const double* u, const double* f, 
 hipib_status launch_divergence_rhs(hipib_ctx* ctx, const double* u, double* b);
 hipib_status launch_project(hipib_ctx* ctx, double* u, const double* p);
 hipib_status launch_zero(hipib_ctx* ctx, double* p, int64_t count);
+// with explicit coefficients: g = rho_dt u - rho_conv C(u) + f; b = -coef D u; u -= coef G p
+hipib_status launch_rhs_build_coef(hipib_ctx* ctx, const double* u, const double* f, double* g,
+                                   double rho_dt, double rho_conv);
+hipib_status launch_divergence_rhs_coef(hipib_ctx* ctx, const double* u, double* b, double coef);
+hipib_status launch_project_coef(hipib_ctx* ctx, double* u, const double* p, double coef);
+// walls.hip (walled box through its mirror image)
+hipib_status walled_create(hipib_ctx* ctx);
+void walled_free(hipib_ctx* ctx);
+hipib_status walled_set_nodes(hipib_ctx* ctx, const double* X_ref_host);
+hipib_status walled_ns_step(hipib_ctx* ctx, const double* f, double* u, double* p);
+hipib_status walled_ib_step(hipib_ctx* ctx, double* u, double* p, double* X, double pressure);
+hipib_status walled_spread(hipib_ctx* ctx, const double* X, const double* F, double* f);
+hipib_status walled_interpolate(hipib_ctx* ctx, const double* X, const double* u, double* U);
+hipib_status walled_solve(hipib_ctx* ctx, int op, int ncomp, const double* b, double* x,
+                          int32_t* cycles, double* relres);
 // mg.hip
 hipib_status mg_solve(hipib_ctx* ctx, int op, int ncomp, const double* b, double* x,
                       int32_t* cycles, double* relres);

@@ -38,7 +38,7 @@ class Config(C.Structure):
                 ("mg_pre", C.c_int32), ("mg_post", C.c_int32), ("mg_max_cycles", C.c_int32),
                 ("mg_fixed_cycles", C.c_int32), ("mg_coarse_sweeps", C.c_int32),
                 ("mg_rtol", C.c_double), ("convection", C.c_int32), ("precision", C.c_int32),
-                ("deterministic", C.c_int32), ("mg_krylov", C.c_int32)]
+                ("deterministic", C.c_int32), ("mg_krylov", C.c_int32), ("walls", C.c_int32)]
 
 
 _lib = None
@@ -327,7 +327,7 @@ def config_for_problem(prob, **over) -> Config:
     kw = dict(n=prob.n, rho=prob.rho, mu=prob.mu, dt=prob.dt, mg_pre=prob.mg_pre,
               mg_post=prob.mg_post, mg_max_cycles=prob.mg_max_cycles, mg_rtol=prob.mg_rtol,
               convection=prob.convection, precision=MIXED if prob.precision == "mixed" else FP64,
-              mg_krylov=prob.mg_krylov)
+              mg_krylov=prob.mg_krylov, walls=prob.walls)
     kw.update(over)
     return default_config(**kw)
 

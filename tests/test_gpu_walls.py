@@ -1,0 +1,128 @@
+"""GPU parity for the walled box (u* = 0 and u^{n+1}.n = 0 on the faces,
+solved on the box's mirror image): spreading and interpolation (nodes near
+the walls included), the walled solves, one fluid step and whole IB runs,
+against the FP64 oracle (1e-11 relative; the same stop decisions)."""
+import numpy as np
+import pytest
+
+from paper_2503_22695_amd import inputs
+from tests.test_gpu_parity import TOL, assert_close, host, plain_ctx, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    return torch
+
+
+@pytest.fixture(scope="module")
+def hp():
+    from paper_2503_22695_amd import hipib
+    hipib.lib()
+    return hipib
+
+
+def wall_faces_zero(u):
+    for d in range(3):
+        w = [slice(None)] * 3
+        w[2 - d] = 0
+        u[d][tuple(w)] = 0.0
+    return u
+
+
+@pytest.mark.parametrize("n,nn", [(16, 300), (24, 500)])
+def test_walled_spread_interpolate(torch_dev, hp, ref, n, nn):
+    torch = torch_dev
+    say("walled spread/interp", n, nn)
+    rng = np.random.default_rng(n)
+    X = rng.uniform(0.01, 0.99, (nn, 3))
+    F = rng.standard_normal((nn, 3))
+    u = wall_faces_zero(rng.standard_normal((3, n, n, n)))
+    f0 = rng.standard_normal((3, n, n, n))
+    ctx = plain_ctx(hp, n, walls=1)
+    ctx.set_mesh(X, np.zeros((0, 8)), np.zeros((0, 3)), np.zeros(0))
+    fd = to_dev(torch, f0)
+    ctx.spread(to_dev(torch, X), to_dev(torch, F), fd)
+    U = ctx.interpolate(to_dev(torch, X), to_dev(torch, u))
+    torch.cuda.synchronize()
+    assert_close("f", host(fd), ref.walled_spread(n, X, F, f0))
+    assert_close("U", host(U), ref.walled_interpolate(X, u))
+
+
+@pytest.mark.parametrize("n", [16, 24])
+def test_walled_solves(torch_dev, hp, ref, n):
+    torch = torch_dev
+    say("walled solves", n)
+    rng = np.random.default_rng(30 + n)
+    rho, mu, dt = 1.0, 0.05, 1e-3
+    ctx = plain_ctx(hp, n, rho=rho, mu=mu, dt=dt, walls=1)
+    fl = ref.fluid(n, rho=rho, mu=mu, dt=dt, walls=1)
+    b = rng.standard_normal((n, n, n))
+    b -= b.mean()
+    x = torch.zeros((1, n, n, n), dtype=torch.float64, device="cuda")
+    cyc, rr = ctx.mg_solve(hp.OP_POISSON, to_dev(torch, b[None]), x)
+    xr, cr, _ = ref.walled_solve(fl, 0.0, 1.0, True, b)
+    assert int(cyc[0]) == cr
+    assert_close("p", host(x)[0], xr)
+    b3 = rng.standard_normal((3, n, n, n))
+    x3 = torch.zeros((3, n, n, n), dtype=torch.float64, device="cuda")
+    cyc, rr = ctx.mg_solve(hp.OP_HELMHOLTZ, to_dev(torch, b3), x3)
+    for c in range(3):
+        xr, cr, _ = ref.walled_solve(fl, rho / dt, mu, False, b3[c])
+        assert int(cyc[c]) == cr
+        assert_close(f"x{c}", host(x3)[c], xr)
+
+
+@pytest.mark.parametrize("convection", [1, 0])
+def test_walled_ns_step(torch_dev, hp, ref, convection):
+    torch = torch_dev
+    n = 24
+    say("walled ns_step", n, convection)
+    rng = np.random.default_rng(40 + convection)
+    u = wall_faces_zero(0.1 * rng.standard_normal((3, n, n, n)))
+    f = wall_faces_zero(rng.standard_normal((3, n, n, n)))
+    p = rng.standard_normal((n, n, n))
+    ctx = plain_ctx(hp, n, walls=1, convection=convection)
+    ud, pd = to_dev(torch, u), to_dev(torch, p)
+    ctx.ns_step(to_dev(torch, f), ud, pd)
+    torch.cuda.synchronize()
+    cyc, _ = ctx.step_stats()
+    ur, pr, st = ref.ns_step(ref.fluid(n, convection=convection, walls=1), f, u, p)
+    assert list(cyc[0]) == list(st.cycles)
+    assert_close("u", host(ud), ur)
+    assert_close("p", host(pd), pr)
+
+
+@pytest.mark.parametrize("name,steps,t0", [("walled_block_32", 10, 0.0), ("walled_shell_64", 3, 0.01)])
+def test_walled_advance(torch_dev, hp, ref, name, steps, t0):
+    torch = torch_dev
+    prob = inputs.workload(name)
+    say("walled advance", name, steps)
+    sim = hp.Simulation(prob)
+    sim.t = t0
+    sim.advance(steps)
+    torch.cuda.synchronize()
+    cyc, _ = sim.ctx.step_stats()
+    ur, pr, Xr, st = ref.run_problem(prob, n_steps=steps, t0=t0)
+    assert [list(c) for c in cyc] == [list(s.cycles) for s in st]
+    assert_close("u", host(sim.u), ur, TOL)
+    assert_close("p", host(sim.p), pr, TOL)
+    assert_close("X - X0", host(sim.X) - prob.X0, Xr - prob.X0, TOL)
+
+
+def test_walled_adjoint_refused(torch_dev, hp):
+    import torch
+    prob = inputs.workload("walled_block_32")
+    say("walled adjoint refused")
+    ctx = hp.context_for_problem(prob)
+    n = prob.n
+    z = torch.zeros((3, n, n, n), dtype=torch.float64, device="cuda")
+    X = to_dev(torch, prob.X0)
+    dth = torch.zeros((hp.MAX_MATERIALS, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(hp.HipIBError) as ei:
+        ctx.adjoint_step(z, X, z, 0.0, z.clone(), X.clone(), dth)
+    assert ei.value.status == 6
