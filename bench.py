@@ -100,6 +100,14 @@ def tet_workload(torch, hipib, inputs):
     return out
 
 
+def walled_workload(torch, hipib, inputs):
+    """The Holzapfel-Ogden shell in a walled 64^3 box (no slip, no penetration),
+    solved on its 128^3 mirror-image grid: its first 20 steps."""
+    out = workload_leg(torch, hipib, inputs, "walled_shell_64", 20)
+    out["boundary"] = "walled box, (2n)^3 mirror-image grid"
+    return out
+
+
 def lv_workload(torch, hipib, inputs):
     """The 128^3 shell with the full Holzapfel-Ogden law (sheet and fibre-sheet
     terms), transmural sheets, the active-tension pulse and the base constraint
@@ -206,6 +214,7 @@ def main():
     ap.add_argument("--steps-192", type=int, default=20)
     ap.add_argument("--no-lv", action="store_true", help="skip the 128^3 left-ventricle-law leg")
     ap.add_argument("--no-tet", action="store_true", help="skip the 64^3 P2-tetrahedra leg")
+    ap.add_argument("--no-walls", action="store_true", help="skip the walled 64^3 shell leg")
     ap.add_argument("--roofline-steps", type=int, default=20,
                     help="steps of the separate pass that times the roofline kernel")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -306,6 +315,10 @@ def main():
     if not args.no_tet:
         tet = tet_workload(torch, hipib, inputs)
 
+    walled = None
+    if not args.no_walls:
+        walled = walled_workload(torch, hipib, inputs)
+
     avg_s = kernel_ms * 1e-3 / max(launches, 1)
     achieved = bytes_per_launch / avg_s / 1e9 if launches else 0.0
     roofline = {
@@ -344,6 +357,7 @@ def main():
         "shell_leaflets_192": larger,
         "lv_shell_128": lv,
         "tet10_block_64": tet,
+        "walled_shell_64": walled,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
