@@ -201,6 +201,11 @@ def copy_calibration(torch, mib: int):
     del src, dst
 
 
+def progress(msg: str):
+    """One line per finished leg on stderr (stdout carries the JSON line only)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +278,7 @@ def main():
                                          "of the Poisson solve (packed layout, 12 B/cell)",
     })
     sim, elapsed, tim, cyc = run(hipib.FP64, True)
+    progress(f"FP64 {args.steps} steps in {elapsed:.3f} s and the roofline pass done")
     # the dominant kernel: the timed class with the most total time
     dom = max(tim, key=lambda k: tim[k][1])
     launches, kernel_ms, bytes_per_launch = tim[dom]
@@ -298,26 +304,32 @@ def main():
                                    "poisson": float(np.mean(mcyc[:, 3]))},
         }
         del msim
+        progress("mixed-precision leg done")
 
     adjoint = None
     if not args.no_adjoint:
         adjoint = adjoint_ratio(torch, hipib, inputs)
+        progress("adjoint leg done")
 
     larger = None
     if not args.no_192:
         larger = larger_workload(torch, hipib, inputs, args.steps_192)
+        progress("192^3 leg done")
 
     lv = None
     if not args.no_lv:
         lv = lv_workload(torch, hipib, inputs)
+        progress("left-ventricle-law leg done")
 
     tet = None
     if not args.no_tet:
         tet = tet_workload(torch, hipib, inputs)
+        progress("P2-tetrahedra leg done")
 
     walled = None
     if not args.no_walls:
         walled = walled_workload(torch, hipib, inputs)
+        progress("walled-box leg done")
 
     avg_s = kernel_ms * 1e-3 / max(launches, 1)
     achieved = bytes_per_launch / avg_s / 1e9 if launches else 0.0
