@@ -139,16 +139,24 @@ k_fe_hvp(const double* __restrict__ X, const double* __restrict__ Xref,
          double Ta, int ne, const double* __restrict__ V, double* __restrict__ out, MGState* st,
          double* __restrict__ contrib) {
     constexpr int N = S::N;
+    // 10-node elements re-read their node data at each point (from L1) instead of
+    // holding it in registers, which would spill; the arithmetic is the same
+    constexpr bool kHold = N <= 8;
+    constexpr int NH = kHold ? N : 1;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
     int nd[N];
     for (int a = 0; a < N; ++a) nd[a] = conn[N * (int64_t)e + a];
-    double xr[N][3], xc[N][3], vv[N][3], he[N][3];
+    double xr[NH][3], xc[NH][3], vv[NH][3], he[N][3];
+    const double r0[3] = {Xref[3 * nd[0]], Xref[3 * nd[0] + 1], Xref[3 * nd[0] + 2]};
+    const double c0[3] = {X[3 * nd[0]], X[3 * nd[0] + 1], X[3 * nd[0] + 2]};
     for (int a = 0; a < N; ++a)
         for (int r = 0; r < 3; ++r) {
-            xr[a][r] = Xref[3 * nd[a] + r] - Xref[3 * nd[0] + r];
-            xc[a][r] = X[3 * nd[a] + r] - X[3 * nd[0] + r];
-            vv[a][r] = V[3 * nd[a] + r];
+            if constexpr (kHold) {
+                xr[a][r] = Xref[3 * nd[a] + r] - r0[r];
+                xc[a][r] = X[3 * nd[a] + r] - c0[r];
+                vv[a][r] = V[3 * nd[a] + r];
+            }
             he[a][r] = 0.0;
         }
     const int m = mat_id[e];
@@ -168,9 +176,23 @@ k_fe_hvp(const double* __restrict__ X, const double* __restrict__ Xref,
         double dN[N][3];
         const double wq = elem_rule<S, double>(g, dN);
         double Jr[9], Jx[9], Jv[9];
-        gather_jac<N>(xr, dN, Jr);
-        gather_jac<N>(xc, dN, Jx);
-        gather_jac<N>(vv, dN, Jv);
+        if constexpr (kHold) {
+            gather_jac<N>(xr, dN, Jr);
+            gather_jac<N>(xc, dN, Jx);
+            gather_jac<N>(vv, dN, Jv);
+        } else {
+            for (int t = 0; t < 9; ++t) Jr[t] = Jx[t] = Jv[t] = 0.0;
+            for (int a = 0; a < N; ++a)
+                for (int r = 0; r < 3; ++r) {
+                    const double dr = Xref[3 * nd[a] + r] - r0[r], dx = X[3 * nd[a] + r] - c0[r];
+                    const double dv = V[3 * nd[a] + r];
+                    for (int c = 0; c < 3; ++c) {
+                        Jr[3 * r + c] += dr * dN[a][c];
+                        Jx[3 * r + c] += dx * dN[a][c];
+                        Jv[3 * r + c] += dv * dN[a][c];
+                    }
+                }
+        }
         const double w = det3(Jr);
         if (!(w > 0.0)) { bad = true; continue; }
         double cr[9], Jri[9];

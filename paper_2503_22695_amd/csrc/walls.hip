@@ -289,7 +289,7 @@ hipib_status walled_solve(hipib_ctx* ctx, int op, int ncomp, const double* b, do
     const int mode = poisson ? W_EVEN : W_ODD;
     HIPIB_TRY(extend(ctx, b, ctx->w_g, ncomp, mode));
     HIPIB_TRY(extend(ctx, x, ctx->w_u, ncomp, mode));
-    if (poisson) HIPIB_TRY(scale(ctx, ctx->w_g, ctx->w_g, 4.0, img->n3, false));
+    if (poisson) HIPIB_TRY(scale(ctx, ctx->w_g, ctx->w_g, 4.0, ncomp * img->n3, false));
     HIPIB_TRY(mg_solve(img, op, ncomp, ctx->w_g, ctx->w_u, cycles, relres));
     return restrict_box(ctx, ctx->w_u, x, ncomp, mode);
 }

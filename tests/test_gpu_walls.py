@@ -126,3 +126,29 @@ def test_walled_adjoint_refused(torch_dev, hp):
     with pytest.raises(hp.HipIBError) as ei:
         ctx.adjoint_step(z, X, z, 0.0, z.clone(), X.clone(), dth)
     assert ei.value.status == 6
+
+
+def test_walled_deterministic_bitwise_and_mixed_precision(torch_dev, hp, ref):
+    """The walled box in deterministic mode gives bitwise the same run twice (and
+    matches the oracle); in mixed precision it stays within the mixed bound of
+    the FP64 walled run."""
+    torch = torch_dev
+    prob = inputs.workload("walled_block_32")
+    say("walled deterministic / mixed")
+    runs = []
+    for _ in range(2):
+        sim = hp.Simulation(prob, deterministic=1)
+        sim.advance(prob.n_steps)
+        torch.cuda.synchronize()
+        runs.append(sim)
+    for f in ("u", "p", "X"):
+        assert torch.equal(getattr(runs[0], f), getattr(runs[1], f)), f
+    ur, pr, Xr, _ = ref.run_problem(prob)
+    assert_close("u", host(runs[0].u), ur, TOL)
+    assert_close("X - X0", host(runs[0].X) - prob.X0, Xr - prob.X0, TOL)
+    mixed = hp.Simulation(prob, precision=hp.MIXED)
+    mixed.advance(prob.n_steps)
+    torch.cuda.synchronize()
+    e_u = np.linalg.norm(host(mixed.u) - ur) / np.linalg.norm(ur)
+    e_X = np.max(np.abs(host(mixed.X) - Xr)) / np.max(np.abs(Xr - prob.X0))
+    assert e_u <= 1e-6 and e_X <= 1e-6, (e_u, e_X)
