@@ -106,6 +106,7 @@ def lib():
             "ibref_wall_extend": (None, [i32, i32, P, P]),
             "ibref_wall_fold": (None, [i32, P, P]),
             "ibref_wall_restrict": (None, [i32, i32, P, P]),
+            "ibref_wall_pad": (None, [i32, i32, P, P]),
             "ibref_walled_spread": (None, [i32, i32, P, P, P]),
             "ibref_walled_interpolate": (None, [i32, i32, P, P, P]),
             "ibref_walled_solve": (C.c_int, [P, f64, f64, i32, P, P, P, P]),
@@ -445,6 +446,15 @@ def wall_restrict(img: np.ndarray, vector: bool) -> np.ndarray:
     n = img.shape[-1] // 2
     out = np.empty(((3,) if vector else ()) + (n,) * 3)
     lib().ibref_wall_restrict(n, int(vector), _p(img), _p(out))
+    return out
+
+
+def wall_pad(box: np.ndarray, vector: bool) -> np.ndarray:
+    """The transpose of wall_restrict."""
+    box = _f64(box)
+    n = box.shape[-1]
+    out = np.empty(((3,) if vector else ()) + (2 * n,) * 3)
+    lib().ibref_wall_pad(n, int(vector), _p(box), _p(out))
     return out
 
 

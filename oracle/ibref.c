@@ -954,21 +954,44 @@ void ibref_wall_extend(int32_t n, int32_t vector, const double* box, double* img
                 }
 }
 
-void ibref_wall_fold(int32_t n, const double* img, double* box) {
+/* the transpose of ibref_wall_extend: each box value collects its images */
+static void wall_fold(int32_t n, int vector, const double* img, double* box) {
     const int m = 2 * n;
     const long M3 = (long)m * m * m, N3 = (long)n * n * n;
-    for (long r = 0; r < 3 * N3; ++r) box[r] = 0.0;
-    for (int d = 0; d < 3; ++d)
+    const int nc = vector ? 3 : 1;
+    for (long r = 0; r < nc * N3; ++r) box[r] = 0.0;
+    for (int d = 0; d < nc; ++d)
         for (int kp = 0; kp < m; ++kp)
             for (int jp = 0; jp < m; ++jp)
                 for (int ip = 0; ip < m; ++ip) {
                     int i = 0, j = 0, k = 0;
-                    int si = wall_map(n, ip, d == 0, &i);
-                    int sj = wall_map(n, jp, d == 1, &j);
-                    int sk = wall_map(n, kp, d == 2, &k);
-                    if (si && sj && sk)
+                    int si = wall_map(n, ip, vector && d == 0, &i);
+                    int sj = wall_map(n, jp, vector && d == 1, &j);
+                    int sk = wall_map(n, kp, vector && d == 2, &k);
+                    if (si && sj && sk) {
+                        double sg = vector ? (double)(si * sj * sk) : 1.0;
                         box[d * N3 + i + (long)n * (j + (long)n * k)] +=
-                            (double)(si * sj * sk) * img[d * M3 + ip + (long)m * (jp + (long)m * kp)];
+                            sg * img[d * M3 + ip + (long)m * (jp + (long)m * kp)];
+                    }
+                }
+}
+
+void ibref_wall_fold(int32_t n, const double* img, double* box) { wall_fold(n, 1, img, box); }
+
+/* the transpose of ibref_wall_restrict: the box values in the box part of the
+ * image grid (wall faces of velocity zero), zero elsewhere */
+void ibref_wall_pad(int32_t n, int32_t vector, const double* box, double* img) {
+    const int m = 2 * n;
+    const long M3 = (long)m * m * m, N3 = (long)n * n * n;
+    const int nc = vector ? 3 : 1;
+    for (long r = 0; r < nc * M3; ++r) img[r] = 0.0;
+    for (int d = 0; d < nc; ++d)
+        for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    int wall = vector && ((d == 0 && i == 0) || (d == 1 && j == 0) || (d == 2 && k == 0));
+                    img[d * M3 + i + (long)m * (j + (long)m * k)] =
+                        wall ? 0.0 : box[d * N3 + i + (long)n * (j + (long)n * k)];
                 }
 }
 
@@ -1653,10 +1676,116 @@ int ibref_project(const ibref_fluid* fl, double* v) {
     return rc;
 }
 
+/*
+ * Reverse of one walled IB step (the walled step of walled_ns_step and the
+ * image spreading / interpolation of ibref_ib_step), given lam_u = dL/du^{n+1}
+ * (box) and lam_X = dL/dX^{n+1}.  Every mirror map contributes its transpose
+ * (extend -> fold, restrict -> pad), the periodic operators theirs
+ * (G^T = -D, D^T = -G, the solves are symmetric, C'(u)^T from
+ * ibref_convection_vjp), spreading at X/2 the interpolation (S^T = J / h'^3)
+ * and positions the factor 1/2 of X/2.  The adjoint solves start from zero.
+ */
+static int walled_adjoint_step(const ibref_fluid* fl, const ibref_mesh* m, const double* u_n,
+                               const double* X_n, const double* u_np1, double pressure, double* lam_u,
+                               double* lam_X, double* dtheta) {
+    const int n = fl->n, m2 = 2 * n, nn = m->n_nodes;
+    const long M3 = (long)m2 * m2 * m2, N3 = (long)n * n * n, nn3 = 3L * nn;
+    const double hi = 1.0 / m2, hi3 = hi * hi * hi;
+    const double rho = fl->rho, dt = fl->dt;
+    const double a = rho / dt, b = 0.5 * rho, c = 0.5 * (dt / rho);
+    ibref_fluid f2 = image_fluid(fl);
+    const size_t nb = (size_t)(nn3 > 0 ? nn3 : 1);
+    double* Xh = (double*)malloc(sizeof(double) * nb);
+    double* sX = (double*)malloc(sizeof(double) * nb);
+    double* tmpX = (double*)malloc(sizeof(double) * nb);
+    double* lamXn = (double*)malloc(sizeof(double) * nb);
+    double* F = (double*)malloc(sizeof(double) * nb);
+    double* lamF = (double*)malloc(sizeof(double) * nb);
+    double* HV = (double*)malloc(sizeof(double) * nb);
+    double* vi = (double*)calloc(3 * (size_t)M3, sizeof(double));   /* image vector scratch */
+    double* wi = (double*)calloc(3 * (size_t)M3, sizeof(double));
+    double* zi = (double*)calloc(3 * (size_t)M3, sizeof(double));
+    double* si = (double*)calloc((size_t)M3, sizeof(double));       /* image scalar scratch */
+    double* ti = (double*)calloc((size_t)M3, sizeof(double));
+    double* vb = (double*)malloc(sizeof(double) * 3 * (size_t)N3);  /* box scratch */
+    int rc = IBREF_OK;
+    for (long r = 0; r < nn3; ++r) {
+        Xh[r] = 0.5 * X_n[r];
+        sX[r] = dt * lam_X[r];
+        lamXn[r] = lam_X[r];
+    }
+    /* X^{n+1} = X^n + dt J(X^n/2) E u^{n+1} */
+    ibref_spread(m2, nn, Xh, sX, vi);                 /* J^T = h'^3 S */
+    for (long i = 0; i < 3 * M3; ++i) vi[i] *= hi3;
+    wall_fold(n, 1, vi, vb);
+    for (long i = 0; i < 3 * N3; ++i) vb[i] += lam_u[i];           /* dL/du^{n+1}, box */
+    ibref_wall_extend(n, 1, u_np1, wi);
+    for (long r = 0; r < nn3; ++r) tmpX[r] = 0.0;
+    ibref_interp_vjp_X(m2, nn, Xh, wi, sX, tmpX);
+    for (long r = 0; r < nn3; ++r) lamXn[r] += 0.5 * tmpX[r];
+    /* u^{n+1} = R(us - c G p),  p = L^{-1} M E_s R_s (-2a D us) */
+    ibref_wall_pad(n, 1, vb, vi);                     /* lam of the image u^{n+1} */
+    ibref_divergence(m2, vi, si);                     /* lam_p = c D lam (G^T = -D) */
+    for (long i = 0; i < M3; ++i) si[i] *= c;
+    remove_mean(M3, si);
+    {
+        int32_t cyc;
+        double rr;
+        rc = ibref_mg_solve(&f2, 0.0, 1.0, 1, si, ti, &cyc, &rr);   /* lam_b = L^{-1} lam_p */
+        remove_mean(M3, ti);   /* the transpose of the mean removal before the solve */
+    }
+    if (!rc) {
+        wall_fold(n, 0, ti, vb);                      /* D^T R_s^T E_s^T (x -2a): + 2a G */
+        ibref_wall_pad(n, 0, vb, si);
+        ibref_gradient(m2, si, wi);
+        for (long i = 0; i < 3 * M3; ++i) vi[i] += 2.0 * a * wi[i];   /* lam_us */
+        wall_fold(n, 1, vi, vb);                      /* us = E R u* */
+        ibref_wall_pad(n, 1, vb, wi);
+        for (int d = 0; d < 3 && !rc; ++d) {          /* u* = H^{-1} g_s */
+            int32_t cyc;
+            double rr;
+            rc = ibref_mg_solve(&f2, a, f2.mu, 0, wi + d * M3, zi + d * M3, &cyc, &rr);
+        }
+    }
+    if (!rc) {
+        wall_fold(n, 1, zi, vb);                      /* g_s = E R g */
+        ibref_wall_pad(n, 1, vb, vi);                 /* lam_g (image) */
+        /* g = a E u - b C(E u) + E f */
+        ibref_wall_extend(n, 1, u_n, wi);
+        for (long i = 0; i < 3 * M3; ++i) zi[i] = 0.0;
+        if (fl->convection) ibref_convection_vjp(m2, wi, vi, zi);
+        for (long i = 0; i < 3 * M3; ++i) wi[i] = a * vi[i] - b * zi[i];
+        wall_fold(n, 1, wi, lam_u);                   /* dL/du^n */
+        wall_fold(n, 1, vi, vb);                      /* dL/df (box) */
+        ibref_wall_extend(n, 1, vb, wi);              /* E dL/df */
+        /* f = (1/8) E^T S(X/2) F */
+        ibref_interpolate(m2, nn, Xh, wi, lamF);
+        for (long r = 0; r < nn3; ++r) lamF[r] *= 0.125 / hi3;
+        rc = ibref_fe_force(m, X_n, F, NULL, NULL);
+    }
+    if (!rc) {
+        if (m->n_faces > 0 && pressure != 0.0) ibref_pressure_load(m->n_faces, m->faces, X_n, pressure, F);
+        for (long r = 0; r < nn3; ++r) tmpX[r] = 0.0;
+        ibref_spread_vjp_X(m2, nn, Xh, F, wi, tmpX);
+        for (long r = 0; r < nn3; ++r) lamXn[r] += 0.0625 * tmpX[r];
+        rc = ibref_fe_hvp(m, X_n, lamF, HV);
+    }
+    if (!rc) {
+        for (long r = 0; r < nn3; ++r) lamXn[r] += HV[r];
+        if (m->n_faces > 0 && pressure != 0.0)
+            ibref_pressure_vjp(m->n_faces, m->faces, X_n, pressure, lamF, lamXn);
+        if (dtheta) rc = ibref_fe_param_vjp(m, X_n, lamF, dtheta);
+        for (long r = 0; r < nn3; ++r) lam_X[r] = lamXn[r];
+    }
+    free(Xh); free(sX); free(tmpX); free(lamXn); free(F); free(lamF); free(HV);
+    free(vi); free(wi); free(zi); free(si); free(ti); free(vb);
+    return rc;
+}
+
 int ibref_adjoint_step(const ibref_fluid* fl, const ibref_mesh* m, const double* u_n,
                        const double* X_n, const double* u_np1, double pressure, double* lam_u,
                        double* lam_X, double* dtheta) {
-    if (fl->walls) return IBREF_E_INVAL;   /* the adjoint covers the periodic box */
+    if (fl->walls) return walled_adjoint_step(fl, m, u_n, X_n, u_np1, pressure, lam_u, lam_X, dtheta);
     const int n = fl->n;
     const long N3 = (long)n * n * n;
     const long nn3 = 3L * m->n_nodes;

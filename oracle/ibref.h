@@ -130,6 +130,7 @@ int ibref_mg_solve(const ibref_fluid* fl, double sigma, double nu, int32_t poiss
 void ibref_wall_extend(int32_t n, int32_t vector, const double* box, double* img);
 void ibref_wall_fold(int32_t n, const double* img, double* box /* := */);
 void ibref_wall_restrict(int32_t n, int32_t vector, const double* img, double* box);
+void ibref_wall_pad(int32_t n, int32_t vector, const double* box, double* img); /* restrict^T */
 /* f += S(X) F and U = J(X) u on the walled box, through the image grid */
 void ibref_walled_spread(int32_t n, int32_t n_nodes, const double* X, const double* F, double* f);
 void ibref_walled_interpolate(int32_t n, int32_t n_nodes, const double* X, const double* u, double* U);

@@ -196,3 +196,86 @@ def test_walled_ib_run_keeps_the_walls(ref):
     assert np.max(np.abs(div_walled(u, h))) <= 1e-7 * np.max(np.abs(u)) / h
     assert np.all((X > 0) & (X < 1))
     assert all(s.cycles[3] > 0 for s in st)
+
+
+def test_pad_is_the_transpose_of_restrict(ref):
+    n = 6
+    rng = np.random.default_rng(11)
+    for vector in (True, False):
+        shp = ((3,) if vector else ()) + (2 * n,) * 3
+        img = rng.standard_normal(shp)
+        box = rng.standard_normal(shp[:-3] + (n,) * 3)
+        lhs = np.sum(ref.wall_restrict(img, vector) * box)
+        rhs = np.sum(img * ref.wall_pad(box, vector))
+        assert abs(lhs - rhs) <= 1e-12 * np.sum(np.abs(img)), vector
+
+
+def walled_step_problem(ref, n=12, convection=1):
+    prob = inputs.ho_block(n=n, n_el=3, n_steps=4)
+    prob.walls = 1
+    fl = ref.fluid_from_problem(prob, rtol=1e-14, convection=convection)
+    mesh = ref.MeshBuffers.from_problem(prob)
+    rng = np.random.default_rng(8)
+    u0 = wall_faces_zero(0.05 * rng.standard_normal((3, n, n, n)))
+    return prob, fl, mesh, u0
+
+
+@pytest.mark.parametrize("convection", [1, 0])
+def test_walled_adjoint_step_against_central_difference(ref, convection):
+    """The reverse of one walled IB step against central differences of the
+    forward step, along a random velocity direction (wall faces included: the
+    step ignores them, so their adjoint is zero) and a random node direction."""
+    prob, fl, mesh, u0 = walled_step_problem(ref, convection=convection)
+    n = prob.n
+    rng = np.random.default_rng(9)
+    X0 = prob.X0
+
+    def fwd(u, X):
+        uu, _, XX, _ = ref.advance(fl, mesh, u, np.zeros((n, n, n)), X, 0.0, 1)
+        return uu, XX
+    u1, X1 = fwd(u0, X0)
+    lam_u1 = rng.standard_normal(u1.shape)
+    lam_X1 = rng.standard_normal(X1.shape)
+    lu0, lX0, _ = ref.adjoint_step(fl, mesh, u0, X0, u1, 0.0, lam_u1, lam_X1)
+    assert np.array_equal(wall_faces_zero(lu0.copy()), lu0)
+    du = rng.standard_normal(u0.shape)
+    dX = rng.standard_normal(X0.shape)
+    for (a, b, pred) in [(du, 0 * dX, np.sum(lu0 * du)), (0 * du, dX, np.sum(lX0 * dX))]:
+        e = 1e-6
+        up, Xp = fwd(u0 + e * a, X0 + e * b)
+        um, Xm = fwd(u0 - e * a, X0 - e * b)
+        fd = (np.sum((up - um) * lam_u1) + np.sum((Xp - Xm) * lam_X1)) / (2 * e)
+        assert abs(pred - fd) <= 2e-6 * max(abs(fd), 1e-12), (pred, fd)
+
+
+def test_walled_rollout_gradient_against_central_difference(ref):
+    """Gradient of L = sum |X^N - X_target|^2 over 3 walled steps with respect
+    to X0 (two directions, second-order remainder) and the first parameter."""
+    prob, fl, mesh, u0 = walled_step_problem(ref)
+    n_steps = 3
+    Xt = prob.X0 + 0.01 * prob.h
+    L, dX0, dth = ref.rollout_grad(fl, mesh, u0, prob.X0, 0.0, n_steps, 0.0, 1.0, Xt)
+    par0 = list(prob.materials[0].params)
+
+    def loss(par, X0):
+        m = ref.MeshBuffers(prob.X_ref, prob.conn, prob.fibre, prob.mat_id,
+                            [prob.materials[0].model], [par])
+        _, _, XN, _ = ref.advance(fl, m, u0, np.zeros((prob.n,) * 3), X0, 0.0, n_steps)
+        return float(np.sum((XN - Xt) ** 2))
+    assert abs(L - loss(par0, prob.X0)) <= 1e-14 * abs(L) + 1e-300
+    par = np.array(par0)
+    e = 1e-3 * par[0]
+    pp, pm = par.copy(), par.copy()
+    pp[0] += e
+    pm[0] -= e
+    fd = (loss(pp, prob.X0) - loss(pm, prob.X0)) / (2 * e)
+    assert abs(dth[0, 0] - fd) <= 2e-6 * abs(fd), (dth[0, 0], fd)
+    rng = np.random.default_rng(10)
+    d = rng.standard_normal(prob.X0.shape)
+    g = np.sum(dX0 * d)
+    errs = []
+    for e in (1e-4, 1e-5, 1e-6):
+        fd = (loss(par0, prob.X0 + e * d) - loss(par0, prob.X0 - e * d)) / (2 * e)
+        errs.append(abs(g - fd))
+    assert errs[2] <= 1e-8 * abs(g)
+    assert 30 < errs[0] / errs[1] < 300
