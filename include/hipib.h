@@ -95,7 +95,10 @@ typedef struct {
                                  library owns: 8 times the grid memory and work);
                                  hipib_mg_solve takes each component as one
                                  cell-centred field (Dirichlet, or Neumann for
-                                 Poisson).  The adjoint calls return HIPIB_E_STATE. */
+                                 Poisson).  hipib_adjoint_step reverses the walled
+                                 step; the derivatives of single periodic operators
+                                 (hipib_spread_vjp_X, hipib_interp_vjp_X,
+                                 hipib_convection_vjp) return HIPIB_E_STATE. */
 } hipib_config;
 
 /* Fills cfg with the defaults: V(2,2), 16 coarse sweeps, rtol 1e-10, 50 cycles,
@@ -236,7 +239,11 @@ int32_t hipib_get_step_stats(hipib_ctx* ctx, int32_t* cycles, double* relres,
  * lam_X in: dL/dX^{n+1}, out: dL/dX^n.  The adjoint Poisson and Helmholtz
  * solves start from the previous call's solutions (zero on a context's first
  * call), as the forward solves start from the previous step's; results depend
- * on that start only within the multigrid tolerance.  Waits for completion. */
+ * on that start only within the multigrid tolerance.  On a walled box
+ * (config walls = 1) the step is reversed on the mirror-image grid, each mirror
+ * map by its transpose (extension by the fold onto the box, restriction by
+ * zero padding), with the adjoint solves starting from zero.  Waits for
+ * completion. */
 hipib_status hipib_adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n,
                                 const double* u_np1, double pressure, double* lam_u,
                                 double* lam_X, double* dtheta);

@@ -473,7 +473,6 @@ hipib_status param_vjp_elements(hipib_ctx* ctx, const double* X, const double* l
 hipib_status adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n, const double* u_np1,
                           double pressure, double* lam_u, double* lam_X, double* dtheta) {
     HIPIB_TRY(ensure_adjoint_scratch(ctx));
-    const bool det = ctx->cfg.deterministic != 0;
     const double h = ctx->h, h3 = h * h * h, rho = ctx->cfg.rho, dt = ctx->cfg.dt;
     const int64_t nn3 = 3 * (int64_t)ctx->nn, g3 = 3 * ctx->n3;
     HIPIB_TRY(launch_bin(ctx, X_n));
@@ -504,24 +503,34 @@ hipib_status adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n, 
         HIPIB_TRY(axpby(ctx, ctx->adj_lamF, ctx->adj_lamF, 1.0 / h3, 0.0, nn3));   // lam_F = J lam_g / h^3
         HIPIB_TRY(launch_fe_force(ctx, X_n, pressure, ctx->F));                    // forward force
         HIPIB_TRY(vjp_X(ctx, X_n, ctx->adj_lg, ctx->F, lam_X, 1.0 / (h * h3)));    // spreading term
-        if (ctx->ne > 0) {
-            HIPIB_TRY(hvp_elements(ctx, X_n, ctx->adj_lamF, lam_X, det ? ctx->det_contrib : nullptr));
-            if (det) HIPIB_TRY(det_gather_nodes(ctx, false, true, lam_X));
-            HIPIB_TRY(param_vjp_elements(ctx, X_n, ctx->adj_lamF, dtheta, det ? ctx->det_param : nullptr));
-            if (det) HIPIB_TRY(det_param_reduce(ctx, dtheta));
-        }
-        HIPIB_TRY(launch_tethers(ctx, X_n, ctx->adj_lamF, lam_X));   // K symmetric: K^T lamF = K lamF
-        if (ctx->nf > 0 && pressure != 0.0) {
-            k_pressure_vjp<<<(ctx->nf + 255) / 256, 256, 0, ctx->stream>>>(
-                X_n, ctx->faces, ctx->nf, pressure, ctx->adj_lamF, lam_X,
-                det ? ctx->det_face_contrib : nullptr);
-            HIPIB_HIP(hipGetLastError());
-            if (det) HIPIB_TRY(det_gather_nodes(ctx, true, true, lam_X));
-        }
+        HIPIB_TRY(adjoint_forces(ctx, X_n, pressure, ctx->adj_lamF, lam_X, dtheta));
     }
     HIPIB_TRY(sync_state(ctx));
     if (ctx->st_host->numeric)
         return fail(HIPIB_E_NUMERIC, "non-positive Jacobian at a Gauss point (inverted element)");
+    return HIPIB_OK;
+}
+
+hipib_status adjoint_scratch(hipib_ctx* ctx) { return ensure_adjoint_scratch(ctx); }
+
+// lam_X += (dF/dX)^T lamF, dtheta += (dF/dtheta)^T lamF for the nodal force F
+// of the elements, the tethers and the pressure load
+hipib_status adjoint_forces(hipib_ctx* ctx, const double* X_n, double pressure, const double* lamF,
+                            double* lam_X, double* dtheta) {
+    const bool det = ctx->cfg.deterministic != 0;
+    if (ctx->ne > 0) {
+        HIPIB_TRY(hvp_elements(ctx, X_n, lamF, lam_X, det ? ctx->det_contrib : nullptr));
+        if (det) HIPIB_TRY(det_gather_nodes(ctx, false, true, lam_X));
+        HIPIB_TRY(param_vjp_elements(ctx, X_n, lamF, dtheta, det ? ctx->det_param : nullptr));
+        if (det) HIPIB_TRY(det_param_reduce(ctx, dtheta));
+    }
+    HIPIB_TRY(launch_tethers(ctx, X_n, lamF, lam_X));   // K symmetric: K^T lamF = K lamF
+    if (ctx->nf > 0 && pressure != 0.0) {
+        k_pressure_vjp<<<(ctx->nf + 255) / 256, 256, 0, ctx->stream>>>(
+            X_n, ctx->faces, ctx->nf, pressure, lamF, lam_X, det ? ctx->det_face_contrib : nullptr);
+        HIPIB_HIP(hipGetLastError());
+        if (det) HIPIB_TRY(det_gather_nodes(ctx, true, true, lam_X));
+    }
     return HIPIB_OK;
 }
 

@@ -635,7 +635,7 @@ hipib_status hipib_adjoint_step(hipib_ctx* ctx, const double* u_n, const double*
         (ctx->nn > 0 && (!aligned8(X_n) || !aligned8(lam_X))))
         return fail(HIPIB_E_INVAL, "bad pointer");
     if (!std::isfinite(pressure)) return fail(HIPIB_E_INVAL, "non-finite pressure");
-    if (ctx->cfg.walls) return fail(HIPIB_E_STATE, "the adjoint covers the periodic box only");
+    if (ctx->cfg.walls) return walled_adjoint_step(ctx, u_n, X_n, u_np1, pressure, lam_u, lam_X, dtheta);
     return adjoint_step(ctx, u_n, X_n, u_np1, pressure, lam_u, lam_X, dtheta);
 }
 
@@ -662,7 +662,7 @@ hipib_status hipib_spread_vjp_X(hipib_ctx* ctx, const double* X, const double* F
     if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
     if (!aligned8(lam_f) || (ctx->nn > 0 && (!aligned8(X) || !aligned8(F) || !aligned8(lamX))))
         return fail(HIPIB_E_INVAL, "bad pointer");
-    if (ctx->cfg.walls) return fail(HIPIB_E_STATE, "the adjoint covers the periodic box only");
+    if (ctx->cfg.walls) return fail(HIPIB_E_STATE, "the periodic operators' derivatives: not defined on a walled box");
     const double h = ctx->h;
     return launch_vjp_X(ctx, X, lam_f, F, lamX, 1.0 / (h * h * h * h));
 }
@@ -673,14 +673,14 @@ hipib_status hipib_interp_vjp_X(hipib_ctx* ctx, const double* X, const double* u
     if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
     if (!aligned8(u) || (ctx->nn > 0 && (!aligned8(X) || !aligned8(lamU) || !aligned8(lamX))))
         return fail(HIPIB_E_INVAL, "bad pointer");
-    if (ctx->cfg.walls) return fail(HIPIB_E_STATE, "the adjoint covers the periodic box only");
+    if (ctx->cfg.walls) return fail(HIPIB_E_STATE, "the periodic operators' derivatives: not defined on a walled box");
     return launch_vjp_X(ctx, X, u, lamU, lamX, 1.0 / ctx->h);
 }
 
 hipib_status hipib_convection_vjp(hipib_ctx* ctx, const double* u, const double* lam, double* out) {
     HIPIB_TRY(check_ctx(ctx));
     if (!aligned8(u) || !aligned8(lam) || !aligned8(out)) return fail(HIPIB_E_INVAL, "bad pointer");
-    if (ctx->cfg.walls) return fail(HIPIB_E_STATE, "the adjoint covers the periodic box only");
+    if (ctx->cfg.walls) return fail(HIPIB_E_STATE, "the periodic operators' derivatives: not defined on a walled box");
     return launch_conv_vjp(ctx, u, lam, out, 0.0, 1.0);
 }
 

@@ -206,6 +206,9 @@ hipib_status walled_spread(hipib_ctx* ctx, const double* X, const double* F, dou
 hipib_status walled_interpolate(hipib_ctx* ctx, const double* X, const double* u, double* U);
 hipib_status walled_solve(hipib_ctx* ctx, int op, int ncomp, const double* b, double* x,
                           int32_t* cycles, double* relres);
+hipib_status walled_adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n,
+                                 const double* u_np1, double pressure, double* lam_u, double* lam_X,
+                                 double* dtheta);
 // mg.hip
 hipib_status mg_solve(hipib_ctx* ctx, int op, int ncomp, const double* b, double* x,
                       int32_t* cycles, double* relres);
@@ -237,6 +240,9 @@ hipib_status adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n, 
                           double pressure, double* lam_u, double* lam_X, double* dtheta);
 hipib_status launch_conv_vjp(hipib_ctx* ctx, const double* u, const double* lam, double* out,
                              double a, double b);
+hipib_status adjoint_scratch(hipib_ctx* ctx);
+hipib_status adjoint_forces(hipib_ctx* ctx, const double* X_n, double pressure, const double* lamF,
+                            double* lam_X, double* dtheta);
 hipib_status launch_fe_hvp(hipib_ctx* ctx, const double* X, const double* V, double* out);
 hipib_status launch_fe_param_vjp(hipib_ctx* ctx, const double* X, const double* lamF, double* dtheta);
 hipib_status launch_vjp_X(hipib_ctx* ctx, const double* X, const double* field, const double* coef,

@@ -79,14 +79,17 @@ k_wall_restrict(const double* __restrict__ img, double* __restrict__ box, int n,
     box[t] = wall ? 0.0 : img[d * M3 + i + (int64_t)m * (j + (int64_t)m * k)];
 }
 
-// box[d] += scale * sum over the image cells mapping to it of sign * img (the
-// transpose of k_wall_extend for velocity), summed in image-index order
+// box[d] += scale * sum over the image cells mapping to it of sign * img, d <
+// ncomp, summed in image-index order: the transpose of k_wall_extend for
+// velocity (mode W_VELOCITY) or an even cell-centred scalar (W_EVEN)
 __global__ void __launch_bounds__(WT)
-k_wall_fold(const double* __restrict__ img, double* __restrict__ box, int n, double scale) {
+k_wall_fold(const double* __restrict__ img, double* __restrict__ box, int n, int ncomp, int mode,
+            double scale) {
+    const bool vector = mode == W_VELOCITY;
     const int m = 2 * n;
     const int64_t M3 = (int64_t)m * m * m, N3 = (int64_t)n * n * n;
     const int64_t t = (int64_t)blockIdx.x * WT + threadIdx.x;
-    if (t >= 3 * N3) return;
+    if (t >= ncomp * N3) return;
     const int d = (int)(t / N3);
     const int64_t r = t - d * N3;
     const int ijk[3] = {(int)(r % n), (int)((r / n) % n), (int)(r / ((int64_t)n * n))};
@@ -94,14 +97,15 @@ k_wall_fold(const double* __restrict__ img, double* __restrict__ box, int n, dou
     int pre[3][2], sg[3][2], cnt[3];
     for (int a = 0; a < 3; ++a) {
         const int x = ijk[a];
-        if (a == d) {   // face-centred: faces 1..n-1 come from x and 2n-x; face 0 is a wall
+        const int mirror = vector ? -1 : 1;
+        if (vector && a == d) {   // face-centred: faces 1..n-1 come from x and 2n-x; face 0 is a wall
             cnt[a] = x == 0 ? 0 : 2;
             pre[a][0] = x; sg[a][0] = 1;
-            pre[a][1] = 2 * n - x; sg[a][1] = -1;
+            pre[a][1] = 2 * n - x; sg[a][1] = mirror;
         } else {
             cnt[a] = 2;
             pre[a][0] = x; sg[a][0] = 1;
-            pre[a][1] = 2 * n - 1 - x; sg[a][1] = -1;
+            pre[a][1] = 2 * n - 1 - x; sg[a][1] = mirror;
         }
     }
     double s = 0.0;
@@ -111,6 +115,26 @@ k_wall_fold(const double* __restrict__ img, double* __restrict__ box, int n, dou
                 s += (double)(sg[0][a] * sg[1][b] * sg[2][c]) *
                      img[d * M3 + pre[0][a] + (int64_t)m * (pre[1][b] + (int64_t)m * pre[2][c])];
     box[t] = box[t] + scale * s;
+}
+
+// the transpose of k_wall_restrict: img = box values in the box part (velocity
+// wall faces zero), zero in the images
+__global__ void __launch_bounds__(WT)
+k_wall_pad(const double* __restrict__ box, double* __restrict__ img, int n, int ncomp, int mode) {
+    const bool vector = mode == W_VELOCITY;
+    const int m = 2 * n;
+    const int64_t M3 = (int64_t)m * m * m, N3 = (int64_t)n * n * n;
+    const int64_t t = (int64_t)blockIdx.x * WT + threadIdx.x;
+    if (t >= ncomp * M3) return;
+    const int d = (int)(t / M3);
+    const int64_t r = t - d * M3;
+    const int ip = (int)(r % m), jp = (int)((r / m) % m), kp = (int)(r / ((int64_t)m * m));
+    double v = 0.0;
+    if (ip < n && jp < n && kp < n) {
+        const bool wall = vector && ((d == 0 && ip == 0) || (d == 1 && jp == 0) || (d == 2 && kp == 0));
+        if (!wall) v = box[d * N3 + ip + (int64_t)n * (jp + (int64_t)n * kp)];
+    }
+    img[t] = v;
 }
 
 // y = a x (element-wise), or y += a x
@@ -132,6 +156,21 @@ hipib_status extend(hipib_ctx* ctx, const double* box, double* img, int ncomp, i
 
 hipib_status restrict_box(hipib_ctx* ctx, const double* img, double* box, int ncomp, int mode) {
     k_wall_restrict<<<blocks_for(ncomp * ctx->n3), WT, 0, ctx->stream>>>(img, box, ctx->n, ncomp, mode);
+    HIPIB_HIP(hipGetLastError());
+    return HIPIB_OK;
+}
+
+// box = fold(img) (box zeroed first) or box += fold(img)
+hipib_status fold(hipib_ctx* ctx, const double* img, double* box, int ncomp, int mode, double s,
+                  bool acc) {
+    if (!acc) HIPIB_TRY(launch_zero(ctx, box, ncomp * ctx->n3));
+    k_wall_fold<<<blocks_for(ncomp * ctx->n3), WT, 0, ctx->stream>>>(img, box, ctx->n, ncomp, mode, s);
+    HIPIB_HIP(hipGetLastError());
+    return HIPIB_OK;
+}
+
+hipib_status pad(hipib_ctx* ctx, const double* box, double* img, int ncomp, int mode) {
+    k_wall_pad<<<blocks_for(ncomp * ctx->img->n3), WT, 0, ctx->stream>>>(box, img, ctx->n, ncomp, mode);
     HIPIB_HIP(hipGetLastError());
     return HIPIB_OK;
 }
@@ -251,9 +290,7 @@ hipib_status walled_spread(hipib_ctx* ctx, const double* X, const double* F, dou
     HIPIB_TRY(launch_zero(ctx, ctx->w_f, 3 * img->n3));
     HIPIB_TRY(launch_spread(img, ctx->w_Xh, F, ctx->w_f));
     // f += (1/8) fold(image force): delta_h at X is 8 times delta_{h/2} at X/2
-    k_wall_fold<<<blocks_for(3 * ctx->n3), WT, 0, ctx->stream>>>(ctx->w_f, f, ctx->n, 0.125);
-    HIPIB_HIP(hipGetLastError());
-    return HIPIB_OK;
+    return fold(ctx, ctx->w_f, f, 3, W_VELOCITY, 0.125, true);
 }
 
 hipib_status walled_interpolate(hipib_ctx* ctx, const double* X, const double* u, double* U) {
@@ -276,6 +313,71 @@ hipib_status walled_ib_step(hipib_ctx* ctx, double* u, double* p, double* X, dou
     HIPIB_TRY(extend(ctx, u, ctx->w_u, 3, W_VELOCITY));
     HIPIB_TRY(launch_interpolate(ctx->img, ctx->w_Xh, ctx->w_u, ctx->w_U, nullptr, 0.0));
     return scale(ctx, ctx->w_U, X, ctx->cfg.dt, 3 * (int64_t)ctx->nn, true);
+}
+
+// Reverse of walled_ib_step, given lam_u = dL/du^{n+1} (box) and lam_X =
+// dL/dX^{n+1}: every mirror map contributes its transpose (extend -> fold,
+// restrict -> pad), the periodic image-grid operators theirs (G^T = -D,
+// D^T = -G, symmetric solves, C'(u)^T), spreading at X/2 the interpolation
+// (S^T = J / h'^3), and the positions the factor 1/2 of X/2.  The adjoint
+// solves start from zero.  Image scratch: w_u, w_g, w_f (vectors), w_p, w_b
+// (scalars); box scratch w_box, w_fbox.
+hipib_status walled_adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n,
+                                 const double* u_np1, double pressure, double* lam_u, double* lam_X,
+                                 double* dtheta) {
+    hipib_ctx* img = ctx->img;
+    img->stream = ctx->stream;
+    HIPIB_TRY(adjoint_scratch(ctx));
+    const double hp = img->h, hp3 = hp * hp * hp, rho = ctx->cfg.rho, dt = ctx->cfg.dt;
+    const double a = rho / dt, b = 0.5 * rho, c = 0.5 * (dt / rho);
+    const int64_t nn3 = 3 * (int64_t)ctx->nn, M3 = img->n3;
+    HIPIB_TRY(image_positions(ctx, X_n));
+    // X^{n+1} = X^n + dt J(X^n / 2) E u^{n+1}
+    HIPIB_TRY(scale(ctx, lam_X, ctx->adj_sX, dt * hp3, nn3, false));      // sX = dt h'^3 lam_X'
+    HIPIB_TRY(launch_zero(ctx, ctx->w_u, 3 * M3));
+    if (ctx->nn > 0) HIPIB_TRY(launch_spread(img, ctx->w_Xh, ctx->adj_sX, ctx->w_u));   // J^T (dt lam_X')
+    HIPIB_TRY(scale(ctx, lam_u, ctx->w_box, 1.0, 3 * ctx->n3, false));
+    HIPIB_TRY(fold(ctx, ctx->w_u, ctx->w_box, 3, W_VELOCITY, 1.0, true));   // dL/du^{n+1}, box
+    if (ctx->nn > 0) {
+        HIPIB_TRY(extend(ctx, u_np1, ctx->w_g, 3, W_VELOCITY));
+        HIPIB_TRY(launch_vjp_X(img, ctx->w_Xh, ctx->w_g, ctx->adj_sX, lam_X, 0.5 / (hp * hp3)));
+    }
+    // u^{n+1} = R(u_s - c G p), p = L^{-1} (mean-free) E_s R_s (-2a D u_s)
+    HIPIB_TRY(pad(ctx, ctx->w_box, ctx->w_u, 3, W_VELOCITY));                // lam of image u^{n+1}
+    HIPIB_TRY(launch_divergence_rhs_coef(img, ctx->w_u, ctx->w_b, -c));      // lam_p = c D lam
+    HIPIB_TRY(mg_remove_mean(img, ctx->w_b, 0));
+    HIPIB_TRY(launch_zero(ctx, ctx->w_p, M3));
+    HIPIB_TRY(mg_solve(img, HIPIB_OP_POISSON, 1, ctx->w_b, ctx->w_p, nullptr, nullptr));
+    HIPIB_TRY(mg_remove_mean(img, ctx->w_p, 0));
+    HIPIB_TRY(fold(ctx, ctx->w_p, ctx->w_box, 1, W_EVEN, 1.0, false));
+    HIPIB_TRY(pad(ctx, ctx->w_box, ctx->w_b, 1, W_EVEN));
+    HIPIB_TRY(launch_project_coef(img, ctx->w_u, ctx->w_b, -2.0 * a));      // lam_us += 2a G lam_b
+    // u_s = E R u*, u* = H^{-1} g_s, g_s = E R g
+    HIPIB_TRY(fold(ctx, ctx->w_u, ctx->w_box, 3, W_VELOCITY, 1.0, false));
+    HIPIB_TRY(pad(ctx, ctx->w_box, ctx->w_g, 3, W_VELOCITY));
+    HIPIB_TRY(launch_zero(ctx, ctx->w_f, 3 * M3));
+    HIPIB_TRY(mg_solve(img, HIPIB_OP_HELMHOLTZ, 3, ctx->w_g, ctx->w_f, nullptr, nullptr));
+    HIPIB_TRY(fold(ctx, ctx->w_f, ctx->w_box, 3, W_VELOCITY, 1.0, false));
+    HIPIB_TRY(pad(ctx, ctx->w_box, ctx->w_u, 3, W_VELOCITY));               // lam_g (image)
+    // g = a E u^n - b C'(E u^n) + E f
+    HIPIB_TRY(extend(ctx, u_n, ctx->w_g, 3, W_VELOCITY));
+    if (ctx->cfg.convection) HIPIB_TRY(launch_conv_vjp(img, ctx->w_g, ctx->w_u, ctx->w_f, a, -b));
+    else HIPIB_TRY(scale(ctx, ctx->w_u, ctx->w_f, a, 3 * M3, false));
+    HIPIB_TRY(fold(ctx, ctx->w_f, lam_u, 3, W_VELOCITY, 1.0, false));       // dL/du^n
+    if (ctx->nn > 0) {
+        // f = (1/8) E^T S(X/2) F
+        HIPIB_TRY(fold(ctx, ctx->w_u, ctx->w_fbox, 3, W_VELOCITY, 1.0, false));   // dL/df (box)
+        HIPIB_TRY(extend(ctx, ctx->w_fbox, ctx->w_g, 3, W_VELOCITY));
+        HIPIB_TRY(launch_interpolate(img, ctx->w_Xh, ctx->w_g, ctx->adj_lamF, nullptr, 0.0));
+        HIPIB_TRY(scale(ctx, ctx->adj_lamF, ctx->adj_lamF, 0.125 / hp3, nn3, false));
+        HIPIB_TRY(launch_fe_force(ctx, X_n, pressure, ctx->F));
+        HIPIB_TRY(launch_vjp_X(img, ctx->w_Xh, ctx->w_g, ctx->F, lam_X, 0.0625 / (hp * hp3)));
+        HIPIB_TRY(adjoint_forces(ctx, X_n, pressure, ctx->adj_lamF, lam_X, dtheta));
+    }
+    HIPIB_TRY(sync_state(ctx));
+    if (ctx->st_host->numeric)
+        return fail(HIPIB_E_NUMERIC, "non-positive Jacobian at a Gauss point (inverted element)");
+    return HIPIB_OK;
 }
 
 // each component a cell-centred scalar: Poisson (Neumann, mirrored evenly,

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2503_22695_amd import inputs
+from tests.test_gpu_adjoint import deformed
 from tests.test_gpu_parity import TOL, assert_close, host, plain_ctx, say, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -114,18 +115,97 @@ def test_walled_advance(torch_dev, hp, ref, name, steps, t0):
     assert_close("X - X0", host(sim.X) - prob.X0, Xr - prob.X0, TOL)
 
 
-def test_walled_adjoint_refused(torch_dev, hp):
+def test_walled_operator_vjps_refused(torch_dev, hp):
+    """The derivatives of single periodic operators are not defined on a walled
+    context; the whole step's reverse is (below)."""
     import torch
     prob = inputs.workload("walled_block_32")
-    say("walled adjoint refused")
+    say("walled operator vjps refused")
     ctx = hp.context_for_problem(prob)
     n = prob.n
     z = torch.zeros((3, n, n, n), dtype=torch.float64, device="cuda")
     X = to_dev(torch, prob.X0)
-    dth = torch.zeros((hp.MAX_MATERIALS, 4), dtype=torch.float64, device="cuda")
     with pytest.raises(hp.HipIBError) as ei:
-        ctx.adjoint_step(z, X, z, 0.0, z.clone(), X.clone(), dth)
+        ctx.spread_vjp_X(X, X.clone(), z, X.clone())
     assert ei.value.status == 6
+
+
+def walled_adjoint_case(torch, hp, ref, prob, x0, pressure, seed, t0=0.0):
+    n = prob.n
+    rng = np.random.default_rng(seed)
+    fl = ref.fluid_from_problem(prob)
+    mesh = ref.MeshBuffers.from_problem(prob)
+    u0 = wall_faces_zero(0.02 * rng.standard_normal((3, n, n, n)))
+    u1, _, _, _ = ref.advance(fl, mesh, u0, np.zeros((n, n, n)), x0, t0, 1, prob.p0, prob.T)
+    lam_u = rng.standard_normal(u0.shape)
+    lam_X = rng.standard_normal(x0.shape)
+    lu_r, lX_r, dth_r = ref.adjoint_step(fl, mesh, u0, x0, u1, pressure, lam_u, lam_X)
+    ctx = hp.context_for_problem(prob)
+    lu, lX = to_dev(torch, lam_u), to_dev(torch, lam_X)
+    dth = torch.zeros((hp.MAX_MATERIALS, 4), dtype=torch.float64, device="cuda")
+    ctx.adjoint_step(to_dev(torch, u0), to_dev(torch, x0), to_dev(torch, u1), pressure, lu, lX, dth)
+    torch.cuda.synchronize()
+    assert_rel("lam_u", host(lu), lu_r, 1e-10)
+    assert_rel("lam_X", host(lX), lX_r, 1e-10)
+    nm = len(prob.materials)
+    assert_rel("dtheta", host(dth)[:nm], dth_r, 1e-10)
+    assert np.any(dth_r != 0) or prob.materials[0].model != inputs.HOLZAPFEL_OGDEN
+
+
+def assert_rel(name, got, want, tol):
+    err = np.max(np.abs(got - want)) / max(np.max(np.abs(want)), 1e-300)
+    say(f"  {name}: rel err {err:.2e}")
+    assert err <= tol, (name, err)
+
+
+def walled_ho_block(n_steps=4):
+    prob = inputs.ho_block(n=32, n_el=6, n_steps=n_steps)
+    prob.name, prob.walls = "walled_ho_block_32", 1
+    return prob
+
+
+def test_walled_adjoint_step_ho_block(torch_dev, hp, ref):
+    prob = walled_ho_block()
+    say("walled adjoint step", prob.name)
+    walled_adjoint_case(torch_dev, hp, ref, prob, deformed(prob, 3, 0.04), 0.0, 41)
+
+
+def test_walled_adjoint_step_shell_with_pressure(torch_dev, hp, ref):
+    """The walled shell (128^3 image grid) at a nonzero cavity pressure, so the
+    pressure load and its derivative take part; inflated 2% across its axis,
+    away from the kink of the fibres' tension-only switch at the reference
+    configuration (where the two sides may take different branches)."""
+    import math
+    prob = inputs.workload("walled_shell_64")
+    t0 = 0.3 * prob.T
+    pressure = prob.p0 * math.sin(math.pi * t0 / prob.T) ** 2
+    c = np.array([0.5, 0.5, 0.5])
+    x0 = c + (prob.X_ref - c) * np.array([1.0, 1.02, 1.02])
+    say("walled adjoint step", prob.name, "pressure", pressure)
+    walled_adjoint_case(torch_dev, hp, ref, prob, x0, pressure, 42, t0)
+
+
+def test_walled_checkpointed_rollout_matches_store_all_oracle(torch_dev, hp, ref):
+    torch = torch_dev
+    prob = walled_ho_block(n_steps=6)
+    say("walled rollout vs oracle", prob.name)
+    theta = np.array(prob.materials[0].params[:4])
+    ro_t = hp.Rollout(prob, checkpoint_every=10 ** 6)
+    th_t = torch.tensor(theta * [1.1, 0.9, 1.1, 0.9], dtype=torch.float64)
+    Xt = host(ro_t.forward(th_t, to_dev(torch, prob.X0), keep_checkpoints=False).clone())
+    ro = hp.Rollout(prob, checkpoint_every=4)                 # ragged segments 4, 2
+    th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    X0 = to_dev(torch, prob.X0).requires_grad_(True)
+    XN = hp.IBRollout().apply(th, X0, ro)
+    L = ((XN - to_dev(torch, Xt)) ** 2).sum()
+    L.backward()
+    fl = ref.fluid_from_problem(prob)
+    mesh = ref.MeshBuffers.from_problem(prob)
+    Lr, dX0r, dthr = ref.rollout_grad(fl, mesh, prob.initial_velocity(), prob.X0, 0.0, prob.n_steps,
+                                      prob.p0, prob.T, Xt)
+    assert abs(float(L) - Lr) <= 1e-9 * Lr
+    assert_rel("dL/dX0", host(X0.grad), dX0r, 1e-9)
+    assert_rel("dL/dtheta", th.grad.numpy(), dthr[0], 1e-8)
 
 
 def test_walled_deterministic_bitwise_and_mixed_precision(torch_dev, hp, ref):
