@@ -232,3 +232,40 @@ def test_walled_deterministic_bitwise_and_mixed_precision(torch_dev, hp, ref):
     e_u = np.linalg.norm(host(mixed.u) - ur) / np.linalg.norm(ur)
     e_X = np.max(np.abs(host(mixed.X) - Xr)) / np.max(np.abs(Xr - prob.X0))
     assert e_u <= 1e-6 and e_X <= 1e-6, (e_u, e_X)
+
+
+def test_walled_rollout_deterministic_bitwise_and_mixed_precision(torch_dev, hp):
+    """The walled rollout gradient in deterministic mode: checkpoints every 4
+    steps and every state kept give bitwise the same loss and gradients.  In
+    mixed precision dL/dX0 = 2 (X^N - X_t)^T dX^N/dX0 is linear in the final
+    residual X^N - X_t, so its relative error is bounded by that of the
+    residual (the mixed forward's error in X^N over max |X^N - X_t|, twice for
+    safety) plus 1e-6 for the FP32 rounding of the reverse steps themselves."""
+    torch = torch_dev
+    prob = walled_ho_block(n_steps=8)
+    say("walled rollout det / mixed", prob.name)
+    theta = np.array(prob.materials[0].params[:4])
+    ro_t = hp.Rollout(prob, checkpoint_every=10 ** 6)
+    Xt = ro_t.forward(torch.tensor(theta * [1.1, 0.9, 1.1, 0.9]), to_dev(torch, prob.X0),
+                      keep_checkpoints=False).clone()
+
+    def grad(**kw):
+        ro = hp.Rollout(prob, **kw)
+        th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+        X0 = to_dev(torch, prob.X0).requires_grad_(True)
+        XN = hp.IBRollout().apply(th, X0, ro)
+        L = ((XN - Xt) ** 2).sum()
+        L.backward()
+        return L.detach().clone(), th.grad.clone(), X0.grad.clone(), XN.detach().clone()
+    a = grad(checkpoint_every=4, deterministic=1)
+    b = grad(checkpoint_every=prob.n_steps, deterministic=1)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    f64 = grad(checkpoint_every=4)
+    mix = grad(checkpoint_every=4, precision=hp.MIXED)
+    res = host(f64[3] - Xt)
+    e_res = np.max(np.abs(host(mix[3]) - host(f64[3]))) / np.max(np.abs(res))
+    say(f"  mixed X^N error over max |X^N - X_t|: {e_res:.2e}")
+    bound = 2.0 * e_res + 1e-6
+    assert_rel("dL/dtheta mixed", mix[1].numpy(), f64[1].numpy(), bound)
+    assert_rel("dL/dX0 mixed", host(mix[2]), host(f64[2]), bound)
