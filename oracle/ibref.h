@@ -176,7 +176,9 @@ void ibref_pressure_vjp(int32_t n_faces, const int32_t* faces, const double* x, 
 int ibref_project(const ibref_fluid* fl, double* v);
 /* Reverse of one ibref_ib_step from (u_n, X_n) to u_np1:
  * in: lam_u = dL/du^{n+1}, lam_X = dL/dX^{n+1};  out: lam_u = dL/du^n,
- * lam_X = dL/dX^n;  dtheta[n_mats][4] += dL/d(a, b, a_f, b_f) of this step. */
+ * lam_X = dL/dX^n;  dtheta[n_mats][4] += dL/d(a, b, a_f, b_f) of this step.
+ * On a walled box the step is reversed on the image grid, each mirror map by
+ * its transpose (extension by the fold, restriction by ibref_wall_pad). */
 int ibref_adjoint_step(const ibref_fluid* fl, const ibref_mesh* m, const double* u_n,
                        const double* X_n, const double* u_np1, double pressure, double* lam_u,
                        double* lam_X, double* dtheta);
