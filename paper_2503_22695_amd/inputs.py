@@ -478,6 +478,29 @@ def shell_base_tethers(X: np.ndarray, n_theta: int, n_psi: int, n_tau: int, kapp
 LV_BASE_KAPPA = 1.0   # nodal penalty stiffness of the base constraint
 
 
+def wall_nodes(n: int = 12, n_nodes: int = 60, seed: int = 5, k: float = 50.0,
+               n_steps: int = 3, dt: float = 1e-3) -> Problem:
+    """Free nodes (no elements) in a walled box, half of them within 2h of a
+    wall, each tethered (isotropic stiffness k) to a target 0.3h away: a
+    workload whose spreading and interpolation stencils cross the walls."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    X = rng.uniform(2.5 * h, 1.0 - 2.5 * h, (n_nodes, 3))
+    near = rng.integers(0, 3, n_nodes // 2)
+    side = rng.integers(0, 2, n_nodes // 2)
+    off = rng.uniform(0.1 * h, 1.9 * h, n_nodes // 2)
+    for q in range(n_nodes // 2):
+        X[q, near[q]] = off[q] if side[q] == 0 else 1.0 - off[q]
+    target = X + 0.3 * h * rng.standard_normal(X.shape) / np.sqrt(3.0)
+    K = np.tile([k, k, k, 0.0, 0.0, 0.0], (n_nodes, 1))
+    return Problem(name=f"wall_nodes_{n}", n=n, rho=1.0, mu=0.01, dt=dt, n_steps=n_steps,
+                   X_ref=X, X0=X.copy(), conn=np.zeros((0, 8), dtype=np.int32),
+                   fibre=np.zeros((0, 3)), mat_id=np.zeros(0, dtype=np.int32),
+                   materials=[Material(NEO_HOOKEAN, (1.0, 10.0))],
+                   faces=np.zeros((0, 4), dtype=np.int32),
+                   tethers=(np.arange(n_nodes, dtype=np.int32), target, K), walls=1)
+
+
 def walled_shell(n: int = 64, n_theta: int = 224, n_psi: int = 80, n_tau: int = 6,
                  n_steps: int = 50, dt: float = 5e-4) -> Problem:
     """The Holzapfel-Ogden shell in a walled box (no slip, no penetration),

@@ -269,3 +269,35 @@ def test_walled_rollout_deterministic_bitwise_and_mixed_precision(torch_dev, hp)
     bound = 2.0 * e_res + 1e-6
     assert_rel("dL/dtheta mixed", mix[1].numpy(), f64[1].numpy(), bound)
     assert_rel("dL/dX0 mixed", host(mix[2]), host(f64[2]), bound)
+
+
+@pytest.mark.parametrize("convection", [1, 0])
+def test_walled_adjoint_step_nodes_at_the_walls(torch_dev, hp, ref, convection):
+    """Tethered free nodes, half within 2h of a wall (stencils crossing the
+    walls on the image grid): one forward step and its reverse against the
+    oracle."""
+    torch = torch_dev
+    prob = inputs.wall_nodes()
+    prob.convection = convection
+    n = prob.n
+    say("walled adjoint, nodes at the walls", convection)
+    rng = np.random.default_rng(12)
+    fl = ref.fluid_from_problem(prob)
+    mesh = ref.MeshBuffers.from_problem(prob)
+    u0 = wall_faces_zero(0.05 * rng.standard_normal((3, n, n, n)))
+    u1, _, X1, _ = ref.advance(fl, mesh, u0, np.zeros((n, n, n)), prob.X0, 0.0, 1)
+    ctx = hp.context_for_problem(prob)
+    ud, pd, Xd = to_dev(torch, u0), torch.zeros((n, n, n), dtype=torch.float64, device="cuda"), to_dev(torch, prob.X0)
+    ctx.ib_step(ud, pd, Xd, 0.0)
+    torch.cuda.synchronize()
+    assert_close("u^1", host(ud), u1, TOL)
+    assert_close("X^1 - X^0", host(Xd) - prob.X0, X1 - prob.X0, TOL)
+    lam_u = rng.standard_normal(u0.shape)
+    lam_X = rng.standard_normal(prob.X0.shape)
+    lu_r, lX_r, _ = ref.adjoint_step(fl, mesh, u0, prob.X0, u1, 0.0, lam_u, lam_X)
+    lu, lX = to_dev(torch, lam_u), to_dev(torch, lam_X)
+    dth = torch.zeros((hp.MAX_MATERIALS, 4), dtype=torch.float64, device="cuda")
+    ctx.adjoint_step(to_dev(torch, u0), to_dev(torch, prob.X0), to_dev(torch, u1), 0.0, lu, lX, dth)
+    torch.cuda.synchronize()
+    assert_rel("lam_u", host(lu), lu_r, 1e-10)
+    assert_rel("lam_X", host(lX), lX_r, 1e-10)

@@ -312,3 +312,34 @@ def test_walled_adjoint_step_shell_with_pressure(ref):
     um, Xm = fwd(u0, x0 - e * dX)
     fd = (np.sum((up - um) * lam_u) + np.sum((Xp - Xm) * lam_X)) / (2 * e)
     assert abs(np.sum(lX * dX) - fd) <= 2e-6 * abs(fd), (np.sum(lX * dX), fd)
+
+
+@pytest.mark.parametrize("convection", [1, 0])
+def test_walled_adjoint_step_nodes_at_the_walls(ref, convection):
+    """Tethered free nodes, half of them within 2h of a wall: the reverse step
+    against central differences along random velocity and node directions,
+    so the position derivatives of spreading and interpolation are checked
+    where their stencils reach across the walls."""
+    prob = inputs.wall_nodes()
+    n = prob.n
+    fl = ref.fluid_from_problem(prob, rtol=1e-14, convection=convection)
+    mesh = ref.MeshBuffers.from_problem(prob)
+    rng = np.random.default_rng(12)
+    u0 = wall_faces_zero(0.05 * rng.standard_normal((3, n, n, n)))
+    X0 = prob.X0
+
+    def fwd(u, X):
+        uu, _, XX, _ = ref.advance(fl, mesh, u, np.zeros((n, n, n)), X, 0.0, 1)
+        return uu, XX
+    u1, X1 = fwd(u0, X0)
+    lam_u1 = rng.standard_normal(u1.shape)
+    lam_X1 = rng.standard_normal(X1.shape)
+    lu0, lX0, _ = ref.adjoint_step(fl, mesh, u0, X0, u1, 0.0, lam_u1, lam_X1)
+    du = rng.standard_normal(u0.shape)
+    dX = rng.standard_normal(X0.shape)
+    for (a, b, pred) in [(du, 0 * dX, np.sum(lu0 * du)), (0 * du, dX, np.sum(lX0 * dX))]:
+        e = 1e-6
+        up, Xp = fwd(u0 + e * a, X0 + e * b)
+        um, Xm = fwd(u0 - e * a, X0 - e * b)
+        fd = (np.sum((up - um) * lam_u1) + np.sum((Xp - Xm) * lam_X1)) / (2 * e)
+        assert abs(pred - fd) <= 2e-6 * max(abs(fd), 1e-12), (pred, fd)
