@@ -118,12 +118,14 @@ def lv_workload(torch, hipib, inputs):
     return out
 
 
-def adjoint_ratio(torch, hipib, inputs):
+def adjoint_ratio(torch, hipib, inputs, name="ho_block_64",
+                  label="ho_block_64: 64^3 grid, 12^3 HO hexes, 50 steps, checkpoints every 10, FP64"):
     """Adjoint workload: 64^3 grid, Holzapfel-Ogden block of 12^3 hexes, 50
     steps, loss |X^N - X_target|^2 with X_target from a run at perturbed
     parameters; (checkpointed forward + backward) time over plain forward time,
-    FP64, checkpoints every 10 steps."""
-    prob = inputs.workload("ho_block_64")
+    FP64, checkpoints every 10 steps.  name selects the same block in a walled
+    box."""
+    prob = inputs.workload(name)
     dev = torch.device("cuda", 0)
     theta = torch.tensor(prob.materials[0].params[:4], dtype=torch.float64)
     X0 = torch.tensor(prob.X0, dtype=torch.float64, device=dev)
@@ -160,7 +162,7 @@ def adjoint_ratio(torch, hipib, inputs):
                                                        "medians of 3 after a warm-up gradient pass",
             "backward_over_forward": round((both - fwd) / fwd, 3), "forward_ms": round(1e3 * fwd, 2),
             "forward_plus_backward_ms": round(1e3 * both, 2),
-            "workload": "ho_block_64: 64^3 grid, 12^3 HO hexes, 50 steps, checkpoints every 10, FP64",
+            "workload": label,
             "grad_theta": [float(v) for v in th.grad]}
 
 
@@ -219,7 +221,8 @@ def main():
     ap.add_argument("--steps-192", type=int, default=20)
     ap.add_argument("--no-lv", action="store_true", help="skip the 128^3 left-ventricle-law leg")
     ap.add_argument("--no-tet", action="store_true", help="skip the 64^3 P2-tetrahedra leg")
-    ap.add_argument("--no-walls", action="store_true", help="skip the walled 64^3 shell leg")
+    ap.add_argument("--no-walls", action="store_true",
+                    help="skip the walled 64^3 shell leg and the walled adjoint ratio")
     ap.add_argument("--roofline-steps", type=int, default=20,
                     help="steps of the separate pass that times the roofline kernel")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -310,6 +313,12 @@ def main():
     if not args.no_adjoint:
         adjoint = adjoint_ratio(torch, hipib, inputs)
         progress("adjoint leg done")
+        if not args.no_walls:
+            adjoint["walled"] = adjoint_ratio(
+                torch, hipib, inputs, "walled_ho_block_64",
+                "walled_ho_block_64: the same block in a walled 64^3 box (128^3 image grid), "
+                "50 steps, checkpoints every 10, FP64")
+            progress("walled adjoint leg done")
 
     larger = None
     if not args.no_192:

@@ -128,6 +128,8 @@ struct hipib_ctx {
     double* w_Xh = nullptr;   // [nn][3] positions on the image grid's unit box (X / 2)
     double* w_U = nullptr;    // [nn][3] interpolated velocity
     int32_t w_nn = -1;        // node count the node buffers are sized for
+    double* w_ap = nullptr;   // [m^3] adjoint pressure of the walled reverse step (its solves' start)
+    double* w_ah = nullptr;   // [3][m^3] adjoint Helmholtz solution of the walled reverse step
     int32_t nt = 0;                  // penalty tethers (hipib_set_tethers)
     int32_t* tether_node = nullptr;  // [nt] distinct node indices
     double* tether_Y = nullptr;      // [nt][3] targets

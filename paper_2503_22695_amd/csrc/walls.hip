@@ -223,7 +223,7 @@ void walled_free(hipib_ctx* ctx) {
     if (ctx->img) (void)hipib_destroy(ctx->img);
     ctx->img = nullptr;
     double** bufs[] = {&ctx->w_u, &ctx->w_f, &ctx->w_g, &ctx->w_p, &ctx->w_b,
-                       &ctx->w_box, &ctx->w_fbox, &ctx->w_Xh, &ctx->w_U};
+                       &ctx->w_box, &ctx->w_fbox, &ctx->w_Xh, &ctx->w_U, &ctx->w_ap, &ctx->w_ah};
     for (double** b : bufs) {
         (void)hipFree(*b);
         *b = nullptr;
@@ -320,14 +320,21 @@ hipib_status walled_ib_step(hipib_ctx* ctx, double* u, double* p, double* X, dou
 // restrict -> pad), the periodic image-grid operators theirs (G^T = -D,
 // D^T = -G, symmetric solves, C'(u)^T), spreading at X/2 the interpolation
 // (S^T = J / h'^3), and the positions the factor 1/2 of X/2.  The adjoint
-// solves start from zero.  Image scratch: w_u, w_g, w_f (vectors), w_p, w_b
-// (scalars); box scratch w_box, w_fbox.
+// solves start from the previous call's solutions (w_ap, w_ah; zero on the
+// first call), as the periodic reverse step's do.  Image scratch: w_u, w_g,
+// w_f (vectors), w_p, w_b (scalars); box scratch w_box, w_fbox.
 hipib_status walled_adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n,
                                  const double* u_np1, double pressure, double* lam_u, double* lam_X,
                                  double* dtheta) {
     hipib_ctx* img = ctx->img;
     img->stream = ctx->stream;
     HIPIB_TRY(adjoint_scratch(ctx));
+    if (!ctx->w_ap) {
+        HIPIB_TRY(alloc(ctx, &ctx->w_ap, (size_t)img->n3));
+        HIPIB_TRY(alloc(ctx, &ctx->w_ah, 3 * (size_t)img->n3));
+        HIPIB_TRY(launch_zero(ctx, ctx->w_ap, img->n3));
+        HIPIB_TRY(launch_zero(ctx, ctx->w_ah, 3 * img->n3));
+    }
     const double hp = img->h, hp3 = hp * hp * hp, rho = ctx->cfg.rho, dt = ctx->cfg.dt;
     const double a = rho / dt, b = 0.5 * rho, c = 0.5 * (dt / rho);
     const int64_t nn3 = 3 * (int64_t)ctx->nn, M3 = img->n3;
@@ -346,18 +353,16 @@ hipib_status walled_adjoint_step(hipib_ctx* ctx, const double* u_n, const double
     HIPIB_TRY(pad(ctx, ctx->w_box, ctx->w_u, 3, W_VELOCITY));                // lam of image u^{n+1}
     HIPIB_TRY(launch_divergence_rhs_coef(img, ctx->w_u, ctx->w_b, -c));      // lam_p = c D lam
     HIPIB_TRY(mg_remove_mean(img, ctx->w_b, 0));
-    HIPIB_TRY(launch_zero(ctx, ctx->w_p, M3));
-    HIPIB_TRY(mg_solve(img, HIPIB_OP_POISSON, 1, ctx->w_b, ctx->w_p, nullptr, nullptr));
-    HIPIB_TRY(mg_remove_mean(img, ctx->w_p, 0));
-    HIPIB_TRY(fold(ctx, ctx->w_p, ctx->w_box, 1, W_EVEN, 1.0, false));
+    HIPIB_TRY(mg_solve(img, HIPIB_OP_POISSON, 1, ctx->w_b, ctx->w_ap, nullptr, nullptr));
+    HIPIB_TRY(mg_remove_mean(img, ctx->w_ap, 0));
+    HIPIB_TRY(fold(ctx, ctx->w_ap, ctx->w_box, 1, W_EVEN, 1.0, false));
     HIPIB_TRY(pad(ctx, ctx->w_box, ctx->w_b, 1, W_EVEN));
     HIPIB_TRY(launch_project_coef(img, ctx->w_u, ctx->w_b, -2.0 * a));      // lam_us += 2a G lam_b
     // u_s = E R u*, u* = H^{-1} g_s, g_s = E R g
     HIPIB_TRY(fold(ctx, ctx->w_u, ctx->w_box, 3, W_VELOCITY, 1.0, false));
     HIPIB_TRY(pad(ctx, ctx->w_box, ctx->w_g, 3, W_VELOCITY));
-    HIPIB_TRY(launch_zero(ctx, ctx->w_f, 3 * M3));
-    HIPIB_TRY(mg_solve(img, HIPIB_OP_HELMHOLTZ, 3, ctx->w_g, ctx->w_f, nullptr, nullptr));
-    HIPIB_TRY(fold(ctx, ctx->w_f, ctx->w_box, 3, W_VELOCITY, 1.0, false));
+    HIPIB_TRY(mg_solve(img, HIPIB_OP_HELMHOLTZ, 3, ctx->w_g, ctx->w_ah, nullptr, nullptr));
+    HIPIB_TRY(fold(ctx, ctx->w_ah, ctx->w_box, 3, W_VELOCITY, 1.0, false));
     HIPIB_TRY(pad(ctx, ctx->w_box, ctx->w_u, 3, W_VELOCITY));               // lam_g (image)
     // g = a E u^n - b C'(E u^n) + E f
     HIPIB_TRY(extend(ctx, u_n, ctx->w_g, 3, W_VELOCITY));

@@ -608,6 +608,10 @@ def workload(name: str) -> Problem:
         return p
     if name == "walled_shell_64":    # walled box, HO shell, 64^3 (128^3 image grid), 50 steps
         return walled_shell()
+    if name == "walled_ho_block_64":  # the adjoint workload in a walled box (128^3 image grid)
+        p = ho_block()
+        p.name, p.walls = "walled_ho_block_64", 1
+        return p
     if name == "tet10_block_64":     # P2 tets, Psi_1, tethered face: the benchmark's settings
         p = tet_block(2, n=64, n_el=10, n_steps=20)
         return p
@@ -616,4 +620,4 @@ def workload(name: str) -> Problem:
 
 WORKLOADS = ("nh_block_32", "ho_shell_128", "shell_leaflets_192",
              "nh_block_32_mixed", "ho_block_64", "lv_shell_128", "lv_block_32", "tet10_block_64",
-             "walled_block_32", "walled_shell_64")
+             "walled_block_32", "walled_shell_64", "walled_ho_block_64")
