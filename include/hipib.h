@@ -243,7 +243,8 @@ int32_t hipib_get_step_stats(hipib_ctx* ctx, int32_t* cycles, double* relres,
  * (config walls = 1) the step is reversed on the mirror-image grid, each mirror
  * map by its transpose (extension by the fold onto the box, restriction by
  * zero padding); its adjoint solves also start from the previous call's
- * solutions.  Waits for completion. */
+ * solutions.  The first call on a context allocates the reverse step's
+ * workspaces (HIPIB_E_NOMEM if that fails).  Waits for completion. */
 hipib_status hipib_adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n,
                                 const double* u_np1, double pressure, double* lam_u,
                                 double* lam_X, double* dtheta);
