@@ -100,6 +100,16 @@ void free_mesh(hipib_ctx* ctx) {
 }
 
 void free_all(hipib_ctx* ctx) {
+    // the side stream's work is joined into the context's stream by every
+    // ib_step; wait for it anyway before anything is freed
+    if (ctx->side) {
+        (void)hipStreamSynchronize(ctx->side);
+        (void)hipStreamDestroy(ctx->side);
+    }
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    ctx->side = nullptr;
+    ctx->ev_fork = ctx->ev_join = nullptr;
     walled_free(ctx);
     free_mesh(ctx);
     (void)hipFree(ctx->faces);
@@ -156,9 +166,20 @@ hipib_status fluid_solves(hipib_ctx* ctx, double* u, double* p) {
 
 hipib_status ib_step(hipib_ctx* ctx, double* u, double* p, double* X, double pressure) {
     if (ctx->cfg.walls) return walled_ib_step(ctx, u, p, X, pressure);
+    // the element forces run on the side stream while the context's stream bins
+    // the nodes and builds the fluid right-hand side (disjoint buffers); the
+    // spreading waits for both
+    HIPIB_HIP(hipEventRecord(ctx->ev_fork, ctx->stream));
+    HIPIB_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+    hipStream_t own = ctx->stream;
+    ctx->stream = ctx->side;
+    const hipib_status fs = launch_fe_force(ctx, X, pressure, ctx->F);
+    ctx->stream = own;
+    HIPIB_TRY(fs);
+    HIPIB_HIP(hipEventRecord(ctx->ev_join, ctx->side));
     HIPIB_TRY(launch_bin(ctx, X));
-    HIPIB_TRY(launch_fe_force(ctx, X, pressure, ctx->F));
     HIPIB_TRY(launch_rhs_build(ctx, u, nullptr, ctx->g));
+    HIPIB_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
     HIPIB_TRY(launch_spread(ctx, X, ctx->F, ctx->g));
     HIPIB_TRY(fluid_solves(ctx, u, p));
     if (ctx->st_host->numeric)
@@ -282,6 +303,13 @@ hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out
         hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&ctx->st_host), sizeof(MGState));
         if (e != hipSuccess) s = fail(HIPIB_E_NOMEM, "pinned host allocation failed");
         else std::memset(ctx->st_host, 0, sizeof(MGState));
+    }
+    if (s == HIPIB_OK) {
+        // default priority, like the context's own stream
+        hipError_t e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) s = fail(HIPIB_E_HIP, "HIP error %d creating the side stream", (int)e);
     }
     if (s == HIPIB_OK) s = mg_prepare(ctx);
     if (s == HIPIB_OK && cfg->walls) s = walled_create(ctx);

@@ -64,6 +64,8 @@ struct StepRecord {
 struct hipib_ctx {
     hipib_config cfg{};
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;         // element forces of ib_step, overlapping the fluid right-hand side
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int device = 0;
     int n = 0;
     int64_t n3 = 0;
