@@ -322,16 +322,16 @@ hipib_status walled_ib_step(hipib_ctx* ctx, double* u, double* p, double* X, dou
 // (S^T = J / h'^3), and the positions the factor 1/2 of X/2.  The adjoint
 // solves start from the previous call's solutions (w_ap, w_ah; zero on the
 // first call), as the periodic reverse step's do.  Image scratch: w_u, w_g,
-// w_f (vectors), w_p, w_b (scalars); box scratch w_box, w_fbox.
+// w_f (vectors), w_b (scalar); box scratch w_box, w_fbox.
 hipib_status walled_adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n,
                                  const double* u_np1, double pressure, double* lam_u, double* lam_X,
                                  double* dtheta) {
     hipib_ctx* img = ctx->img;
     img->stream = ctx->stream;
     HIPIB_TRY(adjoint_scratch(ctx));
-    if (!ctx->w_ap) {
-        HIPIB_TRY(alloc(ctx, &ctx->w_ap, (size_t)img->n3));
-        HIPIB_TRY(alloc(ctx, &ctx->w_ah, 3 * (size_t)img->n3));
+    if (!ctx->w_ap || !ctx->w_ah) {   // first call: the solves' starts, zero
+        if (!ctx->w_ap) HIPIB_TRY(alloc(ctx, &ctx->w_ap, (size_t)img->n3));
+        if (!ctx->w_ah) HIPIB_TRY(alloc(ctx, &ctx->w_ah, 3 * (size_t)img->n3));
         HIPIB_TRY(launch_zero(ctx, ctx->w_ap, img->n3));
         HIPIB_TRY(launch_zero(ctx, ctx->w_ah, 3 * img->n3));
     }
