@@ -136,3 +136,24 @@ def test_adjoint_checkpointed_equals_store_all_bitwise(torch_dev, hp):
         assert same(torch, grads[0][2], g[2])
         assert same(torch, grads[0][0], g[0])
         assert same(torch, grads[0][1], g[1])
+
+
+def test_run_on_a_user_stream_equals_the_default_stream_bitwise(torch_dev, hp):
+    """A context created on a user stream (its element forces forked to the
+    context's side stream and joined back by events, as on the default
+    stream) gives bitwise the same deterministic run as one on the default
+    stream: the 64^3 HO block, 20 steps."""
+    torch = torch_dev
+    prob = inputs.workload("ho_block_64")
+    say("user stream vs default stream", prob.name)
+    a = hp.Simulation(prob, deterministic=1)
+    a.advance(20)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = hp.Simulation(prob, deterministic=1)
+        b.advance(20)
+    s.synchronize()
+    torch.cuda.synchronize()
+    for f in ("u", "p", "X"):
+        assert same(torch, getattr(a, f), getattr(b, f)), f
