@@ -18,9 +18,20 @@
  *   "Eulerian-Lagrangian coupling operators"          spreading, interpolation,
  *                                nodal quadrature rule, nodal force formula
  *   "Constitutive laws"          Psi = W + U(J), U = (kappa/2)(ln J)^2,
- *                                modified invariant I1bar, HO model Psi_4
- *   "Mitral valve model"         neo-Hookean chordae law
+ *                                modified invariant I1bar, the laws Psi_1 to
+ *                                Psi_3 and the HO model Psi_4 with its sheet
+ *                                and fibre-sheet terms
+ *   "Mitral valve model"         neo-Hookean chordae law; tetrahedral meshes
+ *                                (P1 and P2 elements) of the valve set-ups
+ *   "Dynamic left ventricle model"   active fibre stress and its waveform,
+ *                                endocardial pressure, base constraint
+ *   Cook's membrane and aortic valve set-ups   penalty tethers
+ *   "Spatial Discretization"     the walled box's boundary conditions,
+ *                                solved on the box's mirror image
  *   Abstract                     geometric multigrid for the fluid solves
+ * The reverse step and the rollout gradient are not in the paper: they are the
+ * transposes of the steps above.  Every function is pinned by the tests
+ * against closed forms, brute force, invariants or central differences.
  */
 #include "ibref.h"
 
