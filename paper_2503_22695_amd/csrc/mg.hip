@@ -254,7 +254,7 @@ k_restrict(const T* __restrict__ r, int nf, int64_t fcs, T* __restrict__ bc, int
 // One workgroup per coarse tile of RCX x RCY x RCZ cells: the red residuals
 // of its fine window go to LDS once (no residual array in HBM), then each
 // thread sums its window from LDS.
-constexpr int RCX = 32, RCY = 4, RCZ = 4;
+constexpr int RCX = 32, RCY = 8, RCZ = 4;
 constexpr int RWY = 2 * RCY + 2, RWZ = 2 * RCZ + 2;  // fine window rows and planes
 constexpr int RRED = RCX + 1;                        // red cells per window row
 constexpr int RTHREADS = RCX * RCY * RCZ;            // one thread per coarse cell
