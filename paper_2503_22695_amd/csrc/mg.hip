@@ -1050,7 +1050,7 @@ constexpr int KB = 8;                                 // owned cells per axis
 constexpr int KDH = 5, KUH = 4;                       // halos of the down / up kernels
 constexpr int KDE = KB + 2 * KDH, KUE = KB + 2 * KUH; // LDS box sides (18, 16)
 constexpr int KW = KB + 2;                            // restriction window side
-constexpr int KTHREADS = 512;
+constexpr int KTHREADS = 1024;
 
 template <int E>
 __device__ __forceinline__ int lix(int a, int b, int c) { return a + E * (b + E * c); }
