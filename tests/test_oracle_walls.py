@@ -343,3 +343,18 @@ def test_walled_adjoint_step_nodes_at_the_walls(ref, convection):
         um, Xm = fwd(u0 - e * a, X0 - e * b)
         fd = (np.sum((up - um) * lam_u1) + np.sum((Xp - Xm) * lam_X1)) / (2 * e)
         assert abs(pred - fd) <= 2e-6 * max(abs(fd), 1e-12), (pred, fd)
+
+
+def test_wall_nodes_workload_reaches_the_walls():
+    """The near-wall workload places half its nodes within 2h of a wall (so the
+    stencils of the pins above cross the walls) and keeps every node inside
+    the box, each tethered once."""
+    prob = inputs.wall_nodes()
+    h = prob.h
+    X = prob.X0
+    dist = np.minimum(X, 1.0 - X).min(axis=1)
+    assert np.all((X > 0) & (X < 1))
+    assert np.sum(dist < 2 * h) >= len(X) // 2
+    node, target, K = prob.tethers
+    assert sorted(node.tolist()) == list(range(len(X)))
+    assert np.all(K[:, :3] > 0) and np.all(K[:, 3:] == 0)
