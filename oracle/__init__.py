@@ -92,6 +92,7 @@ def lib():
             "ibref_ns_step": (C.c_int, [P, P, P, P, P]),
             "ibref_ib_step": (C.c_int, [P, P, P, P, P, f64, P]),
             "ibref_advance": (C.c_int, [P, P, P, P, P, f64, i32, f64, f64, P]),
+            "ibref_advance_steps": (C.c_int, [P, P, P, P, P, f64, i32, i32, f64, f64, P]),
             "ibref_convection_vjp": (None, [i32, P, P, P]),
             "ibref_dphi": (f64, [f64]),
             "ibref_spread_vjp_X": (None, [i32, i32, P, P, P, P]),
@@ -314,11 +315,13 @@ def ns_step(fl: Fluid, f: np.ndarray, u: np.ndarray, p: np.ndarray):
     return u, p, st
 
 
-def advance(fl: Fluid, mesh: MeshBuffers, u, p, X, t0: float, n_steps: int, p0=0.0, T=1.0):
+def advance(fl: Fluid, mesh: MeshBuffers, u, p, X, t0: float, n_steps: int, p0=0.0, T=1.0,
+            first_step: int = 0):
+    """Steps first_step .. first_step + n_steps - 1 of a run started at t0."""
     u, p, X = _f64(u).copy(), _f64(p).copy(), _f64(X).copy()
     stats = (StepStats * max(n_steps, 1))()
-    _check(lib().ibref_advance(C.byref(fl), C.byref(mesh.s), _p(u), _p(p), _p(X), t0, n_steps,
-                               p0, T, stats), "advance")
+    _check(lib().ibref_advance_steps(C.byref(fl), C.byref(mesh.s), _p(u), _p(p), _p(X), t0,
+                                     int(first_step), n_steps, p0, T, stats), "advance")
     return u, p, X, [stats[i] for i in range(n_steps)]
 
 

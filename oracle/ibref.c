@@ -626,7 +626,12 @@ void ibref_pressure_load(int32_t n_faces, const int32_t* faces, const double* x,
  *   prolongation: cell-centred trilinear (3/4, 1/4 per axis), added to x;
  *   coarse operators rediscretised at 2h; the coarsest level is the first
  *   with fewer than 8 cells per side, solved by mg_coarse_sweeps red+black
- *   sweeps; Poisson (sigma = 0): the mean is removed after the coarse solve
+ *   sweeps, except for the Helmholtz operator (sigma > 0), whose hierarchy
+ *   stops at the first level l >= 1 where sigma >= 4 (6 nu / h_l^2) (diagonal
+ *   dominance by a factor of four: there Gauss-Seidel alone damps every error
+ *   component, so deeper levels add nothing to the cycle's contraction);
+ *   that level is relaxed by max(mg_pre, 1) red+black sweeps from zero;
+ *   Poisson (sigma = 0): the mean is removed after the coarse solve
  *   and once from the final solution (the residual and the sweeps are
  *   invariant to adding a constant, so the iterates need no mean removal).
  * Stop rule: ||b - A x||_2 <= max(rtol, 1e3 eps) ||b||_2, tested before the
@@ -750,12 +755,24 @@ static void mg_free(mg_levels* lv) {
     for (int l = 0; l < lv->L; ++l) { free(lv->x[l]); free(lv->b[l]); free(lv->r[l]); }
 }
 
+/* the level at which the cycle stops descending (see above) */
+static int coarsest_level(const mg_levels* lv, double sigma, double nu) {
+    if (sigma > 0.0)
+        for (int l = 1; l < lv->L - 1; ++l) {
+            const double h = 1.0 / lv->n[l];
+            if (sigma >= 4.0 * (6.0 * nu / (h * h))) return l;
+        }
+    return lv->L - 1;
+}
+
 static void vcycle(const ibref_fluid* fl, mg_levels* lv, int l, double sigma, double nu,
                    int poisson, const double* b, double* x) {
     int n = lv->n[l];
     long N3 = (long)n * n * n;
-    if (l == lv->L - 1) {
-        for (int s = 0; s < fl->mg_coarse_sweeps; ++s) {
+    const int lc = coarsest_level(lv, sigma, nu);
+    if (l == lc) {
+        const int sweeps = lc == lv->L - 1 ? fl->mg_coarse_sweeps : (fl->mg_pre > 1 ? fl->mg_pre : 1);
+        for (int s = 0; s < sweeps; ++s) {
             gs_colour(n, sigma, nu, b, x, 0);
             gs_colour(n, sigma, nu, b, x, 1);
         }
@@ -1222,9 +1239,15 @@ static ibref_mesh mesh_at(const ibref_mesh* m, double t) {
 
 int ibref_advance(const ibref_fluid* fl, const ibref_mesh* m, double* u, double* p, double* X,
                   double t0, int32_t n_steps, double p0, double T, ibref_step_stats* stats) {
+    return ibref_advance_steps(fl, m, u, p, X, t0, 0, n_steps, p0, T, stats);
+}
+
+int ibref_advance_steps(const ibref_fluid* fl, const ibref_mesh* m, double* u, double* p, double* X,
+                        double t0, int32_t first_step, int32_t n_steps, double p0, double T,
+                        ibref_step_stats* stats) {
     const double pi = 3.14159265358979323846;
     for (int s = 0; s < n_steps; ++s) {
-        double t = t0 + s * fl->dt;
+        double t = t0 + (first_step + s) * fl->dt;
         double pr = 0.0;
         if (p0 != 0.0 && T > 0.0) {
             double sn = sin(pi * t / T);

@@ -148,6 +148,11 @@ int ibref_ib_step(const ibref_fluid* fl, const ibref_mesh* m, double* u, double*
  * stats (may be NULL) receives one record per step. */
 int ibref_advance(const ibref_fluid* fl, const ibref_mesh* m, double* u, double* p, double* X,
                   double t0, int32_t n_steps, double p0, double T, ibref_step_stats* stats);
+/* Steps first_step .. first_step + n_steps - 1 of a run started at t0 (step s at
+ * t0 + s dt): a long run taken in pieces gives exactly the unsplit run. */
+int ibref_advance_steps(const ibref_fluid* fl, const ibref_mesh* m, double* u, double* p, double* X,
+                        double t0, int32_t first_step, int32_t n_steps, double p0, double T,
+                        ibref_step_stats* stats);
 
 /* --- discrete adjoint (reverse mode of one IB step) ---------------------
  * Gradients are taken with respect to the plain entries of the arrays
