@@ -110,6 +110,11 @@ void hipib_default_config(hipib_config* cfg);
  * hipStream_t (NULL: the null stream).  Allocates every grid workspace. */
 hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out);
 hipib_status hipib_destroy(hipib_ctx* ctx);
+/* Makes stream (a hipStream_t; NULL: the null stream) the context's stream for
+ * every later call.  Work the context enqueued on its previous stream is
+ * ordered before anything later enqueued on the new one (an event recorded on
+ * the old stream is waited for by the new one); the caller's own work on the
+ * old stream is not.  HIPIB_E_HIP if the event calls fail. */
 hipib_status hipib_set_stream(hipib_ctx* ctx, void* stream);
 const char* hipib_last_error(void);
 
@@ -248,6 +253,12 @@ int32_t hipib_get_step_stats(hipib_ctx* ctx, int32_t* cycles, double* relres,
 hipib_status hipib_adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n,
                                 const double* u_np1, double pressure, double* lam_u,
                                 double* lam_X, double* dtheta);
+/* Zeroes the starting points of the reverse step's adjoint solves (each
+ * hipib_adjoint_step starts them from the previous call's solutions), so a
+ * backward pass that calls this first gives the same gradients whatever
+ * passes ran on the context before it.  Nothing to do before the first
+ * hipib_adjoint_step.  Enqueued on the context's stream. */
+hipib_status hipib_adjoint_reset(hipib_ctx* ctx);
 /* HV := (dF_el/dX) V, the directional derivative of the elastic nodal force
  * (minus the strain-energy Hessian times V). */
 hipib_status hipib_fe_hvp(hipib_ctx* ctx, const double* X, const double* V, double* HV);

@@ -339,8 +339,14 @@ hipib_status hipib_destroy(hipib_ctx* ctx) {
 }
 
 hipib_status hipib_set_stream(hipib_ctx* ctx, void* stream) {
-    if (!ctx) return fail(HIPIB_E_INVAL, "null context");
-    ctx->stream = static_cast<hipStream_t>(stream);
+    HIPIB_TRY(check_ctx(ctx));
+    hipStream_t next = static_cast<hipStream_t>(stream);
+    if (next == ctx->stream) return HIPIB_OK;
+    // work still enqueued on the old stream (a step's interpolation and
+    // position update, for one) is ordered before anything on the new one
+    HIPIB_HIP(hipEventRecord(ctx->ev_fork, ctx->stream));
+    HIPIB_HIP(hipStreamWaitEvent(next, ctx->ev_fork, 0));
+    ctx->stream = next;
     return HIPIB_OK;
 }
 
@@ -665,6 +671,17 @@ hipib_status hipib_adjoint_step(hipib_ctx* ctx, const double* u_n, const double*
     if (!std::isfinite(pressure)) return fail(HIPIB_E_INVAL, "non-finite pressure");
     if (ctx->cfg.walls) return walled_adjoint_step(ctx, u_n, X_n, u_np1, pressure, lam_u, lam_X, dtheta);
     return adjoint_step(ctx, u_n, X_n, u_np1, pressure, lam_u, lam_X, dtheta);
+}
+
+hipib_status hipib_adjoint_reset(hipib_ctx* ctx) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (ctx->adj_lg) HIPIB_TRY(launch_zero(ctx, ctx->adj_lg, 3 * ctx->n3));
+    if (ctx->adj_p) HIPIB_TRY(launch_zero(ctx, ctx->adj_p, ctx->n3));
+    if (ctx->cfg.walls && ctx->img) {
+        if (ctx->w_ap) HIPIB_TRY(launch_zero(ctx, ctx->w_ap, ctx->img->n3));
+        if (ctx->w_ah) HIPIB_TRY(launch_zero(ctx, ctx->w_ah, 3 * ctx->img->n3));
+    }
+    return HIPIB_OK;
 }
 
 hipib_status hipib_fe_hvp(hipib_ctx* ctx, const double* X, const double* V, double* HV) {

@@ -777,6 +777,7 @@ __global__ void k_state_reset(MGState* st, int ncomp) {
 template <typename T>
 struct SmallArgs {
     int pre, post, sweeps, poisson, zero_init;
+    int depth;   // levels below N0 the cycle descends (the last one relaxed by `sweeps`)
     T sigma, nu;
 };
 
@@ -966,7 +967,22 @@ __device__ __forceinline__ void s_up(T* x, const T* b, const T* xc, const SmallA
     }
 }
 
-// One V-cycle over the levels N0 (, N0/2, ...) down to the coarsest (< 8).
+// the level the cycle stops at, relaxed by all threads from x (zero: x = 0 on
+// entry, not read)
+template <int N, typename T>
+__device__ __forceinline__ void s_relax(T* x, const T* b, const SmallArgs<T>& A, bool zero) {
+    T c, inv_diag;
+    level_coef<N>(A, c, inv_diag);
+    for (int s = 0; s < A.sweeps; ++s) {
+        s_gs<N>(x, b, c, inv_diag, 0, threadIdx.x, blockDim.x, zero && s == 0);
+        __syncthreads();
+        s_gs<N>(x, b, c, inv_diag, 1, threadIdx.x, blockDim.x);
+        __syncthreads();
+    }
+}
+
+// One V-cycle over the levels N0 (, N0/2, ...) down to the coarsest (< 8), or
+// down to A.depth levels below N0 when the cycle stops earlier.
 // LDS holds [x, b, r] per level, packed like the global arrays.
 template <int N0, typename T>
 __global__ void __launch_bounds__(kSmallThreads)
@@ -1007,16 +1023,28 @@ k_small_vcycle(T* __restrict__ xg, const T* __restrict__ bg, int64_t cs, SmallAr
         }
     }
     __syncthreads();
+    if (A.depth == 0) {
+        // N0 is the level the cycle stops at
+        s_relax<N0>(x0, b0, A, A.zero_init != 0);
+        for (int o = threadIdx.x; o < C0; o += blockDim.x) xg[comp * cs + o] = x0[o];
+        return;
+    }
     s_down<N0>(x0, b0, r0, b1, A, A.zero_init != 0);
     if constexpr (N1 >= 8) {
         constexpr int N2 = N1 / 2;
         constexpr int C2 = N2 * N2 * N2;
         T* x2 = r1 + C1;
         T* b2 = x2 + C2;
-        s_down<N1>(x1, b1, r1, b2, A, true);
-        if (threadIdx.x < 64) s_coarse_wave<N2>(x2, b2, A);
-        __syncthreads();
-        s_up<N1>(x1, b1, x2, A);
+        if (A.depth == 1) {
+            // N1 is the level the cycle stops at
+            if (threadIdx.x < 64) s_coarse_wave<N1>(x1, b1, A);
+            __syncthreads();
+        } else {
+            s_down<N1>(x1, b1, r1, b2, A, true);
+            if (threadIdx.x < 64) s_coarse_wave<N2>(x2, b2, A);
+            __syncthreads();
+            s_up<N1>(x1, b1, x2, A);
+        }
     } else {
         (void)r1;
         if (threadIdx.x < 64) s_coarse_wave<N1>(x1, b1, A);
@@ -1279,6 +1307,29 @@ OpCoef op_coef(const hipib_ctx* ctx, int op) {
     return {ctx->cfg.rho / ctx->cfg.dt, ctx->cfg.mu, 0};
 }
 
+// The level at which a cycle stops descending.  For the Helmholtz operator
+// (sigma > 0) the hierarchy ends at the first level l >= 1 where
+// sigma >= 4 (6 nu / h_l^2): there the operator is diagonally dominant by a
+// factor of four, red-black Gauss-Seidel alone damps every error component,
+// and deeper levels add nothing to the cycle's contraction.  That level is
+// relaxed by max(pre, 1) red+black sweeps from zero.  Otherwise (and for
+// Poisson) the coarsest level is the first with fewer than 8 cells per side,
+// relaxed by the coarse sweeps.
+int stop_level(const hipib_ctx* ctx, const OpCoef& oc) {
+    if (oc.sigma > 0.0)
+        for (int l = 1; l < ctx->L - 1; ++l) {
+            const double h = 1.0 / ctx->lv[l].n;
+            if (oc.sigma >= 4.0 * (6.0 * oc.nu / (h * h))) return l;
+        }
+    return ctx->L - 1;
+}
+
+// red+black sweeps that relax the level a cycle stops at
+int stop_sweeps(const hipib_ctx* ctx, int lc) {
+    if (lc == ctx->L - 1) return ctx->cfg.mg_coarse_sweeps;
+    return ctx->cfg.mg_pre > 1 ? ctx->cfg.mg_pre : 1;
+}
+
 hipib_status finalize(hipib_ctx* ctx, int64_t nparts, int64_t pstride, int ncomp, int mode,
                       double inv_count) {
     k_finalize<<<1, 1024, 0, ctx->stream>>>(ctx->part, nparts, pstride, ncomp, mode, ctx->st,
@@ -1315,9 +1366,11 @@ template <typename T>
 hipib_status small_vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef& oc,
                           bool zero_init) {
     SmallArgs<T> A{};
+    const int lc = stop_level(ctx, oc);
     A.pre = ctx->cfg.mg_pre;
     A.post = ctx->cfg.mg_post;
-    A.sweeps = ctx->cfg.mg_coarse_sweeps;
+    A.sweeps = stop_sweeps(ctx, lc);
+    A.depth = lc - l;
     A.poisson = oc.poisson;
     A.zero_init = zero_init ? 1 : 0;
     A.sigma = (T)oc.sigma;
@@ -1402,6 +1455,8 @@ hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
     const T h = T(1) / T(n);
     const T c = (T)oc.nu / (h * h);
     const int pre = ctx->cfg.mg_pre, post = ctx->cfg.mg_post;
+    const int lc = stop_level(ctx, oc);
+    if (l == lc) return smooth<T>(ctx, l, p, ncomp, oc, stop_sweeps(ctx, lc), 0, zero_guess);
     if (zero_guess && level_fused(ctx, l)) {
         const T inv_diag = T(1) / ((T)oc.sigma + T(6) * c);
         const Level& C = ctx->lv[l + 1];
@@ -1535,15 +1590,30 @@ hipib_status mg_prepare(hipib_ctx* ctx) {
     for (int l = ctx->small_start; l < ctx->L; ++l) lds += 3 * (size_t)ctx->lv[l].n3 * tsz;
     ctx->small_lds = lds;
     if (lds > 160 * 1024) return fail(HIPIB_E_INVAL, "coarse levels need %zu bytes of LDS", lds);
-    const void* ks[] = {
-        reinterpret_cast<const void*>(&k_small_vcycle<16, double>),
-        reinterpret_cast<const void*>(&k_small_vcycle<12, double>),
-        reinterpret_cast<const void*>(&k_small_vcycle<8, double>),
-        reinterpret_cast<const void*>(&k_small_vcycle<16, float>),
-        reinterpret_cast<const void*>(&k_small_vcycle<12, float>),
-        reinterpret_cast<const void*>(&k_small_vcycle<8, float>)};
-    for (const void* k : ks)
-        HIPIB_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    // The attribute belongs to the kernel, not to a context: each instantiation
+    // gets the LDS of its own level chain ([x, b, r] per level), so contexts
+    // of other sizes or precisions never lower what another one launches with.
+    struct SmallKernel {
+        const void* fn;
+        int bytes;
+    };
+    auto chain = [](int n0, int esz) {
+        int cells = 0;
+        for (int m = n0;; m /= 2) {
+            cells += m * m * m;
+            if (m < 8) break;
+        }
+        return 3 * cells * esz;
+    };
+    const SmallKernel ks[] = {
+        {reinterpret_cast<const void*>(&k_small_vcycle<16, double>), chain(16, 8)},
+        {reinterpret_cast<const void*>(&k_small_vcycle<12, double>), chain(12, 8)},
+        {reinterpret_cast<const void*>(&k_small_vcycle<8, double>), chain(8, 8)},
+        {reinterpret_cast<const void*>(&k_small_vcycle<16, float>), chain(16, 4)},
+        {reinterpret_cast<const void*>(&k_small_vcycle<12, float>), chain(12, 4)},
+        {reinterpret_cast<const void*>(&k_small_vcycle<8, float>), chain(8, 4)}};
+    for (const SmallKernel& k : ks)
+        HIPIB_HIP(hipFuncSetAttribute(k.fn, hipFuncAttributeMaxDynamicSharedMemorySize, k.bytes));
     return HIPIB_OK;
 }
 

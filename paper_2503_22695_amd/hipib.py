@@ -84,6 +84,7 @@ def lib():
             "hipib_advance": (st, [P, P, P, P, f64, i32, f64, f64]),
             "hipib_get_step_stats": (i32, [P, P, P, i32]),
             "hipib_adjoint_step": (st, [P, P, P, P, f64, P, P, P]),
+            "hipib_adjoint_reset": (st, [P]),
             "hipib_fe_hvp": (st, [P, P, P, P]),
             "hipib_fe_param_vjp": (st, [P, P, P, P]),
             "hipib_spread_vjp_X": (st, [P, P, P, P, P]),
@@ -267,6 +268,10 @@ class Context:
                                         _dev(dtheta, (MAX_MATERIALS, 4), "dtheta")),
                "hipib_adjoint_step")
 
+    def adjoint_reset(self):
+        """Zero the starting points of the reverse step's adjoint solves."""
+        _check(lib().hipib_adjoint_reset(self._h), "hipib_adjoint_reset")
+
     def fe_hvp(self, X, V, HV=None):
         import torch
         if HV is None:
@@ -403,7 +408,7 @@ class Rollout:
         self.u0 = torch.tensor(prob.initial_velocity(), dtype=torch.float64, device=self.dev)
         self.kappa = float(prob.materials[mat].params[4])
         self.sheet_params = [float(v) for v in prob.materials[mat].params[5:]]
-        self.checkpoints = []
+        self.last_tape = None
 
     def pressure(self, s0: int, i: int) -> float:
         """Cavity pressure at step s0 + i, with the time rounded exactly as
@@ -433,26 +438,30 @@ class Rollout:
         """X^N from X0.  With keep_checkpoints, (u, p, X) is stored at the start
         of every segment, and the states of the last segment are kept whole as
         they are computed, so the backward pass recomputes every segment but
-        the last."""
+        the last.  The stored states and theta form a RolloutTape, kept as
+        `last_tape` (and passed to backward by IBRollout); a forward pass
+        without checkpoints leaves `last_tape` as it was."""
         import torch
         self.set_theta(theta)
         u = self.u0.clone()
         p = torch.zeros((self.prob.n,) * 3, dtype=torch.float64, device=self.dev)
         X = X0.detach().to(self.dev, torch.float64).contiguous().clone()
-        self.checkpoints = []
-        self.tail = None
+        tape = RolloutTape(self._theta) if keep_checkpoints else None
         s = 0
         while s < self.n_steps:
             m = min(self.k, self.n_steps - s)
             if keep_checkpoints and s + m == self.n_steps:
-                self.tail = (s, self._run_segment(u, p, X, s, m))
-                u, X = self.tail[1][0][-1], self.tail[1][1][-1]
+                tape.tail = (s, self._run_segment(u, p, X, s, m))
+                u, X = tape.tail[1][0][-1], tape.tail[1][1][-1]
             else:
                 if keep_checkpoints:
-                    self.checkpoints.append((s, u.clone(), p.clone(), X.clone()))
+                    tape.checkpoints.append((s, u.clone(), p.clone(), X.clone()))
                 self.ctx.advance(u, p, X, self.t0 + s * self.prob.dt, m, self.prob.p0, self.prob.T)
             s += m
-        return X.clone() if keep_checkpoints else X
+        if keep_checkpoints:
+            self.last_tape = tape
+            return X.clone()
+        return X
 
     def _run_segment(self, u, p, X, s0, m):
         """m steps from (u, p, X) at step s0 (not modified); every u and X."""
@@ -483,12 +492,23 @@ class Rollout:
             Xs.append(X.clone())
         return us, Xs
 
-    def backward(self, grad_XN):
+    def backward(self, grad_XN, tape=None):
+        """dL/dtheta, dL/dX0 and dL/du0 from dL/dX^N, through the states of
+        `tape` (default: the latest forward pass with checkpoints).  The tape is
+        not consumed: the same pass can be reversed again."""
         import torch
+        tape = self.last_tape if tape is None else tape
+        if tape is None:
+            raise RuntimeError("Rollout.backward: no forward pass with checkpoints to reverse")
         lam_X = grad_XN.detach().to(self.dev, torch.float64).contiguous().clone()
         lam_u = torch.zeros_like(self.u0)
         dtheta = torch.zeros((MAX_MATERIALS, 4), dtype=torch.float64, device=self.dev)
-        segs = list(reversed(self.checkpoints))
+        # the adjoint steps and the recomputed segments use the tape's material,
+        # whatever forward passes ran since, and the adjoint solves start from
+        # zero, whatever backward passes ran before
+        self.set_theta(torch.tensor(tape.theta, dtype=torch.float64))
+        self.ctx.adjoint_reset()
+        segs = list(reversed(tape.checkpoints))
         pending = None
         if self.overlap and segs:
             from concurrent.futures import ThreadPoolExecutor
@@ -497,15 +517,13 @@ class Rollout:
                 self._rstream = torch.cuda.Stream()          # default priority
                 with torch.cuda.stream(self._rstream):
                     self._rctx = context_for_problem(self.prob, **self.cfg_over)
-            th = self._theta
-            self._rctx.set_material(self.mat, HOLZAPFEL_OGDEN, self._material(th))
+            self._rctx.set_material(self.mat, HOLZAPFEL_OGDEN, self._material(tape.theta))
             pool = ThreadPoolExecutor(max_workers=1)
             pending = pool.submit(self._recompute, segs[0])
         try:
-            if self.tail is not None:
-                s0, (us, Xs) = self.tail
+            if tape.tail is not None:
+                s0, (us, Xs) = tape.tail
                 self._reverse_segment(s0, us, Xs, lam_u, lam_X, dtheta)
-                self.tail = None
             for idx, (s0, uc, pc, Xc) in enumerate(segs):
                 if pending is not None:
                     us, Xs = pending.result()
@@ -521,6 +539,17 @@ class Rollout:
         return dtheta[self.mat].clone(), lam_X, lam_u
 
 
+class RolloutTape:
+    """What one forward pass of a Rollout leaves for its backward pass: the
+    material parameters, the checkpoints (step, u, p, X) at the start of every
+    segment but the last, and the last segment's states (step, (us, Xs))."""
+
+    def __init__(self, theta):
+        self.theta = list(theta)
+        self.checkpoints = []
+        self.tail = None
+
+
 def _ibrollout_class():
     import torch
 
@@ -533,12 +562,13 @@ def _ibrollout_class():
         def forward(fctx, theta, X0, rollout):
             XN = rollout.forward(theta, X0)
             fctx.rollout = rollout
+            fctx.tape = rollout.last_tape     # this call's states, whatever runs next
             fctx.theta_device = theta.device
             return XN
 
         @staticmethod
         def backward(fctx, grad_XN):
-            dth, dX0, _ = fctx.rollout.backward(grad_XN.contiguous())
+            dth, dX0, _ = fctx.rollout.backward(grad_XN.contiguous(), fctx.tape)
             return dth.to(fctx.theta_device), dX0, None
 
     return IBRollout

@@ -170,6 +170,42 @@ def test_checkpointed_rollout_matches_store_all_oracle(torch_dev, hp, ref):
     assert_rel("dL/dtheta", th.grad.numpy(), dthr[0], 1e-8)
 
 
+def test_rollout_backward_uses_its_own_forward_pass(torch_dev, hp):
+    """Each IBRollout call keeps its own checkpoints and material: a forward
+    probe at another theta between apply and backward (the finite-difference
+    pattern) and a second backward of a retained graph give the gradients of
+    the plain apply-then-backward order, bitwise (deterministic mode)."""
+    torch = torch_dev
+    prob = inputs.ho_block(n=32, n_el=6, n_steps=6)
+    say("rollout tape", prob.name)
+    theta = np.array(prob.materials[0].params[:4])
+    Xt = target_positions(torch, hp, prob, theta * [1.1, 0.9, 1.1, 0.9], prob.n_steps,
+                          deterministic=1)
+
+    def grads(probe, twice):
+        ro = hp.Rollout(prob, checkpoint_every=4, deterministic=1)
+        th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+        X0 = to_dev(torch, prob.X0).requires_grad_(True)
+        L = ((hp.IBRollout().apply(th, X0, ro) - Xt) ** 2).sum()
+        if probe:
+            ro.forward(torch.tensor(theta * 1.3), to_dev(torch, prob.X0) * 1.001,
+                       keep_checkpoints=False)
+        L.backward(retain_graph=twice)
+        out = [th.grad.numpy().copy(), host(X0.grad)]
+        if twice:
+            th.grad, X0.grad = None, None
+            L.backward()
+            out += [th.grad.numpy().copy(), host(X0.grad)]
+        return out
+
+    g_th, g_X = grads(False, False)
+    p_th, p_X = grads(True, False)
+    assert np.array_equal(p_th, g_th) and np.array_equal(p_X, g_X)
+    a_th, a_X, b_th, b_X = grads(False, True)
+    assert np.array_equal(a_th, g_th) and np.array_equal(a_X, g_X)
+    assert np.array_equal(b_th, g_th) and np.array_equal(b_X, g_X)
+
+
 def test_adjoint_workload_against_fourth_order_differences(torch_dev, hp, ref):
     """The adjoint workload: 64^3, 50 steps, HO block of 12^3 hexes, checkpoints
     every 10 steps; target from a forward run at theta * (1.1, 0.9, 1.1, 0.9)."""
