@@ -197,6 +197,19 @@ hipib_status hipib_set_pressure_faces(hipib_ctx* ctx, int32_t n_faces, const int
 hipib_status hipib_fe_force(hipib_ctx* ctx, const double* X, double pressure, double* F);
 /* f += S(X) F:  f^d[idx] += sum_q F^d_q delta_h(x^d_idx - X_q).  f: [3][n^3]. */
 hipib_status hipib_spread(hipib_ctx* ctx, const double* X, const double* F, double* f);
+/* hipib_spread without a context and without allocating, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): f += S(X) F on the periodic n^3
+ * grid in FP64, with the kernels of hipib_spread on an FP64 context, atomic
+ * mode.  X, F: device [n_nodes][3]; f: device [3][n^3], accumulated; stream: a
+ * hipStream_t (NULL: the null stream); nothing waits for completion.  The node
+ * bins live in a static device workspace of 13.1 MB per GPU (held until the
+ * process ends): n must be 4*2^k or 6*2^k in [8, 256] and n_nodes at most
+ * 1048576, else HIPIB_E_INVAL.  Calls that overlap on one GPU (other streams,
+ * other threads) share that workspace and race: order them.  The first call on
+ * a device looks the workspace up (HIPIB_E_HIP if that fails). */
+hipib_status hipib_spread_noalloc(int32_t n, int32_t n_nodes, const double* X, const double* F,
+                                  double* f, void* stream);
 /* U := J(X) u:  U^d_q = sum_idx u^d[idx] delta_h(x^d_idx - X_q) h^3. */
 hipib_status hipib_interpolate(hipib_ctx* ctx, const double* X, const double* u, double* U);
 /* Solves (sigma I - nu Lap_h) x = b for ncomp independent components

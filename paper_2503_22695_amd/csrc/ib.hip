@@ -17,12 +17,35 @@
 // walks the nodes in the same tile order so a wavefront gathers from a small
 // neighbourhood.  Summation order is not fixed, so results agree with a serial
 // sum to rounding.
+#include <mutex>
+
 #include "delta.h"
 
 namespace hipib {
 namespace {
 
+// ---------------------------------------------------------------------------
+// Workspace of hipib_spread_noalloc: the node bins live in one static device
+// array instead of memory the library allocates.  Limits: grids of at most
+// kNaMaxN cells per side (8^3-cell tiles: at most (kNaMaxN/8)^3 tiles; the
+// one smaller valid size that is not a multiple of 8, n = 12, has 27 tiles of
+// 4^3) and at most kNaMaxNodes nodes.  Layout in int32 words: tile counts
+// [ntiles], offsets [ntiles + 1], work list [2 * cap], list length [1], node
+// tiles [nn], node ranks [nn], node order [nn].
+// ---------------------------------------------------------------------------
+constexpr int kNaMaxN = 256;
+constexpr int kNaMaxNodes = 1 << 20;
+constexpr int64_t kNaMaxTiles = (int64_t)(kNaMaxN / 8) * (kNaMaxN / 8) * (kNaMaxN / 8);
+constexpr int64_t kNaMaxList = kNaMaxTiles + (kNaMaxNodes + kSpreadChunk - 1) / kSpreadChunk + 1;
+constexpr int64_t kNaWords = kNaMaxTiles + (kNaMaxTiles + 1) + 2 * kNaMaxList + 1 + 3 * (int64_t)kNaMaxNodes;
 
+static __device__ __align__(256) int32_t scratch[kNaWords];
+
+__global__ void __launch_bounds__(256) k_zero_i32(int32_t* __restrict__ p, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
 
 
 // tile of each node and its rank inside the tile.  Consecutive nodes of a
@@ -296,3 +319,101 @@ hipib_status launch_interpolate(hipib_ctx* ctx, const double* X, const double* u
 }
 
 }  // namespace hipib
+
+// ---------------------------------------------------------------------------
+// hipib_spread_noalloc
+// ---------------------------------------------------------------------------
+
+namespace hipib {
+namespace {
+
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mutex;
+int32_t* g_na_ptr[kNaMaxDevices] = {};   // device address of `scratch`, per device
+
+// Device address of this device's copy of `scratch`, looked up on the first
+// call on each device (with that device current).  Host code never passes the
+// array's own name to a kernel: on the host it is only a stand-in.
+hipib_status noalloc_scratch(int32_t** out) {
+    hipib_ctx* ctx = nullptr;   // (no context to mark broken)
+    int dev = 0;
+    HIPIB_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNaMaxDevices) return fail(HIPIB_E_INVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_na_mutex);
+    if (!g_na_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            return fail(HIPIB_E_HIP, "hipGetSymbolAddress(scratch) failed on device %d: HIP error %d",
+                        dev, (int)e);
+        }
+        g_na_ptr[dev] = static_cast<int32_t*>(p);
+    }
+    *out = g_na_ptr[dev];
+    return HIPIB_OK;
+}
+
+}  // namespace
+
+}  // namespace hipib
+
+using namespace hipib;
+
+hipib_status hipib_spread_noalloc(int32_t n, int32_t n_nodes, const double* X, const double* F,
+                                  double* f, void* stream) {
+    hipib_ctx* ctx = nullptr;   // (no context to mark broken)
+    if (n < 8 || n > kNaMaxN)
+        return fail(HIPIB_E_INVAL, "hipib_spread_noalloc: n = %d outside [8, %d]", n, kNaMaxN);
+    {
+        int m = n;
+        while (m >= 8) {
+            if (m % 2) return fail(HIPIB_E_INVAL, "hipib_spread_noalloc: n = %d is not 4*2^k or 6*2^k", n);
+            m /= 2;
+        }
+        if (m != 4 && m != 6)
+            return fail(HIPIB_E_INVAL, "hipib_spread_noalloc: n = %d is not 4*2^k or 6*2^k", n);
+    }
+    if (n_nodes < 0 || n_nodes > kNaMaxNodes)
+        return fail(HIPIB_E_INVAL, "hipib_spread_noalloc: n_nodes = %d outside [0, %d]", n_nodes,
+                    kNaMaxNodes);
+    if (f == nullptr || (reinterpret_cast<uintptr_t>(f) & 7u) ||
+        (n_nodes > 0 && (X == nullptr || F == nullptr || (reinterpret_cast<uintptr_t>(X) & 7u) ||
+                         (reinterpret_cast<uintptr_t>(F) & 7u))))
+        return fail(HIPIB_E_INVAL, "hipib_spread_noalloc: bad pointer");
+    if (n_nodes == 0) return HIPIB_OK;
+    int32_t* base = nullptr;
+    HIPIB_TRY(noalloc_scratch(&base));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int T = (n % 8 == 0) ? 8 : 4;
+    const int ta = n / T;
+    const int64_t ntiles = (int64_t)ta * ta * ta;
+    const int64_t cap = spread_list_cap(ntiles, n_nodes);
+    int32_t* count = base;
+    int32_t* off = count + ntiles;
+    int32_t* list = off + ntiles + 1;
+    int32_t* nlist = list + 2 * cap;
+    int32_t* node_tile = nlist + 1;
+    int32_t* node_rank = node_tile + n_nodes;
+    int32_t* perm = node_rank + n_nodes;
+    if (perm + n_nodes > base + kNaWords)
+        return fail(HIPIB_E_INVAL, "hipib_spread_noalloc: workspace exceeds its %lld words",
+                    (long long)kNaWords);
+    const double h = 1.0 / n;
+    const int nb = (n_nodes + 255) / 256;
+    // the tile counts start at zero (a fill kernel, so the call can be captured in a graph)
+    k_zero_i32<<<(unsigned)((ntiles + 255) / 256), 256, 0, st>>>(count, ntiles);
+    k_bin_count<<<nb, 256, 0, st>>>(X, n_nodes, n, T, ta, 1.0 / h, node_tile, node_rank, count);
+    k_bin_scan<<<1, 1024, 0, st>>>(count, ntiles, off, list, nlist);
+    k_bin_scatter<<<nb, 256, 0, st>>>(node_tile, node_rank, off, perm, n_nodes);
+    const int blocks = (int)(cap < 8192 ? cap : 8192);
+    const int64_t n3 = (int64_t)n * n * n;
+    if (T == 8)
+        k_spread_tiles<8, double><<<blocks, kSpreadChunk, 0, st>>>(X, F, f, perm, off, list, nlist, n, ta,
+                                                                   n3, 1.0 / h, 1.0 / (h * h * h));
+    else
+        k_spread_tiles<4, double><<<blocks, kSpreadChunk, 0, st>>>(X, F, f, perm, off, list, nlist, n, ta,
+                                                                   n3, 1.0 / h, 1.0 / (h * h * h));
+    HIPIB_HIP(hipGetLastError());
+    return HIPIB_OK;
+}

@@ -77,6 +77,7 @@ def lib():
             "hipib_set_active_waveform": (st, [P, f64, f64, f64]),
             "hipib_fe_force": (st, [P, P, f64, P]),
             "hipib_spread": (st, [P, P, P, P]),
+            "hipib_spread_noalloc": (st, [i32, i32, P, P, P, P]),
             "hipib_interpolate": (st, [P, P, P, P]),
             "hipib_mg_solve": (st, [P, i32, i32, P, P, P, P]),
             "hipib_ns_step": (st, [P, P, P, P]),
@@ -352,6 +353,16 @@ def context_for_problem(prob, **over) -> Context:
     if prob.ta_max:
         ctx.set_active_waveform(prob.ta_max, prob.ta_t_on, prob.ta_duration)
     return ctx
+
+
+def spread_noalloc(n: int, X, F, f):
+    """f += S(X) F on the periodic n^3 grid (FP64), hipib_spread_noalloc: no
+    context, no allocation; X, F [n_nodes, 3] and f [3, n, n, n] device float64,
+    on the current stream."""
+    nn = int(X.shape[0]) if X.dim() == 2 else 0
+    _check(lib().hipib_spread_noalloc(int(n), nn, _dev(X, (nn, 3), "X"), _dev(F, (nn, 3), "F"),
+                                      _dev(f, (3, n, n, n), "f"), _stream_ptr()),
+           "hipib_spread_noalloc")
 
 
 def active_tension(ta_max: float, t_on: float, duration: float, t: float) -> float:
