@@ -15,7 +15,7 @@ level red/black Gauss-Seidel sweep of the Poisson solve), timed with a HIP
 event pair around each of its launches, on the launch stream, during a second
 pass of --roofline-steps steps (events between launches would slow the timed
 region itself).  `cpu_baseline` is the FP64 CPU
-checker timed on this host on a bounded sample of the same workload.
+oracle timed on this host on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -42,7 +42,7 @@ def cpu_threads() -> int:
 
 
 def cpu_baseline(prob, seconds: float):
-    """The CPU checker as it stands, timed on consecutive steps of the same
+    """The CPU oracle as it stands, timed on consecutive steps of the same
     workload from its initial state until `seconds` have elapsed."""
     import numpy as np
     import oracle

@@ -4,7 +4,7 @@ This module builds problem descriptions only: grid size and fluid constants,
 hexahedral Lagrangian meshes, fibre fields, material records, endocardial
 pressure faces and initial velocity fields.  It contains none of the method's
 arithmetic (no delta kernel, no finite-element force, no solver), so both the
-GPU library and the independent CPU checker can take their inputs from here.
+GPU library and the independent CPU oracle can take their inputs from here.
 
 Geometry follows the paper's cardiac workloads in shape and size only (the
 image-based left ventricle and valve meshes are not available):
