@@ -626,19 +626,37 @@ void ibref_pressure_load(int32_t n_faces, const int32_t* faces, const double* x,
  *   prolongation: cell-centred trilinear (3/4, 1/4 per axis), added to x;
  *   coarse operators rediscretised at 2h; the coarsest level is the first
  *   with fewer than 8 cells per side, solved by mg_coarse_sweeps red+black
- *   sweeps, except for the Helmholtz operator (sigma > 0), whose hierarchy
- *   stops at the first level l >= 1 where sigma >= 4 (6 nu / h_l^2) (diagonal
- *   dominance by a factor of four: there Gauss-Seidel alone damps every error
- *   component, so deeper levels add nothing to the cycle's contraction);
- *   that level is relaxed by max(mg_pre, 1) red+black sweeps from zero;
+ *   sweeps;
  *   Poisson (sigma = 0): the mean is removed after the coarse solve
  *   and once from the final solution (the residual and the sweeps are
  *   invariant to adding a constant, so the iterates need no mean removal).
+ * The Helmholtz operator (sigma > 0): on a level of spacing h its Jacobi
+ * iteration matrix has spectral radius rho = 6c / (sigma + 6c), c = nu / h^2
+ * (the constant mode; the periodic operator is symmetric with a constant
+ * diagonal, so the Jacobi eigenvalues are real in [-rho, rho]), and red-black
+ * ordering is consistently ordered, so over-relaxation by Young's factor
+ * omega = 2 / (1 + sqrt(1 - rho^2)) contracts every error component by
+ * omega - 1 per red+black sweep.  Where rho <= 1/2 (sigma >= 6 nu / h^2) that
+ * is at most 0.072 per sweep, and a coarse-grid correction adds nothing (a
+ * two-level cycle contracts less per sweep than the sweeps alone).  So the
+ * Helmholtz hierarchy stops at the first level l >= 0 with rho_l <= 1/2 (or
+ * at the coarsest), and that level is relaxed by red+black sweeps
+ * over-relaxed by its omega_l:
+ *   l = 0: the cycle is mg_pre + mg_post sweeps on the current iterate, each
+ *     red then black (one ordering throughout: reversing it, as the V-cycle's
+ *     post-smoothing does, repeats a colour and loses the SOR rate);
+ *   0 < l < coarsest: max(mg_pre, 1) sweeps (red, black) from zero;
+ *   the coarsest: mg_coarse_sweeps sweeps from zero.
+ * The other Helmholtz levels and every Poisson level keep plain Gauss-Seidel
+ * (omega = 1).
  * Stop rule: ||b - A x||_2 <= max(rtol, 1e3 eps) ||b||_2, tested before the
  * first cycle and after every cycle; ||b|| = 0 gives x = 0.
  */
 
-static void gs_colour(int n, double sigma, double nu, const double* b, double* x, int colour) {
+/* one colour of red-black Gauss-Seidel, over-relaxed by omega when omega != 1:
+ * x <- x + omega ((b + c * neighbour sum) / diag - x) */
+static void gs_colour(int n, double sigma, double nu, const double* b, double* x, int colour,
+                      double omega) {
     const double h = 1.0 / n, c = nu / (h * h), diag = sigma + 6.0 * c;
 #pragma omp parallel for
     for (int k = 0; k < n; ++k)
@@ -647,8 +665,22 @@ static void gs_colour(int n, double sigma, double nu, const double* b, double* x
                 double s = x[gidx(i + 1, j, k, n)] + x[gidx(i - 1, j, k, n)] +
                            x[gidx(i, j + 1, k, n)] + x[gidx(i, j - 1, k, n)] +
                            x[gidx(i, j, k + 1, n)] + x[gidx(i, j, k - 1, n)];
-                x[gidx(i, j, k, n)] = (b[gidx(i, j, k, n)] + c * s) / diag;
+                const double xg = (b[gidx(i, j, k, n)] + c * s) / diag;
+                if (omega == 1.0) {
+                    x[gidx(i, j, k, n)] = xg;
+                } else {
+                    const double xo = x[gidx(i, j, k, n)];
+                    x[gidx(i, j, k, n)] = xo + omega * (xg - xo);
+                }
             }
+}
+
+/* Young's over-relaxation factor of a Helmholtz level (1 for Poisson) */
+static double level_omega(int n, double sigma, double nu) {
+    if (!(sigma > 0.0)) return 1.0;
+    const double h = 1.0 / n, c = nu / (h * h);
+    const double rho = 6.0 * c / (sigma + 6.0 * c);
+    return 2.0 / (1.0 + sqrt(1.0 - rho * rho));
 }
 
 /* r = b - (sigma x - nu Lap_h x) */
@@ -758,9 +790,9 @@ static void mg_free(mg_levels* lv) {
 /* the level at which the cycle stops descending (see above) */
 static int coarsest_level(const mg_levels* lv, double sigma, double nu) {
     if (sigma > 0.0)
-        for (int l = 1; l < lv->L - 1; ++l) {
+        for (int l = 0; l < lv->L - 1; ++l) {
             const double h = 1.0 / lv->n[l];
-            if (sigma >= 4.0 * (6.0 * nu / (h * h))) return l;
+            if (sigma >= 6.0 * nu / (h * h)) return l;
         }
     return lv->L - 1;
 }
@@ -771,17 +803,25 @@ static void vcycle(const ibref_fluid* fl, mg_levels* lv, int l, double sigma, do
     long N3 = (long)n * n * n;
     const int lc = coarsest_level(lv, sigma, nu);
     if (l == lc) {
+        const double w = level_omega(n, sigma, nu);
+        if (l == 0 && lc < lv->L - 1) {
+            for (int s = 0; s < fl->mg_pre + fl->mg_post; ++s) {
+                gs_colour(n, sigma, nu, b, x, 0, w);
+                gs_colour(n, sigma, nu, b, x, 1, w);
+            }
+            return;
+        }
         const int sweeps = lc == lv->L - 1 ? fl->mg_coarse_sweeps : (fl->mg_pre > 1 ? fl->mg_pre : 1);
         for (int s = 0; s < sweeps; ++s) {
-            gs_colour(n, sigma, nu, b, x, 0);
-            gs_colour(n, sigma, nu, b, x, 1);
+            gs_colour(n, sigma, nu, b, x, 0, w);
+            gs_colour(n, sigma, nu, b, x, 1, w);
         }
         if (poisson) remove_mean(N3, x);
         return;
     }
     for (int s = 0; s < fl->mg_pre; ++s) {
-        gs_colour(n, sigma, nu, b, x, 0);
-        gs_colour(n, sigma, nu, b, x, 1);
+        gs_colour(n, sigma, nu, b, x, 0, 1.0);
+        gs_colour(n, sigma, nu, b, x, 1, 1.0);
     }
     residual(n, sigma, nu, b, x, lv->r[l]);
     restrict_fw(n, lv->r[l], lv->b[l + 1]);
@@ -790,8 +830,8 @@ static void vcycle(const ibref_fluid* fl, mg_levels* lv, int l, double sigma, do
     vcycle(fl, lv, l + 1, sigma, nu, poisson, lv->b[l + 1], lv->x[l + 1]);
     prolong_add(n, lv->x[l + 1], x);
     for (int s = 0; s < fl->mg_post; ++s) {
-        gs_colour(n, sigma, nu, b, x, 1);
-        gs_colour(n, sigma, nu, b, x, 0);
+        gs_colour(n, sigma, nu, b, x, 1, 1.0);
+        gs_colour(n, sigma, nu, b, x, 0, 1.0);
     }
 }
 

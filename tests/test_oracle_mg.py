@@ -145,3 +145,57 @@ def test_krylov_needs_fewer_cycles_than_the_plain_iteration(ref):
     x, k_cg, rr = ref.mg_solve(ref.fluid(n, krylov=1), 0.0, 1.0, True, b)
     assert rr <= 1e-10
     assert k_cg <= 0.7 * k_plain, (k_cg, k_plain)
+
+
+def young_omega(n, sigma, nu):
+    c = nu * n * n
+    rho = 6 * c / (sigma + 6 * c)
+    return rho, 2.0 / (1.0 + math.sqrt(1.0 - rho * rho))
+
+
+def test_helmholtz_relaxation_rate_is_youngs():
+    """Where the Helmholtz operator's Jacobi radius rho = 6c / (sigma + 6c) is at
+    most 1/2, its cycle is the red-black relaxation over-relaxed by Young's
+    omega, which contracts the error by omega - 1 per sweep (up to a factor
+    linear in the sweep count: the optimal SOR matrix is defective).  A cycle
+    here is V(2,2) without coarse levels: four sweeps.  The ratio of 128^3 at
+    dt = 5e-4 (sigma / 6c = 2.03) on a 32^3 grid."""
+    import oracle
+    n, nu = 32, 0.01
+    sigma = 2000.0 / 983.04 * 6 * nu * n * n
+    rho, w = young_omega(n, sigma, nu)
+    assert rho <= 0.5
+    rng = np.random.default_rng(7)
+    b = rng.standard_normal((n, n, n))
+    for k in (1, 2):
+        _, cyc, r = oracle.mg_solve(oracle.fluid(n, fixed_cycles=k, krylov=0), sigma, nu, False, b)
+        assert cyc == k
+        sweeps = 4 * k
+        assert r <= 2.0 * sweeps * (w - 1.0) ** sweeps, (k, r, (w - 1.0) ** sweeps)
+    # plain Gauss-Seidel (omega = 1) could not do this: its rate is rho^2 per sweep
+    assert 2.0 * 8 * (w - 1.0) ** 8 < (rho * rho) ** 8 * 1e-2
+
+
+def test_helmholtz_relaxation_matches_numpy_sor():
+    """One cycle at a level-0 stop equals red-black SOR written with numpy:
+    four sweeps (V(2,2): pre + post), each red then black, each colour
+    x += omega ((b + c * neighbour sum) / diag - x)."""
+    import oracle
+    n, nu, sigma = 16, 0.01, 50.0
+    rho, w = young_omega(n, sigma, nu)
+    assert rho <= 0.5
+    rng = np.random.default_rng(8)
+    b = rng.standard_normal((n, n, n))
+    x0 = rng.standard_normal((n, n, n))
+    x, cyc, _ = oracle.mg_solve(oracle.fluid(n, fixed_cycles=1, krylov=0), sigma, nu, False, b, x0)
+    assert cyc == 1
+    c = nu * n * n
+    diag = sigma + 6 * c
+    I, J, K = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    red = (I + J + K) % 2 == 0
+    y = x0.copy()
+    for mask in (red, ~red) * 4:
+        s = sum(np.roll(y, sh, ax) for ax in range(3) for sh in (1, -1))
+        g = (b + c * s) / diag
+        y[mask] = y[mask] + w * (g[mask] - y[mask])
+    assert np.max(np.abs(x - y)) <= 1e-13 * np.max(np.abs(y))
