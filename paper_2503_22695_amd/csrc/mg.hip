@@ -9,6 +9,10 @@
 //   number of red+black sweeps, Poisson means removed after the coarse solve
 //   and once from the final solution (residual and sweeps are invariant to a
 //   constant shift).  Stop: ||r||_2 <= max(rtol, 1e3 eps) ||b||_2.
+//   The Helmholtz hierarchy stops where the operator's Jacobi radius is at most
+//   1/2 (see stop_level), and that level is relaxed by red-black SOR with
+//   Young's factor; when that is the finest level, a cycle is pre + post such
+//   sweeps on the iterate.
 //
 // Storage: every solver array is kept in a packed red-black layout.  For a
 // level of n cells per side (n even) and H = n/2, component c, colour
@@ -37,6 +41,7 @@
 // on the device; the host enqueues the predicted number of cycles and waits
 // once to read them.
 #include <cfloat>
+#include <cmath>
 
 #include <hip/hip_ext.h>
 
@@ -128,6 +133,8 @@ k_unpack(const double* __restrict__ src, double* __restrict__ dst, int n, int64_
 // order i+1, i-1, j+1, j-1, k+1, k-1.
 // zg: the other colour is known to be zero (first half-sweep from a zero
 // guess), so its neighbours are not read; the result is the same to the bit.
+// SOR: over-relaxation, x_q += omega (x_gs - x_q), which also reads the cell's
+// own old value (16 B/cell in FP64 instead of 12) unless zo says it is zero.
 // TAG only separates launches in profiles: 0 coarse levels, 1 finest level of
 // a Helmholtz solve, 2 finest level of a Poisson solve.
 constexpr int KPT = 4;  // column length of the residual norm
@@ -144,10 +151,10 @@ dim3 gs_grid(int n, int ncomp) {
     return dim3((n / 2 + TX - 1) / TX, (n + TY - 1) / TY, ((n + K - 1) / K) * ncomp);
 }
 
-template <typename T, int TAG>
+template <typename T, int TAG, bool SOR = false>
 __global__ void __launch_bounds__(TX * TY)
 k_gs(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, T c, T inv_diag, int q,
-     int zg, const int32_t* __restrict__ active) {
+     int zg, const int32_t* __restrict__ active, T omega = T(1), int zo = 0) {
     constexpr int KPT = gs_kpt<T>();
     const uint3 bid = xcd_block();
     const int nkb = (n + KPT - 1) / KPT;
@@ -162,7 +169,7 @@ k_gs(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, T c, T inv_d
     const T* bq = b + comp * cs + q * half3;
     const int jp = wrapi(j + 1, n), jm = wrapi(j - 1, n);
     const int ihp = ih + 1 < H ? ih + 1 : 0, ihm = ih > 0 ? ih - 1 : H - 1;
-    T col[KPT + 2], side[KPT], yp[KPT], ym[KPT], bv[KPT];
+    T col[KPT + 2], side[KPT], yp[KPT], ym[KPT], bv[KPT], xold[KPT];
     if (!zg) {
 #pragma unroll
         for (int r = 0; r < KPT + 2; ++r) {
@@ -176,6 +183,7 @@ k_gs(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, T c, T inv_d
         if (k < n) {
             const int64_t row = (int64_t)H * ((int64_t)j + (int64_t)n * k);
             bv[r] = bq[row + ih];
+            if (SOR) xold[r] = zo ? T(0) : xq[row + ih];
             if (!zg) {
                 const int p = (j + k + q) & 1;
                 side[r] = xo[row + (p ? ihp : ihm)];
@@ -196,7 +204,9 @@ k_gs(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, T c, T inv_d
                 const T a_im = p ? col[r + 1] : side[r];
                 s = a_ip + a_im + yp[r] + ym[r] + col[r + 2] + col[r];
             }
-            xq[(int64_t)H * ((int64_t)j + (int64_t)n * k) + ih] = (bv[r] + c * s) * inv_diag;
+            const T xg = (bv[r] + c * s) * inv_diag;
+            xq[(int64_t)H * ((int64_t)j + (int64_t)n * k) + ih] =
+                SOR ? xold[r] + omega * (xg - xold[r]) : xg;
         }
     }
 }
@@ -779,6 +789,7 @@ struct SmallArgs {
     int pre, post, sweeps, poisson, zero_init;
     int depth;   // levels below N0 the cycle descends (the last one relaxed by `sweeps`)
     T sigma, nu;
+    T omega;     // over-relaxation of the level the cycle stops at (1: Gauss-Seidel)
 };
 
 template <int N>
@@ -812,17 +823,25 @@ __device__ __forceinline__ T s_nbr(const T* xo, int ih, int j, int k, int q) {
            xo[H * (j + N * wrapc<N>(k - 1)) + ih];
 }
 
-// colour-q half-sweep over packed cells t0, t0 + nt, ...; zg: the other colour is zero
+// colour-q half-sweep over packed cells t0, t0 + nt, ...; zg: the other colour
+// is zero; omega != 1: over-relaxed, x += omega (x_gs - x), with the cell's own
+// old value taken as zero when zo
 template <int N, typename T>
 __device__ __forceinline__ void s_gs(T* x, const T* b, T c, T inv_diag, int q, int t0, int nt,
-                                     bool zg = false) {
+                                     bool zg = false, T omega = T(1), bool zo = false) {
     constexpr int H = N / 2, HALF = H * N * N;
     const T* xo = x + (1 - q) * HALF;
     for (int t = t0; t < HALF; t += nt) {
         const int ih = t % H, rest = t / H;
         const int j = rest % N, k = rest / N;
         const T s = zg ? T(0) : s_nbr<N>(xo, ih, j, k, q);
-        x[q * HALF + t] = (b[q * HALF + t] + c * s) * inv_diag;
+        const T xg = (b[q * HALF + t] + c * s) * inv_diag;
+        if (omega == T(1)) {
+            x[q * HALF + t] = xg;
+        } else {
+            const T xq = zo ? T(0) : x[q * HALF + t];
+            x[q * HALF + t] = xq + omega * (xg - xq);
+        }
     }
 }
 
@@ -911,9 +930,9 @@ __device__ __forceinline__ void s_coarse_wave(T* x, const T* b, const SmallArgs<
         for (int o = lane; o < CNT; o += 64) x[o] = T(0);
     wave_sync();
     for (int s = 0; s < A.sweeps; ++s) {
-        s_gs<N>(x, b, c, inv_diag, 0, lane, 64, s == 0);
+        s_gs<N>(x, b, c, inv_diag, 0, lane, 64, s == 0, A.omega, s == 0);
         wave_sync();
-        s_gs<N>(x, b, c, inv_diag, 1, lane, 64);
+        s_gs<N>(x, b, c, inv_diag, 1, lane, 64, false, A.omega, s == 0);
         wave_sync();
     }
     if (A.poisson) {
@@ -974,9 +993,10 @@ __device__ __forceinline__ void s_relax(T* x, const T* b, const SmallArgs<T>& A,
     T c, inv_diag;
     level_coef<N>(A, c, inv_diag);
     for (int s = 0; s < A.sweeps; ++s) {
-        s_gs<N>(x, b, c, inv_diag, 0, threadIdx.x, blockDim.x, zero && s == 0);
+        const bool z = zero && s == 0;
+        s_gs<N>(x, b, c, inv_diag, 0, threadIdx.x, blockDim.x, z, A.omega, z);
         __syncthreads();
-        s_gs<N>(x, b, c, inv_diag, 1, threadIdx.x, blockDim.x);
+        s_gs<N>(x, b, c, inv_diag, 1, threadIdx.x, blockDim.x, false, A.omega, z);
         __syncthreads();
     }
 }
@@ -1307,27 +1327,42 @@ OpCoef op_coef(const hipib_ctx* ctx, int op) {
     return {ctx->cfg.rho / ctx->cfg.dt, ctx->cfg.mu, 0};
 }
 
-// The level at which a cycle stops descending.  For the Helmholtz operator
-// (sigma > 0) the hierarchy ends at the first level l >= 1 where
-// sigma >= 4 (6 nu / h_l^2): there the operator is diagonally dominant by a
-// factor of four, red-black Gauss-Seidel alone damps every error component,
-// and deeper levels add nothing to the cycle's contraction.  That level is
-// relaxed by max(pre, 1) red+black sweeps from zero.  Otherwise (and for
-// Poisson) the coarsest level is the first with fewer than 8 cells per side,
-// relaxed by the coarse sweeps.
+// The level at which a cycle stops descending.  On a level of spacing h the
+// Helmholtz operator's Jacobi iteration has spectral radius
+// rho = 6c / (sigma + 6c), c = nu / h^2 (the constant mode of the periodic
+// operator, whose Jacobi spectrum is real), and red-black ordering is
+// consistently ordered, so red-black SOR with Young's factor
+// omega = 2 / (1 + sqrt(1 - rho^2)) contracts every error component by
+// omega - 1 per sweep.  The Helmholtz hierarchy stops at the first level
+// l >= 0 with rho_l <= 1/2 (sigma >= 6 nu / h_l^2: at most 0.072 per sweep;
+// a coarse-grid correction adds less than its sweeps would), relaxed there
+// with that level's omega.  Otherwise (and for Poisson) the coarsest level
+// is the first with fewer than 8 cells per side.
 int stop_level(const hipib_ctx* ctx, const OpCoef& oc) {
     if (oc.sigma > 0.0)
-        for (int l = 1; l < ctx->L - 1; ++l) {
+        for (int l = 0; l < ctx->L - 1; ++l) {
             const double h = 1.0 / ctx->lv[l].n;
-            if (oc.sigma >= 4.0 * (6.0 * oc.nu / (h * h))) return l;
+            if (oc.sigma >= 6.0 * oc.nu / (h * h)) return l;
         }
     return ctx->L - 1;
 }
 
-// red+black sweeps that relax the level a cycle stops at
+// red+black sweeps that relax the level a cycle stops at: the coarse sweeps
+// on the coarsest level, pre + post sweeps on the iterate when the finest
+// level is the stop (the cycle has no coarse levels), else max(pre, 1) from
+// zero
 int stop_sweeps(const hipib_ctx* ctx, int lc) {
     if (lc == ctx->L - 1) return ctx->cfg.mg_coarse_sweeps;
+    if (lc == 0) return ctx->cfg.mg_pre + ctx->cfg.mg_post;
     return ctx->cfg.mg_pre > 1 ? ctx->cfg.mg_pre : 1;
+}
+
+// Young's over-relaxation factor of a Helmholtz level (1 for Poisson)
+double level_omega(int n, const OpCoef& oc) {
+    if (!(oc.sigma > 0.0)) return 1.0;
+    const double h = 1.0 / n, c = oc.nu / (h * h);
+    const double rho = 6.0 * c / (oc.sigma + 6.0 * c);
+    return 2.0 / (1.0 + std::sqrt(1.0 - rho * rho));
 }
 
 hipib_status finalize(hipib_ctx* ctx, int64_t nparts, int64_t pstride, int ncomp, int mode,
@@ -1371,6 +1406,7 @@ hipib_status small_vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const
     A.post = ctx->cfg.mg_post;
     A.sweeps = stop_sweeps(ctx, lc);
     A.depth = lc - l;
+    A.omega = (T)level_omega(ctx->lv[lc].n, oc);
     A.poisson = oc.poisson;
     A.zero_init = zero_init ? 1 : 0;
     A.sigma = (T)oc.sigma;
@@ -1415,11 +1451,38 @@ hipib_status gs_sweep(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpC
         // (only the 12 B/cell half-sweeps; a zero-guess first half-sweep moves 8)
         // the events take the dispatch's own start and end timestamps
         hipExtLaunchKernelGGL(k_gs<T, 2>, grid, blk, 0, ctx->stream, t0, t1, 0, p.x, p.b, n, p.cs, c,
-                              inv_diag, colour, zg, act);
+                              inv_diag, colour, zg, act, T(1), 0);
     } else {
         k_gs<T, 2><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, colour, zg, act);
     }
     HIPIB_HIP(hipGetLastError());
+    return HIPIB_OK;
+}
+
+// `sweeps` red+black sweeps, each red then black, over-relaxed by omega: the
+// relaxation of the level a Helmholtz cycle stops at.  zero_guess: x is zero
+// on entry (the first red half-sweep reads neither colour, the first black
+// one not its own).
+template <typename T>
+hipib_status relax(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef& oc, int sweeps,
+                   bool zero_guess, double omega) {
+    const int n = ctx->lv[l].n;
+    const T h = T(1) / T(n);
+    const T c = (T)oc.nu / (h * h);
+    const T inv_diag = T(1) / ((T)oc.sigma + T(6) * c);
+    const int32_t* act = ctx->st->active;
+    const dim3 grid = gs_grid<T>(n, ncomp), blk(TX, TY);
+    for (int s = 0; s < 2 * sweeps; ++s) {
+        const int zg = (s == 0 && zero_guess) ? 1 : 0;
+        const int zo = (s < 2 && zero_guess) ? 1 : 0;
+        if (l == 0)
+            k_gs<T, 1, true><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, s & 1, zg, act,
+                                                           (T)omega, zo);
+        else
+            k_gs<T, 0, true><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, s & 1, zg, act,
+                                                           (T)omega, zo);
+        HIPIB_HIP(hipGetLastError());
+    }
     return HIPIB_OK;
 }
 
@@ -1456,7 +1519,8 @@ hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
     const T c = (T)oc.nu / (h * h);
     const int pre = ctx->cfg.mg_pre, post = ctx->cfg.mg_post;
     const int lc = stop_level(ctx, oc);
-    if (l == lc) return smooth<T>(ctx, l, p, ncomp, oc, stop_sweeps(ctx, lc), 0, zero_guess);
+    if (l == lc) return relax<T>(ctx, l, p, ncomp, oc, stop_sweeps(ctx, lc), zero_guess,
+                                 level_omega(n, oc));
     if (zero_guess && level_fused(ctx, l)) {
         const T inv_diag = T(1) / ((T)oc.sigma + T(6) * c);
         const Level& C = ctx->lv[l + 1];
