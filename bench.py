@@ -297,7 +297,7 @@ def main():
         mixed = {
             "value": round(args.steps / melapsed, 3), "unit": "steps/s",
             "ms_per_step": round(1e3 * melapsed / args.steps, 4),
-            "dtype": "f32 V-cycles, spread weights and interpolation; f64 FE force, outer residual and updates",
+            "dtype": "f32 V-cycles, element stresses (displacement form), spread weights and interpolation; f64 outer residual, CG vectors and updates",
             "error_vs_fp64_path": {
                 "e_u": rel(msim.u, sim.u),
                 "e_p": rel(msim.p - msim.p.mean(), sim.p - sim.p.mean()),

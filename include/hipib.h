@@ -239,6 +239,56 @@ hipib_status hipib_advance(hipib_ctx* ctx, double* u, double* p, double* X, doub
 int32_t hipib_get_step_stats(hipib_ctx* ctx, int32_t* cycles, double* relres,
                              int32_t max_steps);
 
+/* Phases of an immersed-boundary step, timed by hipib_set_phase_timing. */
+typedef enum {
+    HIPIB_PHASE_FORCES = 0,    /* element forces, pressure load, tethers (side stream) */
+    HIPIB_PHASE_RHS = 1,       /* node binning and the fluid right-hand side */
+    HIPIB_PHASE_SPREAD = 2,    /* spreading, after waiting for the forces */
+    HIPIB_PHASE_HELMHOLTZ = 3, /* the three Helmholtz solves */
+    HIPIB_PHASE_POISSON = 4,   /* divergence, mean removal, Poisson solve */
+    HIPIB_PHASE_PROJECT = 5,   /* velocity correction */
+    HIPIB_PHASE_INTERP = 6,    /* interpolation and position update */
+    HIPIB_N_PHASES = 7
+} hipib_phase;
+
+typedef struct {
+    /* the last hipib_advance / hipib_ib_step / hipib_ns_step call */
+    int32_t steps;              /* steps it recorded */
+    int32_t cycles_last[4];     /* multigrid cycles of its last step (Helmholtz x, y, z, Poisson) */
+    double relres_last[4];      /* their final relative residuals */
+    double cycles_mean[4];      /* mean cycles over its steps */
+    /* phase timing (hipib_set_phase_timing) */
+    int32_t timed_steps;        /* steps timed since timing was switched on */
+    double phase_ms[HIPIB_N_PHASES];  /* their accumulated milliseconds per phase */
+    /* of the positions X passed to hipib_get_stats (0 when X is NULL or there
+     * are no elements): det F over all quadrature points, and the solid's
+     * volume sum_e sum_q w_q det(dx/dxi) (its change is the paper's volume
+     * conservation measure, "Benchmarks") */
+    double J_min, J_max, volume;
+    /* of the velocity u passed (0 when u is NULL): (rho/2) h^3 sum |u|^2 over the
+     * face lattices, rho h^3 sum u^d, max over cells of |D u| (the discrete
+     * divergence, sum_d (u^d[c + e_d] - u^d[c]) / h) */
+    double kinetic_energy, momentum[3], max_abs_div;
+} hipib_stats;
+
+/* Run diagnostics: the records of the last step call, the phase times, and
+ * the quantities above computed on the device from u ([3][n^3], may be NULL)
+ * and X ([n_nodes][3], may be NULL; needs hipib_set_mesh).  out: host.
+ * Waits for completion.  The per-workgroup partials are summed on the host in
+ * a fixed order. */
+hipib_status hipib_get_stats(hipib_ctx* ctx, const double* u, const double* X, hipib_stats* out);
+/* enable != 0: every later hipib_ib_step / hipib_advance step of a periodic box
+ * records HIP events at its phase boundaries and adds the phase durations
+ * into the hipib_stats phase times (one extra wait per step); the counts
+ * restart at zero.  enable = 0 switches it off.  Walled steps are not timed
+ * by phase. */
+hipib_status hipib_set_phase_timing(hipib_ctx* ctx, int32_t enable);
+/* The cavity pressure p0 sin^2(pi t / T) of hipib_advance at time t (0 when
+ * p0 = 0 or T <= 0): the load of the left-ventricle model's endocardium over
+ * one beat ("Dynamic left ventricle model"); callers reversing an advance
+ * (the adjoint rollout) take the same values from here. */
+double hipib_cavity_pressure(double p0, double T, double t);
+
 /* --- discrete adjoint ----------------------------------------------------
  * Reverse mode of hipib_ib_step for gradients of a loss L with respect to the
  * node positions and the Holzapfel-Ogden parameters (a, b, a_f, b_f) of each

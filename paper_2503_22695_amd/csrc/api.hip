@@ -138,6 +138,10 @@ void free_all(hipib_ctx* ctx) {
     (void)hipFree(ctx->adj_p);
     (void)hipFree(ctx->adj_sX);
     (void)hipFree(ctx->adj_lamF);
+    for (hipEvent_t e : ctx->ph_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->ph_force)
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     ctx->ev_pool.clear();
 }
@@ -151,16 +155,41 @@ void record_step(hipib_ctx* ctx, const int32_t* cyc, const double* rr) {
     ctx->recs.push_back(r);
 }
 
-// fluid part of a step: g holds the Helmholtz right-hand side on entry
-hipib_status fluid_solves(hipib_ctx* ctx, double* u, double* p) {
+// phase boundary k of a timed step (event on the context's stream)
+hipib_status phase_mark(hipib_ctx* ctx, bool timed, int k) {
+    if (timed) HIPIB_HIP(hipEventRecord(ctx->ph_ev[k], ctx->stream));
+    return HIPIB_OK;
+}
+
+// fluid part of a step: g holds the Helmholtz right-hand side on entry;
+// timed: phase events 3, 4, 5 after the Helmholtz solves, the Poisson solve
+// and the projection
+hipib_status fluid_solves(hipib_ctx* ctx, double* u, double* p, bool timed = false) {
     int32_t cyc[4] = {0, 0, 0, 0};
     double rr[4] = {0, 0, 0, 0};
     HIPIB_TRY(mg_solve(ctx, HIPIB_OP_HELMHOLTZ, 3, ctx->g, u, cyc, rr));
+    HIPIB_TRY(phase_mark(ctx, timed, 3));
     HIPIB_TRY(launch_divergence_rhs(ctx, u, ctx->bp));
     HIPIB_TRY(mg_remove_mean(ctx, ctx->bp, 0));
     HIPIB_TRY(mg_solve(ctx, HIPIB_OP_POISSON, 1, ctx->bp, p, cyc + 3, rr + 3));
+    HIPIB_TRY(phase_mark(ctx, timed, 4));
     HIPIB_TRY(launch_project(ctx, u, p));
+    HIPIB_TRY(phase_mark(ctx, timed, 5));
     record_step(ctx, cyc, rr);
+    return HIPIB_OK;
+}
+
+// adds the phase durations of a timed step (waits for its last event)
+hipib_status phase_accumulate(hipib_ctx* ctx) {
+    HIPIB_HIP(hipEventSynchronize(ctx->ph_ev[6]));
+    float ms = 0.0f;
+    HIPIB_HIP(hipEventElapsedTime(&ms, ctx->ph_force[0], ctx->ph_force[1]));
+    ctx->phase_ms[HIPIB_PHASE_FORCES] += ms;
+    for (int k = 1; k < HIPIB_N_PHASES; ++k) {
+        HIPIB_HIP(hipEventElapsedTime(&ms, ctx->ph_ev[k - 1], ctx->ph_ev[k]));
+        ctx->phase_ms[k] += ms;
+    }
+    ctx->phase_steps += 1;
     return HIPIB_OK;
 }
 
@@ -169,22 +198,30 @@ hipib_status ib_step(hipib_ctx* ctx, double* u, double* p, double* X, double pre
     // the element forces run on the side stream while the context's stream bins
     // the nodes and builds the fluid right-hand side (disjoint buffers); the
     // spreading waits for both
+    const bool timed = ctx->phase_timing;
+    HIPIB_TRY(phase_mark(ctx, timed, 0));
     HIPIB_HIP(hipEventRecord(ctx->ev_fork, ctx->stream));
     HIPIB_HIP(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+    if (timed) HIPIB_HIP(hipEventRecord(ctx->ph_force[0], ctx->side));
     hipStream_t own = ctx->stream;
     ctx->stream = ctx->side;
     const hipib_status fs = launch_fe_force(ctx, X, pressure, ctx->F);
     ctx->stream = own;
     HIPIB_TRY(fs);
+    if (timed) HIPIB_HIP(hipEventRecord(ctx->ph_force[1], ctx->side));
     HIPIB_HIP(hipEventRecord(ctx->ev_join, ctx->side));
     HIPIB_TRY(launch_bin(ctx, X));
     HIPIB_TRY(launch_rhs_build(ctx, u, nullptr, ctx->g));
+    HIPIB_TRY(phase_mark(ctx, timed, 1));
     HIPIB_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
     HIPIB_TRY(launch_spread(ctx, X, ctx->F, ctx->g));
-    HIPIB_TRY(fluid_solves(ctx, u, p));
+    HIPIB_TRY(phase_mark(ctx, timed, 2));
+    HIPIB_TRY(fluid_solves(ctx, u, p, timed));
     if (ctx->st_host->numeric)
         return fail(HIPIB_E_NUMERIC, "non-positive Jacobian at a Gauss point (inverted element)");
     HIPIB_TRY(launch_interpolate(ctx, X, u, nullptr, X, ctx->cfg.dt));
+    HIPIB_TRY(phase_mark(ctx, timed, 6));
+    if (timed) HIPIB_TRY(phase_accumulate(ctx));
     return HIPIB_OK;
 }
 
@@ -645,14 +682,9 @@ hipib_status hipib_advance(hipib_ctx* ctx, double* u, double* p, double* X, doub
     if (n_steps < 0 || !std::isfinite(t0) || !std::isfinite(p0) || !std::isfinite(T))
         return fail(HIPIB_E_INVAL, "bad time arguments");
     ctx->recs.clear();
-    const double pi = 3.14159265358979323846;
     for (int32_t s = 0; s < n_steps; ++s) {
         const double t = t0 + s * ctx->cfg.dt;
-        double pr = 0.0;
-        if (p0 != 0.0 && T > 0.0) {
-            const double sn = std::sin(pi * t / T);
-            pr = p0 * sn * sn;
-        }
+        const double pr = hipib_cavity_pressure(p0, T, t);
         if (ctx->ta_max != 0.0)
             ctx->active_ta = hipib_active_tension(ctx->ta_max, ctx->ta_t_on, ctx->ta_duration, t);
         HIPIB_TRY(ib_step(ctx, u, p, X, pr));
@@ -755,6 +787,47 @@ hipib_status hipib_timer_read(hipib_ctx* ctx, int32_t* launches, double* total_m
     if (bytes_per_launch) *bytes_per_launch = ctx->timer_bytes;
     ctx->ev_used = 0;
     ctx->timer_launches = 0;
+    return HIPIB_OK;
+}
+
+double hipib_cavity_pressure(double p0, double T, double t) {
+    if (p0 == 0.0 || !(T > 0.0)) return 0.0;
+    const double pi = 3.14159265358979323846;
+    const double sn = std::sin(pi * t / T);
+    return p0 * sn * sn;
+}
+
+hipib_status hipib_get_stats(hipib_ctx* ctx, const double* u, const double* X, hipib_stats* out) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (!out) return fail(HIPIB_E_INVAL, "null output");
+    if ((u && !aligned8(u)) || (X && !aligned8(X))) return fail(HIPIB_E_INVAL, "bad pointer");
+    if (X && !ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
+    std::memset(out, 0, sizeof(*out));
+    const int32_t ns = (int32_t)ctx->recs.size();
+    out->steps = ns;
+    for (int t = 0; t < 4; ++t) {
+        double sum = 0.0;
+        for (const StepRecord& r : ctx->recs) sum += r.cycles[t];
+        out->cycles_mean[t] = ns > 0 ? sum / ns : 0.0;
+        if (ns > 0) {
+            out->cycles_last[t] = ctx->recs.back().cycles[t];
+            out->relres_last[t] = ctx->recs.back().relres[t];
+        }
+    }
+    out->timed_steps = (int32_t)ctx->phase_steps;
+    for (int k = 0; k < HIPIB_N_PHASES; ++k) out->phase_ms[k] = ctx->phase_ms[k];
+    return compute_stats(ctx, u, X && ctx->nn > 0 ? X : nullptr, out);
+}
+
+hipib_status hipib_set_phase_timing(hipib_ctx* ctx, int32_t enable) {
+    HIPIB_TRY(check_ctx(ctx));
+    if (enable && !ctx->ph_ev[0]) {
+        for (hipEvent_t& e : ctx->ph_ev) HIPIB_HIP(hipEventCreate(&e));
+        for (hipEvent_t& e : ctx->ph_force) HIPIB_HIP(hipEventCreate(&e));
+    }
+    ctx->phase_timing = enable != 0;
+    ctx->phase_steps = 0;
+    for (double& v : ctx->phase_ms) v = 0.0;
     return HIPIB_OK;
 }
 

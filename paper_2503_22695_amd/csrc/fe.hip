@@ -24,8 +24,12 @@ namespace {
 // T: arithmetic type of the element computation; S: element type (Hex8, Tet4,
 // Tet10).  Node positions are taken relative to the element's first node in
 // FP64 before rounding to T (the Jacobians only see differences), and element
-// forces are accumulated into the FP64 nodal array.
-template <typename T, typename S>
+// forces are accumulated into the FP64 nodal array.  DISP (the FP32 element
+// forces of the mixed-precision form): the nodal displacements X - X_ref are
+// formed in FP64 and rounded to T, the Gauss point works on the displacement
+// gradient H = (dd/dxi) Jr^{-1} and the stress comes from pk1_disp, so the
+// rounding of T is relative to the strain, not to |X| / displacement.
+template <typename T, typename S, bool DISP = false>
 __global__ void __launch_bounds__(128)
 k_fe_force(const double* __restrict__ X, const double* __restrict__ Xref,
            const int32_t* __restrict__ conn, const double* __restrict__ fibre,
@@ -45,7 +49,7 @@ k_fe_force(const double* __restrict__ X, const double* __restrict__ Xref,
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             xr[a][r] = (T)(Xref[3 * nd[a] + r] - r0[r]);
-            xc[a][r] = (T)(X[3 * nd[a] + r] - c0[r]);
+            xc[a][r] = DISP ? (T)(X[3 * nd[a] + r] - Xref[3 * nd[a] + r]) : (T)(X[3 * nd[a] + r] - c0[r]);
             fe[a][r] = T(0);
         }
     const int m = mat_id[e];
@@ -56,10 +60,13 @@ k_fe_force(const double* __restrict__ X, const double* __restrict__ Xref,
     for (int t = 0; t < kMatParams; ++t) par[t] = (T)mats.p[m][t];
     const T ef[3] = {(T)fibre[3 * e], (T)fibre[3 * e + 1], (T)fibre[3 * e + 2]};
     T es[3] = {T(0), T(0), T(0)};
+    T efes = T(0);   // e_f . e_s in FP64 (zero up to the rounding of the inputs)
     if (sh) {
         es[0] = (T)sheet[3 * e];
         es[1] = (T)sheet[3 * e + 1];
         es[2] = (T)sheet[3 * e + 2];
+        efes = (T)(fibre[3 * e] * sheet[3 * e] + fibre[3 * e + 1] * sheet[3 * e + 1] +
+                   fibre[3 * e + 2] * sheet[3 * e + 2]);
     }
     // the active stress acts on Holzapfel-Ogden (myocardium) materials only
     const T ta = model == HIPIB_HOLZAPFEL_OGDEN ? (T)Ta : T(0);
@@ -88,14 +95,18 @@ k_fe_force(const double* __restrict__ X, const double* __restrict__ Xref,
         for (int r = 0; r < 3; ++r)
 #pragma unroll
             for (int c = 0; c < 3; ++c) Jri[3 * r + c] = cr[3 * c + r] * iw;   // Jr^{-1}
-        T Fm[9];
+        T Fm[9];   // F, or H = F - I when DISP
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 Fm[3 * r + c] = Jx[3 * r] * Jri[c] + Jx[3 * r + 1] * Jri[3 + c] + Jx[3 * r + 2] * Jri[6 + c];
         T P[9];
-        if (!pk1<T>(model, par, Fm, ef, es, sh, ta, P)) { bad = true; continue; }
+        if (DISP) {
+            if (!pk1_disp<T>(model, par, Fm, ef, es, efes, sh, ta, P)) { bad = true; continue; }
+        } else {
+            if (!pk1<T>(model, par, Fm, ef, es, sh, ta, P)) { bad = true; continue; }
+        }
         const T wg = w * wq;
         T Q[9];   // wg P Jr^{-T}
 #pragma unroll
@@ -216,9 +227,14 @@ namespace {
 // one element kernel per element type
 template <typename S>
 hipib_status launch_elements(hipib_ctx* ctx, const double* X, double* F, double* contrib) {
-    k_fe_force<double, S><<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
-        X, ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats, ctx->active_ta,
-        ctx->ne, F, ctx->st, contrib);
+    if (ctx->cfg.precision == HIPIB_MIXED)
+        k_fe_force<float, S, true><<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
+            X, ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats, ctx->active_ta,
+            ctx->ne, F, ctx->st, contrib);
+    else
+        k_fe_force<double, S><<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
+            X, ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats, ctx->active_ta,
+            ctx->ne, F, ctx->st, contrib);
     HIPIB_HIP(hipGetLastError());
     return HIPIB_OK;
 }
@@ -249,14 +265,7 @@ hipib_status launch_fe_force(hipib_ctx* ctx, const double* X, double pressure, d
         return launch_tethers(ctx, X, nullptr, F);
     }
     HIPIB_TRY(launch_zero(ctx, F, 3 * (int64_t)ctx->nn));
-    if (ctx->ne > 0) {
-        // FP64 in both precision modes: at interior nodes the element
-        // contributions cancel to a small net force, so FP32 element stresses
-        // would leave rounding-size spurious forces of ~1e-7 relative to the
-        // element forces, which exceeds the mixed mode's 1e-6 error budget over
-        // a run; the force kernel is ~1% of a step.
-        HIPIB_TRY(launch_element_forces(ctx, X, F, nullptr));
-    }
+    if (ctx->ne > 0) HIPIB_TRY(launch_element_forces(ctx, X, F, nullptr));
     if (ctx->nf > 0 && pressure != 0.0) {
         k_pressure_load<<<(ctx->nf + 255) / 256, 256, 0, ctx->stream>>>(X, ctx->faces, ctx->nf,
                                                                          pressure, F, nullptr);

@@ -163,6 +163,14 @@ struct hipib_ctx {
     double* adj_lamF = nullptr;  // [nn][3]
     int32_t adj_ready_nn = -1;
 
+    // phase timing of ib_step (hipib_set_phase_timing): events on the context's
+    // stream at the phase boundaries, and around the element forces on the side stream
+    bool phase_timing = false;
+    hipEvent_t ph_ev[8] = {};
+    hipEvent_t ph_force[2] = {};
+    double phase_ms[HIPIB_N_PHASES] = {};
+    int64_t phase_steps = 0;
+
     // event timing of one kernel class (hipib_timer)
     int timer_which = 0;
     std::vector<hipEvent_t> ev_pool;   // pairs: start 2i, stop 2i+1
@@ -188,6 +196,9 @@ hipib_status hip_fail(hipib_ctx* ctx, hipError_t e, const char* what, const char
         hipib_status s_ = (call);            \
         if (s_ != HIPIB_OK) return s_;       \
     } while (0)
+
+// stats.hip: the on-demand diagnostics of hipib_get_stats (u, X may be null)
+hipib_status compute_stats(hipib_ctx* ctx, const double* u, const double* X, hipib_stats* out);
 
 // ---- launchers (each file owns its kernels) ---------------------------------
 // grid.hip

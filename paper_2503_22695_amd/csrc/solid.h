@@ -120,6 +120,142 @@ __device__ __forceinline__ bool pk1(int model, const T* par, const T* Fm, const 
     return true;
 }
 
+// The same first Piola-Kirchhoff stress written on the displacement gradient
+// H = F - I, for evaluation in FP32: every quantity that vanishes in the
+// reference configuration is formed from H without subtracting O(1) terms, so
+// the rounding error of P is relative to P itself (to the strain) rather than
+// to |X| / displacement.
+//   J - 1 = tr H + (tr(H)^2 - tr(H H)) / 2 + det H,   ln J = log1p(J - 1),
+//   J^{-2/3} - 1 = expm1(-2/3 ln J),   I1 - 3 = 2 tr H + |H|^2,
+//   J^{-2/3}(F - I1/3 F^{-T}) = J^{-2/3} dev(E) F^{-T},  E = B - I = H + H^T + H H^T,
+//   cof F = I + tr(H) I - H^T + cof H,   F^{-T} = cof F / J,
+//   I4 - 1 = 2 e.(H e) + |H e|^2,   F e = e + H e,
+//   I8 = e_f.e_s + e_f.(H e_s) + (H e_f).e_s + (H e_f).(H e_s)   (efes = e_f.e_s, in FP64),
+//   sqrt(I4) - 1 = (I4 - 1) / (sqrt(I4) + 1),
+// and for the standard reinforcing law the fibre and I5 terms combine, at
+// d = (C - I) e = (H + H^T + H^T H) e, into
+//   (E_L + G_T - 4 G_L)/2 (I4 - 1) (F e)(x)e - (G_T - G_L) ((F e)(x)d + (F d)(x)e).
+// Returns false when J <= 0.
+template <typename T>
+__device__ __forceinline__ bool pk1_disp(int model, const T* par, const T* H, const T* ef, const T* es,
+                                         T efes, bool sheet, T Ta, T* P) {
+    const T trH = H[0] + H[4] + H[8];
+    T trHH = T(0), HsqSum = T(0);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            trHH += H[3 * r + c] * H[3 * c + r];
+            HsqSum += H[3 * r + c] * H[3 * r + c];
+        }
+    const T jm1 = trH + T(0.5) * (trH * trH - trHH) + det3(H);   // J - 1
+    if (!(jm1 > T(-1))) return false;
+    const T J = T(1) + jm1;
+    const T lnJ = log1p(jm1);
+    const T jm = expm1(T(-2) / T(3) * lnJ);                        // J^{-2/3} - 1
+    const T i1m3 = T(2) * trH + HsqSum;                             // I1 - 3
+    const T i1bm3 = i1m3 + jm * (T(3) + i1m3);                      // I1bar - 3
+    // G = F^{-T}
+    T G[9];
+    cof3(H, G);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) G[3 * r + c] -= H[3 * c + r];
+    G[0] += T(1) + trH;
+    G[4] += T(1) + trH;
+    G[8] += T(1) + trH;
+    const T invJ = T(1) / J;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) G[r] *= invJ;
+    // dev(E), E = H + H^T + H H^T
+    T E[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            E[3 * r + c] = H[3 * r + c] + H[3 * c + r] +
+                           (H[3 * r] * H[3 * c] + H[3 * r + 1] * H[3 * c + 1] + H[3 * r + 2] * H[3 * c + 2]);
+    const T third = i1m3 / T(3);   // tr E / 3
+    E[0] -= third;
+    E[4] -= third;
+    E[8] -= third;
+    // fibre (and sheet) stretches
+    T He[3] = {T(0), T(0), T(0)}, Fe[3] = {T(0), T(0), T(0)};
+    T I4m1 = T(0);
+    if (model != HIPIB_NEO_HOOKEAN) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) He[r] = H[3 * r] * ef[0] + H[3 * r + 1] * ef[1] + H[3 * r + 2] * ef[2];
+        I4m1 = T(2) * (ef[0] * He[0] + ef[1] * He[1] + ef[2] * He[2]) +
+               (He[0] * He[0] + He[1] * He[1] + He[2] * He[2]);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) Fe[r] = ef[r] + He[r];
+    }
+    T iso, kappa, fib = T(0), sh = T(0), fs = T(0);
+    T Fs[3] = {T(0), T(0), T(0)};
+    if (model == HIPIB_NEO_HOOKEAN) {
+        iso = par[0];
+        kappa = par[1];
+    } else if (model == HIPIB_STANDARD_REINFORCING) {
+        iso = par[0];
+        kappa = par[3];
+        fib = T(0.5) * (par[2] + par[0] - T(4) * par[1]) * I4m1;
+    } else if (model == HIPIB_FIBRE_REINFORCED_1) {
+        iso = T(2) * par[0];
+        kappa = par[3];
+        if (I4m1 > T(0)) fib = T(2) * par[1] * I4m1 * exp(par[2] * I4m1 * I4m1);
+    } else if (model == HIPIB_FIBRE_REINFORCED_2) {
+        iso = T(2) * par[0] * par[1] * exp(par[1] * i1bm3);
+        kappa = par[4];
+        fib = T(2) * par[2] * I4m1 * exp(par[3] * I4m1 * I4m1);
+    } else {
+        kappa = par[4];
+        iso = par[0] * exp(par[1] * i1bm3);
+        if (I4m1 > T(0)) fib = T(2) * par[2] * I4m1 * exp(par[3] * I4m1 * I4m1);
+        if (Ta != T(0)) fib += Ta * (T(1) + T(4.9) * (I4m1 / (sqrt(T(1) + I4m1) + T(1))));
+        if (sheet) {
+            T Hs[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) Hs[r] = H[3 * r] * es[0] + H[3 * r + 1] * es[1] + H[3 * r + 2] * es[2];
+            const T I4sm1 = T(2) * (es[0] * Hs[0] + es[1] * Hs[1] + es[2] * Hs[2]) +
+                            (Hs[0] * Hs[0] + Hs[1] * Hs[1] + Hs[2] * Hs[2]);
+            if (I4sm1 > T(0)) sh = T(2) * par[5] * I4sm1 * exp(par[6] * I4sm1 * I4sm1);
+            const T I8 = efes + (ef[0] * Hs[0] + ef[1] * Hs[1] + ef[2] * Hs[2]) +
+                         (He[0] * es[0] + He[1] * es[1] + He[2] * es[2]) +
+                         (He[0] * Hs[0] + He[1] * Hs[1] + He[2] * Hs[2]);
+            fs = par[7] * I8 * exp(par[8] * I8 * I8);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) Fs[r] = es[r] + Hs[r];
+        }
+    }
+    const T a = iso * (T(1) + jm), vol = kappa * lnJ;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T devG = E[3 * r] * G[c] + E[3 * r + 1] * G[3 + c] + E[3 * r + 2] * G[6 + c];
+            T v = a * devG + vol * G[3 * r + c] + fib * Fe[r] * ef[c];
+            if (sheet) v += sh * Fs[r] * es[c] + fs * (Fe[r] * es[c] + Fs[r] * ef[c]);
+            P[3 * r + c] = v;
+        }
+    if (model == HIPIB_STANDARD_REINFORCING) {
+        // d = (H + H^T + H^T H) e, F d = d + H d
+        T d[3], Fd[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            d[c] = He[c] + (H[c] * ef[0] + H[3 + c] * ef[1] + H[6 + c] * ef[2]) +
+                   (H[c] * He[0] + H[3 + c] * He[1] + H[6 + c] * He[2]);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) Fd[r] = d[r] + H[3 * r] * d[0] + H[3 * r + 1] * d[1] + H[3 * r + 2] * d[2];
+        const T c5 = par[1] - par[0];   // G_L - G_T
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) P[3 * r + c] += c5 * (Fe[r] * d[c] + Fd[r] * ef[c]);
+    }
+    return true;
+}
+
 // dP = dP/dF : dF.  With G = F^{-T}: dG = -G dF^T G, d ln J = G : dF,
 // dI1 = 2 F : dF, d J^{-2/3} = -(2/3) J^{-2/3} d ln J, dI4i = 2 (F e_i).(dF e_i),
 // dI8 = (dF e_f).(F e_s) + (F e_f).(dF e_s); iso coefficient alpha (mu_s, or

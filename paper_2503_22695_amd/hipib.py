@@ -33,6 +33,28 @@ class HipIBError(RuntimeError):
         self.status = status
 
 
+N_PHASES = 7
+PHASES = ("forces", "rhs", "spread", "helmholtz", "poisson", "project", "interp")
+
+
+class Stats(C.Structure):
+    """hipib_stats."""
+    _fields_ = [("steps", C.c_int32), ("cycles_last", C.c_int32 * 4), ("relres_last", C.c_double * 4),
+                ("cycles_mean", C.c_double * 4), ("timed_steps", C.c_int32),
+                ("phase_ms", C.c_double * N_PHASES), ("J_min", C.c_double), ("J_max", C.c_double),
+                ("volume", C.c_double), ("kinetic_energy", C.c_double), ("momentum", C.c_double * 3),
+                ("max_abs_div", C.c_double)]
+
+    def as_dict(self):
+        return {"steps": self.steps, "cycles_last": list(self.cycles_last),
+                "relres_last": list(self.relres_last), "cycles_mean": list(self.cycles_mean),
+                "timed_steps": self.timed_steps,
+                "phase_ms": dict(zip(PHASES, list(self.phase_ms))),
+                "J_min": self.J_min, "J_max": self.J_max, "volume": self.volume,
+                "kinetic_energy": self.kinetic_energy, "momentum": list(self.momentum),
+                "max_abs_div": self.max_abs_div}
+
+
 class Config(C.Structure):
     _fields_ = [("n", C.c_int32), ("rho", C.c_double), ("mu", C.c_double), ("dt", C.c_double),
                 ("mg_pre", C.c_int32), ("mg_post", C.c_int32), ("mg_max_cycles", C.c_int32),
@@ -78,6 +100,9 @@ def lib():
             "hipib_fe_force": (st, [P, P, f64, P]),
             "hipib_spread": (st, [P, P, P, P]),
             "hipib_spread_noalloc": (st, [i32, i32, P, P, P, P]),
+            "hipib_get_stats": (st, [P, P, P, P]),
+            "hipib_set_phase_timing": (st, [P, i32]),
+            "hipib_cavity_pressure": (f64, [f64, f64, f64]),
             "hipib_interpolate": (st, [P, P, P, P]),
             "hipib_mg_solve": (st, [P, i32, i32, P, P, P, P]),
             "hipib_ns_step": (st, [P, P, P, P]),
@@ -322,6 +347,18 @@ class Context:
                "hipib_timer_read")
         return k.value, ms.value, by.value
 
+    def get_stats(self, u=None, X=None) -> dict:
+        """hipib_get_stats: step records, phase times, and the diagnostics of u
+        ([3, n, n, n]) and X ([n_nodes, 3]) when given."""
+        st = Stats()
+        up = C.c_void_p(0) if u is None else _dev(u, self._grid_shape(3), "u")
+        Xp = C.c_void_p(0) if X is None else _dev(X, (self.n_nodes, 3), "X")
+        _check(lib().hipib_get_stats(self._h, up, Xp, C.byref(st)), "hipib_get_stats")
+        return st.as_dict()
+
+    def set_phase_timing(self, enable: bool):
+        _check(lib().hipib_set_phase_timing(self._h, 1 if enable else 0), "hipib_set_phase_timing")
+
     def step_stats(self, max_steps: int = 100000):
         cyc = np.zeros((max_steps, 4), dtype=np.int32)
         rr = np.zeros((max_steps, 4), dtype=np.float64)
@@ -363,6 +400,11 @@ def spread_noalloc(n: int, X, F, f):
     _check(lib().hipib_spread_noalloc(int(n), nn, _dev(X, (nn, 3), "X"), _dev(F, (nn, 3), "F"),
                                       _dev(f, (3, n, n, n), "f"), _stream_ptr()),
            "hipib_spread_noalloc")
+
+
+def cavity_pressure(p0: float, T: float, t: float) -> float:
+    """p0 sin^2(pi t / T) as hipib_advance applies it (hipib_cavity_pressure)."""
+    return lib().hipib_cavity_pressure(float(p0), float(T), float(t))
 
 
 def active_tension(ta_max: float, t_on: float, duration: float, t: float) -> float:
@@ -424,13 +466,8 @@ class Rollout:
     def pressure(self, s0: int, i: int) -> float:
         """Cavity pressure at step s0 + i, with the time rounded exactly as
         hipib_advance rounds it when called at the start of step s0."""
-        import math
-        p0, T = self.prob.p0, self.prob.T
-        if p0 == 0.0 or T <= 0.0:
-            return 0.0
         t = (self.t0 + s0 * self.prob.dt) + i * self.prob.dt
-        sn = math.sin(math.pi * t / T)
-        return p0 * sn * sn
+        return cavity_pressure(self.prob.p0, self.prob.T, t)
 
     def active(self, s0: int, i: int) -> float:
         """Active tension at step s0 + i, timed like pressure()."""

@@ -41,3 +41,17 @@ def test_null_context_is_an_error():
     assert L.hipib_fe_force(None, None, 0.0, None) == hipib.E_INVAL
     assert L.hipib_advance(None, None, None, None, 0.0, 1, 0.0, 0.0) == hipib.E_INVAL
     assert L.hipib_destroy(None) == hipib.OK
+
+
+def test_cavity_pressure_waveform():
+    """hipib_cavity_pressure is the load hipib_advance applies: p0 sin^2(pi t / T),
+    zero for p0 = 0 or T <= 0 (host function, no GPU)."""
+    import math
+    from paper_2503_22695_amd import hipib
+    for p0, T, t in [(1.0, 0.05, 0.0125), (2.5, 0.05, 0.05), (1.0, 0.05, 0.0), (0.7, 1.0, 0.3)]:
+        sn = math.sin(math.pi * t / T)
+        assert hipib.cavity_pressure(p0, T, t) == p0 * sn * sn
+    assert hipib.cavity_pressure(1.0, 0.05, 0.025) == 1.0
+    assert hipib.cavity_pressure(0.0, 0.05, 0.01) == 0.0
+    assert hipib.cavity_pressure(1.0, 0.0, 0.01) == 0.0
+    assert hipib.cavity_pressure(1.0, -1.0, 0.01) == 0.0
