@@ -5,21 +5,28 @@ Workload: the 128^3 Holzapfel-Ogden truncated-ellipsoid shell (127,008 nodes,
 107,520 trilinear hexes, 17,920 endocardial pressure quads), dt = 5e-4,
 p(t) = sin^2(pi t / T) with T = 100 dt, FP64, synthetic inputs from
 paper_2503_22695_amd.inputs.  One step = FE force + pressure load, explicit
-convection right-hand side, spreading, three Helmholtz and one Poisson
-multigrid solve (V(2,2) to 1e-10), projection, interpolation and position
-update, all in libhipib's HIP kernels.
+convection right-hand side, spreading, the Helmholtz and Poisson multigrid
+solves (rtol 1e-10), projection, interpolation and position update, all in
+libhipib's HIP kernels.
 
 Prints one JSON line.  `value` is steps/s over the timed steps with every input
-already resident in HBM.  `roofline` is for the dominant kernel (the finest
-level red/black Gauss-Seidel sweep of the Poisson solve), timed with a HIP
-event pair around each of its launches, on the launch stream, during a second
-pass of --roofline-steps steps (events between launches would slow the timed
-region itself).  `cpu_baseline` is the FP64 CPU
-oracle timed on this host on a bounded sample of the same workload.
+already resident in HBM.  `roofline` is for the dominant kernel class (the one
+with the most time per step), and `roofline.other_kernels` gives the others:
+each class is timed with HIP start/stop events that each dispatch stamps
+itself (hipExtLaunchKernel), on the stream it runs on, during separate passes
+of --roofline-steps steps after the timed region (events between launches
+would slow the timed region itself); achieved = algorithmic bytes (or flops)
+per launch / mean launch time.  `roofline_192` repeats the grid and coupling
+kernels on the 192^3 shell with leaflets, whose solver arrays no longer fit
+the last-level cache.  `cpu_baseline` is the FP64 CPU oracle timed on this
+host on a bounded sample of the same workload (all threads, and one thread);
+the oracle's run of the whole 100 steps also gives `parity_vs_oracle`, the
+errors of the timed FP64 and mixed-precision runs.
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -28,6 +35,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FE_FLOP_PER_HEX = 3.7e3     # FE force, 2x2x2 Gauss points (algorithmic count)
 METRIC = "IB steps/s at 128^3 HO shell: FP64 vs mixed-prec (err≤1e-6); adjoint/fwd time"
 
 
@@ -41,26 +50,98 @@ def cpu_threads() -> int:
         return os.cpu_count() or 1
 
 
-def cpu_baseline(prob, seconds: float):
-    """The CPU oracle as it stands, timed on consecutive steps of the same
-    workload from its initial state until `seconds` have elapsed."""
+def host_cpu():
+    """Model name and physical core count of this host (lscpu fields)."""
+    model, cores, sockets = "unknown", None, None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for ln in out.splitlines():
+            k, _, v = ln.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "Model name":
+                model = v
+            elif k == "Core(s) per socket":
+                cores = int(v)
+            elif k == "Socket(s)":
+                sockets = int(v)
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    phys = cores * sockets if cores and sockets else None
+    return model, phys
+
+
+ORACLE_ONE_THREAD = r"""
+import os, sys, time
+sys.path.insert(0, {root!r})
+import numpy as np
+import oracle
+from paper_2503_22695_amd import inputs
+prob = inputs.workload("ho_shell_128")
+fl = oracle.fluid_from_problem(prob)
+mesh = oracle.MeshBuffers.from_problem(prob)
+u, p, X = prob.initial_velocity(), np.zeros((prob.n,) * 3), prob.X0.copy()
+u, p, X, _ = oracle.advance(fl, mesh, u, p, X, 0.0, 1, prob.p0, prob.T)
+t = time.perf_counter()
+u, p, X, _ = oracle.advance(fl, mesh, u, p, X, 0.0, {steps}, prob.p0, prob.T, first_step=1)
+print(time.perf_counter() - t)
+"""
+
+
+def oracle_one_thread(steps: int):
+    """s/step of the oracle on one thread (a child process with OMP_NUM_THREADS=1):
+    1 warm-up step, then `steps` timed steps of the 128^3 shell."""
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", ORACLE_ONE_THREAD.format(root=ROOT, steps=steps)],
+                         capture_output=True, text=True, env=env, timeout=600, check=True)
+    return float(out.stdout.strip().splitlines()[-1]) / steps
+
+
+def cpu_baseline_and_parity(prob, sample_steps: int, one_thread_steps: int, runs):
+    """The CPU oracle as it stands: its run of the whole workload from t = 0 in
+    pieces, the first `sample_steps` of which are timed (the baseline sample),
+    then the errors of the GPU runs (state after the same steps) against it."""
     import numpy as np
     import oracle
     fl = oracle.fluid_from_problem(prob)
     mesh = oracle.MeshBuffers.from_problem(prob)
-    u = prob.initial_velocity()
-    p = np.zeros((prob.n,) * 3)
-    X = prob.X0.copy()
-    steps, t = 0, 0.0
-    start = time.perf_counter()
-    while steps < 1 or time.perf_counter() - start < seconds:
-        u, p, X, _ = oracle.advance(fl, mesh, u, p, X, t, 1, prob.p0, prob.T)
-        t += prob.dt
-        steps += 1
-    el = time.perf_counter() - start
-    return {"value": steps / el, "unit": "steps/s", "cores": cpu_threads(), "kind": "oracle",
-            "sample": f"first {steps} steps of the 128^3 shell workload from t=0 "
-                      f"({el:.1f} s, FP64 C with OpenMP grid loops)"}
+    u, p, X = prob.initial_velocity(), np.zeros((prob.n,) * 3), prob.X0.copy()
+    t0 = time.perf_counter()
+    u, p, X, _ = oracle.advance(fl, mesh, u, p, X, 0.0, sample_steps, prob.p0, prob.T)
+    el = time.perf_counter() - t0
+    progress(f"oracle: {sample_steps} steps timed ({el:.1f} s)")
+    done = sample_steps
+    while done < prob.n_steps:
+        m = min(25, prob.n_steps - done)
+        u, p, X, _ = oracle.advance(fl, mesh, u, p, X, 0.0, m, prob.p0, prob.T, first_step=done)
+        done += m
+        progress(f"oracle: {done} of {prob.n_steps} steps for the parity check")
+    model, phys = host_cpu()
+    base = {"value": sample_steps / el, "unit": "steps/s", "cores": cpu_threads(), "kind": "oracle",
+            "sample": f"first {sample_steps} steps of the 128^3 shell workload from t=0 ({el:.1f} s, FP64 C "
+                      f"with OpenMP grid loops, {cpu_threads()} threads)",
+            "cpu_model": model, "physical_cores": phys}
+    if one_thread_steps > 0:
+        s1 = oracle_one_thread(one_thread_steps)
+        base["one_thread"] = {"value": 1.0 / s1, "unit": "steps/s", "cores": 1,
+                              "sample": f"steps 2..{1 + one_thread_steps} of the same workload, one thread"}
+        progress("oracle: one-thread sample done")
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    def rel_inf(a, b):
+        return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    par = {}
+    for name, (ug, pg, Xg) in runs.items():
+        pm, prm = pg - pg.mean(), p - p.mean()
+        e = {"e_u": rel(ug, u), "e_p": rel(pm, prm),
+             "e_X": float(np.max(np.abs(Xg - X)) / np.max(np.abs(X - prob.X0))),
+             "u_inf": rel_inf(ug, u), "p_inf": rel_inf(pm, prm), "dX_l2": rel(Xg - prob.X0, X - prob.X0)}
+        par[name] = e
+    par["definition"] = ("after the timed 100 steps from t = 0, against the FP64 oracle's run: e_u, e_p (mean-free) "
+                         "relative l2; e_X = max|X - X_ref| / max|X_ref - X0|; u_inf, p_inf relative max norms; "
+                         "dX_l2 relative l2 of X - X0")
+    return base, par
 
 
 def workload_leg(torch, hipib, inputs, name, steps):
@@ -78,44 +159,11 @@ def workload_leg(torch, hipib, inputs, name, steps):
     el = time.perf_counter() - t0
     cyc, _ = sim.ctx.step_stats()
     import numpy as np
-    return {"value": round(steps / el, 3), "unit": "steps/s", "steps": steps,
-            "ms_per_step": round(1e3 * el / steps, 4), "dtype": "f64",
-            "mg_cycles_per_step": {"helmholtz_max_component": float(np.mean(cyc[:, :3].max(1))),
-                                   "poisson": float(np.mean(cyc[:, 3]))}}
-
-
-def larger_workload(torch, hipib, inputs, steps):
-    """The 192^3 shell with two neo-Hookean leaflets (280,740 nodes, 243,712
-    hexes, random divergence-free initial flow), where the solver's working set
-    no longer fits the last-level cache."""
-    return workload_leg(torch, hipib, inputs, "shell_leaflets_192", steps)
-
-
-def tet_workload(torch, hipib, inputs):
-    """P2 tetrahedra with the modified standard reinforcing law at the
-    benchmark's settings (64^3 grid, dt 1e-3, one face penalised): 6,000 tets,
-    9,261 nodes (27,783 solid DoFs), its 20-step run."""
-    out = workload_leg(torch, hipib, inputs, "tet10_block_64", 20)
-    out["elements"] = "P2 tetrahedra, 4-point rule"
-    return out
-
-
-def walled_workload(torch, hipib, inputs):
-    """The Holzapfel-Ogden shell in a walled 64^3 box (no slip, no penetration),
-    solved on its 128^3 mirror-image grid: its first 20 steps."""
-    out = workload_leg(torch, hipib, inputs, "walled_shell_64", 20)
-    out["boundary"] = "walled box, (2n)^3 mirror-image grid"
-    return out
-
-
-def lv_workload(torch, hipib, inputs):
-    """The 128^3 shell with the full Holzapfel-Ogden law (sheet and fibre-sheet
-    terms), transmural sheets, the active-tension pulse and the base constraint
-    (penalty tethers): its whole 100-step run."""
-    out = workload_leg(torch, hipib, inputs, "lv_shell_128", 100)
-    out["law"] = ("Holzapfel-Ogden with sheet and fibre-sheet terms + active fibre tension; "
-                  "base ring tethered axially and circumferentially")
-    return out
+    out = {"value": round(steps / el, 3), "unit": "steps/s", "steps": steps,
+           "ms_per_step": round(1e3 * el / steps, 4), "dtype": "f64",
+           "mg_cycles_per_step": {"helmholtz_max_component": float(np.mean(cyc[:, :3].max(1))),
+                                  "poisson": float(np.mean(cyc[:, 3]))}}
+    return out, sim, prob
 
 
 def adjoint_ratio(torch, hipib, inputs, name="ho_block_64",
@@ -166,16 +214,104 @@ def adjoint_ratio(torch, hipib, inputs, name="ho_block_64",
             "grad_theta": [float(v) for v in th.grad]}
 
 
-KERNELS = {}  # timer id -> description, filled once the library is loaded
+def kernel_classes(hipib):
+    """(timer, kernel name, algorithmic measure) of the timed kernel classes."""
+    H = hipib
+    return [
+        (H.TIMER_SMOOTH_FINE_POISSON, "k_gs<double,2>",
+         "finest-level red or black Gauss-Seidel half-sweep of the Poisson solve, 12 B/cell"),
+        (H.TIMER_SMOOTH_FINE_HELMHOLTZ, "k_gs<double,1,true>",
+         "finest-level over-relaxed red or black half-sweep of the Helmholtz solves, 16 B/cell per component"),
+        (H.TIMER_RESID_RESTRICT, "k_resid_restrict<double>", "finest-level red residual and restriction, 13 B/cell"),
+        (H.TIMER_PROLONG, "k_prolong_add<double>", "finest-level prolongation to the red cells, 9 B/cell"),
+        (H.TIMER_LEVEL_DOWN, "k_level_down<double>", "first coarse level, down half, 17 B per cell of that level"),
+        (H.TIMER_LEVEL_UP, "k_level_up<double>", "first coarse level, up half, 21 B per cell of that level"),
+        (H.TIMER_SMALL_VCYCLE, "k_small_vcycle<16,double>", "levels <= 16^3 in one workgroup, 16 B per 16^3 cell"),
+        (H.TIMER_RESID_NORM, "k_resid_norm<false>", "residual norm, 16 B/cell per component"),
+        (H.TIMER_CG_DOTS, "k_cg_dots<double>", "r.z and z.q, 24 B/cell"),
+        (H.TIMER_CG_DIR, "k_cg_dir<double>", "p, q = A z + beta q and p.q, 40 B/cell"),
+        (H.TIMER_CG_UPDATE, "k_cg_update", "x, r updates and ||r||^2, 48 B/cell"),
+        (H.TIMER_REDUCE, "k_finalize / k_cg_scalars", "single-workgroup reductions, 8 B per partial"),
+        (H.TIMER_RHS, "k_rhs_build", "fluid right-hand side with convection, 48 B/cell"),
+        (H.TIMER_DIVERGENCE, "k_divergence_rhs", "Poisson right-hand side, 32 B/cell"),
+        (H.TIMER_PROJECT, "k_project", "velocity correction, 56 B/cell"),
+        (H.TIMER_PACK, "k_pack / k_unpack", "layout conversions, 16 B/cell per component"),
+        (H.TIMER_SPREAD, "k_spread_tiles<8,double>",
+         "spreading: 52 B/node (X, F, order) + 16 B per touched grid value (f read and written)"),
+        (H.TIMER_INTERP, "k_interp<double>",
+         "interpolation and position update: 52 B/node (X read and written, order) + 8 B per touched grid value"),
+        (H.TIMER_FE_FORCE, "k_fe_force<double,Hex8>", "element forces, 3.7 kflop per hex (FP64 ALU)"),
+    ]
+
+
+def stencil_footprint(X, n):
+    """Distinct (lattice, grid point) pairs in the 4x4x4 delta-kernel stencils of
+    the nodes at X on the n^3 grid (the support of phi(r - i) for r the node's
+    lattice coordinate: lattice d has offset 0 along d and 1/2 along the
+    others), counted on the host from the stencil definition."""
+    import numpy as np
+    total = 0
+    s = np.arange(4)
+    for d in range(3):
+        off = np.array([0.0 if e == d else 0.5 for e in range(3)])
+        base = np.floor(X * n - off).astype(np.int64) - 1            # first stencil index per axis
+        ix = (base[:, 0:1] + s) % n
+        iy = (base[:, 1:2] + s) % n
+        iz = (base[:, 2:3] + s) % n
+        flat = (ix[:, :, None, None] + n * (iy[:, None, :, None] + n * iz[:, None, None, :])).reshape(-1)
+        total += np.unique(flat).size
+    return total
+
+
+def time_classes(torch, hipib, sim, prob, t_start, steps, classes):
+    """Per-class launch times over `steps` steps continuing the run on copies of
+    its state; (launches, total_ms, bytes_per_launch) per timer."""
+    out = {}
+    ctx = sim.ctx
+    for tid, _, _ in classes:
+        u, p, X = sim.u.clone(), sim.p.clone(), sim.X.clone()
+        ctx.timer_enable(tid)
+        ctx.advance(u, p, X, t_start, steps, prob.p0, prob.T)
+        torch.cuda.synchronize()
+        out[tid] = ctx.timer_read()
+        ctx.timer_enable(hipib.TIMER_OFF)
+        del u, p, X
+    return out
+
+
+def roofline_table(hipib, tim, classes, steps, nodes_bytes, fe_flops):
+    """Achieved GB/s (or TFLOP/s) of every timed class; sorted by time per step."""
+    rows = {}
+    for tid, name, what in classes:
+        launches, ms, bpl = tim.get(tid, (0, 0.0, 0.0))
+        if launches == 0:
+            continue
+        avg_s = ms * 1e-3 / launches
+        row = {"what": what, "launches_per_step": round(launches / steps, 2),
+               "avg_launch_us": round(avg_s * 1e6, 3), "ms_per_step": round(ms / steps, 4)}
+        if tid == hipib.TIMER_FE_FORCE:
+            ach = fe_flops / avg_s / 1e12
+            row.update({"bound": "fp64-alu", "flops_per_launch": fe_flops, "achieved": round(ach, 3),
+                        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4)})
+        else:
+            if tid in nodes_bytes:
+                bpl = nodes_bytes[tid]
+            ach = bpl / avg_s / 1e9
+            row.update({"bound": "hbm", "bytes_per_launch": round(bpl), "achieved": round(ach, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4)})
+        rows[name] = row
+    return dict(sorted(rows.items(), key=lambda kv: -kv[1]["ms_per_step"]))
+
+
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2503_22695_amd", "csrc", "mg.hip")
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of the roofline kernel (e.g. "k_level_down") from the
-    committed counter summary profiles/<kernel>_poisson_fine_128_hbm_traffic.md,
-    or None when the kernel source has changed since it was taken."""
+def measured_traffic(kernel: str, workload: str = "128"):
+    """HBM bytes per launch of kernel `kernel` from the committed counter summary
+    profiles/<kernel>_poisson_fine_<workload>_hbm_traffic.md, or None when the
+    kernel source has changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_poisson_fine_128_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_poisson_fine_{workload}_hbm_traffic.md")
     try:
         lines = open(path).read().splitlines()
     except OSError:
@@ -213,7 +349,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-steps", type=int, default=25, help="oracle steps timed for the CPU baseline")
+    ap.add_argument("--cpu-one-thread-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -224,7 +361,7 @@ def main():
     ap.add_argument("--no-walls", action="store_true",
                     help="skip the walled 64^3 shell leg and the walled adjoint ratio")
     ap.add_argument("--roofline-steps", type=int, default=20,
-                    help="steps of the separate pass that times the roofline kernel")
+                    help="steps of each separate pass that times one kernel class")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (memory-counter calibration)")
     args = ap.parse_args()
@@ -242,8 +379,9 @@ def main():
     if args.copy_calibration_mib > 0:
         copy_calibration(torch, args.copy_calibration_mib)
     prob = inputs.ho_shell()
+    classes = kernel_classes(hipib)
 
-    def run(precision, timer):
+    def run(precision):
         sim = hipib.Simulation(prob, precision=precision)
         ctx = sim.ctx
         # warm-up on a copy of the initial state (also settles the predicted cycle counts)
@@ -258,51 +396,61 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         cyc, _ = ctx.step_stats()
-        tim = {}
-        if timer:
-            # roofline passes: the next steps of the same run, on copies, with
-            # dispatch-stamped events on every launch of one finest-level
-            # Poisson kernel class per pass
-            t_end = args.steps * prob.dt
-            for kind in KERNELS:
-                u, p, X = sim.u.clone(), sim.p.clone(), sim.X.clone()
-                ctx.timer_enable(kind)
-                ctx.advance(u, p, X, t_end, args.roofline_steps, prob.p0, prob.T)
-                torch.cuda.synchronize()
-                tim[kind] = ctx.timer_read()
-                ctx.timer_enable(hipib.TIMER_OFF)
-                del u, p, X
         if not (torch.isfinite(sim.u).all() and torch.isfinite(sim.X).all()):
             raise RuntimeError("non-finite state after the timed run")
-        return sim, t1 - t0, tim, cyc
+        return sim, t1 - t0, cyc
 
-    KERNELS.update({
-        hipib.TIMER_SMOOTH_FINE_POISSON: "k_gs<double,2>: finest-level red or black Gauss-Seidel half-sweep "
-                                         "of the Poisson solve (packed layout, 12 B/cell)",
-    })
-    sim, elapsed, tim, cyc = run(hipib.FP64, True)
-    progress(f"FP64 {args.steps} steps in {elapsed:.3f} s and the roofline pass done")
-    # the dominant kernel: the timed class with the most total time
-    dom = max(tim, key=lambda k: tim[k][1])
-    launches, kernel_ms, bytes_per_launch = tim[dom]
+    sim, elapsed, cyc = run(hipib.FP64)
     steps_per_s = args.steps / elapsed
+    progress(f"FP64 {args.steps} steps in {elapsed:.3f} s")
+    t_end = args.steps * prob.dt
+    # per-class kernel times on the state after the timed region
+    Xh = sim.X.cpu().numpy()
+    fp = stencil_footprint(Xh, prob.n)
+    nodes_bytes = {hipib.TIMER_SPREAD: 52.0 * prob.n_nodes + 16.0 * fp,
+                   hipib.TIMER_INTERP: 52.0 * prob.n_nodes + 8.0 * fp}
+    tim = time_classes(torch, hipib, sim, prob, t_end, args.roofline_steps, classes)
+    table = roofline_table(hipib, tim, classes, args.roofline_steps, nodes_bytes, FE_FLOP_PER_HEX * prob.n_elems)
+    progress("per-kernel roofline passes done")
+    gpu_state = {"fp64": tuple(t.cpu().numpy() for t in (sim.u, sim.p, sim.X))}
+    phase_sim = sim
+    dom_name = next(iter(table))
+    dom = table[dom_name]
+    roofline = {k: dom[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+    roofline["traffic"] = measured_traffic(dom_name.split("<")[0]) if dom["bound"] == "hbm" else None
+    roofline.update({
+        "kernel": f"{dom_name}: {dom['what']}",
+        "bytes_per_launch": dom.get("bytes_per_launch"), "launches_per_step": dom["launches_per_step"],
+        "avg_launch_us": dom["avg_launch_us"], "ms_per_step": dom["ms_per_step"],
+        "timing": f"HIP start/stop events stamped by each dispatch (hipExtLaunchKernel) on its stream, during "
+                  f"{args.roofline_steps} further steps per kernel class run after the timed region",
+        "other_kernels": {k: v for k, v in table.items() if k != dom_name},
+        "stencil_footprint_values": fp,
+    })
+    # phase times over the same number of steps (a separate pass: one wait per step)
+    u, p, X = sim.u.clone(), sim.p.clone(), sim.X.clone()
+    phase_sim.ctx.set_phase_timing(True)
+    phase_sim.ctx.advance(u, p, X, t_end, args.roofline_steps, prob.p0, prob.T)
+    st = phase_sim.ctx.get_stats(u, X)
+    phase_sim.ctx.set_phase_timing(False)
+    phases = {k: round(v / max(st["timed_steps"], 1), 4) for k, v in st["phase_ms"].items()}
+    diagnostics = {"J_min": st["J_min"], "J_max": st["J_max"], "volume": st["volume"],
+                   "volume_change": st["volume"] / phase_sim.ctx.get_stats(None, torch.tensor(
+                       np.ascontiguousarray(prob.X_ref), dtype=torch.float64, device="cuda").contiguous())["volume"]
+                   - 1.0,
+                   "kinetic_energy": st["kinetic_energy"], "max_abs_div": st["max_abs_div"]}
+    del u, p, X
 
     mixed = None
     if not args.no_mixed:
-        msim, melapsed, _, mcyc = run(hipib.MIXED, False)
-
-        def rel(a, b):
-            return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
-        dX = sim.X - torch.tensor(prob.X0, dtype=torch.float64, device=sim.X.device)
+        msim, melapsed, mcyc = run(hipib.MIXED)
+        gpu_state["mixed"] = tuple(t.cpu().numpy() for t in (msim.u, msim.p, msim.X))
         mixed = {
             "value": round(args.steps / melapsed, 3), "unit": "steps/s",
             "ms_per_step": round(1e3 * melapsed / args.steps, 4),
-            "dtype": "f32 V-cycles, element stresses (displacement form), spread weights and interpolation; f64 outer residual, CG vectors and updates",
-            "error_vs_fp64_path": {
-                "e_u": rel(msim.u, sim.u),
-                "e_p": rel(msim.p - msim.p.mean(), sim.p - sim.p.mean()),
-                "e_X": float((msim.X - sim.X).abs().max() / dX.abs().max()),
-            },
+            "over_fp64": round(elapsed / melapsed, 3),
+            "dtype": "f32 V-cycles, element stresses (displacement form), spread weights and interpolation; "
+                     "f64 outer residual, CG vectors and updates",
             "mg_cycles_per_step": {"helmholtz_max_component": float(np.mean(mcyc[:, :3].max(1))),
                                    "poisson": float(np.mean(mcyc[:, 3]))},
         }
@@ -320,40 +468,43 @@ def main():
                 "50 steps, checkpoints every 10, FP64")
             progress("walled adjoint leg done")
 
-    larger = None
+    larger, roof192 = None, None
     if not args.no_192:
-        larger = larger_workload(torch, hipib, inputs, args.steps_192)
+        larger, lsim, lprob = workload_leg(torch, hipib, inputs, "shell_leaflets_192", args.steps_192)
+        sub = [c for c in classes if c[0] in (hipib.TIMER_SMOOTH_FINE_POISSON, hipib.TIMER_SMOOTH_FINE_HELMHOLTZ,
+                                               hipib.TIMER_RESID_RESTRICT, hipib.TIMER_PROLONG,
+                                               hipib.TIMER_CG_DIR, hipib.TIMER_CG_UPDATE, hipib.TIMER_RHS,
+                                               hipib.TIMER_SPREAD, hipib.TIMER_INTERP, hipib.TIMER_FE_FORCE)]
+        fp192 = stencil_footprint(lsim.X.cpu().numpy(), lprob.n)
+        nb192 = {hipib.TIMER_SPREAD: 52.0 * lprob.n_nodes + 16.0 * fp192,
+                 hipib.TIMER_INTERP: 52.0 * lprob.n_nodes + 8.0 * fp192}
+        tim192 = time_classes(torch, hipib, lsim, lprob, args.steps_192 * lprob.dt, 5, sub)
+        roof192 = {"workload": "shell_leaflets_192: 192^3 grid, 280,740 nodes, 243,712 hexes "
+                               "(one solver field 56.6 MB: the solve's arrays exceed the 256 MB last-level cache)",
+                   "kernels": roofline_table(hipib, tim192, sub, 5, nb192, FE_FLOP_PER_HEX * lprob.n_elems),
+                   "stencil_footprint_values": fp192}
+        del lsim
         progress("192^3 leg done")
 
     lv = None
     if not args.no_lv:
-        lv = lv_workload(torch, hipib, inputs)
+        lv, _, _ = workload_leg(torch, hipib, inputs, "lv_shell_128", 100)
+        lv["law"] = ("Holzapfel-Ogden with sheet and fibre-sheet terms + active fibre tension; "
+                     "base ring tethered axially and circumferentially")
         progress("left-ventricle-law leg done")
 
     tet = None
     if not args.no_tet:
-        tet = tet_workload(torch, hipib, inputs)
+        tet, _, _ = workload_leg(torch, hipib, inputs, "tet10_block_64", 20)
+        tet["elements"] = "P2 tetrahedra, 4-point rule"
         progress("P2-tetrahedra leg done")
 
     walled = None
     if not args.no_walls:
-        walled = walled_workload(torch, hipib, inputs)
+        walled, _, _ = workload_leg(torch, hipib, inputs, "walled_shell_64", 20)
+        walled["boundary"] = "walled box, (2n)^3 mirror-image grid"
         progress("walled-box leg done")
 
-    avg_s = kernel_ms * 1e-3 / max(launches, 1)
-    achieved = bytes_per_launch / avg_s / 1e9 if launches else 0.0
-    roofline = {
-        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(KERNELS[dom].split("<")[0]),
-        "kernel": KERNELS[dom],
-        "bytes_per_launch": bytes_per_launch, "launches": launches,
-        "avg_launch_us": round(avg_s * 1e6, 3),
-        "timing": f"HIP start/stop events stamped by each dispatch (hipExtLaunchKernel) on the library's stream, during {args.roofline_steps} "
-                  "further steps run after the timed region",
-        "other_kernels": {KERNELS[k].split(":")[0]: {"launches": v[0], "avg_launch_us": round(1e3 * v[1] / v[0], 3),
-                                                     "achieved_GBs": round(v[2] * v[0] / (v[1] * 1e-3) / 1e9, 1)}
-                          for k, v in tim.items() if k != dom and v[0] > 0},
-    }
     out = {
         "metric": METRIC,
         "value": round(steps_per_s, 3),
@@ -369,19 +520,28 @@ def main():
         "data": "synthetic",
         "config": {"workload": "ho_shell_128", "grid": prob.n, "nodes": prob.n_nodes,
                    "hexes": prob.n_elems, "pressure_quads": prob.n_faces, "dt": prob.dt,
-                   "mg": "V(2,2) red-black GS, rtol 1e-10",
+                   "mg": "Poisson: CG with one V(2,2) cycle; Helmholtz: red-black SOR (Young) at the stop level; "
+                         "rtol 1e-10",
                    "mg_cycles_per_step": {"helmholtz_max_component": float(np.mean(cyc[:, :3].max(1))),
                                           "poisson": float(np.mean(cyc[:, 3]))}},
         "roofline": roofline,
+        "phase_ms_per_step": phases,
+        "diagnostics_after_run": diagnostics,
         "mixed_precision": mixed,
         "adjoint_over_forward": adjoint,
         "shell_leaflets_192": larger,
+        "roofline_192": roof192,
         "lv_shell_128": lv,
         "tet10_block_64": tet,
         "walled_shell_64": walled,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+        if args.steps != prob.n_steps:
+            gpu_state = {}      # the parity check compares the whole 100-step run only
+        base, par = cpu_baseline_and_parity(prob, args.cpu_steps, args.cpu_one_thread_steps, gpu_state)
+        out["cpu_baseline"] = base
+        if gpu_state:
+            out["parity_vs_oracle"] = par
     print(json.dumps(out), flush=True)
 
 

@@ -195,7 +195,10 @@ hipib_status hipib_set_pressure_faces(hipib_ctx* ctx, int32_t n_faces, const int
  * -pressure * integral N_a (dx/dxi x dx/deta) over the pressure faces.
  * X, F: [n_nodes][3]. */
 hipib_status hipib_fe_force(hipib_ctx* ctx, const double* X, double pressure, double* F);
-/* f += S(X) F:  f^d[idx] += sum_q F^d_q delta_h(x^d_idx - X_q).  f: [3][n^3]. */
+/* f += S(X) F:  f^d[idx] += sum_q F^d_q delta_h(x^d_idx - X_q).  f: [3][n^3].
+ * ("Eulerian-Lagrangian coupling operators", spreading.)  Waits for
+ * completion; HIPIB_E_NUMERIC if a position is non-finite or 1e9 cells or more
+ * from the origin (such a node is spread at the origin). */
 hipib_status hipib_spread(hipib_ctx* ctx, const double* X, const double* F, double* f);
 /* hipib_spread without a context and without allocating, for callers that
  * cannot allocate device memory (code under HIP graph capture, tight serving
@@ -205,31 +208,48 @@ hipib_status hipib_spread(hipib_ctx* ctx, const double* X, const double* F, doub
  * hipStream_t (NULL: the null stream); nothing waits for completion.  The node
  * bins live in a static device workspace of 13.1 MB per GPU (held until the
  * process ends): n must be 4*2^k or 6*2^k in [8, 256] and n_nodes at most
- * 1048576, else HIPIB_E_INVAL.  Calls that overlap on one GPU (other streams,
+ * 1048576, else HIPIB_E_INVAL.  Positions are not checked (the call does not
+ * wait): a non-finite one is spread at the origin.  Calls that overlap on one GPU (other streams,
  * other threads) share that workspace and race: order them.  The first call on
  * a device looks the workspace up (HIPIB_E_HIP if that fails). */
 hipib_status hipib_spread_noalloc(int32_t n, int32_t n_nodes, const double* X, const double* F,
                                   double* f, void* stream);
-/* U := J(X) u:  U^d_q = sum_idx u^d[idx] delta_h(x^d_idx - X_q) h^3. */
+/* U := J(X) u:  U^d_q = sum_idx u^d[idx] delta_h(x^d_idx - X_q) h^3
+ * ("Eulerian-Lagrangian coupling operators", interpolation).  Waits for
+ * completion; HIPIB_E_NUMERIC for a non-finite or out-of-range position, as
+ * hipib_spread. */
 hipib_status hipib_interpolate(hipib_ctx* ctx, const double* X, const double* u, double* U);
 /* Solves (sigma I - nu Lap_h) x = b for ncomp independent components
  * (component stride n^3): Helmholtz sigma = rho/dt, nu = mu; Poisson sigma = 0,
- * nu = 1 (right-hand side must have zero mean; x is returned mean-free).
+ * nu = 1 (right-hand side must have zero mean; x is returned mean-free).  The
+ * two elliptic solves of "Spatial Discretization" (first and second
+ * equations) by the geometric multigrid the Abstract names: Poisson by
+ * conjugate gradients preconditioned with one V(pre, post) cycle (mg_krylov),
+ * Helmholtz by cycles whose hierarchy stops where the operator's Jacobi radius
+ * is at most 1/2, relaxed there by red-black SOR with Young's factor.
  * x holds the initial guess on entry.  cycles/relres: host arrays [ncomp]
- * (may be NULL).  Waits for completion. */
+ * (may be NULL).  Waits for completion.  HIPIB_E_NOCONV after mg_max_cycles
+ * cycles, HIPIB_E_NUMERIC for a non-finite residual. */
 hipib_status hipib_mg_solve(hipib_ctx* ctx, int32_t op, int32_t ncomp, const double* b,
                             double* x, int32_t* cycles, double* relres);
-/* One fluid step with force density f ([3][n^3], may be NULL = 0):
+/* One fluid step ("Spatial Discretization": the Chorin split with explicit
+ * convection, "Temporal Discretization") with force density f ([3][n^3], may
+ * be NULL = 0):
  *   ((rho/dt) I - mu Lap_h) u* = (rho/dt) u - rho C(u) + f   (guess u)
  *   (-Lap_h) p = -(rho/dt) D u* (mean removed)                 (guess p)
  *   u := u* - (dt/rho) G p.        u: [3][n^3] in/out, p: [n^3] in/out. */
 hipib_status hipib_ns_step(hipib_ctx* ctx, const double* f, double* u, double* p);
-/* One immersed-boundary step with explicit coupling: F(X^n) incl. pressure,
- * f = S(X^n)F, ns_step, X += dt J(X^n) u^{n+1}.  X: [n_nodes][3] in/out. */
+/* One immersed-boundary step with explicit coupling ("Spatial
+ * Discretization", last equation; "Eulerian-Lagrangian coupling operators"):
+ * F(X^n) incl. pressure, f = S(X^n)F, ns_step, X += dt J(X^n) u^{n+1}.
+ * X: [n_nodes][3] in/out.  HIPIB_E_NUMERIC for an inverted element (J <= 0 at
+ * a Gauss point) or a non-finite or out-of-range position. */
 hipib_status hipib_ib_step(hipib_ctx* ctx, double* u, double* p, double* X, double pressure);
-/* n_steps IB steps from time t0 with cavity pressure p0 sin^2(pi t_n / T)
- * (0 when T <= 0), t_n = t0 + n dt, and the active tension of
- * hipib_set_active_waveform when one is set. */
+/* n_steps IB steps (hipib_ib_step) from time t0 with cavity pressure
+ * hipib_cavity_pressure(p0, T, t_n) (p0 sin^2(pi t_n / T), 0 when T <= 0),
+ * t_n = t0 + n dt, and the active tension of hipib_set_active_waveform when
+ * one is set (the left-ventricle model's loading, "Dynamic left ventricle
+ * model"). */
 hipib_status hipib_advance(hipib_ctx* ctx, double* u, double* p, double* X, double t0,
                            int32_t n_steps, double p0, double T);
 
@@ -340,18 +360,59 @@ hipib_status hipib_convection_vjp(hipib_ctx* ctx, const double* u, const double*
 /* --- measurement -------------------------------------------------------- */
 /* Kernel classes that can be timed with HIP events: each timed launch goes
  * through hipExtLaunchKernel with a start and a stop event, which take the
- * dispatch's own start and end timestamps on the context's stream. */
+ * dispatch's own start and end timestamps on the stream it is launched on.
+ * The algorithmic bytes of a launch are counted per cell of the level it works
+ * on (FP64; n^3 cells, times the components the launch covers): */
 typedef enum {
     HIPIB_TIMER_OFF = 0,
-    /* one red or black Gauss-Seidel sweep on the finest level of a Poisson
-     * solve; algorithmic traffic 12 bytes per cell (read the other colour's
-     * half of x and this colour's half of b, write this colour's half of x) */
-    HIPIB_TIMER_SMOOTH_FINE_POISSON = 1
+    /* red or black Gauss-Seidel half-sweep on the finest level of a Poisson
+     * solve (not the first one from a zero guess): 12 B (read the other
+     * colour's half of x and this colour's half of b, write this colour's x) */
+    HIPIB_TIMER_SMOOTH_FINE_POISSON = 1,
+    /* over-relaxed red or black half-sweep on the finest level of a Helmholtz
+     * solve (on the iterate): 16 B per cell and component (also reads the
+     * colour's own old x) */
+    HIPIB_TIMER_SMOOTH_FINE_HELMHOLTZ = 2,
+    /* finest-level red residual and its restriction: 13 B (x, red b, coarse b) */
+    HIPIB_TIMER_RESID_RESTRICT = 3,
+    /* finest-level prolongation added to the red cells: 9 B */
+    HIPIB_TIMER_PROLONG = 4,
+    /* fused first coarse level, down half (four half-sweeps from zero,
+     * residual, restriction): 17 B per cell of that level */
+    HIPIB_TIMER_LEVEL_DOWN = 5,
+    /* fused first coarse level, up half (prolongation, four half-sweeps): 21 B */
+    HIPIB_TIMER_LEVEL_UP = 6,
+    /* the levels of at most 16^3 cells in one workgroup: 16 B per cell of its
+     * first level (b read, x written) */
+    HIPIB_TIMER_SMALL_VCYCLE = 7,
+    /* residual norm of the finest level: 16 B per cell and component */
+    HIPIB_TIMER_RESID_NORM = 8,
+    /* conjugate-gradient passes: r.z and z.q, 24 B; p, q = A z + beta q and p.q,
+     * 40 B; x, r updates and ||r||^2, 48 B */
+    HIPIB_TIMER_CG_DOTS = 9,
+    HIPIB_TIMER_CG_DIR = 10,
+    HIPIB_TIMER_CG_UPDATE = 11,
+    /* single-workgroup reductions of partials (stop tests, CG scalars): their
+     * partials, 8 B each */
+    HIPIB_TIMER_REDUCE = 12,
+    /* fluid right-hand side 48 B, divergence 32 B, velocity correction 56 B,
+     * layout conversions 16 B per cell and component */
+    HIPIB_TIMER_RHS = 13,
+    HIPIB_TIMER_DIVERGENCE = 14,
+    HIPIB_TIMER_PROJECT = 15,
+    HIPIB_TIMER_PACK = 16,
+    /* spreading, interpolation (with the position update), element forces:
+     * their bytes depend on the node positions and are not counted here
+     * (reported as 0) */
+    HIPIB_TIMER_SPREAD = 17,
+    HIPIB_TIMER_INTERP = 18,
+    HIPIB_TIMER_FE_FORCE = 19,
+    HIPIB_N_TIMERS = 20
 } hipib_timer;
 /* Selects the timed kernel class and clears earlier timings. */
 hipib_status hipib_timer_enable(hipib_ctx* ctx, int32_t which);
 /* Waits for the stream, then returns the number of timed launches, their total
- * duration in milliseconds and the algorithmic bytes one launch moves; clears
+ * duration in milliseconds and the mean algorithmic bytes per launch; clears
  * the accumulated timings. */
 hipib_status hipib_timer_read(hipib_ctx* ctx, int32_t* launches, double* total_ms,
                               double* bytes_per_launch);

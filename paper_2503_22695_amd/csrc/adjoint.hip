@@ -506,6 +506,7 @@ hipib_status adjoint_step(hipib_ctx* ctx, const double* u_n, const double* X_n, 
         HIPIB_TRY(adjoint_forces(ctx, X_n, pressure, ctx->adj_lamF, lam_X, dtheta));
     }
     HIPIB_TRY(sync_state(ctx));
+    HIPIB_TRY(position_status(ctx));
     if (ctx->st_host->numeric)
         return fail(HIPIB_E_NUMERIC, "non-positive Jacobian at a Gauss point (inverted element)");
     return HIPIB_OK;

@@ -217,6 +217,7 @@ hipib_status ib_step(hipib_ctx* ctx, double* u, double* p, double* X, double pre
     HIPIB_TRY(launch_spread(ctx, X, ctx->F, ctx->g));
     HIPIB_TRY(phase_mark(ctx, timed, 2));
     HIPIB_TRY(fluid_solves(ctx, u, p, timed));
+    HIPIB_TRY(position_status(ctx));
     if (ctx->st_host->numeric)
         return fail(HIPIB_E_NUMERIC, "non-positive Jacobian at a Gauss point (inverted element)");
     HIPIB_TRY(launch_interpolate(ctx, X, u, nullptr, X, ctx->cfg.dt));
@@ -629,9 +630,15 @@ hipib_status hipib_spread(hipib_ctx* ctx, const double* X, const double* F, doub
     if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
     if (!aligned8(f) || (ctx->nn > 0 && (!aligned8(X) || !aligned8(F))))
         return fail(HIPIB_E_INVAL, "bad pointer");
-    if (ctx->cfg.walls) return walled_spread(ctx, X, F, f);
+    if (ctx->cfg.walls) {
+        HIPIB_TRY(walled_spread(ctx, X, F, f));
+        HIPIB_TRY(sync_state(ctx->img));
+        return position_status(ctx->img);
+    }
     HIPIB_TRY(launch_bin(ctx, X));
-    return launch_spread(ctx, X, F, f);
+    HIPIB_TRY(launch_spread(ctx, X, F, f));
+    HIPIB_TRY(sync_state(ctx));
+    return position_status(ctx);
 }
 
 hipib_status hipib_interpolate(hipib_ctx* ctx, const double* X, const double* u, double* U) {
@@ -639,9 +646,15 @@ hipib_status hipib_interpolate(hipib_ctx* ctx, const double* X, const double* u,
     if (!ctx->mesh_set) return fail(HIPIB_E_STATE, "hipib_set_mesh has not been called");
     if (!aligned8(u) || (ctx->nn > 0 && (!aligned8(X) || !aligned8(U))))
         return fail(HIPIB_E_INVAL, "bad pointer");
-    if (ctx->cfg.walls) return walled_interpolate(ctx, X, u, U);
+    if (ctx->cfg.walls) {
+        HIPIB_TRY(walled_interpolate(ctx, X, u, U));
+        HIPIB_TRY(sync_state(ctx->img));
+        return position_status(ctx->img);
+    }
     HIPIB_TRY(launch_bin(ctx, X));
-    return launch_interpolate(ctx, X, u, U, nullptr, 0.0);
+    HIPIB_TRY(launch_interpolate(ctx, X, u, U, nullptr, 0.0));
+    HIPIB_TRY(sync_state(ctx));
+    return position_status(ctx);
 }
 
 hipib_status hipib_mg_solve(hipib_ctx* ctx, int32_t op, int32_t ncomp, const double* b, double* x,
@@ -763,12 +776,13 @@ hipib_status hipib_convection_vjp(hipib_ctx* ctx, const double* u, const double*
 
 hipib_status hipib_timer_enable(hipib_ctx* ctx, int32_t which) {
     HIPIB_TRY(check_ctx(ctx));
-    if (which != HIPIB_TIMER_OFF && which != HIPIB_TIMER_SMOOTH_FINE_POISSON)
+    if (which < HIPIB_TIMER_OFF || which >= HIPIB_N_TIMERS)
         return fail(HIPIB_E_INVAL, "unknown timer %d", which);
     HIPIB_HIP(hipStreamSynchronize(ctx->stream));
     ctx->timer_which = which;
     ctx->ev_used = 0;
     ctx->timer_launches = 0;
+    ctx->timer_bytes = 0.0;
     return HIPIB_OK;
 }
 
@@ -784,9 +798,11 @@ hipib_status hipib_timer_read(hipib_ctx* ctx, int32_t* launches, double* total_m
     }
     if (launches) *launches = (int32_t)ctx->timer_launches;
     if (total_ms) *total_ms = tot;
-    if (bytes_per_launch) *bytes_per_launch = ctx->timer_bytes;
+    if (bytes_per_launch)
+        *bytes_per_launch = ctx->timer_launches > 0 ? ctx->timer_bytes / (double)ctx->timer_launches : 0.0;
     ctx->ev_used = 0;
     ctx->timer_launches = 0;
+    ctx->timer_bytes = 0.0;
     return HIPIB_OK;
 }
 

@@ -227,16 +227,14 @@ namespace {
 // one element kernel per element type
 template <typename S>
 hipib_status launch_elements(hipib_ctx* ctx, const double* X, double* F, double* contrib) {
+    const dim3 grid((ctx->ne + 127) / 128);
     if (ctx->cfg.precision == HIPIB_MIXED)
-        k_fe_force<float, S, true><<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
-            X, ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats, ctx->active_ta,
-            ctx->ne, F, ctx->st, contrib);
-    else
-        k_fe_force<double, S><<<(ctx->ne + 127) / 128, 128, 0, ctx->stream>>>(
-            X, ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats, ctx->active_ta,
-            ctx->ne, F, ctx->st, contrib);
-    HIPIB_HIP(hipGetLastError());
-    return HIPIB_OK;
+        return launch_k(ctx, HIPIB_TIMER_FE_FORCE, 0.0, k_fe_force<float, S, true>, grid, dim3(128), 0, X,
+                        ctx->Xref, ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats, ctx->active_ta,
+                        ctx->ne, F, ctx->st, contrib);
+    return launch_k(ctx, HIPIB_TIMER_FE_FORCE, 0.0, k_fe_force<double, S>, grid, dim3(128), 0, X, ctx->Xref,
+                    ctx->conn, ctx->fibre, ctx->sheet, ctx->mat_id, ctx->mats, ctx->active_ta, ctx->ne, F,
+                    ctx->st, contrib);
 }
 
 hipib_status launch_element_forces(hipib_ctx* ctx, const double* X, double* F, double* contrib) {

@@ -110,10 +110,8 @@ dim3 plane_grid(int n) { return dim3((n + TX - 1) / TX, (n + TY - 1) / TY, n); }
 hipib_status launch_rhs_build_coef(hipib_ctx* ctx, const double* u, const double* f, double* g,
                                    double rho_dt, double rho_conv) {
     Grid3 G{ctx->n, ctx->n3};
-    k_rhs_build<<<plane_grid(ctx->n), dim3(TX, TY), 0, ctx->stream>>>(
-        u, f, g, G, rho_dt, rho_conv, 1.0 / ctx->h, ctx->cfg.convection);
-    HIPIB_HIP(hipGetLastError());
-    return HIPIB_OK;
+    return launch_k(ctx, HIPIB_TIMER_RHS, (f ? 72.0 : 48.0) * (double)ctx->n3, k_rhs_build, plane_grid(ctx->n),
+                    dim3(TX, TY), 0, u, f, g, G, rho_dt, rho_conv, 1.0 / ctx->h, ctx->cfg.convection);
 }
 
 hipib_status launch_rhs_build(hipib_ctx* ctx, const double* u, const double* f, double* g) {
@@ -122,10 +120,8 @@ hipib_status launch_rhs_build(hipib_ctx* ctx, const double* u, const double* f, 
 
 hipib_status launch_divergence_rhs_coef(hipib_ctx* ctx, const double* u, double* b, double coef) {
     Grid3 G{ctx->n, ctx->n3};
-    k_divergence_rhs<<<plane_grid(ctx->n), dim3(TX, TY), 0, ctx->stream>>>(u, b, G, coef,
-                                                                            1.0 / ctx->h);
-    HIPIB_HIP(hipGetLastError());
-    return HIPIB_OK;
+    return launch_k(ctx, HIPIB_TIMER_DIVERGENCE, 32.0 * (double)ctx->n3, k_divergence_rhs, plane_grid(ctx->n),
+                    dim3(TX, TY), 0, u, b, G, coef, 1.0 / ctx->h);
 }
 
 hipib_status launch_divergence_rhs(hipib_ctx* ctx, const double* u, double* b) {
@@ -134,9 +130,8 @@ hipib_status launch_divergence_rhs(hipib_ctx* ctx, const double* u, double* b) {
 
 hipib_status launch_project_coef(hipib_ctx* ctx, double* u, const double* p, double coef) {
     Grid3 G{ctx->n, ctx->n3};
-    k_project<<<plane_grid(ctx->n), dim3(TX, TY), 0, ctx->stream>>>(u, p, G, coef, 1.0 / ctx->h);
-    HIPIB_HIP(hipGetLastError());
-    return HIPIB_OK;
+    return launch_k(ctx, HIPIB_TIMER_PROJECT, 56.0 * (double)ctx->n3, k_project, plane_grid(ctx->n), dim3(TX, TY), 0,
+                    u, p, G, coef, 1.0 / ctx->h);
 }
 
 hipib_status launch_project(hipib_ctx* ctx, double* u, const double* p) {

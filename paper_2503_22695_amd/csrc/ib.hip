@@ -52,17 +52,27 @@ __global__ void __launch_bounds__(256) k_zero_i32(int32_t* __restrict__ p, int64
 // mesh mostly share a tile, so the lanes of a wavefront with equal tiles are
 // grouped and one lane adds the group's size to the count (one atomic per
 // distinct tile per wavefront instead of one per node).
+__global__ void k_clear_flag(int32_t* flag) {
+    if (threadIdx.x == 0) *flag = 0;
+}
+
+// A non-finite position, or one 1e9 cells or more from the origin, sets
+// `bad` (when given) and is binned (and later spread and interpolated) at the
+// origin, so every index stays in range; the entry points then fail with
+// HIPIB_E_NUMERIC.
 __global__ void __launch_bounds__(256)
 k_bin_count(const double* __restrict__ X, int nn, int n, int T, int ta, double inv_h,
             int32_t* __restrict__ node_tile, int32_t* __restrict__ node_rank,
-            int32_t* __restrict__ count) {
+            int32_t* __restrict__ count, int32_t* __restrict__ bad) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = q < nn;
     int tile = -1;
     if (valid) {
         int t[3];
         for (int e = 0; e < 3; ++e) {
-            const int c = (int)floor(safe_coord(X[3 * q + e] * inv_h));
+            const double r = X[3 * q + e] * inv_h;
+            if (bad && !(fabs(r) < 1.0e9)) *bad = 1;
+            const int c = (int)floor(safe_coord(r));
             t[e] = wrap_mod(c, n) / T;
         }
         tile = t[0] + ta * (t[1] + ta * t[2]);
@@ -271,9 +281,10 @@ k_interp(const double* X, const double* __restrict__ u, double* __restrict__ U, 
 hipib_status launch_bin(hipib_ctx* ctx, const double* X) {
     if (ctx->nn == 0) return HIPIB_OK;
     const int nb = (ctx->nn + 255) / 256;
+    k_clear_flag<<<1, 64, 0, ctx->stream>>>(&ctx->st->bad_position);
     k_bin_count<<<nb, 256, 0, ctx->stream>>>(X, ctx->nn, ctx->n, ctx->tile, ctx->tiles_axis,
                                              1.0 / ctx->h, ctx->node_tile, ctx->node_rank,
-                                             ctx->bin_count);
+                                             ctx->bin_count, &ctx->st->bad_position);
     k_bin_scan<<<1, 1024, 0, ctx->stream>>>(ctx->bin_count, ctx->ntiles, ctx->bin_off,
                                             ctx->tile_list, ctx->n_list);
     k_bin_scatter<<<nb, 256, 0, ctx->stream>>>(ctx->node_tile, ctx->node_rank, ctx->bin_off,
@@ -291,9 +302,9 @@ hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, dou
     const int blocks = (int)(cap < 8192 ? cap : 8192);
     const bool mixed = ctx->cfg.precision == HIPIB_MIXED;
 #define HIPIB_SPREAD(TT, TW)                                                                       \
-    k_spread_tiles<TT, TW><<<blocks, kSpreadChunk, 0, ctx->stream>>>(                                        \
-        X, F, f, ctx->perm, ctx->bin_off, ctx->tile_list, ctx->n_list, ctx->n, ctx->tiles_axis,     \
-        ctx->n3, 1.0 / h, 1.0 / (h * h * h))
+    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_SPREAD, 0.0, k_spread_tiles<TT, TW>, dim3(blocks), dim3(kSpreadChunk), 0,  \
+                       X, F, f, ctx->perm, ctx->bin_off, ctx->tile_list, ctx->n_list, ctx->n,                 \
+                       ctx->tiles_axis, ctx->n3, 1.0 / h, 1.0 / (h * h * h)))
     if (ctx->tile == 8) {
         if (mixed) HIPIB_SPREAD(8, float); else HIPIB_SPREAD(8, double);
     } else {
@@ -308,14 +319,12 @@ hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, dou
 hipib_status launch_interpolate(hipib_ctx* ctx, const double* X, const double* u, double* U,
                                 double* Xupd, double dt) {
     if (ctx->nn == 0) return HIPIB_OK;
+    const dim3 grid((ctx->nn + 255) / 256);
     if (ctx->cfg.precision == HIPIB_MIXED)
-        k_interp<float><<<(ctx->nn + 255) / 256, 256, 0, ctx->stream>>>(
-            X, u, U, Xupd, dt, ctx->nn, ctx->n, ctx->n3, 1.0 / ctx->h, ctx->perm);
-    else
-        k_interp<double><<<(ctx->nn + 255) / 256, 256, 0, ctx->stream>>>(
-            X, u, U, Xupd, dt, ctx->nn, ctx->n, ctx->n3, 1.0 / ctx->h, ctx->perm);
-    HIPIB_HIP(hipGetLastError());
-    return HIPIB_OK;
+        return launch_k(ctx, HIPIB_TIMER_INTERP, 0.0, k_interp<float>, grid, dim3(256), 0, X, u, U, Xupd, dt,
+                        ctx->nn, ctx->n, ctx->n3, 1.0 / ctx->h, ctx->perm);
+    return launch_k(ctx, HIPIB_TIMER_INTERP, 0.0, k_interp<double>, grid, dim3(256), 0, X, u, U, Xupd, dt,
+                    ctx->nn, ctx->n, ctx->n3, 1.0 / ctx->h, ctx->perm);
 }
 
 }  // namespace hipib
@@ -403,7 +412,7 @@ hipib_status hipib_spread_noalloc(int32_t n, int32_t n_nodes, const double* X, c
     const int nb = (n_nodes + 255) / 256;
     // the tile counts start at zero (a fill kernel, so the call can be captured in a graph)
     k_zero_i32<<<(unsigned)((ntiles + 255) / 256), 256, 0, st>>>(count, ntiles);
-    k_bin_count<<<nb, 256, 0, st>>>(X, n_nodes, n, T, ta, 1.0 / h, node_tile, node_rank, count);
+    k_bin_count<<<nb, 256, 0, st>>>(X, n_nodes, n, T, ta, 1.0 / h, node_tile, node_rank, count, nullptr);
     k_bin_scan<<<1, 1024, 0, st>>>(count, ntiles, off, list, nlist);
     k_bin_scatter<<<nb, 256, 0, st>>>(node_tile, node_rank, off, perm, n_nodes);
     const int blocks = (int)(cap < 8192 ? cap : 8192);

@@ -1,6 +1,7 @@
 // Internal declarations of the hipib library (gfx950).  Not part of the ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -41,7 +42,8 @@ struct MGState {
     int32_t zero_req[3];// ||b|| = 0: the solution is x = 0
     int32_t status;     // HIPIB_OK / HIPIB_E_NOCONV / HIPIB_E_NUMERIC
     int32_t numeric;    // set by the force kernel when J <= 0
-    int32_t pad[3];
+    int32_t bad_position;  // set by the node binning for a non-finite or out-of-range position
+    int32_t pad[2];
     // conjugate gradients (component 0): r.z, step alpha, direction update beta
     double rz, alpha, beta;
 };
@@ -175,7 +177,7 @@ struct hipib_ctx {
     int timer_which = 0;
     std::vector<hipEvent_t> ev_pool;   // pairs: start 2i, stop 2i+1
     size_t ev_used = 0;                // pairs recorded since the last read
-    double timer_bytes = 0.0;          // algorithmic bytes per timed launch
+    double timer_bytes = 0.0;          // algorithmic bytes of the timed launches
     int64_t timer_launches = 0;        // launches timed since the last read
 };
 
@@ -232,6 +234,13 @@ hipib_status mg_prepare(hipib_ctx* ctx);
 size_t mg_level_elem_size(const hipib_ctx* ctx);
 int64_t mg_partials_needed(int n);
 hipib_status sync_state(hipib_ctx* ctx);
+// after a binning of node positions and a synchronisation: HIPIB_E_NUMERIC if
+// a position was non-finite or out of range (it was binned at the origin)
+inline hipib_status position_status(const hipib_ctx* ctx) {
+    if (ctx->st_host->bad_position)
+        return fail(HIPIB_E_NUMERIC, "non-finite or out-of-range node position");
+    return HIPIB_OK;
+}
 // ib.hip
 hipib_status launch_bin(hipib_ctx* ctx, const double* X);
 hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, double* f);
@@ -268,6 +277,24 @@ hipib_status launch_vjp_X(hipib_ctx* ctx, const double* X, const double* field, 
 // pool (the caller launches with hipExtLaunchKernelGGL, which stamps the
 // dispatch's own start and end into them), counts the launch and returns true.
 bool timer_events(hipib_ctx* ctx, int kind, double bytes, hipEvent_t* start, hipEvent_t* stop);
+
+// Launches kernel k on the context's stream; when the timer is on for `kind`
+// (a hipib_timer; 0: never timed), through hipExtLaunchKernel with the
+// dispatch-stamped start and stop events of timer_events.  The arguments are
+// converted to the kernel's parameter types.
+template <typename... KArgs, typename... Args>
+hipib_status launch_k(hipib_ctx* ctx, int kind, double bytes, void (*k)(KArgs...), dim3 grid,
+                      dim3 block, size_t shmem, Args... args) {
+    hipEvent_t t0, t1;
+    if (kind != 0 && timer_events(ctx, kind, bytes, &t0, &t1))
+        hipExtLaunchKernelGGL(k, grid, block, (uint32_t)shmem, ctx->stream, t0, t1, 0,
+                              static_cast<KArgs>(args)...);
+    else
+        hipLaunchKernelGGL(k, grid, block, (uint32_t)shmem, ctx->stream, static_cast<KArgs>(args)...);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "kernel launch", __FILE__, __LINE__);
+    return HIPIB_OK;
+}
 
 // ---- small device helpers ----------------------------------------------------
 __device__ __forceinline__ int wrap_idx(int i, int n) {

@@ -1367,11 +1367,9 @@ double level_omega(int n, const OpCoef& oc) {
 
 hipib_status finalize(hipib_ctx* ctx, int64_t nparts, int64_t pstride, int ncomp, int mode,
                       double inv_count) {
-    k_finalize<<<1, 1024, 0, ctx->stream>>>(ctx->part, nparts, pstride, ncomp, mode, ctx->st,
-                                             ctx->cfg.mg_rtol, ctx->cfg.mg_max_cycles,
-                                             ctx->cfg.mg_fixed_cycles, inv_count);
-    HIPIB_HIP(hipGetLastError());
-    return HIPIB_OK;
+    return launch_k(ctx, HIPIB_TIMER_REDUCE, 8.0 * (double)nparts * ncomp, k_finalize, dim3(1), dim3(1024), 0,
+                    ctx->part, nparts, pstride, ncomp, mode, ctx->st, ctx->cfg.mg_rtol,
+                    ctx->cfg.mg_max_cycles, ctx->cfg.mg_fixed_cycles, inv_count);
 }
 
 template <typename T>
@@ -1414,16 +1412,17 @@ hipib_status small_vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const
     const int n = ctx->lv[l].n;
     const dim3 grid(ncomp), blk(kSmallThreads);
     const int32_t* act = ctx->st->active;
+    const double bytes = 2.0 * sizeof(T) * (double)ctx->lv[l].n3 * ncomp;
     if (n == 16)
-        k_small_vcycle<16, T><<<grid, blk, ctx->small_lds, ctx->stream>>>(p.x, p.b, p.cs, A, act);
-    else if (n == 12)
-        k_small_vcycle<12, T><<<grid, blk, ctx->small_lds, ctx->stream>>>(p.x, p.b, p.cs, A, act);
-    else if (n == 8)
-        k_small_vcycle<8, T><<<grid, blk, ctx->small_lds, ctx->stream>>>(p.x, p.b, p.cs, A, act);
-    else
-        return fail(HIPIB_E_INVAL, "no coarse-level kernel for n = %d", n);
-    HIPIB_HIP(hipGetLastError());
-    return HIPIB_OK;
+        return launch_k(ctx, HIPIB_TIMER_SMALL_VCYCLE, bytes, k_small_vcycle<16, T>, grid, blk, ctx->small_lds,
+                        p.x, p.b, p.cs, A, act);
+    if (n == 12)
+        return launch_k(ctx, HIPIB_TIMER_SMALL_VCYCLE, bytes, k_small_vcycle<12, T>, grid, blk, ctx->small_lds,
+                        p.x, p.b, p.cs, A, act);
+    if (n == 8)
+        return launch_k(ctx, HIPIB_TIMER_SMALL_VCYCLE, bytes, k_small_vcycle<8, T>, grid, blk, ctx->small_lds,
+                        p.x, p.b, p.cs, A, act);
+    return fail(HIPIB_E_INVAL, "no coarse-level kernel for n = %d", n);
 }
 
 // levels run as one k_level_down / k_level_up pair per V-cycle: the levels
@@ -1475,13 +1474,14 @@ hipib_status relax(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef
     for (int s = 0; s < 2 * sweeps; ++s) {
         const int zg = (s == 0 && zero_guess) ? 1 : 0;
         const int zo = (s < 2 && zero_guess) ? 1 : 0;
+        // timed: the finest level's half-sweeps on the iterate (16 B per cell in FP64)
+        const int kind = (l == 0 && !zo) ? HIPIB_TIMER_SMOOTH_FINE_HELMHOLTZ : 0;
         if (l == 0)
-            k_gs<T, 1, true><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, s & 1, zg, act,
-                                                           (T)omega, zo);
+            HIPIB_TRY(launch_k(ctx, kind, 2.0 * sizeof(T) * (double)ctx->lv[l].n3 * ncomp, k_gs<T, 1, true>,
+                               grid, blk, 0, p.x, p.b, n, p.cs, c, inv_diag, s & 1, zg, act, (T)omega, zo));
         else
-            k_gs<T, 0, true><<<grid, blk, 0, ctx->stream>>>(p.x, p.b, n, p.cs, c, inv_diag, s & 1, zg, act,
-                                                           (T)omega, zo);
-        HIPIB_HIP(hipGetLastError());
+            HIPIB_TRY(launch_k(ctx, 0, 0.0, k_gs<T, 0, true>, grid, blk, 0, p.x, p.b, n, p.cs, c, inv_diag,
+                               s & 1, zg, act, (T)omega, zo));
     }
     return HIPIB_OK;
 }
@@ -1529,13 +1529,13 @@ hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
         T* x2 = static_cast<T*>(ctx->lv[l].x2);
         const int nb = n / KB;
         const unsigned blocks = (unsigned)(nb * nb * nb * ncomp);
-        k_level_down<T><<<blocks, KTHREADS, 0, ctx->stream>>>(p.b, x2, n, p.cs, bc, C.n3, (T)oc.sigma,
-                                                              c, inv_diag, act);
-        HIPIB_HIP(hipGetLastError());
+        HIPIB_TRY(launch_k(ctx, l == 1 ? HIPIB_TIMER_LEVEL_DOWN : 0, 17.0 / 8.0 * sizeof(T) * (double)ctx->lv[l].n3 * ncomp,
+                           k_level_down<T>, dim3(blocks), dim3(KTHREADS), 0, p.b, x2, n, p.cs, bc, C.n3,
+                           (T)oc.sigma, c, inv_diag, act));
         HIPIB_TRY(vcycle<T>(ctx, l + 1, LevelPtr<T>{xc, bc, C.n3}, ncomp, oc, true));
-        k_level_up<T><<<blocks, KTHREADS, 0, ctx->stream>>>(p.b, x2, xc, p.x, n, p.cs, C.n3, c,
-                                                            inv_diag, act);
-        HIPIB_HIP(hipGetLastError());
+        HIPIB_TRY(launch_k(ctx, l == 1 ? HIPIB_TIMER_LEVEL_UP : 0, 21.0 / 8.0 * sizeof(T) * (double)ctx->lv[l].n3 * ncomp,
+                           k_level_up<T>, dim3(blocks), dim3(KTHREADS), 0, p.b, x2, xc, p.x, n, p.cs, C.n3, c,
+                           inv_diag, act));
         return HIPIB_OK;
     }
     if (zero_guess && pre == 0) HIPIB_TRY(zero_t<T>(ctx, p.x, ncomp * p.cs));
@@ -1544,8 +1544,10 @@ hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
     T* xc = level_x<T>(ctx, l + 1);
     T* bc = level_b<T>(ctx, l + 1);
     if (pre > 0) {
-        k_resid_restrict<T><<<resid_restrict_grid(C.n, ncomp), RTHREADS, 0, ctx->stream>>>(
-            p.x, p.b, n, p.cs, bc, C.n, C.n3, (T)oc.sigma, c, act);
+        HIPIB_TRY(launch_k(ctx, l == 0 ? HIPIB_TIMER_RESID_RESTRICT : 0,
+                           13.0 / 8.0 * sizeof(T) * (double)ctx->lv[l].n3 * ncomp, k_resid_restrict<T>,
+                           resid_restrict_grid(C.n, ncomp), dim3(RTHREADS), 0, p.x, p.b, n, p.cs, bc, C.n, C.n3,
+                           (T)oc.sigma, c, act));
     } else {
         T* r = static_cast<T*>(ctx->r0);
         k_residual<T><<<packed_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(
@@ -1556,9 +1558,10 @@ hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
     HIPIB_HIP(hipGetLastError());
     HIPIB_TRY(vcycle<T>(ctx, l + 1, LevelPtr<T>{xc, bc, C.n3}, ncomp, oc, true));
     const int nq = post > 0 ? 1 : 2;
-    k_prolong_add<T><<<dim3((n / 2 + TX - 1) / TX, (n + TY - 1) / TY, nq * n * ncomp), dim3(TX, TY), 0,
-                       ctx->stream>>>(p.x, n, p.cs, xc, C.n, C.n3, nq, act);
-    HIPIB_HIP(hipGetLastError());
+    HIPIB_TRY(launch_k(ctx, (l == 0 && nq == 1) ? HIPIB_TIMER_PROLONG : 0,
+                       9.0 / 8.0 * sizeof(T) * (double)ctx->lv[l].n3 * ncomp, k_prolong_add<T>,
+                       dim3((n / 2 + TX - 1) / TX, (n + TY - 1) / TY, nq * n * ncomp), dim3(TX, TY), 0, p.x, n,
+                       p.cs, xc, C.n, C.n3, nq, act));
     HIPIB_TRY(smooth<T>(ctx, l, p, ncomp, oc, post, 1, false));
     return HIPIB_OK;
 }
@@ -1570,13 +1573,14 @@ hipib_status resid_norm(hipib_ctx* ctx, int ncomp, const OpCoef& oc, int mode,
     const int n = ctx->n;
     const double h = 1.0 / n, c = oc.nu / (h * h);
     const int64_t np = norm_parts(n);
+    const double bytes = 16.0 * (double)ctx->n3 * ncomp;
     if (ctx->cfg.precision == HIPIB_MIXED)
-        k_resid_norm<true><<<norm_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(
-            ctx->xp, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, ctx->r32, ctx->part, np, rstore);
+        HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_RESID_NORM, bytes, k_resid_norm<true>, norm_grid(n, ncomp), dim3(TX, TY),
+                           0, ctx->xp, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, ctx->r32, ctx->part, np, rstore));
     else
-        k_resid_norm<false><<<norm_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(
-            ctx->xp, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, nullptr, ctx->part, np, rstore);
-    HIPIB_HIP(hipGetLastError());
+        HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_RESID_NORM, bytes, k_resid_norm<false>, norm_grid(n, ncomp),
+                           dim3(TX, TY), 0, ctx->xp, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, nullptr,
+                           ctx->part, np, rstore));
     return finalize(ctx, np, np, ncomp, mode, 0.0);
 }
 
@@ -1589,26 +1593,28 @@ hipib_status cg_iteration(hipib_ctx* ctx, const OpCoef& oc) {
     double *r = ctx->kv[0], *z = ctx->kv[1], *p = ctx->kv[2], *q = ctx->kv[3];
     const bool mixed = ctx->cfg.precision == HIPIB_MIXED;
     const int64_t np = norm_parts(n);
+    const double zb = mixed ? 4.0 : 8.0;   // bytes of a z value
     if (mixed) {
         HIPIB_TRY(vcycle<float>(ctx, 0, LevelPtr<float>{ctx->e32, ctx->r32, n3}, 1, oc, true));
-        k_cg_dots<float><<<nb, 256, 0, ctx->stream>>>(r, ctx->e32, q, n3, ctx->st, ctx->part, nb);
+        HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_DOTS, (16.0 + zb) * n3, k_cg_dots<float>, dim3(nb), dim3(256), 0, r,
+                           ctx->e32, q, n3, ctx->st, ctx->part, nb));
     } else {
         HIPIB_TRY(vcycle<double>(ctx, 0, LevelPtr<double>{z, r, n3}, 1, oc, true));
-        k_cg_dots<double><<<nb, 256, 0, ctx->stream>>>(r, z, q, n3, ctx->st, ctx->part, nb);
+        HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_DOTS, (16.0 + zb) * n3, k_cg_dots<double>, dim3(nb), dim3(256), 0, r,
+                           z, q, n3, ctx->st, ctx->part, nb));
     }
-    HIPIB_HIP(hipGetLastError());
-    k_cg_scalars<<<1, 1024, 0, ctx->stream>>>(ctx->part, nb, nb, CG_BETA, ctx->st);
+    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_REDUCE, 16.0 * nb, k_cg_scalars, dim3(1), dim3(1024), 0, ctx->part, nb, nb,
+                       (int)CG_BETA, ctx->st));
     if (mixed)
-        k_cg_dir<float><<<norm_grid(n, 1), dim3(TX, TY), 0, ctx->stream>>>(ctx->e32, p, q, n, oc.sigma, c,
-                                                                           ctx->st, ctx->part);
+        HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_DIR, (32.0 + zb) * n3, k_cg_dir<float>, norm_grid(n, 1), dim3(TX, TY),
+                           0, ctx->e32, p, q, n, oc.sigma, c, ctx->st, ctx->part));
     else
-        k_cg_dir<double><<<norm_grid(n, 1), dim3(TX, TY), 0, ctx->stream>>>(z, p, q, n, oc.sigma, c,
-                                                                            ctx->st, ctx->part);
-    HIPIB_HIP(hipGetLastError());
-    k_cg_scalars<<<1, 1024, 0, ctx->stream>>>(ctx->part, np, np, CG_ALPHA, ctx->st);
-    k_cg_update<<<nb, 256, 0, ctx->stream>>>(ctx->xp, r, p, q, n3, ctx->st, mixed ? ctx->r32 : nullptr,
-                                             ctx->part);
-    HIPIB_HIP(hipGetLastError());
+        HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_DIR, (32.0 + zb) * n3, k_cg_dir<double>, norm_grid(n, 1), dim3(TX, TY),
+                           0, z, p, q, n, oc.sigma, c, ctx->st, ctx->part));
+    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_REDUCE, 8.0 * np, k_cg_scalars, dim3(1), dim3(1024), 0, ctx->part, np, np,
+                       (int)CG_ALPHA, ctx->st));
+    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_UPDATE, (mixed ? 52.0 : 48.0) * n3, k_cg_update, dim3(nb), dim3(256), 0,
+                       ctx->xp, r, p, q, n3, ctx->st, mixed ? ctx->r32 : nullptr, ctx->part));
     return finalize(ctx, nb, nb, 1, FIN_CYCLE_R, 0.0);
 }
 
@@ -1643,7 +1649,7 @@ bool timer_events(hipib_ctx* ctx, int kind, double bytes, hipEvent_t* start, hip
     *start = ctx->ev_pool[2 * pair];
     *stop = ctx->ev_pool[2 * pair + 1];
     ctx->ev_used = pair + 1;
-    ctx->timer_bytes = bytes;
+    ctx->timer_bytes += bytes;
     ctx->timer_launches += 1;
     return true;
 }
@@ -1713,8 +1719,10 @@ hipib_status mg_solve(hipib_ctx* ctx, int op, int ncomp, const double* b, double
     const int n = ctx->n;
     const int nb = sum_blocks(ctx->n3);
     // pack the caller's b and initial guess
-    k_pack<<<natural_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(b, ctx->bpk, n, ctx->n3);
-    k_pack<<<natural_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(x, ctx->xp, n, ctx->n3);
+    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_PACK, 16.0 * (double)ctx->n3 * ncomp, k_pack, natural_grid(n, ncomp),
+                       dim3(TX, TY), 0, b, ctx->bpk, n, ctx->n3));
+    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_PACK, 16.0 * (double)ctx->n3 * ncomp, k_pack, natural_grid(n, ncomp),
+                       dim3(TX, TY), 0, x, ctx->xp, n, ctx->n3));
     k_state_reset<<<1, 64, 0, ctx->stream>>>(ctx->st, ncomp);
     k_sum_partials<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->bpk, ctx->n3, ctx->n3, 1, nullptr,
                                                              ctx->part, nb);
@@ -1750,8 +1758,8 @@ hipib_status mg_solve(hipib_ctx* ctx, int op, int ncomp, const double* b, double
         k_sub_mean<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->xp, ctx->n3, ctx->n3, ctx->st, 1);
         HIPIB_HIP(hipGetLastError());
     }
-    k_unpack<<<natural_grid(n, ncomp), dim3(TX, TY), 0, ctx->stream>>>(ctx->xp, x, n, ctx->n3);
-    HIPIB_HIP(hipGetLastError());
+    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_PACK, 16.0 * (double)ctx->n3 * ncomp, k_unpack, natural_grid(n, ncomp),
+                       dim3(TX, TY), 0, ctx->xp, x, n, ctx->n3));
     const MGState& s = *ctx->st_host;
     int mx = 1;
     for (int c = 0; c < ncomp; ++c) {

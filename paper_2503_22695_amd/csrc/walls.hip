@@ -307,6 +307,8 @@ hipib_status walled_ib_step(hipib_ctx* ctx, double* u, double* p, double* X, dou
     HIPIB_TRY(walled_spread(ctx, X, ctx->F, ctx->w_fbox));
     HIPIB_TRY(walled_ns_step(ctx, ctx->w_fbox, u, p));
     HIPIB_TRY(sync_state(ctx));
+    HIPIB_TRY(sync_state(ctx->img));
+    HIPIB_TRY(position_status(ctx->img));
     if (ctx->st_host->numeric)
         return fail(HIPIB_E_NUMERIC, "non-positive Jacobian at a Gauss point (inverted element)");
     // U = J(X^n) u^{n+1} on the image grid (the bins of X^n / 2 are current), X += dt U
@@ -380,6 +382,8 @@ hipib_status walled_adjoint_step(hipib_ctx* ctx, const double* u_n, const double
         HIPIB_TRY(adjoint_forces(ctx, X_n, pressure, ctx->adj_lamF, lam_X, dtheta));
     }
     HIPIB_TRY(sync_state(ctx));
+    HIPIB_TRY(sync_state(ctx->img));
+    HIPIB_TRY(position_status(ctx->img));
     if (ctx->st_host->numeric)
         return fail(HIPIB_E_NUMERIC, "non-positive Jacobian at a Gauss point (inverted element)");
     return HIPIB_OK;

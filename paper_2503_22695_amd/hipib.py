@@ -23,7 +23,10 @@ OK, E_INVAL, E_NOMEM, E_HIP, E_NOCONV, E_NUMERIC, E_STATE = range(7)
 FP64, MIXED = 0, 1
 NEO_HOOKEAN, HOLZAPFEL_OGDEN = 0, 1
 OP_HELMHOLTZ, OP_POISSON = 0, 1
-TIMER_OFF, TIMER_SMOOTH_FINE_POISSON = 0, 1
+(TIMER_OFF, TIMER_SMOOTH_FINE_POISSON, TIMER_SMOOTH_FINE_HELMHOLTZ, TIMER_RESID_RESTRICT, TIMER_PROLONG,
+ TIMER_LEVEL_DOWN, TIMER_LEVEL_UP, TIMER_SMALL_VCYCLE, TIMER_RESID_NORM, TIMER_CG_DOTS, TIMER_CG_DIR,
+ TIMER_CG_UPDATE, TIMER_REDUCE, TIMER_RHS, TIMER_DIVERGENCE, TIMER_PROJECT, TIMER_PACK, TIMER_SPREAD,
+ TIMER_INTERP, TIMER_FE_FORCE) = range(20)   # hipib_timer
 MAX_MATERIALS = 8
 
 

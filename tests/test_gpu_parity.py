@@ -345,3 +345,54 @@ def test_error_paths(torch_dev, hp):
     with pytest.raises(hp.HipIBError) as e:
         ctx.ib_step(u, p, to_dev(torch, prob.X0), 0.0)
     assert e.value.status == hp.E_NUMERIC
+
+
+def test_numeric_and_convergence_errors(torch_dev, hp):
+    """A non-finite or far-away node position fails spreading, interpolation
+    and the step with E_NUMERIC (the node is binned at the origin, so no index
+    leaves the grid); a solve capped at one cycle fails with E_NOCONV; the
+    context stays usable after each."""
+    torch = torch_dev
+    say("numeric / noconv errors")
+    n = 32
+    rng = np.random.default_rng(9)
+    X = rng.uniform(0.2, 0.8, (50, 3))
+    ctx = plain_ctx(hp, n)
+    ctx.set_mesh(X, np.zeros((0, 8)), np.zeros((0, 3)), np.zeros(0))
+    f = torch.zeros((3, n, n, n), dtype=torch.float64, device="cuda")
+    u = to_dev(torch, rng.standard_normal((3, n, n, n)))
+    for bad in (float("nan"), float("inf"), 1e12):
+        Xb = X.copy()
+        Xb[7, 1] = bad
+        Xd, Fd = to_dev(torch, Xb), to_dev(torch, rng.standard_normal((50, 3)))
+        with pytest.raises(hp.HipIBError) as e:
+            ctx.spread(Xd, Fd, f)
+        assert e.value.status == hp.E_NUMERIC
+        with pytest.raises(hp.HipIBError) as e:
+            ctx.interpolate(Xd, u)
+        assert e.value.status == hp.E_NUMERIC
+    # the good positions work again on the same context
+    f.zero_()
+    ctx.spread(to_dev(torch, X), to_dev(torch, np.ones((50, 3))), f)
+    torch.cuda.synchronize()
+    assert abs(float(f.sum()) * (1.0 / n) ** 3 - 150.0) <= 1e-10 * 150.0
+    # the step
+    prob = inputs.neo_hookean_block()
+    sctx = hp.context_for_problem(prob)
+    Xs = prob.X0.copy()
+    Xs[3, 0] = float("nan")
+    ud = torch.zeros((3, 32, 32, 32), dtype=torch.float64, device="cuda")
+    pd = torch.zeros((32, 32, 32), dtype=torch.float64, device="cuda")
+    with pytest.raises(hp.HipIBError) as e:
+        sctx.ib_step(ud, pd, to_dev(torch, Xs), 0.0)
+    assert e.value.status == hp.E_NUMERIC
+    # E_NOCONV: one V-cycle cannot reach 1e-10 on a rough right-hand side
+    b = rng.standard_normal((n, n, n))
+    b -= b.mean()
+    cctx = plain_ctx(hp, n, mg_max_cycles=1, mg_krylov=0)
+    x = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    with pytest.raises(hp.HipIBError) as e:
+        cctx.mg_solve(hp.OP_POISSON, to_dev(torch, b), x)
+    assert e.value.status == hp.E_NOCONV
+    cyc, rr = plain_ctx(hp, n).mg_solve(hp.OP_POISSON, to_dev(torch, b), x)
+    assert rr[0] <= 1e-10
