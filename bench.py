@@ -483,6 +483,8 @@ def main():
                                "(one solver field 56.6 MB: the solve's arrays exceed the 256 MB last-level cache)",
                    "kernels": roofline_table(hipib, tim192, sub, 5, nb192, FE_FLOP_PER_HEX * lprob.n_elems),
                    "stencil_footprint_values": fp192}
+        if "k_gs<double,2>" in roof192["kernels"]:
+            roof192["kernels"]["k_gs<double,2>"]["traffic"] = measured_traffic("k_gs", "192")
         del lsim
         progress("192^3 leg done")
 
