@@ -269,7 +269,7 @@ class MeshBuffers:
 
 
 def fluid(n, rho=1.0, mu=0.01, dt=1e-3, rtol=1e-10, pre=2, post=2, max_cycles=50,
-          fixed_cycles=0, coarse_sweeps=16, convection=1, krylov=1, walls=0) -> Fluid:
+          fixed_cycles=0, coarse_sweeps=0, convection=1, krylov=1, walls=0) -> Fluid:
     return Fluid(n, rho, mu, dt, pre, post, max_cycles, fixed_cycles, coarse_sweeps, rtol,
                  convection, krylov, walls)
 

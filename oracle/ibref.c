@@ -625,8 +625,11 @@ void ibref_pressure_load(int32_t n_faces, const int32_t* faces, const double* x,
  *   restriction: per axis weights (1,3,3,1)/8 over fine cells 2I-1 .. 2I+2;
  *   prolongation: cell-centred trilinear (3/4, 1/4 per axis), added to x;
  *   coarse operators rediscretised at 2h; the coarsest level is the first
- *   with fewer than 8 cells per side, solved by mg_coarse_sweeps red+black
- *   sweeps;
+ *   with at most 16 cells per side, solved exactly (mg_coarse_sweeps = 0: the
+ *   periodic operator is diagonalised by the discrete Fourier modes, with
+ *   eigenvalues sigma + nu (4/h^2) sum_d sin^2(pi k_d / n); Poisson drops the
+ *   k = 0 mode), or the first with fewer than 8 cells, solved by
+ *   mg_coarse_sweeps red+black sweeps (mg_coarse_sweeps > 0);
  *   Poisson (sigma = 0): the mean is removed after the coarse solve
  *   and once from the final solution (the residual and the sweeps are
  *   invariant to adding a constant, so the iterates need no mean removal).
@@ -646,7 +649,7 @@ void ibref_pressure_load(int32_t n_faces, const int32_t* faces, const double* x,
  *     red then black (one ordering throughout: reversing it, as the V-cycle's
  *     post-smoothing does, repeats a colour and loses the SOR rate);
  *   0 < l < coarsest: max(mg_pre, 1) sweeps (red, black) from zero;
- *   the coarsest: mg_coarse_sweeps sweeps from zero.
+ *   the coarsest: its exact solve, or mg_coarse_sweeps sweeps from zero.
  * The other Helmholtz levels and every Poisson level keep plain Gauss-Seidel
  * (omega = 1).
  * Stop rule: ||b - A x||_2 <= max(rtol, 1e3 eps) ||b||_2, tested before the
@@ -787,31 +790,102 @@ static void mg_free(mg_levels* lv) {
     for (int l = 0; l < lv->L; ++l) { free(lv->x[l]); free(lv->b[l]); free(lv->r[l]); }
 }
 
+/* the coarsest level of the hierarchy (see above) */
+static int hierarchy_bottom(const ibref_fluid* fl, const mg_levels* lv) {
+    if (fl->mg_coarse_sweeps > 0) return lv->L - 1;
+    for (int l = 0; l < lv->L; ++l)
+        if (lv->n[l] <= 16) return l;
+    return lv->L - 1;
+}
+
 /* the level at which the cycle stops descending (see above) */
-static int coarsest_level(const mg_levels* lv, double sigma, double nu) {
+static int coarsest_level(const ibref_fluid* fl, const mg_levels* lv, double sigma, double nu) {
+    const int bottom = hierarchy_bottom(fl, lv);
     if (sigma > 0.0)
-        for (int l = 0; l < lv->L - 1; ++l) {
+        for (int l = 0; l < bottom; ++l) {
             const double h = 1.0 / lv->n[l];
             if (sigma >= 6.0 * nu / (h * h)) return l;
         }
-    return lv->L - 1;
+    return bottom;
+}
+
+/* Exact solve of (sigma - nu Lap_h) x = b on the periodic n^3 grid by its
+ * discrete Fourier diagonalisation: bhat = F b (F_kj = e^{-2 pi i k.j / n},
+ * one axis after another), xhat = bhat / lambda_k with
+ * lambda_k = sigma + nu (4/h^2) sum_d sin^2(pi k_d / n), x = Re F^{-1} xhat;
+ * for Poisson (sigma = 0) the k = 0 mode (lambda = 0) is dropped, so x has zero
+ * mean.  Plain O(n^4) transforms. */
+static void coarse_exact(int n, double sigma, double nu, const double* b, double* x) {
+    const double pi = 3.14159265358979323846;
+    const long N3 = (long)n * n * n;
+    double* re = (double*)malloc(sizeof(double) * (size_t)N3);
+    double* im = (double*)malloc(sizeof(double) * (size_t)N3);
+    double* tr = (double*)malloc(sizeof(double) * (size_t)n);
+    double* ti = (double*)malloc(sizeof(double) * (size_t)n);
+    for (long t = 0; t < N3; ++t) { re[t] = b[t]; im[t] = 0.0; }
+    for (int dir = -1; dir <= 1; dir += 2) {          /* forward, then inverse */
+        for (int ax = 0; ax < 3; ++ax) {
+            const long stride = ax == 0 ? 1 : (ax == 1 ? n : (long)n * n);
+            for (long line = 0; line < (long)n * n; ++line) {
+                /* first cell of the line: the other two indices from `line` */
+                const long a = line % n, c = line / n;
+                long base;
+                if (ax == 0) base = n * (a + (long)n * c);
+                else if (ax == 1) base = a + (long)n * n * c;
+                else base = a + (long)n * c;
+                for (int k = 0; k < n; ++k) {
+                    double sr = 0.0, si = 0.0;
+                    for (int j = 0; j < n; ++j) {
+                        const double ang = dir * 2.0 * pi * (double)((long)k * j % n) / n;
+                        const double cr = cos(ang), ci = sin(ang);
+                        const double vr = re[base + j * stride], vi = im[base + j * stride];
+                        sr += vr * cr - vi * ci;
+                        si += vr * ci + vi * cr;
+                    }
+                    tr[k] = sr;
+                    ti[k] = si;
+                }
+                for (int k = 0; k < n; ++k) { re[base + k * stride] = tr[k]; im[base + k * stride] = ti[k]; }
+            }
+        }
+        if (dir == -1) {
+            const double h = 1.0 / n;
+            for (int k3 = 0; k3 < n; ++k3)
+                for (int k2 = 0; k2 < n; ++k2)
+                    for (int k1 = 0; k1 < n; ++k1) {
+                        const double s1 = sin(pi * k1 / n), s2 = sin(pi * k2 / n), s3 = sin(pi * k3 / n);
+                        const double lam = sigma + nu * (4.0 / (h * h)) * (s1 * s1 + s2 * s2 + s3 * s3);
+                        const long t = gidx(k1, k2, k3, n);
+                        if (lam == 0.0) { re[t] = 0.0; im[t] = 0.0; }
+                        else { re[t] /= lam * (double)N3; im[t] /= lam * (double)N3; }
+                    }
+        }
+    }
+    for (long t = 0; t < N3; ++t) x[t] = re[t];
+    free(re); free(im); free(tr); free(ti);
 }
 
 static void vcycle(const ibref_fluid* fl, mg_levels* lv, int l, double sigma, double nu,
                    int poisson, const double* b, double* x) {
     int n = lv->n[l];
     long N3 = (long)n * n * n;
-    const int lc = coarsest_level(lv, sigma, nu);
+    const int bottom = hierarchy_bottom(fl, lv);
+    const int lc = coarsest_level(fl, lv, sigma, nu);
+    if (l == lc && lc == bottom && fl->mg_coarse_sweeps == 0) {
+        coarse_exact(n, sigma, nu, b, x);
+        if (poisson) remove_mean(N3, x);
+        return;
+    }
     if (l == lc) {
         const double w = level_omega(n, sigma, nu);
-        if (l == 0 && lc < lv->L - 1) {
+        if (l == 0 && lc < bottom) {
             for (int s = 0; s < fl->mg_pre + fl->mg_post; ++s) {
                 gs_colour(n, sigma, nu, b, x, 0, w);
                 gs_colour(n, sigma, nu, b, x, 1, w);
             }
             return;
         }
-        const int sweeps = lc == lv->L - 1 ? fl->mg_coarse_sweeps : (fl->mg_pre > 1 ? fl->mg_pre : 1);
+        const int sweeps = lc == bottom ? fl->mg_coarse_sweeps : (fl->mg_pre > 1 ? fl->mg_pre : 1);
         for (int s = 0; s < sweeps; ++s) {
             gs_colour(n, sigma, nu, b, x, 0, w);
             gs_colour(n, sigma, nu, b, x, 1, w);

@@ -46,7 +46,10 @@ typedef struct {
     int32_t mg_pre, mg_post;   /* smoothing sweeps (red+black pairs) */
     int32_t mg_max_cycles;     /* > this many V-cycles: no convergence */
     int32_t mg_fixed_cycles;   /* > 0: run exactly this many cycles, no stop test */
-    int32_t mg_coarse_sweeps;  /* red+black sweeps on the coarsest level */
+    int32_t mg_coarse_sweeps;  /* 0: the coarsest level is the first with at most 16 cells
+                                  per side, solved exactly by its Fourier diagonalisation;
+                                  > 0: the first with fewer than 8, relaxed by this many
+                                  red+black sweeps */
     double mg_rtol;            /* stop when ||r|| <= rtol ||b|| */
     int32_t convection;        /* 1: explicit flux-form convection, 0: Stokes */
     int32_t mg_krylov;         /* 1: Poisson solves by conjugate gradients preconditioned

@@ -89,11 +89,14 @@ def test_zero_rhs_and_error_paths(ref):
     fl = ref.fluid(n)
     x, cyc, rr = ref.mg_solve(fl, 0.0, 1.0, True, np.zeros((n, n, n)), np.ones((n, n, n)))
     assert cyc == 0 and np.all(x == 0)
-    b = np.random.default_rng(1).standard_normal((n, n, n))
+    m = 32   # (a 16^3 grid is its own coarsest level, solved exactly in one cycle)
+    b = np.random.default_rng(1).standard_normal((m, m, m))
     b -= b.mean()
     with pytest.raises(oracle.OracleError) as e:
-        ref.mg_solve(ref.fluid(n, max_cycles=1), 0.0, 1.0, True, b)
+        ref.mg_solve(ref.fluid(m, max_cycles=1), 0.0, 1.0, True, b)
     assert e.value.rc == oracle.E_NOCONV
+    b = np.random.default_rng(1).standard_normal((n, n, n))
+    b -= b.mean()
     b[3, 2, 1] = np.nan
     with pytest.raises(oracle.OracleError) as e:
         ref.mg_solve(fl, 0.0, 1.0, True, b)
@@ -121,8 +124,9 @@ def neg_lap(x):
 
 def test_krylov_first_step_is_energy_optimal_multiple_of_the_vcycle(ref):
     """One preconditioned-CG iteration from x = 0 is alpha z with z one V-cycle
-    applied to b and alpha = (b.z)/(z.Az), the energy-minimising step."""
-    n = 16
+    applied to b and alpha = (b.z)/(z.Az), the energy-minimising step (on 32^3:
+    a 16^3 grid is its own coarsest level, solved exactly, so alpha would be 1)."""
+    n = 32
     rng = np.random.default_rng(3)
     b = rng.standard_normal((n, n, n))
     b -= b.mean()
@@ -181,7 +185,7 @@ def test_helmholtz_relaxation_matches_numpy_sor():
     four sweeps (V(2,2): pre + post), each red then black, each colour
     x += omega ((b + c * neighbour sum) / diag - x)."""
     import oracle
-    n, nu, sigma = 16, 0.01, 50.0
+    n, nu, sigma = 32, 0.01, 100.0
     rho, w = young_omega(n, sigma, nu)
     assert rho <= 0.5
     rng = np.random.default_rng(8)
@@ -199,3 +203,27 @@ def test_helmholtz_relaxation_matches_numpy_sor():
         g = (b + c * s) / diag
         y[mask] = y[mask] + w * (g[mask] - y[mask])
     assert np.max(np.abs(x - y)) <= 1e-13 * np.max(np.abs(y))
+
+
+def test_coarsest_level_is_solved_exactly():
+    """With mg_coarse_sweeps = 0 a grid of at most 16 cells per side is its own
+    coarsest level, solved by its Fourier diagonalisation: one cycle reaches the
+    FFT solution (numpy.fft) to rounding, for Poisson (mean-free) and
+    Helmholtz, at 16^3, 12^3 and 8^3; with coarse sweeps the old hierarchy
+    (down to 4^3 or 6^3) is kept."""
+    import oracle
+    for n in (16, 12, 8):
+        rng = np.random.default_rng(40 + n)
+        b = rng.standard_normal((n, n, n))
+        for sigma, nu, poisson in ((0.0, 1.0, True), (3.0, 0.7, False)):
+            bb = b - b.mean() if poisson else b
+            fl = oracle.fluid(n, fixed_cycles=1, krylov=0)
+            x, cyc, rr = oracle.mg_solve(fl, sigma, nu, poisson, bb)
+            xf = fft_solve(bb, sigma, nu)
+            assert cyc == 1 and rr <= 1e-13, (n, sigma, rr)
+            assert np.max(np.abs(x - xf)) <= 1e-13 * np.max(np.abs(xf)), (n, sigma)
+    # the sweep-based coarsest level needs several cycles on 16^3
+    b = np.random.default_rng(7).standard_normal((16, 16, 16))
+    b -= b.mean()
+    _, cyc, _ = oracle.mg_solve(oracle.fluid(16, coarse_sweeps=16, krylov=0), 0.0, 1.0, True, b)
+    assert cyc > 3
