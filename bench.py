@@ -226,7 +226,8 @@ def kernel_classes(hipib):
         (H.TIMER_PROLONG, "k_prolong_add<double>", "finest-level prolongation to the red cells, 9 B/cell"),
         (H.TIMER_LEVEL_DOWN, "k_level_down<double>", "first coarse level, down half, 17 B per cell of that level"),
         (H.TIMER_LEVEL_UP, "k_level_up<double>", "first coarse level, up half, 21 B per cell of that level"),
-        (H.TIMER_SMALL_VCYCLE, "k_small_vcycle<16,double>", "levels <= 16^3 in one workgroup, 16 B per 16^3 cell"),
+        (H.TIMER_SMALL_VCYCLE, "k_coarse_exact<16,double>",
+         "coarsest level (16^3) solved exactly in one workgroup, 16 B per 16^3 cell"),
         (H.TIMER_RESID_NORM, "k_resid_norm<false>", "residual norm, 16 B/cell per component"),
         (H.TIMER_CG_DOTS, "k_cg_dots<double>", "r.z and z.q, 24 B/cell"),
         (H.TIMER_CG_DIR, "k_cg_dir<double>", "p, q = A z + beta q and p.q, 40 B/cell"),

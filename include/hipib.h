@@ -74,7 +74,10 @@ typedef struct {
                                  coarse-grid correction (V(2,2): 2, 2) */
     int32_t mg_max_cycles;    /* more cycles than this: HIPIB_E_NOCONV */
     int32_t mg_fixed_cycles;  /* > 0: exactly this many cycles, no stop test */
-    int32_t mg_coarse_sweeps; /* red+black sweeps on the coarsest level (16) */
+    int32_t mg_coarse_sweeps; /* 0 (default): the coarsest level is the first with at
+                                 most 16 cells per side, solved exactly by its Fourier
+                                 diagonalisation; > 0: the first with fewer than 8,
+                                 relaxed by this many red+black sweeps */
     double mg_rtol;           /* stop when ||b - A x||_2 <= rtol ||b||_2 */
     int32_t convection;       /* 1: explicit flux-form convection; 0: Stokes */
     int32_t precision;        /* hipib_precision */
@@ -101,7 +104,7 @@ typedef struct {
                                  hipib_convection_vjp) return HIPIB_E_STATE. */
 } hipib_config;
 
-/* Fills cfg with the defaults: V(2,2), 16 coarse sweeps, rtol 1e-10, 50 cycles,
+/* Fills cfg with the defaults: V(2,2), exact coarsest solve, rtol 1e-10, 50 cycles,
  * convection on, FP64, atomic mode, Krylov Poisson solves, periodic box;
  * n/rho/mu/dt are set to 32/1/0.01/1e-3. */
 void hipib_default_config(hipib_config* cfg);
@@ -382,8 +385,9 @@ typedef enum {
     HIPIB_TIMER_LEVEL_DOWN = 5,
     /* fused first coarse level, up half (prolongation, four half-sweeps): 21 B */
     HIPIB_TIMER_LEVEL_UP = 6,
-    /* the levels of at most 16^3 cells in one workgroup: 16 B per cell of its
-     * first level (b read, x written) */
+    /* the coarsest level in one workgroup (its exact solve, or with
+     * mg_coarse_sweeps > 0 the levels of at most 16^3 cells): 16 B per cell of
+     * that level (b read, x written) */
     HIPIB_TIMER_SMALL_VCYCLE = 7,
     /* residual norm of the finest level: 16 B per cell and component */
     HIPIB_TIMER_RESID_NORM = 8,

@@ -138,6 +138,8 @@ void free_all(hipib_ctx* ctx) {
     (void)hipFree(ctx->adj_p);
     (void)hipFree(ctx->adj_sX);
     (void)hipFree(ctx->adj_lamF);
+    (void)hipFree(ctx->coarse_tab);
+    (void)hipFree(ctx->coarse_tab32);
     for (hipEvent_t e : ctx->ph_ev)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->ph_force)
@@ -241,7 +243,7 @@ void hipib_default_config(hipib_config* cfg) {
     cfg->mg_post = 2;
     cfg->mg_max_cycles = 50;
     cfg->mg_fixed_cycles = 0;
-    cfg->mg_coarse_sweeps = 16;
+    cfg->mg_coarse_sweeps = 0;
     cfg->mg_rtol = 1e-10;
     cfg->convection = 1;
     cfg->precision = HIPIB_FP64;
@@ -268,7 +270,7 @@ hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out
     if (!(cfg->rho > 0) || !(cfg->mu > 0) || !(cfg->dt > 0))
         return fail(HIPIB_E_INVAL, "rho, mu and dt must be positive");
     if (cfg->mg_pre < 0 || cfg->mg_post < 0 || cfg->mg_max_cycles < 1 || cfg->mg_fixed_cycles < 0 ||
-        cfg->mg_coarse_sweeps < 1 || !(cfg->mg_rtol >= 0))
+        cfg->mg_coarse_sweeps < 0 || !(cfg->mg_rtol >= 0))
         return fail(HIPIB_E_INVAL, "invalid multigrid parameters");
     if (cfg->precision != HIPIB_FP64 && cfg->precision != HIPIB_MIXED)
         return fail(HIPIB_E_INVAL, "unknown precision %d", cfg->precision);

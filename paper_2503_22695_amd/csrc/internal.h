@@ -77,6 +77,10 @@ struct hipib_ctx {
     int L = 0;              // number of levels
     int small_start = 0;    // first level run by the single-workgroup kernel
     size_t small_lds = 0;   // its dynamic LDS bytes
+    // exact solve of the coarsest level (mg_coarse_sweeps = 0): the level's real
+    // Fourier basis Q [N][N] and eigenvalue factors s [N], FP64 and FP32 copies
+    double* coarse_tab = nullptr;
+    float* coarse_tab32 = nullptr;
     hipib::Level lv[hipib::kMaxLevels];
     void* r0 = nullptr;     // [3][n3] residual scratch of the V-cycle type (any level)
     double* xp = nullptr;   // [3][n3] packed FP64 solution of the current solve

@@ -42,6 +42,7 @@
 // once to read them.
 #include <cfloat>
 #include <cmath>
+#include <vector>
 
 #include <hip/hip_ext.h>
 
@@ -808,6 +809,91 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// ---------------------------------------------------------------------------
+// Exact solve of the coarsest level (at most 16 cells per side) of the periodic
+// operator sigma I - nu Lap_h, in one workgroup per component:
+//   x = Q3 diag(1 / lambda) Q3^T b,  Q3 = Q (x) Q (x) Q,
+// with Q the level's real orthonormal Fourier basis (columns: the constant,
+// sqrt(2/N) cos(2 pi f j / N) for f = 1 .. N/2 - 1, the alternating (-1)^j,
+// sqrt(2/N) sin(2 pi f j / N)) and lambda = sigma + nu (s[m1] + s[m2] + s[m3]),
+// s[m] = (4 / h^2) sin^2(pi f(m) / N); lambda = 0 (the Poisson constant mode) is
+// dropped.  The three forward and three inverse passes each transform the
+// slowest axis of the LDS array and write its index as the fastest of the next
+// layout (x, y, z -> mz, x, y -> my, mz, x -> mx, my, mz -> ... -> x, y, z), so
+// a wavefront's lanes read consecutive cells; rows are padded to N + 1 values.
+// A thread computes CG consecutive outputs of one line; for N = 16 a wavefront's
+// output group is uniform, so its coefficients come through the scalar cache.
+// ---------------------------------------------------------------------------
+constexpr int kExactThreads = 1024, kExactGroup = 4;
+
+template <int N>
+constexpr int exact_lds_words() { return 2 * (N + 1) * N * N; }
+
+template <int N, typename T>
+__device__ __forceinline__ void exact_pass(const T* __restrict__ in, T* __restrict__ out,
+                                           const T* __restrict__ Q, bool forward) {
+    constexpr int NP = N + 1, R = N * N, G = N / kExactGroup;
+    const int t = threadIdx.x;
+    if (t >= R * G) return;
+    int grp = t / R;
+    if constexpr ((R % 64) == 0) grp = __builtin_amdgcn_readfirstlane(grp);
+    const int r = t - grp * R;
+    const int f = r % N, sdx = r / N;        // fastest and middle index of the input layout
+    T v[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) v[a] = in[f + NP * sdx + NP * N * a];
+#pragma unroll
+    for (int u = 0; u < kExactGroup; ++u) {
+        const int o = grp * kExactGroup + u;
+        T acc = T(0);
+#pragma unroll
+        for (int a = 0; a < N; ++a) acc += (forward ? Q[a * N + o] : Q[o * N + a]) * v[a];
+        out[o + NP * f + NP * N * sdx] = acc;
+    }
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(kExactThreads)
+k_coarse_exact(T* __restrict__ xg, const T* __restrict__ bg, int64_t cs, const T* __restrict__ tab,
+               T sigma, T nu, const int32_t* __restrict__ active) {
+    extern __shared__ unsigned char lds_raw[];
+    constexpr int NP = N + 1, N3 = N * N * N;
+    T* A = reinterpret_cast<T*>(lds_raw);
+    T* B = A + NP * N * N;
+    const int comp = blockIdx.x;
+    if (!active[comp]) return;
+    const T* Q = tab;
+    const T* sv = tab + N * N;
+    for (int o = threadIdx.x; o < N3; o += kExactThreads) {
+        const int i = o % N, j = (o / N) % N, k = o / (N * N);
+        A[i + NP * j + NP * N * k] = bg[comp * cs + pkc<N>(i, j, k)];
+    }
+    __syncthreads();
+    exact_pass<N>(A, B, Q, true);     // z
+    __syncthreads();
+    exact_pass<N>(B, A, Q, true);     // y
+    __syncthreads();
+    exact_pass<N>(A, B, Q, true);     // x: B holds (mx, my, mz)
+    __syncthreads();
+    for (int o = threadIdx.x; o < N3; o += kExactThreads) {
+        const int m1 = o % N, m2 = (o / N) % N, m3 = o / (N * N);
+        const T lam = sigma + nu * (sv[m1] + sv[m2] + sv[m3]);
+        T* v = B + m1 + NP * m2 + NP * N * m3;
+        *v = lam != T(0) ? *v / lam : T(0);
+    }
+    __syncthreads();
+    exact_pass<N>(B, A, Q, false);    // z
+    __syncthreads();
+    exact_pass<N>(A, B, Q, false);    // y
+    __syncthreads();
+    exact_pass<N>(B, A, Q, false);    // x: A holds (x, y, z)
+    __syncthreads();
+    for (int o = threadIdx.x; o < N3; o += kExactThreads) {
+        const int i = o % N, j = (o / N) % N, k = o / (N * N);
+        xg[comp * cs + pkc<N>(i, j, k)] = A[i + NP * j + NP * N * k];
+    }
+}
+
 // sum of the six neighbours (order i+1, i-1, j+1, j-1, k+1, k-1) of the
 // colour-q cell at packed position (ih, j, k), from the other colour's half xo
 template <int N, typename T>
@@ -1338,13 +1424,20 @@ OpCoef op_coef(const hipib_ctx* ctx, int op) {
 // a coarse-grid correction adds less than its sweeps would), relaxed there
 // with that level's omega.  Otherwise (and for Poisson) the coarsest level
 // is the first with fewer than 8 cells per side.
+// The coarsest level: with mg_coarse_sweeps = 0 the first with at most 16 cells
+// per side, solved exactly (k_coarse_exact); otherwise the first with fewer
+// than 8, relaxed by the coarse sweeps.
+bool exact_coarse(const hipib_ctx* ctx) { return ctx->cfg.mg_coarse_sweeps == 0; }
+int bottom_level(const hipib_ctx* ctx) { return exact_coarse(ctx) ? ctx->small_start : ctx->L - 1; }
+
 int stop_level(const hipib_ctx* ctx, const OpCoef& oc) {
+    const int bottom = bottom_level(ctx);
     if (oc.sigma > 0.0)
-        for (int l = 0; l < ctx->L - 1; ++l) {
+        for (int l = 0; l < bottom; ++l) {
             const double h = 1.0 / ctx->lv[l].n;
             if (oc.sigma >= 6.0 * oc.nu / (h * h)) return l;
         }
-    return ctx->L - 1;
+    return bottom;
 }
 
 // red+black sweeps that relax the level a cycle stops at: the coarse sweeps
@@ -1352,7 +1445,7 @@ int stop_level(const hipib_ctx* ctx, const OpCoef& oc) {
 // level is the stop (the cycle has no coarse levels), else max(pre, 1) from
 // zero
 int stop_sweeps(const hipib_ctx* ctx, int lc) {
-    if (lc == ctx->L - 1) return ctx->cfg.mg_coarse_sweeps;
+    if (lc == bottom_level(ctx)) return ctx->cfg.mg_coarse_sweeps;
     if (lc == 0) return ctx->cfg.mg_pre + ctx->cfg.mg_post;
     return ctx->cfg.mg_pre > 1 ? ctx->cfg.mg_pre : 1;
 }
@@ -1394,6 +1487,33 @@ template <typename T>
 T* level_x(hipib_ctx* ctx, int l) { return static_cast<T*>(ctx->lv[l].x); }
 template <typename T>
 T* level_b(hipib_ctx* ctx, int l) { return static_cast<T*>(ctx->lv[l].b); }
+
+template <typename T>
+const T* exact_table(const hipib_ctx* ctx);
+template <>
+const double* exact_table<double>(const hipib_ctx* ctx) { return ctx->coarse_tab; }
+template <>
+const float* exact_table<float>(const hipib_ctx* ctx) { return ctx->coarse_tab32; }
+
+// exact solve of the coarsest level l (the first with at most 16 cells per side)
+template <typename T>
+hipib_status coarse_exact(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef& oc) {
+    const int n = ctx->lv[l].n;
+    const dim3 grid(ncomp), blk(kExactThreads);
+    const int32_t* act = ctx->st->active;
+    const double bytes = 2.0 * sizeof(T) * (double)ctx->lv[l].n3 * ncomp;
+    const T* tab = exact_table<T>(ctx);
+    if (n == 16)
+        return launch_k(ctx, HIPIB_TIMER_SMALL_VCYCLE, bytes, k_coarse_exact<16, T>, grid, blk,
+                        exact_lds_words<16>() * sizeof(T), p.x, p.b, p.cs, tab, (T)oc.sigma, (T)oc.nu, act);
+    if (n == 12)
+        return launch_k(ctx, HIPIB_TIMER_SMALL_VCYCLE, bytes, k_coarse_exact<12, T>, grid, blk,
+                        exact_lds_words<12>() * sizeof(T), p.x, p.b, p.cs, tab, (T)oc.sigma, (T)oc.nu, act);
+    if (n == 8)
+        return launch_k(ctx, HIPIB_TIMER_SMALL_VCYCLE, bytes, k_coarse_exact<8, T>, grid, blk,
+                        exact_lds_words<8>() * sizeof(T), p.x, p.b, p.cs, tab, (T)oc.sigma, (T)oc.nu, act);
+    return fail(HIPIB_E_INVAL, "no exact coarse solve for n = %d", n);
+}
 
 template <typename T>
 hipib_status small_vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef& oc,
@@ -1512,7 +1632,10 @@ hipib_status smooth(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
 template <typename T>
 hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef& oc,
                     bool zero_guess) {
-    if (l == ctx->small_start) return small_vcycle<T>(ctx, l, p, ncomp, oc, zero_guess);
+    if (l == ctx->small_start) {
+        if (exact_coarse(ctx)) return coarse_exact<T>(ctx, l, p, ncomp, oc);   // (x is not read)
+        return small_vcycle<T>(ctx, l, p, ncomp, oc, zero_guess);
+    }
     const int n = ctx->lv[l].n;
     const int32_t* act = ctx->st->active;
     const T h = T(1) / T(n);
@@ -1684,6 +1807,45 @@ hipib_status mg_prepare(hipib_ctx* ctx) {
         {reinterpret_cast<const void*>(&k_small_vcycle<8, float>), chain(8, 4)}};
     for (const SmallKernel& k : ks)
         HIPIB_HIP(hipFuncSetAttribute(k.fn, hipFuncAttributeMaxDynamicSharedMemorySize, k.bytes));
+    const SmallKernel ke[] = {
+        {reinterpret_cast<const void*>(&k_coarse_exact<16, double>), exact_lds_words<16>() * 8},
+        {reinterpret_cast<const void*>(&k_coarse_exact<12, double>), exact_lds_words<12>() * 8},
+        {reinterpret_cast<const void*>(&k_coarse_exact<8, double>), exact_lds_words<8>() * 8},
+        {reinterpret_cast<const void*>(&k_coarse_exact<16, float>), exact_lds_words<16>() * 4},
+        {reinterpret_cast<const void*>(&k_coarse_exact<12, float>), exact_lds_words<12>() * 4},
+        {reinterpret_cast<const void*>(&k_coarse_exact<8, float>), exact_lds_words<8>() * 4}};
+    for (const SmallKernel& k : ke)
+        HIPIB_HIP(hipFuncSetAttribute(k.fn, hipFuncAttributeMaxDynamicSharedMemorySize, k.bytes));
+    if (ctx->cfg.mg_coarse_sweeps == 0) {
+        // the coarsest level's real Fourier basis and eigenvalue factors
+        const int N = ctx->lv[ctx->small_start].n;
+        if (N != 16 && N != 12 && N != 8)
+            return fail(HIPIB_E_INVAL, "no exact coarse solve for n = %d", N);
+        const double pi = 3.14159265358979323846;
+        std::vector<double> tab((size_t)N * N + N);
+        for (int j = 0; j < N; ++j)
+            for (int m = 0; m < N; ++m) {
+                double q;
+                if (m == 0) q = 1.0 / std::sqrt((double)N);
+                else if (m < N / 2) q = std::sqrt(2.0 / N) * std::cos(2.0 * pi * m * j / N);
+                else if (m == N / 2) q = ((j & 1) ? -1.0 : 1.0) / std::sqrt((double)N);
+                else q = std::sqrt(2.0 / N) * std::sin(2.0 * pi * (m - N / 2) * j / N);
+                tab[(size_t)j * N + m] = q;
+            }
+        for (int m = 0; m < N; ++m) {
+            const int f = m <= N / 2 ? m : m - N / 2;
+            const double sn = std::sin(pi * f / N);
+            tab[(size_t)N * N + m] = 4.0 * N * N * sn * sn;     // (4 / h^2) sin^2, h = 1 / N
+        }
+        std::vector<float> tab32(tab.begin(), tab.end());
+        if (hipMalloc(reinterpret_cast<void**>(&ctx->coarse_tab), tab.size() * sizeof(double)) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void**>(&ctx->coarse_tab32), tab.size() * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(HIPIB_E_NOMEM, "coarse-level table allocation failed");
+        }
+        HIPIB_HIP(hipMemcpy(ctx->coarse_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPIB_HIP(hipMemcpy(ctx->coarse_tab32, tab32.data(), tab32.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
     return HIPIB_OK;
 }
 

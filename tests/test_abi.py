@@ -18,7 +18,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_config_values():
     from paper_2503_22695_amd import hipib
     cfg = hipib.default_config()
-    assert (cfg.mg_pre, cfg.mg_post, cfg.mg_coarse_sweeps, cfg.mg_max_cycles) == (2, 2, 16, 50)
+    assert (cfg.mg_pre, cfg.mg_post, cfg.mg_coarse_sweeps, cfg.mg_max_cycles) == (2, 2, 0, 50)
     assert cfg.mg_rtol == 1e-10 and cfg.convection == 1 and cfg.precision == hipib.FP64
     assert cfg.deterministic == 0 and cfg.mg_krylov == 1
 

@@ -162,7 +162,9 @@ def test_mg_poisson(torch_dev, hp, ref, n, krylov):
     cyc, rr = ctx.mg_solve(hp.OP_POISSON, to_dev(torch, b), xd)
     xr, cr, rrr = ref.mg_solve(ref.fluid(n, krylov=krylov), 0.0, 1.0, True, b, x0)
     assert int(cyc[0]) == cr
-    assert abs(rr[0] - rrr) <= 1e-3 * rrr
+    # at n = 16 the coarsest level is the finest, solved exactly: both relative
+    # residuals are then rounding (cond(A) ~ 1e2 times eps ~ 1e-16, over n^3 sums)
+    assert abs(rr[0] - rrr) <= 1e-3 * rrr + 1e-11
     assert_close("x", host(xd), xr)
 
 
