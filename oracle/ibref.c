@@ -625,7 +625,7 @@ void ibref_pressure_load(int32_t n_faces, const int32_t* faces, const double* x,
  *   restriction: per axis weights (1,3,3,1)/8 over fine cells 2I-1 .. 2I+2;
  *   prolongation: cell-centred trilinear (3/4, 1/4 per axis), added to x;
  *   coarse operators rediscretised at 2h; the coarsest level is the first
- *   with at most 16 cells per side, solved exactly (mg_coarse_sweeps = 0: the
+ *   with at most 32 cells per side, solved exactly (mg_coarse_sweeps = 0: the
  *   periodic operator is diagonalised by the discrete Fourier modes, with
  *   eigenvalues sigma + nu (4/h^2) sum_d sin^2(pi k_d / n); Poisson drops the
  *   k = 0 mode), or the first with fewer than 8 cells, solved by
@@ -794,7 +794,7 @@ static void mg_free(mg_levels* lv) {
 static int hierarchy_bottom(const ibref_fluid* fl, const mg_levels* lv) {
     if (fl->mg_coarse_sweeps > 0) return lv->L - 1;
     for (int l = 0; l < lv->L; ++l)
-        if (lv->n[l] <= 16) return l;
+        if (lv->n[l] <= 32) return l;
     return lv->L - 1;
 }
 
@@ -820,32 +820,45 @@ static void coarse_exact(int n, double sigma, double nu, const double* b, double
     const long N3 = (long)n * n * n;
     double* re = (double*)malloc(sizeof(double) * (size_t)N3);
     double* im = (double*)malloc(sizeof(double) * (size_t)N3);
-    double* tr = (double*)malloc(sizeof(double) * (size_t)n);
-    double* ti = (double*)malloc(sizeof(double) * (size_t)n);
+    /* e^{2 pi i m / n}, m = 0 .. n-1: the exponent k j only matters mod n */
+    double* cw = (double*)malloc(sizeof(double) * (size_t)n);
+    double* sw = (double*)malloc(sizeof(double) * (size_t)n);
+    for (int m = 0; m < n; ++m) {
+        cw[m] = cos(2.0 * pi * (double)m / n);
+        sw[m] = sin(2.0 * pi * (double)m / n);
+    }
     for (long t = 0; t < N3; ++t) { re[t] = b[t]; im[t] = 0.0; }
     for (int dir = -1; dir <= 1; dir += 2) {          /* forward, then inverse */
         for (int ax = 0; ax < 3; ++ax) {
             const long stride = ax == 0 ? 1 : (ax == 1 ? n : (long)n * n);
-            for (long line = 0; line < (long)n * n; ++line) {
-                /* first cell of the line: the other two indices from `line` */
-                const long a = line % n, c = line / n;
-                long base;
-                if (ax == 0) base = n * (a + (long)n * c);
-                else if (ax == 1) base = a + (long)n * n * c;
-                else base = a + (long)n * c;
-                for (int k = 0; k < n; ++k) {
-                    double sr = 0.0, si = 0.0;
-                    for (int j = 0; j < n; ++j) {
-                        const double ang = dir * 2.0 * pi * (double)((long)k * j % n) / n;
-                        const double cr = cos(ang), ci = sin(ang);
-                        const double vr = re[base + j * stride], vi = im[base + j * stride];
-                        sr += vr * cr - vi * ci;
-                        si += vr * ci + vi * cr;
+#pragma omp parallel
+            {
+                double* tr = (double*)malloc(sizeof(double) * (size_t)n);
+                double* ti = (double*)malloc(sizeof(double) * (size_t)n);
+#pragma omp for
+                for (long line = 0; line < (long)n * n; ++line) {
+                    /* first cell of the line: the other two indices from `line` */
+                    const long a = line % n, c = line / n;
+                    long base;
+                    if (ax == 0) base = n * (a + (long)n * c);
+                    else if (ax == 1) base = a + (long)n * n * c;
+                    else base = a + (long)n * c;
+                    for (int k = 0; k < n; ++k) {
+                        double sr = 0.0, si = 0.0;
+                        for (int j = 0; j < n; ++j) {
+                            const int m = (int)((long)k * j % n);
+                            const double cr = cw[m], ci = dir * sw[m];
+                            const double vr = re[base + j * stride], vi = im[base + j * stride];
+                            sr += vr * cr - vi * ci;
+                            si += vr * ci + vi * cr;
+                        }
+                        tr[k] = sr;
+                        ti[k] = si;
                     }
-                    tr[k] = sr;
-                    ti[k] = si;
+                    for (int k = 0; k < n; ++k) { re[base + k * stride] = tr[k]; im[base + k * stride] = ti[k]; }
                 }
-                for (int k = 0; k < n; ++k) { re[base + k * stride] = tr[k]; im[base + k * stride] = ti[k]; }
+                free(tr);
+                free(ti);
             }
         }
         if (dir == -1) {
@@ -862,7 +875,7 @@ static void coarse_exact(int n, double sigma, double nu, const double* b, double
         }
     }
     for (long t = 0; t < N3; ++t) x[t] = re[t];
-    free(re); free(im); free(tr); free(ti);
+    free(re); free(im); free(cw); free(sw);
 }
 
 static void vcycle(const ibref_fluid* fl, mg_levels* lv, int l, double sigma, double nu,

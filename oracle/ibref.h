@@ -46,7 +46,7 @@ typedef struct {
     int32_t mg_pre, mg_post;   /* smoothing sweeps (red+black pairs) */
     int32_t mg_max_cycles;     /* > this many V-cycles: no convergence */
     int32_t mg_fixed_cycles;   /* > 0: run exactly this many cycles, no stop test */
-    int32_t mg_coarse_sweeps;  /* 0: the coarsest level is the first with at most 16 cells
+    int32_t mg_coarse_sweeps;  /* 0: the coarsest level is the first with at most 32 cells
                                   per side, solved exactly by its Fourier diagonalisation;
                                   > 0: the first with fewer than 8, relaxed by this many
                                   red+black sweeps */

@@ -68,8 +68,9 @@ def test_matches_fft_solution(ref, n, sigma, nu, poisson, krylov):
 
 
 def test_vcycle_contraction(ref):
-    """Residual reduction per V(2,2) cycle on a rough right-hand side."""
-    n = 32
+    """Residual reduction per V(2,2) cycle on a rough right-hand side (64^3:
+    one level above the exactly solved 32^3)."""
+    n = 64
     rng = np.random.default_rng(0)
     b = rng.standard_normal((n, n, n))
     b -= b.mean()
@@ -89,7 +90,7 @@ def test_zero_rhs_and_error_paths(ref):
     fl = ref.fluid(n)
     x, cyc, rr = ref.mg_solve(fl, 0.0, 1.0, True, np.zeros((n, n, n)), np.ones((n, n, n)))
     assert cyc == 0 and np.all(x == 0)
-    m = 32   # (a 16^3 grid is its own coarsest level, solved exactly in one cycle)
+    m = 64   # (a 32^3 grid is its own coarsest level, solved exactly in one cycle)
     b = np.random.default_rng(1).standard_normal((m, m, m))
     b -= b.mean()
     with pytest.raises(oracle.OracleError) as e:
@@ -124,9 +125,9 @@ def neg_lap(x):
 
 def test_krylov_first_step_is_energy_optimal_multiple_of_the_vcycle(ref):
     """One preconditioned-CG iteration from x = 0 is alpha z with z one V-cycle
-    applied to b and alpha = (b.z)/(z.Az), the energy-minimising step (on 32^3:
-    a 16^3 grid is its own coarsest level, solved exactly, so alpha would be 1)."""
-    n = 32
+    applied to b and alpha = (b.z)/(z.Az), the energy-minimising step (on 64^3:
+    a 32^3 grid is its own coarsest level, solved exactly, so alpha would be 1)."""
+    n = 64
     rng = np.random.default_rng(3)
     b = rng.standard_normal((n, n, n))
     b -= b.mean()
@@ -141,7 +142,7 @@ def test_krylov_first_step_is_energy_optimal_multiple_of_the_vcycle(ref):
 
 
 def test_krylov_needs_fewer_cycles_than_the_plain_iteration(ref):
-    n = 32
+    n = 64
     rng = np.random.default_rng(5)
     b = rng.standard_normal((n, n, n))
     b -= b.mean()
@@ -163,9 +164,10 @@ def test_helmholtz_relaxation_rate_is_youngs():
     omega, which contracts the error by omega - 1 per sweep (up to a factor
     linear in the sweep count: the optimal SOR matrix is defective).  A cycle
     here is V(2,2) without coarse levels: four sweeps.  The ratio of 128^3 at
-    dt = 5e-4 (sigma / 6c = 2.03) on a 32^3 grid."""
+    dt = 5e-4 (sigma / 6c = 2.03) on a 64^3 grid (above the exactly solved
+    32^3)."""
     import oracle
-    n, nu = 32, 0.01
+    n, nu = 64, 0.01
     sigma = 2000.0 / 983.04 * 6 * nu * n * n
     rho, w = young_omega(n, sigma, nu)
     assert rho <= 0.5
@@ -185,7 +187,7 @@ def test_helmholtz_relaxation_matches_numpy_sor():
     four sweeps (V(2,2): pre + post), each red then black, each colour
     x += omega ((b + c * neighbour sum) / diag - x)."""
     import oracle
-    n, nu, sigma = 32, 0.01, 100.0
+    n, nu, sigma = 64, 0.01, 400.0
     rho, w = young_omega(n, sigma, nu)
     assert rho <= 0.5
     rng = np.random.default_rng(8)
@@ -206,13 +208,13 @@ def test_helmholtz_relaxation_matches_numpy_sor():
 
 
 def test_coarsest_level_is_solved_exactly():
-    """With mg_coarse_sweeps = 0 a grid of at most 16 cells per side is its own
+    """With mg_coarse_sweeps = 0 a grid of at most 32 cells per side is its own
     coarsest level, solved by its Fourier diagonalisation: one cycle reaches the
     FFT solution (numpy.fft) to rounding, for Poisson (mean-free) and
-    Helmholtz, at 16^3, 12^3 and 8^3; with coarse sweeps the old hierarchy
-    (down to 4^3 or 6^3) is kept."""
+    Helmholtz, at 32^3, 24^3, 16^3, 12^3 and 8^3; with coarse sweeps the old
+    hierarchy (down to 4^3 or 6^3) is kept."""
     import oracle
-    for n in (16, 12, 8):
+    for n in (32, 24, 16, 12, 8):
         rng = np.random.default_rng(40 + n)
         b = rng.standard_normal((n, n, n))
         for sigma, nu, poisson in ((0.0, 1.0, True), (3.0, 0.7, False)):
