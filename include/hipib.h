@@ -75,7 +75,7 @@ typedef struct {
     int32_t mg_max_cycles;    /* more cycles than this: HIPIB_E_NOCONV */
     int32_t mg_fixed_cycles;  /* > 0: exactly this many cycles, no stop test */
     int32_t mg_coarse_sweeps; /* 0 (default): the coarsest level is the first with at
-                                 most 16 cells per side, solved exactly by its Fourier
+                                 most 32 cells per side, solved exactly by its Fourier
                                  diagonalisation; > 0: the first with fewer than 8,
                                  relaxed by this many red+black sweeps */
     double mg_rtol;           /* stop when ||b - A x||_2 <= rtol ||b||_2 */

@@ -139,6 +139,7 @@ void free_all(hipib_ctx* ctx) {
     (void)hipFree(ctx->adj_sX);
     (void)hipFree(ctx->adj_lamF);
     (void)hipFree(ctx->coarse_tab);
+    (void)hipFree(ctx->coarse_work);
     (void)hipFree(ctx->coarse_tab32);
     for (hipEvent_t e : ctx->ph_ev)
         if (e) (void)hipEventDestroy(e);
@@ -300,6 +301,9 @@ hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out
     ctx->small_start = L - 1;
     for (int l = 0; l < L; ++l)
         if (ctx->lv[l].n <= kSmallMax) { ctx->small_start = l; break; }
+    ctx->exact_level = L - 1;
+    for (int l = 0; l < L; ++l)
+        if (ctx->lv[l].n <= 32) { ctx->exact_level = l; break; }
     hipib_status s = HIPIB_OK;
     const size_t esz = mg_level_elem_size(ctx);
     auto alloc_bytes = [&](void** p, size_t bytes) {

@@ -79,6 +79,8 @@ struct hipib_ctx {
     size_t small_lds = 0;   // its dynamic LDS bytes
     // exact solve of the coarsest level (mg_coarse_sweeps = 0): the level's real
     // Fourier basis Q [N][N] and eigenvalue factors s [N], FP64 and FP32 copies
+    int exact_level = 0;    // first level with at most 32 cells per side (the exact coarsest level)
+    void* coarse_work = nullptr;   // its transform array (24^3 and 32^3), 3 components
     double* coarse_tab = nullptr;
     float* coarse_tab32 = nullptr;
     hipib::Level lv[hipib::kMaxLevels];

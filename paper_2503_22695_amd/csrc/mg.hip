@@ -894,6 +894,116 @@ k_coarse_exact(T* __restrict__ xg, const T* __restrict__ bg, int64_t cs, const T
     }
 }
 
+// The same solve at 24^3 and 32^3, where a component's level no longer fits
+// one workgroup's LDS, in three launches of one workgroup per plane:
+//   k_exact_fwd_xy  plane k:  b -> transforms along x, then y   -> W[k][my][mx]
+//   k_exact_z       plane my: transform along z, divide by lambda, inverse
+//                             along z, in place in W
+//   k_exact_inv_xy  plane k:  inverse along y, then x           -> x (packed)
+// Every output of a pass is one thread's N-term sum over a row of LDS; the
+// basis sits in LDS with rows padded to N + 1 values.  W holds N^3 values per
+// component.
+constexpr int kPlaneThreads = 1024;
+
+template <int N, typename T>
+__device__ __forceinline__ void exact_load_basis(T* Qs, const T* __restrict__ tab) {
+    for (int t = threadIdx.x; t < N * N; t += kPlaneThreads) Qs[(t / N) * (N + 1) + t % N] = tab[t];
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(kPlaneThreads)
+k_exact_fwd_xy(const T* __restrict__ bg, int64_t cs, const T* __restrict__ tab, T* __restrict__ work,
+               const int32_t* __restrict__ active) {
+    constexpr int NP = N + 1;
+    __shared__ T Qs[N * NP], P[N * NP], U[N * NP];
+    const int k = blockIdx.x, comp = blockIdx.y;
+    if (!active[comp]) return;
+    exact_load_basis<N>(Qs, tab);
+    for (int t = threadIdx.x; t < N * N; t += kPlaneThreads) {
+        const int i = t % N, j = t / N;
+        P[j * NP + i] = bg[comp * cs + pkc<N>(i, j, k)];
+    }
+    __syncthreads();
+    const int t = threadIdx.x, a = t % N, r = t / N;
+    const bool on = t < N * N;
+    if (on) {   // U[j][mx] = sum_i Q[i][mx] b[j][i]
+        T acc = T(0);
+#pragma unroll 8
+        for (int i = 0; i < N; ++i) acc += Qs[i * NP + a] * P[r * NP + i];
+        U[r * NP + a] = acc;
+    }
+    __syncthreads();
+    if (on) {   // W[k][my][mx] = sum_j Q[j][my] U[j][mx]
+        T acc = T(0);
+#pragma unroll 8
+        for (int j = 0; j < N; ++j) acc += Qs[j * NP + r] * U[j * NP + a];
+        work[(int64_t)comp * N * N * N + (k * N + r) * N + a] = acc;
+    }
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(kPlaneThreads)
+k_exact_z(T* __restrict__ work, const T* __restrict__ tab, T sigma, T nu,
+          const int32_t* __restrict__ active) {
+    constexpr int NP = N + 1;
+    __shared__ T Qs[N * NP], Z[N * NP], V[N * NP];
+    const int my = blockIdx.x, comp = blockIdx.y;
+    if (!active[comp]) return;
+    const T* sv = tab + N * N;
+    T* wc = work + (int64_t)comp * N * N * N;
+    exact_load_basis<N>(Qs, tab);
+    for (int t = threadIdx.x; t < N * N; t += kPlaneThreads) {
+        const int mx = t % N, k = t / N;
+        Z[k * NP + mx] = wc[(k * N + my) * N + mx];
+    }
+    __syncthreads();
+    const int t = threadIdx.x, a = t % N, r = t / N;
+    const bool on = t < N * N;
+    if (on) {   // V[mz][mx] = sum_k Q[k][mz] Z[k][mx] / lambda(mx, my, mz)
+        T acc = T(0);
+#pragma unroll 8
+        for (int k = 0; k < N; ++k) acc += Qs[k * NP + r] * Z[k * NP + a];
+        const T lam = sigma + nu * (sv[a] + sv[my] + sv[r]);
+        V[r * NP + a] = lam != T(0) ? acc / lam : T(0);
+    }
+    __syncthreads();
+    if (on) {   // W[k][my][mx] = sum_mz Q[k][mz] V[mz][mx]
+        T acc = T(0);
+#pragma unroll 8
+        for (int m = 0; m < N; ++m) acc += Qs[r * NP + m] * V[m * NP + a];
+        wc[(r * N + my) * N + a] = acc;
+    }
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(kPlaneThreads)
+k_exact_inv_xy(T* __restrict__ xg, int64_t cs, const T* __restrict__ tab, const T* __restrict__ work,
+               const int32_t* __restrict__ active) {
+    constexpr int NP = N + 1;
+    __shared__ T Qs[N * NP], P[N * NP], U[N * NP];
+    const int k = blockIdx.x, comp = blockIdx.y;
+    if (!active[comp]) return;
+    const T* wc = work + (int64_t)comp * N * N * N;
+    exact_load_basis<N>(Qs, tab);
+    for (int t = threadIdx.x; t < N * N; t += kPlaneThreads) P[(t / N) * NP + t % N] = wc[k * N * N + t];
+    __syncthreads();
+    const int t = threadIdx.x, a = t % N, r = t / N;
+    const bool on = t < N * N;
+    if (on) {   // U[j][mx] = sum_my Q[j][my] W[k][my][mx]
+        T acc = T(0);
+#pragma unroll 8
+        for (int m = 0; m < N; ++m) acc += Qs[r * NP + m] * P[m * NP + a];
+        U[r * NP + a] = acc;
+    }
+    __syncthreads();
+    if (on) {   // x[k][j][i] = sum_mx Q[i][mx] U[j][mx]
+        T acc = T(0);
+#pragma unroll 8
+        for (int m = 0; m < N; ++m) acc += Qs[a * NP + m] * U[r * NP + m];
+        xg[comp * cs + pkc<N>(a, r, k)] = acc;
+    }
+}
+
 // sum of the six neighbours (order i+1, i-1, j+1, j-1, k+1, k-1) of the
 // colour-q cell at packed position (ih, j, k), from the other colour's half xo
 template <int N, typename T>
@@ -1424,11 +1534,11 @@ OpCoef op_coef(const hipib_ctx* ctx, int op) {
 // a coarse-grid correction adds less than its sweeps would), relaxed there
 // with that level's omega.  Otherwise (and for Poisson) the coarsest level
 // is the first with fewer than 8 cells per side.
-// The coarsest level: with mg_coarse_sweeps = 0 the first with at most 16 cells
-// per side, solved exactly (k_coarse_exact); otherwise the first with fewer
-// than 8, relaxed by the coarse sweeps.
+// The coarsest level: with mg_coarse_sweeps = 0 the first with at most 32 cells
+// per side, solved exactly (k_coarse_exact, k_exact_*); otherwise the first
+// with fewer than 8, relaxed by the coarse sweeps.
 bool exact_coarse(const hipib_ctx* ctx) { return ctx->cfg.mg_coarse_sweeps == 0; }
-int bottom_level(const hipib_ctx* ctx) { return exact_coarse(ctx) ? ctx->small_start : ctx->L - 1; }
+int bottom_level(const hipib_ctx* ctx) { return exact_coarse(ctx) ? ctx->exact_level : ctx->L - 1; }
 
 int stop_level(const hipib_ctx* ctx, const OpCoef& oc) {
     const int bottom = bottom_level(ctx);
@@ -1495,7 +1605,7 @@ const double* exact_table<double>(const hipib_ctx* ctx) { return ctx->coarse_tab
 template <>
 const float* exact_table<float>(const hipib_ctx* ctx) { return ctx->coarse_tab32; }
 
-// exact solve of the coarsest level l (the first with at most 16 cells per side)
+// exact solve of the coarsest level l (the first with at most 32 cells per side)
 template <typename T>
 hipib_status coarse_exact(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef& oc) {
     const int n = ctx->lv[l].n;
@@ -1512,6 +1622,25 @@ hipib_status coarse_exact(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const
     if (n == 8)
         return launch_k(ctx, HIPIB_TIMER_SMALL_VCYCLE, bytes, k_coarse_exact<8, T>, grid, blk,
                         exact_lds_words<8>() * sizeof(T), p.x, p.b, p.cs, tab, (T)oc.sigma, (T)oc.nu, act);
+    T* work = static_cast<T*>(ctx->coarse_work);
+    if (n == 32 || n == 24) {
+        const dim3 pg(n, ncomp), pb(kPlaneThreads);
+        const double wb = sizeof(T) * (double)ctx->lv[l].n3 * ncomp;
+        if (n == 32) {
+            HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_SMALL_VCYCLE, wb * 2, k_exact_fwd_xy<32, T>, pg, pb, 0, p.b, p.cs,
+                               tab, work, act));
+            HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_SMALL_VCYCLE, wb * 2, k_exact_z<32, T>, pg, pb, 0, work, tab,
+                               (T)oc.sigma, (T)oc.nu, act));
+            return launch_k(ctx, HIPIB_TIMER_SMALL_VCYCLE, wb * 2, k_exact_inv_xy<32, T>, pg, pb, 0, p.x, p.cs,
+                            tab, work, act);
+        }
+        HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_SMALL_VCYCLE, wb * 2, k_exact_fwd_xy<24, T>, pg, pb, 0, p.b, p.cs,
+                           tab, work, act));
+        HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_SMALL_VCYCLE, wb * 2, k_exact_z<24, T>, pg, pb, 0, work, tab,
+                           (T)oc.sigma, (T)oc.nu, act));
+        return launch_k(ctx, HIPIB_TIMER_SMALL_VCYCLE, wb * 2, k_exact_inv_xy<24, T>, pg, pb, 0, p.x, p.cs, tab,
+                        work, act);
+    }
     return fail(HIPIB_E_INVAL, "no exact coarse solve for n = %d", n);
 }
 
@@ -1632,10 +1761,8 @@ hipib_status smooth(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
 template <typename T>
 hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef& oc,
                     bool zero_guess) {
-    if (l == ctx->small_start) {
-        if (exact_coarse(ctx)) return coarse_exact<T>(ctx, l, p, ncomp, oc);   // (x is not read)
-        return small_vcycle<T>(ctx, l, p, ncomp, oc, zero_guess);
-    }
+    if (exact_coarse(ctx) && l == ctx->exact_level) return coarse_exact<T>(ctx, l, p, ncomp, oc);  // (x not read)
+    if (l == ctx->small_start) return small_vcycle<T>(ctx, l, p, ncomp, oc, zero_guess);
     const int n = ctx->lv[l].n;
     const int32_t* act = ctx->st->active;
     const T h = T(1) / T(n);
@@ -1818,8 +1945,8 @@ hipib_status mg_prepare(hipib_ctx* ctx) {
         HIPIB_HIP(hipFuncSetAttribute(k.fn, hipFuncAttributeMaxDynamicSharedMemorySize, k.bytes));
     if (ctx->cfg.mg_coarse_sweeps == 0) {
         // the coarsest level's real Fourier basis and eigenvalue factors
-        const int N = ctx->lv[ctx->small_start].n;
-        if (N != 16 && N != 12 && N != 8)
+        const int N = ctx->lv[ctx->exact_level].n;
+        if (N != 32 && N != 24 && N != 16 && N != 12 && N != 8)
             return fail(HIPIB_E_INVAL, "no exact coarse solve for n = %d", N);
         const double pi = 3.14159265358979323846;
         std::vector<double> tab((size_t)N * N + N);
@@ -1845,6 +1972,10 @@ hipib_status mg_prepare(hipib_ctx* ctx) {
         }
         HIPIB_HIP(hipMemcpy(ctx->coarse_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
         HIPIB_HIP(hipMemcpy(ctx->coarse_tab32, tab32.data(), tab32.size() * sizeof(float), hipMemcpyHostToDevice));
+        if (N > 16 && hipMalloc(&ctx->coarse_work, 3 * (size_t)N * N * N * tsz) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(HIPIB_E_NOMEM, "coarse-level work array allocation failed");
+        }
     }
     return HIPIB_OK;
 }
