@@ -229,7 +229,8 @@ def kernel_classes(hipib):
         (H.TIMER_SMALL_VCYCLE, "k_coarse_exact<16,double>",
          "coarsest level (16^3) solved exactly in one workgroup, 16 B per 16^3 cell"),
         (H.TIMER_RESID_NORM, "k_resid_norm<false>", "residual norm, 16 B/cell per component"),
-        (H.TIMER_CG_DOTS, "k_cg_dots<double>", "r.z and z.q, 24 B/cell"),
+        (H.TIMER_CG_DOTS, "k_gs_dot<double>",
+         "last two post-smoothing half-sweeps of the preconditioner, with r.z and z.q, 16 B/cell"),
         (H.TIMER_CG_DIR, "k_cg_dir<double>", "p, q = A z + beta q and p.q, 40 B/cell"),
         (H.TIMER_CG_UPDATE, "k_cg_update", "x, r updates and ||r||^2, 48 B/cell"),
         (H.TIMER_REDUCE, "k_finalize / k_cg_scalars", "single-workgroup reductions, 8 B per partial"),

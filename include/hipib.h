@@ -391,8 +391,10 @@ typedef enum {
     HIPIB_TIMER_SMALL_VCYCLE = 7,
     /* residual norm of the finest level: 16 B per cell and component */
     HIPIB_TIMER_RESID_NORM = 8,
-    /* conjugate-gradient passes: r.z and z.q, 24 B; p, q = A z + beta q and p.q,
-     * 40 B; x, r updates and ||r||^2, 48 B */
+    /* conjugate-gradient passes: r.z and z.q (the preconditioner's last two
+     * finest-level half-sweeps, which sum them: 16 B per cell in FP64; where
+     * the finest level is the exactly solved one, a separate 24 B pass);
+     * p, q = A z + beta q and p.q, 40 B; x, r updates and ||r||^2, 48 B */
     HIPIB_TIMER_CG_DOTS = 9,
     HIPIB_TIMER_CG_DIR = 10,
     HIPIB_TIMER_CG_UPDATE = 11,

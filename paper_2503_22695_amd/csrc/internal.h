@@ -79,6 +79,14 @@ struct hipib_ctx {
     size_t small_lds = 0;   // its dynamic LDS bytes
     // exact solve of the coarsest level (mg_coarse_sweeps = 0): the level's real
     // Fourier basis Q [N][N] and eigenvalue factors s [N], FP64 and FP32 copies
+    // set by a conjugate-gradient iteration around its preconditioner: r and q
+    // for the dots fused into the finest level's last half-sweeps (parts: the
+    // partials those wrote, 0 if none)
+    struct CgDotsReq {
+        const double* r = nullptr;
+        const double* q = nullptr;
+        int64_t parts = 0;
+    } cg_dots;
     int exact_level = 0;    // first level with at most 32 cells per side (the exact coarsest level)
     void* coarse_work = nullptr;   // its transform array (24^3 and 32^3), 3 components
     double* coarse_tab = nullptr;

@@ -212,6 +212,91 @@ k_gs(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, T c, T inv_d
     }
 }
 
+// A finest-level Poisson half-sweep of the conjugate-gradient preconditioner
+// (one component, nonzero guess, no over-relaxation) that also sums, over the
+// cells it writes, the dots r.z and z.q of the z it finishes: the last two
+// half-sweeps of the post-smoothing write each colour's final z.  In FP64 r is
+// the sweep's own right-hand side; in mixed mode the sweep runs on e = z / ||b||
+// and reads the FP64 residual rd.  Block partials go to part[poff + block]
+// (r.z) and part[pstride + poff + block] (z.q).
+template <typename T>
+__global__ void __launch_bounds__(TX * TY)
+k_gs_dot(T* __restrict__ x, const T* __restrict__ b, int n, T c, T inv_diag, int q,
+         const double* __restrict__ rd, const double* __restrict__ qd, const MGState* __restrict__ st,
+         double* __restrict__ part, int64_t pstride, int64_t poff) {
+    constexpr int KPT = gs_kpt<T>();
+    __shared__ double red[2][(TX * TY) / 64];
+    if (!st->active[0]) return;  // uniform
+    const uint3 bid = xcd_block();
+    const int k0 = bid.z * KPT;
+    const int H = n >> 1;
+    const int ih = bid.x * TX + threadIdx.x, j = bid.y * TY + threadIdx.y;
+    const double zs = sizeof(T) == 4 ? st->bn[0] : 1.0;
+    double a = 0.0, d = 0.0;
+    if (ih < H && j < n) {
+        const int64_t half3 = (int64_t)H * n * n;
+        T* xq = x + q * half3;
+        const T* xo = x + (1 - q) * half3;
+        const T* bq = b + q * half3;
+        const int jp = wrapi(j + 1, n), jm = wrapi(j - 1, n);
+        const int ihp = ih + 1 < H ? ih + 1 : 0, ihm = ih > 0 ? ih - 1 : H - 1;
+        T col[KPT + 2], side[KPT], yp[KPT], ym[KPT], bv[KPT];
+        double rv[KPT], qv[KPT];
+#pragma unroll
+        for (int r = 0; r < KPT + 2; ++r)
+            col[r] = xo[ih + (int64_t)H * ((int64_t)j + (int64_t)n * wrapi(k0 - 1 + r, n))];
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) {
+            const int k = k0 + r;
+            if (k < n) {
+                const int64_t row = (int64_t)H * ((int64_t)j + (int64_t)n * k);
+                const int p = (j + k + q) & 1;
+                bv[r] = bq[row + ih];
+                side[r] = xo[row + (p ? ihp : ihm)];
+                yp[r] = xo[(int64_t)H * ((int64_t)jp + (int64_t)n * k) + ih];
+                ym[r] = xo[(int64_t)H * ((int64_t)jm + (int64_t)n * k) + ih];
+                rv[r] = sizeof(T) == 8 ? (double)bv[r] : rd[q * half3 + row + ih];
+                qv[r] = qd[q * half3 + row + ih];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) {
+            const int k = k0 + r;
+            if (k < n) {
+                const int p = (j + k + q) & 1;
+                const T a_ip = p ? side[r] : col[r + 1];
+                const T a_im = p ? col[r + 1] : side[r];
+                const T sn = a_ip + a_im + yp[r] + ym[r] + col[r + 2] + col[r];
+                const T xg = (bv[r] + c * sn) * inv_diag;
+                xq[(int64_t)H * ((int64_t)j + (int64_t)n * k) + ih] = xg;
+                const double zv = zs * (double)xg;
+                a += rv[r] * zv;
+                d += zv * qv[r];
+            }
+        }
+    }
+    const int tid = threadIdx.x + TX * threadIdx.y;
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_down(a, o, 64);
+        d += __shfl_down(d, o, 64);
+    }
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = a;
+        red[1][tid >> 6] = d;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double sa = 0.0, sd = 0.0;
+        for (int w = 0; w < (TX * TY) / 64; ++w) {
+            sa += red[0][w];
+            sd += red[1][w];
+        }
+        const int64_t blk = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+        part[poff + blk] = sa;
+        part[pstride + poff + blk] = sd;
+    }
+}
+
 // r = b - (sigma x - c (sum_nbr x - 6 x)), both colours
 template <typename T>
 __global__ void __launch_bounds__(TX * TY)
@@ -1746,9 +1831,23 @@ hipib_status smooth(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
     const T h = T(1) / T(n);
     const T c = (T)oc.nu / (h * h);
     const T inv_diag = T(1) / ((T)oc.sigma + T(6) * c);
+    // the preconditioner's finest-level post-smoothing of a conjugate-gradient
+    // iteration: its last two half-sweeps also sum r.z and z.q
+    const bool dots = l == 0 && ctx->cg_dots.q != nullptr && !zero_guess && ncomp == 1;
+    const dim3 grid = gs_grid<T>(n, 1);
+    const int64_t nb = (int64_t)grid.x * grid.y * grid.z;
     for (int s = 0; s < 2 * sweeps; ++s) {
         const int zg = (s == 0 && zero_guess) ? 1 : 0;
-        HIPIB_TRY(gs_sweep<T>(ctx, l, p, ncomp, oc, c, inv_diag, (s & 1) ? 1 - first : first, zg));
+        const int colour = (s & 1) ? 1 - first : first;
+        if (dots && s >= 2 * sweeps - 2) {
+            const int64_t poff = s == 2 * sweeps - 2 ? 0 : nb;
+            HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_DOTS, (sizeof(T) * 1.5 + (sizeof(T) == 4 ? 8.0 : 4.0)) * (double)ctx->n3,
+                               k_gs_dot<T>, grid, dim3(TX, TY), 0, p.x, p.b, n, c, inv_diag, colour,
+                               ctx->cg_dots.r, ctx->cg_dots.q, ctx->st, ctx->part, 2 * nb, poff));
+            ctx->cg_dots.parts = 2 * nb;
+        } else {
+            HIPIB_TRY(gs_sweep<T>(ctx, l, p, ncomp, oc, c, inv_diag, colour, zg));
+        }
     }
     return HIPIB_OK;
 }
@@ -1844,17 +1943,27 @@ hipib_status cg_iteration(hipib_ctx* ctx, const OpCoef& oc) {
     const bool mixed = ctx->cfg.precision == HIPIB_MIXED;
     const int64_t np = norm_parts(n);
     const double zb = mixed ? 4.0 : 8.0;   // bytes of a z value
-    if (mixed) {
-        HIPIB_TRY(vcycle<float>(ctx, 0, LevelPtr<float>{ctx->e32, ctx->r32, n3}, 1, oc, true));
-        HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_DOTS, (16.0 + zb) * n3, k_cg_dots<float>, dim3(nb), dim3(256), 0, r,
-                           ctx->e32, q, n3, ctx->st, ctx->part, nb));
-    } else {
-        HIPIB_TRY(vcycle<double>(ctx, 0, LevelPtr<double>{z, r, n3}, 1, oc, true));
-        HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_DOTS, (16.0 + zb) * n3, k_cg_dots<double>, dim3(nb), dim3(256), 0, r,
-                           z, q, n3, ctx->st, ctx->part, nb));
+    // z = M r; the preconditioner's last two half-sweeps sum r.z and z.q when
+    // it post-smooths the finest level, else k_cg_dots does
+    ctx->cg_dots = hipib_ctx::CgDotsReq{r, q, 0};
+    hipib_status vs;
+    if (mixed) vs = vcycle<float>(ctx, 0, LevelPtr<float>{ctx->e32, ctx->r32, n3}, 1, oc, true);
+    else vs = vcycle<double>(ctx, 0, LevelPtr<double>{z, r, n3}, 1, oc, true);
+    const int64_t fused = ctx->cg_dots.parts;
+    ctx->cg_dots = hipib_ctx::CgDotsReq{};
+    HIPIB_TRY(vs);
+    int64_t dparts = fused;
+    if (fused == 0) {
+        if (mixed)
+            HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_DOTS, (16.0 + zb) * n3, k_cg_dots<float>, dim3(nb), dim3(256), 0,
+                               r, ctx->e32, q, n3, ctx->st, ctx->part, nb));
+        else
+            HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_DOTS, (16.0 + zb) * n3, k_cg_dots<double>, dim3(nb), dim3(256), 0,
+                               r, z, q, n3, ctx->st, ctx->part, nb));
+        dparts = nb;
     }
-    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_REDUCE, 16.0 * nb, k_cg_scalars, dim3(1), dim3(1024), 0, ctx->part, nb, nb,
-                       (int)CG_BETA, ctx->st));
+    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_REDUCE, 16.0 * dparts, k_cg_scalars, dim3(1), dim3(1024), 0, ctx->part,
+                       dparts, dparts, (int)CG_BETA, ctx->st));
     if (mixed)
         HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_DIR, (32.0 + zb) * n3, k_cg_dir<float>, norm_grid(n, 1), dim3(TX, TY),
                            0, ctx->e32, p, q, n, oc.sigma, c, ctx->st, ctx->part));
@@ -1980,7 +2089,7 @@ hipib_status mg_prepare(hipib_ctx* ctx) {
     return HIPIB_OK;
 }
 
-int64_t mg_partials_needed(int n) { return 3 * (norm_parts(n) + 1024); }
+int64_t mg_partials_needed(int n) { return 4 * (norm_parts(n) + 1024); }
 
 size_t mg_level_elem_size(const hipib_ctx* ctx) {
     return ctx->cfg.precision == HIPIB_MIXED ? sizeof(float) : sizeof(double);
