@@ -167,17 +167,13 @@ hipib_status phase_mark(hipib_ctx* ctx, bool timed, int k) {
 // fluid part of a step: g holds the Helmholtz right-hand side on entry;
 // timed: phase events 3, 4, 5 after the Helmholtz solves, the Poisson solve
 // and the projection
+hipib_status mark_timed(hipib_ctx* ctx, int k) { return phase_mark(ctx, true, k); }
+
+// (u^n packed into xp by the right-hand side builder)
 hipib_status fluid_solves(hipib_ctx* ctx, double* u, double* p, bool timed = false) {
     int32_t cyc[4] = {0, 0, 0, 0};
     double rr[4] = {0, 0, 0, 0};
-    HIPIB_TRY(mg_solve(ctx, HIPIB_OP_HELMHOLTZ, 3, ctx->g, u, cyc, rr));
-    HIPIB_TRY(phase_mark(ctx, timed, 3));
-    HIPIB_TRY(launch_divergence_rhs(ctx, u, ctx->bp));
-    HIPIB_TRY(mg_remove_mean(ctx, ctx->bp, 0));
-    HIPIB_TRY(mg_solve(ctx, HIPIB_OP_POISSON, 1, ctx->bp, p, cyc + 3, rr + 3));
-    HIPIB_TRY(phase_mark(ctx, timed, 4));
-    HIPIB_TRY(launch_project(ctx, u, p));
-    HIPIB_TRY(phase_mark(ctx, timed, 5));
+    HIPIB_TRY(fluid_step_packed(ctx, u, p, cyc, rr, timed ? mark_timed : nullptr));
     record_step(ctx, cyc, rr);
     return HIPIB_OK;
 }
@@ -214,7 +210,7 @@ hipib_status ib_step(hipib_ctx* ctx, double* u, double* p, double* X, double pre
     if (timed) HIPIB_HIP(hipEventRecord(ctx->ph_force[1], ctx->side));
     HIPIB_HIP(hipEventRecord(ctx->ev_join, ctx->side));
     HIPIB_TRY(launch_bin(ctx, X));
-    HIPIB_TRY(launch_rhs_build(ctx, u, nullptr, ctx->g));
+    HIPIB_TRY(launch_rhs_build(ctx, u, nullptr, ctx->g, ctx->xp));
     HIPIB_TRY(phase_mark(ctx, timed, 1));
     HIPIB_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
     HIPIB_TRY(launch_spread(ctx, X, ctx->F, ctx->g));
@@ -678,7 +674,7 @@ hipib_status hipib_ns_step(hipib_ctx* ctx, const double* f, double* u, double* p
     if (!aligned8(u) || !aligned8(p) || (f && !aligned8(f))) return fail(HIPIB_E_INVAL, "bad pointer");
     ctx->recs.clear();
     if (ctx->cfg.walls) return walled_ns_step(ctx, f, u, p);
-    HIPIB_TRY(launch_rhs_build(ctx, u, f, ctx->g));
+    HIPIB_TRY(launch_rhs_build(ctx, u, f, ctx->g, ctx->xp));
     return fluid_solves(ctx, u, p);
 }
 

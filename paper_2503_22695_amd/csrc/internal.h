@@ -94,12 +94,13 @@ struct hipib_ctx {
     hipib::Level lv[hipib::kMaxLevels];
     void* r0 = nullptr;     // [3][n3] residual scratch of the V-cycle type (any level)
     double* xp = nullptr;   // [3][n3] packed FP64 solution of the current solve
+    double* sx = nullptr;   // the packed solution array the running solve iterates on (xp or bp)
     double* kv[4] = {nullptr, nullptr, nullptr, nullptr};  // [n3] packed CG vectors r, z, p, q
     double* bpk = nullptr;  // [3][n3] packed FP64 right-hand side
     float* e32 = nullptr;   // [3][n3] packed FP32 correction (mixed precision)
     float* r32 = nullptr;   // [3][n3] packed FP32 scaled residual (mixed precision)
     double* g = nullptr;    // [3][n3] Helmholtz right-hand side
-    double* bp = nullptr;   // [n3] Poisson right-hand side
+    double* bp = nullptr;   // [n3] Poisson right-hand side (natural), or p packed during a step
     double* part = nullptr; // reduction partials
     int64_t part_cap = 0;
     hipib::MGState* st = nullptr;       // device
@@ -218,13 +219,19 @@ hipib_status compute_stats(hipib_ctx* ctx, const double* u, const double* X, hip
 
 // ---- launchers (each file owns its kernels) ---------------------------------
 // grid.hip
-hipib_status launch_rhs_build(hipib_ctx* ctx, const double* u, const double* f, double* g);
+hipib_status launch_rhs_build(hipib_ctx* ctx, const double* u, const double* f, double* g,
+                              double* upk = nullptr);
+// the fluid part of a step on the packed layout (g built and spread, u^n
+// packed in xp): Helmholtz, divergence, Poisson, projection into u and p;
+// mark(ctx, k) (optional) after each of the three phases, k = 3, 4, 5
+hipib_status fluid_step_packed(hipib_ctx* ctx, double* u, double* p, int32_t* cyc, double* rr,
+                               hipib_status (*mark)(hipib_ctx*, int));
 hipib_status launch_divergence_rhs(hipib_ctx* ctx, const double* u, double* b);
 hipib_status launch_project(hipib_ctx* ctx, double* u, const double* p);
 hipib_status launch_zero(hipib_ctx* ctx, double* p, int64_t count);
 // with explicit coefficients: g = rho_dt u - rho_conv C(u) + f; b = -coef D u; u -= coef G p
 hipib_status launch_rhs_build_coef(hipib_ctx* ctx, const double* u, const double* f, double* g,
-                                   double rho_dt, double rho_conv);
+                                   double rho_dt, double rho_conv, double* upk = nullptr);
 hipib_status launch_divergence_rhs_coef(hipib_ctx* ctx, const double* u, double* b, double coef);
 hipib_status launch_project_coef(hipib_ctx* ctx, double* u, const double* p, double coef);
 // walls.hip (walled box through its mirror image)
@@ -313,6 +320,15 @@ hipib_status launch_k(hipib_ctx* ctx, int kind, double bytes, void (*k)(KArgs...
 // ---- small device helpers ----------------------------------------------------
 __device__ __forceinline__ int wrap_idx(int i, int n) {
     return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+// offset of cell (i,j,k) of an n^3 component in the packed red-black layout:
+// the red cells ((i+j+k) even) first, then the black ones, each colour as
+// rows of n/2 cells (i >> 1) ordered by j, then k
+__device__ __forceinline__ int64_t pk(int i, int j, int k, int n) {
+    const int q = (i + j + k) & 1;
+    const int H = n >> 1;
+    return (int64_t)q * ((int64_t)H * n * n) + (i >> 1) + (int64_t)H * ((int64_t)j + (int64_t)n * k);
 }
 
 // Sum over a workgroup of blockDim.x (multiple of 64, <= 1024) threads.

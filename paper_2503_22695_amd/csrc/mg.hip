@@ -54,16 +54,13 @@ namespace {
 constexpr int TX = 64, TY = 4;
 constexpr int kSmallThreads = 1024;
 
-enum FinalizeMode { FIN_BNORM = 0, FIN_INIT_R = 1, FIN_CYCLE_R = 2, FIN_MEAN = 3, FIN_MEAN_ALL = 4 };
+enum FinalizeMode {
+    FIN_BNORM = 0, FIN_INIT_R = 1, FIN_CYCLE_R = 2, FIN_MEAN = 3, FIN_MEAN_ALL = 4,
+    FIN_MEAN_BNORM = 5   // component 0: mean of b from slot 0 (sum b), ||b - mean|| with slot 1 (sum b^2)
+};
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// packed offset of cell (i,j,k) (any colour) inside one component
-__device__ __forceinline__ int64_t pk(int i, int j, int k, int n) {
-    const int q = (i + j + k) & 1;
-    const int H = n >> 1;
-    return (int64_t)q * ((int64_t)H * n * n) + (i >> 1) + (int64_t)H * ((int64_t)j + (int64_t)n * k);
-}
 
 // Sum of the six neighbours of the colour-q cell at packed (ih, j, k), read
 // from the other colour's array xo, in the order i+1, i-1, j+1, j-1, k+1, k-1.
@@ -115,11 +112,13 @@ k_pack(const double* __restrict__ src, double* __restrict__ dst, int n, int64_t 
 }
 
 __global__ void __launch_bounds__(TX * TY)
-k_unpack(const double* __restrict__ src, double* __restrict__ dst, int n, int64_t n3) {
+k_unpack(const double* __restrict__ src, double* __restrict__ dst, int n, int64_t n3,
+         const double* __restrict__ mean) {
     const int comp = blockIdx.z / n, k = blockIdx.z - comp * n;
     const int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y;
     if (i >= n || j >= n) return;
-    dst[comp * n3 + i + (int64_t)n * (j + (int64_t)n * k)] = src[comp * n3 + pk(i, j, k, n)];
+    const double v = src[comp * n3 + pk(i, j, k, n)];
+    dst[comp * n3 + i + (int64_t)n * (j + (int64_t)n * k)] = mean ? v - mean[comp] : v;
 }
 
 // ---------------------------------------------------------------------------
@@ -477,9 +476,9 @@ __global__ void k_zero_t(T* __restrict__ p, int64_t count) {
 // KPT cells of colour q along z with the loads of k_gs.
 template <bool TO32>
 __global__ void __launch_bounds__(TX * TY)
-k_resid_norm(const double* __restrict__ x, const double* __restrict__ b, int n, int64_t cs,
+k_resid_norm(const double* __restrict__ x, double* __restrict__ b, int n, int64_t cs,
              double sigma, double c, const MGState* __restrict__ st, float* __restrict__ r32,
-             double* __restrict__ part, int64_t pstride, double* __restrict__ rstore) {
+             double* __restrict__ part, int64_t pstride, double* __restrict__ rstore, int submean) {
     __shared__ double red[16];
     const int nkb = (n + KPT - 1) / KPT;
     const int z = blockIdx.z, comp = z / (2 * nkb), rem = z - comp * 2 * nkb, q = rem / nkb;
@@ -492,7 +491,8 @@ k_resid_norm(const double* __restrict__ x, const double* __restrict__ b, int n, 
         const int64_t half3 = (int64_t)H * n * n;
         const double* xq = x + comp * cs + q * half3;
         const double* xo = x + comp * cs + (1 - q) * half3;
-        const double* bq = b + comp * cs + q * half3;
+        double* bq = b + comp * cs + q * half3;
+        const double bmean = submean ? st->mean[comp] : 0.0;
         const int jp = wrapi(j + 1, n), jm = wrapi(j - 1, n);
         const int ihp = ih + 1 < H ? ih + 1 : 0, ihm = ih > 0 ? ih - 1 : H - 1;
         double col[KPT + 2], side[KPT], yp[KPT], ym[KPT], bv[KPT], xv[KPT];
@@ -521,6 +521,10 @@ k_resid_norm(const double* __restrict__ x, const double* __restrict__ b, int n, 
                 const double a_ip = p ? side[r] : col[r + 1];
                 const double a_im = p ? col[r + 1] : side[r];
                 const double s = a_ip + a_im + yp[r] + ym[r] + col[r + 2] + col[r];
+                if (submean) {
+                    bv[r] -= bmean;
+                    bq[(int64_t)H * ((int64_t)j + (int64_t)n * k) + ih] = bv[r];
+                }
                 const double rr = bv[r] - (sigma * xv[r] - c * (s - 6.0 * xv[r]));
                 v += rr * rr;
                 if (rstore) rstore[comp * cs + q * half3 + (int64_t)H * ((int64_t)j + (int64_t)n * k) + ih] = rr;
@@ -780,6 +784,21 @@ __global__ void __launch_bounds__(1024)
 k_finalize(const double* __restrict__ part, int64_t nparts, int64_t pstride, int ncomp, int mode,
            MGState* st, double rtol, int max_cycles, int fixed_cycles, double inv_count) {
     __shared__ double red[16];
+    if (mode == FIN_MEAN_BNORM) {
+        double s = 0.0, s2 = 0.0;
+        for (int64_t t = threadIdx.x; t < nparts; t += blockDim.x) {
+            s += part[t];
+            s2 += part[pstride + t];
+        }
+        s = block_sum(s, red);
+        s2 = block_sum(s2, red);
+        if (threadIdx.x == 0) {
+            const double m = s * inv_count;
+            st->mean[0] = m;
+            st->bn[0] = sqrt(fmax(s2 - s * m, 0.0));   // sum (b - m)^2 = sum b^2 - m sum b
+        }
+        return;
+    }
     for (int comp = 0; comp < ncomp; ++comp) {
         const bool skip = (mode == FIN_CYCLE_R || mode == FIN_MEAN) && !st->active[comp];
         if (skip) continue;  // uniform across the block
@@ -1918,18 +1937,19 @@ hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
 // ||b - A x|| per component into the state (mode FIN_INIT_R / FIN_CYCLE_R);
 // in mixed mode also writes the scaled FP32 residual of every active component
 hipib_status resid_norm(hipib_ctx* ctx, int ncomp, const OpCoef& oc, int mode,
-                        double* rstore = nullptr) {
+                        double* rstore = nullptr, int submean = 0) {
     const int n = ctx->n;
     const double h = 1.0 / n, c = oc.nu / (h * h);
     const int64_t np = norm_parts(n);
     const double bytes = 16.0 * (double)ctx->n3 * ncomp;
     if (ctx->cfg.precision == HIPIB_MIXED)
         HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_RESID_NORM, bytes, k_resid_norm<true>, norm_grid(n, ncomp), dim3(TX, TY),
-                           0, ctx->xp, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, ctx->r32, ctx->part, np, rstore));
+                           0, ctx->sx, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, ctx->r32, ctx->part, np, rstore,
+                           submean));
     else
         HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_RESID_NORM, bytes, k_resid_norm<false>, norm_grid(n, ncomp),
-                           dim3(TX, TY), 0, ctx->xp, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, nullptr,
-                           ctx->part, np, rstore));
+                           dim3(TX, TY), 0, ctx->sx, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, nullptr,
+                           ctx->part, np, rstore, submean));
     return finalize(ctx, np, np, ncomp, mode, 0.0);
 }
 
@@ -1973,7 +1993,7 @@ hipib_status cg_iteration(hipib_ctx* ctx, const OpCoef& oc) {
     HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_REDUCE, 8.0 * np, k_cg_scalars, dim3(1), dim3(1024), 0, ctx->part, np, np,
                        (int)CG_ALPHA, ctx->st));
     HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_UPDATE, (mixed ? 52.0 : 48.0) * n3, k_cg_update, dim3(nb), dim3(256), 0,
-                       ctx->xp, r, p, q, n3, ctx->st, mixed ? ctx->r32 : nullptr, ctx->part));
+                       ctx->sx, r, p, q, n3, ctx->st, mixed ? ctx->r32 : nullptr, ctx->part));
     return finalize(ctx, nb, nb, 1, FIN_CYCLE_R, 0.0);
 }
 
@@ -1987,10 +2007,10 @@ hipib_status cycle(hipib_ctx* ctx, int ncomp, const OpCoef& oc) {
     const int nb = sum_blocks(ctx->n3);
     if (ctx->cfg.precision == HIPIB_MIXED) {
         HIPIB_TRY(vcycle<float>(ctx, 0, LevelPtr<float>{ctx->e32, ctx->r32, ctx->n3}, ncomp, oc, true));
-        k_update<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->xp, ctx->e32, ctx->n3, ctx->st);
+        k_update<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->sx, ctx->e32, ctx->n3, ctx->st);
         HIPIB_HIP(hipGetLastError());
     } else {
-        HIPIB_TRY(vcycle<double>(ctx, 0, LevelPtr<double>{ctx->xp, ctx->bpk, ctx->n3}, ncomp, oc, false));
+        HIPIB_TRY(vcycle<double>(ctx, 0, LevelPtr<double>{ctx->sx, ctx->bpk, ctx->n3}, ncomp, oc, false));
     }
     return resid_norm(ctx, ncomp, oc, FIN_CYCLE_R);
 }
@@ -2115,24 +2135,33 @@ hipib_status mg_remove_mean(hipib_ctx* ctx, double* v, int /*slot*/) {
     return HIPIB_OK;
 }
 
-hipib_status mg_solve(hipib_ctx* ctx, int op, int ncomp, const double* b, double* x,
-                      int32_t* cycles, double* relres) {
+// The solve on packed arrays: xpk holds the initial guess, ctx->bpk the
+// right-hand side.  b_ready: the state was reset and holds ||b - mean(b)|| and
+// the mean of b (Poisson, component 0), which the initial residual pass then
+// subtracts from b.  A converged Poisson solve leaves the solution's mean in
+// the state for the caller to subtract (the null space of the periodic
+// Laplacian); *mean_ok says whether it is there.
+// device address of the state's mean[] (no host access to the state)
+const double* state_mean(const hipib_ctx* ctx) {
+    return reinterpret_cast<const double*>(reinterpret_cast<const char*>(ctx->st) + offsetof(MGState, mean));
+}
+
+hipib_status solve_packed(hipib_ctx* ctx, int op, int ncomp, double* xpk, bool b_ready, int32_t* cycles,
+                          double* relres, bool* mean_ok) {
     const OpCoef oc = op_coef(ctx, op);
-    const int n = ctx->n;
     const int nb = sum_blocks(ctx->n3);
-    // pack the caller's b and initial guess
-    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_PACK, 16.0 * (double)ctx->n3 * ncomp, k_pack, natural_grid(n, ncomp),
-                       dim3(TX, TY), 0, b, ctx->bpk, n, ctx->n3));
-    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_PACK, 16.0 * (double)ctx->n3 * ncomp, k_pack, natural_grid(n, ncomp),
-                       dim3(TX, TY), 0, x, ctx->xp, n, ctx->n3));
-    k_state_reset<<<1, 64, 0, ctx->stream>>>(ctx->st, ncomp);
-    k_sum_partials<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->bpk, ctx->n3, ctx->n3, 1, nullptr,
-                                                             ctx->part, nb);
-    HIPIB_HIP(hipGetLastError());
-    HIPIB_TRY(finalize(ctx, nb, nb, ncomp, FIN_BNORM, 0.0));
+    ctx->sx = xpk;
+    if (!b_ready) {
+        k_state_reset<<<1, 64, 0, ctx->stream>>>(ctx->st, ncomp);
+        k_sum_partials<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->bpk, ctx->n3, ctx->n3, 1, nullptr,
+                                                                 ctx->part, nb);
+        HIPIB_HIP(hipGetLastError());
+        HIPIB_TRY(finalize(ctx, nb, nb, ncomp, FIN_BNORM, 0.0));
+    }
     // (conjugate gradients keep the initial residual as their r)
-    HIPIB_TRY(resid_norm(ctx, ncomp, oc, FIN_INIT_R, use_cg(ctx, oc, ncomp) ? ctx->kv[0] : nullptr));
-    k_zero_requested<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->xp, ctx->n3, ctx->n3, ctx->st);
+    HIPIB_TRY(resid_norm(ctx, ncomp, oc, FIN_INIT_R, use_cg(ctx, oc, ncomp) ? ctx->kv[0] : nullptr,
+                         b_ready && oc.poisson ? 1 : 0));
+    k_zero_requested<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(xpk, ctx->n3, ctx->n3, ctx->st);
     HIPIB_HIP(hipGetLastError());
 
     int enqueue = ctx->predicted[op] > 0 ? ctx->predicted[op] : 1;
@@ -2151,17 +2180,13 @@ hipib_status mg_solve(hipib_ctx* ctx, int op, int ncomp, const double* b, double
         if (total > limit) return fail(HIPIB_E_NOCONV, "multigrid: stop state did not settle");
         enqueue = 1;
     }
-    if (oc.poisson && ctx->st_host->status == HIPIB_OK) {
-        // the solution's mean (the null space of the periodic Laplacian) is removed once
-        k_sum_partials<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->xp, ctx->n3, ctx->n3, 0,
-                                                                  nullptr, ctx->part, nb);
+    *mean_ok = oc.poisson && ctx->st_host->status == HIPIB_OK;
+    if (*mean_ok) {
+        k_sum_partials<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(xpk, ctx->n3, ctx->n3, 0, nullptr, ctx->part,
+                                                                 nb);
         HIPIB_HIP(hipGetLastError());
         HIPIB_TRY(finalize(ctx, nb, nb, ncomp, FIN_MEAN_ALL, 1.0 / (double)ctx->n3));
-        k_sub_mean<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->xp, ctx->n3, ctx->n3, ctx->st, 1);
-        HIPIB_HIP(hipGetLastError());
     }
-    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_PACK, 16.0 * (double)ctx->n3 * ncomp, k_unpack, natural_grid(n, ncomp),
-                       dim3(TX, TY), 0, ctx->xp, x, n, ctx->n3));
     const MGState& s = *ctx->st_host;
     int mx = 1;
     for (int c = 0; c < ncomp; ++c) {
@@ -2174,6 +2199,152 @@ hipib_status mg_solve(hipib_ctx* ctx, int op, int ncomp, const double* b, double
         return fail(HIPIB_E_NOCONV, "multigrid did not reach rtol %g in %d cycles", ctx->cfg.mg_rtol,
                     ctx->cfg.mg_max_cycles);
     if (s.status == HIPIB_E_NUMERIC) return fail(HIPIB_E_NUMERIC, "multigrid: non-finite residual");
+    return HIPIB_OK;
+}
+
+hipib_status mg_solve(hipib_ctx* ctx, int op, int ncomp, const double* b, double* x,
+                      int32_t* cycles, double* relres) {
+    const int n = ctx->n;
+    // pack the caller's b and initial guess
+    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_PACK, 16.0 * (double)ctx->n3 * ncomp, k_pack, natural_grid(n, ncomp),
+                       dim3(TX, TY), 0, b, ctx->bpk, n, ctx->n3));
+    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_PACK, 16.0 * (double)ctx->n3 * ncomp, k_pack, natural_grid(n, ncomp),
+                       dim3(TX, TY), 0, x, ctx->xp, n, ctx->n3));
+    bool mean_ok = false;
+    const hipib_status s = solve_packed(ctx, op, ncomp, ctx->xp, false, cycles, relres, &mean_ok);
+    // unpack (a Poisson solution without its mean), also after a failed solve
+    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_PACK, 16.0 * (double)ctx->n3 * ncomp, k_unpack, natural_grid(n, ncomp),
+                       dim3(TX, TY), 0, ctx->xp, x, n, ctx->n3,
+                       mean_ok ? state_mean(ctx) : nullptr));
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// The fluid part of a step on the packed layout: the right-hand side builder
+// packs u^n as the Helmholtz guess, u* stays packed from the Helmholtz solve
+// to the projection, the divergence writes the Poisson right-hand side packed
+// (with the partial sums of its mean and norm), and p is solved in place in
+// its own packed array (ctx->bp).
+// ---------------------------------------------------------------------------
+
+// b = -(rho/dt) D u* on the colour-q cells of a column, from the packed u*;
+// block partials of sum b (slot 0) and sum b^2 (slot 1).  Grid and columns as
+// k_resid_norm (one component, both colours).
+__global__ void __launch_bounds__(TX * TY)
+k_divergence_packed(const double* __restrict__ u, double* __restrict__ b, int n, int64_t n3, double rho_dt,
+                    double inv_h, double* __restrict__ part, int64_t pstride) {
+    __shared__ double red[2][(TX * TY) / 64];
+    const int nkb = (n + KPT - 1) / KPT;
+    const int rem = blockIdx.z, q = rem / nkb, k0 = (rem - q * nkb) * KPT;
+    const int H = n >> 1;
+    const int ih = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y;
+    double s1 = 0.0, s2 = 0.0;
+    if (ih < H && j < n) {
+        const int64_t half3 = (int64_t)H * n * n;
+        const int64_t oo = (1 - q) * half3;   // the other colour: the + neighbours
+        const int jp = wrapi(j + 1, n);
+        const int ihp = ih + 1 < H ? ih + 1 : 0;
+        double ux[KPT], uxp[KPT], uy[KPT], uyp[KPT], uz[KPT], uzp[KPT];
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) {
+            const int k = k0 + r;
+            if (k < n) {
+                const int64_t row = (int64_t)H * ((int64_t)j + (int64_t)n * k);
+                const int64_t oq = q * half3 + row + ih;
+                const int p = (j + k + q) & 1;        // i = 2 ih + p; i + 1 sits at ih + p
+                ux[r] = u[oq];
+                uxp[r] = u[oo + row + (p ? ihp : ih)];
+                uy[r] = u[n3 + oq];
+                uyp[r] = u[n3 + oo + (int64_t)H * ((int64_t)jp + (int64_t)n * k) + ih];
+                uz[r] = u[2 * n3 + oq];
+                uzp[r] = u[2 * n3 + oo + (int64_t)H * ((int64_t)j + (int64_t)n * wrapi(k + 1, n)) + ih];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) {
+            const int k = k0 + r;
+            if (k < n) {
+                double sd = (uxp[r] - ux[r]) * inv_h;
+                sd += (uyp[r] - uy[r]) * inv_h;
+                sd += (uzp[r] - uz[r]) * inv_h;
+                const double bv = -rho_dt * sd;
+                b[q * half3 + (int64_t)H * ((int64_t)j + (int64_t)n * k) + ih] = bv;
+                s1 += bv;
+                s2 += bv * bv;
+            }
+        }
+    }
+    const int tid = threadIdx.x + TX * threadIdx.y;
+    for (int o = 32; o > 0; o >>= 1) {
+        s1 += __shfl_down(s1, o, 64);
+        s2 += __shfl_down(s2, o, 64);
+    }
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = s1;
+        red[1][tid >> 6] = s2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double a = 0.0, c = 0.0;
+        for (int w = 0; w < (TX * TY) / 64; ++w) {
+            a += red[0][w];
+            c += red[1][w];
+        }
+        const int64_t blk = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * rem);
+        part[blk] = a;
+        part[pstride + blk] = c;
+    }
+}
+
+// u^{n+1}[c] = u*[c] - (dt/rho) G p and p[c] (natural) from the packed u* and
+// p, with p's mean subtracted first (mean may be null)
+__global__ void __launch_bounds__(TX * TY)
+k_project_packed(const double* __restrict__ us, const double* __restrict__ pp, const double* __restrict__ mean,
+                 double* __restrict__ u, double* __restrict__ p, int n, int64_t n3, double dt_rho, double inv_h) {
+    const int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
+    if (i >= n || j >= n) return;
+    const double m = mean ? mean[0] : 0.0;
+    const int64_t o = pk(i, j, k, n);
+    const double pc = pp[o] - m;
+    const double px = pp[pk(wrapi(i - 1, n), j, k, n)] - m;
+    const double py = pp[pk(i, wrapi(j - 1, n), k, n)] - m;
+    const double pz = pp[pk(i, j, wrapi(k - 1, n), n)] - m;
+    const int64_t c = i + (int64_t)n * (j + (int64_t)n * k);
+    u[c] = us[o] - dt_rho * ((pc - px) * inv_h);
+    u[n3 + c] = us[n3 + o] - dt_rho * ((pc - py) * inv_h);
+    u[2 * n3 + c] = us[2 * n3 + o] - dt_rho * ((pc - pz) * inv_h);
+    p[c] = pc;
+}
+
+hipib_status fluid_step_packed(hipib_ctx* ctx, double* u, double* p, int32_t* cyc, double* rr,
+                               hipib_status (*mark)(hipib_ctx*, int)) {
+    const int n = ctx->n;
+    const int64_t n3 = ctx->n3;
+    // Helmholtz: g (natural, built and spread by the caller) packed into b; the
+    // guess u^n was packed into xp by the right-hand side builder
+    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_PACK, 48.0 * (double)n3, k_pack, natural_grid(n, 3), dim3(TX, TY), 0,
+                       ctx->g, ctx->bpk, n, n3));
+    bool mean_ok = false;
+    HIPIB_TRY(solve_packed(ctx, HIPIB_OP_HELMHOLTZ, 3, ctx->xp, false, cyc, rr, &mean_ok));
+    if (mark) HIPIB_TRY(mark(ctx, 3));
+    // Poisson: guess p^{n-1} packed into bp; b = -(rho/dt) D u* packed, its mean
+    // and norm reduced from the divergence pass's partials
+    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_PACK, 16.0 * (double)n3, k_pack, natural_grid(n, 1), dim3(TX, TY), 0, p,
+                       ctx->bp, n, n3));
+    k_state_reset<<<1, 64, 0, ctx->stream>>>(ctx->st, 1);
+    HIPIB_HIP(hipGetLastError());
+    const int64_t np = norm_parts(n);
+    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_DIVERGENCE, 32.0 * (double)n3, k_divergence_packed, norm_grid(n, 1),
+                       dim3(TX, TY), 0, ctx->xp, ctx->bpk, n, n3, ctx->cfg.rho / ctx->cfg.dt, 1.0 / ctx->h,
+                       ctx->part, np));
+    HIPIB_TRY(finalize(ctx, np, np, 1, FIN_MEAN_BNORM, 1.0 / (double)n3));
+    HIPIB_TRY(solve_packed(ctx, HIPIB_OP_POISSON, 1, ctx->bp, true, cyc + 3, rr + 3, &mean_ok));
+    if (mark) HIPIB_TRY(mark(ctx, 4));
+    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_PROJECT, 64.0 * (double)n3, k_project_packed, natural_grid(n, 1),
+                       dim3(TX, TY), 0, ctx->xp, ctx->bp,
+                       mean_ok ? state_mean(ctx) : nullptr, u, p, n, n3,
+                       ctx->cfg.dt / ctx->cfg.rho, 1.0 / ctx->h));
+    if (mark) HIPIB_TRY(mark(ctx, 5));
     return HIPIB_OK;
 }
 
