@@ -660,16 +660,29 @@ k_cg_dir(const TZ* __restrict__ z, double* __restrict__ p, double* __restrict__ 
     }
 }
 
-// x += alpha p, r -= alpha q, partial ||r||^2 per block; r32 (mixed) = r / ||b||
+// alpha = (r.z) / (p.q), p.q summed from the npq partials of k_cg_dir in a
+// fixed order by every block (so all blocks hold the same alpha; block 0 keeps
+// it in the state for the next beta); then x += alpha p, r -= alpha q, partials
+// of ||r||^2 (part[block]) and of sum x (part[gridDim.x + block], for the mean
+// of the converged solution); r32 (mixed) = r / ||b||
 __global__ void __launch_bounds__(256)
 k_cg_update(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
-            const double* __restrict__ q, int64_t n3, const MGState* __restrict__ st,
-            float* __restrict__ r32, double* __restrict__ part) {
+            const double* __restrict__ q, int64_t n3, MGState* __restrict__ st,
+            float* __restrict__ r32, const double* __restrict__ pq_part, int64_t npq, double* __restrict__ part) {
     __shared__ double red[16];
     if (!st->active[0]) return;  // uniform
-    const double alpha = st->alpha, inv_bn = r32 ? 1.0 / st->bn[0] : 0.0;
+    double a = 0.0;
+    for (int64_t t = threadIdx.x; t < npq; t += 256) a += pq_part[t];
+    a = block_sum(a, red);
+    __shared__ double alpha_s;
+    if (threadIdx.x == 0) {
+        alpha_s = a != 0.0 ? st->rz / a : 0.0;
+        if (blockIdx.x == 0) st->alpha = alpha_s;
+    }
+    __syncthreads();
+    const double alpha = alpha_s, inv_bn = r32 ? 1.0 / st->bn[0] : 0.0;
     const int64_t stride = (int64_t)gridDim.x * 256;
-    double v = 0.0;
+    double v = 0.0, sx = 0.0;
     for (int64_t t0 = (int64_t)blockIdx.x * 256 + threadIdx.x; t0 < n3; t0 += 4 * stride) {
         double xv[4], rv[4], pv[4], qv[4];
 #pragma unroll
@@ -687,40 +700,40 @@ k_cg_update(double* __restrict__ x, double* __restrict__ r, const double* __rest
             const int64_t t = t0 + u * stride;
             if (t < n3) {
                 const double rn = rv[u] - alpha * qv[u];
-                x[t] = xv[u] + alpha * pv[u];
+                const double xn = xv[u] + alpha * pv[u];
+                x[t] = xn;
                 r[t] = rn;
                 v += rn * rn;
+                sx += xn;
                 if (r32) r32[t] = (float)(rn * inv_bn);
             }
         }
     }
     v = block_sum(v, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = v;
+    sx = block_sum(sx, red);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = v;
+        part[gridDim.x + blockIdx.x] = sx;
+    }
 }
 
-enum CgMode { CG_BETA = 0, CG_ALPHA = 1 };
-
-// reduce the partials in a fixed order and update the CG scalars
+// reduce the dot partials (slot 0: r.z, slot 1: z.q) in a fixed order; beta and
+// the new r.z into the state
 __global__ void __launch_bounds__(1024)
-k_cg_scalars(const double* __restrict__ part, int64_t nparts, int64_t pstride, int mode,
-             MGState* st) {
+k_cg_scalars(const double* __restrict__ part, int64_t nparts, int64_t pstride, MGState* st) {
     __shared__ double red[16];
     if (!st->active[0]) return;  // uniform
     double a = 0.0, b = 0.0;
     for (int64_t t = threadIdx.x; t < nparts; t += blockDim.x) {
         a += part[t];
-        if (mode == CG_BETA) b += part[pstride + t];
+        b += part[pstride + t];
     }
     a = block_sum(a, red);
     b = block_sum(b, red);
     if (threadIdx.x == 0) {
-        if (mode == CG_BETA) {
-            // a = r.z (new), b = z.q with q = A p of the previous iteration
-            st->beta = (st->cycles[0] == 0 || st->rz == 0.0) ? 0.0 : -st->alpha * b / st->rz;
-            st->rz = a;
-        } else {
-            st->alpha = a != 0.0 ? st->rz / a : 0.0;   // a = p.q
-        }
+        // a = r.z (new), b = z.q with q = A p of the previous iteration
+        st->beta = (st->cycles[0] == 0 || st->rz == 0.0) ? 0.0 : -st->alpha * b / st->rz;
+        st->rz = a;
     }
 }
 
@@ -1672,11 +1685,17 @@ double level_omega(int n, const OpCoef& oc) {
     return 2.0 / (1.0 + std::sqrt(1.0 - rho * rho));
 }
 
+// reduce the partials at ctx->part + offset
+hipib_status finalize_at(hipib_ctx* ctx, int64_t offset, int64_t nparts, int64_t pstride, int ncomp, int mode,
+                         double inv_count) {
+    return launch_k(ctx, HIPIB_TIMER_REDUCE, 8.0 * (double)nparts * ncomp, k_finalize, dim3(1), dim3(1024), 0,
+                    ctx->part + offset, nparts, pstride, ncomp, mode, ctx->st, ctx->cfg.mg_rtol,
+                    ctx->cfg.mg_max_cycles, ctx->cfg.mg_fixed_cycles, inv_count);
+}
+
 hipib_status finalize(hipib_ctx* ctx, int64_t nparts, int64_t pstride, int ncomp, int mode,
                       double inv_count) {
-    return launch_k(ctx, HIPIB_TIMER_REDUCE, 8.0 * (double)nparts * ncomp, k_finalize, dim3(1), dim3(1024), 0,
-                    ctx->part, nparts, pstride, ncomp, mode, ctx->st, ctx->cfg.mg_rtol,
-                    ctx->cfg.mg_max_cycles, ctx->cfg.mg_fixed_cycles, inv_count);
+    return finalize_at(ctx, 0, nparts, pstride, ncomp, mode, inv_count);
 }
 
 template <typename T>
@@ -1983,18 +2002,17 @@ hipib_status cg_iteration(hipib_ctx* ctx, const OpCoef& oc) {
         dparts = nb;
     }
     HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_REDUCE, 16.0 * dparts, k_cg_scalars, dim3(1), dim3(1024), 0, ctx->part,
-                       dparts, dparts, (int)CG_BETA, ctx->st));
+                       dparts, dparts, ctx->st));
     if (mixed)
         HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_DIR, (32.0 + zb) * n3, k_cg_dir<float>, norm_grid(n, 1), dim3(TX, TY),
                            0, ctx->e32, p, q, n, oc.sigma, c, ctx->st, ctx->part));
     else
         HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_DIR, (32.0 + zb) * n3, k_cg_dir<double>, norm_grid(n, 1), dim3(TX, TY),
                            0, z, p, q, n, oc.sigma, c, ctx->st, ctx->part));
-    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_REDUCE, 8.0 * np, k_cg_scalars, dim3(1), dim3(1024), 0, ctx->part, np, np,
-                       (int)CG_ALPHA, ctx->st));
+    // (alpha is reduced by k_cg_update itself: its ||r||^2 partials go after p.q's)
     HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_UPDATE, (mixed ? 52.0 : 48.0) * n3, k_cg_update, dim3(nb), dim3(256), 0,
-                       ctx->sx, r, p, q, n3, ctx->st, mixed ? ctx->r32 : nullptr, ctx->part));
-    return finalize(ctx, nb, nb, 1, FIN_CYCLE_R, 0.0);
+                       ctx->sx, r, p, q, n3, ctx->st, mixed ? ctx->r32 : nullptr, ctx->part, np, ctx->part + np));
+    return finalize_at(ctx, np, nb, nb, 1, FIN_CYCLE_R, 0.0);
 }
 
 bool use_cg(const hipib_ctx* ctx, const OpCoef& oc, int ncomp) {
@@ -2181,7 +2199,11 @@ hipib_status solve_packed(hipib_ctx* ctx, int op, int ncomp, double* xpk, bool b
         enqueue = 1;
     }
     *mean_ok = oc.poisson && ctx->st_host->status == HIPIB_OK;
-    if (*mean_ok) {
+    if (*mean_ok && use_cg(ctx, oc, ncomp) && ctx->st_host->cycles[0] > 0) {
+        // the last conjugate-gradient update left the partial sums of x after
+        // its ||r||^2 partials (later enqueued cycles were no-ops)
+        HIPIB_TRY(finalize_at(ctx, norm_parts(ctx->n) + nb, nb, nb, 1, FIN_MEAN_ALL, 1.0 / (double)ctx->n3));
+    } else if (*mean_ok) {
         k_sum_partials<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(xpk, ctx->n3, ctx->n3, 0, nullptr, ctx->part,
                                                                  nb);
         HIPIB_HIP(hipGetLastError());
