@@ -226,17 +226,21 @@ def kernel_classes(hipib):
         (H.TIMER_PROLONG, "k_prolong_add<double>", "finest-level prolongation to the red cells, 9 B/cell"),
         (H.TIMER_LEVEL_DOWN, "k_level_down<double>", "first coarse level, down half, 17 B per cell of that level"),
         (H.TIMER_LEVEL_UP, "k_level_up<double>", "first coarse level, up half, 21 B per cell of that level"),
-        (H.TIMER_SMALL_VCYCLE, "k_coarse_exact<16,double>",
-         "coarsest level (16^3) solved exactly in one workgroup, 16 B per 16^3 cell"),
+        (H.TIMER_SMALL_VCYCLE, "k_exact_fwd_xy / k_exact_z / k_exact_inv_xy <32,double>",
+         "coarsest level (32^3) solved exactly, three plane-parallel passes, 16 B per 32^3 cell each"),
         (H.TIMER_RESID_NORM, "k_resid_norm<false>", "residual norm, 16 B/cell per component"),
         (H.TIMER_CG_DOTS, "k_gs_dot<double>",
          "last two post-smoothing half-sweeps of the preconditioner, with r.z and z.q, 16 B/cell"),
         (H.TIMER_CG_DIR, "k_cg_dir<double>", "p, q = A z + beta q and p.q, 40 B/cell"),
-        (H.TIMER_CG_UPDATE, "k_cg_update", "x, r updates and ||r||^2, 48 B/cell"),
+        (H.TIMER_CG_UPDATE, "k_cg_update",
+         "alpha from the p.q partials, x, r updates, ||r||^2 and sum-x partials, 48 B/cell"),
         (H.TIMER_REDUCE, "k_finalize / k_cg_scalars", "single-workgroup reductions, 8 B per partial"),
-        (H.TIMER_RHS, "k_rhs_build", "fluid right-hand side with convection, 48 B/cell"),
-        (H.TIMER_DIVERGENCE, "k_divergence_rhs", "Poisson right-hand side, 32 B/cell"),
-        (H.TIMER_PROJECT, "k_project", "velocity correction, 56 B/cell"),
+        (H.TIMER_RHS, "k_rhs_build",
+         "fluid right-hand side with convection, u^n packed as the Helmholtz guess, 72 B/cell"),
+        (H.TIMER_DIVERGENCE, "k_divergence_packed",
+         "Poisson right-hand side from the packed u*, with sum-b and sum-b^2 partials, 32 B/cell"),
+        (H.TIMER_PROJECT, "k_project_packed",
+         "velocity correction from the packed u* and p, u and p written in natural layout, 64 B/cell"),
         (H.TIMER_PACK, "k_pack / k_unpack", "layout conversions, 16 B/cell per component"),
         (H.TIMER_SPREAD, "k_spread_tiles<8,double>",
          "spreading: 52 B/node (X, F, order) + 16 B per touched grid value (f read and written)"),

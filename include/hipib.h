@@ -401,8 +401,10 @@ typedef enum {
     /* single-workgroup reductions of partials (stop tests, CG scalars): their
      * partials, 8 B each */
     HIPIB_TIMER_REDUCE = 12,
-    /* fluid right-hand side 48 B, divergence 32 B, velocity correction 56 B,
-     * layout conversions 16 B per cell and component */
+    /* fluid right-hand side 48 B (72 B with u^n packed as the Helmholtz guess
+     * inside a step), divergence 32 B, velocity correction 56 B (64 B from the
+     * packed u* and p inside a step), layout conversions 16 B per cell and
+     * component */
     HIPIB_TIMER_RHS = 13,
     HIPIB_TIMER_DIVERGENCE = 14,
     HIPIB_TIMER_PROJECT = 15,
