@@ -211,6 +211,127 @@ k_gs(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, T c, T inv_d
     }
 }
 
+// The first post-smoothing half-sweep (colour q, nonzero guess, no
+// over-relaxation) fused with the coarse-grid correction: the other colour's
+// values in its stencil are taken as x + P e, P the cell-centred trilinear
+// prolongation of the coarse correction e (3/4 on the nearest coarse cell,
+// 1/4 on the next, per axis).  x of the other colour is left uncorrected in
+// memory: the next half-sweep, of that colour, overwrites it from this
+// colour's values alone.  The workgroup stages the coarse values its stencils
+// reach in LDS, interpolates them along y and z into one row per fine (j, k)
+// it needs (Rw), and each neighbour's correction is the x-interpolation of two
+// row values.  Grid and columns as k_gs.
+template <typename T>
+__global__ void __launch_bounds__(TX * TY)
+k_gs_prolong(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, const T* __restrict__ xc, int nc,
+             int64_t ccs, T c, T inv_diag, int q, const int32_t* __restrict__ active) {
+    constexpr int KPT = gs_kpt<T>();
+    constexpr int RI = TX + 4;                        // coarse I: ih0 - 2 .. ih0 + TX + 1
+    constexpr int CJ = TY / 2 + 2, CK = KPT / 2 + 2;  // coarse J: j0/2 - 1 .. j0/2 + TY/2, K likewise
+    constexpr int NRJ = TY + 2, NRK = KPT + 2;        // fine rows j0 - 1 .. j0 + TY, planes k0 - 1 .. k0 + KPT
+    constexpr int NE = CK * CJ * RI, EPT = (NE + TX * TY - 1) / (TX * TY);
+    __shared__ T E[CK][CJ][RI];
+    __shared__ T Rw[NRK][NRJ][RI];
+    const uint3 bid = xcd_block();
+    const int nkb = (n + KPT - 1) / KPT;
+    const int comp = bid.z / nkb, k0 = (bid.z - comp * nkb) * KPT;
+    if (!active[comp]) return;  // block-uniform
+    const int H = n >> 1;
+    const int ih0 = bid.x * TX, j0 = bid.y * TY;
+    const int tid = threadIdx.x + TX * threadIdx.y;
+    const int ih = ih0 + threadIdx.x, j = j0 + threadIdx.y;
+    const bool own = ih < H && j < n;
+    const int64_t half3 = (int64_t)H * n * n;
+    T* xq = x + comp * cs + q * half3;
+    const T* xo = x + comp * cs + (1 - q) * half3;
+    const T* bq = b + comp * cs + q * half3;
+    const int jp = wrapi(j + 1, n), jm = wrapi(j - 1, n);
+    const int ihp = ih + 1 < H ? ih + 1 : 0, ihm = ih > 0 ? ih - 1 : H - 1;
+    // the half-sweep's own loads first, so their latency overlaps the staging
+    T col[KPT + 2], side[KPT], yp[KPT], ym[KPT], bv[KPT];
+    if (own) {
+#pragma unroll
+        for (int r = 0; r < KPT + 2; ++r) {
+            const int kk = wrapi(k0 - 1 + r, n);
+            col[r] = xo[ih + (int64_t)H * ((int64_t)j + (int64_t)n * kk)];
+        }
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) {
+            const int k = k0 + r;
+            if (k < n) {
+                const int64_t row = (int64_t)H * ((int64_t)j + (int64_t)n * k);
+                const int p = (j + k + q) & 1;
+                bv[r] = bq[row + ih];
+                side[r] = xo[row + (p ? ihp : ihm)];
+                yp[r] = xo[(int64_t)H * ((int64_t)jp + (int64_t)n * k) + ih];
+                ym[r] = xo[(int64_t)H * ((int64_t)jm + (int64_t)n * k) + ih];
+            }
+        }
+    }
+    const int I_lo = ih0 - 2, J_lo = j0 / 2 - 1, K_lo = k0 / 2 - 1;
+    const T* ec = xc + comp * ccs;
+    {
+        T ev[EPT];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int t = tid + e * TX * TY;
+            if (t < NE) {
+                const int ci = t % RI, cj = (t / RI) % CJ, ck = t / (RI * CJ);
+                // (I reaches ih0 + TX + 1, beyond 2 nc on small grids, where the
+                // high entries are staged but never read)
+                int I = I_lo + ci, J = J_lo + cj, K = K_lo + ck;   // all >= -2
+                I = I < 0 ? I + nc : (I >= nc ? I % nc : I);
+                J = J < 0 ? J + nc : (J >= nc ? J % nc : J);
+                K = K < 0 ? K + nc : (K >= nc ? K % nc : K);
+                ev[e] = ec[pk(I, J, K, nc)];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int t = tid + e * TX * TY;
+            if (t < NE) (&E[0][0][0])[t] = ev[e];
+        }
+    }
+    __syncthreads();
+    const T w0 = T(0.75), w1 = T(0.25);
+    for (int t = tid; t < NRK * NRJ * RI; t += TX * TY) {
+        const int ri = t % RI, rj = (t / RI) % NRJ, rk = t / (RI * NRJ);
+        // unwrapped fine row (j', k') and its two coarse rows per axis (arithmetic shifts floor)
+        const int ju = j0 - 1 + rj, ku = k0 - 1 + rk;
+        const int Jn = (ju >> 1) - J_lo, Jf = Jn + ((ju & 1) ? 1 : -1);
+        const int Kn = (ku >> 1) - K_lo, Kf = Kn + ((ku & 1) ? 1 : -1);
+        Rw[rk][rj][ri] = w0 * (w0 * E[Kn][Jn][ri] + w1 * E[Kn][Jf][ri]) +
+                         w1 * (w0 * E[Kf][Jn][ri] + w1 * E[Kf][Jf][ri]);
+    }
+    __syncthreads();
+    if (!own) return;
+    // correction at the other-colour cell of packed half-index hu (unwrapped) in
+    // row (rj, rk): its fine i = 2 hu + ((j' + k' + 1 - q) & 1)
+    auto pe = [&](int hu, int rj, int rk) -> T {
+        const int par = (j0 - 1 + rj + k0 - 1 + rk + 1 - q) & 1;
+        const int li = hu - I_lo;                     // local index of I = hu
+        const int lf = li + (par ? 1 : -1);
+        return w0 * Rw[rk][rj][li] + w1 * Rw[rk][rj][lf];
+    };
+    const int rj0 = threadIdx.y + 1;
+#pragma unroll
+    for (int r = 0; r < KPT + 2; ++r) col[r] += pe(ih, rj0, r);
+#pragma unroll
+    for (int r = 0; r < KPT; ++r) {
+        const int k = k0 + r;
+        if (k < n) {
+            const int p = (j + k + q) & 1;
+            side[r] += pe(p ? ih + 1 : ih - 1, rj0, r + 1);
+            yp[r] += pe(ih, rj0 + 1, r + 1);
+            ym[r] += pe(ih, rj0 - 1, r + 1);
+            const T a_ip = p ? side[r] : col[r + 1];
+            const T a_im = p ? col[r + 1] : side[r];
+            const T sn = a_ip + a_im + yp[r] + ym[r] + col[r + 2] + col[r];
+            xq[(int64_t)H * ((int64_t)j + (int64_t)n * k) + ih] = (bv[r] + c * sn) * inv_diag;
+        }
+    }
+}
+
 // A finest-level Poisson half-sweep of the conjugate-gradient preconditioner
 // (one component, nonzero guess, no over-relaxation) that also sums, over the
 // cells it writes, the dots r.z and z.q of the z it finishes: the last two
@@ -1863,7 +1984,7 @@ hipib_status relax(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef
 // Poisson half-sweep is timed on its own when the timer is on.
 template <typename T>
 hipib_status smooth(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoef& oc, int sweeps,
-                    int first, bool zero_guess) {
+                    int first, bool zero_guess, int start = 0) {
     if (sweeps <= 0) return HIPIB_OK;
     const int n = ctx->lv[l].n;
     const T h = T(1) / T(n);
@@ -1874,7 +1995,7 @@ hipib_status smooth(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
     const bool dots = l == 0 && ctx->cg_dots.q != nullptr && !zero_guess && ncomp == 1;
     const dim3 grid = gs_grid<T>(n, 1);
     const int64_t nb = (int64_t)grid.x * grid.y * grid.z;
-    for (int s = 0; s < 2 * sweeps; ++s) {
+    for (int s = start; s < 2 * sweeps; ++s) {
         const int zg = (s == 0 && zero_guess) ? 1 : 0;
         const int colour = (s & 1) ? 1 - first : first;
         if (dots && s >= 2 * sweeps - 2) {
@@ -1944,6 +2065,13 @@ hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
     }
     HIPIB_HIP(hipGetLastError());
     HIPIB_TRY(vcycle<T>(ctx, l + 1, LevelPtr<T>{xc, bc, C.n3}, ncomp, oc, true));
+    if (post >= 2) {
+        // the correction enters through the first (black) post-smoothing half-sweep
+        HIPIB_TRY(launch_k(ctx, l == 0 ? HIPIB_TIMER_PROLONG : 0, 13.0 / 8.0 * sizeof(T) * (double)ctx->lv[l].n3 * ncomp,
+                           k_gs_prolong<T>, gs_grid<T>(n, ncomp), dim3(TX, TY), 0, p.x, p.b, n, p.cs, xc, C.n,
+                           C.n3, c, T(1) / ((T)oc.sigma + T(6) * c), 1, act));
+        return smooth<T>(ctx, l, p, ncomp, oc, post, 1, false, 1);
+    }
     const int nq = post > 0 ? 1 : 2;
     HIPIB_TRY(launch_k(ctx, (l == 0 && nq == 1) ? HIPIB_TIMER_PROLONG : 0,
                        9.0 / 8.0 * sizeof(T) * (double)ctx->lv[l].n3 * ncomp, k_prolong_add<T>,
