@@ -244,7 +244,7 @@ def kernel_classes(hipib):
         (H.TIMER_PACK, "k_pack / k_unpack", "layout conversions, 16 B/cell per component"),
         (H.TIMER_SPREAD, "k_spread_tiles<8,double>",
          "spreading: 52 B/node (X, F, order) + 16 B per touched grid value (f read and written)"),
-        (H.TIMER_INTERP, "k_interp<double>",
+        (H.TIMER_INTERP, "k_interp_tiles<8,double>",
          "interpolation and position update: 52 B/node (X read and written, order) + 8 B per touched grid value"),
         (H.TIMER_FE_FORCE, "k_fe_force<double,Hex8>", "element forces, 3.7 kflop per hex (FP64 ALU)"),
     ]

@@ -222,57 +222,81 @@ k_spread_tiles(const double* __restrict__ X, const double* __restrict__ F, doubl
     }
 }
 
-// one thread per node: gather 3 x 64 values; optionally X += dt U (in place,
-// FP64).  TW: type of the weights and the accumulation.
-template <typename TW>
-__global__ void __launch_bounds__(256)
-k_interp(const double* X, const double* __restrict__ u, double* __restrict__ U, double* Xupd,
-         double dt, int nn, int n, int64_t n3, double inv_h, const int32_t* __restrict__ perm) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nn) return;
-    const int q = perm ? perm[t] : t;
-    const double X0 = X[3 * q], X1 = X[3 * q + 1], X2 = X[3 * q + 2];
-    const double x[3] = {X0 * inv_h, X1 * inv_h, X2 * inv_h};
-    double Uq[3];
-    for (int d = 0; d < 3; ++d) {
-        int i0[3];
-        TW w[3][4];
-        for (int e = 0; e < 3; ++e) {
-            const double r = safe_coord(x[e] - (e == d ? 0.0 : 0.5));
-            const double bf = floor(r);
-            const TW fr = (TW)(r - bf);
-            const TW sq = sqrt(TW(1) + TW(4) * fr * (TW(1) - fr));
-            w[e][0] = (TW(3) - TW(2) * fr - sq) * TW(0.125);
-            w[e][1] = (TW(3) - TW(2) * fr + sq) * TW(0.125);
-            w[e][2] = (TW(1) + TW(2) * fr + sq) * TW(0.125);
-            w[e][3] = (TW(1) + TW(2) * fr - sq) * TW(0.125);
-            i0[e] = wrap_mod((int)bf - 1, n);
+// Interpolation U = J(X) u, optionally X += dt U (in place, FP64), by the
+// binning's work items: one workgroup per item (grid-stride over the list),
+// up to kSpreadChunk nodes of one tile, one node per thread.  The E^3 box of
+// each velocity component around the tile (E = T + 4, from T * tile - 2, the
+// reach of every node's 4x4x4 stencils on all three staggered lattices) is
+// staged in LDS with coalesced row loads, so the stencil values a tile's nodes
+// share are fetched from L2 once; each node's 3 x 64-term sums then read LDS,
+// in the same weights and order as a direct gather.  TW: type of the box, the
+// weights and the accumulation.
+template <int T, typename TW>
+__global__ void __launch_bounds__(kSpreadChunk)
+k_interp_tiles(const double* X, const double* __restrict__ u, double* __restrict__ U, double* Xupd, double dt,
+               const int32_t* __restrict__ perm, const int32_t* __restrict__ off,
+               const int32_t* __restrict__ list, const int32_t* __restrict__ nlist, int n, int ta,
+               int64_t n3, double inv_h) {
+    constexpr int E = T + 4, E3 = E * E * E;
+    __shared__ TW box[3 * E3];
+    const int ntl = *nlist;
+    for (int li = blockIdx.x; li < ntl; li += gridDim.x) {
+        const int tile = list[2 * li];
+        const int tb[3] = {T * (tile % ta), T * ((tile / ta) % ta), T * (tile / (ta * ta))};
+        __syncthreads();   // the previous item's reads of the box are done
+        for (int e = threadIdx.x; e < 3 * E3; e += blockDim.x) {
+            const int d = e / E3, r = e - d * E3;
+            const int lx = r % E, ly = (r / E) % E, lz = r / (E * E);
+            const int gx = wrap_mod(tb[0] - 2 + lx, n), gy = wrap_mod(tb[1] - 2 + ly, n),
+                      gz = wrap_mod(tb[2] - 2 + lz, n);
+            box[e] = (TW)u[d * n3 + gx + (int64_t)n * (gy + (int64_t)n * gz)];
         }
-        const double* ud = u + d * n3;
-        TW acc = TW(0);
-        for (int c = 0; c < 4; ++c) {
-            const int kk = step_wrap(i0[2] + c, n);
-            for (int b = 0; b < 4; ++b) {
-                const int jj = step_wrap(i0[1] + b, n);
-                const TW wyz = w[1][b] * w[2][c];
-                const int64_t row = (int64_t)n * ((int64_t)jj + (int64_t)n * kk);
-                for (int a = 0; a < 4; ++a) {
-                    const int ii = step_wrap(i0[0] + a, n);
-                    acc += (TW)ud[row + ii] * (w[0][a] * wyz);
+        __syncthreads();
+        const int idx = off[tile] + list[2 * li + 1] + threadIdx.x;
+        if (idx < off[tile + 1]) {
+            const int q = perm[idx];
+            const double X0 = X[3 * q], X1 = X[3 * q + 1], X2 = X[3 * q + 2];
+            const double xs[3] = {safe_coord(X0 * inv_h), safe_coord(X1 * inv_h), safe_coord(X2 * inv_h)};
+            int cw[3];
+            for (int e = 0; e < 3; ++e) cw[e] = wrap_mod((int)floor(xs[e]), n);
+            TW Uq[3];
+            for (int d = 0; d < 3; ++d) {
+                int ls[3];
+                TW w[3][4];
+                for (int e = 0; e < 3; ++e) {
+                    const double r = xs[e] - (e == d ? 0.0 : 0.5);
+                    const double bf = floor(r);
+                    const TW fr = (TW)(r - bf);
+                    const TW sq = sqrt(TW(1) + TW(4) * fr * (TW(1) - fr));
+                    w[e][0] = (TW(3) - TW(2) * fr - sq) * TW(0.125);
+                    w[e][1] = (TW(3) - TW(2) * fr + sq) * TW(0.125);
+                    w[e][2] = (TW(1) + TW(2) * fr + sq) * TW(0.125);
+                    w[e][3] = (TW(1) + TW(2) * fr - sq) * TW(0.125);
+                    // stencil start relative to the node's cell is -1 or -2
+                    const int ds = (int)bf - 1 - (int)floor(xs[e]);
+                    ls[e] = cw[e] - tb[e] + 2 + ds;
                 }
+                const TW* bd = box + d * E3;
+                TW acc = TW(0);
+                for (int c = 0; c < 4; ++c)
+                    for (int b = 0; b < 4; ++b) {
+                        const TW wyz = w[1][b] * w[2][c];
+                        const int row = ls[0] + E * ((ls[1] + b) + E * (ls[2] + c));
+                        for (int a = 0; a < 4; ++a) acc += bd[row + a] * (w[0][a] * wyz);
+                    }
+                Uq[d] = acc;
+            }
+            if (U) {
+                U[3 * q] = (double)Uq[0];
+                U[3 * q + 1] = (double)Uq[1];
+                U[3 * q + 2] = (double)Uq[2];
+            }
+            if (Xupd) {
+                Xupd[3 * q] = X0 + dt * (double)Uq[0];
+                Xupd[3 * q + 1] = X1 + dt * (double)Uq[1];
+                Xupd[3 * q + 2] = X2 + dt * (double)Uq[2];
             }
         }
-        Uq[d] = (double)acc;
-    }
-    if (U) {
-        U[3 * q] = Uq[0];
-        U[3 * q + 1] = Uq[1];
-        U[3 * q + 2] = Uq[2];
-    }
-    if (Xupd) {
-        Xupd[3 * q] = X0 + dt * Uq[0];
-        Xupd[3 * q + 1] = X1 + dt * Uq[1];
-        Xupd[3 * q + 2] = X2 + dt * Uq[2];
     }
 }
 
@@ -319,12 +343,20 @@ hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, dou
 hipib_status launch_interpolate(hipib_ctx* ctx, const double* X, const double* u, double* U,
                                 double* Xupd, double dt) {
     if (ctx->nn == 0) return HIPIB_OK;
-    const dim3 grid((ctx->nn + 255) / 256);
-    if (ctx->cfg.precision == HIPIB_MIXED)
-        return launch_k(ctx, HIPIB_TIMER_INTERP, 0.0, k_interp<float>, grid, dim3(256), 0, X, u, U, Xupd, dt,
-                        ctx->nn, ctx->n, ctx->n3, 1.0 / ctx->h, ctx->perm);
-    return launch_k(ctx, HIPIB_TIMER_INTERP, 0.0, k_interp<double>, grid, dim3(256), 0, X, u, U, Xupd, dt,
-                    ctx->nn, ctx->n, ctx->n3, 1.0 / ctx->h, ctx->perm);
+    const int64_t cap = spread_list_cap(ctx->ntiles, ctx->nn);
+    const int blocks = (int)(cap < 8192 ? cap : 8192);
+    const bool mixed = ctx->cfg.precision == HIPIB_MIXED;
+#define HIPIB_INTERP(TT, TW)                                                                               \
+    return launch_k(ctx, HIPIB_TIMER_INTERP, 0.0, k_interp_tiles<TT, TW>, dim3(blocks), dim3(kSpreadChunk), 0, X, \
+                    u, U, Xupd, dt, ctx->perm, ctx->bin_off, ctx->tile_list, ctx->n_list, ctx->n,               \
+                    ctx->tiles_axis, ctx->n3, 1.0 / ctx->h)
+    if (ctx->tile == 8) {
+        if (mixed) HIPIB_INTERP(8, float);
+        HIPIB_INTERP(8, double);
+    }
+    if (mixed) HIPIB_INTERP(4, float);
+    HIPIB_INTERP(4, double);
+#undef HIPIB_INTERP
 }
 
 }  // namespace hipib
