@@ -1673,48 +1673,57 @@ k_level_up(const T* __restrict__ b, const T* __restrict__ xpre, const T* __restr
     const T* bcp = b + comp * cs;
     const T* xpp = xpre + comp * cs;
     const T* xcc = xc + comp * ccs;
+    // the coarse correction around the block (the 10^3 coarse cells the
+    // trilinear prolongation reaches from the box) in LDS, read once
+    constexpr int KCE = (KUE / 2) + 2;
+    __shared__ T cs_[KCE * KCE * KCE];
+    const int c0x = g0x / 2 - 1, c0y = g0y / 2 - 1, c0z = g0z / 2 - 1;   // (g0 even)
+    for (int u = threadIdx.x; u < KCE * KCE * KCE; u += KTHREADS) {
+        const int a = u % KCE, bb = (u / KCE) % KCE, cc = u / (KCE * KCE);
+        cs_[u] = xcc[pk(wrapi(c0x + a, nc), wrapi(c0y + bb, nc), wrapi(c0z + cc, nc), nc)];
+    }
+    __syncthreads();
     // red cells of the whole box: smoothed x plus the trilinear correction
     {
         constexpr int S = KUE, S2 = S / 2, CNT = S2 * S * S;
         const T wt[2] = {T(0.75), T(0.25)};
-        // two passes of half the cells each keep the loads of a pass in flight
-        for (int pass = 0; pass < 2; ++pass) {
-            constexpr int R = (CNT / 2 + KTHREADS - 1) / KTHREADS;
-            T cv[R][8], xv[R];
-            int oo[R];
+        constexpr int R = (CNT + KTHREADS - 1) / KTHREADS;
+        T xv[R];
+        int oo[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int u = pass * (CNT / 2) + threadIdx.x + r * KTHREADS;
-                oo[r] = -1;
-                if (u < (pass + 1) * (CNT / 2)) {
-                    const int ah = u % S2, rest = u / S2;
-                    const int lb = rest % S, lc = rest / S;
-                    const int la = 2 * ah + ((g0x + g0y + lb + g0z + lc) & 1);
-                    const int ijk[3] = {wrapi(g0x + la, n), wrapi(g0y + lb, n), wrapi(g0z + lc, n)};
-                    int base[3][2];
-                    for (int d = 0; d < 3; ++d) {
-                        const int I = ijk[d] >> 1;
-                        base[d][0] = I;
-                        base[d][1] = (ijk[d] & 1) ? wrapi(I + 1, nc) : wrapi(I - 1, nc);
-                    }
-                    for (int cz = 0; cz < 2; ++cz)
-                        for (int cy = 0; cy < 2; ++cy)
-                            for (int cx = 0; cx < 2; ++cx)
-                                cv[r][cx + 2 * (cy + 2 * cz)] = xcc[pk(base[0][cx], base[1][cy], base[2][cz], nc)];
-                    xv[r] = xpp[pk(ijk[0], ijk[1], ijk[2], n)];
-                    oo[r] = lix<KUE>(la, lb, lc);
-                }
+        for (int r = 0; r < R; ++r) {
+            const int u = threadIdx.x + r * KTHREADS;
+            oo[r] = -1;
+            if (u < CNT) {
+                const int ah = u % S2, rest = u / S2;
+                const int lb = rest % S, lc = rest / S;
+                const int la = 2 * ah + ((g0x + g0y + lb + g0z + lc) & 1);
+                xv[r] = xpp[pkw(g0x + la, g0y + lb, g0z + lc, n)];
+                oo[r] = lix<KUE>(la, lb, lc);
             }
+        }
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (oo[r] >= 0) {
-                    T v = T(0);
-                    for (int cz = 0; cz < 2; ++cz)
-                        for (int cy = 0; cy < 2; ++cy)
-                            for (int cx = 0; cx < 2; ++cx)
-                                v += wt[cx] * wt[cy] * wt[cz] * cv[r][cx + 2 * (cy + 2 * cz)];
-                    xs[oo[r]] = xv[r] + v;
+        for (int r = 0; r < R; ++r) {
+            if (oo[r] >= 0) {
+                const int u = threadIdx.x + r * KTHREADS;
+                const int ah = u % S2, rest = u / S2;
+                const int lb = rest % S, lc = rest / S;
+                const int la = 2 * ah + ((g0x + g0y + lb + g0z + lc) & 1);
+                // per axis: nearest coarse cell (unwrapped fine index >> 1) and the next
+                const int l3[3] = {g0x + la, g0y + lb, g0z + lc};
+                const int c3[3] = {c0x, c0y, c0z};
+                int base[3][2];
+                for (int d = 0; d < 3; ++d) {
+                    const int I = (l3[d] >> 1) - c3[d];
+                    base[d][0] = I;
+                    base[d][1] = (l3[d] & 1) ? I + 1 : I - 1;
                 }
+                T v = T(0);
+                for (int cz = 0; cz < 2; ++cz)
+                    for (int cy = 0; cy < 2; ++cy)
+                        for (int cx = 0; cx < 2; ++cx)
+                            v += wt[cx] * wt[cy] * wt[cz] * cs_[lix<KCE>(base[0][cx], base[1][cy], base[2][cz])];
+                xs[oo[r]] = xv[r] + v;
             }
         }
     }
