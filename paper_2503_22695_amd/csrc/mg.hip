@@ -221,15 +221,17 @@ k_gs(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, T c, T inv_d
 // reach in LDS, interpolates them along y and z into one row per fine (j, k)
 // it needs (Rw), and each neighbour's correction is the x-interpolation of two
 // row values.  Grid and columns as k_gs.
-template <typename T>
-__global__ void __launch_bounds__(TX * TY)
+constexpr int kProlongRows = 16;  // y rows of columns per k_gs_prolong workgroup (4: 14.7 us, 8: 13.5, 16: 13.0 at 128^3)
+
+template <typename T, int PY>
+__global__ void __launch_bounds__(TX * PY)
 k_gs_prolong(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, const T* __restrict__ xc, int nc,
              int64_t ccs, T c, T inv_diag, int q, const int32_t* __restrict__ active) {
     constexpr int KPT = gs_kpt<T>();
     constexpr int RI = TX + 4;                        // coarse I: ih0 - 2 .. ih0 + TX + 1
-    constexpr int CJ = TY / 2 + 2, CK = KPT / 2 + 2;  // coarse J: j0/2 - 1 .. j0/2 + TY/2, K likewise
-    constexpr int NRJ = TY + 2, NRK = KPT + 2;        // fine rows j0 - 1 .. j0 + TY, planes k0 - 1 .. k0 + KPT
-    constexpr int NE = CK * CJ * RI, EPT = (NE + TX * TY - 1) / (TX * TY);
+    constexpr int CJ = PY / 2 + 2, CK = KPT / 2 + 2;  // coarse J: j0/2 - 1 .. j0/2 + PY/2, K likewise
+    constexpr int NRJ = PY + 2, NRK = KPT + 2;        // fine rows j0 - 1 .. j0 + PY, planes k0 - 1 .. k0 + KPT
+    constexpr int NE = CK * CJ * RI, EPT = (NE + TX * PY - 1) / (TX * PY);
     __shared__ T E[CK][CJ][RI];
     __shared__ T Rw[NRK][NRJ][RI];
     const uint3 bid = xcd_block();
@@ -237,7 +239,7 @@ k_gs_prolong(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, cons
     const int comp = bid.z / nkb, k0 = (bid.z - comp * nkb) * KPT;
     if (!active[comp]) return;  // block-uniform
     const int H = n >> 1;
-    const int ih0 = bid.x * TX, j0 = bid.y * TY;
+    const int ih0 = bid.x * TX, j0 = bid.y * PY;
     const int tid = threadIdx.x + TX * threadIdx.y;
     const int ih = ih0 + threadIdx.x, j = j0 + threadIdx.y;
     const bool own = ih < H && j < n;
@@ -274,7 +276,7 @@ k_gs_prolong(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, cons
         T ev[EPT];
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const int t = tid + e * TX * TY;
+            const int t = tid + e * TX * PY;
             if (t < NE) {
                 const int ci = t % RI, cj = (t / RI) % CJ, ck = t / (RI * CJ);
                 // (I reaches ih0 + TX + 1, beyond 2 nc on small grids, where the
@@ -288,13 +290,13 @@ k_gs_prolong(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, cons
         }
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const int t = tid + e * TX * TY;
+            const int t = tid + e * TX * PY;
             if (t < NE) (&E[0][0][0])[t] = ev[e];
         }
     }
     __syncthreads();
     const T w0 = T(0.75), w1 = T(0.25);
-    for (int t = tid; t < NRK * NRJ * RI; t += TX * TY) {
+    for (int t = tid; t < NRK * NRJ * RI; t += TX * PY) {
         const int ri = t % RI, rj = (t / RI) % NRJ, rk = t / (RI * NRJ);
         // unwrapped fine row (j', k') and its two coarse rows per axis (arithmetic shifts floor)
         const int ju = j0 - 1 + rj, ku = k0 - 1 + rk;
@@ -2076,8 +2078,10 @@ hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
     HIPIB_TRY(vcycle<T>(ctx, l + 1, LevelPtr<T>{xc, bc, C.n3}, ncomp, oc, true));
     if (post >= 2) {
         // the correction enters through the first (black) post-smoothing half-sweep
+        constexpr int KP = gs_kpt<T>();
+        const dim3 pg((n / 2 + TX - 1) / TX, (n + kProlongRows - 1) / kProlongRows, ((n + KP - 1) / KP) * ncomp);
         HIPIB_TRY(launch_k(ctx, l == 0 ? HIPIB_TIMER_PROLONG : 0, 13.0 / 8.0 * sizeof(T) * (double)ctx->lv[l].n3 * ncomp,
-                           k_gs_prolong<T>, gs_grid<T>(n, ncomp), dim3(TX, TY), 0, p.x, p.b, n, p.cs, xc, C.n,
+                           k_gs_prolong<T, kProlongRows>, pg, dim3(TX, kProlongRows), 0, p.x, p.b, n, p.cs, xc, C.n,
                            C.n3, c, T(1) / ((T)oc.sigma + T(6) * c), 1, act));
         return smooth<T>(ctx, l, p, ncomp, oc, post, 1, false, 1);
     }
