@@ -788,14 +788,15 @@ k_cg_dir(const TZ* __restrict__ z, double* __restrict__ p, double* __restrict__ 
 // it in the state for the next beta); then x += alpha p, r -= alpha q, partials
 // of ||r||^2 (part[block]) and of sum x (part[gridDim.x + block], for the mean
 // of the converged solution); r32 (mixed) = r / ||b||
-__global__ void __launch_bounds__(256)
+constexpr int kUpdThreads = 512, kUpdMaxBlocks = 512;   // (256 x 1024: 22.1 us at 128^3; 512 x 512: 19.7)
+__global__ void __launch_bounds__(kUpdThreads)
 k_cg_update(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
             const double* __restrict__ q, int64_t n3, MGState* __restrict__ st,
             float* __restrict__ r32, const double* __restrict__ pq_part, int64_t npq, double* __restrict__ part) {
     __shared__ double red[16];
     if (!st->active[0]) return;  // uniform
     double a = 0.0;
-    for (int64_t t = threadIdx.x; t < npq; t += 256) a += pq_part[t];
+    for (int64_t t = threadIdx.x; t < npq; t += kUpdThreads) a += pq_part[t];
     a = block_sum(a, red);
     __shared__ double alpha_s;
     if (threadIdx.x == 0) {
@@ -804,9 +805,9 @@ k_cg_update(double* __restrict__ x, double* __restrict__ r, const double* __rest
     }
     __syncthreads();
     const double alpha = alpha_s, inv_bn = r32 ? 1.0 / st->bn[0] : 0.0;
-    const int64_t stride = (int64_t)gridDim.x * 256;
+    const int64_t stride = (int64_t)gridDim.x * kUpdThreads;
     double v = 0.0, sx = 0.0;
-    for (int64_t t0 = (int64_t)blockIdx.x * 256 + threadIdx.x; t0 < n3; t0 += 4 * stride) {
+    for (int64_t t0 = (int64_t)blockIdx.x * kUpdThreads + threadIdx.x; t0 < n3; t0 += 4 * stride) {
         double xv[4], rv[4], pv[4], qv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -1762,6 +1763,12 @@ int sum_blocks(int64_t count) {
     return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
 }
 
+// workgroups of the conjugate-gradient update pass
+int update_blocks(int64_t count) {
+    int64_t b = (count + kUpdThreads - 1) / kUpdThreads;
+    return (int)(b < kUpdMaxBlocks ? (b < 1 ? 1 : b) : kUpdMaxBlocks);
+}
+
 struct OpCoef {
     double sigma, nu;
     int poisson;
@@ -2151,9 +2158,10 @@ hipib_status cg_iteration(hipib_ctx* ctx, const OpCoef& oc) {
         HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_DIR, (32.0 + zb) * n3, k_cg_dir<double>, norm_grid(n, 1), dim3(TX, TY),
                            0, z, p, q, n, oc.sigma, c, ctx->st, ctx->part));
     // (alpha is reduced by k_cg_update itself: its ||r||^2 partials go after p.q's)
-    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_UPDATE, (mixed ? 52.0 : 48.0) * n3, k_cg_update, dim3(nb), dim3(256), 0,
+    const int nbu = update_blocks(n3);
+    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_CG_UPDATE, (mixed ? 52.0 : 48.0) * n3, k_cg_update, dim3(nbu), dim3(kUpdThreads), 0,
                        ctx->sx, r, p, q, n3, ctx->st, mixed ? ctx->r32 : nullptr, ctx->part, np, ctx->part + np));
-    return finalize_at(ctx, np, nb, nb, 1, FIN_CYCLE_R, 0.0);
+    return finalize_at(ctx, np, nbu, nbu, 1, FIN_CYCLE_R, 0.0);
 }
 
 bool use_cg(const hipib_ctx* ctx, const OpCoef& oc, int ncomp) {
@@ -2343,7 +2351,8 @@ hipib_status solve_packed(hipib_ctx* ctx, int op, int ncomp, double* xpk, bool b
     if (*mean_ok && use_cg(ctx, oc, ncomp) && ctx->st_host->cycles[0] > 0) {
         // the last conjugate-gradient update left the partial sums of x after
         // its ||r||^2 partials (later enqueued cycles were no-ops)
-        HIPIB_TRY(finalize_at(ctx, norm_parts(ctx->n) + nb, nb, nb, 1, FIN_MEAN_ALL, 1.0 / (double)ctx->n3));
+        const int nbu = update_blocks(ctx->n3);
+        HIPIB_TRY(finalize_at(ctx, norm_parts(ctx->n) + nbu, nbu, nbu, 1, FIN_MEAN_ALL, 1.0 / (double)ctx->n3));
     } else if (*mean_ok) {
         k_sum_partials<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(xpk, ctx->n3, ctx->n3, 0, nullptr, ctx->part,
                                                                  nb);
