@@ -144,11 +144,12 @@ def cpu_baseline_and_parity(prob, sample_steps: int, one_thread_steps: int, runs
     return base, par
 
 
-def workload_leg(torch, hipib, inputs, name, steps):
-    """FP64 steps/s of another workload over its first `steps` steps from t = 0
-    (3 warm-up steps on a copy of the state first)."""
+def workload_leg(torch, hipib, inputs, name, steps, **over):
+    """FP64 steps/s of another workload (or configuration: `over`) over its
+    first `steps` steps from t = 0 (3 warm-up steps on a copy of the state
+    first)."""
     prob = inputs.workload(name)
-    sim = hipib.Simulation(prob)
+    sim = hipib.Simulation(prob, **over)
     u, p, X = sim.u.clone(), sim.p.clone(), sim.X.clone()
     sim.ctx.advance(u, p, X, 0.0, 3, prob.p0, prob.T)     # warm-up on a copy
     del u, p, X
@@ -363,6 +364,7 @@ def main():
     ap.add_argument("--no-192", action="store_true", help="skip the 192^3 shell+leaflets leg")
     ap.add_argument("--steps-192", type=int, default=20)
     ap.add_argument("--no-lv", action="store_true", help="skip the 128^3 left-ventricle-law leg")
+    ap.add_argument("--no-det", action="store_true", help="skip the deterministic-mode leg")
     ap.add_argument("--no-tet", action="store_true", help="skip the 64^3 P2-tetrahedra leg")
     ap.add_argument("--no-walls", action="store_true",
                     help="skip the walled 64^3 shell leg and the walled adjoint ratio")
@@ -507,6 +509,13 @@ def main():
         tet["elements"] = "P2 tetrahedra, 4-point rule"
         progress("P2-tetrahedra leg done")
 
+    det = None
+    if not args.no_det:
+        det, _, _ = workload_leg(torch, hipib, inputs, "ho_shell_128", 20, deterministic=1)
+        det["mode"] = ("deterministic: spreading by sorted (grid value, node) pairs summed in a fixed "
+                       "order, bitwise reproducible; first 20 steps of the headline workload")
+        progress("deterministic-mode leg done")
+
     walled = None
     if not args.no_walls:
         walled, _, _ = workload_leg(torch, hipib, inputs, "walled_shell_64", 20)
@@ -528,8 +537,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "ho_shell_128", "grid": prob.n, "nodes": prob.n_nodes,
                    "hexes": prob.n_elems, "pressure_quads": prob.n_faces, "dt": prob.dt,
-                   "mg": "Poisson: CG with one V(2,2) cycle; Helmholtz: red-black SOR (Young) at the stop level; "
-                         "rtol 1e-10",
+                   "mg": "Poisson: CG with one V(2,2) cycle, coarsest level 32^3 solved exactly; Helmholtz: "
+                         "red-black SOR (Young) at the stop level; rtol 1e-10",
                    "mg_cycles_per_step": {"helmholtz_max_component": float(np.mean(cyc[:, :3].max(1))),
                                           "poisson": float(np.mean(cyc[:, 3]))}},
         "roofline": roofline,
@@ -542,6 +551,7 @@ def main():
         "lv_shell_128": lv,
         "tet10_block_64": tet,
         "walled_shell_64": walled,
+        "deterministic_128": det,
     }
     if not args.no_cpu_baseline:
         if args.steps != prob.n_steps:
