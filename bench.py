@@ -224,7 +224,8 @@ def kernel_classes(hipib):
         (H.TIMER_SMOOTH_FINE_HELMHOLTZ, "k_gs<double,1,true>",
          "finest-level over-relaxed red or black half-sweep of the Helmholtz solves, 16 B/cell per component"),
         (H.TIMER_RESID_RESTRICT, "k_resid_restrict<double>", "finest-level red residual and restriction, 13 B/cell"),
-        (H.TIMER_PROLONG, "k_prolong_add<double>", "finest-level prolongation to the red cells, 9 B/cell"),
+        (H.TIMER_PROLONG, "k_gs_prolong<double,16>",
+         "first post-smoothing half-sweep with the trilinear coarse-grid correction folded in, 13 B/cell"),
         (H.TIMER_LEVEL_DOWN, "k_level_down<double>", "first coarse level, down half, 17 B per cell of that level"),
         (H.TIMER_LEVEL_UP, "k_level_up<double>", "first coarse level, up half, 21 B per cell of that level"),
         (H.TIMER_SMALL_VCYCLE, "k_exact_fwd_xy / k_exact_z / k_exact_inv_xy <32,double>",
@@ -313,12 +314,19 @@ def roofline_table(hipib, tim, classes, steps, nodes_bytes, fe_flops):
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2503_22695_amd", "csrc", "mg.hip")
 
 
-def measured_traffic(kernel: str, workload: str = "128"):
-    """HBM bytes per launch of kernel `kernel` from the committed counter summary
-    profiles/<kernel>_poisson_fine_<workload>_hbm_traffic.md, or None when the
-    kernel source has changed since it was taken."""
+# kernel classes with a committed counter summary: profiles/<prefix>_<workload>_hbm_traffic.md
+TRAFFIC_PROFILES = {"k_gs<double,2>": "k_gs_poisson_fine", "k_gs<double,1,true>": "k_gs_helmholtz_sor_fine"}
+
+
+def measured_traffic(kernel_class: str, workload: str = "128"):
+    """HBM bytes per launch of the kernel class `kernel_class` from its
+    committed counter summary, or None when there is none for this workload or
+    the kernel source has changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_poisson_fine_{workload}_hbm_traffic.md")
+    prefix = TRAFFIC_PROFILES.get(kernel_class)
+    if prefix is None:
+        return None
+    path = os.path.join(ROOT, "profiles", f"{prefix}_{workload}_hbm_traffic.md")
     try:
         lines = open(path).read().splitlines()
     except OSError:
@@ -422,10 +430,13 @@ def main():
     progress("per-kernel roofline passes done")
     gpu_state = {"fp64": tuple(t.cpu().numpy() for t in (sim.u, sim.p, sim.X))}
     phase_sim = sim
+    for name in table:
+        if name in TRAFFIC_PROFILES:
+            table[name]["traffic"] = measured_traffic(name)
     dom_name = next(iter(table))
     dom = table[dom_name]
     roofline = {k: dom[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
-    roofline["traffic"] = measured_traffic(dom_name.split("<")[0]) if dom["bound"] == "hbm" else None
+    roofline["traffic"] = measured_traffic(dom_name) if dom["bound"] == "hbm" else None
     roofline.update({
         "kernel": f"{dom_name}: {dom['what']}",
         "bytes_per_launch": dom.get("bytes_per_launch"), "launches_per_step": dom["launches_per_step"],
@@ -492,7 +503,7 @@ def main():
                    "kernels": roofline_table(hipib, tim192, sub, 5, nb192, FE_FLOP_PER_HEX * lprob.n_elems),
                    "stencil_footprint_values": fp192}
         if "k_gs<double,2>" in roof192["kernels"]:
-            roof192["kernels"]["k_gs<double,2>"]["traffic"] = measured_traffic("k_gs", "192")
+            roof192["kernels"]["k_gs<double,2>"]["traffic"] = measured_traffic("k_gs<double,2>", "192")
         del lsim
         progress("192^3 leg done")
 

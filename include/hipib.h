@@ -378,7 +378,10 @@ typedef enum {
     HIPIB_TIMER_SMOOTH_FINE_HELMHOLTZ = 2,
     /* finest-level red residual and its restriction: 13 B (x, red b, coarse b) */
     HIPIB_TIMER_RESID_RESTRICT = 3,
-    /* finest-level prolongation added to the red cells: 9 B */
+    /* finest-level coarse-grid correction: with at least two post-smoothing
+     * sweeps folded into the first (black) post-smoothing half-sweep, 13 B
+     * (that half-sweep's 12 B and the coarse correction); otherwise the
+     * prolongation added to the red cells, 9 B */
     HIPIB_TIMER_PROLONG = 4,
     /* fused first coarse level, down half (four half-sweeps from zero,
      * residual, restriction): 17 B per cell of that level */
