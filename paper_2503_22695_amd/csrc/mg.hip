@@ -604,11 +604,12 @@ k_resid_norm(const double* __restrict__ x, double* __restrict__ b, int n, int64_
              double* __restrict__ part, int64_t pstride, double* __restrict__ rstore, int submean) {
     __shared__ double red[16];
     const int nkb = (n + KPT - 1) / KPT;
-    const int z = blockIdx.z, comp = z / (2 * nkb), rem = z - comp * 2 * nkb, q = rem / nkb;
+    const uint3 bid = xcd_block();
+    const int z = bid.z, comp = z / (2 * nkb), rem = z - comp * 2 * nkb, q = rem / nkb;
     const int k0 = (rem - q * nkb) * KPT;
     if (!st->active[comp]) return;  // block-uniform
     const int H = n >> 1;
-    const int ih = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y;
+    const int ih = bid.x * TX + threadIdx.x, j = bid.y * TY + threadIdx.y;
     double v = 0.0;
     if (ih < H && j < n) {
         const int64_t half3 = (int64_t)H * n * n;
@@ -664,7 +665,7 @@ k_resid_norm(const double* __restrict__ x, double* __restrict__ b, int n, int64_
     if (tid == 0) {
         double s = 0.0;
         for (int w = 0; w < (TX * TY) / 64; ++w) s += red[w];
-        const int64_t blk = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * rem);
+        const int64_t blk = bid.x + (int64_t)gridDim.x * (bid.y + (int64_t)gridDim.y * rem);
         part[comp * pstride + blk] = s;
     }
 }
@@ -722,11 +723,12 @@ k_cg_dir(const TZ* __restrict__ z, double* __restrict__ p, double* __restrict__ 
          double sigma, double c, const MGState* __restrict__ st, double* __restrict__ part) {
     __shared__ double red[16];
     const int nkb = (n + KPT - 1) / KPT;
-    const int rem = blockIdx.z, qc = rem / nkb, k0 = (rem - qc * nkb) * KPT;
+    const uint3 bid = xcd_block();
+    const int rem = bid.z, qc = rem / nkb, k0 = (rem - qc * nkb) * KPT;
     if (!st->active[0]) return;  // uniform
     const double beta = st->beta, zs = sizeof(TZ) == 4 ? st->bn[0] : 1.0;
     const int H = n >> 1;
-    const int ih = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y;
+    const int ih = bid.x * TX + threadIdx.x, j = bid.y * TY + threadIdx.y;
     double v = 0.0;
     if (ih < H && j < n) {
         const int64_t half3 = (int64_t)H * n * n;
@@ -779,7 +781,7 @@ k_cg_dir(const TZ* __restrict__ z, double* __restrict__ p, double* __restrict__ 
     if (tid == 0) {
         double s = 0.0;
         for (int w = 0; w < (TX * TY) / 64; ++w) s += red[w];
-        part[blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * rem)] = s;
+        part[bid.x + (int64_t)gridDim.x * (bid.y + (int64_t)gridDim.y * rem)] = s;
     }
 }
 
@@ -1600,48 +1602,77 @@ k_level_down(const T* __restrict__ b, T* __restrict__ xpre, int n, int64_t cs, T
     if (!active[comp]) return;
     const int g0x = i0 - KDH, g0y = j0 - KDH, g0z = k0 - KDH;
     const T* bcp = b + comp * cs;
-    box_gs<KDE, KDH, 5>(xs, bcp, n, g0x, g0y, g0z, 0, c, inv_diag, true);
-    __syncthreads();
-    box_gs<KDE, KDH, 4>(xs, bcp, n, g0x, g0y, g0z, 1, c, inv_diag, false);
-    __syncthreads();
-    box_gs<KDE, KDH, 3>(xs, bcp, n, g0x, g0y, g0z, 0, c, inv_diag, false);
-    __syncthreads();
-    box_gs<KDE, KDH, 2>(xs, bcp, n, g0x, g0y, g0z, 1, c, inv_diag, false);
-    __syncthreads();
-    // red residuals on the window, black entries zero
-    {
-        constexpr int CW = KW * KW * KW, R = (CW + KTHREADS - 1) / KTHREADS;
-        T bv[R];
-        int oo[R];
+    constexpr int CW = KW * KW * KW;
+    for (int u = threadIdx.x; u < CW; u += KTHREADS) rw[u] = T(0);   // black entries stay zero
+    // Each thread owns up to RR red cells of the box reaching 5 cells beyond the
+    // block and up to RK black cells of the one reaching 4 (the cells of the
+    // first half-sweep of each colour, numbered as in box_gs); their b is
+    // loaded once, and each later half-sweep updates the owned cells inside its
+    // smaller box (distance from the block: the largest per-axis overhang).
+    constexpr int S5 = KB + 10, CR = (S5 / 2) * S5 * S5, RR = (CR + KTHREADS - 1) / KTHREADS;
+    constexpr int S4 = KB + 8, CK = (S4 / 2) * S4 * S4, RK = (CK + KTHREADS - 1) / KTHREADS;
+    auto dist = [](int la, int lb, int lc) {
+        const int dx = max(max(KDH - la, la - (KDH + KB - 1)), 0);
+        const int dy = max(max(KDH - lb, lb - (KDH + KB - 1)), 0);
+        const int dz = max(max(KDH - lc, lc - (KDH + KB - 1)), 0);
+        return max(dx, max(dy, dz));
+    };
+    T br[RR], bk[RK];
+    int orr[RR], ork[RK], dr[RR], dk[RK], wr[RR];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int u = threadIdx.x + r * KTHREADS;
-            oo[r] = -1;
-            bv[r] = T(0);
-            if (u < CW) {
-                const int la = KDH - 1 + u % KW, lb = KDH - 1 + (u / KW) % KW, lc = KDH - 1 + u / (KW * KW);
-                if (((g0x + la + g0y + lb + g0z + lc) & 1) == 0) {
-                    oo[r] = lix<KDE>(la, lb, lc);
-                    bv[r] = bcp[pkw(g0x + la, g0y + lb, g0z + lc, n)];
-                }
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int u = threadIdx.x + r * KTHREADS;
-            if (u < CW) {
-                T res = T(0);
-                const int o = oo[r];
-                if (o >= 0) {
-                    const T xo = xs[o];
-                    const T sum = xs[o + 1] + xs[o - 1] + xs[o + KDE] + xs[o - KDE] + xs[o + KDE * KDE] +
-                                  xs[o - KDE * KDE];
-                    res = bv[r] - (sigma * xo - c * (sum - T(6) * xo));
-                }
-                rw[u] = res;
-            }
+    for (int r = 0; r < RR; ++r) {
+        const int u = threadIdx.x + r * KTHREADS;
+        orr[r] = -1;
+        if (u < CR) {
+            const int lo = KDH - 5, ah = u % (S5 / 2), rest = u / (S5 / 2);
+            const int lb = lo + rest % S5, lc = lo + rest / S5;
+            const int la = lo + 2 * ah + ((g0x + lo + g0y + lb + g0z + lc) & 1);
+            orr[r] = lix<KDE>(la, lb, lc);
+            dr[r] = dist(la, lb, lc);
+            wr[r] = dr[r] <= 1 ? lix<KW>(la - (KDH - 1), lb - (KDH - 1), lc - (KDH - 1)) : -1;
+            br[r] = bcp[pkw(g0x + la, g0y + lb, g0z + lc, n)];
         }
     }
+#pragma unroll
+    for (int r = 0; r < RK; ++r) {
+        const int u = threadIdx.x + r * KTHREADS;
+        ork[r] = -1;
+        if (u < CK) {
+            const int lo = KDH - 4, ah = u % (S4 / 2), rest = u / (S4 / 2);
+            const int lb = lo + rest % S4, lc = lo + rest / S4;
+            const int la = lo + 2 * ah + ((1 + g0x + lo + g0y + lb + g0z + lc) & 1);
+            ork[r] = lix<KDE>(la, lb, lc);
+            dk[r] = dist(la, lb, lc);
+            bk[r] = bcp[pkw(g0x + la, g0y + lb, g0z + lc, n)];
+        }
+    }
+    auto nsum = [&](int o) {
+        return xs[o + 1] + xs[o - 1] + xs[o + KDE] + xs[o - KDE] + xs[o + KDE * KDE] + xs[o - KDE * KDE];
+    };
+    // red from x = 0, black, red, black on boxes reaching 5, 4, 3, 2 cells
+#pragma unroll
+    for (int r = 0; r < RR; ++r)
+        if (orr[r] >= 0) xs[orr[r]] = (br[r] + c * T(0)) * inv_diag;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RK; ++r)
+        if (ork[r] >= 0) xs[ork[r]] = (bk[r] + c * nsum(ork[r])) * inv_diag;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RR; ++r)
+        if (orr[r] >= 0 && dr[r] <= 3) xs[orr[r]] = (br[r] + c * nsum(orr[r])) * inv_diag;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RK; ++r)
+        if (ork[r] >= 0 && dk[r] <= 2) xs[ork[r]] = (bk[r] + c * nsum(ork[r])) * inv_diag;
+    __syncthreads();
+    // red residuals on the restriction window (1 cell beyond the block)
+#pragma unroll
+    for (int r = 0; r < RR; ++r)
+        if (orr[r] >= 0 && wr[r] >= 0) {
+            const T xo = xs[orr[r]];
+            rw[wr[r]] = br[r] - (sigma * xo - c * (nsum(orr[r]) - T(6) * xo));
+        }
     // the block's smoothed x
     T* xp = xpre + comp * cs;
     for (int u = threadIdx.x; u < KB * KB * KB; u += KTHREADS) {
@@ -2407,9 +2438,10 @@ k_divergence_packed(const double* __restrict__ u, double* __restrict__ b, int n,
                     double inv_h, double* __restrict__ part, int64_t pstride) {
     __shared__ double red[2][(TX * TY) / 64];
     const int nkb = (n + KPT - 1) / KPT;
-    const int rem = blockIdx.z, q = rem / nkb, k0 = (rem - q * nkb) * KPT;
+    const uint3 bid = xcd_block();
+    const int rem = bid.z, q = rem / nkb, k0 = (rem - q * nkb) * KPT;
     const int H = n >> 1;
-    const int ih = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y;
+    const int ih = bid.x * TX + threadIdx.x, j = bid.y * TY + threadIdx.y;
     double s1 = 0.0, s2 = 0.0;
     if (ih < H && j < n) {
         const int64_t half3 = (int64_t)H * n * n;
@@ -2462,7 +2494,7 @@ k_divergence_packed(const double* __restrict__ u, double* __restrict__ b, int n,
             a += red[0][w];
             c += red[1][w];
         }
-        const int64_t blk = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * rem);
+        const int64_t blk = bid.x + (int64_t)gridDim.x * (bid.y + (int64_t)gridDim.y * rem);
         part[blk] = a;
         part[pstride + blk] = c;
     }
