@@ -211,6 +211,71 @@ k_gs(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, T c, T inv_d
     }
 }
 
+// The first two half-sweeps of a pre-smoothing from a zero guess, in one pass:
+// red x = b / diag (its neighbours are zero) and black x = (b + c * sum of those
+// red values) / diag.  Each thread takes a column of black cells as k_gs does,
+// forms its red neighbours from b, and also writes the red cells at the
+// packed positions of its column, so every red cell is written once.  The
+// values are those of the two separate half-sweeps (red ones as
+// (b + c * 0) / diag).
+template <typename T>
+__global__ void __launch_bounds__(TX * TY)
+k_gs_zero2(T* __restrict__ x, const T* __restrict__ b, int n, int64_t cs, T c, T inv_diag,
+           const int32_t* __restrict__ active) {
+    constexpr int KPT = gs_kpt<T>();
+    const uint3 bid = xcd_block();
+    const int nkb = (n + KPT - 1) / KPT;
+    const int comp = bid.z / nkb, k0 = (bid.z - comp * nkb) * KPT;
+    if (!active[comp]) return;
+    const int H = n >> 1;
+    const int ih = bid.x * TX + threadIdx.x, j = bid.y * TY + threadIdx.y;
+    if (ih >= H || j >= n) return;
+    const int64_t half3 = (int64_t)H * n * n;
+    T* xr = x + comp * cs;            // red half
+    T* xq = xr + half3;               // black half
+    const T* br = b + comp * cs;
+    const T* bq = br + half3;
+    const int jp = wrapi(j + 1, n), jm = wrapi(j - 1, n);
+    const int ihp = ih + 1 < H ? ih + 1 : 0, ihm = ih > 0 ? ih - 1 : H - 1;
+    T col[KPT + 2], side[KPT], yp[KPT], ym[KPT], bv[KPT];
+#pragma unroll
+    for (int r = 0; r < KPT + 2; ++r) {
+        const int kk = wrapi(k0 - 1 + r, n);
+        col[r] = br[ih + (int64_t)H * ((int64_t)j + (int64_t)n * kk)];
+    }
+#pragma unroll
+    for (int r = 0; r < KPT; ++r) {
+        const int k = k0 + r;
+        if (k < n) {
+            const int64_t row = (int64_t)H * ((int64_t)j + (int64_t)n * k);
+            const int p = (j + k + 1) & 1;
+            bv[r] = bq[row + ih];
+            side[r] = br[row + (p ? ihp : ihm)];
+            yp[r] = br[(int64_t)H * ((int64_t)jp + (int64_t)n * k) + ih];
+            ym[r] = br[(int64_t)H * ((int64_t)jm + (int64_t)n * k) + ih];
+        }
+    }
+    // red values from a zero guess
+#pragma unroll
+    for (int r = 0; r < KPT + 2; ++r) col[r] = (col[r] + c * T(0)) * inv_diag;
+#pragma unroll
+    for (int r = 0; r < KPT; ++r) {
+        const int k = k0 + r;
+        if (k < n) {
+            side[r] = (side[r] + c * T(0)) * inv_diag;
+            yp[r] = (yp[r] + c * T(0)) * inv_diag;
+            ym[r] = (ym[r] + c * T(0)) * inv_diag;
+            const int p = (j + k + 1) & 1;
+            const T a_ip = p ? side[r] : col[r + 1];
+            const T a_im = p ? col[r + 1] : side[r];
+            const T sn = a_ip + a_im + yp[r] + ym[r] + col[r + 2] + col[r];
+            const int64_t row = (int64_t)H * ((int64_t)j + (int64_t)n * k);
+            xq[row + ih] = (bv[r] + c * sn) * inv_diag;
+            xr[row + ih] = col[r + 1];
+        }
+    }
+}
+
 // The first post-smoothing half-sweep (colour q, nonzero guess, no
 // over-relaxation) fused with the coarse-grid correction: the other colour's
 // values in its stencil are taken as x + P e, P the cell-centred trilinear
@@ -2044,6 +2109,11 @@ hipib_status smooth(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
     const bool dots = l == 0 && ctx->cg_dots.q != nullptr && !zero_guess && ncomp == 1;
     const dim3 grid = gs_grid<T>(n, 1);
     const int64_t nb = (int64_t)grid.x * grid.y * grid.z;
+    if (start == 0 && zero_guess && first == 0) {
+        HIPIB_TRY(launch_k(ctx, 0, 0.0, k_gs_zero2<T>, gs_grid<T>(n, ncomp), dim3(TX, TY), 0, p.x, p.b, n, p.cs, c,
+                           inv_diag, ctx->st->active));
+        start = 2;
+    }
     for (int s = start; s < 2 * sweeps; ++s) {
         const int zg = (s == 0 && zero_guess) ? 1 : 0;
         const int colour = (s & 1) ? 1 - first : first;
