@@ -56,7 +56,8 @@ constexpr int kSmallThreads = 1024;
 
 enum FinalizeMode {
     FIN_BNORM = 0, FIN_INIT_R = 1, FIN_CYCLE_R = 2, FIN_MEAN = 3, FIN_MEAN_ALL = 4,
-    FIN_MEAN_BNORM = 5   // component 0: mean of b from slot 0 (sum b), ||b - mean|| with slot 1 (sum b^2)
+    FIN_MEAN_BNORM = 5,  // component 0: mean of b from slot 0 (sum b), ||b - mean|| with slot 1 (sum b^2)
+    FIN_BNORM_INIT_R = 6 // per component: ||b|| from the b^2 partials after ncomp * pstride, then as FIN_INIT_R
 };
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
@@ -659,15 +660,16 @@ __global__ void k_zero_t(T* __restrict__ p, int64_t count) {
 // FP64 outer loop: residual norm (and FP32 scaled residual), update, means
 // ---------------------------------------------------------------------------
 
-// sum of r^2 per block; TO32: also r32 = (float)(r / ||b||).  Grid: (packed
+// sum of r^2 per block (and with bsq = ncomp of b^2, after ncomp * pstride
+// partials); TO32: also r32 = (float)(r / ||b||).  Grid: (packed
 // x tiles, y tiles, (comp * 2 + q) * z-columns); each thread takes a column of
 // KPT cells of colour q along z with the loads of k_gs.
 template <bool TO32>
 __global__ void __launch_bounds__(TX * TY)
 k_resid_norm(const double* __restrict__ x, double* __restrict__ b, int n, int64_t cs,
              double sigma, double c, const MGState* __restrict__ st, float* __restrict__ r32,
-             double* __restrict__ part, int64_t pstride, double* __restrict__ rstore, int submean) {
-    __shared__ double red[16];
+             double* __restrict__ part, int64_t pstride, double* __restrict__ rstore, int submean, int bsq) {
+    __shared__ double red[2][16];
     const int nkb = (n + KPT - 1) / KPT;
     const uint3 bid = xcd_block();
     const int z = bid.z, comp = z / (2 * nkb), rem = z - comp * 2 * nkb, q = rem / nkb;
@@ -675,7 +677,7 @@ k_resid_norm(const double* __restrict__ x, double* __restrict__ b, int n, int64_
     if (!st->active[comp]) return;  // block-uniform
     const int H = n >> 1;
     const int ih = bid.x * TX + threadIdx.x, j = bid.y * TY + threadIdx.y;
-    double v = 0.0;
+    double v = 0.0, vb = 0.0;
     if (ih < H && j < n) {
         const int64_t half3 = (int64_t)H * n * n;
         const double* xq = x + comp * cs + q * half3;
@@ -716,6 +718,7 @@ k_resid_norm(const double* __restrict__ x, double* __restrict__ b, int n, int64_
                 }
                 const double rr = bv[r] - (sigma * xv[r] - c * (s - 6.0 * xv[r]));
                 v += rr * rr;
+                vb += bv[r] * bv[r];
                 if (rstore) rstore[comp * cs + q * half3 + (int64_t)H * ((int64_t)j + (int64_t)n * k) + ih] = rr;
                 if (TO32)
                     r32[comp * cs + q * half3 + (int64_t)H * ((int64_t)j + (int64_t)n * k) + ih] =
@@ -724,14 +727,24 @@ k_resid_norm(const double* __restrict__ x, double* __restrict__ b, int n, int64_
         }
     }
     const int tid = threadIdx.x + TX * threadIdx.y;
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    if ((tid & 63) == 0) red[tid >> 6] = v;
+    for (int o = 32; o > 0; o >>= 1) {
+        v += __shfl_down(v, o, 64);
+        vb += __shfl_down(vb, o, 64);
+    }
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = v;
+        red[1][tid >> 6] = vb;
+    }
     __syncthreads();
     if (tid == 0) {
-        double s = 0.0;
-        for (int w = 0; w < (TX * TY) / 64; ++w) s += red[w];
+        double s = 0.0, sb = 0.0;
+        for (int w = 0; w < (TX * TY) / 64; ++w) {
+            s += red[0][w];
+            sb += red[1][w];
+        }
         const int64_t blk = bid.x + (int64_t)gridDim.x * (bid.y + (int64_t)gridDim.y * rem);
         part[comp * pstride + blk] = s;
+        if (bsq) part[(bsq + comp) * pstride + blk] = sb;   // bsq = ncomp: ||b||^2 after the residuals
     }
 }
 
@@ -1006,6 +1019,13 @@ k_finalize(const double* __restrict__ part, int64_t nparts, int64_t pstride, int
     for (int comp = 0; comp < ncomp; ++comp) {
         const bool skip = (mode == FIN_CYCLE_R || mode == FIN_MEAN) && !st->active[comp];
         if (skip) continue;  // uniform across the block
+        if (mode == FIN_BNORM_INIT_R) {
+            double sb = 0.0;
+            for (int64_t t = threadIdx.x; t < nparts; t += blockDim.x) sb += part[(ncomp + comp) * pstride + t];
+            sb = block_sum(sb, red);
+            if (threadIdx.x == 0) st->bn[comp] = sqrt(sb);
+            __syncthreads();
+        }
         double s = 0.0;
         // loads in batches of 8, summed in index order
         for (int64_t t0 = threadIdx.x; t0 < nparts; t0 += 8 * (int64_t)blockDim.x) {
@@ -1026,7 +1046,7 @@ k_finalize(const double* __restrict__ part, int64_t nparts, int64_t pstride, int
                 st->mean[comp] = s * inv_count;
             } else {
                 const double bn = st->bn[comp];
-                if (mode == FIN_INIT_R) {
+                if (mode == FIN_INIT_R || mode == FIN_BNORM_INIT_R) {
                     st->cycles[comp] = 0;
                     st->zero_req[comp] = 0;
                 } else {
@@ -2206,6 +2226,8 @@ hipib_status vcycle(hipib_ctx* ctx, int l, LevelPtr<T> p, int ncomp, const OpCoe
 // in mixed mode also writes the scaled FP32 residual of every active component
 hipib_status resid_norm(hipib_ctx* ctx, int ncomp, const OpCoef& oc, int mode,
                         double* rstore = nullptr, int submean = 0) {
+    // FIN_BNORM_INIT_R (FP64): ||b|| from the same pass
+    const int bsq = mode == FIN_BNORM_INIT_R ? ncomp : 0;
     const int n = ctx->n;
     const double h = 1.0 / n, c = oc.nu / (h * h);
     const int64_t np = norm_parts(n);
@@ -2213,11 +2235,11 @@ hipib_status resid_norm(hipib_ctx* ctx, int ncomp, const OpCoef& oc, int mode,
     if (ctx->cfg.precision == HIPIB_MIXED)
         HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_RESID_NORM, bytes, k_resid_norm<true>, norm_grid(n, ncomp), dim3(TX, TY),
                            0, ctx->sx, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, ctx->r32, ctx->part, np, rstore,
-                           submean));
+                           submean, 0));
     else
         HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_RESID_NORM, bytes, k_resid_norm<false>, norm_grid(n, ncomp),
                            dim3(TX, TY), 0, ctx->sx, ctx->bpk, n, ctx->n3, oc.sigma, c, ctx->st, nullptr,
-                           ctx->part, np, rstore, submean));
+                           ctx->part, np, rstore, submean, bsq));
     return finalize(ctx, np, np, ncomp, mode, 0.0);
 }
 
@@ -2377,7 +2399,7 @@ hipib_status mg_prepare(hipib_ctx* ctx) {
     return HIPIB_OK;
 }
 
-int64_t mg_partials_needed(int n) { return 4 * (norm_parts(n) + 1024); }
+int64_t mg_partials_needed(int n) { return 6 * (norm_parts(n) + 1024); }
 
 size_t mg_level_elem_size(const hipib_ctx* ctx) {
     return ctx->cfg.precision == HIPIB_MIXED ? sizeof(float) : sizeof(double);
@@ -2419,7 +2441,13 @@ hipib_status solve_packed(hipib_ctx* ctx, int op, int ncomp, double* xpk, bool b
     const OpCoef oc = op_coef(ctx, op);
     const int nb = sum_blocks(ctx->n3);
     ctx->sx = xpk;
-    if (!b_ready) {
+    // in FP64 ||b|| comes from the initial residual pass (mixed mode scales its
+    // FP32 residual by ||b||, so it needs ||b|| first)
+    const bool fused_bnorm = !b_ready && ctx->cfg.precision == HIPIB_FP64;
+    if (fused_bnorm) {
+        k_state_reset<<<1, 64, 0, ctx->stream>>>(ctx->st, ncomp);
+        HIPIB_HIP(hipGetLastError());
+    } else if (!b_ready) {
         k_state_reset<<<1, 64, 0, ctx->stream>>>(ctx->st, ncomp);
         k_sum_partials<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(ctx->bpk, ctx->n3, ctx->n3, 1, nullptr,
                                                                  ctx->part, nb);
@@ -2427,8 +2455,8 @@ hipib_status solve_packed(hipib_ctx* ctx, int op, int ncomp, double* xpk, bool b
         HIPIB_TRY(finalize(ctx, nb, nb, ncomp, FIN_BNORM, 0.0));
     }
     // (conjugate gradients keep the initial residual as their r)
-    HIPIB_TRY(resid_norm(ctx, ncomp, oc, FIN_INIT_R, use_cg(ctx, oc, ncomp) ? ctx->kv[0] : nullptr,
-                         b_ready && oc.poisson ? 1 : 0));
+    HIPIB_TRY(resid_norm(ctx, ncomp, oc, fused_bnorm ? FIN_BNORM_INIT_R : FIN_INIT_R,
+                         use_cg(ctx, oc, ncomp) ? ctx->kv[0] : nullptr, b_ready && oc.poisson ? 1 : 0));
     k_zero_requested<<<dim3(nb, ncomp), 256, 0, ctx->stream>>>(xpk, ctx->n3, ctx->n3, ctx->st);
     HIPIB_HIP(hipGetLastError());
 
