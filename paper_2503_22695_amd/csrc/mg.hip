@@ -5,9 +5,11 @@
 //   red-black Gauss-Seidel in place (red = (i+j+k) even; pre: red, black;
 //   post: black, red), residual, restriction by per-axis weights (1,3,3,1)/8,
 //   coarse operators rediscretised at 2h, cell-centred trilinear prolongation
-//   added to x, coarsest level (first with < 8 cells per side) solved by a fixed
-//   number of red+black sweeps, Poisson means removed after the coarse solve
-//   and once from the final solution (residual and sweeps are invariant to a
+//   added to x, coarsest level (the first with at most 32 cells per side)
+//   solved exactly by its discrete Fourier diagonalisation (with
+//   mg_coarse_sweeps > 0: the first with fewer than 8 cells, relaxed by that
+//   many red+black sweeps), Poisson means removed after the coarse solve and
+//   once from the final solution (residual and sweeps are invariant to a
 //   constant shift).  Stop: ||r||_2 <= max(rtol, 1e3 eps) ||b||_2.
 //   The Helmholtz hierarchy stops where the operator's Jacobi radius is at most
 //   1/2 (see stop_level), and that level is relaxed by red-black SOR with
@@ -24,7 +26,8 @@
 // (j,k+-1).  A half-sweep therefore streams exactly what it needs: the other
 // colour of x, its own colour of b, its own colour of x written (12 B/cell in
 // FP64), with unit-stride rows.  The caller's arrays are packed on entry to a
-// solve and the solution unpacked on exit.
+// solve and the solution unpacked on exit; inside a step the fluid arrays
+// stay packed from the right-hand side to the projection (fluid_step_packed).
 //
 // Precision: in FP64 mode the V-cycles run on the FP64 solution.  In mixed
 // mode the outer loop stays in FP64 (residual, norm, stop test, solution
@@ -34,12 +37,16 @@
 // rounded to FP32 (iterative refinement with a V-cycle preconditioner).
 //
 // GPU mapping: one bandwidth-bound kernel per fine-level stage (64x4 thread
-// tiles); all levels with at most 16 cells per side run inside ONE workgroup
-// of 1024 threads with the arrays in LDS; up to three components (the three
-// velocity lattices) share every launch and stop independently through
-// per-component `active` flags read at block start.  Stop decisions are made
-// on the device; the host enqueues the predicted number of cycles and waits
-// once to read them.
+// tiles), with the stages that can share a pass fused (the zero-guess pair of
+// half-sweeps, the coarse-grid correction in the first post-smoothing
+// half-sweep, the CG dots in the last two); the first coarse levels run as
+// one down and one up workgroup-blocked launch each; the exact coarsest solve
+// is one workgroup per component (at most 16^3) or three plane-parallel
+// launches (24^3, 32^3).  Up to three components (the three velocity
+// lattices) share every launch and stop independently through per-component
+// `active` flags read at block start.  Stop decisions are made on the device;
+// the host enqueues the predicted number of cycles and waits once to read
+// them.
 #include <cfloat>
 #include <cmath>
 #include <vector>
@@ -1138,7 +1145,7 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // ---------------------------------------------------------------------------
-// Exact solve of the coarsest level (at most 16 cells per side) of the periodic
+// Exact solve of a coarsest level of at most 16 cells per side of the periodic
 // operator sigma I - nu Lap_h, in one workgroup per component:
 //   x = Q3 diag(1 / lambda) Q3^T b,  Q3 = Q (x) Q (x) Q,
 // with Q the level's real orthonormal Fourier basis (columns: the constant,
