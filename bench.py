@@ -321,8 +321,7 @@ TRAFFIC_PROFILES = {"k_gs<double,2>": "k_gs_poisson_fine", "k_gs<double,1,true>"
 def measured_traffic(kernel_class: str, workload: str = "128"):
     """HBM bytes per launch of the kernel class `kernel_class` from its
     committed counter summary, or None when there is none for this workload or
-    the kernel source has changed since it was taken."""
-    import hashlib
+    the kernel code has changed since it was taken."""
     prefix = TRAFFIC_PROFILES.get(kernel_class)
     if prefix is None:
         return None
@@ -336,10 +335,23 @@ def measured_traffic(kernel_class: str, workload: str = "128"):
         if ln.startswith("- ") and ": " in ln:
             k, v = ln[2:].split(": ", 1)
             vals[k.strip("`")] = v.strip().strip("`")
-    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if vals.get("kernel_source_sha256") != src or "traffic_bytes_per_launch" not in vals:
+    if vals.get("kernel_code_sha256") != kernel_code_sha256() or "traffic_bytes_per_launch" not in vals:
         return None
     return float(vals["traffic_bytes_per_launch"])
+
+
+def kernel_code_sha256(path: str = None) -> str:
+    """sha256 of the multigrid source without its // comments, trailing blanks
+    and empty lines: the code the counters were taken on (comment edits do not
+    change it)."""
+    import hashlib
+    import re
+    lines = []
+    for ln in open(path or KERNEL_SOURCE, encoding="utf-8").read().splitlines():
+        ln = re.sub(r"//.*$", "", ln).rstrip()
+        if ln:
+            lines.append(ln)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()
 
 
 def copy_calibration(torch, mib: int):
