@@ -30,7 +30,7 @@ def hp():
     return hipib
 
 
-@pytest.mark.parametrize("n", [16, 32, 48])
+@pytest.mark.parametrize("n", [16, 32, 48, 64, 96])
 def test_mixed_poisson_matches_fp64_solution(torch_dev, hp, ref, n):
     torch = torch_dev
     say("mixed poisson", n)

@@ -146,8 +146,8 @@ def test_fe_force_leaflets_mixed_materials(torch_dev, hp, ref):
 # multigrid
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,krylov", [(16, 1), (24, 1), (32, 1), (48, 1), (64, 1), (16, 0),
-                                      (32, 0), (48, 0)])
+@pytest.mark.parametrize("n,krylov", [(16, 1), (24, 1), (32, 1), (48, 1), (64, 1), (96, 1), (16, 0),
+                                      (32, 0), (48, 0), (96, 0)])
 def test_mg_poisson(torch_dev, hp, ref, n, krylov):
     """Poisson solve: V-cycle-preconditioned conjugate gradients (krylov = 1,
     the default) and the plain V-cycle iteration, against the oracle."""
@@ -168,20 +168,23 @@ def test_mg_poisson(torch_dev, hp, ref, n, krylov):
     assert_close("x", host(xd), xr)
 
 
-@pytest.mark.parametrize("n", [24, 32, 64])
-def test_mg_helmholtz_three_components(torch_dev, hp, ref, n):
+@pytest.mark.parametrize("n,dt", [(24, 5e-4), (32, 5e-4), (64, 5e-4), (96, 5e-4), (96, 1e-2)])
+def test_mg_helmholtz_three_components(torch_dev, hp, ref, n, dt):
+    """Three components in the same launches.  dt = 5e-4: the finest level is
+    the relaxation (stop) level; 96^3 at dt = 1e-2: V-cycles over 96^3 and the
+    fused 48^3 level down to the exactly solved 24^3, three components each."""
     torch = torch_dev
-    say("mg helmholtz", n)
+    say("mg helmholtz", n, dt)
     rng = np.random.default_rng(100 + n)
     b = rng.standard_normal((3, n, n, n))
     b[2] *= 1e-3
     x0 = rng.standard_normal((3, n, n, n)) * 1e-4
-    ctx = plain_ctx(hp, n, dt=5e-4)
+    ctx = plain_ctx(hp, n, dt=dt)
     xd = to_dev(torch, x0)
     cyc, rr = ctx.mg_solve(hp.OP_HELMHOLTZ, to_dev(torch, b), xd)
-    fl = ref.fluid(n, dt=5e-4)
+    fl = ref.fluid(n, dt=dt)
     for d in range(3):
-        xr, cr, _ = ref.mg_solve(fl, 1.0 / 5e-4, 0.01, False, b[d], x0[d])
+        xr, cr, _ = ref.mg_solve(fl, 1.0 / dt, 0.01, False, b[d], x0[d])
         assert int(cyc[d]) == cr
         assert_close(f"x[{d}]", host(xd)[d], xr)
 
