@@ -388,9 +388,10 @@ typedef enum {
     HIPIB_TIMER_LEVEL_DOWN = 5,
     /* fused first coarse level, up half (prolongation, four half-sweeps): 21 B */
     HIPIB_TIMER_LEVEL_UP = 6,
-    /* the coarsest level in one workgroup (its exact solve, or with
-     * mg_coarse_sweeps > 0 the levels of at most 16^3 cells): 16 B per cell of
-     * that level (b read, x written) */
+    /* the coarsest level: its exact solve (one workgroup per component at
+     * most 16^3; three plane-parallel passes at 24^3 and 32^3), or with
+     * mg_coarse_sweeps > 0 the levels of at most 16^3 cells in one workgroup:
+     * 16 B per cell of that level and pass (b read, x written) */
     HIPIB_TIMER_SMALL_VCYCLE = 7,
     /* residual norm of the finest level: 16 B per cell and component */
     HIPIB_TIMER_RESID_NORM = 8,
