@@ -535,8 +535,9 @@ def main():
     det = None
     if not args.no_det:
         det, _, _ = workload_leg(torch, hipib, inputs, "ho_shell_128", 20, deterministic=1)
-        det["mode"] = ("deterministic: spreading by sorted (grid value, node) pairs summed in a fixed "
-                       "order, bitwise reproducible; first 20 steps of the headline workload")
+        det["mode"] = ("deterministic: nodes sorted by cell, each work item summed in node order into "
+                       "its own box, boxes added per grid value in a fixed order; bitwise reproducible; "
+                       "first 20 steps of the headline workload")
         progress("deterministic-mode leg done")
 
     walled = None

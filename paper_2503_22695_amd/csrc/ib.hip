@@ -98,10 +98,11 @@ k_bin_count(const double* __restrict__ X, int nn, int n, int T, int ta, double i
 // Exclusive scan of the tile counts and the list of work items: each
 // occupied tile is cut into chunks of at most kSpreadChunk nodes, listed as
 // (tile, first rank) pairs, so a tile crowded with nodes is spread by several
-// workgroups.  Counts are reset to 0 for the next binning.
+// workgroups.  Counts are reset to 0 for the next binning.  When given,
+// lfirst[t] receives the list index of tile t's first work item.
 __global__ void __launch_bounds__(1024)
 k_bin_scan(int32_t* __restrict__ count, int64_t ntiles, int32_t* __restrict__ off,
-           int32_t* __restrict__ list, int32_t* __restrict__ nlist) {
+           int32_t* __restrict__ list, int32_t* __restrict__ nlist, int32_t* __restrict__ lfirst) {
     __shared__ int32_t s_sum[1024], s_nz[1024];
     const int tid = threadIdx.x;
     const int64_t per = (ntiles + 1023) / 1024;
@@ -126,6 +127,7 @@ k_bin_scan(int32_t* __restrict__ count, int64_t ntiles, int32_t* __restrict__ of
     int32_t run = s_sum[tid] - sum, lrun = s_nz[tid] - nz;
     for (int64_t i = beg; i < end; ++i) {
         off[i] = run;
+        if (lfirst) lfirst[i] = lrun;
         const int32_t c = count[i];
         run += c;
         for (int32_t r = 0; r < c; r += kSpreadChunk) {
@@ -310,7 +312,7 @@ hipib_status launch_bin(hipib_ctx* ctx, const double* X) {
                                              1.0 / ctx->h, ctx->node_tile, ctx->node_rank,
                                              ctx->bin_count, &ctx->st->bad_position);
     k_bin_scan<<<1, 1024, 0, ctx->stream>>>(ctx->bin_count, ctx->ntiles, ctx->bin_off,
-                                            ctx->tile_list, ctx->n_list);
+                                            ctx->tile_list, ctx->n_list, ctx->det_lfirst);
     k_bin_scatter<<<nb, 256, 0, ctx->stream>>>(ctx->node_tile, ctx->node_rank, ctx->bin_off,
                                                ctx->perm, ctx->nn);
     HIPIB_HIP(hipGetLastError());
@@ -445,7 +447,7 @@ hipib_status hipib_spread_noalloc(int32_t n, int32_t n_nodes, const double* X, c
     // the tile counts start at zero (a fill kernel, so the call can be captured in a graph)
     k_zero_i32<<<(unsigned)((ntiles + 255) / 256), 256, 0, st>>>(count, ntiles);
     k_bin_count<<<nb, 256, 0, st>>>(X, n_nodes, n, T, ta, 1.0 / h, node_tile, node_rank, count, nullptr);
-    k_bin_scan<<<1, 1024, 0, st>>>(count, ntiles, off, list, nlist);
+    k_bin_scan<<<1, 1024, 0, st>>>(count, ntiles, off, list, nlist, nullptr);
     k_bin_scatter<<<nb, 256, 0, st>>>(node_tile, node_rank, off, perm, n_nodes);
     const int blocks = (int)(cap < 8192 ? cap : 8192);
     const int64_t n3 = (int64_t)n * n * n;

@@ -165,12 +165,15 @@ struct hipib_ctx {
     int32_t* det_face_off = nullptr;   // [nn + 1] CSR: node -> (face, local node)
     int32_t* det_face_inc = nullptr;   // [4 nf] entries f * 4 + a
     double* det_face_contrib = nullptr;  // [nf][4][3]
-    int64_t det_pairs = 0;             // 192 nn spreading pairs
-    uint32_t* det_keys[2] = {nullptr, nullptr};  // pair grid indices (unsorted, sorted)
-    double* det_vals[2] = {nullptr, nullptr};    // pair values
-    void* det_temp = nullptr;          // radix-sort workspace
-    size_t det_temp_bytes = 0;
-    int det_end_bit = 0;               // bits of the largest grid index
+    uint32_t* det_key[2] = {nullptr, nullptr};  // node sort keys (cell index, tile-major)
+    int32_t* det_idx[2] = {nullptr, nullptr};   // node numbers in key order
+    int32_t* det_hist = nullptr;       // [256][det_nblk] digit counts, then offsets
+    int32_t* det_lfirst = nullptr;     // [ntiles] work-list index of each tile's first item
+    int32_t* det_active = nullptr;     // [ntiles] tiles some item's box reaches; then their count
+    int32_t* det_nactive = nullptr;    // det_active + ntiles
+    double* det_buf = nullptr;         // [spread_list_cap][3][(T + 4)^3] per-item spreading boxes
+    int det_nblk = 0;                  // radix-sort workgroups
+    int det_bits = 0;                  // bits of the largest cell key
 
     // adjoint workspaces (allocated on the first adjoint call)
     double* adj_tot = nullptr;   // [3][n3]
