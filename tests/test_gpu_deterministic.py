@@ -53,6 +53,31 @@ def test_spread_random_nodes_bitwise_and_oracle(torch_dev, hp, ref):
     assert_close("f", host(outs[0]), ref.spread(n, X, F, f0))
 
 
+@pytest.mark.parametrize("n,nn", [(8, 300), (12, 400), (16, 600), (24, 700)])
+def test_spread_small_grids_bitwise_and_oracle(torch_dev, hp, ref, n, nn):
+    """Grids of one tile per axis (n = 8: every tile box wraps onto itself),
+    4^3-cell tiles (n = 12), two tiles per axis (n = 16: the tile below and
+    above a tile are the same one) and three (n = 24), with half of the nodes in
+    one crowded cluster (more than one work item in its tile)."""
+    torch = torch_dev
+    say("det spread small grid", n, nn)
+    rng = np.random.default_rng(n)
+    X = rng.uniform(-0.3, 1.3, (nn, 3))
+    X[: nn // 2] = 0.5 + 0.01 * rng.standard_normal((nn // 2, 3))
+    F = rng.standard_normal((nn, 3))
+    f0 = rng.standard_normal((3, n, n, n))
+    outs = []
+    for _ in range(2):
+        ctx = plain_ctx(hp, n, deterministic=1)
+        ctx.set_mesh(X, np.zeros((0, 8)), np.zeros((0, 3)), np.zeros(0))
+        fd = to_dev(torch, f0)
+        ctx.spread(to_dev(torch, X), to_dev(torch, F), fd)
+        torch.cuda.synchronize()
+        outs.append(fd)
+    assert same(torch, outs[0], outs[1])
+    assert_close("f", host(outs[0]), ref.spread(n, X, F, f0))
+
+
 def test_spread_shell_bitwise(torch_dev, hp, ref):
     torch = torch_dev
     prob = inputs.ho_shell()
