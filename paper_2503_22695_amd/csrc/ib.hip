@@ -11,9 +11,10 @@
 // Spreading is binned: nodes are counting-sorted by the Eulerian tile (T^3
 // cells) holding floor(X/h); every stencil point of a node in tile t lies in
 // the (T+4)^3 box starting two cells below the tile, on all three lattices.
-// One workgroup per occupied tile accumulates its box in LDS with FP64 LDS
-// atomics, then adds the box to the grid with one coalesced pass of global
-// atomics (boxes of neighbouring tiles overlap by four cells).  Interpolation
+// One workgroup per work item (at most kSpreadChunk nodes of one tile) and
+// lattice accumulates its box in LDS with FP64 LDS atomics, then adds the box
+// to the grid with one coalesced pass of global atomics (boxes of
+// neighbouring tiles overlap by four cells).  Interpolation
 // walks the nodes in the same tile order so a wavefront gathers from a small
 // neighbourhood.  Summation order is not fixed, so results agree with a serial
 // sum to rounding.
@@ -151,9 +152,11 @@ k_bin_scatter(const int32_t* __restrict__ node_tile, const int32_t* __restrict__
     perm[off[node_tile[q]] + node_rank[q]] = q;
 }
 
-// one workgroup per work item (grid-stride over the list): up to
-// kSpreadChunk nodes of one tile, one node per thread; LDS box of E^3 cells
-// per lattice, E = T + 4, starting at T * tile - 2.  Ranks inside the chunk
+// one workgroup per (work item, lattice d = blockIdx.y) (grid-stride over the
+// list): up to kSpreadChunk nodes of one tile, one node per thread; LDS box of
+// E^3 cells of lattice d, E = T + 4, starting at T * tile - 2 (a workgroup per
+// lattice: a third of the LDS atomics per thread and three times the
+// workgroups of a single box of all three lattices).  Ranks inside the chunk
 // are dealt to threads with an odd stride, so the lanes of a wavefront take
 // nodes that are far apart in mesh order, which keeps apart the LDS addresses
 // they add to in the same instruction.  TW: type of the
@@ -167,12 +170,13 @@ k_spread_tiles(const double* __restrict__ X, const double* __restrict__ F, doubl
                const int32_t* __restrict__ list, const int32_t* __restrict__ nlist, int n, int ta,
                int64_t n3, double inv_h, double ih3) {
     constexpr int E = T + 4, E3 = E * E * E;
-    __shared__ double box[3 * E3];
+    __shared__ double box[E3];
+    const int d = blockIdx.y;
     const int ntl = *nlist;
     for (int li = blockIdx.x; li < ntl; li += gridDim.x) {
         const int tile = list[2 * li];
         const int tb[3] = {T * (tile % ta), T * ((tile / ta) % ta), T * (tile / (ta * ta))};
-        for (int e = threadIdx.x; e < 3 * E3; e += blockDim.x) box[e] = 0.0;
+        for (int e = threadIdx.x; e < E3; e += blockDim.x) box[e] = 0.0;
         __syncthreads();
         const int idx = off[tile] + list[2 * li + 1] + ((threadIdx.x * 109) & (kSpreadChunk - 1));
         if (idx < off[tile + 1]) {
@@ -183,7 +187,7 @@ k_spread_tiles(const double* __restrict__ X, const double* __restrict__ F, doubl
                 xs[e] = safe_coord(X[3 * q + e] * inv_h);
                 cw[e] = wrap_mod((int)floor(xs[e]), n);
             }
-            for (int d = 0; d < 3; ++d) {
+            {
                 const TW val = (TW)(F[3 * q + d] * ih3);
                 int ls[3];
                 TW w[3][4];
@@ -200,7 +204,7 @@ k_spread_tiles(const double* __restrict__ X, const double* __restrict__ F, doubl
                     const int ds = (int)bf - 1 - (int)floor(xs[e]);
                     ls[e] = cw[e] - tb[e] + 2 + ds;
                 }
-                double* bd = box + d * E3;
+                double* bd = box;
                 for (int c = 0; c < 4; ++c)
                     for (int b = 0; b < 4; ++b) {
                         const TW wyz = w[1][b] * w[2][c];
@@ -210,10 +214,10 @@ k_spread_tiles(const double* __restrict__ X, const double* __restrict__ F, doubl
             }
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < 3 * E3; e += blockDim.x) {
+        for (int e = threadIdx.x; e < E3; e += blockDim.x) {
             const double v = box[e];
             if (v != 0.0) {
-                const int d = e / E3, r = e - d * E3;
+                const int r = e;
                 const int lx = r % E, ly = (r / E) % E, lz = r / (E * E);
                 const int gx = wrap_mod(tb[0] - 2 + lx, n), gy = wrap_mod(tb[1] - 2 + ly, n),
                           gz = wrap_mod(tb[2] - 2 + lz, n);
@@ -328,7 +332,7 @@ hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, dou
     const int blocks = (int)(cap < 8192 ? cap : 8192);
     const bool mixed = ctx->cfg.precision == HIPIB_MIXED;
 #define HIPIB_SPREAD(TT, TW)                                                                       \
-    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_SPREAD, 0.0, k_spread_tiles<TT, TW>, dim3(blocks), dim3(kSpreadChunk), 0,  \
+    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_SPREAD, 0.0, k_spread_tiles<TT, TW>, dim3(blocks, 3), dim3(kSpreadChunk), 0,  \
                        X, F, f, ctx->perm, ctx->bin_off, ctx->tile_list, ctx->n_list, ctx->n,                 \
                        ctx->tiles_axis, ctx->n3, 1.0 / h, 1.0 / (h * h * h)))
     if (ctx->tile == 8) {
@@ -452,10 +456,10 @@ hipib_status hipib_spread_noalloc(int32_t n, int32_t n_nodes, const double* X, c
     const int blocks = (int)(cap < 8192 ? cap : 8192);
     const int64_t n3 = (int64_t)n * n * n;
     if (T == 8)
-        k_spread_tiles<8, double><<<blocks, kSpreadChunk, 0, st>>>(X, F, f, perm, off, list, nlist, n, ta,
+        k_spread_tiles<8, double><<<dim3(blocks, 3), kSpreadChunk, 0, st>>>(X, F, f, perm, off, list, nlist, n, ta,
                                                                    n3, 1.0 / h, 1.0 / (h * h * h));
     else
-        k_spread_tiles<4, double><<<blocks, kSpreadChunk, 0, st>>>(X, F, f, perm, off, list, nlist, n, ta,
+        k_spread_tiles<4, double><<<dim3(blocks, 3), kSpreadChunk, 0, st>>>(X, F, f, perm, off, list, nlist, n, ta,
                                                                    n3, 1.0 / h, 1.0 / (h * h * h));
     HIPIB_HIP(hipGetLastError());
     return HIPIB_OK;
