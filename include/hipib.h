@@ -81,7 +81,10 @@ typedef struct {
     double mg_rtol;           /* stop when ||b - A x||_2 <= rtol ||b||_2 */
     int32_t convection;       /* 1: explicit flux-form convection; 0: Stokes */
     int32_t precision;        /* hipib_precision */
-    int32_t deterministic;    /* 1: atomic-free, bitwise run-to-run reproducible */
+    int32_t deterministic;    /* 1: atomic-free, bitwise run-to-run reproducible.
+                                 Spreading then keeps one box per work item: about
+                                 (n^3/T^3 + nodes/256) x 3 (T+4)^3 x 8 bytes of device
+                                 memory (T = 8; 4 when n = 12), 190 MB at n = 128 */
     int32_t mg_krylov;        /* 1: Poisson solves by conjugate gradients preconditioned
                                  with one V-cycle (the "combined" multigrid reading of
                                  the abstract; one iteration counts as one cycle);
