@@ -33,8 +33,8 @@ static_assert(kRadixThreads == kRadixBins, "one thread per digit in the radix pa
 
 // sort key of every node: tile-major index of the cell holding floor(X/h)
 // (the binning's tile and cell, so the key order groups the tile bins);
-// values start as the node numbers
-// (also clears the count of active tiles for k_det_active)
+// values start as the node numbers.  Thread 0 also clears the count of
+// active tiles that k_det_active fills.
 __global__ void __launch_bounds__(256)
 k_det_keys(const double* __restrict__ X, int nn, int n, int T, int ta, double inv_h,
            uint32_t* __restrict__ key, int32_t* __restrict__ idx, int32_t* __restrict__ nactive) {
@@ -109,13 +109,13 @@ k_radix_scan(int32_t* __restrict__ hist, int64_t total) {
     }
 }
 
-// stable scatter by one digit.  Wavefront w of the workgroup takes its
-// kRadixPerThread rounds of 64 consecutive keys (keys [256 w, 256 w + 256) of
-// the block); in each round the lanes holding equal digits are found with one
-// ballot per digit bit, which gives each key its rank among the round's equal
-// digits and the round's count per digit.  Counts of the 16 (wave, round)
-// groups are prefix-summed per digit in group order, on top of the digit's
-// offset for this block, so equal digits keep their input order.
+// stable scatter by one digit.  With R = kRadixPerThread, wavefront w of the
+// workgroup takes R rounds of 64 consecutive keys (keys [64 R w, 64 R (w + 1))
+// of the block); in each round the lanes holding equal digits are found with
+// one ballot per digit bit, which gives each key its rank among the round's
+// equal digits and the round's count per digit.  Counts of the 4 R (wave,
+// round) groups are prefix-summed per digit in group order, on top of the
+// digit's offset for this block, so equal digits keep their input order.
 __global__ void __launch_bounds__(kRadixThreads)
 k_radix_scatter(const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin, int64_t count,
                 int shift, const int32_t* __restrict__ hist, int nblocks, uint32_t* __restrict__ kout,
