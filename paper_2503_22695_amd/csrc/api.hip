@@ -124,7 +124,6 @@ void free_all(hipib_ctx* ctx) {
     (void)hipFree(ctx->e32);
     for (int v = 0; v < 4; ++v) (void)hipFree(ctx->kv[v]);
     (void)hipFree(ctx->r32);
-    (void)hipFree(ctx->g);
     (void)hipFree(ctx->bp);
     (void)hipFree(ctx->part);
     (void)hipFree(ctx->bin_count);
@@ -210,10 +209,10 @@ hipib_status ib_step(hipib_ctx* ctx, double* u, double* p, double* X, double pre
     if (timed) HIPIB_HIP(hipEventRecord(ctx->ph_force[1], ctx->side));
     HIPIB_HIP(hipEventRecord(ctx->ev_join, ctx->side));
     HIPIB_TRY(launch_bin(ctx, X));
-    HIPIB_TRY(launch_rhs_build(ctx, u, nullptr, ctx->g, ctx->xp));
+    HIPIB_TRY(launch_rhs_build(ctx, u, nullptr, ctx->bpk, ctx->xp, true));
     HIPIB_TRY(phase_mark(ctx, timed, 1));
     HIPIB_HIP(hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0));
-    HIPIB_TRY(launch_spread(ctx, X, ctx->F, ctx->g));
+    HIPIB_TRY(launch_spread(ctx, X, ctx->F, ctx->bpk, true));
     HIPIB_TRY(phase_mark(ctx, timed, 2));
     HIPIB_TRY(fluid_solves(ctx, u, p, timed));
     HIPIB_TRY(position_status(ctx));
@@ -325,7 +324,6 @@ hipib_status hipib_create(const hipib_config* cfg, void* stream, hipib_ctx** out
         if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->e32, 3 * (size_t)ctx->n3);
         if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->r32, 3 * (size_t)ctx->n3);
     }
-    if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->g, 3 * (size_t)ctx->n3);
     if (cfg->mg_krylov)   // conjugate-gradient vectors r, z, p, q of the Poisson solve
         for (int v = 0; v < 4 && s == HIPIB_OK; ++v) s = dev_alloc(ctx, &ctx->kv[v], (size_t)ctx->n3);
     if (s == HIPIB_OK) s = dev_alloc(ctx, &ctx->bp, (size_t)ctx->n3);
@@ -674,7 +672,7 @@ hipib_status hipib_ns_step(hipib_ctx* ctx, const double* f, double* u, double* p
     if (!aligned8(u) || !aligned8(p) || (f && !aligned8(f))) return fail(HIPIB_E_INVAL, "bad pointer");
     ctx->recs.clear();
     if (ctx->cfg.walls) return walled_ns_step(ctx, f, u, p);
-    HIPIB_TRY(launch_rhs_build(ctx, u, f, ctx->g, ctx->xp));
+    HIPIB_TRY(launch_rhs_build(ctx, u, f, ctx->bpk, ctx->xp, true));
     return fluid_solves(ctx, u, p);
 }
 

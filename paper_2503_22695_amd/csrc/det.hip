@@ -267,7 +267,8 @@ template <int T>
 __global__ void __launch_bounds__(T * T * T)
 k_det_combine(const double* __restrict__ buf, const int32_t* __restrict__ bin_off,
               const int32_t* __restrict__ lfirst, const int32_t* __restrict__ active,
-              const int32_t* __restrict__ nactive, int n, int ta, int64_t n3, double* __restrict__ f) {
+              const int32_t* __restrict__ nactive, int n, int ta, int64_t n3, double* __restrict__ f,
+              int f_packed) {
     constexpr int E = T + 4, E3 = E * E * E;
     __shared__ int32_t s_nch[27], s_l0[27], s_org[27][3];
     const int d = blockIdx.y;
@@ -319,7 +320,8 @@ k_det_combine(const double* __restrict__ buf, const int32_t* __restrict__ bin_of
                         any = true;
                     }
         }
-        if (any) f[d * n3 + g[0] + (int64_t)n * (g[1] + (int64_t)n * g[2])] += acc;
+        if (any)
+            f[d * n3 + (f_packed ? pk(g[0], g[1], g[2], n) : g[0] + (int64_t)n * (g[1] + (int64_t)n * g[2]))] += acc;
     }
 }
 
@@ -436,7 +438,7 @@ hipib_status det_prepare_faces(hipib_ctx* ctx, const int32_t* faces, int nf) {
     return HIPIB_OK;
 }
 
-hipib_status det_spread(hipib_ctx* ctx, const double* X, const double* F, double* f) {
+hipib_status det_spread(hipib_ctx* ctx, const double* X, const double* F, double* f, bool f_packed) {
     const int nn = ctx->nn;
     if (nn == 0) return HIPIB_OK;
     const double h = ctx->h;
@@ -464,7 +466,8 @@ hipib_status det_spread(hipib_ctx* ctx, const double* X, const double* F, double
                        F, ctx->det_idx[cur], ctx->bin_off, ctx->tile_list, ctx->n_list, ctx->n, ta,        \
                        1.0 / h, 1.0 / (h * h * h), ctx->det_buf));                                         \
     k_det_combine<TT><<<gc, TT * TT * TT, 0, st>>>(ctx->det_buf, ctx->bin_off, ctx->det_lfirst,             \
-                                                    ctx->det_active, ctx->det_nactive, ctx->n, ta, ctx->n3, f)
+                                                    ctx->det_active, ctx->det_nactive, ctx->n, ta, ctx->n3, f, \
+                                                    f_packed ? 1 : 0)
     if (T == 8) {
         if (mixed) { HIPIB_DET(8, float); } else { HIPIB_DET(8, double); }
     } else {

@@ -54,17 +54,19 @@ __device__ __forceinline__ double conv_component(const double* __restrict__ u, c
 
 __global__ void __launch_bounds__(TX * TY)
 k_rhs_build(const double* __restrict__ u, const double* __restrict__ f, double* __restrict__ g,
-            Grid3 G, double rho_dt, double rho, double inv_h, int convection, double* __restrict__ upk) {
+            Grid3 G, double rho_dt, double rho, double inv_h, int convection, double* __restrict__ upk,
+            int g_packed) {
     const int i = blockIdx.x * TX + threadIdx.x, j = blockIdx.y * TY + threadIdx.y, k = blockIdx.z;
     if (i >= G.n || j >= G.n) return;
     const int64_t c = G.at(i, j, k);
-    const int64_t o = upk ? pk(i, j, k, G.n) : 0;
+    const int64_t o = (upk || g_packed) ? pk(i, j, k, G.n) : 0;
+    const int64_t og = g_packed ? o : c;
     for (int d = 0; d < 3; ++d) {
         const double cv = convection ? conv_component(u, G, d, i, j, k, inv_h) : 0.0;
         const double ud = u[d * G.n3 + c];
         double v = rho_dt * ud - rho * cv;
         if (f) v = v + f[d * G.n3 + c];
-        g[d * G.n3 + c] = v;
+        g[d * G.n3 + og] = v;
         if (upk) upk[d * G.n3 + o] = ud;   // u^n packed: the Helmholtz guess
     }
 }
@@ -111,15 +113,17 @@ dim3 plane_grid(int n) { return dim3((n + TX - 1) / TX, (n + TY - 1) / TY, n); }
 }  // namespace
 
 hipib_status launch_rhs_build_coef(hipib_ctx* ctx, const double* u, const double* f, double* g,
-                                   double rho_dt, double rho_conv, double* upk) {
+                                   double rho_dt, double rho_conv, double* upk, bool g_packed) {
     Grid3 G{ctx->n, ctx->n3};
     const double bytes = (f ? 72.0 : 48.0) + (upk ? 24.0 : 0.0);
     return launch_k(ctx, HIPIB_TIMER_RHS, bytes * (double)ctx->n3, k_rhs_build, plane_grid(ctx->n),
-                    dim3(TX, TY), 0, u, f, g, G, rho_dt, rho_conv, 1.0 / ctx->h, ctx->cfg.convection, upk);
+                    dim3(TX, TY), 0, u, f, g, G, rho_dt, rho_conv, 1.0 / ctx->h, ctx->cfg.convection, upk,
+                    g_packed ? 1 : 0);
 }
 
-hipib_status launch_rhs_build(hipib_ctx* ctx, const double* u, const double* f, double* g, double* upk) {
-    return launch_rhs_build_coef(ctx, u, f, g, ctx->cfg.rho / ctx->cfg.dt, ctx->cfg.rho, upk);
+hipib_status launch_rhs_build(hipib_ctx* ctx, const double* u, const double* f, double* g, double* upk,
+                              bool g_packed) {
+    return launch_rhs_build_coef(ctx, u, f, g, ctx->cfg.rho / ctx->cfg.dt, ctx->cfg.rho, upk, g_packed);
 }
 
 hipib_status launch_divergence_rhs_coef(hipib_ctx* ctx, const double* u, double* b, double coef) {

@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(kSpreadChunk)
 k_spread_tiles(const double* __restrict__ X, const double* __restrict__ F, double* __restrict__ f,
                const int32_t* __restrict__ perm, const int32_t* __restrict__ off,
                const int32_t* __restrict__ list, const int32_t* __restrict__ nlist, int n, int ta,
-               int64_t n3, double inv_h, double ih3) {
+               int64_t n3, double inv_h, double ih3, int f_packed) {
     constexpr int E = T + 4, E3 = E * E * E;
     __shared__ double box[E3];
     const int d = blockIdx.y;
@@ -221,7 +221,8 @@ k_spread_tiles(const double* __restrict__ X, const double* __restrict__ F, doubl
                 const int lx = r % E, ly = (r / E) % E, lz = r / (E * E);
                 const int gx = wrap_mod(tb[0] - 2 + lx, n), gy = wrap_mod(tb[1] - 2 + ly, n),
                           gz = wrap_mod(tb[2] - 2 + lz, n);
-                atomicAdd(f + d * n3 + gx + (int64_t)n * (gy + (int64_t)n * gz), v);
+                const int64_t g = f_packed ? pk(gx, gy, gz, n) : gx + (int64_t)n * (gy + (int64_t)n * gz);
+                atomicAdd(f + d * n3 + g, v);
             }
         }
         __syncthreads();
@@ -324,9 +325,9 @@ hipib_status launch_bin(hipib_ctx* ctx, const double* X) {
 }
 
 // expects launch_bin(ctx, X) to have been enqueued for the same X
-hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, double* f) {
+hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, double* f, bool f_packed) {
     if (ctx->nn == 0) return HIPIB_OK;
-    if (ctx->cfg.deterministic) return det_spread(ctx, X, F, f);
+    if (ctx->cfg.deterministic) return det_spread(ctx, X, F, f, f_packed);
     const double h = ctx->h;
     const int64_t cap = spread_list_cap(ctx->ntiles, ctx->nn);
     const int blocks = (int)(cap < 8192 ? cap : 8192);
@@ -334,7 +335,7 @@ hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, dou
 #define HIPIB_SPREAD(TT, TW)                                                                       \
     HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_SPREAD, 0.0, k_spread_tiles<TT, TW>, dim3(blocks, 3), dim3(kSpreadChunk), 0,  \
                        X, F, f, ctx->perm, ctx->bin_off, ctx->tile_list, ctx->n_list, ctx->n,                 \
-                       ctx->tiles_axis, ctx->n3, 1.0 / h, 1.0 / (h * h * h)))
+                       ctx->tiles_axis, ctx->n3, 1.0 / h, 1.0 / (h * h * h), f_packed ? 1 : 0))
     if (ctx->tile == 8) {
         if (mixed) HIPIB_SPREAD(8, float); else HIPIB_SPREAD(8, double);
     } else {
@@ -457,10 +458,10 @@ hipib_status hipib_spread_noalloc(int32_t n, int32_t n_nodes, const double* X, c
     const int64_t n3 = (int64_t)n * n * n;
     if (T == 8)
         k_spread_tiles<8, double><<<dim3(blocks, 3), kSpreadChunk, 0, st>>>(X, F, f, perm, off, list, nlist, n, ta,
-                                                                   n3, 1.0 / h, 1.0 / (h * h * h));
+                                                                   n3, 1.0 / h, 1.0 / (h * h * h), 0);
     else
         k_spread_tiles<4, double><<<dim3(blocks, 3), kSpreadChunk, 0, st>>>(X, F, f, perm, off, list, nlist, n, ta,
-                                                                   n3, 1.0 / h, 1.0 / (h * h * h));
+                                                                   n3, 1.0 / h, 1.0 / (h * h * h), 0);
     HIPIB_HIP(hipGetLastError());
     return HIPIB_OK;
 }

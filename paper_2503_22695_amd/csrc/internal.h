@@ -99,7 +99,6 @@ struct hipib_ctx {
     double* bpk = nullptr;  // [3][n3] packed FP64 right-hand side
     float* e32 = nullptr;   // [3][n3] packed FP32 correction (mixed precision)
     float* r32 = nullptr;   // [3][n3] packed FP32 scaled residual (mixed precision)
-    double* g = nullptr;    // [3][n3] Helmholtz right-hand side
     double* bp = nullptr;   // [n3] Poisson right-hand side (natural), or p packed during a step
     double* part = nullptr; // reduction partials
     int64_t part_cap = 0;
@@ -222,10 +221,11 @@ hipib_status compute_stats(hipib_ctx* ctx, const double* u, const double* X, hip
 
 // ---- launchers (each file owns its kernels) ---------------------------------
 // grid.hip
+// g_packed: g is written in the packed red-black layout (pk) instead of the natural one
 hipib_status launch_rhs_build(hipib_ctx* ctx, const double* u, const double* f, double* g,
-                              double* upk = nullptr);
-// the fluid part of a step on the packed layout (g built and spread, u^n
-// packed in xp): Helmholtz, divergence, Poisson, projection into u and p;
+                              double* upk = nullptr, bool g_packed = false);
+// the fluid part of a step on the packed layout (g built and spread packed in
+// bpk, u^n packed in xp): Helmholtz, divergence, Poisson, projection into u and p;
 // mark(ctx, k) (optional) after each of the three phases, k = 3, 4, 5
 hipib_status fluid_step_packed(hipib_ctx* ctx, double* u, double* p, int32_t* cyc, double* rr,
                                hipib_status (*mark)(hipib_ctx*, int));
@@ -234,7 +234,8 @@ hipib_status launch_project(hipib_ctx* ctx, double* u, const double* p);
 hipib_status launch_zero(hipib_ctx* ctx, double* p, int64_t count);
 // with explicit coefficients: g = rho_dt u - rho_conv C(u) + f; b = -coef D u; u -= coef G p
 hipib_status launch_rhs_build_coef(hipib_ctx* ctx, const double* u, const double* f, double* g,
-                                   double rho_dt, double rho_conv, double* upk = nullptr);
+                                   double rho_dt, double rho_conv, double* upk = nullptr,
+                                   bool g_packed = false);
 hipib_status launch_divergence_rhs_coef(hipib_ctx* ctx, const double* u, double* b, double coef);
 hipib_status launch_project_coef(hipib_ctx* ctx, double* u, const double* p, double coef);
 // walls.hip (walled box through its mirror image)
@@ -267,7 +268,9 @@ inline hipib_status position_status(const hipib_ctx* ctx) {
 }
 // ib.hip
 hipib_status launch_bin(hipib_ctx* ctx, const double* X);
-hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, double* f);
+// f_packed: f is in the packed red-black layout (pk) instead of the natural one
+hipib_status launch_spread(hipib_ctx* ctx, const double* X, const double* F, double* f,
+                           bool f_packed = false);
 hipib_status launch_interpolate(hipib_ctx* ctx, const double* X, const double* u, double* U,
                                 double* Xupd, double dt);
 // fe.hip
@@ -277,7 +280,7 @@ hipib_status launch_tethers(hipib_ctx* ctx, const double* X, const double* V, do
 // det.hip (deterministic mode)
 hipib_status det_prepare_mesh(hipib_ctx* ctx, const int32_t* conn);
 hipib_status det_prepare_faces(hipib_ctx* ctx, const int32_t* faces, int nf);
-hipib_status det_spread(hipib_ctx* ctx, const double* X, const double* F, double* f);
+hipib_status det_spread(hipib_ctx* ctx, const double* X, const double* F, double* f, bool f_packed);
 // out (= or +=) per-node sums of det_contrib (faces: det_face_contrib) in element order
 hipib_status det_gather_nodes(hipib_ctx* ctx, bool faces, bool accumulate, double* out);
 hipib_status det_param_reduce(hipib_ctx* ctx, double* dtheta);

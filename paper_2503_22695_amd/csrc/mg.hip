@@ -2629,10 +2629,8 @@ hipib_status fluid_step_packed(hipib_ctx* ctx, double* u, double* p, int32_t* cy
                                hipib_status (*mark)(hipib_ctx*, int)) {
     const int n = ctx->n;
     const int64_t n3 = ctx->n3;
-    // Helmholtz: g (natural, built and spread by the caller) packed into b; the
-    // guess u^n was packed into xp by the right-hand side builder
-    HIPIB_TRY(launch_k(ctx, HIPIB_TIMER_PACK, 48.0 * (double)n3, k_pack, natural_grid(n, 3), dim3(TX, TY), 0,
-                       ctx->g, ctx->bpk, n, n3));
+    // Helmholtz: its right-hand side g was built and spread packed in bpk by the
+    // caller, the guess u^n packed into xp by the right-hand side builder
     bool mean_ok = false;
     HIPIB_TRY(solve_packed(ctx, HIPIB_OP_HELMHOLTZ, 3, ctx->xp, false, cyc, rr, &mean_ok));
     if (mark) HIPIB_TRY(mark(ctx, 3));
