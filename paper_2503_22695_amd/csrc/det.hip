@@ -395,7 +395,7 @@ hipib_status det_prepare_mesh(hipib_ctx* ctx, const int32_t* conn) {
     HIPIB_TRY(alloc(reinterpret_cast<void**>(&ctx->det_contrib), sizeof(double) * 3 * npe * (size_t)ne));
     HIPIB_TRY(alloc(reinterpret_cast<void**>(&ctx->det_param), sizeof(double) * 4 * (size_t)ne));
     // spreading: sort keys and values (two buffers each), digit histograms,
-    // cell segment starts, per (lattice, node) lines
+    // each tile's first work item, the active tiles and one box per work item
     const int nblk = (int)((nn + kRadixBlock - 1) / kRadixBlock);
     ctx->det_nblk = nblk;
     int bits = 1;
