@@ -395,7 +395,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs one GPU only (the step is not sharded across GPUs); "
+        print("bench.py: this library runs on one GPU only (the step is not sharded across GPUs); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
